@@ -1,0 +1,164 @@
+/*
+ * fmmbem.h -- C ABI of the MI355X FMM-BEM library (libfmmbem.so).
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950), the
+ * FMM-accelerated boundary-element matrix-vector product that dominates the
+ * GMRES solve of the paper's Bempp-Exafmm linearised Poisson-Boltzmann
+ * solver (Wang, Cooper, Betcke, Barba, arXiv 2103.01048; Methods,
+ * "FMM-accelerated evaluation of integral operators" and "Fast multipole
+ * method").
+ *
+ * Conventions shared by every entry point
+ *   - Lengths in Angstrom, charges in e.  Kernels (Methods, boundary integral
+ *     formulation): Laplace g = 1/(4 pi r), Yukawa g = exp(-kappa r)/(4 pi r).
+ *   - "gradient" is +grad_x of the potential at the target (not the field).
+ *   - A pair of points at zero distance (bitwise-equal coordinates)
+ *     contributes nothing.
+ *   - Device pointers are HIP device allocations owned by the caller; the
+ *     library never frees them.  Plans and operators own their internal
+ *     buffers and release them in *_free.
+ *   - Every call that takes a stream enqueues its work on that stream and
+ *     returns without synchronising, except fmm_setup and bem_setup, which
+ *     synchronise the stream once.  A null stream is the default stream.
+ *   - No exception crosses the ABI.  Every int-returning call returns one of
+ *     the FMM_* status codes; fmm_last_error() gives a message for the last
+ *     failure on the calling thread.
+ *   - A plan or operator may be used by one stream at a time: evaluations
+ *     share its workspace.
+ */
+#ifndef FMMBEM_H
+#define FMMBEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_plan fmm_plan;
+typedef struct bem_op bem_op;
+typedef void *fmm_stream_t; /* a hipStream_t */
+
+enum { FMM_LAPLACE = 0, FMM_YUKAWA = 1 };
+
+/* Arithmetic of the evaluation.
+ *   FMM_FP64        every stage in double precision (P2P on FP64 VALU,
+ *                   translations on FP64 MFMA)
+ *   FMM_FP32        single precision; translations on FP32 MFMA
+ *   FMM_FP32_BF16X3 single precision; the dense translations (M2L, UC2E,
+ *                   DC2E, M2M, L2L) on bf16 MFMA with each FP32 operand
+ *                   split into a bf16 high and low part (three products,
+ *                   FP32 accumulation)
+ * Densities, potentials and gradients are double for FMM_FP64, float
+ * otherwise. */
+enum { FMM_FP64 = 0, FMM_FP32 = 1, FMM_FP32_BF16X3 = 2 };
+
+enum {
+  FMM_OK = 0,
+  FMM_EINVAL = -1,     /* bad argument */
+  FMM_ENOMEM = -2,     /* device or host allocation failed */
+  FMM_EHIP = -3,       /* a HIP runtime call failed */
+  FMM_ENOTCONV = -4,   /* GMRES hit maxiter before the tolerance */
+  FMM_EBREAKDOWN = -5  /* GMRES breakdown (non-finite residual) */
+};
+
+/* ------------------------------------------------------------------------
+ * Fast multipole evaluation of the particle sum
+ *      pot_i = sum_{j != i} g(|x_i - x_j|) q_j,   grad_i = grad_x pot_i
+ * with targets = sources = the n points (the N-body sum of "FMM-accelerated
+ * evaluation of integral operators").  Kernel-independent FMM ("Fast
+ * multipole method"): an adaptive octree that splits a box while it holds
+ * more than ncrit points; upward and downward equivalent densities on cube
+ * surfaces of p x p x p grid points (n_surf = 6 (p-1)^2 + 2 points); P2M,
+ * M2M, M2L, L2L, L2P and P2P in the paper's pass order.
+ * ------------------------------------------------------------------------ */
+
+/* Build a plan for the points xyz_dev (device, n x 3 doubles, row-major,
+ * read during the call only).  kernel: FMM_LAPLACE or FMM_YUKAWA; kappa >= 0
+ * (used by Yukawa only); p in [2, 16]; ncrit >= 1; precision: FMM_FP64,
+ * FMM_FP32 or FMM_FP32_BF16X3.  Sorts the points along a Morton curve on the
+ * device, builds the tree and interaction lists on the host, precomputes the
+ * translation operators in FP64 (truncated-SVD pseudo-inverses of the
+ * check-to-equivalent kernel matrices) and uploads them.  Synchronises
+ * `stream` once.  n = 0 gives a valid empty plan.  Errors: FMM_EINVAL for
+ * n < 0, a null output, a non-finite coordinate, p or ncrit out of range,
+ * kappa < 0 or non-finite; FMM_ENOMEM; FMM_EHIP. */
+int fmm_setup(const double *xyz_dev, int64_t n, int kernel, double kappa, int p, int ncrit,
+              int precision, fmm_stream_t stream, fmm_plan **out);
+
+/* Evaluate nrhs density columns.  q_dev: nrhs x n (column c at q_dev + c*n),
+ * in the caller's point order, element type double (FMM_FP64) or float.
+ * pot_dev: nrhs x n, same type; grad_dev: nrhs x n x 3 (gradient of point i
+ * of column c at grad_dev + (c*n + i)*3), or NULL to skip gradients.
+ * 1 <= nrhs <= 64.  Asynchronous on `stream`.  Errors: FMM_EINVAL for a null
+ * plan or buffer, nrhs out of range; FMM_ENOMEM when the workspace for a
+ * larger nrhs cannot be allocated; FMM_EHIP for a failed launch. */
+int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *grad_dev,
+             fmm_stream_t stream);
+
+/* Sizes of the plan's tree, for tests and reports. */
+typedef struct {
+  int64_t n_points;
+  int64_t n_boxes;
+  int64_t n_leaves;
+  int32_t max_level;
+  int32_t n_surf;        /* points per equivalent/check surface */
+  int64_t n_u_pairs;     /* leaf-leaf near-field pairs (U lists) */
+  int64_t n_v_pairs;     /* M2L pairs (V lists) */
+  int64_t n_w_pairs;     /* M2P pairs (W lists) */
+  int64_t n_x_pairs;     /* P2L pairs (X lists) */
+  int64_t n_p2p_interactions; /* sum over leaves of targets x U-list sources */
+  int64_t device_bytes;  /* device memory held by the plan */
+  double setup_ms;       /* wall time of fmm_setup */
+} fmm_info_t;
+
+int fmm_info(const fmm_plan *plan, fmm_info_t *out);
+
+/* Copy the plan's tree to host arrays (test access to the integer work).
+ * Any pointer may be NULL to skip that array.
+ *   perm   [n_points]   sorted position -> caller index (int64)
+ *   keys   [n_points]   sorted 63-bit Morton keys (int64)
+ *   level, anchor_xyz (3 per box), begin, end, parent, child_begin, nchild
+ *          [n_boxes]    boxes ordered by (level, key)
+ *   list_off [4*(n_boxes+1)], list_idx [n_u+n_v+n_w+n_x]: the U, V, W, X
+ *          lists in CSR form, one after the other (list k of box b is
+ *          list_idx[list_off[k*(nb+1)+b] .. list_off[k*(nb+1)+b+1]),
+ *          offsets counted from the start of list_idx), each sorted. */
+int fmm_get_tree(const fmm_plan *plan, int64_t *perm, int64_t *keys, int32_t *level,
+                 int64_t *anchor_xyz, int64_t *begin, int64_t *end, int64_t *parent,
+                 int64_t *child_begin, int32_t *nchild, int64_t *list_off, int64_t *list_idx);
+
+/* Root cube of the plan: lower corner (3 doubles) and side. */
+int fmm_get_root(const fmm_plan *plan, double *lo3, double *width);
+
+/* Per-phase timing with HIP events recorded on the evaluation stream.
+ * fmm_set_profiling(plan, 1) makes later fmm_eval calls record an event
+ * pair around each phase; fmm_get_phase_times synchronises on those events,
+ * writes the accumulated milliseconds and launch counts of the first
+ * `nphase` phases (FMM_PHASE_COUNT at most) and clears them. */
+enum {
+  FMM_PHASE_PERMUTE = 0, /* densities into Morton order */
+  FMM_PHASE_P2M = 1,     /* leaf sources -> upward check potentials */
+  FMM_PHASE_UC2E = 2,    /* upward check -> equivalent (MFMA) */
+  FMM_PHASE_M2M = 3,     /* children -> parent upward densities (MFMA) */
+  FMM_PHASE_P2L = 4,     /* X-list sources -> downward check potentials */
+  FMM_PHASE_M2L = 5,     /* V-list translations (MFMA) */
+  FMM_PHASE_M2L_SUM = 6, /* per-box sum of the M2L pair results */
+  FMM_PHASE_L2L = 7,     /* parent downward density -> child check (MFMA) */
+  FMM_PHASE_DC2E = 8,    /* downward check -> equivalent (MFMA) */
+  FMM_PHASE_LEAF = 9,    /* P2P + M2P + L2P at the leaves, unpermute, 1/(4 pi) */
+  FMM_PHASE_COUNT = 10
+};
+int fmm_set_profiling(fmm_plan *plan, int enable);
+int fmm_get_phase_times(fmm_plan *plan, double *ms, int64_t *launches, int nphase);
+
+void fmm_free(fmm_plan *plan);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *fmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMMBEM_H */

@@ -1,0 +1,6 @@
+"""MI355X-native FMM-BEM hot path (arXiv 2103.01048, Bempp-Exafmm): the
+kernel-independent FMM matrix-vector product, the direct-formulation BEM
+matvec and an FP64 GMRES, as hand-written HIP kernels for gfx950 behind the
+C ABI in include/fmmbem.h.  This package is the thin Python binding."""
+from ._lib import FmmError, lib  # noqa: F401
+from .fmm import FMMPlan  # noqa: F401

@@ -1,0 +1,965 @@
+// Host planner of the MI355X FMM library: argument checks, octree and
+// interaction lists, FP64 operator precompute, task lists, and the C ABI
+// entry points fmm_setup / fmm_eval / fmm_info / fmm_get_tree / fmm_free.
+//
+// Tree (Methods, Fast multipole method: an enclosing cube subdivided until
+// each leaf holds at most a constant number of points):
+//   root cube centred on the bounding box, side W = extent * (1 + 2^-20);
+//   63-bit Morton keys floor(((x - lo) / W) * 2^21) per axis, interleaved
+//   x,y,z; stable sort; a box splits while it holds more than ncrit points
+//   (level cap 21); boxes numbered by (level, key).
+// Lists of an adaptive tree: U (adjacent leaves), V (the interaction list:
+// children of the parent's neighbours not adjacent to the box), W
+// (descendants of neighbours not adjacent but with an adjacent parent) and
+// X (the transpose of W).
+// Operators (the matching equations for upward and downward equivalent
+// densities): surfaces of p x p x p grid points on cubes of half-width
+// 1.05 h / 2.95 h; check-to-equivalent maps are truncated-SVD
+// pseudo-inverses computed in FP64; M2M, L2L and M2L are kernel matrices
+// between surfaces (M2M composed with the parent's pseudo-inverse).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <atomic>
+#include <map>
+#include <thread>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], double mx[3], bool *finite);
+int device_morton_sort(const double *xyz, int64_t n, const double lo[3], double W, hipStream_t s,
+                       std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out);
+int device_gather_points(const double *xyz, const int32_t *perm, int64_t n, const double shift[3], int prec,
+                         void *pts, hipStream_t s);
+int eval_dispatch(fmm_plan *P, const void *q, int nrhs, void *pot, void *grad, hipStream_t s);
+
+static int dev_alloc(fmm_plan *P, void **ptr, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    set_error("hipMalloc(" + std::to_string(bytes) + " bytes): " + hipGetErrorString(e));
+    *ptr = nullptr;
+    return FMM_ENOMEM;
+  }
+  P->allocs.push_back(*ptr);
+  P->device_bytes += (int64_t)bytes;
+  return FMM_OK;
+}
+
+template <typename V>
+static int upload(fmm_plan *P, void **ptr, const std::vector<V> &h) {
+  int rc = dev_alloc(P, ptr, h.size() * sizeof(V));
+  if (rc) return rc;
+  if (!h.empty()) FMM_HIP_TRY(hipMemcpy(*ptr, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
+  return FMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tree
+// ---------------------------------------------------------------------------
+static inline int64_t prefix_of(int64_t key, int l) { return key >> (3 * (MAXLEVEL - l)); }
+
+static void build_tree(fmm_plan *P) {
+  const int64_t n = P->n;
+  const std::vector<int64_t> &K = P->keys;
+  struct B { int l; int64_t pre, b, e, par; };
+  std::vector<B> boxes;
+  boxes.push_back({0, 0, 0, n, -1});
+  std::vector<int64_t> lb = {0};
+  int64_t lvl_start = 0, lvl_end = 1;
+  while (true) {
+    lb.push_back(lvl_end);
+    for (int64_t bi = lvl_start; bi < lvl_end; ++bi) {
+      const B bx = boxes[bi];
+      if (bx.e - bx.b <= P->ncrit || bx.l >= MAXLEVEL) continue;
+      const int shift = 3 * (MAXLEVEL - (bx.l + 1));
+      int64_t pos = bx.b;
+      for (int c = 0; c < 8 && pos < bx.e; ++c) {
+        // first key of the next octant; the last octant ends with its parent
+        // (for the root, (7 + 1) << 60 would overflow the signed key type)
+        int64_t end = bx.e;
+        if (c < 7) {
+          const int64_t bound = (((bx.pre << 3) | c) + 1) << shift;
+          end = std::lower_bound(K.begin() + pos, K.begin() + bx.e, bound) - K.begin();
+        }
+        if (end > pos) boxes.push_back({bx.l + 1, (bx.pre << 3) | c, pos, end, bi});
+        pos = end;
+      }
+    }
+    if ((int64_t)boxes.size() == lvl_end) { lb.pop_back(); break; }
+    lvl_start = lvl_end;
+    lvl_end = (int64_t)boxes.size();
+  }
+  lb.push_back((int64_t)boxes.size());
+  const int64_t nb = (int64_t)boxes.size();
+  P->level.resize(nb); P->anchor.resize(3 * nb); P->begin.resize(nb); P->end.resize(nb);
+  P->parent.resize(nb); P->child_begin.assign(nb, -1); P->nchild.assign(nb, 0);
+  for (int64_t b = 0; b < nb; ++b) {
+    const B &bx = boxes[b];
+    P->level[b] = bx.l; P->begin[b] = bx.b; P->end[b] = bx.e; P->parent[b] = bx.par;
+    int64_t a[3] = {0, 0, 0};
+    for (int k = 0; k < bx.l; ++k) {
+      const int64_t dig = (bx.pre >> (3 * (bx.l - 1 - k))) & 7;
+      a[0] = (a[0] << 1) | ((dig >> 2) & 1);
+      a[1] = (a[1] << 1) | ((dig >> 1) & 1);
+      a[2] = (a[2] << 1) | (dig & 1);
+    }
+    P->anchor[3 * b] = a[0]; P->anchor[3 * b + 1] = a[1]; P->anchor[3 * b + 2] = a[2];
+    if (bx.par >= 0) {
+      if (P->child_begin[bx.par] < 0) P->child_begin[bx.par] = b;
+      P->nchild[bx.par]++;
+    }
+  }
+  P->level_begin = lb;  // level l boxes: [lb[l], lb[l+1])
+}
+
+static inline int64_t interleave3(int64_t x, int64_t y, int64_t z, int l) {
+  int64_t k = 0;
+  for (int b = 0; b < l; ++b) {
+    k |= ((x >> b) & 1) << (3 * b + 2);
+    k |= ((y >> b) & 1) << (3 * b + 1);
+    k |= ((z >> b) & 1) << (3 * b);
+  }
+  return k;
+}
+
+struct Lookup {
+  const fmm_plan *P;
+  std::vector<std::vector<int64_t>> pre;  // per level, sorted prefixes
+  explicit Lookup(const fmm_plan *p) : P(p) {
+    const int nl = (int)P->level_begin.size() - 1;
+    pre.resize(nl);
+    for (int l = 0; l < nl; ++l)
+      for (int64_t b = P->level_begin[l]; b < P->level_begin[l + 1]; ++b)
+        pre[l].push_back(interleave3(P->anchor[3 * b], P->anchor[3 * b + 1], P->anchor[3 * b + 2], l));
+  }
+  int64_t find(int l, int64_t x, int64_t y, int64_t z) const {
+    if (l >= (int)pre.size()) return -1;
+    const int64_t side = (int64_t)1 << l;
+    if (x < 0 || y < 0 || z < 0 || x >= side || y >= side || z >= side) return -1;
+    const int64_t k = interleave3(x, y, z, l);
+    auto it = std::lower_bound(pre[l].begin(), pre[l].end(), k);
+    if (it == pre[l].end() || *it != k) return -1;
+    return P->level_begin[l] + (it - pre[l].begin());
+  }
+};
+
+static bool adjacent(const fmm_plan *P, int64_t a, int64_t b) {
+  const int la = P->level[a], lbv = P->level[b];
+  const int64_t sa = (int64_t)1 << (MAXLEVEL - la), sb = (int64_t)1 << (MAXLEVEL - lbv);
+  for (int d = 0; d < 3; ++d) {
+    const int64_t loa = P->anchor[3 * a + d] * sa, lob = P->anchor[3 * b + d] * sb;
+    if (loa > lob + sb || lob > loa + sa) return false;
+  }
+  return true;
+}
+
+static void build_lists(fmm_plan *P) {
+  const int64_t nb = (int64_t)P->level.size();
+  Lookup lk(P);
+  std::vector<std::vector<int64_t>> U(nb), V(nb), Wl(nb), X(nb);
+  auto children = [&](int64_t b, std::vector<int64_t> &out) {
+    for (int c = 0; c < P->nchild[b]; ++c) out.push_back(P->child_begin[b] + c);
+  };
+  for (int64_t b = 0; b < nb; ++b) {
+    const int l = P->level[b];
+    const int64_t ax = P->anchor[3 * b], ay = P->anchor[3 * b + 1], az = P->anchor[3 * b + 2];
+    if (l >= 2) {
+      const int64_t p = P->parent[b];
+      const int64_t px = P->anchor[3 * p], py = P->anchor[3 * p + 1], pz = P->anchor[3 * p + 2];
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dz = -1; dz <= 1; ++dz) {
+            const int64_t c = lk.find(l - 1, px + dx, py + dy, pz + dz);
+            if (c < 0) continue;
+            for (int k = 0; k < P->nchild[c]; ++k) {
+              const int64_t ch = P->child_begin[c] + k;
+              if (!adjacent(P, ch, b)) V[b].push_back(ch);
+            }
+          }
+      std::sort(V[b].begin(), V[b].end());
+    }
+    if (P->nchild[b] != 0) continue;
+    std::vector<int64_t> uu, ww, stack;
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dz = -1; dz <= 1; ++dz) {
+          int64_t cx = ax + dx, cy = ay + dy, cz = az + dz;
+          const int64_t side = (int64_t)1 << l;
+          if (cx < 0 || cy < 0 || cz < 0 || cx >= side || cy >= side || cz >= side) continue;
+          int ll = l;
+          int64_t box = -1;
+          while (ll >= 0) {
+            box = lk.find(ll, cx, cy, cz);
+            if (box >= 0) break;
+            --ll;
+            cx >>= 1; cy >>= 1; cz >>= 1;
+          }
+          if (box < 0) continue;
+          if (P->nchild[box] == 0) {
+            uu.push_back(box);
+          } else if (ll == l) {
+            stack.clear();
+            children(box, stack);
+            while (!stack.empty()) {
+              const int64_t d = stack.back();
+              stack.pop_back();
+              if (adjacent(P, d, b)) {
+                if (P->nchild[d] == 0) uu.push_back(d);
+                else children(d, stack);
+              } else {
+                ww.push_back(d);
+              }
+            }
+          }
+        }
+    std::sort(uu.begin(), uu.end());
+    uu.erase(std::unique(uu.begin(), uu.end()), uu.end());
+    std::sort(ww.begin(), ww.end());
+    ww.erase(std::unique(ww.begin(), ww.end()), ww.end());
+    U[b] = uu;
+    Wl[b] = ww;
+  }
+  for (int64_t b = 0; b < nb; ++b)
+    for (int64_t a : Wl[b]) X[a].push_back(b);
+  std::vector<std::vector<int64_t>> *L[4] = {&U, &V, &Wl, &X};
+  for (int k = 0; k < 4; ++k) {
+    P->loff[k].assign(nb + 1, 0);
+    P->lidx[k].clear();
+    for (int64_t b = 0; b < nb; ++b) {
+      P->loff[k][b + 1] = P->loff[k][b] + (int64_t)(*L[k])[b].size();
+      P->lidx[k].insert(P->lidx[k].end(), (*L[k])[b].begin(), (*L[k])[b].end());
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Operators
+// ---------------------------------------------------------------------------
+static std::vector<double> surface_grid(int p) {
+  std::vector<double> g;
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < p; ++j)
+      for (int k = 0; k < p; ++k)
+        if (std::min(i, std::min(j, k)) == 0 || std::max(i, std::max(j, k)) == p - 1) {
+          g.push_back(2.0 * i / (p - 1) - 1.0);
+          g.push_back(2.0 * j / (p - 1) - 1.0);
+          g.push_back(2.0 * k / (p - 1) - 1.0);
+        }
+  return g;
+}
+
+// K[i][j] = g(|x_i - y_j|) without 1/(4 pi); x_i = cx + ax*grid_i, y_j = cy + ay*grid_j
+static void kernel_matrix(const std::vector<double> &grid, int n, const double cx[3], double ax, const double cy[3],
+                          double ay, int yuk, double kappa, double *out, int ldo) {
+  for (int i = 0; i < n; ++i) {
+    const double x0 = cx[0] + ax * grid[3 * i], x1 = cx[1] + ax * grid[3 * i + 1], x2 = cx[2] + ax * grid[3 * i + 2];
+    for (int j = 0; j < n; ++j) {
+      const double d0 = x0 - (cy[0] + ay * grid[3 * j]);
+      const double d1 = x1 - (cy[1] + ay * grid[3 * j + 1]);
+      const double d2 = x2 - (cy[2] + ay * grid[3 * j + 2]);
+      const double r = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      out[(size_t)i * ldo + j] = r == 0.0 ? 0.0 : (yuk ? std::exp(-kappa * r) / r : 1.0 / r);
+    }
+  }
+}
+
+static void matmul(int n, const double *A, const double *B, int ldb, double *C, int ldc) {
+  // C (n x n, ldc) = A (n x n) * B (n x n, ldb)
+  std::vector<double> row(n);
+  for (int i = 0; i < n; ++i) {
+    std::fill(row.begin(), row.end(), 0.0);
+    for (int k = 0; k < n; ++k) {
+      const double a = A[(size_t)i * n + k];
+      const double *b = B + (size_t)k * ldb;
+      for (int j = 0; j < n; ++j) row[j] += a * b[j];
+    }
+    std::copy(row.begin(), row.end(), C + (size_t)i * ldc);
+  }
+}
+
+template <typename F>
+static void parallel_for(int64_t count, F f) {
+  unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  if (count <= 1 || nt == 1) { for (int64_t i = 0; i < count; ++i) f(i); return; }
+  std::vector<std::thread> th;
+  std::atomic<int64_t> next(0);
+  for (unsigned t = 0; t < std::min<int64_t>(nt, count); ++t)
+    th.emplace_back([&]() { for (int64_t i; (i = next.fetch_add(1)) < count;) f(i); });
+  for (auto &t : th) t.join();
+}
+
+// Swizzle a dense row-major matrix A (rows x K, lda) into the MFMA fragment
+// order used by k_gemm: element [((rb*(K/16) + kq)*64 + lane)*4 + t] holds
+// A[rb*16 + slot(lane%16)][(kq*4 + t)*4 + lane/16].
+// The 16x16x4 f32 MFMA returns rows 4*(lane/16) + reg of its 16x16 block in
+// lane order; the f64 one returns rows lane/16 + 4*reg.  For double, row
+// slot s of the block is fed with row 4*(s%4) + s/4, so that both types
+// leave four consecutive rows in each lane's four result registers.
+template <typename T>
+static void swizzle(const double *A, int rows, int cols, int lda, int ld_rows, int Kfull, T *out) {
+  const int KQ = Kfull / 16;
+  const bool f64 = sizeof(T) == 8;
+  for (int rb = 0; rb < ld_rows / 16; ++rb)
+    for (int kq = 0; kq < KQ; ++kq)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int t = 0; t < 4; ++t) {
+          const int sl = lane & 15;
+          const int i = rb * 16 + (f64 ? 4 * (sl & 3) + (sl >> 2) : sl), k = (kq * 4 + t) * 4 + (lane >> 4);
+          const double v = (i < rows && k < cols) ? A[(size_t)i * lda + k] : 0.0;
+          out[((size_t)(rb * KQ + kq) * 64 + lane) * 4 + t] = (T)v;
+        }
+}
+
+static int m2l_code(int ox, int oy, int oz) { return (ox + 3) * 49 + (oy + 3) * 7 + (oz + 3); }
+
+template <typename T>
+static int precompute_typed(fmm_plan *P) {
+  const int p = P->p, n = P->nsurf, ld = P->ld;
+  const int yuk = P->kernel == FMM_YUKAWA;
+  const int maxl = (int)P->level_begin.size() - 2;
+  const double tau = P->precision == FMM_FP64 ? 1e-11 : 1e-7;
+  const std::vector<double> grid = surface_grid(p);
+  const double zero[3] = {0, 0, 0};
+  auto h_of = [&](int l) { return P->W / (double)(1ll << (l + 1)); };
+
+  std::vector<std::vector<char>> m2l_used(maxl + 1, std::vector<char>(343, 0));
+  for (int64_t b = 0; b < (int64_t)P->level.size(); ++b)
+    for (int64_t k = P->loff[1][b]; k < P->loff[1][b + 1]; ++k) {
+      const int64_t a = P->lidx[1][k];
+      const int c = m2l_code((int)(P->anchor[3 * a] - P->anchor[3 * b]), (int)(P->anchor[3 * a + 1] - P->anchor[3 * b + 1]),
+                             (int)(P->anchor[3 * a + 2] - P->anchor[3 * b + 2]));
+      m2l_used[P->level[b]][c] = 1;
+    }
+  std::vector<char> has_children(maxl + 1, 0);
+  for (int64_t b = 0; b < (int64_t)P->level.size(); ++b)
+    if (P->nchild[b]) has_children[P->level[b]] = 1;
+
+  // Geometry levels for which matrices are computed: every level >= 2 for
+  // Yukawa; one unit level (half-width 1) for Laplace, whose kernel scales as
+  // 1/h, so that level l uses the unit matrices times a power of h_l.
+  std::vector<int> glevels;
+  if (yuk) for (int l = 2; l <= maxl; ++l) glevels.push_back(l);
+  else if (maxl >= 2) glevels.push_back(-1);
+  auto gh = [&](int gl) { return gl < 0 ? 1.0 : h_of(gl); };
+
+  // kinds: 0 UT_u, 1 VS_u, 2 UT_d, 3 VS_d, 4 M2M stack (pool8), 5 L2L, 6 M2L
+  struct Job { int kind, l, oct, code; };
+  std::vector<Job> jobs;
+  for (int gl : glevels) {
+    for (int k = 0; k < 4; ++k) jobs.push_back({k, gl, 0, 0});
+    if (gl < 0 || has_children[gl]) {
+      jobs.push_back({4, gl, 0, 0});
+      for (int c = 0; c < 8; ++c) jobs.push_back({5, gl, c, 0});
+    }
+    for (int code = 0; code < 343; ++code) {
+      bool used = false;
+      if (gl < 0) { for (int l = 2; l <= maxl; ++l) used |= m2l_used[l][code] != 0; }
+      else used = m2l_used[gl][code] != 0;
+      if (used) jobs.push_back({6, gl, 0, code});
+    }
+  }
+  // truncated SVD factors of the check-from-equivalent matrices
+  std::map<int, std::vector<double>> ut_u, vs_u, ut_d, vs_d;
+  std::map<int, int> rk_u, rk_d;
+  for (int gl : glevels) {
+    ut_u[gl].assign((size_t)n * n, 0); vs_u[gl].assign((size_t)n * n, 0);
+    ut_d[gl].assign((size_t)n * n, 0); vs_d[gl].assign((size_t)n * n, 0);
+    rk_u[gl] = rk_d[gl] = 0;
+  }
+  {
+    std::vector<std::pair<int, int>> pj;
+    for (int gl : glevels) { pj.push_back({0, gl}); pj.push_back({1, gl}); }
+    std::vector<int> ranks(pj.size());
+    parallel_for((int64_t)pj.size(), [&](int64_t i) {
+      const int kind = pj[i].first, gl = pj[i].second;
+      const double h = gh(gl);
+      std::vector<double> Km((size_t)n * n);
+      if (kind == 0) {
+        kernel_matrix(grid, n, zero, ALPHA_UC * h, zero, ALPHA_UE * h, yuk, P->kappa, Km.data(), n);
+        ranks[i] = tsvd_factors(n, Km.data(), tau, ut_u[gl].data(), vs_u[gl].data());
+      } else {
+        kernel_matrix(grid, n, zero, ALPHA_DC * h, zero, ALPHA_DE * h, yuk, P->kappa, Km.data(), n);
+        ranks[i] = tsvd_factors(n, Km.data(), tau, ut_d[gl].data(), vs_d[gl].data());
+      }
+    });
+    for (size_t i = 0; i < pj.size(); ++i) (pj[i].first == 0 ? rk_u : rk_d)[pj[i].second] = ranks[i];
+  }
+  std::vector<int> id1(jobs.size(), -1), id8(jobs.size(), -1);
+  int64_t c1 = 0, c8 = 0;
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    if (jobs[j].kind == 4) id8[j] = (int)c8++;
+    else id1[j] = (int)c1++;
+  }
+  const size_t m1 = (size_t)ld * ld, m8 = (size_t)ld * ld * 8;
+  std::vector<T> pool1(std::max<size_t>(1, c1 * m1)), pool8(std::max<size_t>(1, c8 * m8));
+  parallel_for((int64_t)jobs.size(), [&](int64_t j) {
+    const Job &jb = jobs[j];
+    const double h = gh(jb.l);
+    T *dst = jb.kind == 4 ? pool8.data() + id8[j] * m8 : pool1.data() + id1[j] * m1;
+    switch (jb.kind) {
+      case 0: swizzle<T>(ut_u[jb.l].data(), n, n, n, ld, ld, dst); break;
+      case 1: swizzle<T>(vs_u[jb.l].data(), n, n, n, ld, ld, dst); break;
+      case 2: swizzle<T>(ut_d[jb.l].data(), n, n, n, ld, ld, dst); break;
+      case 3: swizzle<T>(vs_d[jb.l].data(), n, n, n, ld, ld, dst); break;
+      case 4: {
+        // parent upward check surface from the 8 children's upward equivalent
+        // surfaces; block c occupies columns [c*ld, c*ld + n)
+        std::vector<double> big((size_t)n * 8 * ld, 0.0), Km((size_t)n * n);
+        for (int c = 0; c < 8; ++c) {
+          const double off[3] = {(((c >> 2) & 1) ? 0.5 : -0.5) * h, (((c >> 1) & 1) ? 0.5 : -0.5) * h,
+                                 ((c & 1) ? 0.5 : -0.5) * h};
+          kernel_matrix(grid, n, zero, ALPHA_UC * h, off, ALPHA_UE * h * 0.5, yuk, P->kappa, Km.data(), n);
+          for (int i = 0; i < n; ++i)
+            std::copy(Km.begin() + (size_t)i * n, Km.begin() + (size_t)(i + 1) * n,
+                      big.begin() + (size_t)i * 8 * ld + c * ld);
+        }
+        swizzle<T>(big.data(), n, 8 * ld, 8 * ld, ld, 8 * ld, dst);
+        break;
+      }
+      case 5: {
+        // child (octant oct, half-width h/2) downward check surface from the
+        // parent's downward equivalent surface
+        const int c = jb.oct;
+        const double off[3] = {(((c >> 2) & 1) ? 0.5 : -0.5) * h, (((c >> 1) & 1) ? 0.5 : -0.5) * h,
+                               ((c & 1) ? 0.5 : -0.5) * h};
+        std::vector<double> Km((size_t)n * n);
+        kernel_matrix(grid, n, off, ALPHA_DC * h * 0.5, zero, ALPHA_DE * h, yuk, P->kappa, Km.data(), n);
+        swizzle<T>(Km.data(), n, n, n, ld, ld, dst);
+        break;
+      }
+      default: {
+        const int code = jb.code;
+        const double o[3] = {2.0 * h * (code / 49 - 3), 2.0 * h * ((code / 7) % 7 - 3), 2.0 * h * (code % 7 - 3)};
+        std::vector<double> Km((size_t)n * n);
+        kernel_matrix(grid, n, zero, ALPHA_DC * h, o, ALPHA_UE * h, yuk, P->kappa, Km.data(), n);
+        swizzle<T>(Km.data(), n, n, n, ld, ld, dst);
+      }
+    }
+  });
+  // per-level matrix ids, ranks and scale factors (Laplace: pinv of K/h is
+  // h * pinv(K), so the V S^-1 factor carries h and kernel matrices 1/h)
+  const int L1 = maxl + 1;
+  P->utu_id.assign(L1, -1); P->vsu_id.assign(L1, -1); P->utd_id.assign(L1, -1); P->vsd_id.assign(L1, -1);
+  P->rank_u.assign(L1, 0); P->rank_d.assign(L1, 0);
+  P->m2m_id.assign(L1, -1);
+  P->l2l_id.assign(L1, std::vector<int>(8, -1));
+  P->m2l_id.assign(L1, std::vector<int>(343, -1));
+  P->vs_alpha.assign(L1, 1); P->k_alpha.assign(L1, 1);
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    const Job &jb = jobs[j];
+    for (int l = 2; l <= maxl; ++l) {
+      if (jb.l >= 0 && jb.l != l) continue;
+      const double h = h_of(l);
+      const bool unit = jb.l < 0;
+      P->vs_alpha[l] = unit ? h : 1.0;
+      P->k_alpha[l] = unit ? 1.0 / h : 1.0;
+      P->rank_u[l] = rk_u[jb.l];
+      P->rank_d[l] = rk_d[jb.l];
+      switch (jb.kind) {
+        case 0: P->utu_id[l] = id1[j]; break;
+        case 1: P->vsu_id[l] = id1[j]; break;
+        case 2: P->utd_id[l] = id1[j]; break;
+        case 3: P->vsd_id[l] = id1[j]; break;
+        case 4: P->m2m_id[l] = id8[j]; break;
+        case 5: P->l2l_id[l][jb.oct] = id1[j]; break;
+        case 6: P->m2l_id[l][jb.code] = id1[j]; break;
+      }
+    }
+  }
+  P->pool1_count = c1;
+  P->pool8_count = c8;
+  int rc;
+  if ((rc = upload(P, &P->pool1, pool1))) return rc;
+  if ((rc = upload(P, &P->pool8, pool8))) return rc;
+  // surface grid table (T4)
+  std::vector<T> sg((size_t)n * 4);
+  for (int i = 0; i < n; ++i) {
+    sg[4 * i] = (T)grid[3 * i]; sg[4 * i + 1] = (T)grid[3 * i + 1]; sg[4 * i + 2] = (T)grid[3 * i + 2]; sg[4 * i + 3] = 0;
+  }
+  if ((rc = upload(P, &P->surf, sg))) return rc;
+  // box geometry (T4: centre relative to the root centre, half width)
+  const int64_t nb = (int64_t)P->level.size();
+  std::vector<T> geom((size_t)nb * 4);
+  for (int64_t b = 0; b < nb; ++b) {
+    const int l = P->level[b];
+    const double sd = P->W / (double)(1ll << l);
+    for (int d = 0; d < 3; ++d) geom[4 * b + d] = (T)((P->anchor[3 * b + d] + 0.5) * sd - 0.5 * P->W);
+    geom[4 * b + 3] = (T)(0.5 * sd);
+  }
+  if ((rc = upload(P, &P->dt.box_geom, geom))) return rc;
+  return FMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device lists
+// ---------------------------------------------------------------------------
+static int upload_lists(fmm_plan *P) {
+  const int64_t nb = (int64_t)P->level.size();
+  DevTree &D = P->dt;
+  D.nbox = (int)nb;
+  D.maxlevel = (int)P->level_begin.size() - 2;
+  std::vector<int32_t> bb(nb), be(nb);
+  for (int64_t b = 0; b < nb; ++b) { bb[b] = (int32_t)P->begin[b]; be[b] = (int32_t)P->end[b]; }
+  int rc;
+  if ((rc = upload(P, (void **)&D.box_begin, bb))) return rc;
+  if ((rc = upload(P, (void **)&D.box_end, be))) return rc;
+  std::vector<int32_t> leaves, uo = {0}, ui, wo = {0}, wi, hl, p2m, p2mo = {0};
+  int64_t inter = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    if (P->nchild[b]) continue;
+    leaves.push_back((int32_t)b);
+    const int64_t m = P->end[b] - P->begin[b];
+    for (int64_t k = P->loff[0][b]; k < P->loff[0][b + 1]; ++k) {
+      const int64_t a = P->lidx[0][k];
+      ui.push_back((int32_t)a);
+      inter += m * (P->end[a] - P->begin[a]);
+    }
+    uo.push_back((int32_t)ui.size());
+    for (int64_t k = P->loff[2][b]; k < P->loff[2][b + 1]; ++k) wi.push_back((int32_t)P->lidx[2][k]);
+    wo.push_back((int32_t)wi.size());
+    hl.push_back(P->level[b] >= 2 ? 1 : 0);
+    if (P->level[b] >= 2) { p2m.push_back((int32_t)b); p2mo.push_back((int32_t)p2m.size()); }
+  }
+  P->leaf_ids = leaves;
+  P->p2p_inter = inter;
+  D.nleaf = (int)leaves.size();
+  if ((rc = upload(P, (void **)&D.leaves, leaves))) return rc;
+  if ((rc = upload(P, (void **)&D.u_off, uo))) return rc;
+  if ((rc = upload(P, (void **)&D.u_idx, ui))) return rc;
+  if ((rc = upload(P, (void **)&D.w_off, wo))) return rc;
+  if ((rc = upload(P, (void **)&D.w_idx, wi))) return rc;
+  if ((rc = upload(P, (void **)&P->d_has_local, hl))) return rc;
+  P->p2m_count = (int)p2m.size();
+  if ((rc = upload(P, (void **)&P->d_p2m_box, p2m))) return rc;
+  if ((rc = upload(P, (void **)&P->d_p2m_off, p2mo))) return rc;
+  // X lists
+  std::vector<int32_t> xb, xo = {0}, xi;
+  for (int64_t b = 0; b < nb; ++b) {
+    if (P->loff[3][b + 1] == P->loff[3][b]) continue;
+    xb.push_back((int32_t)b);
+    for (int64_t k = P->loff[3][b]; k < P->loff[3][b + 1]; ++k) xi.push_back((int32_t)P->lidx[3][k]);
+    xo.push_back((int32_t)xi.size());
+  }
+  D.nxbox = (int)xb.size();
+  if ((rc = upload(P, (void **)&D.x_box, xb))) return rc;
+  if ((rc = upload(P, (void **)&D.x_off, xo))) return rc;
+  if ((rc = upload(P, (void **)&D.x_idx, xi))) return rc;
+  // V pairs in GEMM order: (level, offset code, target)
+  struct VP { int l, code; int64_t tgt, src; };
+  std::vector<VP> vp;
+  for (int64_t b = 0; b < nb; ++b)
+    for (int64_t k = P->loff[1][b]; k < P->loff[1][b + 1]; ++k) {
+      const int64_t a = P->lidx[1][k];
+      vp.push_back({P->level[b], m2l_code((int)(P->anchor[3 * a] - P->anchor[3 * b]), (int)(P->anchor[3 * a + 1] - P->anchor[3 * b + 1]),
+                                          (int)(P->anchor[3 * a + 2] - P->anchor[3 * b + 2])), b, a});
+    }
+  std::stable_sort(vp.begin(), vp.end(), [](const VP &x, const VP &y) {
+    if (x.l != y.l) return x.l < y.l;
+    if (x.code != y.code) return x.code < y.code;
+    return x.tgt < y.tgt;
+  });
+  P->vpair_src.resize(vp.size());
+  P->vpair_tgt.resize(vp.size());
+  std::vector<std::vector<int32_t>> per_tgt(nb);
+  for (size_t i = 0; i < vp.size(); ++i) {
+    P->vpair_src[i] = (int32_t)vp[i].src;
+    P->vpair_tgt[i] = (int32_t)vp[i].tgt;
+    per_tgt[vp[i].tgt].push_back((int32_t)i);
+  }
+  std::vector<int32_t> vt, vo = {0}, vpp;
+  for (int64_t b = 0; b < nb; ++b) {
+    if (per_tgt[b].empty()) continue;
+    // reduction order: by source box id (the V-list order)
+    std::sort(per_tgt[b].begin(), per_tgt[b].end(),
+              [&](int32_t x, int32_t y) { return P->vpair_src[x] < P->vpair_src[y]; });
+    vt.push_back((int32_t)b);
+    vpp.insert(vpp.end(), per_tgt[b].begin(), per_tgt[b].end());
+    vo.push_back((int32_t)vpp.size());
+  }
+  D.nvbox = (int)vt.size();
+  D.nvpair = (int64_t)vp.size();
+  if ((rc = upload(P, (void **)&D.v_tgt, vt))) return rc;
+  if ((rc = upload(P, (void **)&D.v_off, vo))) return rc;
+  if ((rc = upload(P, (void **)&D.v_pair, vpp))) return rc;
+  return FMM_OK;
+}
+
+static void add_columns(GemmBatch &bt, int mat, double alpha, const std::vector<int32_t> &src,
+                        const std::vector<int32_t> &dst) {
+  // src has S entries per column; split into tasks of GEMM_NT columns
+  const int nc = (int)dst.size();
+  const int base = (int)bt.h_dst.size();
+  for (int c0 = 0; c0 < nc; c0 += GEMM_NT) {
+    GemmTask t;
+    t.mat = mat;
+    t.col0 = base + c0;
+    t.ncol = std::min(GEMM_NT, nc - c0);
+    t.pad_ = 0;
+    t.alpha = alpha;
+    bt.h_tasks.push_back(t);
+  }
+  bt.h_src.insert(bt.h_src.end(), src.begin(), src.end());
+  bt.h_dst.insert(bt.h_dst.end(), dst.begin(), dst.end());
+}
+
+static int finish_batch(fmm_plan *P, GemmBatch &bt) {
+  const int64_t nmat = bt.pool == 0 ? P->pool1_count : P->pool8_count;
+  for (const GemmTask &t : bt.h_tasks)
+    if (t.mat < 0 || t.mat >= nmat) {
+      set_error("internal: GEMM task references a missing operator");
+      return FMM_EINVAL;
+    }
+  bt.ntask = (int)bt.h_tasks.size();
+  bt.ncols = (int)bt.h_dst.size();
+  int rc;
+  if ((rc = upload(P, (void **)&bt.d_tasks, bt.h_tasks))) return rc;
+  if ((rc = upload(P, (void **)&bt.d_src, bt.h_src))) return rc;
+  if ((rc = upload(P, (void **)&bt.d_dst, bt.h_dst))) return rc;
+  bt.h_tasks.clear(); bt.h_tasks.shrink_to_fit();
+  bt.h_src.clear(); bt.h_src.shrink_to_fit();
+  bt.h_dst.clear(); bt.h_dst.shrink_to_fit();
+  return FMM_OK;
+}
+
+int ensure_lists(fmm_plan *P, int nr) {
+  PassLists &L = P->lists_by_nr[nr];
+  if (L.nr == nr) return FMM_OK;
+  const int maxl = P->dt.maxlevel;
+  const int ld = P->ld;
+  int rc;
+  std::vector<int32_t> src, dst;
+  auto cols_for = [&](const std::vector<int64_t> &boxes_src, const std::vector<int64_t> &boxes_dst) {
+    src.clear(); dst.clear();
+    for (size_t i = 0; i < boxes_dst.size(); ++i)
+      for (int r = 0; r < nr; ++r) {
+        src.push_back((int32_t)(boxes_src[i] * nr + r));
+        dst.push_back((int32_t)(boxes_dst[i] * nr + r));
+      }
+  };
+  auto r16 = [](int r) { return std::max(16, ((r + 15) / 16) * 16); };
+  const int L1 = std::max(maxl + 1, 0);
+  L.m2m.assign(L1, GemmBatch()); L.ut_u.assign(L1, GemmBatch()); L.vs_u.assign(L1, GemmBatch());
+  L.l2l.assign(L1, GemmBatch()); L.ut_d.assign(L1, GemmBatch()); L.vs_d.assign(L1, GemmBatch());
+  for (int l = 2; l <= maxl; ++l) {
+    std::vector<int64_t> all;
+    for (int64_t b = P->level_begin[l]; b < P->level_begin[l + 1]; ++b) all.push_back(b);
+    // M2M: parent upward check potential from the children's equivalent densities
+    {
+      GemmBatch &bt = L.m2m[l];
+      bt.S = 8;
+      bt.pool = 1;
+      bt.nrb = ld / 16;
+      bt.klen = 8 * ld;
+      src.clear(); dst.clear();
+      for (int64_t b : all) {
+        if (!P->nchild[b]) continue;
+        int64_t ch[8];
+        for (int c = 0; c < 8; ++c) ch[c] = -1;
+        for (int k = 0; k < P->nchild[b]; ++k) {
+          const int64_t c = P->child_begin[b] + k;
+          const int oct = (int)(((P->anchor[3 * c] & 1) << 2) | ((P->anchor[3 * c + 1] & 1) << 1) | (P->anchor[3 * c + 2] & 1));
+          ch[oct] = c;
+        }
+        for (int r = 0; r < nr; ++r) {
+          for (int c = 0; c < 8; ++c) src.push_back(ch[c] < 0 ? -1 : (int32_t)(ch[c] * nr + r));
+          dst.push_back((int32_t)(b * nr + r));
+        }
+      }
+      if (!dst.empty()) add_columns(bt, P->m2m_id[l], P->k_alpha[l], src, dst);
+      if ((rc = finish_batch(P, bt))) return rc;
+    }
+    // upward check -> equivalent: U^T then V S^-1
+    cols_for(all, all);
+    L.ut_u[l].nrb = r16(P->rank_u[l]) / 16; L.ut_u[l].klen = ld;
+    add_columns(L.ut_u[l], P->utu_id[l], 1.0, src, dst);
+    if ((rc = finish_batch(P, L.ut_u[l]))) return rc;
+    L.vs_u[l].nrb = ld / 16; L.vs_u[l].klen = r16(P->rank_u[l]);
+    add_columns(L.vs_u[l], P->vsu_id[l], P->vs_alpha[l], src, dst);
+    if ((rc = finish_batch(P, L.vs_u[l]))) return rc;
+    // L2L (levels >= 3): child check += K * parent downward equivalent
+    if (l >= 3) {
+      GemmBatch &bt = L.l2l[l];
+      bt.mode = GEMM_ADD;
+      bt.nrb = ld / 16; bt.klen = ld;
+      for (int oct = 0; oct < 8; ++oct) {
+        std::vector<int64_t> bs, bd;
+        for (int64_t b : all) {
+          const int o = (int)(((P->anchor[3 * b] & 1) << 2) | ((P->anchor[3 * b + 1] & 1) << 1) | (P->anchor[3 * b + 2] & 1));
+          if (o != oct) continue;
+          bs.push_back(P->parent[b]);
+          bd.push_back(b);
+        }
+        if (bd.empty()) continue;
+        cols_for(bs, bd);
+        add_columns(bt, P->l2l_id[l - 1][oct], P->k_alpha[l - 1], src, dst);
+      }
+      if ((rc = finish_batch(P, bt))) return rc;
+    }
+    // downward check -> equivalent
+    cols_for(all, all);
+    L.ut_d[l].nrb = r16(P->rank_d[l]) / 16; L.ut_d[l].klen = ld;
+    add_columns(L.ut_d[l], P->utd_id[l], 1.0, src, dst);
+    if ((rc = finish_batch(P, L.ut_d[l]))) return rc;
+    L.vs_d[l].nrb = ld / 16; L.vs_d[l].klen = r16(P->rank_d[l]);
+    add_columns(L.vs_d[l], P->vsd_id[l], P->vs_alpha[l], src, dst);
+    if ((rc = finish_batch(P, L.vs_d[l]))) return rc;
+  }
+  // M2L: pairs in GEMM order, tasks split at (level, offset) changes
+  L.m2l = GemmBatch();
+  L.m2l.nrb = ld / 16;
+  L.m2l.klen = ld;
+  {
+    const int64_t np = (int64_t)P->vpair_src.size();
+    auto code_of = [&](int64_t j) {
+      const int64_t t = P->vpair_tgt[j], a = P->vpair_src[j];
+      return m2l_code((int)(P->anchor[3 * a] - P->anchor[3 * t]), (int)(P->anchor[3 * a + 1] - P->anchor[3 * t + 1]),
+                      (int)(P->anchor[3 * a + 2] - P->anchor[3 * t + 2]));
+    };
+    int64_t i = 0;
+    while (i < np) {
+      const int l = P->level[P->vpair_tgt[i]];
+      const int code = code_of(i);
+      int64_t j = i;
+      src.clear(); dst.clear();
+      while (j < np && P->level[P->vpair_tgt[j]] == l && code_of(j) == code) {
+        for (int r = 0; r < nr; ++r) {
+          src.push_back((int32_t)(P->vpair_src[j] * nr + r));
+          dst.push_back((int32_t)(j * nr + r));
+        }
+        ++j;
+      }
+      add_columns(L.m2l, P->m2l_id[l][code], P->k_alpha[l], src, dst);
+      i = j;
+    }
+  }
+  if ((rc = finish_batch(P, L.m2l))) return rc;
+  L.nr = nr;
+  return FMM_OK;
+}
+
+int ensure_work(fmm_plan *P, int nr) {
+  if (P->work_nr >= nr) return FMM_OK;
+  const size_t es = P->precision == FMM_FP64 ? 8 : 4;
+  const int64_t nb = P->dt.nbox;
+  const size_t wbytes = (size_t)nb * nr * P->ld * es;
+  int rc;
+  // old buffers stay in allocs until fmm_free (simple and safe for in-flight work)
+  if ((rc = dev_alloc(P, &P->qs, (size_t)P->n * nr * es))) return rc;
+  if ((rc = dev_alloc(P, &P->equ, wbytes))) return rc;
+  if ((rc = dev_alloc(P, &P->chk, wbytes))) return rc;
+  if ((rc = dev_alloc(P, &P->eqd, wbytes))) return rc;
+  if ((rc = dev_alloc(P, &P->chku, wbytes))) return rc;
+  if ((rc = dev_alloc(P, &P->tmp, wbytes))) return rc;
+  if ((rc = dev_alloc(P, &P->pairbuf, (size_t)std::max<int64_t>(1, P->dt.nvpair) * nr * P->ld * es))) return rc;
+  // padding rows/columns must hold zeros (the GEMM K dimension reads them)
+  FMM_HIP_TRY(hipMemset(P->equ, 0, wbytes));
+  FMM_HIP_TRY(hipMemset(P->chk, 0, wbytes));
+  FMM_HIP_TRY(hipMemset(P->eqd, 0, wbytes));
+  FMM_HIP_TRY(hipMemset(P->chku, 0, wbytes));
+  FMM_HIP_TRY(hipMemset(P->tmp, 0, wbytes));
+  P->work_nr = nr;
+  return FMM_OK;
+}
+
+hipEvent_t prof_begin(fmm_plan *P, hipStream_t s) {
+  if (!P->profiling) return nullptr;
+  hipEvent_t e = nullptr;
+  if (!P->event_pool.empty()) {
+    e = P->event_pool.back();
+    P->event_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  (void)hipEventRecord(e, s);
+  return e;
+}
+
+void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
+  if (!P->profiling || !begin) return;
+  hipEvent_t e = nullptr;
+  if (!P->event_pool.empty()) {
+    e = P->event_pool.back();
+    P->event_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return;
+  }
+  (void)hipEventRecord(e, s);
+  P->prof_events.push_back({phase, {begin, e}});
+}
+
+}  // namespace fmm
+
+using namespace fmm;
+
+extern "C" {
+
+const char *fmm_last_error(void) { return g_err.c_str(); }
+
+int fmm_setup(const double *xyz_dev, int64_t n, int kernel, double kappa, int p, int ncrit, int precision,
+              fmm_stream_t stream, fmm_plan **out) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!out) { set_error("fmm_setup: out is NULL"); return FMM_EINVAL; }
+  *out = nullptr;
+  if (n < 0 || n > 0x7fffffffll) { set_error("fmm_setup: n out of range"); return FMM_EINVAL; }
+  if (n > 0 && !xyz_dev) { set_error("fmm_setup: xyz is NULL"); return FMM_EINVAL; }
+  if (kernel != FMM_LAPLACE && kernel != FMM_YUKAWA) { set_error("fmm_setup: unknown kernel"); return FMM_EINVAL; }
+  if (!(kappa >= 0.0) || !std::isfinite(kappa)) { set_error("fmm_setup: kappa must be finite and >= 0"); return FMM_EINVAL; }
+  if (p < 2 || p > 16) { set_error("fmm_setup: p must be in [2, 16]"); return FMM_EINVAL; }
+  if (ncrit < 1) { set_error("fmm_setup: ncrit must be >= 1"); return FMM_EINVAL; }
+  if (precision != FMM_FP64 && precision != FMM_FP32 && precision != FMM_FP32_BF16X3) {
+    set_error("fmm_setup: unknown precision");
+    return FMM_EINVAL;
+  }
+  fmm_plan *P = new (std::nothrow) fmm_plan();
+  if (!P) { set_error("fmm_setup: out of host memory"); return FMM_ENOMEM; }
+  P->kernel = kernel; P->kappa = kernel == FMM_YUKAWA ? kappa : 0.0; P->p = p; P->ncrit = ncrit; P->precision = precision;
+  P->n = n;
+  P->nsurf = 6 * (p - 1) * (p - 1) + 2;
+  P->ld = ((P->nsurf + 15) / 16) * 16;
+  if (P->ld / 16 > 32) { delete P; set_error("fmm_setup: p too large for the GEMM kernel"); return FMM_EINVAL; }
+  hipGetDevice(&P->device);
+  hipStream_t s = (hipStream_t)stream;
+  int rc = FMM_OK;
+  do {
+    if (n == 0) {
+      P->level = {0}; P->nchild = {0}; P->anchor = {0, 0, 0}; P->begin = {0}; P->end = {0}; P->parent = {-1};
+      P->child_begin = {-1}; P->level_begin = {0, 1};
+      for (int k = 0; k < 4; ++k) { P->loff[k] = {0, 0}; P->lidx[k].clear(); }
+      P->dt.nbox = 1; P->dt.maxlevel = 0;
+      break;
+    }
+    double mn[3], mx[3];
+    bool finite = true;
+    if ((rc = device_bbox(xyz_dev, n, s, mn, mx, &finite))) break;
+    if (!finite) { set_error("fmm_setup: non-finite coordinate"); rc = FMM_EINVAL; break; }
+    double ext = 0, cen[3];
+    for (int d = 0; d < 3; ++d) { cen[d] = (mn[d] + mx[d]) * 0.5; ext = std::max(ext, mx[d] - mn[d]); }
+    P->W = ext > 0 ? ext * (1.0 + std::ldexp(1.0, -20)) : 1.0;
+    for (int d = 0; d < 3; ++d) { P->lo[d] = cen[d] - 0.5 * P->W; P->shift[d] = P->lo[d] + 0.5 * P->W; }
+    if ((rc = device_morton_sort(xyz_dev, n, P->lo, P->W, s, P->keys, P->perm))) break;
+    build_tree(P);
+    build_lists(P);
+    // device tree
+    std::vector<int32_t> perm32(n);
+    for (int64_t i = 0; i < n; ++i) perm32[i] = (int32_t)P->perm[i];
+    if ((rc = upload(P, (void **)&P->dt.perm, perm32))) break;
+    const size_t es = precision == FMM_FP64 ? 8 : 4;
+    if ((rc = dev_alloc(P, &P->dt.pts, (size_t)n * 4 * es))) break;
+    P->dt.n = n;
+    if ((rc = device_gather_points(xyz_dev, P->dt.perm, n, P->shift, precision, P->dt.pts, s))) break;
+    if ((rc = upload_lists(P))) break;
+    rc = precision == FMM_FP64 ? precompute_typed<double>(P) : precompute_typed<float>(P);
+    if (rc) break;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { set_error(std::string("fmm_setup: ") + hipGetErrorString(e)); rc = FMM_EHIP; }
+  } while (0);
+  if (rc) { fmm_free(P); return rc; }
+  P->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = P;
+  return FMM_OK;
+}
+
+int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *grad_dev, fmm_stream_t stream) {
+  if (!plan) { set_error("fmm_eval: plan is NULL"); return FMM_EINVAL; }
+  if (nrhs < 1 || nrhs > 64) { set_error("fmm_eval: nrhs must be in [1, 64]"); return FMM_EINVAL; }
+  if (plan->n == 0) return FMM_OK;
+  if (!q_dev || !pot_dev) { set_error("fmm_eval: null buffer"); return FMM_EINVAL; }
+  return eval_dispatch(plan, q_dev, nrhs, pot_dev, grad_dev, (hipStream_t)stream);
+}
+
+int fmm_info(const fmm_plan *P, fmm_info_t *o) {
+  if (!P || !o) { set_error("fmm_info: null argument"); return FMM_EINVAL; }
+  std::memset(o, 0, sizeof(*o));
+  o->n_points = P->n;
+  o->n_boxes = (int64_t)P->level.size();
+  int64_t nl = 0;
+  for (auto c : P->nchild) nl += c == 0;
+  o->n_leaves = P->n ? nl : 0;
+  o->max_level = (int32_t)P->level_begin.size() - 2;
+  o->n_surf = P->nsurf;
+  o->n_u_pairs = (int64_t)P->lidx[0].size();
+  o->n_v_pairs = (int64_t)P->lidx[1].size();
+  o->n_w_pairs = (int64_t)P->lidx[2].size();
+  o->n_x_pairs = (int64_t)P->lidx[3].size();
+  o->n_p2p_interactions = P->p2p_inter;
+  o->device_bytes = P->device_bytes;
+  o->setup_ms = P->setup_ms;
+  return FMM_OK;
+}
+
+int fmm_get_tree(const fmm_plan *P, int64_t *perm, int64_t *keys, int32_t *level, int64_t *anchor_xyz,
+                 int64_t *begin, int64_t *end, int64_t *parent, int64_t *child_begin, int32_t *nchild,
+                 int64_t *list_off, int64_t *list_idx) {
+  if (!P) { set_error("fmm_get_tree: plan is NULL"); return FMM_EINVAL; }
+  const size_t nb = P->level.size();
+  if (perm) std::copy(P->perm.begin(), P->perm.end(), perm);
+  if (keys) std::copy(P->keys.begin(), P->keys.end(), keys);
+  if (level) std::copy(P->level.begin(), P->level.end(), level);
+  if (anchor_xyz) std::copy(P->anchor.begin(), P->anchor.end(), anchor_xyz);
+  if (begin) std::copy(P->begin.begin(), P->begin.end(), begin);
+  if (end) std::copy(P->end.begin(), P->end.end(), end);
+  if (parent) std::copy(P->parent.begin(), P->parent.end(), parent);
+  if (child_begin) std::copy(P->child_begin.begin(), P->child_begin.end(), child_begin);
+  if (nchild) std::copy(P->nchild.begin(), P->nchild.end(), nchild);
+  int64_t base = 0;
+  for (int k = 0; k < 4; ++k) {
+    if (list_off)
+      for (size_t b = 0; b <= nb; ++b) list_off[k * (nb + 1) + b] = base + P->loff[k][b];
+    if (list_idx) std::copy(P->lidx[k].begin(), P->lidx[k].end(), list_idx + base);
+    base += (int64_t)P->lidx[k].size();
+  }
+  return FMM_OK;
+}
+
+int fmm_get_root(const fmm_plan *P, double *lo3, double *width) {
+  if (!P) { set_error("fmm_get_root: plan is NULL"); return FMM_EINVAL; }
+  if (lo3) for (int d = 0; d < 3; ++d) lo3[d] = P->lo[d];
+  if (width) *width = P->W;
+  return FMM_OK;
+}
+
+int fmm_set_profiling(fmm_plan *P, int enable) {
+  if (!P) { set_error("fmm_set_profiling: plan is NULL"); return FMM_EINVAL; }
+  P->profiling = enable ? 1 : 0;
+  return FMM_OK;
+}
+
+int fmm_get_phase_times(fmm_plan *P, double *ms, int64_t *launches, int nphase) {
+  if (!P || nphase < 0 || nphase > FMM_PHASE_COUNT) { set_error("fmm_get_phase_times: bad argument"); return FMM_EINVAL; }
+  std::vector<double> acc(FMM_PHASE_COUNT, 0.0);
+  std::vector<int64_t> cnt(FMM_PHASE_COUNT, 0);
+  for (auto &pe : P->prof_events) {
+    FMM_HIP_TRY(hipEventSynchronize(pe.second.second));
+    float t = 0;
+    FMM_HIP_TRY(hipEventElapsedTime(&t, pe.second.first, pe.second.second));
+    acc[pe.first] += t;
+    cnt[pe.first] += 1;
+    P->event_pool.push_back(pe.second.first);
+    P->event_pool.push_back(pe.second.second);
+  }
+  P->prof_events.clear();
+  for (int i = 0; i < nphase; ++i) {
+    if (ms) ms[i] = acc[i];
+    if (launches) launches[i] = cnt[i];
+  }
+  return FMM_OK;
+}
+
+void fmm_free(fmm_plan *P) {
+  if (!P) return;
+  for (auto &pe : P->prof_events) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
+  for (hipEvent_t e : P->event_pool) (void)hipEventDestroy(e);
+  for (void *p : P->allocs) (void)hipFree(p);
+  delete P;
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// Internal structures of the MI355X FMM library (host planner + kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fmmbem.h"
+
+namespace fmm {
+
+constexpr int MAXLEVEL = 21;
+constexpr int GEMM_NT = 64;   // columns per GEMM task (4 MFMA column blocks)
+constexpr int MAX_NR = 4;     // density columns handled by one kernel pass
+
+// Surface radii, in units of the box half-width (upward equivalent, upward
+// check, downward equivalent, downward check).
+constexpr double ALPHA_UE = 1.05, ALPHA_UC = 2.95, ALPHA_DE = 2.95, ALPHA_DC = 1.05;
+
+void set_error(const std::string &msg);
+hipEvent_t prof_begin(fmm_plan *P, hipStream_t s);
+void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s);
+void pinv_tsvd(int n, const double *A, double tau, double *out);
+int tsvd_factors(int n, const double *A, double tau, double *UT, double *VS);
+
+#define FMM_HIP_TRY(call)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      ::fmm::set_error(std::string(#call) + ": " + hipGetErrorString(e_));       \
+      return FMM_EHIP;                                                           \
+    }                                                                            \
+  } while (0)
+
+// One GEMM work item: Y[dst[c]] (op)= alpha * A[mat] * concat_s X[src[c*S+s]]
+// for columns c in [col0, col0 + ncol), ncol <= GEMM_NT.
+struct GemmTask {
+  int32_t mat;
+  int32_t col0;
+  int32_t ncol;
+  int32_t pad_;
+  double alpha;
+};
+
+enum GemmMode { GEMM_STORE = 0, GEMM_ADD = 1, GEMM_ATOMIC = 2 };
+
+// A batch of GEMM tasks that can run in one launch (no write conflicts
+// except through GEMM_ATOMIC).
+struct GemmBatch {
+  int S = 1;                   // K segments per column
+  int nrb = 0;                 // 16-row blocks of A that are computed
+  int klen = 0;                // K extent actually read (multiple of 16)
+  int mode = GEMM_STORE;
+  int pool = 0;                // 0: single-segment matrix pool, 1: M2M pool
+  int ntask = 0;
+  GemmTask *d_tasks = nullptr;
+  int32_t *d_src = nullptr;    // ncols*S  (row index into X, already * nr + r)
+  int32_t *d_dst = nullptr;    // ncols    (row index into Y)
+  int ncols = 0;
+  // host copies kept until upload
+  std::vector<GemmTask> h_tasks;
+  std::vector<int32_t> h_src, h_dst;
+};
+
+// Per-nrhs-chunk task lists.  Row indices in the work arrays are
+// box * nr + r, so the lists depend on nr.
+struct PassLists {
+  int nr = 0;
+  // per level l (index l, levels >= 2)
+  std::vector<GemmBatch> m2m;   // parent upward check from children (stacked K)
+  std::vector<GemmBatch> ut_u;  // upward check -> singular coordinates
+  std::vector<GemmBatch> vs_u;  // singular coordinates -> upward equivalent
+  std::vector<GemmBatch> l2l;   // child downward check += K * parent equivalent
+  std::vector<GemmBatch> ut_d;  // downward check -> singular coordinates
+  std::vector<GemmBatch> vs_d;  // singular coordinates -> downward equivalent
+  GemmBatch m2l;                // all levels, writes pair slots
+};
+
+struct DevTree {
+  int64_t n = 0;
+  int nbox = 0, nleaf = 0, maxlevel = 0;
+  // sorted points, shifted to the root-cube centre; xyz + pad, in T
+  void *pts = nullptr;
+  int32_t *perm = nullptr;      // sorted -> caller index
+  // boxes
+  void *box_geom = nullptr;     // T4: centre xyz (shifted), half width
+  int32_t *box_begin = nullptr, *box_end = nullptr;
+  int32_t *leaves = nullptr;    // leaf box ids
+  int32_t *u_off = nullptr, *u_idx = nullptr;   // per leaf slot
+  int32_t *w_off = nullptr, *w_idx = nullptr;   // per leaf slot
+  int32_t *x_box = nullptr;     // boxes with a non-empty X list
+  int32_t *x_off = nullptr, *x_idx = nullptr;
+  int nxbox = 0;
+  int32_t *v_tgt = nullptr;     // boxes with a non-empty V list
+  int32_t *v_off = nullptr;     // pair ids of each such box (CSR)
+  int32_t *v_pair = nullptr;
+  int nvbox = 0;
+  int64_t nvpair = 0;
+};
+
+}  // namespace fmm
+
+struct fmm_plan {
+  int kernel = 0, p = 0, ncrit = 0, precision = 0;
+  double kappa = 0;
+  int64_t n = 0;
+  int nsurf = 0, ld = 0;           // surface points, padded leading dimension
+  double lo[3] = {0, 0, 0}, W = 1, shift[3] = {0, 0, 0};
+  int device = 0;
+  // host tree
+  std::vector<int64_t> keys, perm;
+  std::vector<int32_t> level, nchild;
+  std::vector<int64_t> anchor, begin, end, parent, child_begin;
+  std::vector<int64_t> level_begin;  // size maxlevel+2
+  std::vector<int64_t> loff[4];      // U, V, W, X CSR offsets (nbox+1)
+  std::vector<int64_t> lidx[4];
+  std::vector<int32_t> leaf_ids;
+  std::vector<int32_t> vpair_src, vpair_tgt;  // V pairs in GEMM order
+  int64_t p2p_inter = 0;
+  // device
+  fmm::DevTree dt;
+  void *surf = nullptr;            // T4 grid offsets in [-1,1]^3, nsurf entries
+  void *pool1 = nullptr;           // swizzled ld x ld matrices
+  void *pool8 = nullptr;           // swizzled ld x 8ld matrices (M2M)
+  int64_t pool1_count = 0, pool8_count = 0;
+  // matrix ids (pool1 unless noted) per level; -1 when absent
+  std::vector<int> utu_id, vsu_id, utd_id, vsd_id;  // truncated-SVD factors
+  std::vector<int> rank_u, rank_d;                  // their ranks
+  std::vector<int> m2m_id;                          // pool8
+  std::vector<std::vector<int>> l2l_id;             // [parent level][octant]
+  std::vector<std::vector<int>> m2l_id;             // [level][343 offset code]
+  std::vector<double> vs_alpha, k_alpha;            // Laplace level scaling
+  // work arrays, sized for work_nr columns
+  int work_nr = 0;
+  void *qs = nullptr, *equ = nullptr, *chk = nullptr, *eqd = nullptr, *chku = nullptr,
+       *tmp = nullptr, *pairbuf = nullptr;
+  fmm::PassLists lists_by_nr[fmm::MAX_NR + 1];  // task lists per column count
+  // P2M targets (leaves at level >= 2) and per-leaf flags
+  int p2m_count = 0;
+  int32_t *d_p2m_box = nullptr;   // box ids
+  int32_t *d_p2m_off = nullptr;   // 0..p2m_count (each box is its own source)
+  int32_t *d_has_local = nullptr; // per leaf slot: level >= 2
+  // profiling: event pairs per phase, recorded during fmm_eval
+  int profiling = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_events;
+  std::vector<hipEvent_t> event_pool;
+  int64_t device_bytes = 0;
+  double setup_ms = 0;
+  std::vector<void *> allocs;      // everything to free
+};

@@ -1,0 +1,702 @@
+// HIP kernels of the kernel-independent FMM for gfx950 (MI355X) and the
+// evaluation driver behind fmm_eval.
+//
+// Pass order (Methods, Fast multipole method): P2M at the leaves, M2M
+// bottom-up, M2L (plus P2L for X-list boxes), L2L top-down, then at every
+// leaf L2P, M2P (W list) and P2P (U list).  All dense translations
+// (UC2E after P2M, M2M, M2L, L2L, DC2E) run through one gather-GEMM kernel on
+// MFMA; the point-kernel stages (P2P/L2P/M2P and P2M/P2L) run on the VALU
+// with sources staged through LDS.
+//
+// Kernel arithmetic: every kernel evaluation omits the 1/(4 pi) of the
+// Green's functions (the matching equations are invariant to it); the final
+// write multiplies by 1/(4 pi).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = floatx4; };
+template <> struct Vec4<double> { using type = doublex4; };
+
+__device__ inline floatx4 mfma_16x16x4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline doublex4 mfma_16x16x4(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ inline float dev_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double dev_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ inline float dev_exp(float x) { return __expf(x); }
+__device__ inline double dev_exp(double x) { return exp(x); }
+
+// ---------------------------------------------------------------------------
+// Setup helpers: bounding box, Morton keys, point gather.
+// ---------------------------------------------------------------------------
+__global__ void k_bbox_partial(const double *__restrict__ xyz, int64_t n, double *__restrict__ part) {
+  __shared__ double smin[3][256], smax[3][256];
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int bad = 0;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    for (int d = 0; d < 3; ++d) {
+      double v = xyz[i * 3 + d];
+      if (!isfinite(v)) bad = 1;
+      mn[d] = fmin(mn[d], v);
+      mx[d] = fmax(mx[d], v);
+    }
+  }
+  if (bad) { mn[0] = NAN; }
+  for (int d = 0; d < 3; ++d) { smin[d][threadIdx.x] = mn[d]; smax[d][threadIdx.x] = mx[d]; }
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int d = 0; d < 3; ++d) {
+        double a = smin[d][threadIdx.x], b = smin[d][threadIdx.x + s];
+        smin[d][threadIdx.x] = (isnan(a) || isnan(b)) ? NAN : fmin(a, b);
+        smax[d][threadIdx.x] = fmax(smax[d][threadIdx.x], smax[d][threadIdx.x + s]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int d = 0; d < 3; ++d) { part[blockIdx.x * 6 + d] = smin[d][0]; part[blockIdx.x * 6 + 3 + d] = smax[d][0]; }
+}
+
+__device__ inline uint64_t spread3(uint64_t v) {
+  v &= 0x1fffff;
+  v = (v | v << 32) & 0x1f00000000ffffull;
+  v = (v | v << 16) & 0x1f0000ff0000ffull;
+  v = (v | v << 8) & 0x100f00f00f00f00full;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+  v = (v | v << 2) & 0x1249249249249249ull;
+  return v;
+}
+
+__global__ void k_morton(const double *__restrict__ xyz, int64_t n, double lox, double loy, double loz,
+                         double W, uint64_t *__restrict__ keys, int32_t *__restrict__ idx) {
+  int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= n) return;
+  const double lo[3] = {lox, loy, loz};
+  uint64_t c[3];
+  for (int d = 0; d < 3; ++d) {
+    double t = (xyz[i * 3 + d] - lo[d]) / W;
+    double f = floor(t * 2097152.0);
+    f = f < 0.0 ? 0.0 : (f > 2097151.0 ? 2097151.0 : f);
+    c[d] = (uint64_t)f;
+  }
+  keys[i] = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);
+  idx[i] = (int32_t)i;
+}
+
+template <typename T>
+__global__ void k_gather_points(const double *__restrict__ xyz, const int32_t *__restrict__ perm, int64_t n,
+                                double sx, double sy, double sz, T *__restrict__ pts) {
+  int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= n) return;
+  int64_t j = perm[i];
+  pts[i * 4 + 0] = (T)(xyz[j * 3 + 0] - sx);
+  pts[i * 4 + 1] = (T)(xyz[j * 3 + 1] - sy);
+  pts[i * 4 + 2] = (T)(xyz[j * 3 + 2] - sz);
+  pts[i * 4 + 3] = (T)0;
+}
+
+int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], double mx[3], bool *finite) {
+  int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  double *part = nullptr;
+  FMM_HIP_TRY(hipMalloc(&part, sizeof(double) * 6 * nb));
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(256), 0, s, xyz, n, part);
+  std::vector<double> h(6 * nb);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(part);
+  if (e != hipSuccess) { set_error(std::string("bbox: ") + hipGetErrorString(e)); return FMM_EHIP; }
+  *finite = true;
+  for (int d = 0; d < 3; ++d) { mn[d] = INFINITY; mx[d] = -INFINITY; }
+  for (int b = 0; b < nb; ++b)
+    for (int d = 0; d < 3; ++d) {
+      double a = h[b * 6 + d], c = h[b * 6 + 3 + d];
+      if (std::isnan(a) || std::isinf(a) || std::isinf(c)) *finite = false;
+      mn[d] = std::min(mn[d], a);
+      mx[d] = std::max(mx[d], c);
+    }
+  return FMM_OK;
+}
+
+// Morton keys + stable radix sort on the device; returns sorted keys and the
+// permutation on the host.
+int device_morton_sort(const double *xyz, int64_t n, const double lo[3], double W, hipStream_t s,
+                       std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out) {
+  uint64_t *k0 = nullptr, *k1 = nullptr;
+  int32_t *v0 = nullptr, *v1 = nullptr;
+  void *tmp = nullptr;
+  size_t tmp_bytes = 0;
+  int rc = FMM_OK;
+  auto fail = [&](const char *what, hipError_t e) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    rc = FMM_EHIP;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&k0, n * 8)) != hipSuccess || (e = hipMalloc(&k1, n * 8)) != hipSuccess ||
+      (e = hipMalloc(&v0, n * 4)) != hipSuccess || (e = hipMalloc(&v1, n * 4)) != hipSuccess) {
+    fail("morton alloc", e);
+  } else {
+    hipLaunchKernelGGL(k_morton, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xyz, n, lo[0], lo[1], lo[2], W, k0, v0);
+    e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, k0, k1, v0, v1, (size_t)n, 0, 63, s);
+    if (e == hipSuccess) e = hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 16));
+    if (e == hipSuccess) e = rocprim::radix_sort_pairs(tmp, tmp_bytes, k0, k1, v0, v1, (size_t)n, 0, 63, s);
+    std::vector<uint64_t> hk(n);
+    std::vector<int32_t> hv(n);
+    if (e == hipSuccess) e = hipMemcpyAsync(hk.data(), k1, n * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hv.data(), v1, n * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) fail("morton sort", e);
+    else {
+      keys_out.resize(n);
+      perm_out.resize(n);
+      for (int64_t i = 0; i < n; ++i) { keys_out[i] = (int64_t)hk[i]; perm_out[i] = hv[i]; }
+    }
+  }
+  (void)hipFree(k0); (void)hipFree(k1); (void)hipFree(v0); (void)hipFree(v1); (void)hipFree(tmp);
+  return rc;
+}
+
+int device_gather_points(const double *xyz, const int32_t *perm, int64_t n, const double shift[3], int prec,
+                         void *pts, hipStream_t s) {
+  if (n == 0) return FMM_OK;
+  dim3 g((unsigned)((n + 255) / 256));
+  if (prec == FMM_FP64)
+    hipLaunchKernelGGL(k_gather_points<double>, g, dim3(256), 0, s, xyz, perm, n, shift[0], shift[1], shift[2], (double *)pts);
+  else
+    hipLaunchKernelGGL(k_gather_points<float>, g, dim3(256), 0, s, xyz, perm, n, shift[0], shift[1], shift[2], (float *)pts);
+  FMM_HIP_TRY(hipGetLastError());
+  return FMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Gather-GEMM on MFMA:  Y[dst[c]] (op)= alpha * A * concat_s X[src[c*S+s]]
+// One workgroup (4 waves) computes all ld rows of a 64-column tile.  A is
+// pre-swizzled so that each lane loads the A operands of four consecutive
+// 16x16x4 MFMA k-steps with one 4-element vector load; B (the gathered
+// columns) is staged through LDS 64 k-values at a time.
+// Each wave owns RBW consecutive 16-row blocks and all four 16-column blocks.
+// ---------------------------------------------------------------------------
+template <typename T, int RBW>
+__global__ __launch_bounds__(256) void k_gemm(const GemmTask *__restrict__ tasks, const T *__restrict__ pool,
+                                              int64_t mat_stride, int S, int ld, int nrb, int K,
+                                              const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
+                                              const T *__restrict__ X, T *__restrict__ Y, int mode) {
+  using V4 = typename Vec4<T>::type;
+  const GemmTask tk = tasks[blockIdx.x];
+  const int KQ = (S * ld) >> 4;  // k-groups per row block of the stored matrix
+  const int KQK = K >> 4;         // k-groups actually read
+  const T *__restrict__ A = pool + (int64_t)tk.mat * mat_stride;
+  __shared__ T Bs[64][GEMM_NT + 1];
+  __shared__ int32_t s_src[GEMM_NT * 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < GEMM_NT * S; i += 256) {
+    int c = i / S;
+    s_src[i] = (c < tk.ncol) ? src[(int64_t)(tk.col0 + c) * S + (i - c * S)] : -1;
+  }
+  V4 acc[RBW][4];
+#pragma unroll
+  for (int r = 0; r < RBW; ++r)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[r][cb] = V4{0, 0, 0, 0};
+  __syncthreads();
+  const int scol = tid >> 2, spart = (tid & 3) * 16;
+  for (int kc = 0; kc < K; kc += 64) {
+    {
+      T vals[16];
+      const int k0 = kc + spart;
+      int row = -1, kk = 0;
+      if (k0 < K) {
+        int sg = k0 / ld;
+        kk = k0 - sg * ld;
+        row = s_src[scol * S + sg];
+      }
+      if (row >= 0) {
+        const V4 *p = reinterpret_cast<const V4 *>(X + (int64_t)row * ld + kk);
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          V4 v = p[q4];
+          vals[q4 * 4 + 0] = v[0]; vals[q4 * 4 + 1] = v[1]; vals[q4 * 4 + 2] = v[2]; vals[q4 * 4 + 3] = v[3];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) vals[e] = (T)0;
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) Bs[spart + e][scol] = vals[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) {
+      const int gkq = (kc >> 4) + kq;
+      if (gkq < KQK) {
+        V4 a[RBW];
+#pragma unroll
+        for (int r = 0; r < RBW; ++r) {
+          const int rb = wave * RBW + r;
+          if (rb < nrb) a[r] = *reinterpret_cast<const V4 *>(A + ((int64_t)(rb * KQ + gkq) * 64 + lane) * 4);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int kl = (kq * 4 + t) * 4 + (lane >> 4);
+          T b[4];
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) b[cb] = Bs[kl][cb * 16 + (lane & 15)];
+#pragma unroll
+          for (int r = 0; r < RBW; ++r) {
+            if (wave * RBW + r < nrb) {
+#pragma unroll
+              for (int cb = 0; cb < 4; ++cb) acc[r][cb] = mfma_16x16x4(a[r][t], b[cb], acc[r][cb]);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const T alpha = (T)tk.alpha;
+#pragma unroll
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = wave * RBW + r;
+    if (rb >= nrb) continue;
+    const int i0 = rb * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int c = cb * 16 + (lane & 15);
+      if (c >= tk.ncol) continue;
+      const int64_t row = dst[tk.col0 + c];
+      T *y = Y + row * ld + i0;
+      V4 v = acc[r][cb] * alpha;
+      if (mode == GEMM_STORE) {
+        *reinterpret_cast<V4 *>(y) = v;
+      } else if (mode == GEMM_ADD) {
+        V4 o = *reinterpret_cast<V4 *>(y);
+        *reinterpret_cast<V4 *>(y) = o + v;
+      } else {
+        atomicAdd(y + 0, v[0]); atomicAdd(y + 1, v[1]); atomicAdd(y + 2, v[2]); atomicAdd(y + 3, v[3]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Point-kernel evaluation.  KERN 0 = Laplace 1/r, 1 = Yukawa exp(-kappa r)/r.
+// g and f = -(1/r) dg/dr for a pair at squared distance r2 (0 for r2 == 0).
+// ---------------------------------------------------------------------------
+template <typename T, int KERN>
+__device__ inline void pair_gf(T r2, T kappa, T &g, T &f) {
+  const T invr = r2 > (T)0 ? dev_rsqrt(r2) : (T)0;
+  if (KERN == 0) {
+    g = invr;
+    f = invr * invr * invr;
+  } else {
+    const T r = r2 * invr;
+    const T e = dev_exp(-kappa * r);
+    g = e * invr;
+    f = ((T)1 + kappa * r) * e * invr * invr * invr;
+  }
+}
+
+// Fused leaf kernel: for every target of leaf `b`
+//   P2P over U(b), M2P over W(b) upward equivalent surfaces, L2P from b's
+//   downward equivalent surface.  Writes potential (and gradient) scaled by
+//   `scale` into the caller's order.
+template <typename T, int NR, int KERN>
+__global__ __launch_bounds__(256) void k_leaf_eval(
+    const int32_t *__restrict__ leaves, const T *__restrict__ pts, const T *__restrict__ qs, int64_t N,
+    const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end, const T *__restrict__ box_geom,
+    const T *__restrict__ surf, int nsurf, int ld, const int32_t *__restrict__ u_off,
+    const int32_t *__restrict__ u_idx, const int32_t *__restrict__ w_off, const int32_t *__restrict__ w_idx,
+    const T *__restrict__ equ, const T *__restrict__ eqd, const int32_t *__restrict__ has_local,
+    const int32_t *__restrict__ perm, T *__restrict__ pot, T *__restrict__ grad, T kappa, T scale) {
+  __shared__ T sx[256], sy[256], sz[256], sq[NR][256];
+  __shared__ T red[NR * 4][256];
+  const int slot = blockIdx.x;
+  const int b = leaves[slot];
+  const int tb = box_begin[b], te = box_end[b];
+  const int m = te - tb;
+  const int tid = threadIdx.x;
+  const int lpg = m <= 64 ? 64 : (m <= 128 ? 128 : 256);
+  const int G = 256 / lpg;
+  const int g = tid / lpg, tl = tid - g * lpg;
+  const T ue_r = (T)ALPHA_UE, de_r = (T)ALPHA_DE;
+
+  for (int t0 = 0; t0 < m; t0 += lpg) {
+    const int ti = t0 + tl;
+    const bool active = ti < m;
+    T xi = 0, yi = 0, zi = 0;
+    if (active) {
+      xi = pts[(int64_t)(tb + ti) * 4 + 0];
+      yi = pts[(int64_t)(tb + ti) * 4 + 1];
+      zi = pts[(int64_t)(tb + ti) * 4 + 2];
+    }
+    T ap[NR], agx[NR], agy[NR], agz[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) ap[r] = agx[r] = agy[r] = agz[r] = (T)0;
+
+    auto consume = [&](int cnt) {
+      for (int j = g; j < cnt; j += G) {
+        const T dx = xi - sx[j], dy = yi - sy[j], dz = zi - sz[j];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        T gg, ff;
+        pair_gf<T, KERN>(r2, kappa, gg, ff);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const T qj = sq[r][j];
+          ap[r] += gg * qj;
+          const T fq = ff * qj;
+          agx[r] -= fq * dx;
+          agy[r] -= fq * dy;
+          agz[r] -= fq * dz;
+        }
+      }
+    };
+
+    // P2P over U(b)
+    for (int u = u_off[slot]; u < u_off[slot + 1]; ++u) {
+      const int a = u_idx[u];
+      const int sb = box_begin[a], se = box_end[a];
+      for (int c0 = sb; c0 < se; c0 += 256) {
+        const int j = c0 + tid;
+        if (j < se) {
+          sx[tid] = pts[(int64_t)j * 4 + 0];
+          sy[tid] = pts[(int64_t)j * 4 + 1];
+          sz[tid] = pts[(int64_t)j * 4 + 2];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) sq[r][tid] = qs[(int64_t)r * N + j];
+        }
+        __syncthreads();
+        consume(min(256, se - c0));
+        __syncthreads();
+      }
+    }
+    // M2P over W(b), then L2P from b's own downward equivalent surface
+    const int wend = w_off[slot + 1];
+    const int nsrc_box = wend - w_off[slot] + (has_local[slot] ? 1 : 0);
+    for (int k = 0; k < nsrc_box; ++k) {
+      const bool own = (w_off[slot] + k) >= wend;
+      const int a = own ? b : w_idx[w_off[slot] + k];
+      const T cx = box_geom[a * 4 + 0], cy = box_geom[a * 4 + 1], cz = box_geom[a * 4 + 2];
+      const T rr = box_geom[a * 4 + 3] * (own ? de_r : ue_r);
+      const T *dens = (own ? eqd : equ) + (int64_t)a * NR * ld;
+      for (int c0 = 0; c0 < nsurf; c0 += 256) {
+        const int j = c0 + tid;
+        if (j < nsurf) {
+          sx[tid] = cx + rr * surf[j * 4 + 0];
+          sy[tid] = cy + rr * surf[j * 4 + 1];
+          sz[tid] = cz + rr * surf[j * 4 + 2];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) sq[r][tid] = dens[(int64_t)r * ld + j];
+        }
+        __syncthreads();
+        consume(min(256, nsurf - c0));
+        __syncthreads();
+      }
+    }
+    // combine the G source groups in a fixed order
+    if (G > 1) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        red[r * 4 + 0][tid] = ap[r];
+        red[r * 4 + 1][tid] = agx[r];
+        red[r * 4 + 2][tid] = agy[r];
+        red[r * 4 + 3][tid] = agz[r];
+      }
+      __syncthreads();
+      if (g == 0) {
+        for (int h = 1; h < G; ++h) {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            ap[r] += red[r * 4 + 0][tid + h * lpg];
+            agx[r] += red[r * 4 + 1][tid + h * lpg];
+            agy[r] += red[r * 4 + 2][tid + h * lpg];
+            agz[r] += red[r * 4 + 3][tid + h * lpg];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (g == 0 && active) {
+      const int64_t o = perm[tb + ti];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        pot[(int64_t)r * N + o] = ap[r] * scale;
+        if (grad) {
+          T *gp = grad + ((int64_t)r * N + o) * 3;
+          gp[0] = agx[r] * scale;
+          gp[1] = agy[r] * scale;
+          gp[2] = agz[r] * scale;
+        }
+      }
+    }
+  }
+}
+
+// Surface kernel: potential at the surface points (radius `alpha` * h) of
+// box tbox[slot] from the points of the leaves src_idx[src_off[slot] ..].
+// Y[(box*NR + r)*ld + i] (mode 0: store, 1: add).
+template <typename T, int NR, int KERN>
+__global__ __launch_bounds__(256) void k_surf_eval(
+    const int32_t *__restrict__ tbox, const int32_t *__restrict__ src_off, const int32_t *__restrict__ src_idx,
+    const T *__restrict__ pts, const T *__restrict__ qs, int64_t N, const int32_t *__restrict__ box_begin,
+    const int32_t *__restrict__ box_end, const T *__restrict__ box_geom, const T *__restrict__ surf, int nsurf,
+    int ld, T alpha, T *__restrict__ Y, int mode, T kappa) {
+  __shared__ T sx[256], sy[256], sz[256], sq[NR][256];
+  const int slot = blockIdx.x;
+  const int b = tbox[slot];
+  const int tid = threadIdx.x;
+  const T cx = box_geom[b * 4 + 0], cy = box_geom[b * 4 + 1], cz = box_geom[b * 4 + 2];
+  const T rr = box_geom[b * 4 + 3] * alpha;
+  for (int i0 = 0; i0 < nsurf; i0 += 512) {
+    T tx[2], ty[2], tz[2];
+    T acc[2][NR];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = i0 + tid + h * 256;
+      const int ii = i < nsurf ? i : 0;
+      tx[h] = cx + rr * surf[ii * 4 + 0];
+      ty[h] = cy + rr * surf[ii * 4 + 1];
+      tz[h] = cz + rr * surf[ii * 4 + 2];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[h][r] = (T)0;
+    }
+    for (int s = src_off[slot]; s < src_off[slot + 1]; ++s) {
+      const int a = src_idx[s];
+      const int sb = box_begin[a], se = box_end[a];
+      for (int c0 = sb; c0 < se; c0 += 256) {
+        const int j = c0 + tid;
+        if (j < se) {
+          sx[tid] = pts[(int64_t)j * 4 + 0];
+          sy[tid] = pts[(int64_t)j * 4 + 1];
+          sz[tid] = pts[(int64_t)j * 4 + 2];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) sq[r][tid] = qs[(int64_t)r * N + j];
+        }
+        __syncthreads();
+        const int cnt = min(256, se - c0);
+        for (int j2 = 0; j2 < cnt; ++j2) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const T dx = tx[h] - sx[j2], dy = ty[h] - sy[j2], dz = tz[h] - sz[j2];
+            T gg, ff;
+            pair_gf<T, KERN>(dx * dx + dy * dy + dz * dz, kappa, gg, ff);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[h][r] += gg * sq[r][j2];
+          }
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = i0 + tid + h * 256;
+      if (i < nsurf) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          T *y = Y + ((int64_t)b * NR + r) * ld + i;
+          if (mode == 0) *y = acc[h][r];
+          else *y += acc[h][r];
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_permute(const T *__restrict__ q, const int32_t *__restrict__ perm, int64_t N, int nr,
+                          T *__restrict__ qs) {
+  int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= N) return;
+  const int64_t j = perm[i];
+  for (int r = 0; r < nr; ++r) qs[(int64_t)r * N + i] = q[(int64_t)r * N + j];
+}
+
+template <typename T>
+__global__ void k_fill_zero(T *__restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = (T)0;
+}
+
+// chk[box] += sum over the box's M2L pairs (fixed order) of pairbuf[pair].
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_reduce(const int32_t *__restrict__ tgt, const int32_t *__restrict__ off,
+                                                     const int32_t *__restrict__ pairs, const T *__restrict__ pairbuf,
+                                                     T *__restrict__ chk, int nr, int ld) {
+  const int slot = blockIdx.x;
+  const int b = tgt[slot];
+  const int p0 = off[slot], p1 = off[slot + 1];
+  for (int e = threadIdx.x; e < nr * ld; e += 256) {
+    const int r = e / ld, i = e - r * ld;
+    T s = (T)0;
+    for (int p = p0; p < p1; ++p) s += pairbuf[((int64_t)pairs[p] * nr + r) * ld + i];
+    chk[((int64_t)b * nr + r) * ld + i] += s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation driver
+// ---------------------------------------------------------------------------
+template <typename T, int RBW>
+static void launch_gemm_rbw(const GemmBatch &bt, const T *pool, int64_t mstride, int ld, int nrb, const T *X, T *Y,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm<T, RBW>), dim3(bt.ntask), dim3(256), 0, s, bt.d_tasks, pool, mstride, bt.S, ld, nrb,
+                     bt.klen, bt.d_src, bt.d_dst, X, Y, bt.mode);
+}
+
+template <typename T>
+static int launch_gemm(fmm_plan *P, const GemmBatch &bt, const T *X, T *Y, hipStream_t s) {
+  if (bt.ntask == 0) return FMM_OK;
+  const int ld = P->ld;
+  const int nrb = bt.nrb;
+  const int rbw = (nrb + 3) / 4;
+  const T *pool = (const T *)(bt.pool == 0 ? P->pool1 : P->pool8);
+  const int64_t mstride = (int64_t)ld * ld * (bt.pool == 0 ? 1 : 8);
+  switch (rbw) {
+    case 1: launch_gemm_rbw<T, 1>(bt, pool, mstride, ld, nrb, X, Y, s); break;
+    case 2: launch_gemm_rbw<T, 2>(bt, pool, mstride, ld, nrb, X, Y, s); break;
+    case 3: launch_gemm_rbw<T, 3>(bt, pool, mstride, ld, nrb, X, Y, s); break;
+    case 4: launch_gemm_rbw<T, 4>(bt, pool, mstride, ld, nrb, X, Y, s); break;
+    case 5: launch_gemm_rbw<T, 5>(bt, pool, mstride, ld, nrb, X, Y, s); break;
+    case 6: launch_gemm_rbw<T, 6>(bt, pool, mstride, ld, nrb, X, Y, s); break;
+    case 7: launch_gemm_rbw<T, 7>(bt, pool, mstride, ld, nrb, X, Y, s); break;
+    case 8: launch_gemm_rbw<T, 8>(bt, pool, mstride, ld, nrb, X, Y, s); break;
+    default: set_error("expansion order too large for the GEMM kernel"); return FMM_EINVAL;
+  }
+  FMM_HIP_TRY(hipGetLastError());
+  return FMM_OK;
+}
+
+int ensure_lists(fmm_plan *P, int nr);   // host planner
+int ensure_work(fmm_plan *P, int nr);
+
+template <typename T, int NR, int KERN>
+static int eval_chunk(fmm_plan *P, const T *q, T *pot, T *grad, hipStream_t s) {
+  const DevTree &D = P->dt;
+  const int64_t N = P->n;
+  const int ld = P->ld;
+  const PassLists &L = P->lists_by_nr[NR];
+  T *qs = (T *)P->qs, *equ = (T *)P->equ, *chk = (T *)P->chk, *eqd = (T *)P->eqd, *chku = (T *)P->chku,
+    *tmp = (T *)P->tmp;
+  const T kappa = (T)P->kappa;
+  int rc;
+  hipEvent_t ev = prof_begin(P, s);
+  hipLaunchKernelGGL(k_permute<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, q, D.perm, N, NR, qs);
+  FMM_HIP_TRY(hipGetLastError());
+  prof_end(P, FMM_PHASE_PERMUTE, ev, s);
+  const bool far = D.maxlevel >= 2;
+  if (far) {
+    const int64_t nwork = (int64_t)D.nbox * NR * ld;
+    // P2M: upward check potentials of the leaves at level >= 2
+    ev = prof_begin(P, s);
+    if (P->p2m_count > 0)
+      hipLaunchKernelGGL((k_surf_eval<T, NR, KERN>), dim3(P->p2m_count), dim3(256), 0, s, P->d_p2m_box,
+                         P->d_p2m_off, P->d_p2m_box, (const T *)D.pts, qs, N, D.box_begin, D.box_end,
+                         (const T *)D.box_geom, (const T *)P->surf, P->nsurf, ld, (T)ALPHA_UC, chku, 0, kappa);
+    FMM_HIP_TRY(hipGetLastError());
+    prof_end(P, FMM_PHASE_P2M, ev, s);
+    // upward pass, deepest level first: M2M into the parents' check
+    // potentials, then check -> equivalent (U^T, then V S^-1) for the level
+    for (int l = D.maxlevel; l >= 2; --l) {
+      if (L.m2m[l].ntask) {
+        ev = prof_begin(P, s);
+        if ((rc = launch_gemm<T>(P, L.m2m[l], equ, chku, s))) return rc;
+        prof_end(P, FMM_PHASE_M2M, ev, s);
+      }
+      ev = prof_begin(P, s);
+      if ((rc = launch_gemm<T>(P, L.ut_u[l], chku, tmp, s))) return rc;
+      if ((rc = launch_gemm<T>(P, L.vs_u[l], tmp, equ, s))) return rc;
+      prof_end(P, FMM_PHASE_UC2E, ev, s);
+    }
+    // P2L over X lists (after zeroing the downward check potentials)
+    ev = prof_begin(P, s);
+    hipLaunchKernelGGL(k_fill_zero<T>, dim3(1024), dim3(256), 0, s, chk, nwork);
+    if (D.nxbox > 0)
+      hipLaunchKernelGGL((k_surf_eval<T, NR, KERN>), dim3(D.nxbox), dim3(256), 0, s, D.x_box, D.x_off, D.x_idx,
+                         (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom,
+                         (const T *)P->surf, P->nsurf, ld, (T)ALPHA_DC, chk, 1, kappa);
+    FMM_HIP_TRY(hipGetLastError());
+    prof_end(P, FMM_PHASE_P2L, ev, s);
+    // M2L into pair slots, then a fixed-order sum per target box
+    ev = prof_begin(P, s);
+    if ((rc = launch_gemm<T>(P, L.m2l, equ, (T *)P->pairbuf, s))) return rc;
+    prof_end(P, FMM_PHASE_M2L, ev, s);
+    ev = prof_begin(P, s);
+    if (D.nvbox > 0)
+      hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.nvbox), dim3(256), 0, s, D.v_tgt, D.v_off, D.v_pair,
+                         (const T *)P->pairbuf, chk, NR, ld);
+    FMM_HIP_TRY(hipGetLastError());
+    prof_end(P, FMM_PHASE_M2L_SUM, ev, s);
+    // downward pass, coarsest level first: L2L into the check potential,
+    // then check -> equivalent
+    for (int l = 2; l <= D.maxlevel; ++l) {
+      if (L.l2l[l].ntask) {
+        ev = prof_begin(P, s);
+        if ((rc = launch_gemm<T>(P, L.l2l[l], eqd, chk, s))) return rc;
+        prof_end(P, FMM_PHASE_L2L, ev, s);
+      }
+      ev = prof_begin(P, s);
+      if ((rc = launch_gemm<T>(P, L.ut_d[l], chk, tmp, s))) return rc;
+      if ((rc = launch_gemm<T>(P, L.vs_d[l], tmp, eqd, s))) return rc;
+      prof_end(P, FMM_PHASE_DC2E, ev, s);
+    }
+  }
+  const T scale = (T)(1.0 / (4.0 * M_PI));
+  ev = prof_begin(P, s);
+  if (D.nleaf > 0)
+    hipLaunchKernelGGL((k_leaf_eval<T, NR, KERN>), dim3(D.nleaf), dim3(256), 0, s, D.leaves, (const T *)D.pts, qs, N,
+                       D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)P->surf, P->nsurf, ld, D.u_off,
+                       D.u_idx, D.w_off, D.w_idx, equ, eqd, P->d_has_local, D.perm, pot, grad, kappa, scale);
+  FMM_HIP_TRY(hipGetLastError());
+  prof_end(P, FMM_PHASE_LEAF, ev, s);
+  return FMM_OK;
+}
+
+template <typename T, int KERN>
+static int eval_nr(fmm_plan *P, int nr, const T *q, T *pot, T *grad, hipStream_t s) {
+  switch (nr) {
+    case 1: return eval_chunk<T, 1, KERN>(P, q, pot, grad, s);
+    case 2: return eval_chunk<T, 2, KERN>(P, q, pot, grad, s);
+    case 3: return eval_chunk<T, 3, KERN>(P, q, pot, grad, s);
+    case 4: return eval_chunk<T, 4, KERN>(P, q, pot, grad, s);
+  }
+  set_error("bad column count");
+  return FMM_EINVAL;
+}
+
+template <typename T>
+static int eval_typed(fmm_plan *P, const T *q, int nrhs, T *pot, T *grad, hipStream_t s) {
+  const int64_t N = P->n;
+  for (int c0 = 0; c0 < nrhs; c0 += MAX_NR) {
+    const int nr = std::min(MAX_NR, nrhs - c0);
+    int rc;
+    if ((rc = ensure_work(P, nr))) return rc;
+    if ((rc = ensure_lists(P, nr))) return rc;
+    const T *qc = q + (int64_t)c0 * N;
+    T *pc = pot + (int64_t)c0 * N;
+    T *gc = grad ? grad + (int64_t)c0 * N * 3 : nullptr;
+    rc = (P->kernel == FMM_YUKAWA) ? eval_nr<T, 1>(P, nr, qc, pc, gc, s) : eval_nr<T, 0>(P, nr, qc, pc, gc, s);
+    if (rc) return rc;
+  }
+  return FMM_OK;
+}
+
+int eval_dispatch(fmm_plan *P, const void *q, int nrhs, void *pot, void *grad, hipStream_t s) {
+  if (P->precision == FMM_FP64) return eval_typed<double>(P, (const double *)q, nrhs, (double *)pot, (double *)grad, s);
+  return eval_typed<float>(P, (const float *)q, nrhs, (float *)pot, (float *)grad, s);
+}
+
+}  // namespace fmm

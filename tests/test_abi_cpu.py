@@ -1,0 +1,61 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+declared in include/*.h, and rejects bad arguments before touching a GPU."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2103_01048_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", src, re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("fmm_setup", "fmm_eval", "fmm_free", "fmm_info", "fmm_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("args,frag", [
+    ((None, 10, 0, 0.0, 6, 64, 1), "xyz"),
+    ((None, -1, 0, 0.0, 6, 64, 1), "n out of range"),
+    ((1, 10, 7, 0.0, 6, 64, 1), "kernel"),
+    ((1, 10, 1, -0.1, 6, 64, 1), "kappa"),
+    ((1, 10, 1, float("nan"), 6, 64, 1), "kappa"),
+    ((1, 10, 0, 0.0, 1, 64, 1), "p must"),
+    ((1, 10, 0, 0.0, 17, 64, 1), "p must"),
+    ((1, 10, 0, 0.0, 6, 0, 1), "ncrit"),
+    ((1, 10, 0, 0.0, 6, 64, 9), "precision"),
+])
+def test_setup_rejects_bad_arguments(args, frag):
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    ptr = ctypes.c_void_p(args[0]) if args[0] else None
+    rc = L.fmm_setup(ptr, *args[1:], None, ctypes.byref(h))
+    assert rc == _lib.FMM_EINVAL
+    assert frag in L.fmm_last_error().decode()
+    assert not h.value
+
+
+def test_eval_rejects_null_plan():
+    L = _lib.lib()
+    assert L.fmm_eval(None, None, 1, None, None, None) == _lib.FMM_EINVAL

@@ -1,0 +1,164 @@
+"""GPU parity of fmm_setup / fmm_eval against the FP64 oracle.
+
+Integer work (Morton keys, sort permutation, boxes, U/V/W/X lists) must be
+bit-exact; floating-point results are compared by relative L2 error.
+Tolerances: FP64 single leaf (the exact direct sum up to rounding) 1e-12;
+FP64 KIFMM against the FP64 KIFMM oracle on the same tree, p and SVD cutoff
+1e-8 (only rounding order and the SVD routine differ); FP32 against the FP64
+direct sum 1e-4 (the accuracy bar of the single-precision path)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct as D
+from oracle import kifmm, tree as T
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+KAPPA = 0.125
+
+
+def _plan(x, **kw):
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    return FMMPlan(torch.tensor(x, dtype=torch.float64, device="cuda"), **kw)
+
+
+def _eval(plan, q, gradient=True):
+    torch = require_gpu()
+    pot, grad = plan.eval(torch.tensor(q, device="cuda"), gradient=gradient)
+    torch.cuda.synchronize()
+    return pot.double().cpu().numpy(), (grad.double().cpu().numpy() if grad is not None else None)
+
+
+def _clouds():
+    rng = np.random.default_rng(21)
+    x, _ = synth.unit_sphere_cloud(8192, seed=0)
+    yield "sphere8192", x, 64
+    yield "uniform", rng.uniform(0, 1, (3000, 3)), 20
+    c = np.concatenate([rng.normal(0, 0.01, (700, 3)), rng.uniform(-1, 1, (700, 3))])
+    yield "clustered", c, 16
+    yield "duplicates", np.concatenate([np.zeros((40, 3)), rng.uniform(0, 1, (200, 3))]), 8
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_tree_bit_exact(case):
+    name, x, ncrit = list(_clouds())[case]
+    print(f"[tree] case={name} n={len(x)} ncrit={ncrit}", flush=True)
+    plan = _plan(x, p=4, ncrit=ncrit, precision="fp64")
+    g = plan.tree()
+    o = T.build_tree(x, ncrit)
+    lo, W = T.root_cube(x)
+    assert np.array_equal(g["lo"], lo) and g["W_root"] == W
+    assert np.array_equal(g["keys"], o.keys)
+    assert np.array_equal(g["perm"], o.perm)
+    assert np.array_equal(g["level"], o.level)
+    assert np.array_equal(g["anchor"], o.anchor)
+    for k in ("begin", "end", "parent", "child_begin"):
+        assert np.array_equal(g[k], getattr(o, k)), k
+    assert np.array_equal(g["nchild"], o.nchild)
+    assert g["U"] == o.U and g["V"] == o.V and g["W"] == o.W_ and g["X"] == o.X
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_single_leaf_is_direct_sum(kernel, precision, tol):
+    x, q = synth.unit_sphere_cloud(300, seed=22)
+    print(f"[single-leaf] {kernel} {precision}", flush=True)
+    plan = _plan(x, kernel=kernel, kappa=KAPPA, p=4, ncrit=512, precision=precision)
+    pot, grad = _eval(plan, q)
+    p0, g0 = D.direct(x, x, q, kernel, KAPPA)
+    assert D.rel_l2(pot, p0) < tol
+    assert D.rel_l2(grad, g0) < tol
+
+
+@pytest.mark.parametrize("kernel,kappa", [("laplace", 0.0), ("yukawa", 2.0)])
+def test_fp64_matches_kifmm_oracle(kernel, kappa):
+    """Same tree, surfaces, p and SVD cutoff as the oracle's pass-by-pass KIFMM."""
+    x, q = synth.unit_sphere_cloud(4000, seed=23)
+    print(f"[fp64-vs-kifmm] {kernel}", flush=True)
+    plan = _plan(x, kernel=kernel, kappa=kappa, p=5, ncrit=32, precision="fp64")
+    pot, grad = _eval(plan, q)
+    r = kifmm.evaluate(x, q, kernel, kappa, p=5, ncrit=32, tau=1e-11)
+    assert D.rel_l2(pot, r.pot) < 1e-8
+    assert D.rel_l2(grad, r.grad) < 1e-8
+    p0, g0 = D.direct(x, x, q, kernel, kappa)
+    assert D.rel_l2(pot, p0) < 1e-4
+
+
+def test_config0_fp64_laplace_vs_direct():
+    """8,192 points on the unit sphere, densities U[-1,1], Laplace, p=6,
+    ncrit=64, FP64; potential and gradient against the O(N^2) sum."""
+    x, q = synth.unit_sphere_cloud(8192, seed=0)
+    plan = _plan(x, kernel="laplace", p=6, ncrit=64, precision="fp64")
+    pot, grad = _eval(plan, q)
+    p0, g0 = D.direct(x, x, q)
+    ep, eg = D.rel_l2(pot, p0), D.rel_l2(grad, g0)
+    print(f"[config0] pot {ep:.3e} grad {eg:.3e}", flush=True)
+    assert ep < 5e-6 and eg < 5e-6
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_surface_cloud_vs_direct(kernel, precision):
+    """Sphere-union surface cloud (40 spheres, 24k points), p=8; every
+    target against the FP64 direct sum."""
+    su = synth.sphere_union_spheres(40, seed=24, box=20.0)
+    v, t = synth.sphere_union_mesh(su, 8000, seed=24)
+    x = synth.three_point_cloud(v, t)
+    q = np.random.default_rng(24).standard_normal(len(x))
+    plan = _plan(x, kernel=kernel, kappa=KAPPA, p=8, ncrit=64, precision=precision)
+    pot, grad = _eval(plan, q)
+    p0, g0 = D.direct(x, x, q, kernel, KAPPA)
+    ep, eg = D.rel_l2(pot, p0), D.rel_l2(grad, g0)
+    print(f"[surface] {kernel} {precision} pot {ep:.3e} grad {eg:.3e}", flush=True)
+    assert ep < 1e-4 and eg < 1e-4
+
+
+def test_multi_column_matches_single_columns():
+    torch = require_gpu()
+    x, _ = synth.unit_sphere_cloud(5000, seed=25)
+    rng = np.random.default_rng(25)
+    Q = rng.standard_normal((6, len(x)))
+    plan = _plan(x, kernel="yukawa", kappa=KAPPA, p=5, ncrit=40, precision="fp64")
+    pot, grad = plan.eval(torch.tensor(Q, device="cuda"))
+    torch.cuda.synchronize()
+    for c in range(6):
+        p1, g1 = _eval(plan, Q[c])
+        np.testing.assert_allclose(pot[c].cpu().numpy(), p1, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(grad[c].cpu().numpy(), g1, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_bitwise_deterministic(precision):
+    x, q = synth.unit_sphere_cloud(6000, seed=26)
+    plan = _plan(x, kernel="laplace", p=6, ncrit=48, precision=precision)
+    a = _eval(plan, q)
+    b = _eval(plan, q)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_empty_and_duplicates():
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    plan = FMMPlan(torch.zeros((0, 3), dtype=torch.float64, device="cuda"), p=4, ncrit=8)
+    pot, grad = plan.eval(torch.zeros(0, device="cuda"))
+    assert pot.numel() == 0
+    x = np.concatenate([np.zeros((30, 3)), np.random.default_rng(27).uniform(0, 1, (500, 3))])
+    q = np.ones(len(x))
+    pl = _plan(x, p=5, ncrit=8, precision="fp64")
+    pot, grad = _eval(pl, q)
+    p0, g0 = D.direct(x, x, q)
+    assert np.all(np.isfinite(pot)) and np.all(np.isfinite(grad))
+    assert D.rel_l2(pot, p0) < 1e-4
+
+
+def test_nonfinite_input_rejected():
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, FmmError
+    x = torch.zeros((10, 3), dtype=torch.float64, device="cuda")
+    x[3, 1] = float("nan")
+    with pytest.raises(FmmError):
+        FMMPlan(x)
