@@ -110,6 +110,9 @@ typedef struct {
   int64_t n_p2p_interactions; /* sum over leaves of targets x U-list sources */
   int64_t device_bytes;  /* device memory held by the plan */
   double setup_ms;       /* wall time of fmm_setup */
+  int64_t n_far_interactions; /* leaf targets x surface points (M2P + L2P) */
+  int32_t rank_up;       /* kept singular values of the upward check-to-equivalent map (max over levels) */
+  int32_t rank_down;     /* same, downward */
 } fmm_info_t;
 
 int fmm_info(const fmm_plan *plan, fmm_info_t *out);
@@ -132,8 +135,11 @@ int fmm_get_tree(const fmm_plan *plan, int64_t *perm, int64_t *keys, int32_t *le
 int fmm_get_root(const fmm_plan *plan, double *lo3, double *width);
 
 /* Per-phase timing with HIP events recorded on the evaluation stream.
- * fmm_set_profiling(plan, 1) makes later fmm_eval calls record an event
- * pair around each phase; fmm_get_phase_times synchronises on those events,
+ * fmm_set_profiling(plan, mask) makes later fmm_eval calls record an event
+ * pair around every launch group of each phase k with bit k set in `mask`
+ * (0 switches timing off, FMM_PHASE_ALL times every phase; each event pair
+ * costs a few microseconds of stream time); fmm_get_phase_times synchronises
+ * on those events,
  * writes the accumulated milliseconds and launch counts of the first
  * `nphase` phases (FMM_PHASE_COUNT at most) and clears them. */
 enum {
@@ -147,7 +153,8 @@ enum {
   FMM_PHASE_L2L = 7,     /* parent downward density -> child check (MFMA) */
   FMM_PHASE_DC2E = 8,    /* downward check -> equivalent (MFMA) */
   FMM_PHASE_LEAF = 9,    /* P2P + M2P + L2P at the leaves, unpermute, 1/(4 pi) */
-  FMM_PHASE_COUNT = 10
+  FMM_PHASE_COUNT = 10,
+  FMM_PHASE_ALL = 0x3ff
 };
 int fmm_set_profiling(fmm_plan *plan, int enable);
 int fmm_get_phase_times(fmm_plan *plan, double *ms, int64_t *launches, int nphase);

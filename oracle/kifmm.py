@@ -21,6 +21,11 @@ Readings (the paper leaves these open):
     M2L, W-list boxes through their upward equivalent densities (M2P),
     X-list boxes through their sources evaluated on the downward check
     surface (P2L), U-list leaves directly (P2P).
+  * With direct_small=True (the default), a W-list box holding at most n
+    points contributes its points directly instead of its n equivalent
+    points, and a leaf with at most n points takes its X-list sources
+    directly at its points instead of through its check surface: both are
+    exact and cheaper than the surface they replace.
 """
 from __future__ import annotations
 
@@ -130,7 +135,8 @@ class FMMResult:
     eqd: np.ndarray      # downward equivalent densities per box
 
 
-def evaluate(x, q, kernel="laplace", kappa=0.0, p=6, ncrit=64, tau=1e-14, t=None, ops=None):
+def evaluate(x, q, kernel="laplace", kappa=0.0, p=6, ncrit=64, tau=1e-14, t=None, ops=None,
+             direct_small=True):
     """FMM potential and gradient at every point from densities q (targets =
     sources = x; zero-distance pairs excluded).  Returns FMMResult in the
     caller's point order."""
@@ -171,7 +177,8 @@ def evaluate(x, q, kernel="laplace", kappa=0.0, p=6, ncrit=64, tau=1e-14, t=None
         for a in t.V[b]:
             o = tuple(int(v) for v in (t.anchor[a] - t.anchor[b]))
             chk[b] += _m2l_matrix(ops, t, p, grid, l, o, kernel, kappa) @ equ[a]
-        if t.X[b]:
+        x_direct = direct_small and t.is_leaf(b) and (t.end[b] - t.begin[b]) <= n
+        if t.X[b] and not x_direct:
             dc = ALPHA_DC * hh[b] * grid + cen[b]
             for a in t.X[b]:
                 s = slice(t.begin[a], t.end[a])
@@ -195,11 +202,17 @@ def evaluate(x, q, kernel="laplace", kappa=0.0, p=6, ncrit=64, tau=1e-14, t=None
         de = ALPHA_DE * hh[b] * grid + cen[b]
         pot[s] += kernel_matrix(tx, de, kernel, kappa) @ eqd[b]
         grad[s] += np.einsum("ijd,j->id", kernel_grad(tx, de, kernel, kappa), eqd[b])
+        direct = list(t.U[b])
         for a in t.W_[b]:
+            if direct_small and t.end[a] - t.begin[a] <= n:
+                direct.append(a)
+                continue
             ue = ALPHA_UE * hh[a] * grid + cen[a]
             pot[s] += kernel_matrix(tx, ue, kernel, kappa) @ equ[a]
             grad[s] += np.einsum("ijd,j->id", kernel_grad(tx, ue, kernel, kappa), equ[a])
-        for a in t.U[b]:
+        if direct_small and (t.end[b] - t.begin[b]) <= n:
+            direct += list(t.X[b])
+        for a in direct:
             sa = slice(t.begin[a], t.end[a])
             pot[s] += kernel_matrix(tx, xs[sa], kernel, kappa) @ qs[sa]
             grad[s] += np.einsum("ijd,j->id", kernel_grad(tx, xs[sa], kernel, kappa), qs[sa])

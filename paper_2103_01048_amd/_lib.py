@@ -32,6 +32,7 @@ class FmmInfo(ctypes.Structure):
         ("max_level", ctypes.c_int32), ("n_surf", ctypes.c_int32), ("n_u_pairs", ctypes.c_int64),
         ("n_v_pairs", ctypes.c_int64), ("n_w_pairs", ctypes.c_int64), ("n_x_pairs", ctypes.c_int64),
         ("n_p2p_interactions", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double),
+        ("n_far_interactions", ctypes.c_int64), ("rank_up", ctypes.c_int32), ("rank_down", ctypes.c_int32),
     ]
 
 

@@ -272,6 +272,21 @@ static void kernel_matrix(const std::vector<double> &grid, int n, const double c
   }
 }
 
+// C (m x p, ldc) = A (m x k, lda) * B (k x p, ldb)
+static void matmul_rect(int m, int k, int p, const double *A, int lda, const double *B, int ldb, double *C, int ldc) {
+  std::vector<double> row(p);
+  for (int i = 0; i < m; ++i) {
+    std::fill(row.begin(), row.end(), 0.0);
+    for (int kk = 0; kk < k; ++kk) {
+      const double a = A[(size_t)i * lda + kk];
+      if (a == 0.0) continue;
+      const double *b = B + (size_t)kk * ldb;
+      for (int j = 0; j < p; ++j) row[j] += a * b[j];
+    }
+    std::copy(row.begin(), row.end(), C + (size_t)i * ldc);
+  }
+}
+
 static void matmul(int n, const double *A, const double *B, int ldb, double *C, int ldc) {
   // C (n x n, ldc) = A (n x n) * B (n x n, ldb)
   std::vector<double> row(n);
@@ -351,12 +366,18 @@ static int precompute_typed(fmm_plan *P) {
   else if (maxl >= 2) glevels.push_back(-1);
   auto gh = [&](int gl) { return gl < 0 ? 1.0 : h_of(gl); };
 
-  // kinds: 0 UT_u, 1 VS_u, 2 UT_d, 3 VS_d, 4 M2M stack (pool8), 5 L2L, 6 M2L
+  // kinds: 0 UT_u, 1 VS_u, 2 UT_d, 3 VS_d, 4 M2M (pool8), 5 L2L, 6 M2L.
+  // M2M, L2L and M2L act between singular coordinates of the check
+  // potentials (c = U^T chk, equivalent density = V S^-1 c):
+  //   M2M_c  = U_u^T(l)   K(parent upward check, child c upward equiv) V_u S_u^-1(l+1)
+  //   L2L_c  = U_d^T(l+1) K(child c downward check, parent downward equiv) V_d S_d^-1(l)
+  //   M2L_o  = U_d^T(l)   K(downward check, upward equiv at offset o) V_u S_u^-1(l)
   struct Job { int kind, l, oct, code; };
   std::vector<Job> jobs;
   for (int gl : glevels) {
     for (int k = 0; k < 4; ++k) jobs.push_back({k, gl, 0, 0});
-    if (gl < 0 || has_children[gl]) {
+    const bool kids = gl < 0 || (gl < maxl && has_children[gl]);
+    if (kids) {
       jobs.push_back({4, gl, 0, 0});
       for (int c = 0; c < 8; ++c) jobs.push_back({5, gl, c, 0});
     }
@@ -370,7 +391,9 @@ static int precompute_typed(fmm_plan *P) {
   // truncated SVD factors of the check-from-equivalent matrices
   std::map<int, std::vector<double>> ut_u, vs_u, ut_d, vs_d;
   std::map<int, int> rk_u, rk_d;
-  for (int gl : glevels) {
+  std::vector<int> svd_levels = glevels;
+  if (yuk && maxl >= 2) svd_levels.push_back(maxl + 1);  // never used; keeps l+1 lookups defined
+  for (int gl : svd_levels) {
     ut_u[gl].assign((size_t)n * n, 0); vs_u[gl].assign((size_t)n * n, 0);
     ut_d[gl].assign((size_t)n * n, 0); vs_d[gl].assign((size_t)n * n, 0);
     rk_u[gl] = rk_d[gl] = 0;
@@ -393,6 +416,10 @@ static int precompute_typed(fmm_plan *P) {
     });
     for (size_t i = 0; i < pj.size(); ++i) (pj[i].first == 0 ? rk_u : rk_d)[pj[i].second] = ranks[i];
   }
+  auto r16 = [](int r) { return std::max(16, ((r + 15) / 16) * 16); };
+  // the child level of a geometry level (Laplace: the unit level itself,
+  // with the child factors scaled by 1/2 below)
+  auto child_of = [&](int gl) { return gl < 0 ? gl : gl + 1; };
   std::vector<int> id1(jobs.size(), -1), id8(jobs.size(), -1);
   int64_t c1 = 0, c8 = 0;
   for (size_t j = 0; j < jobs.size(); ++j) {
@@ -411,59 +438,67 @@ static int precompute_typed(fmm_plan *P) {
       case 2: swizzle<T>(ut_d[jb.l].data(), n, n, n, ld, ld, dst); break;
       case 3: swizzle<T>(vs_d[jb.l].data(), n, n, n, ld, ld, dst); break;
       case 4: {
-        // parent upward check surface from the 8 children's upward equivalent
-        // surfaces; block c occupies columns [c*ld, c*ld + n)
-        std::vector<double> big((size_t)n * 8 * ld, 0.0), Km((size_t)n * n);
+        const int cl = child_of(jb.l);
+        const int rp = rk_u[jb.l], rc = rk_u[cl], seg = r16(rc);
+        const double cs = jb.l < 0 ? 0.5 : 1.0;  // Laplace: child V S^-1 at half the unit size
+        std::vector<double> big((size_t)rp * 8 * seg, 0.0), Km((size_t)n * n), KV((size_t)n * rc), M((size_t)rp * rc);
         for (int c = 0; c < 8; ++c) {
           const double off[3] = {(((c >> 2) & 1) ? 0.5 : -0.5) * h, (((c >> 1) & 1) ? 0.5 : -0.5) * h,
                                  ((c & 1) ? 0.5 : -0.5) * h};
           kernel_matrix(grid, n, zero, ALPHA_UC * h, off, ALPHA_UE * h * 0.5, yuk, P->kappa, Km.data(), n);
-          for (int i = 0; i < n; ++i)
-            std::copy(Km.begin() + (size_t)i * n, Km.begin() + (size_t)(i + 1) * n,
-                      big.begin() + (size_t)i * 8 * ld + c * ld);
+          matmul_rect(n, n, rc, Km.data(), n, vs_u[cl].data(), n, KV.data(), rc);
+          matmul_rect(rp, n, rc, ut_u[jb.l].data(), n, KV.data(), rc, M.data(), rc);
+          for (int i = 0; i < rp; ++i)
+            for (int k = 0; k < rc; ++k) big[(size_t)i * 8 * seg + c * seg + k] = cs * M[(size_t)i * rc + k];
         }
-        swizzle<T>(big.data(), n, 8 * ld, 8 * ld, ld, 8 * ld, dst);
+        swizzle<T>(big.data(), rp, 8 * seg, 8 * seg, ld, 8 * seg, dst);
         break;
       }
       case 5: {
-        // child (octant oct, half-width h/2) downward check surface from the
-        // parent's downward equivalent surface
+        const int cl = child_of(jb.l);
         const int c = jb.oct;
+        const int rp = rk_d[jb.l], rc = rk_d[cl];
         const double off[3] = {(((c >> 2) & 1) ? 0.5 : -0.5) * h, (((c >> 1) & 1) ? 0.5 : -0.5) * h,
                                ((c & 1) ? 0.5 : -0.5) * h};
-        std::vector<double> Km((size_t)n * n);
+        std::vector<double> Km((size_t)n * n), KV((size_t)n * rp), M((size_t)rc * rp);
         kernel_matrix(grid, n, off, ALPHA_DC * h * 0.5, zero, ALPHA_DE * h, yuk, P->kappa, Km.data(), n);
-        swizzle<T>(Km.data(), n, n, n, ld, ld, dst);
+        matmul_rect(n, n, rp, Km.data(), n, vs_d[jb.l].data(), n, KV.data(), rp);
+        matmul_rect(rc, n, rp, ut_d[cl].data(), n, KV.data(), rp, M.data(), rp);
+        swizzle<T>(M.data(), rc, rp, rp, ld, ld, dst);
         break;
       }
       default: {
         const int code = jb.code;
         const double o[3] = {2.0 * h * (code / 49 - 3), 2.0 * h * ((code / 7) % 7 - 3), 2.0 * h * (code % 7 - 3)};
-        std::vector<double> Km((size_t)n * n);
+        const int ru = rk_u[jb.l], rd = rk_d[jb.l];
+        std::vector<double> Km((size_t)n * n), KV((size_t)n * ru), M((size_t)rd * ru);
         kernel_matrix(grid, n, zero, ALPHA_DC * h, o, ALPHA_UE * h, yuk, P->kappa, Km.data(), n);
-        swizzle<T>(Km.data(), n, n, n, ld, ld, dst);
+        matmul_rect(n, n, ru, Km.data(), n, vs_u[jb.l].data(), n, KV.data(), ru);
+        matmul_rect(rd, n, ru, ut_d[jb.l].data(), n, KV.data(), ru, M.data(), ru);
+        swizzle<T>(M.data(), rd, ru, ru, ld, ld, dst);
       }
     }
   });
-  // per-level matrix ids, ranks and scale factors (Laplace: pinv of K/h is
-  // h * pinv(K), so the V S^-1 factor carries h and kernel matrices 1/h)
+  // per-level matrix ids, ranks and scale factors.  Laplace: K(h) = K(1)/h,
+  // so V S^-1 at level l is h_l times the unit factor; M2M, L2L and M2L in
+  // singular coordinates are scale-free.
   const int L1 = maxl + 1;
   P->utu_id.assign(L1, -1); P->vsu_id.assign(L1, -1); P->utd_id.assign(L1, -1); P->vsd_id.assign(L1, -1);
-  P->rank_u.assign(L1, 0); P->rank_d.assign(L1, 0);
+  P->rank_u.assign(L1 + 1, 0); P->rank_d.assign(L1 + 1, 0);
   P->m2m_id.assign(L1, -1);
   P->l2l_id.assign(L1, std::vector<int>(8, -1));
   P->m2l_id.assign(L1, std::vector<int>(343, -1));
   P->vs_alpha.assign(L1, 1); P->k_alpha.assign(L1, 1);
+  for (int l = 2; l <= maxl; ++l) {
+    const int gl = yuk ? l : -1;
+    P->rank_u[l] = rk_u[gl];
+    P->rank_d[l] = rk_d[gl];
+    P->vs_alpha[l] = yuk ? 1.0 : h_of(l);
+  }
   for (size_t j = 0; j < jobs.size(); ++j) {
     const Job &jb = jobs[j];
     for (int l = 2; l <= maxl; ++l) {
       if (jb.l >= 0 && jb.l != l) continue;
-      const double h = h_of(l);
-      const bool unit = jb.l < 0;
-      P->vs_alpha[l] = unit ? h : 1.0;
-      P->k_alpha[l] = unit ? 1.0 / h : 1.0;
-      P->rank_u[l] = rk_u[jb.l];
-      P->rank_d[l] = rk_d[jb.l];
       switch (jb.kind) {
         case 0: P->utu_id[l] = id1[j]; break;
         case 1: P->vsu_id[l] = id1[j]; break;
@@ -512,44 +547,97 @@ static int upload_lists(fmm_plan *P) {
   int rc;
   if ((rc = upload(P, (void **)&D.box_begin, bb))) return rc;
   if ((rc = upload(P, (void **)&D.box_end, be))) return rc;
-  std::vector<int32_t> leaves, uo = {0}, ui, wo = {0}, wi, hl, p2m, p2mo = {0};
-  int64_t inter = 0;
+  // Leaf work.  Near sources are point ranges: the U list, W-list boxes
+  // holding at most n_surf points (their points are cheaper and exact
+  // compared with their equivalent surface) and, for leaves with at most
+  // n_surf targets, the X list (evaluated at the targets instead of on the
+  // leaf's check surface).  Far sources are surfaces: the remaining W-list
+  // boxes (upward equivalent) and the leaf's own downward equivalent surface.
+  const int64_t ns = P->nsurf;
+  std::vector<int32_t> leaves, no = {0}, wo = {0}, wi, hl, p2m, p2mo = {0};
+  std::vector<int32_t> nr_;  // near ranges, (begin, end) pairs
+  std::vector<int32_t> items;
+  struct Item { int64_t cost; int32_t slot, t0; int split; };
+  std::vector<Item> item_list;
+  std::vector<char> x_direct(nb, 0);
+  int64_t inter = 0, far_inter = 0;
   for (int64_t b = 0; b < nb; ++b) {
     if (P->nchild[b]) continue;
+    const int32_t slot = (int32_t)leaves.size();
     leaves.push_back((int32_t)b);
     const int64_t m = P->end[b] - P->begin[b];
-    for (int64_t k = P->loff[0][b]; k < P->loff[0][b + 1]; ++k) {
-      const int64_t a = P->lidx[0][k];
-      ui.push_back((int32_t)a);
+    auto add_range = [&](int64_t a) {
+      nr_.push_back((int32_t)P->begin[a]);
+      nr_.push_back((int32_t)P->end[a]);
       inter += m * (P->end[a] - P->begin[a]);
+    };
+    const size_t r0 = nr_.size();
+    for (int64_t k = P->loff[0][b]; k < P->loff[0][b + 1]; ++k) add_range(P->lidx[0][k]);
+    int64_t nwm = 0;
+    for (int64_t k = P->loff[2][b]; k < P->loff[2][b + 1]; ++k) {
+      const int64_t a = P->lidx[2][k];
+      if (P->end[a] - P->begin[a] <= ns) add_range(a);
+      else { wi.push_back((int32_t)a); ++nwm; }
     }
-    uo.push_back((int32_t)ui.size());
-    for (int64_t k = P->loff[2][b]; k < P->loff[2][b + 1]; ++k) wi.push_back((int32_t)P->lidx[2][k]);
+    if (m <= ns) {
+      x_direct[b] = 1;
+      for (int64_t k = P->loff[3][b]; k < P->loff[3][b + 1]; ++k) add_range(P->lidx[3][k]);
+    }
+    // sort this leaf's ranges and merge the contiguous ones (the ranges are
+    // disjoint; neighbouring boxes are often adjacent along the Morton curve)
+    {
+      std::vector<std::pair<int32_t, int32_t>> rg;
+      for (size_t k = r0; k < nr_.size(); k += 2) rg.push_back({nr_[k], nr_[k + 1]});
+      std::sort(rg.begin(), rg.end());
+      nr_.resize(r0);
+      for (auto &x : rg) {
+        if (nr_.size() > r0 && nr_.back() == x.first) nr_.back() = x.second;
+        else { nr_.push_back(x.first); nr_.push_back(x.second); }
+      }
+    }
+    const int64_t near_pts = [&]() { int64_t t = 0; for (size_t k = r0; k < nr_.size(); k += 2) t += nr_[k + 1] - nr_[k]; return t; }();
+    no.push_back((int32_t)(nr_.size() / 2));
     wo.push_back((int32_t)wi.size());
     hl.push_back(P->level[b] >= 2 ? 1 : 0);
+    far_inter += m * ns * (nwm + (P->level[b] >= 2 ? 1 : 0));
     if (P->level[b] >= 2) { p2m.push_back((int32_t)b); p2mo.push_back((int32_t)p2m.size()); }
+    // tiles of 64 targets; a tile of at most 32 targets runs in split mode
+    // (both half-waves take the same targets and alternate sources)
+    const int64_t cost = near_pts + ns * (nwm + (P->level[b] >= 2 ? 1 : 0));
+    for (int64_t t0 = 0; t0 < m; t0 += 64) {
+      const int split = (m - t0) <= 32 ? 2 : 1;
+      item_list.push_back({cost / split, slot, (int32_t)t0, split});
+    }
   }
+  // longest tiles first, so that the last wave of work is made of short tiles
+  std::stable_sort(item_list.begin(), item_list.end(),
+                   [](const Item &x, const Item &y) { return x.cost > y.cost; });
+  for (const Item &it : item_list) { items.push_back(it.slot); items.push_back(it.t0 | (it.split << 24)); }
   P->leaf_ids = leaves;
   P->p2p_inter = inter;
+  P->far_inter = far_inter;
   D.nleaf = (int)leaves.size();
+  D.nitems = (int)(items.size() / 2);
   if ((rc = upload(P, (void **)&D.leaves, leaves))) return rc;
-  if ((rc = upload(P, (void **)&D.u_off, uo))) return rc;
-  if ((rc = upload(P, (void **)&D.u_idx, ui))) return rc;
+  if ((rc = upload(P, (void **)&D.items, items))) return rc;
+  if ((rc = upload(P, (void **)&D.near_off, no))) return rc;
+  if ((rc = upload(P, (void **)&D.near_rng, nr_))) return rc;
   if ((rc = upload(P, (void **)&D.w_off, wo))) return rc;
   if ((rc = upload(P, (void **)&D.w_idx, wi))) return rc;
   if ((rc = upload(P, (void **)&P->d_has_local, hl))) return rc;
   P->p2m_count = (int)p2m.size();
   if ((rc = upload(P, (void **)&P->d_p2m_box, p2m))) return rc;
   if ((rc = upload(P, (void **)&P->d_p2m_off, p2mo))) return rc;
-  // X lists
+  // P2L: X lists of the boxes whose X list is not evaluated directly
   std::vector<int32_t> xb, xo = {0}, xi;
   for (int64_t b = 0; b < nb; ++b) {
-    if (P->loff[3][b + 1] == P->loff[3][b]) continue;
+    if (P->loff[3][b + 1] == P->loff[3][b] || x_direct[b]) continue;
     xb.push_back((int32_t)b);
     for (int64_t k = P->loff[3][b]; k < P->loff[3][b + 1]; ++k) xi.push_back((int32_t)P->lidx[3][k]);
     xo.push_back((int32_t)xi.size());
   }
   D.nxbox = (int)xb.size();
+  P->p2l_boxes = xb;
   if ((rc = upload(P, (void **)&D.x_box, xb))) return rc;
   if ((rc = upload(P, (void **)&D.x_off, xo))) return rc;
   if ((rc = upload(P, (void **)&D.x_idx, xi))) return rc;
@@ -577,7 +665,7 @@ static int upload_lists(fmm_plan *P) {
   }
   std::vector<int32_t> vt, vo = {0}, vpp;
   for (int64_t b = 0; b < nb; ++b) {
-    if (per_tgt[b].empty()) continue;
+    if (P->level[b] < 2) continue;  // every box at level >= 2 gets its sum (possibly empty)
     // reduction order: by source box id (the V-list order)
     std::sort(per_tgt[b].begin(), per_tgt[b].end(),
               [&](int32_t x, int32_t y) { return P->vpair_src[x] < P->vpair_src[y]; });
@@ -635,6 +723,8 @@ int ensure_lists(fmm_plan *P, int nr) {
   if (L.nr == nr) return FMM_OK;
   const int maxl = P->dt.maxlevel;
   const int ld = P->ld;
+  const int64_t nb = (int64_t)P->level.size();
+  const int64_t ns = P->nsurf;
   int rc;
   std::vector<int32_t> src, dst;
   auto cols_for = [&](const std::vector<int64_t> &boxes_src, const std::vector<int64_t> &boxes_dst) {
@@ -646,77 +736,109 @@ int ensure_lists(fmm_plan *P, int nr) {
       }
   };
   auto r16 = [](int r) { return std::max(16, ((r + 15) / 16) * 16); };
+  auto oct_of = [&](int64_t b) {
+    return (int)(((P->anchor[3 * b] & 1) << 2) | ((P->anchor[3 * b + 1] & 1) << 1) | (P->anchor[3 * b + 2] & 1));
+  };
+  int maxru = 16, maxrd = 16;
+  for (int l = 2; l <= maxl; ++l) { maxru = std::max(maxru, r16(P->rank_u[l])); maxrd = std::max(maxrd, r16(P->rank_d[l])); }
   const int L1 = std::max(maxl + 1, 0);
-  L.m2m.assign(L1, GemmBatch()); L.ut_u.assign(L1, GemmBatch()); L.vs_u.assign(L1, GemmBatch());
-  L.l2l.assign(L1, GemmBatch()); L.ut_d.assign(L1, GemmBatch()); L.vs_d.assign(L1, GemmBatch());
+  L.m2m.assign(L1, GemmBatch()); L.ut_u.assign(L1, GemmBatch()); L.l2l.assign(L1, GemmBatch());
+  L.vs_u = GemmBatch(); L.ut_dx = GemmBatch(); L.vs_d = GemmBatch(); L.m2l = GemmBatch();
+  L.vs_u.nrb = ld / 16; L.vs_u.klen = maxru;
+  L.ut_dx.nrb = maxrd / 16; L.ut_dx.klen = ld; L.ut_dx.mode = GEMM_ADD;
+  L.vs_d.nrb = ld / 16; L.vs_d.klen = maxrd;
+  L.m2l.nrb = maxrd / 16; L.m2l.klen = maxru;
+  // boxes whose upward equivalent density is evaluated (M2P sources)
+  std::vector<char> need_equ(nb, 0);
+  for (int64_t b = 0; b < nb; ++b) {
+    if (P->nchild[b]) continue;
+    for (int64_t k = P->loff[2][b]; k < P->loff[2][b + 1]; ++k) {
+      const int64_t a = P->lidx[2][k];
+      if (P->end[a] - P->begin[a] > ns) need_equ[a] = 1;
+    }
+  }
   for (int l = 2; l <= maxl; ++l) {
-    std::vector<int64_t> all;
-    for (int64_t b = P->level_begin[l]; b < P->level_begin[l + 1]; ++b) all.push_back(b);
-    // M2M: parent upward check potential from the children's equivalent densities
-    {
+    std::vector<int64_t> leaves, all;
+    for (int64_t b = P->level_begin[l]; b < P->level_begin[l + 1]; ++b) {
+      all.push_back(b);
+      if (!P->nchild[b]) leaves.push_back(b);
+    }
+    // upward: M2M from the children's singular coordinates (non-leaf boxes)
+    if (l < maxl) {
       GemmBatch &bt = L.m2m[l];
       bt.S = 8;
       bt.pool = 1;
-      bt.nrb = ld / 16;
-      bt.klen = 8 * ld;
+      bt.seg = r16(P->rank_u[l + 1]);
+      bt.kq_stride = 8 * bt.seg / 16;
+      bt.nrb = r16(P->rank_u[l]) / 16;
+      bt.klen = 8 * bt.seg;
       src.clear(); dst.clear();
       for (int64_t b : all) {
         if (!P->nchild[b]) continue;
         int64_t ch[8];
         for (int c = 0; c < 8; ++c) ch[c] = -1;
-        for (int k = 0; k < P->nchild[b]; ++k) {
-          const int64_t c = P->child_begin[b] + k;
-          const int oct = (int)(((P->anchor[3 * c] & 1) << 2) | ((P->anchor[3 * c + 1] & 1) << 1) | (P->anchor[3 * c + 2] & 1));
-          ch[oct] = c;
-        }
+        for (int k = 0; k < P->nchild[b]; ++k) ch[oct_of(P->child_begin[b] + k)] = P->child_begin[b] + k;
         for (int r = 0; r < nr; ++r) {
           for (int c = 0; c < 8; ++c) src.push_back(ch[c] < 0 ? -1 : (int32_t)(ch[c] * nr + r));
           dst.push_back((int32_t)(b * nr + r));
         }
       }
-      if (!dst.empty()) add_columns(bt, P->m2m_id[l], P->k_alpha[l], src, dst);
+      if (!dst.empty()) add_columns(bt, P->m2m_id[l], 1.0, src, dst);
       if ((rc = finish_batch(P, bt))) return rc;
     }
-    // upward check -> equivalent: U^T then V S^-1
-    cols_for(all, all);
-    L.ut_u[l].nrb = r16(P->rank_u[l]) / 16; L.ut_u[l].klen = ld;
-    add_columns(L.ut_u[l], P->utu_id[l], 1.0, src, dst);
+    // upward: leaves' check potentials to singular coordinates
+    cols_for(leaves, leaves);
+    L.ut_u[l].nrb = r16(P->rank_u[l]) / 16;
+    L.ut_u[l].klen = ld;
+    if (!dst.empty()) add_columns(L.ut_u[l], P->utu_id[l], 1.0, src, dst);
     if ((rc = finish_batch(P, L.ut_u[l]))) return rc;
-    L.vs_u[l].nrb = ld / 16; L.vs_u[l].klen = r16(P->rank_u[l]);
-    add_columns(L.vs_u[l], P->vsu_id[l], P->vs_alpha[l], src, dst);
-    if ((rc = finish_batch(P, L.vs_u[l]))) return rc;
-    // L2L (levels >= 3): child check += K * parent downward equivalent
+    // upward equivalent densities of the M2P sources
+    std::vector<int64_t> eb;
+    for (int64_t b : all) if (need_equ[b]) eb.push_back(b);
+    cols_for(eb, eb);
+    if (!dst.empty()) add_columns(L.vs_u, P->vsu_id[l], P->vs_alpha[l], src, dst);
+    // downward: L2L between singular coordinates (levels >= 3)
     if (l >= 3) {
       GemmBatch &bt = L.l2l[l];
       bt.mode = GEMM_ADD;
-      bt.nrb = ld / 16; bt.klen = ld;
+      bt.nrb = r16(P->rank_d[l]) / 16;
+      bt.klen = r16(P->rank_d[l - 1]);
       for (int oct = 0; oct < 8; ++oct) {
         std::vector<int64_t> bs, bd;
         for (int64_t b : all) {
-          const int o = (int)(((P->anchor[3 * b] & 1) << 2) | ((P->anchor[3 * b + 1] & 1) << 1) | (P->anchor[3 * b + 2] & 1));
-          if (o != oct) continue;
+          if (oct_of(b) != oct) continue;
           bs.push_back(P->parent[b]);
           bd.push_back(b);
         }
         if (bd.empty()) continue;
         cols_for(bs, bd);
-        add_columns(bt, P->l2l_id[l - 1][oct], P->k_alpha[l - 1], src, dst);
+        add_columns(bt, P->l2l_id[l - 1][oct], 1.0, src, dst);
       }
       if ((rc = finish_batch(P, bt))) return rc;
     }
-    // downward check -> equivalent
-    cols_for(all, all);
-    L.ut_d[l].nrb = r16(P->rank_d[l]) / 16; L.ut_d[l].klen = ld;
-    add_columns(L.ut_d[l], P->utd_id[l], 1.0, src, dst);
-    if ((rc = finish_batch(P, L.ut_d[l]))) return rc;
-    L.vs_d[l].nrb = ld / 16; L.vs_d[l].klen = r16(P->rank_d[l]);
-    add_columns(L.vs_d[l], P->vsd_id[l], P->vs_alpha[l], src, dst);
-    if ((rc = finish_batch(P, L.vs_d[l]))) return rc;
+    // downward equivalent densities of the leaves
+    cols_for(leaves, leaves);
+    if (!dst.empty()) add_columns(L.vs_d, P->vsd_id[l], P->vs_alpha[l], src, dst);
   }
+  // P2L boxes: their check potentials to singular coordinates (added)
+  {
+    std::vector<int64_t> xb;
+    for (int32_t b : P->p2l_boxes) xb.push_back(b);
+    std::stable_sort(xb.begin(), xb.end(), [&](int64_t x, int64_t y) { return P->level[x] < P->level[y]; });
+    size_t i = 0;
+    while (i < xb.size()) {
+      size_t j = i;
+      while (j < xb.size() && P->level[xb[j]] == P->level[xb[i]]) ++j;
+      std::vector<int64_t> part(xb.begin() + i, xb.begin() + j);
+      cols_for(part, part);
+      add_columns(L.ut_dx, P->utd_id[P->level[xb[i]]], 1.0, src, dst);
+      i = j;
+    }
+  }
+  if ((rc = finish_batch(P, L.vs_u))) return rc;
+  if ((rc = finish_batch(P, L.ut_dx))) return rc;
+  if ((rc = finish_batch(P, L.vs_d))) return rc;
   // M2L: pairs in GEMM order, tasks split at (level, offset) changes
-  L.m2l = GemmBatch();
-  L.m2l.nrb = ld / 16;
-  L.m2l.klen = ld;
   {
     const int64_t np = (int64_t)P->vpair_src.size();
     auto code_of = [&](int64_t j) {
@@ -737,7 +859,7 @@ int ensure_lists(fmm_plan *P, int nr) {
         }
         ++j;
       }
-      add_columns(L.m2l, P->m2l_id[l][code], P->k_alpha[l], src, dst);
+      add_columns(L.m2l, P->m2l_id[l][code], 1.0, src, dst);
       i = j;
     }
   }
@@ -758,20 +880,22 @@ int ensure_work(fmm_plan *P, int nr) {
   if ((rc = dev_alloc(P, &P->chk, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->eqd, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->chku, wbytes))) return rc;
-  if ((rc = dev_alloc(P, &P->tmp, wbytes))) return rc;
+  if ((rc = dev_alloc(P, &P->cu, wbytes))) return rc;
+  if ((rc = dev_alloc(P, &P->yd, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->pairbuf, (size_t)std::max<int64_t>(1, P->dt.nvpair) * nr * P->ld * es))) return rc;
   // padding rows/columns must hold zeros (the GEMM K dimension reads them)
   FMM_HIP_TRY(hipMemset(P->equ, 0, wbytes));
   FMM_HIP_TRY(hipMemset(P->chk, 0, wbytes));
   FMM_HIP_TRY(hipMemset(P->eqd, 0, wbytes));
   FMM_HIP_TRY(hipMemset(P->chku, 0, wbytes));
-  FMM_HIP_TRY(hipMemset(P->tmp, 0, wbytes));
+  FMM_HIP_TRY(hipMemset(P->cu, 0, wbytes));
+  FMM_HIP_TRY(hipMemset(P->yd, 0, wbytes));
   P->work_nr = nr;
   return FMM_OK;
 }
 
-hipEvent_t prof_begin(fmm_plan *P, hipStream_t s) {
-  if (!P->profiling) return nullptr;
+hipEvent_t prof_begin(fmm_plan *P, int phase, hipStream_t s) {
+  if (!((P->profiling >> phase) & 1)) return nullptr;
   hipEvent_t e = nullptr;
   if (!P->event_pool.empty()) {
     e = P->event_pool.back();
@@ -893,6 +1017,9 @@ int fmm_info(const fmm_plan *P, fmm_info_t *o) {
   o->n_p2p_interactions = P->p2p_inter;
   o->device_bytes = P->device_bytes;
   o->setup_ms = P->setup_ms;
+  o->n_far_interactions = P->far_inter;
+  for (size_t l = 0; l < P->rank_u.size(); ++l) o->rank_up = std::max(o->rank_up, (int32_t)P->rank_u[l]);
+  for (size_t l = 0; l < P->rank_d.size(); ++l) o->rank_down = std::max(o->rank_down, (int32_t)P->rank_d[l]);
   return FMM_OK;
 }
 
@@ -929,7 +1056,7 @@ int fmm_get_root(const fmm_plan *P, double *lo3, double *width) {
 
 int fmm_set_profiling(fmm_plan *P, int enable) {
   if (!P) { set_error("fmm_set_profiling: plan is NULL"); return FMM_EINVAL; }
-  P->profiling = enable ? 1 : 0;
+  P->profiling = enable & ((1 << FMM_PHASE_COUNT) - 1);
   return FMM_OK;
 }
 

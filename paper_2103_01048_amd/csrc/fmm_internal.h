@@ -20,7 +20,7 @@ constexpr int MAX_NR = 4;     // density columns handled by one kernel pass
 constexpr double ALPHA_UE = 1.05, ALPHA_UC = 2.95, ALPHA_DE = 2.95, ALPHA_DC = 1.05;
 
 void set_error(const std::string &msg);
-hipEvent_t prof_begin(fmm_plan *P, hipStream_t s);
+hipEvent_t prof_begin(fmm_plan *P, int phase, hipStream_t s);
 void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s);
 void pinv_tsvd(int n, const double *A, double tau, double *out);
 int tsvd_factors(int n, const double *A, double tau, double *UT, double *VS);
@@ -52,6 +52,8 @@ struct GemmBatch {
   int S = 1;                   // K segments per column
   int nrb = 0;                 // 16-row blocks of A that are computed
   int klen = 0;                // K extent actually read (multiple of 16)
+  int seg = 0;                 // K length of one segment (0: the work-array row length)
+  int kq_stride = 0;           // 16-wide k groups per stored row block (0: row length / 16)
   int mode = GEMM_STORE;
   int pool = 0;                // 0: single-segment matrix pool, 1: M2M pool
   int ntask = 0;
@@ -68,14 +70,14 @@ struct GemmBatch {
 // box * nr + r, so the lists depend on nr.
 struct PassLists {
   int nr = 0;
-  // per level l (index l, levels >= 2)
-  std::vector<GemmBatch> m2m;   // parent upward check from children (stacked K)
-  std::vector<GemmBatch> ut_u;  // upward check -> singular coordinates
-  std::vector<GemmBatch> vs_u;  // singular coordinates -> upward equivalent
-  std::vector<GemmBatch> l2l;   // child downward check += K * parent equivalent
-  std::vector<GemmBatch> ut_d;  // downward check -> singular coordinates
-  std::vector<GemmBatch> vs_d;  // singular coordinates -> downward equivalent
-  GemmBatch m2l;                // all levels, writes pair slots
+  // per level l (index l, levels >= 2), in singular coordinates c = U^T chk
+  std::vector<GemmBatch> m2m;   // parent c_u from the 8 children's c_u
+  std::vector<GemmBatch> ut_u;  // leaf upward check -> c_u
+  std::vector<GemmBatch> l2l;   // child c_d += L2L * parent c_d (levels >= 3)
+  GemmBatch vs_u;               // c_u -> upward equivalent (M2P sources), all levels
+  GemmBatch ut_dx;              // P2L check -> c_d (added), all levels
+  GemmBatch vs_d;               // c_d -> downward equivalent (leaves), all levels
+  GemmBatch m2l;                // all levels, c_u -> pair slots of c_d
 };
 
 struct DevTree {
@@ -88,12 +90,15 @@ struct DevTree {
   void *box_geom = nullptr;     // T4: centre xyz (shifted), half width
   int32_t *box_begin = nullptr, *box_end = nullptr;
   int32_t *leaves = nullptr;    // leaf box ids
-  int32_t *u_off = nullptr, *u_idx = nullptr;   // per leaf slot
-  int32_t *w_off = nullptr, *w_idx = nullptr;   // per leaf slot
+  int32_t *items = nullptr;     // (leaf slot, first target) per 64-target tile
+  int nitems = 0;
+  int32_t *near_off = nullptr;  // per leaf slot, into near_rng
+  int32_t *near_rng = nullptr;  // (begin, end) point ranges of near sources
+  int32_t *w_off = nullptr, *w_idx = nullptr;   // per leaf slot: M2P boxes
   int32_t *x_box = nullptr;     // boxes with a non-empty X list
   int32_t *x_off = nullptr, *x_idx = nullptr;
   int nxbox = 0;
-  int32_t *v_tgt = nullptr;     // boxes with a non-empty V list
+  int32_t *v_tgt = nullptr;     // boxes at level >= 2 (M2L sums)
   int32_t *v_off = nullptr;     // pair ids of each such box (CSR)
   int32_t *v_pair = nullptr;
   int nvbox = 0;
@@ -118,7 +123,8 @@ struct fmm_plan {
   std::vector<int64_t> lidx[4];
   std::vector<int32_t> leaf_ids;
   std::vector<int32_t> vpair_src, vpair_tgt;  // V pairs in GEMM order
-  int64_t p2p_inter = 0;
+  std::vector<int32_t> p2l_boxes;             // boxes whose X list goes through P2L
+  int64_t p2p_inter = 0, far_inter = 0;
   // device
   fmm::DevTree dt;
   void *surf = nullptr;            // T4 grid offsets in [-1,1]^3, nsurf entries
@@ -135,7 +141,9 @@ struct fmm_plan {
   // work arrays, sized for work_nr columns
   int work_nr = 0;
   void *qs = nullptr, *equ = nullptr, *chk = nullptr, *eqd = nullptr, *chku = nullptr,
-       *tmp = nullptr, *pairbuf = nullptr;
+       *cu = nullptr, *yd = nullptr, *pairbuf = nullptr;
+  // cu: upward check in singular coordinates (U_u^T chk); yd: downward
+  // check in singular coordinates (M2L sums + U_d^T chk)
   fmm::PassLists lists_by_nr[fmm::MAX_NR + 1];  // task lists per column count
   // P2M targets (leaves at level >= 2) and per-leaf flags
   int p2m_count = 0;
@@ -143,7 +151,7 @@ struct fmm_plan {
   int32_t *d_p2m_off = nullptr;   // 0..p2m_count (each box is its own source)
   int32_t *d_has_local = nullptr; // per leaf slot: level >= 2
   // profiling: event pairs per phase, recorded during fmm_eval
-  int profiling = 0;
+  int profiling = 0;               // bit k set: time phase k
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_events;
   std::vector<hipEvent_t> event_pool;
   int64_t device_bytes = 0;

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -41,6 +42,8 @@ __device__ inline float dev_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double dev_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ inline float dev_exp(float x) { return __expf(x); }
 __device__ inline double dev_exp(double x) { return exp(x); }
+__device__ inline float dev_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ inline double dev_exp2(double x) { return exp2(x); }
 
 // ---------------------------------------------------------------------------
 // Setup helpers: bounding box, Morton keys, point gather.
@@ -194,17 +197,21 @@ int device_gather_points(const double *xyz, const int32_t *perm, int64_t n, cons
 // ---------------------------------------------------------------------------
 template <typename T, int RBW>
 __global__ __launch_bounds__(256) void k_gemm(const GemmTask *__restrict__ tasks, const T *__restrict__ pool,
-                                              int64_t mat_stride, int S, int ld, int nrb, int K,
-                                              const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
-                                              const T *__restrict__ X, T *__restrict__ Y, int mode) {
+                                              int64_t mat_stride, int S, int seg, int KQ, int ld, int nrb,
+                                              int K, const int32_t *__restrict__ src,
+                                              const int32_t *__restrict__ dst, const T *__restrict__ X,
+                                              T *__restrict__ Y, int mode) {
+  // S segments of `seg` k-values per column (segment s of column c is row
+  // src[c*S+s] of X, leading dimension ld); KQ: 16-wide k groups per stored
+  // row block of A; K: k-values read; nrb: 16-row blocks computed.
   using V4 = typename Vec4<T>::type;
   const GemmTask tk = tasks[blockIdx.x];
-  const int KQ = (S * ld) >> 4;  // k-groups per row block of the stored matrix
   const int KQK = K >> 4;         // k-groups actually read
   const T *__restrict__ A = pool + (int64_t)tk.mat * mat_stride;
   __shared__ T Bs[64][GEMM_NT + 1];
   __shared__ int32_t s_src[GEMM_NT * 8];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = (int)blockIdx.y * 4 + (tid >> 6);  // row-block group of this wave
   for (int i = tid; i < GEMM_NT * S; i += 256) {
     int c = i / S;
     s_src[i] = (c < tk.ncol) ? src[(int64_t)(tk.col0 + c) * S + (i - c * S)] : -1;
@@ -222,8 +229,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask *__restrict__ tasks
       const int k0 = kc + spart;
       int row = -1, kk = 0;
       if (k0 < K) {
-        int sg = k0 / ld;
-        kk = k0 - sg * ld;
+        int sg = k0 / seg;
+        kk = k0 - sg * seg;
         row = s_src[scol * S + sg];
       }
       if (row >= 0) {
@@ -312,136 +319,174 @@ __device__ inline void pair_gf(T r2, T kappa, T &g, T &f) {
   }
 }
 
-// Fused leaf kernel: for every target of leaf `b`
-//   P2P over U(b), M2P over W(b) upward equivalent surfaces, L2P from b's
-//   downward equivalent surface.  Writes potential (and gradient) scaled by
-//   `scale` into the caller's order.
+// Fused leaf kernel.  One wave per tile of up to 64 targets of a leaf, one
+// target per lane.  Sources are read with wave-uniform addresses (scalar
+// loads) and broadcast to all lanes for free:
+//   near point ranges (U list, small W-list boxes, direct X list): P2P
+//   W-list upward equivalent surfaces: M2P
+//   the leaf's own downward equivalent surface: L2P
+// A tile of at most 32 targets runs split: both half-waves hold the same
+// targets and take alternate sources (vector loads, one per half), and the
+// halves are added at the end.  With one density column the source charge
+// travels in the fourth component of the point record.  Only a range that
+// contains the tile's own leaf can hold a source at zero distance, so only
+// that range pays for the exclusion test (points in different leaves have
+// different Morton cells; surfaces never touch the targets they serve).
+// Writes potential (and gradient) times `scale` in the caller's order.
+template <typename T, int KERN, bool CHECK, int NR>
+__device__ __forceinline__ void leaf_pair(T xi, T yi, T zi, T sx, T sy, T sz, const T (&qv)[NR], T kappa, T kl2,
+                                          T (&ap)[NR], T (&agx)[NR], T (&agy)[NR], T (&agz)[NR]) {
+  const T dx = xi - sx, dy = yi - sy, dz = zi - sz;
+  const T r2 = dx * dx + dy * dy + dz * dz;
+  T invr = dev_rsqrt(r2);
+  if (CHECK) invr = r2 > (T)0 ? invr : (T)0;
+  T g, f;
+  if (KERN == 0) {
+    g = invr;
+    f = invr * invr * invr;
+  } else {
+    const T r = r2 * invr;
+    g = dev_exp2(-kl2 * r) * invr;
+    f = ((T)1 + kappa * r) * g * (invr * invr);
+  }
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    ap[c] += g * qv[c];
+    const T fq = f * qv[c];
+    agx[c] -= fq * dx;
+    agy[c] -= fq * dy;
+    agz[c] -= fq * dz;
+  }
+}
+
 template <typename T, int NR, int KERN>
-__global__ __launch_bounds__(256) void k_leaf_eval(
-    const int32_t *__restrict__ leaves, const T *__restrict__ pts, const T *__restrict__ qs, int64_t N,
-    const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end, const T *__restrict__ box_geom,
-    const T *__restrict__ surf, int nsurf, int ld, const int32_t *__restrict__ u_off,
-    const int32_t *__restrict__ u_idx, const int32_t *__restrict__ w_off, const int32_t *__restrict__ w_idx,
+__global__ __launch_bounds__(64) void k_leaf_eval(
+    const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts,
+    const T *__restrict__ qs, int64_t N, const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end,
+    const T *__restrict__ box_geom, const T *__restrict__ surf, int nsurf, int ld, const int32_t *__restrict__ near_off,
+    const int32_t *__restrict__ near_rng, const int32_t *__restrict__ w_off, const int32_t *__restrict__ w_idx,
     const T *__restrict__ equ, const T *__restrict__ eqd, const int32_t *__restrict__ has_local,
     const int32_t *__restrict__ perm, T *__restrict__ pot, T *__restrict__ grad, T kappa, T scale) {
-  __shared__ T sx[256], sy[256], sz[256], sq[NR][256];
-  __shared__ T red[NR * 4][256];
-  const int slot = blockIdx.x;
+  using V4 = typename Vec4<T>::type;
+  const V4 *__restrict__ p4 = reinterpret_cast<const V4 *>(pts);
+  const V4 *__restrict__ s4 = reinterpret_cast<const V4 *>(surf);
+  const int slot = items[2 * blockIdx.x];
+  const int code = items[2 * blockIdx.x + 1];
+  const int split = code >> 24;
   const int b = leaves[slot];
-  const int tb = box_begin[b], te = box_end[b];
-  const int m = te - tb;
-  const int tid = threadIdx.x;
-  const int lpg = m <= 64 ? 64 : (m <= 128 ? 128 : 256);
-  const int G = 256 / lpg;
-  const int g = tid / lpg, tl = tid - g * lpg;
-  const T ue_r = (T)ALPHA_UE, de_r = (T)ALPHA_DE;
+  const int lb = box_begin[b], le = box_end[b];
+  const int tb = lb + (code & 0xffffff);
+  const int lane = threadIdx.x;
+  const int half = split == 2 ? (lane >> 5) : 0;
+  const int tl = split == 2 ? (lane & 31) : lane;
+  const int m = min(64 / split, le - tb);
+  const bool active = tl < m;
+  const V4 xv = p4[tb + (active ? tl : 0)];
+  const T xi = xv[0], yi = xv[1], zi = xv[2];
+  const T kl2 = kappa * (T)1.4426950408889634;  // kappa * log2(e)
+  T ap[NR], agx[NR], agy[NR], agz[NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) ap[c] = agx[c] = agy[c] = agz[c] = (T)0;
 
-  for (int t0 = 0; t0 < m; t0 += lpg) {
-    const int ti = t0 + tl;
-    const bool active = ti < m;
-    T xi = 0, yi = 0, zi = 0;
-    if (active) {
-      xi = pts[(int64_t)(tb + ti) * 4 + 0];
-      yi = pts[(int64_t)(tb + ti) * 4 + 1];
-      zi = pts[(int64_t)(tb + ti) * 4 + 2];
-    }
-    T ap[NR], agx[NR], agy[NR], agz[NR];
+  // near field: point ranges
+  const int u1 = near_off[slot + 1];
+  for (int u = near_off[slot]; u < u1; ++u) {
+    const int j0 = near_rng[2 * u], j1 = near_rng[2 * u + 1];
+    const bool self = j0 <= lb && le <= j1;
+    if (split == 1) {
+      auto body = [&](int j, auto chk) {
+        const V4 sp = p4[j];
+        T qv[NR];
+        if (NR == 1) qv[0] = sp[3];
+        else {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) ap[r] = agx[r] = agy[r] = agz[r] = (T)0;
-
-    auto consume = [&](int cnt) {
-      for (int j = g; j < cnt; j += G) {
-        const T dx = xi - sx[j], dy = yi - sy[j], dz = zi - sz[j];
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        T gg, ff;
-        pair_gf<T, KERN>(r2, kappa, gg, ff);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const T qj = sq[r][j];
-          ap[r] += gg * qj;
-          const T fq = ff * qj;
-          agx[r] -= fq * dx;
-          agy[r] -= fq * dy;
-          agz[r] -= fq * dz;
+          for (int c = 0; c < NR; ++c) qv[c] = qs[(int64_t)c * N + j];
         }
+        leaf_pair<T, KERN, decltype(chk)::value, NR>(xi, yi, zi, sp[0], sp[1], sp[2], qv, kappa, kl2, ap, agx, agy, agz);
+      };
+      if (self) {
+#pragma unroll 4
+        for (int j = j0; j < j1; ++j) body(j, std::true_type());
+      } else {
+#pragma unroll 8
+        for (int j = j0; j < j1; ++j) body(j, std::false_type());
       }
-    };
-
-    // P2P over U(b)
-    for (int u = u_off[slot]; u < u_off[slot + 1]; ++u) {
-      const int a = u_idx[u];
-      const int sb = box_begin[a], se = box_end[a];
-      for (int c0 = sb; c0 < se; c0 += 256) {
-        const int j = c0 + tid;
-        if (j < se) {
-          sx[tid] = pts[(int64_t)j * 4 + 0];
-          sy[tid] = pts[(int64_t)j * 4 + 1];
-          sz[tid] = pts[(int64_t)j * 4 + 2];
+    } else {
+      // split: lane half h takes sources j0 + h, j0 + h + 2, ...; an odd
+      // count leaves the last upper-half step with a zero charge
+      auto body = [&](int j, auto chk) {
+        const int jj = j + half;
+        const bool ok = jj < j1;
+        const V4 sp = p4[ok ? jj : j];
+        T qv[NR];
+        if (NR == 1) qv[0] = ok ? sp[3] : (T)0;
+        else {
 #pragma unroll
-          for (int r = 0; r < NR; ++r) sq[r][tid] = qs[(int64_t)r * N + j];
+          for (int c = 0; c < NR; ++c) qv[c] = ok ? qs[(int64_t)c * N + jj] : (T)0;
         }
-        __syncthreads();
-        consume(min(256, se - c0));
-        __syncthreads();
+        leaf_pair<T, KERN, decltype(chk)::value, NR>(xi, yi, zi, sp[0], sp[1], sp[2], qv, kappa, kl2, ap, agx, agy, agz);
+      };
+      if (self) {
+#pragma unroll 2
+        for (int j = j0; j < j1; j += 2) body(j, std::true_type());
+      } else {
+#pragma unroll 4
+        for (int j = j0; j < j1; j += 2) body(j, std::false_type());
       }
     }
-    // M2P over W(b), then L2P from b's own downward equivalent surface
-    const int wend = w_off[slot + 1];
-    const int nsrc_box = wend - w_off[slot] + (has_local[slot] ? 1 : 0);
-    for (int k = 0; k < nsrc_box; ++k) {
-      const bool own = (w_off[slot] + k) >= wend;
-      const int a = own ? b : w_idx[w_off[slot] + k];
-      const T cx = box_geom[a * 4 + 0], cy = box_geom[a * 4 + 1], cz = box_geom[a * 4 + 2];
-      const T rr = box_geom[a * 4 + 3] * (own ? de_r : ue_r);
-      const T *dens = (own ? eqd : equ) + (int64_t)a * NR * ld;
-      for (int c0 = 0; c0 < nsurf; c0 += 256) {
-        const int j = c0 + tid;
-        if (j < nsurf) {
-          sx[tid] = cx + rr * surf[j * 4 + 0];
-          sy[tid] = cy + rr * surf[j * 4 + 1];
-          sz[tid] = cz + rr * surf[j * 4 + 2];
+  }
+  // far field: W-list equivalent surfaces, then the own downward surface
+  const int w0 = w_off[slot], w1 = w_off[slot + 1];
+  const int nfar = w1 - w0 + (has_local[slot] ? 1 : 0);
+  for (int k = 0; k < nfar; ++k) {
+    const bool own = (w0 + k) >= w1;
+    const int a = own ? b : w_idx[w0 + k];
+    const T cx = box_geom[a * 4 + 0], cy = box_geom[a * 4 + 1], cz = box_geom[a * 4 + 2];
+    const T rr = box_geom[a * 4 + 3] * (own ? (T)ALPHA_DE : (T)ALPHA_UE);
+    const T *__restrict__ dens = (own ? eqd : equ) + (int64_t)a * NR * ld;
+    if (split == 1) {
+#pragma unroll 4
+      for (int j = 0; j < nsurf; ++j) {
+        const V4 g = s4[j];
+        T qv[NR];
 #pragma unroll
-          for (int r = 0; r < NR; ++r) sq[r][tid] = dens[(int64_t)r * ld + j];
-        }
-        __syncthreads();
-        consume(min(256, nsurf - c0));
-        __syncthreads();
+        for (int c = 0; c < NR; ++c) qv[c] = dens[(int64_t)c * ld + j];
+        leaf_pair<T, KERN, false, NR>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qv, kappa, kl2, ap,
+                                      agx, agy, agz);
+      }
+    } else {
+#pragma unroll 2
+      for (int j = 0; j < nsurf; j += 2) {
+        const int jj = j + half;
+        const bool ok = jj < nsurf;
+        const V4 g = s4[ok ? jj : j];
+        T qv[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) qv[c] = ok ? dens[(int64_t)c * ld + jj] : (T)0;
+        leaf_pair<T, KERN, false, NR>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qv, kappa, kl2, ap,
+                                      agx, agy, agz);
       }
     }
-    // combine the G source groups in a fixed order
-    if (G > 1) {
+  }
+  if (split == 2) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        red[r * 4 + 0][tid] = ap[r];
-        red[r * 4 + 1][tid] = agx[r];
-        red[r * 4 + 2][tid] = agy[r];
-        red[r * 4 + 3][tid] = agz[r];
-      }
-      __syncthreads();
-      if (g == 0) {
-        for (int h = 1; h < G; ++h) {
-#pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            ap[r] += red[r * 4 + 0][tid + h * lpg];
-            agx[r] += red[r * 4 + 1][tid + h * lpg];
-            agy[r] += red[r * 4 + 2][tid + h * lpg];
-            agz[r] += red[r * 4 + 3][tid + h * lpg];
-          }
-        }
-      }
-      __syncthreads();
+    for (int c = 0; c < NR; ++c) {
+      ap[c] += __shfl_xor(ap[c], 32);
+      agx[c] += __shfl_xor(agx[c], 32);
+      agy[c] += __shfl_xor(agy[c], 32);
+      agz[c] += __shfl_xor(agz[c], 32);
     }
-    if (g == 0 && active) {
-      const int64_t o = perm[tb + ti];
+  }
+  if (active && half == 0) {
+    const int64_t o = perm[tb + tl];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        pot[(int64_t)r * N + o] = ap[r] * scale;
-        if (grad) {
-          T *gp = grad + ((int64_t)r * N + o) * 3;
-          gp[0] = agx[r] * scale;
-          gp[1] = agy[r] * scale;
-          gp[2] = agz[r] * scale;
-        }
+    for (int c = 0; c < NR; ++c) {
+      pot[(int64_t)c * N + o] = ap[c] * scale;
+      if (grad) {
+        T *gp = grad + ((int64_t)c * N + o) * 3;
+        gp[0] = agx[c] * scale;
+        gp[1] = agy[c] * scale;
+        gp[2] = agz[c] * scale;
       }
     }
   }
@@ -517,13 +562,16 @@ __global__ __launch_bounds__(256) void k_surf_eval(
   }
 }
 
+// Densities into Morton order; with one column the density is also stored
+// as the fourth component of the sorted point record (read by k_leaf_eval).
 template <typename T>
 __global__ void k_permute(const T *__restrict__ q, const int32_t *__restrict__ perm, int64_t N, int nr,
-                          T *__restrict__ qs) {
+                          T *__restrict__ qs, T *__restrict__ pts) {
   int64_t i = blockIdx.x * 256ll + threadIdx.x;
   if (i >= N) return;
   const int64_t j = perm[i];
   for (int r = 0; r < nr; ++r) qs[(int64_t)r * N + i] = q[(int64_t)r * N + j];
+  if (nr == 1) pts[i * 4 + 3] = q[j];
 }
 
 template <typename T>
@@ -531,19 +579,23 @@ __global__ void k_fill_zero(T *__restrict__ y, int64_t n) {
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = (T)0;
 }
 
-// chk[box] += sum over the box's M2L pairs (fixed order) of pairbuf[pair].
+// y[box] = sum over the box's M2L pairs (fixed order) of pairbuf[pair],
+// first `rows` entries of each column; 4 entries per thread.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pair_reduce(const int32_t *__restrict__ tgt, const int32_t *__restrict__ off,
-                                                     const int32_t *__restrict__ pairs, const T *__restrict__ pairbuf,
-                                                     T *__restrict__ chk, int nr, int ld) {
+__global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ tgt, const int32_t *__restrict__ off,
+                                                    const int32_t *__restrict__ pairs, const T *__restrict__ pairbuf,
+                                                    T *__restrict__ y, int nr, int ld, int rows) {
+  using V4 = typename Vec4<T>::type;
   const int slot = blockIdx.x;
   const int b = tgt[slot];
   const int p0 = off[slot], p1 = off[slot + 1];
-  for (int e = threadIdx.x; e < nr * ld; e += 256) {
-    const int r = e / ld, i = e - r * ld;
-    T s = (T)0;
-    for (int p = p0; p < p1; ++p) s += pairbuf[((int64_t)pairs[p] * nr + r) * ld + i];
-    chk[((int64_t)b * nr + r) * ld + i] += s;
+  const int rq = rows >> 2, lq = ld >> 2;
+  for (int e = threadIdx.x; e < nr * rq; e += 64) {
+    const int r = e / rq, i = e - r * rq;
+    V4 acc = V4{0, 0, 0, 0};
+    for (int p = p0; p < p1; ++p)
+      acc += reinterpret_cast<const V4 *>(pairbuf)[((int64_t)pairs[p] * nr + r) * lq + i];
+    reinterpret_cast<V4 *>(y)[((int64_t)b * nr + r) * lq + i] = acc;
   }
 }
 
@@ -553,8 +605,11 @@ __global__ __launch_bounds__(256) void k_pair_reduce(const int32_t *__restrict__
 template <typename T, int RBW>
 static void launch_gemm_rbw(const GemmBatch &bt, const T *pool, int64_t mstride, int ld, int nrb, const T *X, T *Y,
                             hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm<T, RBW>), dim3(bt.ntask), dim3(256), 0, s, bt.d_tasks, pool, mstride, bt.S, ld, nrb,
-                     bt.klen, bt.d_src, bt.d_dst, X, Y, bt.mode);
+  const unsigned gy = (unsigned)((nrb + 4 * RBW - 1) / (4 * RBW));
+  const int seg = bt.seg ? bt.seg : ld;
+  const int kq = bt.kq_stride ? bt.kq_stride : ld / 16;
+  hipLaunchKernelGGL((k_gemm<T, RBW>), dim3(bt.ntask, gy), dim3(256), 0, s, bt.d_tasks, pool, mstride, bt.S, seg, kq,
+                     ld, nrb, bt.klen, bt.d_src, bt.d_dst, X, Y, bt.mode);
 }
 
 template <typename T>
@@ -562,7 +617,9 @@ static int launch_gemm(fmm_plan *P, const GemmBatch &bt, const T *X, T *Y, hipSt
   if (bt.ntask == 0) return FMM_OK;
   const int ld = P->ld;
   const int nrb = bt.nrb;
-  const int rbw = (nrb + 3) / 4;
+  // Small launches (few column tiles) split the row blocks over a second grid
+  // dimension so that more workgroups share the work.
+  const int rbw = bt.ntask >= 1024 ? (nrb + 3) / 4 : 1;
   const T *pool = (const T *)(bt.pool == 0 ? P->pool1 : P->pool8);
   const int64_t mstride = (int64_t)ld * ld * (bt.pool == 0 ? 1 : 8);
   switch (rbw) {
@@ -590,76 +647,82 @@ static int eval_chunk(fmm_plan *P, const T *q, T *pot, T *grad, hipStream_t s) {
   const int ld = P->ld;
   const PassLists &L = P->lists_by_nr[NR];
   T *qs = (T *)P->qs, *equ = (T *)P->equ, *chk = (T *)P->chk, *eqd = (T *)P->eqd, *chku = (T *)P->chku,
-    *tmp = (T *)P->tmp;
+    *cu = (T *)P->cu, *yd = (T *)P->yd;
+  (void)equ;
   const T kappa = (T)P->kappa;
   int rc;
-  hipEvent_t ev = prof_begin(P, s);
-  hipLaunchKernelGGL(k_permute<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, q, D.perm, N, NR, qs);
+  hipEvent_t ev = prof_begin(P, FMM_PHASE_PERMUTE, s);
+  hipLaunchKernelGGL(k_permute<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, q, D.perm, N, NR, qs,
+                     (T *)D.pts);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(P, FMM_PHASE_PERMUTE, ev, s);
   const bool far = D.maxlevel >= 2;
   if (far) {
-    const int64_t nwork = (int64_t)D.nbox * NR * ld;
     // P2M: upward check potentials of the leaves at level >= 2
-    ev = prof_begin(P, s);
+    ev = prof_begin(P, FMM_PHASE_P2M, s);
     if (P->p2m_count > 0)
       hipLaunchKernelGGL((k_surf_eval<T, NR, KERN>), dim3(P->p2m_count), dim3(256), 0, s, P->d_p2m_box,
                          P->d_p2m_off, P->d_p2m_box, (const T *)D.pts, qs, N, D.box_begin, D.box_end,
                          (const T *)D.box_geom, (const T *)P->surf, P->nsurf, ld, (T)ALPHA_UC, chku, 0, kappa);
     FMM_HIP_TRY(hipGetLastError());
     prof_end(P, FMM_PHASE_P2M, ev, s);
-    // upward pass, deepest level first: M2M into the parents' check
-    // potentials, then check -> equivalent (U^T, then V S^-1) for the level
+    // upward pass in singular coordinates, deepest level first
     for (int l = D.maxlevel; l >= 2; --l) {
-      if (L.m2m[l].ntask) {
-        ev = prof_begin(P, s);
-        if ((rc = launch_gemm<T>(P, L.m2m[l], equ, chku, s))) return rc;
+      if (l < (int)L.m2m.size() && L.m2m[l].ntask) {
+        ev = prof_begin(P, FMM_PHASE_M2M, s);
+        if ((rc = launch_gemm<T>(P, L.m2m[l], cu, cu, s))) return rc;
         prof_end(P, FMM_PHASE_M2M, ev, s);
       }
-      ev = prof_begin(P, s);
-      if ((rc = launch_gemm<T>(P, L.ut_u[l], chku, tmp, s))) return rc;
-      if ((rc = launch_gemm<T>(P, L.vs_u[l], tmp, equ, s))) return rc;
-      prof_end(P, FMM_PHASE_UC2E, ev, s);
+      if (L.ut_u[l].ntask) {
+        ev = prof_begin(P, FMM_PHASE_UC2E, s);
+        if ((rc = launch_gemm<T>(P, L.ut_u[l], chku, cu, s))) return rc;
+        prof_end(P, FMM_PHASE_UC2E, ev, s);
+      }
     }
-    // P2L over X lists (after zeroing the downward check potentials)
-    ev = prof_begin(P, s);
-    hipLaunchKernelGGL(k_fill_zero<T>, dim3(1024), dim3(256), 0, s, chk, nwork);
+    ev = prof_begin(P, FMM_PHASE_UC2E, s);
+    if ((rc = launch_gemm<T>(P, L.vs_u, cu, equ, s))) return rc;
+    prof_end(P, FMM_PHASE_UC2E, ev, s);
+    // P2L: X-list sources on the downward check surfaces
+    ev = prof_begin(P, FMM_PHASE_P2L, s);
     if (D.nxbox > 0)
       hipLaunchKernelGGL((k_surf_eval<T, NR, KERN>), dim3(D.nxbox), dim3(256), 0, s, D.x_box, D.x_off, D.x_idx,
                          (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom,
-                         (const T *)P->surf, P->nsurf, ld, (T)ALPHA_DC, chk, 1, kappa);
+                         (const T *)P->surf, P->nsurf, ld, (T)ALPHA_DC, chk, 0, kappa);
     FMM_HIP_TRY(hipGetLastError());
     prof_end(P, FMM_PHASE_P2L, ev, s);
-    // M2L into pair slots, then a fixed-order sum per target box
-    ev = prof_begin(P, s);
-    if ((rc = launch_gemm<T>(P, L.m2l, equ, (T *)P->pairbuf, s))) return rc;
+    // M2L between singular coordinates into pair slots, then a fixed-order
+    // sum per target box (every box at level >= 2)
+    ev = prof_begin(P, FMM_PHASE_M2L, s);
+    if ((rc = launch_gemm<T>(P, L.m2l, cu, (T *)P->pairbuf, s))) return rc;
     prof_end(P, FMM_PHASE_M2L, ev, s);
-    ev = prof_begin(P, s);
+    ev = prof_begin(P, FMM_PHASE_M2L_SUM, s);
     if (D.nvbox > 0)
-      hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.nvbox), dim3(256), 0, s, D.v_tgt, D.v_off, D.v_pair,
-                         (const T *)P->pairbuf, chk, NR, ld);
+      hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.nvbox), dim3(64), 0, s, D.v_tgt, D.v_off, D.v_pair,
+                         (const T *)P->pairbuf, yd, NR, ld, L.m2l.nrb * 16);
     FMM_HIP_TRY(hipGetLastError());
     prof_end(P, FMM_PHASE_M2L_SUM, ev, s);
-    // downward pass, coarsest level first: L2L into the check potential,
-    // then check -> equivalent
-    for (int l = 2; l <= D.maxlevel; ++l) {
+    ev = prof_begin(P, FMM_PHASE_DC2E, s);
+    if ((rc = launch_gemm<T>(P, L.ut_dx, chk, yd, s))) return rc;
+    prof_end(P, FMM_PHASE_DC2E, ev, s);
+    // downward pass: L2L between singular coordinates, coarsest level first
+    for (int l = 3; l <= D.maxlevel; ++l) {
       if (L.l2l[l].ntask) {
-        ev = prof_begin(P, s);
-        if ((rc = launch_gemm<T>(P, L.l2l[l], eqd, chk, s))) return rc;
+        ev = prof_begin(P, FMM_PHASE_L2L, s);
+        if ((rc = launch_gemm<T>(P, L.l2l[l], yd, yd, s))) return rc;
         prof_end(P, FMM_PHASE_L2L, ev, s);
       }
-      ev = prof_begin(P, s);
-      if ((rc = launch_gemm<T>(P, L.ut_d[l], chk, tmp, s))) return rc;
-      if ((rc = launch_gemm<T>(P, L.vs_d[l], tmp, eqd, s))) return rc;
-      prof_end(P, FMM_PHASE_DC2E, ev, s);
     }
+    ev = prof_begin(P, FMM_PHASE_DC2E, s);
+    if ((rc = launch_gemm<T>(P, L.vs_d, yd, eqd, s))) return rc;
+    prof_end(P, FMM_PHASE_DC2E, ev, s);
   }
   const T scale = (T)(1.0 / (4.0 * M_PI));
-  ev = prof_begin(P, s);
-  if (D.nleaf > 0)
-    hipLaunchKernelGGL((k_leaf_eval<T, NR, KERN>), dim3(D.nleaf), dim3(256), 0, s, D.leaves, (const T *)D.pts, qs, N,
-                       D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)P->surf, P->nsurf, ld, D.u_off,
-                       D.u_idx, D.w_off, D.w_idx, equ, eqd, P->d_has_local, D.perm, pot, grad, kappa, scale);
+  ev = prof_begin(P, FMM_PHASE_LEAF, s);
+  if (D.nitems > 0)
+    hipLaunchKernelGGL((k_leaf_eval<T, NR, KERN>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
+                       (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)P->surf,
+                       P->nsurf, ld, D.near_off, D.near_rng, D.w_off, D.w_idx, equ, eqd, P->d_has_local, D.perm, pot,
+                       grad, kappa, scale);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(P, FMM_PHASE_LEAF, ev, s);
   return FMM_OK;

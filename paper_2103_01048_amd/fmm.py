@@ -78,8 +78,17 @@ class FMMPlan:
             return pot[0], (grad[0] if grad is not None else None)
         return pot, grad
 
-    def set_profiling(self, enable: bool = True):
-        check(lib().fmm_set_profiling(self._h, 1 if enable else 0), "fmm_set_profiling")
+    def set_profiling(self, enable=True):
+        """enable: True (every phase), False, or an iterable of phase names."""
+        if enable is True:
+            mask = (1 << len(_lib.PHASES)) - 1
+        elif not enable:
+            mask = 0
+        else:
+            mask = 0
+            for name in enable:
+                mask |= 1 << _lib.PHASES.index(name)
+        check(lib().fmm_set_profiling(self._h, mask), "fmm_set_profiling")
 
     def phase_times(self) -> dict:
         """Accumulated per-phase milliseconds and launch counts since the last
