@@ -1,0 +1,303 @@
+"""Dense P0 Galerkin boundary-element oracle for the direct formulation of
+the linearised Poisson-Boltzmann interface problem (Methods: the integral
+representation, the single- and double-layer operators, the direct
+formulation, the reaction potential and the polar solvation energy; the
+split of the discrete operator into a regular quadrature-point sum plus a
+singular correction, FMM-accelerated evaluation of integral operators).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  FP64, dense, small
+meshes.
+
+Discretisation (readings where the paper is silent):
+  * Triangles with counter-clockwise vertices seen from the solvent; unit
+    normal n_t = (v1 - v0) x (v2 - v0) / |.| points out of the molecule.
+  * P0 trial and test functions; unknowns u_t (potential) and v_t (its
+    normal derivative from the solute side) per triangle.
+  * Regular quadrature: 3-point rule (barycentric (2/3, 1/6, 1/6) and
+    permutations, weights 1/3) or the 6-point degree-4 rule.
+  * Operator entries for a pair (s, t):
+      V[s,t] = int_Ts int_Tt g(x, y),  K[s,t] = int_Ts int_Tt dg/dn_y(x, y)
+    with dg/dn_y = n_t . (x - y) (1 + kappa r) exp(-kappa r) / (4 pi r^3).
+    Pairs that share no vertex use the regular rule on both triangles (the
+    same sums the quadrature-point FMM evaluates).  Pairs that share a vertex
+    (identical, edge- or vertex-adjacent) use the singular rule below; the
+    difference between the two rules is the correction S - C of the split
+    A = P2^T (G - C) P1 + S.
+  * Singular rule: the Laplace part of the inner integral over the flat
+    trial triangle in closed form -- the potential of a uniform triangle
+    (sum over edges of logarithm and arctangent terms) and, for the double
+    layer, minus the signed solid angle of the triangle (Van Oosterom and
+    Strackee's formula) -- integrated over the test triangle with an n x n
+    collapsed Gauss-Legendre rule; the Yukawa remainder
+    (exp(-kappa r) - 1) / (4 pi r) and its normal derivative are bounded and
+    use an m x m collapsed rule on both triangles.
+  * System (2T unknowns):
+      [ M/2 + K_L    -V_L           ] [u]   [b]
+      [ M/2 - K_Y    (eps1/eps2) V_Y] [v] = [0],   M = diag(area)
+    b_s = int_Ts (1/eps1) sum_k q_k g_L(x, r_k).
+  * Reaction potential at the charges: sum over quadrature points of
+    W_j [-dg_L/dn_y(r_k, y_j) u_t + g_L(r_k, y_j) v_t]; energy
+    dG = 1/2 sum_k q_k phi_reac(r_k) * 4 pi * 332.0637 kcal/mol (the 4 pi
+    undoes the 1/(4 pi) of g).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from .analytic import KCAL_PER_MOL
+
+FOUR_PI = 4.0 * math.pi
+
+
+# ---------------------------------------------------------------------------
+# quadrature rules on the reference triangle (barycentric coordinates)
+# ---------------------------------------------------------------------------
+def regular_rule(npts: int):
+    """(bary (k,3), weights (k,)) with sum of weights 1."""
+    if npts == 1:
+        return np.array([[1 / 3, 1 / 3, 1 / 3]]), np.array([1.0])
+    if npts == 3:
+        b = np.array([[2 / 3, 1 / 6, 1 / 6], [1 / 6, 2 / 3, 1 / 6], [1 / 6, 1 / 6, 2 / 3]])
+        return b, np.full(3, 1 / 3)
+    if npts == 6:
+        a1, w1 = 0.445948490915965, 0.223381589678011
+        a2, w2 = 0.091576213509771, 0.109951743655322
+        b = np.array([[a1, a1, 1 - 2 * a1], [a1, 1 - 2 * a1, a1], [1 - 2 * a1, a1, a1],
+                      [a2, a2, 1 - 2 * a2], [a2, 1 - 2 * a2, a2], [1 - 2 * a2, a2, a2]])
+        return b, np.array([w1, w1, w1, w2, w2, w2])
+    raise ValueError("regular rule with 1, 3 or 6 points")
+
+
+def collapsed_rule(n: int):
+    """n*n collapsed Gauss-Legendre rule: point v0 + xi (v1 - v0) + xi eta
+    (v2 - v1) for Gauss nodes xi, eta on [0,1]; weights (sum 1) include the
+    Jacobian 2 xi."""
+    g, w = np.polynomial.legendre.leggauss(n)
+    g = 0.5 * (g + 1)
+    w = 0.5 * w
+    bary, wt = [], []
+    for i in range(n):
+        for j in range(n):
+            xi, eta = g[i], g[j]
+            l1 = xi * (1 - eta)
+            l2 = xi * eta
+            bary.append([1 - xi, l1, l2])
+            wt.append(2 * xi * w[i] * w[j])
+    return np.array(bary), np.array(wt)
+
+
+# ---------------------------------------------------------------------------
+# closed-form inner integrals over a flat triangle (Laplace, without 1/4pi)
+# ---------------------------------------------------------------------------
+def tri_potential(x, tri, n):
+    """int_T 1/|x - y| dy (the potential of a uniform unit density on the
+    flat triangle T).  Batched: x (..., k, 3), tri (..., 3, 3), n (..., 3)."""
+    x = np.asarray(x, dtype=np.float64)
+    tri = np.asarray(tri, dtype=np.float64)
+    n = np.asarray(n, dtype=np.float64)
+    nn = n[..., None, :]
+    d = np.sum((x - tri[..., 0:1, :]) * nn, axis=-1)
+    rho = x - d[..., None] * nn
+    ad = np.abs(d)
+    out = np.zeros(x.shape[:-1])
+    for i in range(3):
+        a = tri[..., i:i + 1, :]
+        b = tri[..., (i + 1) % 3:(i + 1) % 3 + 1, :]
+        L = np.linalg.norm(b - a, axis=-1)
+        lh = (b - a) / L[..., None]
+        uh = np.cross(lh, nn)
+        t0 = np.sum((a - rho) * uh, axis=-1)
+        lp = np.sum((b - rho) * lh, axis=-1)
+        lm = np.sum((a - rho) * lh, axis=-1)
+        Rp = np.linalg.norm(x - b, axis=-1)
+        Rm = np.linalg.norm(x - a, axis=-1)
+        R02 = t0 * t0 + d * d
+        with np.errstate(divide="ignore", invalid="ignore"):
+            lg = np.log((Rp + lp) / (Rm + lm))
+        lg = np.where(np.abs(t0) > 1e-14 * L, lg, 0.0)
+        out += t0 * lg
+        out -= ad * (np.arctan2(t0 * lp, R02 + ad * Rp) - np.arctan2(t0 * lm, R02 + ad * Rm))
+    return out
+
+
+def tri_dlp(x, tri, n):
+    """int_T n . (x - y) / |x - y|^3 dy: minus the signed solid angle of T
+    seen from x (Van Oosterom-Strackee); for x in the plane of T the value
+    is the principal value 0.  Batched like tri_potential."""
+    x = np.asarray(x, dtype=np.float64)
+    tri = np.asarray(tri, dtype=np.float64)
+    R1, R2, R3 = tri[..., 0:1, :] - x, tri[..., 1:2, :] - x, tri[..., 2:3, :] - x
+    r1, r2, r3 = (np.linalg.norm(R, axis=-1) for R in (R1, R2, R3))
+    num = np.sum(R1 * np.cross(R2, R3), axis=-1)
+    den = (r1 * r2 * r3 + np.sum(R1 * R2, axis=-1) * r3 + np.sum(R1 * R3, axis=-1) * r2
+           + np.sum(R2 * R3, axis=-1) * r1)
+    om = -2.0 * np.arctan2(num, den)
+    return np.where(np.abs(num) <= 1e-13 * r1 * r2 * r3, 0.0, om)
+
+
+# ---------------------------------------------------------------------------
+# mesh data
+# ---------------------------------------------------------------------------
+@dataclass
+class Mesh:
+    verts: np.ndarray
+    tris: np.ndarray
+    area: np.ndarray
+    normal: np.ndarray
+    qpts: np.ndarray     # (T, k, 3)
+    qw: np.ndarray       # (T, k) = rule weight * area
+
+
+def make_mesh(verts, tris, npts: int = 3) -> Mesh:
+    v = np.asarray(verts, dtype=np.float64)
+    t = np.asarray(tris, dtype=np.int64)
+    a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+    cr = np.cross(b - a, c - a)
+    nrm = np.linalg.norm(cr, axis=1)
+    area = 0.5 * nrm
+    normal = cr / nrm[:, None]
+    bary, w = regular_rule(npts)
+    qp = np.einsum("kj,tjd->tkd", bary, np.stack([a, b, c], axis=1))
+    return Mesh(v, t, area, normal, qp, area[:, None] * w[None, :])
+
+
+def singular_pairs(m: Mesh):
+    """(s, t) pairs that share at least one vertex, s-major, t ascending."""
+    vt = [[] for _ in range(len(m.verts))]
+    for ti, tri in enumerate(m.tris):
+        for vi in tri:
+            vt[vi].append(ti)
+    out = []
+    for s, tri in enumerate(m.tris):
+        nb = sorted(set(t for vi in tri for t in vt[vi]))
+        out += [(s, t) for t in nb]
+    return out
+
+
+def _gk(r, kappa):
+    return np.exp(-kappa * r) / (FOUR_PI * r)
+
+
+def regular_entries(m: Mesh, s, t, kappa):
+    """Regular-rule (quadrature-point) values of V and K for pair (s, t),
+    zero-distance point pairs left out."""
+    x = m.qpts[s]
+    y = m.qpts[t]
+    d = x[:, None, :] - y[None, :, :]
+    r = np.linalg.norm(d, axis=2)
+    ww = m.qw[s][:, None] * m.qw[t][None, :]
+    mask = r > 0
+    rr = np.where(mask, r, 1.0)
+    g = np.where(mask, np.exp(-kappa * rr) / (FOUR_PI * rr), 0.0)
+    dn = d @ m.normal[t]
+    kk = np.where(mask, dn * (1 + kappa * rr) * np.exp(-kappa * rr) / (FOUR_PI * rr ** 3), 0.0)
+    return float(np.sum(ww * g)), float(np.sum(ww * kk))
+
+
+def singular_entries(m: Mesh, s, t, kappa, n_outer: int = 8, n_rem: int = 4):
+    """Accurate V and K for pairs sharing a vertex (see the module notes).
+    s, t: arrays of triangle indices (one entry per pair)."""
+    s = np.atleast_1d(np.asarray(s))
+    t = np.atleast_1d(np.asarray(t))
+    tri_s = m.verts[m.tris[s]]            # (P,3,3)
+    tri_t = m.verts[m.tris[t]]
+    nt = m.normal[t]                      # (P,3)
+    bo, wo = collapsed_rule(n_outer)
+    xo = np.einsum("kj,pjd->pkd", bo, tri_s)
+    W = wo[None, :] * m.area[s][:, None]
+    V = np.sum(W * tri_potential(xo, tri_t, nt), axis=1) / FOUR_PI
+    K = np.sum(W * tri_dlp(xo, tri_t, nt), axis=1) / FOUR_PI
+    if kappa > 0:
+        br, wr = collapsed_rule(n_rem)
+        xr = np.einsum("kj,pjd->pkd", br, tri_s)
+        yr = np.einsum("kj,pjd->pkd", br, tri_t)
+        d = xr[:, :, None, :] - yr[:, None, :, :]
+        r = np.linalg.norm(d, axis=-1)
+        ww = (wr[None, :] * m.area[s][:, None])[:, :, None] * (wr[None, :] * m.area[t][:, None])[:, None, :]
+        kr = kappa * r
+        dn = np.einsum("pabd,pd->pab", d, nt)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            remV = np.where(r > 0, np.expm1(-kr) / (FOUR_PI * r), -kappa / FOUR_PI)
+            fac = (1 + kr) * np.exp(-kr) - 1.0
+            remK = np.where(r > 0, dn * fac / (FOUR_PI * r ** 3), 0.0)
+        V = V + np.sum(ww * remV, axis=(1, 2))
+        K = K + np.sum(ww * remK, axis=(1, 2))
+    return V, K
+
+
+def operators(m: Mesh, kappa: float, n_outer: int = 8, n_rem: int = 4, chunk: int = 64):
+    """Dense V and K (T x T) for one kernel (rows assembled in chunks)."""
+    T = len(m.tris)
+    k = m.qpts.shape[1]
+    X = m.qpts.reshape(-1, 3)
+    Wf = m.qw.reshape(-1)
+    nY = np.repeat(m.normal, k, axis=0)
+    Vq = np.zeros((T, T))
+    Kq = np.zeros((T, T))
+    for s0 in range(0, T, chunk):
+        s1 = min(T, s0 + chunk)
+        Xs = X[s0 * k:s1 * k]
+        d = Xs[:, None, :] - X[None, :, :]
+        r = np.sqrt(np.einsum("ijd,ijd->ij", d, d))
+        mask = r > 0
+        rr = np.where(mask, r, 1.0)
+        e = np.exp(-kappa * rr) if kappa > 0 else 1.0
+        g = np.where(mask, e / (FOUR_PI * rr), 0.0)
+        dn = np.einsum("ijd,jd->ij", d, nY)
+        kk = np.where(mask, dn * (1 + kappa * rr) * e / (FOUR_PI * rr ** 3), 0.0)
+        ws = Wf[s0 * k:s1 * k]
+        Vq[s0:s1] = (ws[:, None] * g * Wf[None, :]).reshape(s1 - s0, k, T, k).sum(axis=(1, 3))
+        Kq[s0:s1] = (ws[:, None] * kk * Wf[None, :]).reshape(s1 - s0, k, T, k).sum(axis=(1, 3))
+    sp = np.array(singular_pairs(m))
+    Vs, Ks = singular_entries(m, sp[:, 0], sp[:, 1], kappa, n_outer, n_rem)
+    Vq[sp[:, 0], sp[:, 1]] = Vs
+    Kq[sp[:, 0], sp[:, 1]] = Ks
+    return Vq, Kq
+
+
+def system(m: Mesh, eps1: float, eps2: float, kappa: float, **kw):
+    VL, KL = operators(m, 0.0, **kw)
+    VY, KY = operators(m, kappa, **kw)
+    M = np.diag(m.area)
+    A = np.block([[0.5 * M + KL, -VL], [0.5 * M - KY, (eps1 / eps2) * VY]])
+    return A
+
+
+def rhs(m: Mesh, qxyz, q, eps1: float):
+    X = m.qpts.reshape(-1, 3)
+    d = np.linalg.norm(X[:, None, :] - np.asarray(qxyz)[None, :, :], axis=2)
+    f = (np.asarray(q)[None, :] / (FOUR_PI * eps1 * d)).sum(axis=1)
+    T, k = m.qw.shape
+    b = (m.qw.reshape(-1) * f).reshape(T, k).sum(axis=1)
+    return np.concatenate([b, np.zeros(T)])
+
+
+def reaction_potential(m: Mesh, x, qxyz):
+    T = len(m.tris)
+    u, v = x[:T], x[T:]
+    k = m.qpts.shape[1]
+    Y = m.qpts.reshape(-1, 3)
+    W = m.qw.reshape(-1)
+    nY = np.repeat(m.normal, k, axis=0)
+    uu = np.repeat(u, k) * W
+    vv = np.repeat(v, k) * W
+    R = np.asarray(qxyz)[:, None, :] - Y[None, :, :]
+    r = np.linalg.norm(R, axis=2)
+    g = 1.0 / (FOUR_PI * r)
+    dgdn = np.einsum("kjd,jd->kj", R, nY) / (FOUR_PI * r ** 3)
+    return -dgdn @ uu + g @ vv
+
+
+def energy(m: Mesh, x, qxyz, q):
+    phi = reaction_potential(m, x, qxyz)
+    return 0.5 * float(np.dot(q, phi)) * FOUR_PI * KCAL_PER_MOL
+
+
+def solve(m: Mesh, qxyz, q, eps1=4.0, eps2=80.0, kappa=0.125, **kw):
+    A = system(m, eps1, eps2, kappa, **kw)
+    b = rhs(m, qxyz, q, eps1)
+    x = np.linalg.solve(A, b)
+    return x, A, b

@@ -1,0 +1,123 @@
+"""Pins of the dense BEM oracle: quadrature exactness, the closed-form
+triangle integrals against brute force, Gauss's theorem for the double
+layer, the uniform-shell potentials for the single layer, and the Born and
+Kirkwood solvation energies with first-order convergence."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import analytic as A
+from oracle import bem
+
+KAPPA = 0.125
+
+
+def _mono_exact(a, b):
+    # int over the unit right triangle of x^a y^b = a! b! / (a + b + 2)!
+    return math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
+
+
+@pytest.mark.parametrize("npts,deg", [(3, 2), (6, 4)])
+def test_regular_rules_exact_to_their_degree(npts, deg):
+    bary, w = bem.regular_rule(npts)
+    x, y = bary[:, 1], bary[:, 2]
+    for a in range(deg + 1):
+        for b in range(deg + 1 - a):
+            assert 0.5 * np.sum(w * x ** a * y ** b) == pytest.approx(_mono_exact(a, b), rel=1e-12, abs=1e-15)
+    # and not beyond (a sanity check that the test has teeth)
+    assert abs(0.5 * np.sum(w * x ** (deg + 1)) - _mono_exact(deg + 1, 0)) > 1e-8
+
+
+def test_collapsed_rule_exact():
+    bary, w = bem.collapsed_rule(5)
+    x, y = bary[:, 1], bary[:, 2]
+    for a in range(8):
+        for b in range(8 - a):
+            assert 0.5 * np.sum(w * x ** a * y ** b) == pytest.approx(_mono_exact(a, b), rel=1e-12)
+
+
+def _brute(x, tri, n, f):
+    bary, w = bem.collapsed_rule(60)
+    y = bary @ tri
+    area = 0.5 * np.linalg.norm(np.cross(tri[1] - tri[0], tri[2] - tri[0]))
+    return np.array([area * np.sum(w * f(xx, y)) for xx in x])
+
+
+def test_closed_form_triangle_integrals_against_brute_force():
+    tri = np.array([[0.0, 0.0, 0.0], [1.3, 0.1, 0.0], [0.2, 0.9, 0.1]])
+    n = np.cross(tri[1] - tri[0], tri[2] - tri[0])
+    n /= np.linalg.norm(n)
+    rng = np.random.default_rng(31)
+    x = tri.mean(axis=0) + rng.normal(0, 1.0, (12, 3)) + 1.5 * n
+    pot = bem.tri_potential(x, tri, n)
+    dlp = bem.tri_dlp(x, tri, n)
+    bp = _brute(x, tri, n, lambda xx, y: 1.0 / np.linalg.norm(xx - y, axis=1))
+    bd = _brute(x, tri, n, lambda xx, y: ((xx - y) @ n) / np.linalg.norm(xx - y, axis=1) ** 3)
+    np.testing.assert_allclose(pot, bp, rtol=1e-9)
+    np.testing.assert_allclose(dlp, bd, rtol=1e-7, atol=1e-12)
+
+
+def test_solid_angles_of_a_closed_surface():
+    """Gauss: sum over a closed outward-oriented surface of
+    int n.(x-y)/|x-y|^3 is -4 pi inside and 0 outside."""
+    v, t = synth.octa_sphere(2, 2.0)
+    m = bem.make_mesh(v, t, 3)
+    for x, ref in (([0.3, -0.2, 0.5], -4 * math.pi), ([0.0, 0.0, 3.5], 0.0)):
+        tot = sum(bem.tri_dlp(np.array([x]), m.verts[m.tris[i]], m.normal[i])[0] for i in range(len(t)))
+        assert tot == pytest.approx(ref, abs=1e-10)
+
+
+def test_double_layer_of_a_constant_is_minus_half():
+    """On a closed smooth surface the double layer of a constant density is
+    -1/2 (the jump relation); tested on the sphere, row sums of K_L against
+    -area/2."""
+    v, t = synth.octa_sphere(3, 4.0)
+    m = bem.make_mesh(v, t, 3)
+    _, K = bem.operators(m, 0.0)
+    ratio = K.sum(axis=1) / m.area
+    assert np.abs(ratio + 0.5).max() < 0.02
+    assert abs(ratio.mean() + 0.5) < 2e-3
+
+
+@pytest.mark.parametrize("kappa", [0.0, 0.3])
+def test_single_layer_of_a_constant_is_shell_potential(kappa):
+    """Uniform unit density on a sphere of radius R, observed on the sphere:
+    R (Laplace), (1 - exp(-2 kappa R)) / (2 kappa) (Yukawa)."""
+    R = 4.0
+    ref = R if kappa == 0 else (1 - math.exp(-2 * kappa * R)) / (2 * kappa)
+    errs = []
+    for lev in (2, 3):
+        v, t = synth.octa_sphere(lev, R)
+        m = bem.make_mesh(v, t, 3)
+        V, _ = bem.operators(m, kappa)
+        errs.append(abs((V.sum(axis=1) / m.area).mean() / ref - 1))
+    # the flat-facet surface approaches the sphere at second order
+    assert errs[1] < 1e-2 and errs[0] / errs[1] > 3.0, errs
+
+
+def test_identical_pair_double_layer_vanishes():
+    v, t = synth.octa_sphere(2, 4.0)
+    m = bem.make_mesh(v, t, 3)
+    V, K = bem.singular_entries(m, np.arange(5), np.arange(5), KAPPA)
+    assert np.all(np.abs(K) < 1e-25) and np.all(V > 0)
+
+
+def test_born_and_kirkwood_first_order_convergence():
+    ref_b = A.born_energy(4.0, 1.0, 4.0, 80.0, KAPPA)
+    ref_k = A.kirkwood_energy(4.0, [1, 1, 1], [1.0], 4.0, 80.0, KAPPA)
+    eb, ek = [], []
+    for lev in (2, 3):
+        v, t = synth.octa_sphere(lev, 4.0)
+        m = bem.make_mesh(v, t, 3)
+        A_ = bem.system(m, 4.0, 80.0, KAPPA)
+        for (qx, ref, store) in (([[0, 0, 0]], ref_b, eb), ([[1, 1, 1]], ref_k, ek)):
+            b = bem.rhs(m, qx, [1.0], 4.0)
+            x = np.linalg.solve(A_, b)
+            store.append(abs(bem.energy(m, x, qx, [1.0]) - ref))
+    # refinement by 4 in the number of elements divides the error by ~4
+    for e in (eb, ek):
+        order = math.log(e[0] / e[1]) / math.log(4.0)
+        assert 0.85 < order < 1.15, (e, order)
+    assert ek[1] / abs(ref_k) < 0.015
