@@ -161,6 +161,93 @@ int fmm_get_phase_times(fmm_plan *plan, double *ms, int64_t *launches, int nphas
 
 void fmm_free(fmm_plan *plan);
 
+/* ------------------------------------------------------------------------
+ * Boundary-element operator of the direct formulation (Methods, boundary
+ * integral formulation: the direct, Yoon-Lenhoff, system for the solute-side
+ * potential u and its normal derivative v on the molecular surface), with
+ * piecewise-constant (P0) Galerkin discretisation on a triangle mesh and the
+ * matrix-vector split A x = P2^T (G - C) P1 x + S x ("FMM-accelerated
+ * evaluation of integral operators"):
+ *
+ *   [ M/2 + K_L    -V_L            ] [u]   [b]
+ *   [ M/2 - K_Y    (eps1/eps2) V_Y ] [v] = [0],     M = diag(triangle areas)
+ *
+ * V and K are the single- and double-layer operators of the Laplace (L) and
+ * Yukawa (Y) kernels.  G is evaluated by fmm_eval on the regular quadrature
+ * points (4 density columns per kernel: the three normal-weighted columns of
+ * the double layer, whose gradients give K, and the single-layer column);
+ * for pairs of triangles that share a vertex the regular-rule values C are
+ * replaced by accurate values S (closed-form inner integrals of the Laplace
+ * part over the flat triangle, Gauss rules for the bounded Yukawa remainder),
+ * applied as one precomputed sparse FP64 matrix S - C.
+ * ------------------------------------------------------------------------ */
+
+/* Build the operator.  verts (nv x 3 doubles) and tris (nt x 3 int32, vertex
+ * indices, counter-clockwise seen from the solvent so that normals point
+ * out of the molecule) are HOST arrays read during the call.  quad_pts: 3 or
+ * 6 (regular rule per triangle); eps_in, eps_out > 0; kappa >= 0; p, ncrit,
+ * precision as for fmm_setup (the two FMM plans).  Synchronises `stream`.
+ * Errors: FMM_EINVAL for bad sizes, indices or parameters, a degenerate
+ * triangle; FMM_ENOMEM; FMM_EHIP. */
+int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, int quad_pts, double eps_in,
+              double eps_out, double kappa, int p, int ncrit, int precision, fmm_stream_t stream,
+              bem_op **out);
+
+/* y = A x; x_dev, y_dev: device, 2*nt doubles ([u; v] and the two row
+ * blocks).  x_dev and y_dev must not overlap.  Asynchronous. */
+int bem_matvec(bem_op *op, const double *x_dev, double *y_dev, fmm_stream_t stream);
+
+/* Right-hand side b_dev (2*nt doubles: [b; 0]) for nq point charges at
+ * qxyz_dev (device, nq x 3) with charges q_dev (device, nq), e and
+ * Angstrom: b_s = int_Ts (1/eps_in) sum_k q_k / (4 pi |x - r_k|), regular rule,
+ * FP64 direct sum.  Asynchronous. */
+int bem_rhs(bem_op *op, const double *qxyz_dev, const double *q_dev, int64_t nq, double *b_dev,
+            fmm_stream_t stream);
+
+/* Polar solvation energy (kcal/mol) of the charges for the solution x_dev:
+ * reaction potential phi_reac(r_k) = -K_L u + V_L v evaluated at the charges
+ * (eq. of the reaction potential, FP64 direct sum over the quadrature
+ * points), dG = 1/2 sum_k q_k phi_reac(r_k) * 4 pi * 332.0637 (FP64
+ * reduction on the device).  Synchronises `stream`; result in *dG. */
+int bem_energy(bem_op *op, const double *x_dev, const double *qxyz_dev, const double *q_dev, int64_t nq,
+               double *dG, fmm_stream_t stream);
+
+/* Apply the block-diagonal preconditioner (per triangle, the inverse of the
+ * 2 x 2 block of A on the identical-pair entries): y = P^-1 x.  Device
+ * vectors of 2*nt doubles.  Asynchronous. */
+int bem_precondition(bem_op *op, const double *x_dev, double *y_dev, fmm_stream_t stream);
+
+/* FP64 GMRES on A x = b with right block-diagonal preconditioning,
+ * classical Gram-Schmidt with reorthogonalisation on the device and Givens
+ * rotations on the host.  restart: Krylov dimension before a restart
+ * (<= 0: maxiter, full GMRES).  Stops when the recomputed residual
+ * |b - A x| / |b| <= tol.  x_dev holds the initial guess and receives the
+ * solution.  refine (may be NULL): an operator on the same mesh, usually
+ * FMM_FP64 with a higher order; then the solve is an iterative refinement:
+ * residuals are computed with `refine` and each correction is solved with
+ * `op` to a relative tolerance inner_tol.  iters (may be NULL) receives the
+ * total number of inner iterations; resid_hist (host, may be NULL, maxiter
+ * entries) the estimated relative residual after each inner iteration.
+ * Synchronises `stream` every iteration.  Returns FMM_OK, FMM_ENOTCONV
+ * (maxiter reached; x holds the last iterate) or FMM_EBREAKDOWN. */
+int gmres_solve(bem_op *op, bem_op *refine, const double *b_dev, double *x_dev, double tol, double inner_tol,
+                int maxiter, int restart, int *iters, double *resid_hist, fmm_stream_t stream);
+
+typedef struct {
+  int64_t n_triangles;
+  int64_t n_points;           /* quadrature points = FMM points */
+  int64_t n_singular_pairs;   /* triangle pairs sharing a vertex (incl. identical) */
+  int32_t quad_pts;
+  int32_t precision;
+} bem_info_t;
+int bem_info(const bem_op *op, bem_info_t *out);
+
+/* The FMM plan of kernel FMM_LAPLACE or FMM_YUKAWA used by the operator
+ * (owned by the operator). */
+fmm_plan *bem_fmm_plan(bem_op *op, int kernel);
+
+void bem_free(bem_op *op);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *fmm_last_error(void);
 

@@ -210,6 +210,9 @@ def singular_entries(m: Mesh, s, t, kappa, n_outer: int = 8, n_rem: int = 4):
     W = wo[None, :] * m.area[s][:, None]
     V = np.sum(W * tri_potential(xo, tri_t, nt), axis=1) / FOUR_PI
     K = np.sum(W * tri_dlp(xo, tri_t, nt), axis=1) / FOUR_PI
+    # on its own flat element n . (x - y) = 0: the self double layer vanishes
+    # (evaluating the solid angle there only sees rounding in the plane test)
+    K = np.where(s == t, 0.0, K)
     if kappa > 0:
         br, wr = collapsed_rule(n_rem)
         xr = np.einsum("kj,pjd->pkd", br, tri_s)
@@ -224,7 +227,7 @@ def singular_entries(m: Mesh, s, t, kappa, n_outer: int = 8, n_rem: int = 4):
             fac = (1 + kr) * np.exp(-kr) - 1.0
             remK = np.where(r > 0, dn * fac / (FOUR_PI * r ** 3), 0.0)
         V = V + np.sum(ww * remV, axis=(1, 2))
-        K = K + np.sum(ww * remK, axis=(1, 2))
+        K = K + np.where(s == t, 0.0, np.sum(ww * remK, axis=(1, 2)))
     return V, K
 
 

@@ -4,3 +4,4 @@ matvec and an FP64 GMRES, as hand-written HIP kernels for gfx950 behind the
 C ABI in include/fmmbem.h.  This package is the thin Python binding."""
 from ._lib import FmmError, lib  # noqa: F401
 from .fmm import FMMPlan  # noqa: F401
+from .bem import BEMOperator, gmres  # noqa: F401,E402

@@ -53,6 +53,15 @@ SIGNATURES = {
     "fmm_free": (None, [vp]),
     "fmm_last_error": (ctypes.c_char_p, []),
     "fmm_set_profiling": (i32, [vp, i32]),
+    "bem_setup": (i32, [vp, i64, vp, i64, i32, dbl, dbl, dbl, i32, i32, i32, vp, P(vp)]),
+    "bem_matvec": (i32, [vp, vp, vp, vp]),
+    "bem_rhs": (i32, [vp, vp, vp, i64, vp, vp]),
+    "bem_energy": (i32, [vp, vp, vp, vp, i64, P(dbl), vp]),
+    "bem_precondition": (i32, [vp, vp, vp, vp]),
+    "gmres_solve": (i32, [vp, vp, vp, vp, dbl, dbl, i32, i32, P(i32), vp, vp]),
+    "bem_info": (i32, [vp, vp]),
+    "bem_fmm_plan": (vp, [vp, i32]),
+    "bem_free": (None, [vp]),
     "fmm_get_phase_times": (i32, [vp, vp, vp, i32]),
 }
 

@@ -1,0 +1,816 @@
+// Boundary-element operator of the direct formulation on top of the FMM
+// plans, the FP64 direct sums for the right-hand side and the reaction
+// potential, and the FP64 GMRES solver.
+//
+// Matrix-vector split (Methods, FMM-accelerated evaluation of integral
+// operators): A x = P2^T (G - C) P1 x + S x.  P1 turns the P0 coefficients
+// into weighted densities at the regular quadrature points, G is the FMM,
+// P2^T integrates the FMM output against the test triangles, and S - C (the
+// accurate minus the regular-rule values for triangle pairs that share a
+// vertex) is precomputed once as a sparse FP64 matrix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+int eval_dispatch(fmm_plan *P, const void *q, int nrhs, void *pot, void *grad, hipStream_t s);
+}
+
+using fmm::set_error;
+
+namespace {
+
+constexpr double FOUR_PI = 12.566370614359172953850573533118;
+constexpr double KCAL = 332.0637;  // e^2/A -> kcal/mol
+constexpr int NO = 8;              // outer collapsed Gauss rule, NO x NO points
+constexpr int NREM = 4;            // Yukawa remainder rule, NREM x NREM on each triangle
+
+// Gauss-Legendre nodes and weights on [0, 1] (Newton iteration on P_n).
+void gauss01(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1; }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = 0.5 * (1 - z);
+    w[i] = 1.0 / ((1 - z * z) * dp * dp);  // (2/((1-z^2) P'^2)) * 1/2
+  }
+}
+
+// Collapsed rule on a triangle: barycentric (1 - xi, xi (1 - eta), xi eta),
+// weight 2 xi w_i w_j (sums to 1).
+void collapsed(int n, std::vector<double> &rule /* 3 per point: l1, l2, w */) {
+  std::vector<double> g, w;
+  gauss01(n, g, w);
+  rule.clear();
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      rule.push_back(g[i] * (1 - g[j]));
+      rule.push_back(g[i] * g[j]);
+      rule.push_back(2 * g[i] * w[i] * w[j]);
+    }
+}
+
+void regular(int npts, std::vector<double> &rule) {
+  rule.clear();
+  if (npts == 3) {
+    const double b[3][2] = {{1.0 / 6, 1.0 / 6}, {2.0 / 3, 1.0 / 6}, {1.0 / 6, 2.0 / 3}};
+    for (auto &e : b) { rule.push_back(e[0]); rule.push_back(e[1]); rule.push_back(1.0 / 3); }
+  } else {
+    // degree-4 six-point rule: orbits of (a, a, 1 - 2a)
+    const double a1 = 0.445948490915965, w1 = 0.223381589678011;
+    const double a2 = 0.091576213509771, w2 = 0.109951743655322;
+    const double pts[6][2] = {{a1, 1 - 2 * a1}, {1 - 2 * a1, a1}, {a1, a1}, {a2, 1 - 2 * a2}, {1 - 2 * a2, a2}, {a2, a2}};
+    for (int k = 0; k < 6; ++k) {
+      rule.push_back(pts[k][0]);
+      rule.push_back(pts[k][1]);
+      rule.push_back(k < 3 ? w1 : w2);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// device helpers (FP64)
+// ---------------------------------------------------------------------------
+struct D3 { double x, y, z; };
+__device__ inline D3 mk(double a, double b, double c) { return {a, b, c}; }
+__device__ inline D3 sub(D3 a, D3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline D3 add(D3 a, D3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ inline D3 scl(D3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ inline double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline D3 cross(D3 a, D3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+__device__ inline double nrm(D3 a) { return sqrt(dot(a, a)); }
+
+// Potential of a uniform unit density on the flat triangle v[3] with unit
+// normal n at x (int_T 1/|x - y| dy): a sum over the edges of a logarithm
+// term and an arctangent term (the edge-based closed form of the potential
+// of a polygon).
+__device__ double tri_pot(D3 x, const D3 *v, D3 n) {
+  const double d = dot(sub(x, v[0]), n);
+  const D3 rho = sub(x, scl(n, d));
+  const double ad = fabs(d);
+  double out = 0;
+  for (int i = 0; i < 3; ++i) {
+    const D3 a = v[i], b = v[(i + 1) % 3];
+    const D3 e = sub(b, a);
+    const double L = nrm(e);
+    const D3 lh = scl(e, 1.0 / L);
+    const D3 uh = cross(lh, n);
+    const double t0 = dot(sub(a, rho), uh);
+    const double lp = dot(sub(b, rho), lh), lm = dot(sub(a, rho), lh);
+    const double Rp = nrm(sub(x, b)), Rm = nrm(sub(x, a));
+    const double R02 = t0 * t0 + d * d;
+    if (fabs(t0) > 1e-14 * L) out += t0 * log((Rp + lp) / (Rm + lm));
+    out -= ad * (atan2(t0 * lp, R02 + ad * Rp) - atan2(t0 * lm, R02 + ad * Rm));
+  }
+  return out;
+}
+
+// int_T n.(x - y)/|x - y|^3 dy: minus the signed solid angle of the triangle
+// seen from x; the principal value 0 for x in the triangle's plane.
+__device__ double tri_dlp(D3 x, const D3 *v) {
+  const D3 R1 = sub(v[0], x), R2 = sub(v[1], x), R3 = sub(v[2], x);
+  const double r1 = nrm(R1), r2 = nrm(R2), r3 = nrm(R3);
+  const double num = dot(R1, cross(R2, R3));
+  if (fabs(num) <= 1e-13 * r1 * r2 * r3) return 0.0;
+  const double den = r1 * r2 * r3 + dot(R1, R2) * r3 + dot(R1, R3) * r2 + dot(R2, R3) * r1;
+  return -2.0 * atan2(num, den);
+}
+
+// One thread per singular pair (s, t): D = S - C for V_L, K_L, V_Y, K_Y.
+__global__ void k_singular(int64_t npair, const int32_t *__restrict__ ps, const int32_t *__restrict__ pt,
+                           const double *__restrict__ tri, const double *__restrict__ normal,
+                           const double *__restrict__ area, const double *__restrict__ rule_o, int no,
+                           const double *__restrict__ rule_r, int nr, const double *__restrict__ rule_q, int nq,
+                           double kappa, double *__restrict__ Dval, double *__restrict__ sdiag) {
+  const int64_t k = blockIdx.x * 128ll + threadIdx.x;
+  if (k >= npair) return;
+  const int s = ps[k], t = pt[k];
+  D3 vs[3], vt[3];
+  for (int i = 0; i < 3; ++i) {
+    vs[i] = mk(tri[s * 9 + 3 * i], tri[s * 9 + 3 * i + 1], tri[s * 9 + 3 * i + 2]);
+    vt[i] = mk(tri[t * 9 + 3 * i], tri[t * 9 + 3 * i + 1], tri[t * 9 + 3 * i + 2]);
+  }
+  const D3 nt = mk(normal[t * 3], normal[t * 3 + 1], normal[t * 3 + 2]);
+  const double As = area[s], At = area[t];
+  auto point = [](const D3 *v, double l1, double l2) {
+    return add(add(scl(v[0], 1 - l1 - l2), scl(v[1], l1)), scl(v[2], l2));
+  };
+  // accurate values: closed-form inner Laplace integrals, outer collapsed rule
+  double sv = 0, sk = 0;
+  for (int c = 0; c < no; ++c) {
+    const D3 x = point(vs, rule_o[3 * c], rule_o[3 * c + 1]);
+    const double w = rule_o[3 * c + 2] * As;
+    sv += w * tri_pot(x, vt, nt);
+    if (s != t) sk += w * tri_dlp(x, vt);  // n.(x - y) = 0 on the element itself
+  }
+  sv /= FOUR_PI;
+  sk /= FOUR_PI;
+  double svy = sv, sky = sk;
+  if (kappa > 0) {
+    for (int a = 0; a < nr; ++a) {
+      const D3 x = point(vs, rule_r[3 * a], rule_r[3 * a + 1]);
+      const double wa = rule_r[3 * a + 2] * As;
+      for (int b = 0; b < nr; ++b) {
+        const D3 y = point(vt, rule_r[3 * b], rule_r[3 * b + 1]);
+        const double w = wa * rule_r[3 * b + 2] * At;
+        const D3 d = sub(x, y);
+        const double r = nrm(d);
+        const double kr = kappa * r;
+        if (r > 0) {
+          svy += w * expm1(-kr) / (FOUR_PI * r);
+          if (s != t) sky += w * dot(d, nt) * ((1 + kr) * exp(-kr) - 1.0) / (FOUR_PI * r * r * r);
+        } else {
+          svy += w * (-kappa / FOUR_PI);
+        }
+      }
+    }
+  }
+  // regular-rule values the quadrature-point sum contains for this pair
+  double cv = 0, ck = 0, cvy = 0, cky = 0;
+  for (int a = 0; a < nq; ++a) {
+    const D3 x = point(vs, rule_q[3 * a], rule_q[3 * a + 1]);
+    const double wa = rule_q[3 * a + 2] * As;
+    for (int b = 0; b < nq; ++b) {
+      const D3 y = point(vt, rule_q[3 * b], rule_q[3 * b + 1]);
+      const double w = wa * rule_q[3 * b + 2] * At;
+      const D3 d = sub(x, y);
+      const double r = nrm(d);
+      if (!(r > 0)) continue;
+      const double e = exp(-kappa * r);
+      const double dn = dot(d, nt);
+      cv += w / (FOUR_PI * r);
+      ck += w * dn / (FOUR_PI * r * r * r);
+      cvy += w * e / (FOUR_PI * r);
+      cky += w * dn * (1 + kappa * r) * e / (FOUR_PI * r * r * r);
+    }
+  }
+  Dval[4 * k + 0] = sv - cv;
+  Dval[4 * k + 1] = sk - ck;
+  Dval[4 * k + 2] = svy - cvy;
+  Dval[4 * k + 3] = sky - cky;
+  if (s == t) {
+    sdiag[2 * s] = sv;
+    sdiag[2 * s + 1] = svy;
+  }
+}
+
+// Inverse of the 2x2 diagonal block [[A/2, -V_L,ss], [A/2, (e1/e2) V_Y,ss]]
+// (K_ss = 0 on a flat triangle).
+__global__ void k_precond_setup(int64_t nt, const double *__restrict__ area, const double *__restrict__ sdiag,
+                                double eratio, double *__restrict__ pre) {
+  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+  if (s >= nt) return;
+  const double a = 0.5 * area[s], b = -sdiag[2 * s], c = 0.5 * area[s], d = eratio * sdiag[2 * s + 1];
+  const double det = a * d - b * c;
+  pre[4 * s + 0] = d / det;
+  pre[4 * s + 1] = -b / det;
+  pre[4 * s + 2] = -c / det;
+  pre[4 * s + 3] = a / det;
+}
+
+__global__ void k_precond_apply(int64_t nt, const double *__restrict__ pre, const double *__restrict__ x,
+                                double *__restrict__ y) {
+  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+  if (s >= nt) return;
+  const double u = x[s], v = x[nt + s];
+  y[s] = pre[4 * s] * u + pre[4 * s + 1] * v;
+  y[nt + s] = pre[4 * s + 2] * u + pre[4 * s + 3] * v;
+}
+
+// P1: densities at the quadrature points, 4 columns: W n_d u (d = 0,1,2), W v.
+template <typename T>
+__global__ void k_bem_p1(int64_t nt, int nq, const double *__restrict__ x, const double *__restrict__ qw,
+                         const double *__restrict__ normal, T *__restrict__ q) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  const int64_t N = nt * nq;
+  if (i >= N) return;
+  const int64_t t = i / nq;
+  const double w = qw[i], u = x[t], v = x[nt + t];
+  q[i] = (T)(w * normal[3 * t] * u);
+  q[N + i] = (T)(w * normal[3 * t + 1] * u);
+  q[2 * N + i] = (T)(w * normal[3 * t + 2] * u);
+  q[3 * N + i] = (T)(w * v);
+}
+
+// P2^T, the sparse correction and the block assembly, one thread per test
+// triangle s.
+template <typename T>
+__global__ void k_bem_p2(int64_t nt, int nq, const T *__restrict__ potl, const T *__restrict__ gradl,
+                         const T *__restrict__ poty, const T *__restrict__ grady, const double *__restrict__ qw,
+                         const double *__restrict__ area, const int32_t *__restrict__ sp_off,
+                         const int32_t *__restrict__ sp_idx, const double *__restrict__ Dval,
+                         const double *__restrict__ x, double eratio, double *__restrict__ y) {
+  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+  if (s >= nt) return;
+  const int64_t N = nt * nq;
+  double kl = 0, vl = 0, ky = 0, vy = 0;
+  for (int a = 0; a < nq; ++a) {
+    const int64_t i = s * nq + a;
+    const double w = qw[i];
+    // K x = -(d/dx_0 of column 0 + d/dx_1 of column 1 + d/dx_2 of column 2)
+    kl -= w * ((double)gradl[i * 3 + 0] + (double)gradl[(N + i) * 3 + 1] + (double)gradl[(2 * N + i) * 3 + 2]);
+    ky -= w * ((double)grady[i * 3 + 0] + (double)grady[(N + i) * 3 + 1] + (double)grady[(2 * N + i) * 3 + 2]);
+    vl += w * (double)potl[3 * N + i];
+    vy += w * (double)poty[3 * N + i];
+  }
+  for (int k = sp_off[s]; k < sp_off[s + 1]; ++k) {
+    const int t = sp_idx[k];
+    const double u = x[t], v = x[nt + t];
+    vl += Dval[4 * k + 0] * v;
+    kl += Dval[4 * k + 1] * u;
+    vy += Dval[4 * k + 2] * v;
+    ky += Dval[4 * k + 3] * u;
+  }
+  const double hu = 0.5 * area[s] * x[s];
+  y[s] = hu + kl - vl;
+  y[nt + s] = hu - ky + eratio * vy;
+}
+
+// FP64 direct sum with monopole and dipole sources:
+//   out_i = sum_j sig_j / (4 pi r) - dip_j . (x_i - y_j) / (4 pi r^3), r > 0.
+__global__ __launch_bounds__(256) void k_direct_md(int64_t nt, const double *__restrict__ tx, int64_t ns,
+                                                   const double *__restrict__ sy, const double *__restrict__ sig,
+                                                   const double *__restrict__ dip, double *__restrict__ out) {
+  __shared__ double sx[256], syy[256], sz[256], ss[256], dx[256], dyy[256], dz[256];
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  const bool act = i < nt;
+  const double xi = act ? tx[3 * i] : 0, yi = act ? tx[3 * i + 1] : 0, zi = act ? tx[3 * i + 2] : 0;
+  double acc = 0;
+  for (int64_t j0 = 0; j0 < ns; j0 += 256) {
+    const int64_t j = j0 + threadIdx.x;
+    if (j < ns) {
+      sx[threadIdx.x] = sy[3 * j];
+      syy[threadIdx.x] = sy[3 * j + 1];
+      sz[threadIdx.x] = sy[3 * j + 2];
+      ss[threadIdx.x] = sig[j];
+      dx[threadIdx.x] = dip ? dip[3 * j] : 0.0;
+      dyy[threadIdx.x] = dip ? dip[3 * j + 1] : 0.0;
+      dz[threadIdx.x] = dip ? dip[3 * j + 2] : 0.0;
+    }
+    __syncthreads();
+    const int cnt = (int)min<int64_t>(256, ns - j0);
+    for (int k = 0; k < cnt; ++k) {
+      const double ax = xi - sx[k], ay = yi - syy[k], az = zi - sz[k];
+      const double r2 = ax * ax + ay * ay + az * az;
+      if (r2 > 0) {
+        const double ir = 1.0 / sqrt(r2);
+        acc += ss[k] * ir - (dx[k] * ax + dyy[k] * ay + dz[k] * az) * ir * ir * ir;
+      }
+    }
+    __syncthreads();
+  }
+  if (act) out[i] = acc / FOUR_PI;
+}
+
+__global__ void k_rhs_assemble(int64_t nt, int nq, const double *__restrict__ qw, const double *__restrict__ f,
+                               double *__restrict__ b) {
+  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+  if (s >= nt) return;
+  double acc = 0;
+  for (int a = 0; a < nq; ++a) acc += qw[s * nq + a] * f[s * nq + a];
+  b[s] = acc;
+  b[nt + s] = 0.0;
+}
+
+__global__ void k_energy_sources(int64_t nt, int nq, const double *__restrict__ x, const double *__restrict__ qw,
+                                 const double *__restrict__ normal, double *__restrict__ sig, double *__restrict__ dip) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= nt * nq) return;
+  const int64_t t = i / nq;
+  sig[i] = qw[i] * x[nt + t];
+  const double mu = qw[i] * x[t];
+  dip[3 * i] = mu * normal[3 * t];
+  dip[3 * i + 1] = mu * normal[3 * t + 1];
+  dip[3 * i + 2] = mu * normal[3 * t + 2];
+}
+
+// ---------------------------------------------------------------------------
+// FP64 vector kernels for GMRES (fixed reduction order: deterministic)
+// ---------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 512;
+
+// partial[r * RED_BLOCKS + b] = sum over block b's chunk of V_r . w
+__global__ __launch_bounds__(256) void k_multidot(const double *__restrict__ V, int64_t n,
+                                                  const double *__restrict__ w, double *__restrict__ partial) {
+  __shared__ double red[256];
+  const int r = blockIdx.y;
+  const int64_t chunk = (n + RED_BLOCKS - 1) / RED_BLOCKS;
+  const int64_t e0 = blockIdx.x * chunk, e1 = min<int64_t>(n, e0 + chunk);
+  const double *v = V + (int64_t)r * n;
+  double acc = 0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) acc += v[e] * w[e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)r * RED_BLOCKS + blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_partials(int nrow, const double *__restrict__ partial, double *__restrict__ out) {
+  const int r = blockIdx.x * 64 + threadIdx.x;
+  if (r >= nrow) return;
+  double acc = 0;
+  for (int b = 0; b < RED_BLOCKS; ++b) acc += partial[(int64_t)r * RED_BLOCKS + b];
+  out[r] = acc;
+}
+
+// w -= sum_r h_r V_r
+__global__ void k_sub_combo(const double *__restrict__ V, int nrow, int64_t n, const double *__restrict__ h,
+                            double *__restrict__ w) {
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  if (e >= n) return;
+  double acc = 0;
+  for (int r = 0; r < nrow; ++r) acc += h[r] * V[(int64_t)r * n + e];
+  w[e] -= acc;
+}
+
+// out = sum_r y_r V_r
+__global__ void k_combo(const double *__restrict__ V, int nrow, int64_t n, const double *__restrict__ y,
+                        double *__restrict__ out) {
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  if (e >= n) return;
+  double acc = 0;
+  for (int r = 0; r < nrow; ++r) acc += y[r] * V[(int64_t)r * n + e];
+  out[e] = acc;
+}
+
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double b, const double *__restrict__ y,
+                        double *__restrict__ out) {
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  if (e < n) out[e] = a * x[e] + b * y[e];
+}
+
+__global__ void k_energy_reduce(int64_t nq, const double *__restrict__ q, const double *__restrict__ phi,
+                                double *__restrict__ out) {
+  __shared__ double red[1024];
+  double acc = 0;
+  for (int64_t k = threadIdx.x; k < nq; k += 1024) acc += q[k] * phi[k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 512; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = 0.5 * red[0] * FOUR_PI * KCAL;
+}
+
+inline unsigned blocks(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+struct bem_op {
+  int64_t nt = 0, nv = 0, N = 0, npair = 0;
+  int nq = 0, precision = 0;
+  double eps_in = 0, eps_out = 0, kappa = 0;
+  fmm_plan *fl = nullptr, *fy = nullptr;
+  double *d_tri = nullptr, *d_normal = nullptr, *d_area = nullptr, *d_qw = nullptr, *d_qpts = nullptr;
+  int32_t *d_sp_off = nullptr, *d_sp_idx = nullptr;
+  double *d_D = nullptr, *d_sdiag = nullptr, *d_pre = nullptr;
+  void *q4 = nullptr, *potl = nullptr, *gradl = nullptr, *poty = nullptr, *grady = nullptr;
+  // GMRES / energy scratch
+  double *d_partial = nullptr, *d_h = nullptr, *d_V = nullptr, *d_z = nullptr, *d_w = nullptr, *d_r = nullptr,
+         *d_xc = nullptr;
+  int64_t V_rows = 0;
+  std::vector<void *> allocs;
+};
+
+namespace {
+
+int balloc(bem_op *op, void **p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+  if (e != hipSuccess) {
+    set_error("bem: hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    *p = nullptr;
+    return FMM_ENOMEM;
+  }
+  op->allocs.push_back(*p);
+  return FMM_OK;
+}
+
+template <typename V>
+int bupload(bem_op *op, V **p, const std::vector<V> &h) {
+  int rc = balloc(op, (void **)p, h.size() * sizeof(V));
+  if (rc) return rc;
+  if (!h.empty()) FMM_HIP_TRY(hipMemcpy(*p, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
+  return FMM_OK;
+}
+
+int ensure_krylov(bem_op *op, int64_t rows) {
+  if (op->V_rows >= rows) return FMM_OK;
+  const int64_t n = 2 * op->nt;
+  int rc;
+  if ((rc = balloc(op, (void **)&op->d_V, (size_t)rows * n * sizeof(double)))) return rc;
+  if ((rc = balloc(op, (void **)&op->d_partial, (size_t)rows * RED_BLOCKS * sizeof(double)))) return rc;
+  if ((rc = balloc(op, (void **)&op->d_h, (size_t)rows * sizeof(double)))) return rc;
+  op->V_rows = rows;
+  return FMM_OK;
+}
+
+// dot products of the first `rows` Krylov vectors (or any rows-by-n block)
+// with w; result on the host
+int multidot(bem_op *op, const double *V, int rows, const double *w, double *h_host, hipStream_t s) {
+  const int64_t n = 2 * op->nt;
+  hipLaunchKernelGGL(k_multidot, dim3(RED_BLOCKS, rows), dim3(256), 0, s, V, n, w, op->d_partial);
+  hipLaunchKernelGGL(k_sum_partials, dim3(blocks(rows, 64)), dim3(64), 0, s, rows, op->d_partial, op->d_h);
+  FMM_HIP_TRY(hipGetLastError());
+  FMM_HIP_TRY(hipMemcpyAsync(h_host, op->d_h, rows * sizeof(double), hipMemcpyDeviceToHost, s));
+  FMM_HIP_TRY(hipStreamSynchronize(s));
+  return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, int quad_pts, double eps_in,
+              double eps_out, double kappa, int p, int ncrit, int precision, fmm_stream_t stream, bem_op **out) {
+  if (!out) { set_error("bem_setup: out is NULL"); return FMM_EINVAL; }
+  *out = nullptr;
+  if (nv <= 0 || nt <= 0 || !verts || !tris) { set_error("bem_setup: empty or null mesh"); return FMM_EINVAL; }
+  if (quad_pts != 3 && quad_pts != 6) { set_error("bem_setup: quad_pts must be 3 or 6"); return FMM_EINVAL; }
+  if (!(eps_in > 0) || !(eps_out > 0) || !std::isfinite(eps_in) || !std::isfinite(eps_out)) {
+    set_error("bem_setup: permittivities must be positive");
+    return FMM_EINVAL;
+  }
+  if (!(kappa >= 0) || !std::isfinite(kappa)) { set_error("bem_setup: kappa must be finite and >= 0"); return FMM_EINVAL; }
+  if (nt * quad_pts > 0x7fffffffll) { set_error("bem_setup: too many quadrature points"); return FMM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  bem_op *op = new (std::nothrow) bem_op();
+  if (!op) { set_error("bem_setup: out of host memory"); return FMM_ENOMEM; }
+  op->nt = nt; op->nv = nv; op->nq = quad_pts; op->N = nt * quad_pts; op->precision = precision;
+  op->eps_in = eps_in; op->eps_out = eps_out; op->kappa = kappa;
+  int rc = FMM_OK;
+  do {
+    // geometry on the host
+    std::vector<double> tri(nt * 9), normal(nt * 3), area(nt), qw(op->N), qpts(op->N * 3);
+    std::vector<double> rq;
+    regular(quad_pts, rq);
+    bool bad = false;
+    for (int64_t t = 0; t < nt; ++t) {
+      double v[3][3];
+      for (int i = 0; i < 3; ++i) {
+        const int32_t vi = tris[3 * t + i];
+        if (vi < 0 || vi >= nv) { bad = true; break; }
+        for (int d = 0; d < 3; ++d) { v[i][d] = verts[3 * vi + d]; tri[t * 9 + 3 * i + d] = v[i][d]; }
+      }
+      if (bad) break;
+      const double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
+      const double e2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
+      const double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+      const double cn = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+      if (!(cn > 0) || !std::isfinite(cn)) { bad = true; break; }
+      area[t] = 0.5 * cn;
+      for (int d = 0; d < 3; ++d) normal[3 * t + d] = c[d] / cn;
+      for (int a = 0; a < quad_pts; ++a) {
+        const double l1 = rq[3 * a], l2 = rq[3 * a + 1], w = rq[3 * a + 2];
+        for (int d = 0; d < 3; ++d) qpts[(t * quad_pts + a) * 3 + d] = (1 - l1 - l2) * v[0][d] + l1 * v[1][d] + l2 * v[2][d];
+        qw[t * quad_pts + a] = w * area[t];
+      }
+    }
+    if (bad) { set_error("bem_setup: bad vertex index or degenerate triangle"); rc = FMM_EINVAL; break; }
+    // pairs of triangles that share a vertex (identical included), s-major
+    std::vector<std::vector<int32_t>> vt(nv);
+    for (int64_t t = 0; t < nt; ++t)
+      for (int i = 0; i < 3; ++i) vt[tris[3 * t + i]].push_back((int32_t)t);
+    std::vector<int32_t> off(nt + 1, 0), idx, ps;
+    std::vector<int32_t> nb;
+    for (int64_t t = 0; t < nt; ++t) {
+      nb.clear();
+      for (int i = 0; i < 3; ++i) nb.insert(nb.end(), vt[tris[3 * t + i]].begin(), vt[tris[3 * t + i]].end());
+      std::sort(nb.begin(), nb.end());
+      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+      idx.insert(idx.end(), nb.begin(), nb.end());
+      ps.insert(ps.end(), nb.size(), (int32_t)t);
+      off[t + 1] = (int32_t)idx.size();
+    }
+    op->npair = (int64_t)idx.size();
+    if ((rc = bupload(op, &op->d_tri, tri))) break;
+    if ((rc = bupload(op, &op->d_normal, normal))) break;
+    if ((rc = bupload(op, &op->d_area, area))) break;
+    if ((rc = bupload(op, &op->d_qw, qw))) break;
+    if ((rc = bupload(op, &op->d_qpts, qpts))) break;
+    if ((rc = bupload(op, &op->d_sp_off, off))) break;
+    if ((rc = bupload(op, &op->d_sp_idx, idx))) break;
+    int32_t *d_ps = nullptr;
+    if ((rc = bupload(op, &d_ps, ps))) break;
+    std::vector<double> ro, rr;
+    collapsed(NO, ro);
+    collapsed(NREM, rr);
+    double *d_ro = nullptr, *d_rr = nullptr, *d_rq = nullptr;
+    if ((rc = bupload(op, &d_ro, ro))) break;
+    if ((rc = bupload(op, &d_rr, rr))) break;
+    if ((rc = bupload(op, &d_rq, rq))) break;
+    if ((rc = balloc(op, (void **)&op->d_D, op->npair * 4 * sizeof(double)))) break;
+    if ((rc = balloc(op, (void **)&op->d_sdiag, nt * 2 * sizeof(double)))) break;
+    if ((rc = balloc(op, (void **)&op->d_pre, nt * 4 * sizeof(double)))) break;
+    hipLaunchKernelGGL(k_singular, dim3(blocks(op->npair, 128)), dim3(128), 0, s, op->npair, d_ps, op->d_sp_idx,
+                       op->d_tri, op->d_normal, op->d_area, d_ro, NO * NO, d_rr, NREM * NREM, d_rq, quad_pts, kappa,
+                       op->d_D, op->d_sdiag);
+    hipLaunchKernelGGL(k_precond_setup, dim3(blocks(nt)), dim3(256), 0, s, nt, op->d_area, op->d_sdiag,
+                       eps_in / eps_out, op->d_pre);
+    if (hipGetLastError() != hipSuccess) { set_error("bem_setup: launch failed"); rc = FMM_EHIP; break; }
+    // the two FMM plans on the quadrature points
+    if ((rc = fmm_setup(op->d_qpts, op->N, FMM_LAPLACE, 0.0, p, ncrit, precision, stream, &op->fl))) break;
+    if ((rc = fmm_setup(op->d_qpts, op->N, FMM_YUKAWA, kappa, p, ncrit, precision, stream, &op->fy))) break;
+    const size_t es = precision == FMM_FP64 ? 8 : 4;
+    if ((rc = balloc(op, &op->q4, 4 * op->N * es))) break;
+    if ((rc = balloc(op, &op->potl, 4 * op->N * es))) break;
+    if ((rc = balloc(op, &op->gradl, 12 * op->N * es))) break;
+    if ((rc = balloc(op, &op->poty, 4 * op->N * es))) break;
+    if ((rc = balloc(op, &op->grady, 12 * op->N * es))) break;
+    if ((rc = balloc(op, (void **)&op->d_z, 2 * nt * sizeof(double)))) break;
+    if ((rc = balloc(op, (void **)&op->d_w, 2 * nt * sizeof(double)))) break;
+    if ((rc = balloc(op, (void **)&op->d_r, 2 * nt * sizeof(double)))) break;
+    if ((rc = balloc(op, (void **)&op->d_xc, 2 * nt * sizeof(double)))) break;
+    if ((rc = ensure_krylov(op, 2))) break;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { set_error(std::string("bem_setup: ") + hipGetErrorString(e)); rc = FMM_EHIP; }
+  } while (0);
+  if (rc) { bem_free(op); return rc; }
+  *out = op;
+  return FMM_OK;
+}
+
+int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
+  if (!op || !x || !y) { set_error("bem_matvec: null argument"); return FMM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t N = op->N, nt = op->nt;
+  int rc;
+  const double er = op->eps_in / op->eps_out;
+  if (op->precision == FMM_FP64) {
+    hipLaunchKernelGGL(k_bem_p1<double>, dim3(blocks(N)), dim3(256), 0, s, nt, op->nq, x, op->d_qw, op->d_normal,
+                       (double *)op->q4);
+  } else {
+    hipLaunchKernelGGL(k_bem_p1<float>, dim3(blocks(N)), dim3(256), 0, s, nt, op->nq, x, op->d_qw, op->d_normal,
+                       (float *)op->q4);
+  }
+  FMM_HIP_TRY(hipGetLastError());
+  if ((rc = fmm::eval_dispatch(op->fl, op->q4, 4, op->potl, op->gradl, s))) return rc;
+  if ((rc = fmm::eval_dispatch(op->fy, op->q4, 4, op->poty, op->grady, s))) return rc;
+  if (op->precision == FMM_FP64) {
+    hipLaunchKernelGGL(k_bem_p2<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const double *)op->potl,
+                       (const double *)op->gradl, (const double *)op->poty, (const double *)op->grady, op->d_qw,
+                       op->d_area, op->d_sp_off, op->d_sp_idx, op->d_D, x, er, y);
+  } else {
+    hipLaunchKernelGGL(k_bem_p2<float>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const float *)op->potl,
+                       (const float *)op->gradl, (const float *)op->poty, (const float *)op->grady, op->d_qw,
+                       op->d_area, op->d_sp_off, op->d_sp_idx, op->d_D, x, er, y);
+  }
+  FMM_HIP_TRY(hipGetLastError());
+  return FMM_OK;
+}
+
+int bem_precondition(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
+  if (!op || !x || !y) { set_error("bem_precondition: null argument"); return FMM_EINVAL; }
+  hipLaunchKernelGGL(k_precond_apply, dim3(blocks(op->nt)), dim3(256), 0, (hipStream_t)stream, op->nt, op->d_pre, x, y);
+  FMM_HIP_TRY(hipGetLastError());
+  return FMM_OK;
+}
+
+int bem_rhs(bem_op *op, const double *qxyz, const double *q, int64_t nq, double *b, fmm_stream_t stream) {
+  if (!op || !b || nq < 0 || (nq > 0 && (!qxyz || !q))) { set_error("bem_rhs: bad argument"); return FMM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  double *sig = nullptr, *f = nullptr;
+  FMM_HIP_TRY(hipMallocAsync((void **)&sig, std::max<int64_t>(1, nq) * sizeof(double), s));
+  FMM_HIP_TRY(hipMallocAsync((void **)&f, op->N * sizeof(double), s));
+  // sigma_k = q_k / eps_in
+  hipLaunchKernelGGL(k_axpby, dim3(blocks(std::max<int64_t>(1, nq))), dim3(256), 0, s, nq, 1.0 / op->eps_in, q, 0.0, q,
+                     sig);
+  hipLaunchKernelGGL(k_direct_md, dim3(blocks(op->N)), dim3(256), 0, s, op->N, op->d_qpts, nq, qxyz, sig,
+                     (const double *)nullptr, f);
+  hipLaunchKernelGGL(k_rhs_assemble, dim3(blocks(op->nt)), dim3(256), 0, s, op->nt, op->nq, op->d_qw, f, b);
+  FMM_HIP_TRY(hipGetLastError());
+  FMM_HIP_TRY(hipFreeAsync(sig, s));
+  FMM_HIP_TRY(hipFreeAsync(f, s));
+  return FMM_OK;
+}
+
+int bem_energy(bem_op *op, const double *x, const double *qxyz, const double *q, int64_t nq, double *dG,
+               fmm_stream_t stream) {
+  if (!op || !x || !dG || nq < 0 || (nq > 0 && (!qxyz || !q))) { set_error("bem_energy: bad argument"); return FMM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  *dG = 0;
+  if (nq == 0) return FMM_OK;
+  double *sig = nullptr, *dip = nullptr, *phi = nullptr, *res = nullptr;
+  FMM_HIP_TRY(hipMallocAsync((void **)&sig, op->N * sizeof(double), s));
+  FMM_HIP_TRY(hipMallocAsync((void **)&dip, op->N * 3 * sizeof(double), s));
+  FMM_HIP_TRY(hipMallocAsync((void **)&phi, nq * sizeof(double), s));
+  FMM_HIP_TRY(hipMallocAsync((void **)&res, sizeof(double), s));
+  hipLaunchKernelGGL(k_energy_sources, dim3(blocks(op->N)), dim3(256), 0, s, op->nt, op->nq, x, op->d_qw,
+                     op->d_normal, sig, dip);
+  hipLaunchKernelGGL(k_direct_md, dim3(blocks(nq)), dim3(256), 0, s, nq, qxyz, op->N, op->d_qpts, sig, dip, phi);
+  hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(1024), 0, s, nq, q, phi, res);
+  FMM_HIP_TRY(hipGetLastError());
+  FMM_HIP_TRY(hipMemcpyAsync(dG, res, sizeof(double), hipMemcpyDeviceToHost, s));
+  FMM_HIP_TRY(hipStreamSynchronize(s));
+  (void)hipFreeAsync(sig, s);
+  (void)hipFreeAsync(dip, s);
+  (void)hipFreeAsync(phi, s);
+  (void)hipFreeAsync(res, s);
+  return FMM_OK;
+}
+
+// One GMRES run on op (right preconditioning) from x: stops at relative
+// residual tol (relative to bnorm) measured with the recomputed residual.
+static int gmres_core(bem_op *op, const double *b, double *x, double bnorm, double tol, int maxiter, int restart,
+                      int *it_total, double *hist, int hist_cap, hipStream_t s) {
+  const int64_t n = 2 * op->nt;
+  int rc;
+  if (restart <= 0 || restart > maxiter) restart = maxiter;
+  if ((rc = ensure_krylov(op, restart + 1))) return rc;
+  std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h(restart + 1),
+      h2(restart + 1), y(restart);
+  double *V = op->d_V;
+  while (true) {
+    // r = b - A x
+    if ((rc = bem_matvec(op, x, op->d_w, s))) return rc;
+    hipLaunchKernelGGL(k_axpby, dim3(blocks(n)), dim3(256), 0, s, n, 1.0, b, -1.0, op->d_w, op->d_r);
+    double rr;
+    if ((rc = multidot(op, op->d_r, 1, op->d_r, &rr, s))) return rc;
+    double beta = std::sqrt(rr);
+    if (!std::isfinite(beta)) { set_error("gmres: non-finite residual"); return FMM_EBREAKDOWN; }
+    if (beta <= tol * bnorm) return FMM_OK;
+    if (*it_total >= maxiter) return FMM_ENOTCONV;
+    hipLaunchKernelGGL(k_axpby, dim3(blocks(n)), dim3(256), 0, s, n, 1.0 / beta, op->d_r, 0.0, op->d_r, V);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    for (; j < restart && *it_total < maxiter; ++j) {
+      double *vj = V + (int64_t)j * n, *vn = V + (int64_t)(j + 1) * n;
+      if ((rc = bem_precondition(op, vj, op->d_z, s))) return rc;
+      if ((rc = bem_matvec(op, op->d_z, vn, s))) return rc;
+      // classical Gram-Schmidt, twice
+      if ((rc = multidot(op, V, j + 1, vn, h.data(), s))) return rc;
+      FMM_HIP_TRY(hipMemcpyAsync(op->d_h, h.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_sub_combo, dim3(blocks(n)), dim3(256), 0, s, V, j + 1, n, op->d_h, vn);
+      if ((rc = multidot(op, V, j + 1, vn, h2.data(), s))) return rc;
+      FMM_HIP_TRY(hipMemcpyAsync(op->d_h, h2.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_sub_combo, dim3(blocks(n)), dim3(256), 0, s, V, j + 1, n, op->d_h, vn);
+      for (int i = 0; i <= j; ++i) h[i] += h2[i];
+      double ww;
+      if ((rc = multidot(op, vn, 1, vn, &ww, s))) return rc;
+      const double hn = std::sqrt(ww);
+      if (!std::isfinite(hn)) { set_error("gmres: non-finite Arnoldi vector"); return FMM_EBREAKDOWN; }
+      if (hn > 0)
+        hipLaunchKernelGGL(k_axpby, dim3(blocks(n)), dim3(256), 0, s, n, 1.0 / hn, vn, 0.0, vn, vn);
+      // Givens rotations on the Hessenberg column
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+      }
+      const double den = std::hypot(h[j], hn);
+      cs[j] = den > 0 ? h[j] / den : 1.0;
+      sn[j] = den > 0 ? hn / den : 0.0;
+      h[j] = den;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      for (int i = 0; i <= j; ++i) H[(size_t)i * restart + j] = h[i];
+      const double est = std::fabs(g[j + 1]) / bnorm;
+      if (hist && *it_total < hist_cap) hist[*it_total] = est;
+      ++*it_total;
+      if (est <= tol || hn == 0) { ++j; break; }
+    }
+    // solve the triangular system and update x += P^-1 V y
+    for (int i = j - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int k = i + 1; k < j; ++k) t -= H[(size_t)i * restart + k] * y[k];
+      y[i] = t / H[(size_t)i * restart + i];
+    }
+    FMM_HIP_TRY(hipMemcpyAsync(op->d_h, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_combo, dim3(blocks(n)), dim3(256), 0, s, V, j, n, op->d_h, op->d_w);
+    if ((rc = bem_precondition(op, op->d_w, op->d_z, s))) return rc;
+    hipLaunchKernelGGL(k_axpby, dim3(blocks(n)), dim3(256), 0, s, n, 1.0, x, 1.0, op->d_z, x);
+    FMM_HIP_TRY(hipGetLastError());
+  }
+}
+
+int gmres_solve(bem_op *op, bem_op *refine, const double *b, double *x, double tol, double inner_tol, int maxiter,
+                int restart, int *iters, double *hist, fmm_stream_t stream) {
+  if (!op || !b || !x || !(tol > 0) || maxiter < 1) { set_error("gmres_solve: bad argument"); return FMM_EINVAL; }
+  if (refine && refine->nt != op->nt) { set_error("gmres_solve: refine operator on another mesh"); return FMM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = 2 * op->nt;
+  int it = 0, rc;
+  double bb;
+  if ((rc = multidot(op, b, 1, b, &bb, s))) return rc;
+  const double bnorm = std::sqrt(bb);
+  if (iters) *iters = 0;
+  if (bnorm == 0) {
+    hipLaunchKernelGGL(k_axpby, dim3(blocks(n)), dim3(256), 0, s, n, 0.0, b, 0.0, b, x);
+    FMM_HIP_TRY(hipStreamSynchronize(s));
+    return FMM_OK;
+  }
+  if (!refine) {
+    rc = gmres_core(op, b, x, bnorm, tol, maxiter, restart, &it, hist, maxiter, s);
+    if (iters) *iters = it;
+    return rc;
+  }
+  // iterative refinement: residuals with `refine`, corrections with `op`
+  if (!(inner_tol > 0)) inner_tol = 1e-4;
+  for (int outer = 0; outer < 50; ++outer) {
+    if ((rc = bem_matvec(refine, x, refine->d_w, s))) return rc;
+    hipLaunchKernelGGL(k_axpby, dim3(blocks(n)), dim3(256), 0, s, n, 1.0, b, -1.0, refine->d_w, refine->d_r);
+    double rr;
+    if ((rc = multidot(op, refine->d_r, 1, refine->d_r, &rr, s))) return rc;
+    const double rn = std::sqrt(rr);
+    if (!std::isfinite(rn)) { set_error("gmres: non-finite residual"); return FMM_EBREAKDOWN; }
+    if (rn <= tol * bnorm) { if (iters) *iters = it; return FMM_OK; }
+    if (it >= maxiter) break;
+    // correction d: op d = r, from d = 0
+    hipLaunchKernelGGL(k_axpby, dim3(blocks(n)), dim3(256), 0, s, n, 0.0, b, 0.0, b, refine->d_xc);
+    rc = gmres_core(op, refine->d_r, refine->d_xc, rn, inner_tol, maxiter, restart, &it, hist, maxiter, s);
+    if (rc != FMM_OK && rc != FMM_ENOTCONV) return rc;
+    hipLaunchKernelGGL(k_axpby, dim3(blocks(n)), dim3(256), 0, s, n, 1.0, x, 1.0, refine->d_xc, x);
+    FMM_HIP_TRY(hipGetLastError());
+  }
+  if (iters) *iters = it;
+  return FMM_ENOTCONV;
+}
+
+int bem_info(const bem_op *op, bem_info_t *o) {
+  if (!op || !o) { set_error("bem_info: null argument"); return FMM_EINVAL; }
+  o->n_triangles = op->nt;
+  o->n_points = op->N;
+  o->n_singular_pairs = op->npair;
+  o->quad_pts = op->nq;
+  o->precision = op->precision;
+  return FMM_OK;
+}
+
+fmm_plan *bem_fmm_plan(bem_op *op, int kernel) {
+  if (!op) return nullptr;
+  return kernel == FMM_YUKAWA ? op->fy : op->fl;
+}
+
+void bem_free(bem_op *op) {
+  if (!op) return;
+  fmm_free(op->fl);
+  fmm_free(op->fy);
+  for (void *p : op->allocs) (void)hipFree(p);
+  delete op;
+}
+
+}  // extern "C"

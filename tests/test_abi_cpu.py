@@ -59,3 +59,26 @@ def test_setup_rejects_bad_arguments(args, frag):
 def test_eval_rejects_null_plan():
     L = _lib.lib()
     assert L.fmm_eval(None, None, 1, None, None, None) == _lib.FMM_EINVAL
+
+
+@pytest.mark.parametrize("case", ["quad", "eps", "kappa", "index", "degenerate"])
+def test_bem_setup_rejects_bad_arguments(case):
+    import numpy as np
+    L = _lib.lib()
+    v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
+    t = np.array([[0, 1, 2], [0, 1, 3]], dtype=np.int32)
+    quad, eps, kap = 3, 4.0, 0.1
+    if case == "quad":
+        quad = 4
+    elif case == "eps":
+        eps = -1.0
+    elif case == "kappa":
+        kap = float("inf")
+    elif case == "index":
+        t = np.array([[0, 1, 7]], dtype=np.int32)
+    elif case == "degenerate":
+        t = np.array([[0, 1, 1]], dtype=np.int32)
+    h = ctypes.c_void_p()
+    rc = L.bem_setup(ctypes.c_void_p(v.ctypes.data), len(v), ctypes.c_void_p(t.ctypes.data), len(t), quad, eps, 80.0,
+                     kap, 6, 64, 1, None, ctypes.byref(h))
+    assert rc == _lib.FMM_EINVAL and not h.value

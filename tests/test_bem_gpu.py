@@ -1,0 +1,145 @@
+"""GPU parity of the boundary-element path (bem_matvec, bem_rhs, GMRES,
+bem_energy) against the dense FP64 BEM oracle, and the Born/Kirkwood
+closed forms.
+
+Tolerances: the FMM (p = 8, FP64) is accurate to ~1e-8 and the singular
+corrections use the same closed-form scheme on both sides, so the FP64
+matvec matches the dense oracle to 1e-6; the FP32 path to 1e-4.  GMRES
+solutions are compared after solving to 1e-9 (FP64) and, with FP64
+refinement, from the FP32 operator."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import analytic as A
+from oracle import bem as B
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+KAPPA = 0.125
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def _ops(v, t, precision, p=8, ncrit=64, quad=3):
+    require_gpu()
+    from paper_2103_01048_amd import BEMOperator
+    return BEMOperator(v, t, quad_pts=quad, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=p, ncrit=ncrit,
+                       precision=precision)
+
+
+@pytest.fixture(scope="module")
+def sphere512():
+    v, t = synth.octa_sphere(3, 4.0)
+    m = B.make_mesh(v, t, 3)
+    A_ = B.system(m, 4.0, 80.0, KAPPA)
+    return v, t, m, A_
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-4)])
+def test_matvec_matches_dense_oracle(sphere512, precision, tol):
+    torch = require_gpu()
+    v, t, m, A_ = sphere512
+    op = _ops(v, t, precision)
+    rng = np.random.default_rng(41)
+    for _ in range(2):
+        x = rng.standard_normal(2 * len(t))
+        y = op.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
+        e = _rel(y, A_ @ x)
+        print(f"[bem matvec {precision}] rel {e:.2e}", flush=True)
+        assert e < tol
+
+
+def test_matvec_sphere_union_mesh():
+    torch = require_gpu()
+    su = synth.sphere_union_spheres(12, seed=42, box=8.0)
+    v, t = synth.sphere_union_mesh(su, 1200, seed=42)
+    m = B.make_mesh(v, t, 3)
+    A_ = B.system(m, 4.0, 80.0, KAPPA)
+    x = np.random.default_rng(42).standard_normal(2 * len(t))
+    op = _ops(v, t, "fp64", ncrit=48)
+    y = op.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert _rel(y, A_ @ x) < 1e-6
+
+
+def test_rhs_matches_oracle(sphere512):
+    require_gpu()
+    v, t, m, _ = sphere512
+    op = _ops(v, t, "fp64")
+    qx = np.array([[1.0, 1.0, 1.0], [-0.5, 0.2, 0.3]])
+    q = np.array([1.0, -0.4])
+    b = op.rhs(qx, q).cpu().numpy()
+    np.testing.assert_allclose(b, B.rhs(m, qx, q, 4.0), rtol=1e-12, atol=1e-15)
+
+
+def test_gmres_solution_and_energy(sphere512):
+    require_gpu()
+    from paper_2103_01048_amd import gmres
+    v, t, m, A_ = sphere512
+    qx, q = [[1.0, 1.0, 1.0]], [1.0]
+    x_lu = np.linalg.solve(A_, B.rhs(m, qx, q, 4.0))
+    e_lu = B.energy(m, x_lu, qx, q)
+    op = _ops(v, t, "fp64")
+    b = op.rhs(qx, q)
+    x, it, hist, rc = gmres(op, b, tol=1e-10, maxiter=300)
+    assert rc == 0 and 0 < it < 300
+    assert np.all(np.diff(hist) <= 1e-12 + 0 * hist[1:])  # GMRES residuals never increase
+    xs = x.cpu().numpy()
+    assert _rel(xs, x_lu) < 1e-5
+    e = op.energy(x, qx, q)
+    print(f"[bem energy] gpu {e:.8f} oracle {e_lu:.8f} iters {it}", flush=True)
+    assert e == pytest.approx(e_lu, rel=1e-6)
+
+
+def test_refinement_recovers_fp64_solution(sphere512):
+    require_gpu()
+    from paper_2103_01048_amd import gmres
+    v, t, m, A_ = sphere512
+    qx, q = [[1.0, 1.0, 1.0]], [1.0]
+    x_lu = np.linalg.solve(A_, B.rhs(m, qx, q, 4.0))
+    lo = _ops(v, t, "fp32", p=6)
+    hi = _ops(v, t, "fp64", p=8)
+    b = hi.rhs(qx, q)
+    x, it, hist, rc = gmres(lo, b, tol=1e-8, maxiter=400, refine=hi, inner_tol=1e-4)
+    assert rc == 0
+    assert _rel(x.cpu().numpy(), x_lu) < 1e-6
+
+
+def test_zero_rhs_and_maxiter(sphere512):
+    torch = require_gpu()
+    from paper_2103_01048_amd import gmres
+    v, t, _, _ = sphere512
+    op = _ops(v, t, "fp32", p=5)
+    z = torch.zeros(2 * len(t), dtype=torch.float64, device="cuda")
+    x, it, _, rc = gmres(op, z, tol=1e-6, maxiter=10)
+    assert rc == 0 and it == 0 and float(x.abs().max()) == 0.0
+    b = op.rhs([[1.0, 1.0, 1.0]], [1.0])
+    x, it, _, rc = gmres(op, b, tol=1e-14, maxiter=3)
+    assert rc == -4 and it == 3
+
+
+def test_kirkwood_convergence_on_gpu():
+    """Sphere R = 4 A, unit charge at (1,1,1), eps 4/80, kappa 0.125:
+    error of the solvation energy against Kirkwood's series falls ~4x per
+    4x refinement (the paper's order-1 convergence)."""
+    require_gpu()
+    from paper_2103_01048_amd import gmres
+    ref = A.kirkwood_energy(4.0, [1, 1, 1], [1.0], 4.0, 80.0, KAPPA)
+    errs = []
+    for lev in (3, 4, 5):
+        v, t = synth.octa_sphere(lev, 4.0)
+        op = _ops(v, t, "fp64", p=8, ncrit=64, quad=6)
+        b = op.rhs([[1.0, 1.0, 1.0]], [1.0])
+        x, it, _, rc = gmres(op, b, tol=1e-8, maxiter=500)
+        assert rc == 0
+        e = op.energy(x, [[1.0, 1.0, 1.0]], [1.0])
+        errs.append(abs(e - ref))
+        print(f"[kirkwood] T={len(t)} dG={e:.6f} ref={ref:.6f} iters={it}", flush=True)
+    for a, b in zip(errs, errs[1:]):
+        order = math.log(a / b) / math.log(4.0)
+        assert 0.85 < order < 1.15, errs
+    assert errs[-1] / abs(ref) < 2e-3
