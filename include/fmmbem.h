@@ -96,6 +96,19 @@ int fmm_setup(const double *xyz_dev, int64_t n, int kernel, double kappa, int p,
 int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *grad_dev,
              fmm_stream_t stream);
 
+/* Adjoint of fmm_eval for a loss L(pot) with upstream gradient gbar_dev =
+ * dL/dpot (nrhs x n, same type and layout as pot).  Because the kernel is
+ * symmetric and targets = sources, the density gradient is one more
+ * evaluation, dq = G gbar; the position gradient of point k (summed over the
+ * columns) is  dxyz_k = sum_c [gbar_ck grad(pot_c)_k + q_ck grad(psi_c)_k]
+ * with psi = G gbar.  q_dev and grad_fwd_dev are the forward densities and
+ * the forward gradient output (nrhs x n x 3).  dq_dev (nrhs x n) and
+ * dxyz_dev (n x 3) are written; either may be NULL to skip it.  Gradients
+ * of L with respect to the forward gradient output are not supported (they
+ * need second derivatives of the kernel).  Asynchronous. */
+int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const void *grad_fwd_dev, int nrhs,
+                void *dq_dev, void *dxyz_dev, fmm_stream_t stream);
+
 /* Sizes of the plan's tree, for tests and reports. */
 typedef struct {
   int64_t n_points;

@@ -5,3 +5,4 @@ C ABI in include/fmmbem.h.  This package is the thin Python binding."""
 from ._lib import FmmError, lib  # noqa: F401
 from .fmm import FMMPlan  # noqa: F401
 from .bem import BEMOperator, gmres  # noqa: F401,E402
+from .autograd import FMMPotential, fmm_potential, solvation_style_energy  # noqa: F401,E402

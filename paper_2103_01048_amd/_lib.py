@@ -53,6 +53,7 @@ SIGNATURES = {
     "fmm_free": (None, [vp]),
     "fmm_last_error": (ctypes.c_char_p, []),
     "fmm_set_profiling": (i32, [vp, i32]),
+    "fmm_adjoint": (i32, [vp, vp, vp, vp, i32, vp, vp, vp]),
     "bem_setup": (i32, [vp, i64, vp, i64, i32, dbl, dbl, dbl, i32, i32, i32, vp, P(vp)]),
     "bem_matvec": (i32, [vp, vp, vp, vp]),
     "bem_rhs": (i32, [vp, vp, vp, i64, vp, vp]),

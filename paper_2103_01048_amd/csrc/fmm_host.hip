@@ -40,6 +40,8 @@ int device_morton_sort(const double *xyz, int64_t n, const double lo[3], double 
 int device_gather_points(const double *xyz, const int32_t *perm, int64_t n, const double shift[3], int prec,
                          void *pts, hipStream_t s);
 int eval_dispatch(fmm_plan *P, const void *q, int nrhs, void *pot, void *grad, hipStream_t s);
+int adjoint_combine(fmm_plan *P, int nrhs, const void *q, const void *gbar, const void *gphi, const void *gpsi,
+                    void *dx, hipStream_t s);
 
 static int dev_alloc(fmm_plan *P, void **ptr, size_t bytes) {
   if (bytes == 0) bytes = 16;
@@ -998,6 +1000,28 @@ int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *g
   if (plan->n == 0) return FMM_OK;
   if (!q_dev || !pot_dev) { set_error("fmm_eval: null buffer"); return FMM_EINVAL; }
   return eval_dispatch(plan, q_dev, nrhs, pot_dev, grad_dev, (hipStream_t)stream);
+}
+
+int fmm_adjoint(fmm_plan *P, const void *q, const void *gbar, const void *gfwd, int nrhs, void *dq, void *dxyz,
+                fmm_stream_t stream) {
+  if (!P || !gbar || nrhs < 1 || nrhs > 64) { set_error("fmm_adjoint: bad argument"); return FMM_EINVAL; }
+  if (dxyz && (!q || !gfwd)) { set_error("fmm_adjoint: position gradient needs q and the forward gradient"); return FMM_EINVAL; }
+  if (P->n == 0) return FMM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t es = P->precision == FMM_FP64 ? 8 : 4;
+  const size_t need = (size_t)nrhs * P->n * 4 * es;  // psi + grad psi
+  if (P->adj_bytes < need) {
+    int rc;
+    if ((rc = dev_alloc(P, &P->adj, need))) return rc;
+    P->adj_bytes = need;
+  }
+  char *psi = (char *)P->adj;
+  char *gpsi = psi + (size_t)nrhs * P->n * es;
+  int rc;
+  if ((rc = eval_dispatch(P, gbar, nrhs, psi, dxyz ? gpsi : nullptr, s))) return rc;
+  if (dq) FMM_HIP_TRY(hipMemcpyAsync(dq, psi, (size_t)nrhs * P->n * es, hipMemcpyDeviceToDevice, s));
+  if (dxyz) return adjoint_combine(P, nrhs, q, gbar, gfwd, gpsi, dxyz, s);
+  return FMM_OK;
 }
 
 int fmm_info(const fmm_plan *P, fmm_info_t *o) {

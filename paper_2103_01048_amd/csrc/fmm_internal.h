@@ -154,6 +154,8 @@ struct fmm_plan {
   int profiling = 0;               // bit k set: time phase k
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_events;
   std::vector<hipEvent_t> event_pool;
+  void *adj = nullptr;              // adjoint scratch: psi and grad psi
+  size_t adj_bytes = 0;
   int64_t device_bytes = 0;
   double setup_ms = 0;
   std::vector<void *> allocs;      // everything to free

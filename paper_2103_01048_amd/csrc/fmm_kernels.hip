@@ -757,6 +757,39 @@ static int eval_typed(fmm_plan *P, const T *q, int nrhs, T *pot, T *grad, hipStr
   return FMM_OK;
 }
 
+// dxyz_k = sum_c gbar_ck gphi_ck + q_ck gpsi_ck  (c over density columns)
+template <typename T>
+__global__ void k_adjoint_combine(int64_t N, int nrhs, const T *__restrict__ q, const T *__restrict__ gbar,
+                                  const T *__restrict__ gphi, const T *__restrict__ gpsi, T *__restrict__ dx) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= N) return;
+  T a0 = 0, a1 = 0, a2 = 0;
+  for (int c = 0; c < nrhs; ++c) {
+    const int64_t j = (int64_t)c * N + i;
+    const T gb = gbar[j], qq = q[j];
+    a0 += gb * gphi[3 * j] + qq * gpsi[3 * j];
+    a1 += gb * gphi[3 * j + 1] + qq * gpsi[3 * j + 1];
+    a2 += gb * gphi[3 * j + 2] + qq * gpsi[3 * j + 2];
+  }
+  dx[3 * i] = a0;
+  dx[3 * i + 1] = a1;
+  dx[3 * i + 2] = a2;
+}
+
+int adjoint_combine(fmm_plan *P, int nrhs, const void *q, const void *gbar, const void *gphi, const void *gpsi,
+                    void *dx, hipStream_t s) {
+  const int64_t N = P->n;
+  if (P->precision == FMM_FP64)
+    hipLaunchKernelGGL(k_adjoint_combine<double>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, nrhs,
+                       (const double *)q, (const double *)gbar, (const double *)gphi, (const double *)gpsi,
+                       (double *)dx);
+  else
+    hipLaunchKernelGGL(k_adjoint_combine<float>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, nrhs,
+                       (const float *)q, (const float *)gbar, (const float *)gphi, (const float *)gpsi, (float *)dx);
+  FMM_HIP_TRY(hipGetLastError());
+  return FMM_OK;
+}
+
 int eval_dispatch(fmm_plan *P, const void *q, int nrhs, void *pot, void *grad, hipStream_t s) {
   if (P->precision == FMM_FP64) return eval_typed<double>(P, (const double *)q, nrhs, (double *)pot, (double *)grad, s);
   return eval_typed<float>(P, (const float *)q, nrhs, (float *)pot, (float *)grad, s);

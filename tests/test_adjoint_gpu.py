@@ -1,0 +1,87 @@
+"""GPU checks of the hand-written adjoint (fmm_adjoint behind
+torch.autograd.Function) against the FP64 oracle and finite differences.
+
+E = 1/2 q . phi:  dE/dq = phi,  dE/dx_k = q_k grad(phi)_k.
+General upstream w:  dL/dq = G w,  dL/dx_k = w_k grad(phi)_k + q_k grad(psi)_k, psi = G w."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct as D
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(x, **kw):
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    return FMMPlan(torch.tensor(x, dtype=torch.float64, device="cuda"), **kw)
+
+
+def test_density_gradcheck_single_leaf():
+    """N <= ncrit: the FMM is the exact direct sum, so torch's finite-
+    difference gradcheck applies in FP64."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPotential
+    x, q = synth.unit_sphere_cloud(120, seed=51)
+    plan = _plan(x, kernel="yukawa", kappa=0.5, p=4, ncrit=512, precision="fp64")
+    qt = torch.tensor(q, device="cuda", requires_grad=True)
+    xt = torch.zeros((len(x), 3), dtype=torch.float64, device="cuda")
+    assert torch.autograd.gradcheck(lambda qq: FMMPotential.apply(qq, xt, plan), (qt,), eps=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
+def test_general_upstream_matches_oracle(kernel):
+    torch = require_gpu()
+    from paper_2103_01048_amd import fmm_potential
+    x, q = synth.unit_sphere_cloud(3000, seed=52)
+    w = np.random.default_rng(52).standard_normal(len(x))
+    plan = _plan(x, kernel=kernel, kappa=0.3, p=8, ncrit=32, precision="fp64")
+    qt = torch.tensor(q, device="cuda", requires_grad=True)
+    xt = torch.tensor(x, device="cuda", requires_grad=True)
+    pot = fmm_potential(plan, qt, xt)
+    (pot * torch.tensor(w, device="cuda")).sum().backward()
+    phi, gphi = D.direct(x, x, q, kernel, 0.3)
+    psi, gpsi = D.direct(x, x, w, kernel, 0.3)
+    assert D.rel_l2(qt.grad.cpu().numpy(), psi) < 1e-6
+    ref_dx = w[:, None] * gphi + q[:, None] * gpsi
+    assert D.rel_l2(xt.grad.cpu().numpy(), ref_dx) < 1e-6
+
+
+def test_energy_gradients_fp32_vs_finite_differences():
+    """Sphere-union surface cloud, Laplace, FP32 forward and adjoint; dE/dq
+    against the FP64 potential, dE/dx on 64 seeded coordinates against
+    central differences (h = 1e-4 A) of the FP64 pair sum."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import solvation_style_energy
+    su = synth.sphere_union_spheres(60, seed=53, box=25.0)
+    v, t = synth.sphere_union_mesh(su, 20000, seed=53)
+    x = synth.three_point_cloud(v, t)
+    q = np.random.default_rng(53).uniform(-1, 1, len(x))
+    plan = _plan(x, kernel="laplace", p=8, ncrit=128, precision="fp32")
+    qt = torch.tensor(q, device="cuda", requires_grad=True)
+    xt = torch.tensor(x, device="cuda", requires_grad=True)
+    E = solvation_style_energy(plan, qt, xt)
+    E.backward()
+    dq = qt.grad.cpu().numpy()
+    dx = xt.grad.cpu().numpy()
+    rng = np.random.default_rng(54)
+    rows = rng.choice(len(x), 2048, replace=False)
+    phi, _ = D.direct(x[rows], x, q)
+    assert D.rel_l2(dq[rows], phi) < 1e-4
+    pick = rng.choice(len(x), 64, replace=False)
+    dims = rng.integers(0, 3, 64)
+    h = 1e-4
+    fd = np.empty(64)
+    for n_, (k, d) in enumerate(zip(pick, dims)):
+        e = np.zeros(3)
+        e[d] = h
+        others = np.delete(np.arange(len(x)), k)
+        pp, _ = D.direct(x[k:k + 1] + e, x[others], q[others])
+        pm, _ = D.direct(x[k:k + 1] - e, x[others], q[others])
+        fd[n_] = q[k] * (pp[0] - pm[0]) / (2 * h)
+    got = dx[pick, dims]
+    err = D.rel_l2(got, fd)
+    print(f"[adjoint fd] rel L2 over 64 coordinates {err:.2e}", flush=True)
+    assert err < 1e-3
