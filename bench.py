@@ -45,6 +45,26 @@ PEAK_HBM = 8.0e12
 FLOP_PER_PAIR = {"laplace": 20, "yukawa": 27}
 
 
+def measured_traffic(kernel: str, phase: str, precision: str):
+    """HBM bytes per launch (read + write) of the dominant kernel, from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in profiles/, or None
+    when the kernel source changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2103_01048_amd", "csrc", "fmm_kernels.hip")
+    if phase != "leaf" or precision == "fp64" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernels_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    name = f"void fmm::k_leaf_eval<float, 1, {1 if kernel == 'yukawa' else 0}>"
+    t = rec["traffic"].get(name)
+    if not t:
+        return None
+    return {"bytes_per_launch": round(t["read_bytes"] + t["write_bytes"]), "read_bytes": round(t["read_bytes"]),
+            "write_bytes": round(t["write_bytes"]), "source": "profiles/" + rec["profile"]}
+
+
 def workload(seed: int = 1):
     import synth
     su = synth.sphere_union_spheres(200, seed=seed, box=40.0, rmin=1.5, rmax=2.0)
@@ -64,6 +84,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -107,6 +129,14 @@ def main():
         for pl in plans.values():
             pl.set_profiling(False)
         return dt, prof
+
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     qd = {torch.float32: torch.tensor(q, dtype=torch.float32, device=dev),
           torch.float64: torch.tensor(q, dtype=torch.float64, device=dev)}
@@ -172,9 +202,10 @@ def main():
         roof = {"bound": "alu", "peak": PEAK_VALU_FP32, "unit": "TFLOP/s"}
     avg_ms = dms / max(1, dcnt)
     achieved = flops / (avg_ms * 1e-3)
+    traffic = measured_traffic(dk, dname, args.precision)
     roofline = {"bound": roof["bound"], "kernel": f"{dk}:{dname}", "achieved": round(achieved / 1e12, 3),
                 "peak": round(roof["peak"] / 1e12, 1), "unit": roof["unit"],
-                "frac": round(achieved / roof["peak"], 4), "traffic": None,
+                "frac": round(achieved / roof["peak"], 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_launch": flops}
 
     # CPU baseline (FP64 direct sum oracle) on a bounded sample of target rows;
