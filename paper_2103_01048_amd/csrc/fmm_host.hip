@@ -368,7 +368,7 @@ static int precompute_typed(fmm_plan *P) {
   else if (maxl >= 2) glevels.push_back(-1);
   auto gh = [&](int gl) { return gl < 0 ? 1.0 : h_of(gl); };
 
-  // kinds: 0 UT_u, 1 VS_u, 2 UT_d, 3 VS_d, 4 M2M (pool8), 5 L2L, 6 M2L.
+  // kinds: 0 UT_u, 1 VS_u, 2 UT_d, 3 VS_d, 4 M2M (per octant), 5 L2L, 6 M2L.
   // M2M, L2L and M2L act between singular coordinates of the check
   // potentials (c = U^T chk, equivalent density = V S^-1 c):
   //   M2M_c  = U_u^T(l)   K(parent upward check, child c upward equiv) V_u S_u^-1(l+1)
@@ -380,7 +380,7 @@ static int precompute_typed(fmm_plan *P) {
     for (int k = 0; k < 4; ++k) jobs.push_back({k, gl, 0, 0});
     const bool kids = gl < 0 || (gl < maxl && has_children[gl]);
     if (kids) {
-      jobs.push_back({4, gl, 0, 0});
+      for (int c = 0; c < 8; ++c) jobs.push_back({4, gl, c, 0});
       for (int c = 0; c < 8; ++c) jobs.push_back({5, gl, c, 0});
     }
     for (int code = 0; code < 343; ++code) {
@@ -424,36 +424,32 @@ static int precompute_typed(fmm_plan *P) {
   auto child_of = [&](int gl) { return gl < 0 ? gl : gl + 1; };
   std::vector<int> id1(jobs.size(), -1), id8(jobs.size(), -1);
   int64_t c1 = 0, c8 = 0;
-  for (size_t j = 0; j < jobs.size(); ++j) {
-    if (jobs[j].kind == 4) id8[j] = (int)c8++;
-    else id1[j] = (int)c1++;
-  }
+  for (size_t j = 0; j < jobs.size(); ++j) id1[j] = (int)c1++;
   const size_t m1 = (size_t)ld * ld, m8 = (size_t)ld * ld * 8;
   std::vector<T> pool1(std::max<size_t>(1, c1 * m1)), pool8(std::max<size_t>(1, c8 * m8));
   parallel_for((int64_t)jobs.size(), [&](int64_t j) {
     const Job &jb = jobs[j];
     const double h = gh(jb.l);
-    T *dst = jb.kind == 4 ? pool8.data() + id8[j] * m8 : pool1.data() + id1[j] * m1;
+    T *dst = pool1.data() + id1[j] * m1;
     switch (jb.kind) {
       case 0: swizzle<T>(ut_u[jb.l].data(), n, n, n, ld, ld, dst); break;
       case 1: swizzle<T>(vs_u[jb.l].data(), n, n, n, ld, ld, dst); break;
       case 2: swizzle<T>(ut_d[jb.l].data(), n, n, n, ld, ld, dst); break;
       case 3: swizzle<T>(vs_d[jb.l].data(), n, n, n, ld, ld, dst); break;
       case 4: {
+        // octant c: parent singular coordinates from the child's
         const int cl = child_of(jb.l);
-        const int rp = rk_u[jb.l], rc = rk_u[cl], seg = r16(rc);
+        const int rp = rk_u[jb.l], rc = rk_u[cl];
         const double cs = jb.l < 0 ? 0.5 : 1.0;  // Laplace: child V S^-1 at half the unit size
-        std::vector<double> big((size_t)rp * 8 * seg, 0.0), Km((size_t)n * n), KV((size_t)n * rc), M((size_t)rp * rc);
-        for (int c = 0; c < 8; ++c) {
-          const double off[3] = {(((c >> 2) & 1) ? 0.5 : -0.5) * h, (((c >> 1) & 1) ? 0.5 : -0.5) * h,
-                                 ((c & 1) ? 0.5 : -0.5) * h};
-          kernel_matrix(grid, n, zero, ALPHA_UC * h, off, ALPHA_UE * h * 0.5, yuk, P->kappa, Km.data(), n);
-          matmul_rect(n, n, rc, Km.data(), n, vs_u[cl].data(), n, KV.data(), rc);
-          matmul_rect(rp, n, rc, ut_u[jb.l].data(), n, KV.data(), rc, M.data(), rc);
-          for (int i = 0; i < rp; ++i)
-            for (int k = 0; k < rc; ++k) big[(size_t)i * 8 * seg + c * seg + k] = cs * M[(size_t)i * rc + k];
-        }
-        swizzle<T>(big.data(), rp, 8 * seg, 8 * seg, ld, 8 * seg, dst);
+        const int c = jb.oct;
+        std::vector<double> Km((size_t)n * n), KV((size_t)n * rc), M((size_t)rp * rc);
+        const double off[3] = {(((c >> 2) & 1) ? 0.5 : -0.5) * h, (((c >> 1) & 1) ? 0.5 : -0.5) * h,
+                               ((c & 1) ? 0.5 : -0.5) * h};
+        kernel_matrix(grid, n, zero, ALPHA_UC * h, off, ALPHA_UE * h * 0.5, yuk, P->kappa, Km.data(), n);
+        matmul_rect(n, n, rc, Km.data(), n, vs_u[cl].data(), n, KV.data(), rc);
+        matmul_rect(rp, n, rc, ut_u[jb.l].data(), n, KV.data(), rc, M.data(), rc);
+        for (double &v : M) v *= cs;
+        swizzle<T>(M.data(), rp, rc, rc, ld, ld, dst);
         break;
       }
       case 5: {
@@ -487,7 +483,7 @@ static int precompute_typed(fmm_plan *P) {
   const int L1 = maxl + 1;
   P->utu_id.assign(L1, -1); P->vsu_id.assign(L1, -1); P->utd_id.assign(L1, -1); P->vsd_id.assign(L1, -1);
   P->rank_u.assign(L1 + 1, 0); P->rank_d.assign(L1 + 1, 0);
-  P->m2m_id.assign(L1, -1);
+  P->m2m_id.assign(L1, std::vector<int>(8, -1));
   P->l2l_id.assign(L1, std::vector<int>(8, -1));
   P->m2l_id.assign(L1, std::vector<int>(343, -1));
   P->vs_alpha.assign(L1, 1); P->k_alpha.assign(L1, 1);
@@ -506,7 +502,7 @@ static int precompute_typed(fmm_plan *P) {
         case 1: P->vsu_id[l] = id1[j]; break;
         case 2: P->utd_id[l] = id1[j]; break;
         case 3: P->vsd_id[l] = id1[j]; break;
-        case 4: P->m2m_id[l] = id8[j]; break;
+        case 4: P->m2m_id[l][jb.oct] = id1[j]; break;
         case 5: P->l2l_id[l][jb.oct] = id1[j]; break;
         case 6: P->m2l_id[l][jb.code] = id1[j]; break;
       }
@@ -556,76 +552,139 @@ static int upload_lists(fmm_plan *P) {
   // leaf's check surface).  Far sources are surfaces: the remaining W-list
   // boxes (upward equivalent) and the leaf's own downward equivalent surface.
   const int64_t ns = P->nsurf;
-  std::vector<int32_t> leaves, no = {0}, wo = {0}, wi, hl, p2m, p2mo = {0};
-  std::vector<int32_t> nr_;  // near ranges, (begin, end) pairs
-  std::vector<int32_t> items;
-  struct Item { int64_t cost; int32_t slot, t0; int split; };
-  std::vector<Item> item_list;
+  std::vector<int32_t> leaves, hl, p2m, p2mo = {0};
   std::vector<char> x_direct(nb, 0);
   int64_t inter = 0, far_inter = 0;
+  // per leaf slot: merged near ranges and far surface boxes (bit 30 marks
+  // the leaf's own downward surface)
+  struct LeafSrc { std::vector<std::pair<int32_t, int32_t>> near; std::vector<int32_t> far; int64_t m; };
+  std::vector<LeafSrc> src;
   for (int64_t b = 0; b < nb; ++b) {
     if (P->nchild[b]) continue;
-    const int32_t slot = (int32_t)leaves.size();
     leaves.push_back((int32_t)b);
-    const int64_t m = P->end[b] - P->begin[b];
+    LeafSrc L;
+    L.m = P->end[b] - P->begin[b];
+    std::vector<std::pair<int32_t, int32_t>> rg;
     auto add_range = [&](int64_t a) {
-      nr_.push_back((int32_t)P->begin[a]);
-      nr_.push_back((int32_t)P->end[a]);
-      inter += m * (P->end[a] - P->begin[a]);
+      rg.push_back({(int32_t)P->begin[a], (int32_t)P->end[a]});
+      inter += L.m * (P->end[a] - P->begin[a]);
     };
-    const size_t r0 = nr_.size();
     for (int64_t k = P->loff[0][b]; k < P->loff[0][b + 1]; ++k) add_range(P->lidx[0][k]);
-    int64_t nwm = 0;
     for (int64_t k = P->loff[2][b]; k < P->loff[2][b + 1]; ++k) {
       const int64_t a = P->lidx[2][k];
       if (P->end[a] - P->begin[a] <= ns) add_range(a);
-      else { wi.push_back((int32_t)a); ++nwm; }
+      else L.far.push_back((int32_t)a);
     }
-    if (m <= ns) {
+    if (L.m <= ns) {
       x_direct[b] = 1;
       for (int64_t k = P->loff[3][b]; k < P->loff[3][b + 1]; ++k) add_range(P->lidx[3][k]);
     }
-    // sort this leaf's ranges and merge the contiguous ones (the ranges are
-    // disjoint; neighbouring boxes are often adjacent along the Morton curve)
-    {
-      std::vector<std::pair<int32_t, int32_t>> rg;
-      for (size_t k = r0; k < nr_.size(); k += 2) rg.push_back({nr_[k], nr_[k + 1]});
-      std::sort(rg.begin(), rg.end());
-      nr_.resize(r0);
-      for (auto &x : rg) {
-        if (nr_.size() > r0 && nr_.back() == x.first) nr_.back() = x.second;
-        else { nr_.push_back(x.first); nr_.push_back(x.second); }
-      }
+    if (P->level[b] >= 2) L.far.push_back((int32_t)b | (1 << 30));
+    // sort and merge contiguous ranges (disjoint; neighbouring boxes are
+    // often adjacent along the Morton curve)
+    std::sort(rg.begin(), rg.end());
+    for (auto &x : rg) {
+      if (!L.near.empty() && L.near.back().second == x.first) L.near.back().second = x.second;
+      else L.near.push_back(x);
     }
-    const int64_t near_pts = [&]() { int64_t t = 0; for (size_t k = r0; k < nr_.size(); k += 2) t += nr_[k + 1] - nr_[k]; return t; }();
-    no.push_back((int32_t)(nr_.size() / 2));
-    wo.push_back((int32_t)wi.size());
+    far_inter += L.m * ns * (int64_t)L.far.size();
     hl.push_back(P->level[b] >= 2 ? 1 : 0);
-    far_inter += m * ns * (nwm + (P->level[b] >= 2 ? 1 : 0));
     if (P->level[b] >= 2) { p2m.push_back((int32_t)b); p2mo.push_back((int32_t)p2m.size()); }
-    // tiles of 64 targets; a tile of at most 32 targets runs in split mode
-    // (both half-waves take the same targets and alternate sources)
-    const int64_t cost = near_pts + ns * (nwm + (P->level[b] >= 2 ? 1 : 0));
-    for (int64_t t0 = 0; t0 < m; t0 += 64) {
-      const int split = (m - t0) <= 32 ? 2 : 1;
-      item_list.push_back({cost / split, slot, (int32_t)t0, split});
+    src.push_back(std::move(L));
+  }
+  // Tiles of 64 targets (a tile of at most 32 targets runs split: both
+  // half-waves take the same targets and alternate sources).  A tile whose
+  // source work exceeds `cap` is cut into parts of about `cap` (near ranges
+  // cut at point boundaries, surfaces whole); parts write partial sums that
+  // k_leaf_parts adds in part order.  With the waves of one launch resident
+  // at once, capping the work per wave is what balances the SIMDs.
+  const double far_w = 1.15;  // a surface source also computes its position
+  struct Tile { double cost; int32_t slot, t0, split; };
+  std::vector<Tile> tiles;
+  double total = 0;
+  for (size_t sl = 0; sl < src.size(); ++sl) {
+    double c = 0;
+    for (auto &r : src[sl].near) c += r.second - r.first;
+    c += far_w * ns * (double)src[sl].far.size();
+    for (int64_t t0 = 0; t0 < src[sl].m; t0 += 64) {
+      const int split = (src[sl].m - t0) <= 32 ? 2 : 1;
+      tiles.push_back({c / split, (int32_t)sl, (int32_t)t0, split});
+      total += c / split;
     }
   }
-  // longest tiles first, so that the last wave of work is made of short tiles
-  std::stable_sort(item_list.begin(), item_list.end(),
-                   [](const Item &x, const Item &y) { return x.cost > y.cost; });
-  for (const Item &it : item_list) { items.push_back(it.slot); items.push_back(it.t0 | (it.split << 24)); }
+  const double cap = std::max(512.0, total / 16384.0);
+  struct Item { double cost; int32_t slot, code, part; std::vector<std::pair<int32_t, int32_t>> near; std::vector<int32_t> far; };
+  std::vector<Item> items;
+  std::vector<int32_t> split_tiles;  // (slot, code, first part, nparts)
+  int32_t nparts_total = 0;
+  for (const Tile &t : tiles) {
+    const LeafSrc &L = src[t.slot];
+    const int32_t code = t.t0 | (t.split << 24);
+    const int nparts = (int)std::ceil(t.cost / cap - 1e-9);
+    if (nparts <= 1) {
+      items.push_back({t.cost, t.slot, code, -1, L.near, L.far});
+      continue;
+    }
+    const double per = t.cost * t.split / nparts;  // unsplit-source units per part
+    split_tiles.push_back(t.slot); split_tiles.push_back(code);
+    split_tiles.push_back(nparts_total);
+    int made = 0;
+    Item cur{0, t.slot, code, nparts_total, {}, {}};
+    double acc = 0;
+    auto flush = [&]() {
+      cur.cost = acc / t.split;
+      cur.part = nparts_total++;
+      items.push_back(cur);
+      ++made;
+      cur = Item{0, t.slot, code, 0, {}, {}};
+      acc = 0;
+    };
+    for (auto r : L.near) {
+      int32_t j = r.first;
+      while (j < r.second) {
+        const int32_t take = (int32_t)std::max<double>(1.0, std::min<double>(r.second - j, per - acc));
+        cur.near.push_back({j, j + take});
+        acc += take;
+        j += take;
+        if (acc >= per - 0.5 && made < nparts - 1) flush();
+      }
+    }
+    for (int32_t f : L.far) {
+      cur.far.push_back(f);
+      acc += far_w * ns;
+      if (acc >= per - 0.5 && made < nparts - 1) flush();
+    }
+    if (!cur.near.empty() || !cur.far.empty() || made == 0) flush();
+    split_tiles.push_back(made);
+  }
+  // longest items first
+  std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+  std::vector<int32_t> it4, no = {0}, nrng, fo = {0}, far;
+  for (const Item &it : items) {
+    it4.push_back(it.slot); it4.push_back(it.code); it4.push_back(it.part); it4.push_back(0);
+    for (auto &r : it.near) { nrng.push_back(r.first); nrng.push_back(r.second); }
+    no.push_back((int32_t)(nrng.size() / 2));
+    far.insert(far.end(), it.far.begin(), it.far.end());
+    fo.push_back((int32_t)far.size());
+  }
   P->leaf_ids = leaves;
   P->p2p_inter = inter;
   P->far_inter = far_inter;
   D.nleaf = (int)leaves.size();
-  D.nitems = (int)(items.size() / 2);
+  D.nitems = (int)items.size();
+  D.nsplit = (int)(split_tiles.size() / 4);
+  D.nparts = nparts_total;
   if ((rc = upload(P, (void **)&D.leaves, leaves))) return rc;
-  if ((rc = upload(P, (void **)&D.items, items))) return rc;
+  if ((rc = upload(P, (void **)&D.items, it4))) return rc;
   if ((rc = upload(P, (void **)&D.near_off, no))) return rc;
-  if ((rc = upload(P, (void **)&D.near_rng, nr_))) return rc;
-  if ((rc = upload(P, (void **)&D.w_off, wo))) return rc;
-  if ((rc = upload(P, (void **)&D.w_idx, wi))) return rc;
+  if ((rc = upload(P, (void **)&D.near_rng, nrng))) return rc;
+  if ((rc = upload(P, (void **)&D.far_off, fo))) return rc;
+  if ((rc = upload(P, (void **)&D.far_idx, far))) return rc;
+  if ((rc = upload(P, (void **)&D.split_tiles, split_tiles))) return rc;
+  {
+    const size_t es = P->precision == FMM_FP64 ? 8 : 4;
+    if ((rc = dev_alloc(P, &D.parts, std::max<size_t>(1, (size_t)nparts_total) * MAX_NR * 4 * 64 * es))) return rc;
+  }
   if ((rc = upload(P, (void **)&P->d_has_local, hl))) return rc;
   P->p2m_count = (int)p2m.size();
   if ((rc = upload(P, (void **)&P->d_p2m_box, p2m))) return rc;
@@ -674,6 +733,24 @@ static int upload_lists(fmm_plan *P) {
     vt.push_back((int32_t)b);
     vpp.insert(vpp.end(), per_tgt[b].begin(), per_tgt[b].end());
     vo.push_back((int32_t)vpp.size());
+  }
+  // M2M sums: per level, the non-leaf boxes and their children (octant order)
+  D.m2m_tgt.assign(D.maxlevel + 1, nullptr);
+  D.m2m_off.assign(D.maxlevel + 1, nullptr);
+  D.m2m_kid.assign(D.maxlevel + 1, nullptr);
+  D.m2m_n.assign(D.maxlevel + 1, 0);
+  for (int l = 2; l < D.maxlevel; ++l) {
+    std::vector<int32_t> tg, of = {0}, kd;
+    for (int64_t b = P->level_begin[l]; b < P->level_begin[l + 1]; ++b) {
+      if (!P->nchild[b]) continue;
+      tg.push_back((int32_t)b);
+      for (int k = 0; k < P->nchild[b]; ++k) kd.push_back((int32_t)(P->child_begin[b] + k));
+      of.push_back((int32_t)kd.size());
+    }
+    D.m2m_n[l] = (int)tg.size();
+    if ((rc = upload(P, (void **)&D.m2m_tgt[l], tg))) return rc;
+    if ((rc = upload(P, (void **)&D.m2m_off[l], of))) return rc;
+    if ((rc = upload(P, (void **)&D.m2m_kid[l], kd))) return rc;
   }
   D.nvbox = (int)vt.size();
   D.nvpair = (int64_t)vp.size();
@@ -744,8 +821,9 @@ int ensure_lists(fmm_plan *P, int nr) {
   int maxru = 16, maxrd = 16;
   for (int l = 2; l <= maxl; ++l) { maxru = std::max(maxru, r16(P->rank_u[l])); maxrd = std::max(maxrd, r16(P->rank_d[l])); }
   const int L1 = std::max(maxl + 1, 0);
-  L.m2m.assign(L1, GemmBatch()); L.ut_u.assign(L1, GemmBatch()); L.l2l.assign(L1, GemmBatch());
-  L.vs_u = GemmBatch(); L.ut_dx = GemmBatch(); L.vs_d = GemmBatch(); L.m2l = GemmBatch();
+  L.m2m.assign(L1, GemmBatch()); L.l2l.assign(L1, GemmBatch());
+  L.ut_u_all = GemmBatch(); L.vs_u = GemmBatch(); L.ut_dx = GemmBatch(); L.vs_d = GemmBatch(); L.m2l = GemmBatch();
+  L.ut_u_all.nrb = maxru / 16; L.ut_u_all.klen = ld;
   L.vs_u.nrb = ld / 16; L.vs_u.klen = maxru;
   L.ut_dx.nrb = maxrd / 16; L.ut_dx.klen = ld; L.ut_dx.mode = GEMM_ADD;
   L.vs_d.nrb = ld / 16; L.vs_d.klen = maxrd;
@@ -765,35 +843,26 @@ int ensure_lists(fmm_plan *P, int nr) {
       all.push_back(b);
       if (!P->nchild[b]) leaves.push_back(b);
     }
-    // upward: M2M from the children's singular coordinates (non-leaf boxes)
+    // upward: M2M slots, one per child box at level l + 1 (grouped by
+    // octant), summed per parent by k_pair_reduce
     if (l < maxl) {
       GemmBatch &bt = L.m2m[l];
-      bt.S = 8;
-      bt.pool = 1;
-      bt.seg = r16(P->rank_u[l + 1]);
-      bt.kq_stride = 8 * bt.seg / 16;
       bt.nrb = r16(P->rank_u[l]) / 16;
-      bt.klen = 8 * bt.seg;
-      src.clear(); dst.clear();
-      for (int64_t b : all) {
-        if (!P->nchild[b]) continue;
-        int64_t ch[8];
-        for (int c = 0; c < 8; ++c) ch[c] = -1;
-        for (int k = 0; k < P->nchild[b]; ++k) ch[oct_of(P->child_begin[b] + k)] = P->child_begin[b] + k;
-        for (int r = 0; r < nr; ++r) {
-          for (int c = 0; c < 8; ++c) src.push_back(ch[c] < 0 ? -1 : (int32_t)(ch[c] * nr + r));
-          dst.push_back((int32_t)(b * nr + r));
-        }
+      bt.klen = r16(P->rank_u[l + 1]);
+      for (int oct = 0; oct < 8; ++oct) {
+        std::vector<int64_t> kids;
+        for (int64_t b = P->level_begin[l + 1]; b < P->level_begin[l + 2]; ++b)
+          if (oct_of(b) == oct) kids.push_back(b);
+        if (kids.empty()) continue;
+        cols_for(kids, kids);
+        add_columns(bt, P->m2m_id[l][oct], 1.0, src, dst);
       }
-      if (!dst.empty()) add_columns(bt, P->m2m_id[l], 1.0, src, dst);
       if ((rc = finish_batch(P, bt))) return rc;
     }
-    // upward: leaves' check potentials to singular coordinates
+    // upward: leaves' check potentials to singular coordinates (one batch
+    // for every level, launched before the M2M sweep)
     cols_for(leaves, leaves);
-    L.ut_u[l].nrb = r16(P->rank_u[l]) / 16;
-    L.ut_u[l].klen = ld;
-    if (!dst.empty()) add_columns(L.ut_u[l], P->utu_id[l], 1.0, src, dst);
-    if ((rc = finish_batch(P, L.ut_u[l]))) return rc;
+    if (!dst.empty()) add_columns(L.ut_u_all, P->utu_id[l], 1.0, src, dst);
     // upward equivalent densities of the M2P sources
     std::vector<int64_t> eb;
     for (int64_t b : all) if (need_equ[b]) eb.push_back(b);
@@ -837,6 +906,7 @@ int ensure_lists(fmm_plan *P, int nr) {
       i = j;
     }
   }
+  if ((rc = finish_batch(P, L.ut_u_all))) return rc;
   if ((rc = finish_batch(P, L.vs_u))) return rc;
   if ((rc = finish_batch(P, L.ut_dx))) return rc;
   if ((rc = finish_batch(P, L.vs_d))) return rc;
@@ -884,6 +954,7 @@ int ensure_work(fmm_plan *P, int nr) {
   if ((rc = dev_alloc(P, &P->chku, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->cu, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->yd, wbytes))) return rc;
+  if ((rc = dev_alloc(P, &P->mslot, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->pairbuf, (size_t)std::max<int64_t>(1, P->dt.nvpair) * nr * P->ld * es))) return rc;
   // padding rows/columns must hold zeros (the GEMM K dimension reads them)
   FMM_HIP_TRY(hipMemset(P->equ, 0, wbytes));

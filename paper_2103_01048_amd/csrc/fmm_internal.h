@@ -71,8 +71,8 @@ struct GemmBatch {
 struct PassLists {
   int nr = 0;
   // per level l (index l, levels >= 2), in singular coordinates c = U^T chk
-  std::vector<GemmBatch> m2m;   // parent c_u from the 8 children's c_u
-  std::vector<GemmBatch> ut_u;  // leaf upward check -> c_u
+  std::vector<GemmBatch> m2m;   // per-child M2M slots of the parents at level l
+  GemmBatch ut_u_all;           // leaf upward check -> c_u, all levels
   std::vector<GemmBatch> l2l;   // child c_d += L2L * parent c_d (levels >= 3)
   GemmBatch vs_u;               // c_u -> upward equivalent (M2P sources), all levels
   GemmBatch ut_dx;              // P2L check -> c_d (added), all levels
@@ -90,11 +90,16 @@ struct DevTree {
   void *box_geom = nullptr;     // T4: centre xyz (shifted), half width
   int32_t *box_begin = nullptr, *box_end = nullptr;
   int32_t *leaves = nullptr;    // leaf box ids
-  int32_t *items = nullptr;     // (leaf slot, first target) per 64-target tile
+  // leaf work items: (leaf slot, first target | split << 24, part or -1, 0)
+  int32_t *items = nullptr;
   int nitems = 0;
-  int32_t *near_off = nullptr;  // per leaf slot, into near_rng
+  int32_t *near_off = nullptr;  // per item, into near_rng
   int32_t *near_rng = nullptr;  // (begin, end) point ranges of near sources
-  int32_t *w_off = nullptr, *w_idx = nullptr;   // per leaf slot: M2P boxes
+  int32_t *far_off = nullptr;   // per item, into far_idx
+  int32_t *far_idx = nullptr;   // surface boxes (bit 30: own downward surface)
+  int32_t *split_tiles = nullptr;  // (slot, code, first part, nparts) per split tile
+  int nsplit = 0, nparts = 0;
+  void *parts = nullptr;        // partial sums of split tiles
   int32_t *x_box = nullptr;     // boxes with a non-empty X list
   int32_t *x_off = nullptr, *x_idx = nullptr;
   int nxbox = 0;
@@ -103,6 +108,9 @@ struct DevTree {
   int32_t *v_pair = nullptr;
   int nvbox = 0;
   int64_t nvpair = 0;
+  // per level: non-leaf boxes, CSR of their children (for the M2M sums)
+  std::vector<int32_t *> m2m_tgt, m2m_off, m2m_kid;
+  std::vector<int> m2m_n;
 };
 
 }  // namespace fmm
@@ -134,14 +142,14 @@ struct fmm_plan {
   // matrix ids (pool1 unless noted) per level; -1 when absent
   std::vector<int> utu_id, vsu_id, utd_id, vsd_id;  // truncated-SVD factors
   std::vector<int> rank_u, rank_d;                  // their ranks
-  std::vector<int> m2m_id;                          // pool8
+  std::vector<std::vector<int>> m2m_id;             // [parent level][octant]
   std::vector<std::vector<int>> l2l_id;             // [parent level][octant]
   std::vector<std::vector<int>> m2l_id;             // [level][343 offset code]
   std::vector<double> vs_alpha, k_alpha;            // Laplace level scaling
   // work arrays, sized for work_nr columns
   int work_nr = 0;
   void *qs = nullptr, *equ = nullptr, *chk = nullptr, *eqd = nullptr, *chku = nullptr,
-       *cu = nullptr, *yd = nullptr, *pairbuf = nullptr;
+       *cu = nullptr, *yd = nullptr, *pairbuf = nullptr, *mslot = nullptr;
   // cu: upward check in singular coordinates (U_u^T chk); yd: downward
   // check in singular coordinates (M2L sums + U_d^T chk)
   fmm::PassLists lists_by_nr[fmm::MAX_NR + 1];  // task lists per column count

@@ -331,7 +331,8 @@ __device__ inline void pair_gf(T r2, T kappa, T &g, T &f) {
 // travels in the fourth component of the point record.  Only a range that
 // contains the tile's own leaf can hold a source at zero distance, so only
 // that range pays for the exclusion test (points in different leaves have
-// different Morton cells; surfaces never touch the targets they serve).
+// different Morton cells; surfaces never touch the targets they serve),
+// and a range counts as holding it when it overlaps the leaf's points.
 // Writes potential (and gradient) times `scale` in the caller's order.
 template <typename T, int KERN, bool CHECK, int NR>
 __device__ __forceinline__ void leaf_pair(T xi, T yi, T zi, T sx, T sy, T sz, const T (&qv)[NR], T kappa, T kl2,
@@ -364,14 +365,16 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
     const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts,
     const T *__restrict__ qs, int64_t N, const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end,
     const T *__restrict__ box_geom, const T *__restrict__ surf, int nsurf, int ld, const int32_t *__restrict__ near_off,
-    const int32_t *__restrict__ near_rng, const int32_t *__restrict__ w_off, const int32_t *__restrict__ w_idx,
-    const T *__restrict__ equ, const T *__restrict__ eqd, const int32_t *__restrict__ has_local,
-    const int32_t *__restrict__ perm, T *__restrict__ pot, T *__restrict__ grad, T kappa, T scale) {
+    const int32_t *__restrict__ near_rng, const int32_t *__restrict__ far_off, const int32_t *__restrict__ far_idx,
+    const T *__restrict__ equ, const T *__restrict__ eqd, T *__restrict__ parts, const int32_t *__restrict__ perm,
+    T *__restrict__ pot, T *__restrict__ grad, T kappa, T scale) {
   using V4 = typename Vec4<T>::type;
   const V4 *__restrict__ p4 = reinterpret_cast<const V4 *>(pts);
   const V4 *__restrict__ s4 = reinterpret_cast<const V4 *>(surf);
-  const int slot = items[2 * blockIdx.x];
-  const int code = items[2 * blockIdx.x + 1];
+  const int item = blockIdx.x;
+  const int slot = items[4 * item];
+  const int code = items[4 * item + 1];
+  const int part = items[4 * item + 2];
   const int split = code >> 24;
   const int b = leaves[slot];
   const int lb = box_begin[b], le = box_end[b];
@@ -389,10 +392,10 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
   for (int c = 0; c < NR; ++c) ap[c] = agx[c] = agy[c] = agz[c] = (T)0;
 
   // near field: point ranges
-  const int u1 = near_off[slot + 1];
-  for (int u = near_off[slot]; u < u1; ++u) {
+  const int u1 = near_off[item + 1];
+  for (int u = near_off[item]; u < u1; ++u) {
     const int j0 = near_rng[2 * u], j1 = near_rng[2 * u + 1];
-    const bool self = j0 <= lb && le <= j1;
+    const bool self = j0 < le && lb < j1;  // overlaps the tile's own leaf
     if (split == 1) {
       auto body = [&](int j, auto chk) {
         const V4 sp = p4[j];
@@ -435,12 +438,12 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
       }
     }
   }
-  // far field: W-list equivalent surfaces, then the own downward surface
-  const int w0 = w_off[slot], w1 = w_off[slot + 1];
-  const int nfar = w1 - w0 + (has_local[slot] ? 1 : 0);
-  for (int k = 0; k < nfar; ++k) {
-    const bool own = (w0 + k) >= w1;
-    const int a = own ? b : w_idx[w0 + k];
+  // far field: W-list upward equivalent surfaces and the own downward one
+  const int f1 = far_off[item + 1];
+  for (int k = far_off[item]; k < f1; ++k) {
+    const int fe = far_idx[k];
+    const bool own = (fe >> 30) & 1;
+    const int a = fe & 0x3fffffff;
     const T cx = box_geom[a * 4 + 0], cy = box_geom[a * 4 + 1], cz = box_geom[a * 4 + 2];
     const T rr = box_geom[a * 4 + 3] * (own ? (T)ALPHA_DE : (T)ALPHA_UE);
     const T *__restrict__ dens = (own ? eqd : equ) + (int64_t)a * NR * ld;
@@ -477,6 +480,20 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
       agz[c] += __shfl_xor(agz[c], 32);
     }
   }
+  if (part >= 0) {
+    // partial sums of a split tile: [part][column][component][lane]
+    if (half == 0) {
+      T *pp = parts + (int64_t)part * NR * 4 * 64;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        pp[(c * 4 + 0) * 64 + tl] = ap[c];
+        pp[(c * 4 + 1) * 64 + tl] = agx[c];
+        pp[(c * 4 + 2) * 64 + tl] = agy[c];
+        pp[(c * 4 + 3) * 64 + tl] = agz[c];
+      }
+    }
+    return;
+  }
   if (active && half == 0) {
     const int64_t o = perm[tb + tl];
 #pragma unroll
@@ -488,6 +505,40 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
         gp[1] = agy[c] * scale;
         gp[2] = agz[c] * scale;
       }
+    }
+  }
+}
+
+// Sum of the parts of split tiles, in part order; one wave per tile.
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_leaf_parts(const int32_t *__restrict__ tiles, const int32_t *__restrict__ leaves,
+                                                   const int32_t *__restrict__ box_begin,
+                                                   const int32_t *__restrict__ box_end, const T *__restrict__ parts,
+                                                   const int32_t *__restrict__ perm, int64_t N, T *__restrict__ pot,
+                                                   T *__restrict__ grad, T scale) {
+  const int slot = tiles[4 * blockIdx.x], code = tiles[4 * blockIdx.x + 1];
+  const int p0 = tiles[4 * blockIdx.x + 2], np = tiles[4 * blockIdx.x + 3];
+  const int split = code >> 24;
+  const int b = leaves[slot];
+  const int tb = box_begin[b] + (code & 0xffffff);
+  const int m = min(64 / split, box_end[b] - tb);
+  const int lane = threadIdx.x;
+  if (lane >= m) return;
+  const int64_t o = perm[tb + lane];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    T acc[4] = {0, 0, 0, 0};
+    for (int k = 0; k < np; ++k) {
+      const T *pp = parts + (int64_t)(p0 + k) * NR * 4 * 64;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] += pp[(c * 4 + e) * 64 + lane];
+    }
+    pot[(int64_t)c * N + o] = acc[0] * scale;
+    if (grad) {
+      T *gp = grad + ((int64_t)c * N + o) * 3;
+      gp[0] = acc[1] * scale;
+      gp[1] = acc[2] * scale;
+      gp[2] = acc[3] * scale;
     }
   }
 }
@@ -666,18 +717,19 @@ static int eval_chunk(fmm_plan *P, const T *q, T *pot, T *grad, hipStream_t s) {
                          (const T *)D.box_geom, (const T *)P->surf, P->nsurf, ld, (T)ALPHA_UC, chku, 0, kappa);
     FMM_HIP_TRY(hipGetLastError());
     prof_end(P, FMM_PHASE_P2M, ev, s);
-    // upward pass in singular coordinates, deepest level first
-    for (int l = D.maxlevel; l >= 2; --l) {
-      if (l < (int)L.m2m.size() && L.m2m[l].ntask) {
-        ev = prof_begin(P, FMM_PHASE_M2M, s);
-        if ((rc = launch_gemm<T>(P, L.m2m[l], cu, cu, s))) return rc;
-        prof_end(P, FMM_PHASE_M2M, ev, s);
-      }
-      if (L.ut_u[l].ntask) {
-        ev = prof_begin(P, FMM_PHASE_UC2E, s);
-        if ((rc = launch_gemm<T>(P, L.ut_u[l], chku, cu, s))) return rc;
-        prof_end(P, FMM_PHASE_UC2E, ev, s);
-      }
+    // upward pass in singular coordinates: every leaf's U^T projection,
+    // then M2M slots and per-parent sums, deepest level first
+    ev = prof_begin(P, FMM_PHASE_UC2E, s);
+    if ((rc = launch_gemm<T>(P, L.ut_u_all, chku, cu, s))) return rc;
+    prof_end(P, FMM_PHASE_UC2E, ev, s);
+    for (int l = D.maxlevel - 1; l >= 2; --l) {
+      if (!L.m2m[l].ntask) continue;
+      ev = prof_begin(P, FMM_PHASE_M2M, s);
+      if ((rc = launch_gemm<T>(P, L.m2m[l], cu, (T *)P->mslot, s))) return rc;
+      hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.m2m_n[l]), dim3(64), 0, s, D.m2m_tgt[l], D.m2m_off[l], D.m2m_kid[l],
+                         (const T *)P->mslot, cu, NR, ld, L.m2m[l].nrb * 16);
+      FMM_HIP_TRY(hipGetLastError());
+      prof_end(P, FMM_PHASE_M2M, ev, s);
     }
     ev = prof_begin(P, FMM_PHASE_UC2E, s);
     if ((rc = launch_gemm<T>(P, L.vs_u, cu, equ, s))) return rc;
@@ -721,8 +773,11 @@ static int eval_chunk(fmm_plan *P, const T *q, T *pot, T *grad, hipStream_t s) {
   if (D.nitems > 0)
     hipLaunchKernelGGL((k_leaf_eval<T, NR, KERN>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
                        (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)P->surf,
-                       P->nsurf, ld, D.near_off, D.near_rng, D.w_off, D.w_idx, equ, eqd, P->d_has_local, D.perm, pot,
-                       grad, kappa, scale);
+                       P->nsurf, ld, D.near_off, D.near_rng, D.far_off, D.far_idx, equ, eqd, (T *)D.parts, D.perm,
+                       pot, grad, kappa, scale);
+  if (D.nsplit > 0)
+    hipLaunchKernelGGL((k_leaf_parts<T, NR>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
+                       D.box_end, (const T *)D.parts, D.perm, N, pot, grad, scale);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(P, FMM_PHASE_LEAF, ev, s);
   return FMM_OK;
