@@ -338,12 +338,47 @@ static void swizzle(const double *A, int rows, int cols, int lda, int ld_rows, i
 
 static int m2l_code(int ox, int oy, int oz) { return (ox + 3) * 49 + (oy + 3) * 7 + (oz + 3); }
 
+static inline uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static inline float bf16_to_f(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Split a row-major matrix (rows x cols) into bf16 high and low parts in the
+// fragment order of k_gemm_bf3: for row block rb and 32-wide k block kb, 64
+// lanes x 8 values of the high part, then 64 x 8 of the low part; lane l
+// holds row rb*16 + l%16, k = kb*32 + 8*(l/16) .. +7.
+static void swizzle_bf3(const double *A, int rows, int cols, int lda, int ld_rows, int KB, uint16_t *out) {
+  for (int rb = 0; rb < ld_rows / 16; ++rb)
+    for (int kb = 0; kb < KB; ++kb)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int e = 0; e < 8; ++e) {
+          const int i = rb * 16 + (lane & 15), k = kb * 32 + 8 * (lane >> 4) + e;
+          const double v = (i < rows && k < cols) ? A[(size_t)i * lda + k] : 0.0;
+          const uint16_t h = bf16_rne((float)v);
+          const uint16_t l = bf16_rne((float)(v - (double)bf16_to_f(h)));
+          const size_t base = ((size_t)(rb * KB + kb) * 2) * 64 * 8;
+          out[base + lane * 8 + e] = h;
+          out[base + 64 * 8 + lane * 8 + e] = l;
+        }
+}
+
 template <typename T>
 static int precompute_typed(fmm_plan *P) {
   const int p = P->p, n = P->nsurf, ld = P->ld;
   const int yuk = P->kernel == FMM_YUKAWA;
   const int maxl = (int)P->level_begin.size() - 2;
-  const double tau = P->precision == FMM_FP64 ? 1e-11 : 1e-7;
+  // singular values kept above tau * s_max: FP64 1e-11; single precision
+  // 1e-6 (components below that are at the FP32 rounding level of the data
+  // that flows through them)
+  const double tau = P->precision == FMM_FP64 ? 1e-11 : 1e-6;
   const std::vector<double> grid = surface_grid(p);
   const double zero[3] = {0, 0, 0};
   auto h_of = [&](int l) { return P->W / (double)(1ll << (l + 1)); };
@@ -427,6 +462,16 @@ static int precompute_typed(fmm_plan *P) {
   for (size_t j = 0; j < jobs.size(); ++j) id1[j] = (int)c1++;
   const size_t m1 = (size_t)ld * ld, m8 = (size_t)ld * ld * 8;
   std::vector<T> pool1(std::max<size_t>(1, c1 * m1)), pool8(std::max<size_t>(1, c8 * m8));
+  // bf16x3 mode: the M2L operators also in split bf16 form (K padded to 32)
+  const bool bf3 = P->precision == FMM_FP32_BF16X3;
+  const int KB = (ld + 31) / 32;
+  const size_t mbf = (size_t)(ld / 16) * KB * 2 * 64 * 8;
+  std::vector<int> idbf(jobs.size(), -1);
+  int64_t cbf = 0;
+  if (bf3)
+    for (size_t j = 0; j < jobs.size(); ++j)
+      if (jobs[j].kind == 6) idbf[j] = (int)cbf++;
+  std::vector<uint16_t> poolbf(std::max<size_t>(1, cbf * mbf));
   parallel_for((int64_t)jobs.size(), [&](int64_t j) {
     const Job &jb = jobs[j];
     const double h = gh(jb.l);
@@ -474,6 +519,7 @@ static int precompute_typed(fmm_plan *P) {
         matmul_rect(n, n, ru, Km.data(), n, vs_u[jb.l].data(), n, KV.data(), ru);
         matmul_rect(rd, n, ru, ut_d[jb.l].data(), n, KV.data(), ru, M.data(), ru);
         swizzle<T>(M.data(), rd, ru, ru, ld, ld, dst);
+        if (idbf[j] >= 0) swizzle_bf3(M.data(), rd, ru, ru, ld, KB, poolbf.data() + idbf[j] * mbf);
       }
     }
   });
@@ -504,7 +550,7 @@ static int precompute_typed(fmm_plan *P) {
         case 3: P->vsd_id[l] = id1[j]; break;
         case 4: P->m2m_id[l][jb.oct] = id1[j]; break;
         case 5: P->l2l_id[l][jb.oct] = id1[j]; break;
-        case 6: P->m2l_id[l][jb.code] = id1[j]; break;
+        case 6: P->m2l_id[l][jb.code] = bf3 ? idbf[j] : id1[j]; break;
       }
     }
   }
@@ -513,6 +559,9 @@ static int precompute_typed(fmm_plan *P) {
   int rc;
   if ((rc = upload(P, &P->pool1, pool1))) return rc;
   if ((rc = upload(P, &P->pool8, pool8))) return rc;
+  P->bf_kb = KB;
+  P->poolbf_count = cbf;
+  if (bf3 && (rc = upload(P, &P->pool_bf, poolbf))) return rc;
   // surface grid table (T4)
   std::vector<T> sg((size_t)n * 4);
   for (int i = 0; i < n; ++i) {
@@ -779,7 +828,7 @@ static void add_columns(GemmBatch &bt, int mat, double alpha, const std::vector<
 }
 
 static int finish_batch(fmm_plan *P, GemmBatch &bt) {
-  const int64_t nmat = bt.pool == 0 ? P->pool1_count : P->pool8_count;
+  const int64_t nmat = bt.pool == 0 ? P->pool1_count : (bt.pool == 1 ? P->pool8_count : P->poolbf_count);
   for (const GemmTask &t : bt.h_tasks)
     if (t.mat < 0 || t.mat >= nmat) {
       set_error("internal: GEMM task references a missing operator");
@@ -828,6 +877,10 @@ int ensure_lists(fmm_plan *P, int nr) {
   L.ut_dx.nrb = maxrd / 16; L.ut_dx.klen = ld; L.ut_dx.mode = GEMM_ADD;
   L.vs_d.nrb = ld / 16; L.vs_d.klen = maxrd;
   L.m2l.nrb = maxrd / 16; L.m2l.klen = maxru;
+  if (P->precision == FMM_FP32_BF16X3) {
+    L.m2l.pool = 2;
+    L.m2l.klen = std::min(((maxru + 31) / 32) * 32, P->bf_kb * 32);
+  }
   // boxes whose upward equivalent density is evaluated (M2P sources)
   std::vector<char> need_equ(nb, 0);
   for (int64_t b = 0; b < nb; ++b) {

@@ -55,7 +55,7 @@ struct GemmBatch {
   int seg = 0;                 // K length of one segment (0: the work-array row length)
   int kq_stride = 0;           // 16-wide k groups per stored row block (0: row length / 16)
   int mode = GEMM_STORE;
-  int pool = 0;                // 0: single-segment matrix pool, 1: M2M pool
+  int pool = 0;                // 0: matrix pool, 1: stacked pool, 2: bf16x3 split pool
   int ntask = 0;
   GemmTask *d_tasks = nullptr;
   int32_t *d_src = nullptr;    // ncols*S  (row index into X, already * nr + r)
@@ -138,7 +138,9 @@ struct fmm_plan {
   void *surf = nullptr;            // T4 grid offsets in [-1,1]^3, nsurf entries
   void *pool1 = nullptr;           // swizzled ld x ld matrices
   void *pool8 = nullptr;           // swizzled ld x 8ld matrices (M2M)
-  int64_t pool1_count = 0, pool8_count = 0;
+  int64_t pool1_count = 0, pool8_count = 0, poolbf_count = 0;
+  void *pool_bf = nullptr;         // bf16x3 mode: split M2L operators
+  int bf_kb = 0;                   // 32-wide k blocks per row block in pool_bf
   // matrix ids (pool1 unless noted) per level; -1 when absent
   std::vector<int> utu_id, vsu_id, utd_id, vsd_id;  // truncated-SVD factors
   std::vector<int> rank_u, rank_d;                  // their ranks

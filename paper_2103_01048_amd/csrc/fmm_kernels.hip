@@ -302,6 +302,124 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask *__restrict__ tasks
 }
 
 // ---------------------------------------------------------------------------
+// The same gather-GEMM with each FP32 operand split into bf16 high and low
+// parts (x = hi + lo, hi = bf16(x), lo = bf16(x - hi)) and three
+// 16x16x32 bf16 MFMAs per 32-wide k step (hi*hi + hi*lo + lo*hi), FP32
+// accumulation.  A is pre-split and swizzled (per 16-row block and 32-wide k
+// block, 64 lanes x 8 bf16 for hi, then for lo); B is split while it is
+// staged to LDS, stored column-major so that each lane reads its 8
+// consecutive k values with one 16-byte LDS load.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline unsigned short f2bf_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+template <int RBW>
+__global__ __launch_bounds__(256) void k_gemm_bf3(const GemmTask *__restrict__ tasks, const uint4 *__restrict__ pool,
+                                                  int64_t mat_stride16, int KB, int ld, int nrb, int K,
+                                                  const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
+                                                  const float *__restrict__ X, float *__restrict__ Y, int mode) {
+  const GemmTask tk = tasks[blockIdx.x];
+  const uint4 *__restrict__ A = pool + (int64_t)tk.mat * mat_stride16;
+  __shared__ unsigned short Bh[GEMM_NT][64 + 8], Bl[GEMM_NT][64 + 8];
+  __shared__ int32_t s_src[GEMM_NT];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = (int)blockIdx.y * 4 + (tid >> 6);
+  if (tid < GEMM_NT) s_src[tid] = tid < tk.ncol ? src[tk.col0 + tid] : -1;
+  floatx4 acc[RBW][4];
+#pragma unroll
+  for (int r = 0; r < RBW; ++r)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[r][cb] = floatx4{0, 0, 0, 0};
+  __syncthreads();
+  const int scol = tid >> 2, spart = (tid & 3) * 16;
+  for (int kc = 0; kc < K; kc += 64) {
+    {
+      const int k0 = kc + spart;
+      const int row = s_src[scol];
+      float vals[16];
+      if (row >= 0 && k0 < K && k0 < ld) {  // k beyond the row (padding to 32) reads as zero
+        const floatx4 *p = reinterpret_cast<const floatx4 *>(X + (int64_t)row * ld + k0);
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          floatx4 v = p[q4];
+          vals[q4 * 4 + 0] = v[0]; vals[q4 * 4 + 1] = v[1]; vals[q4 * 4 + 2] = v[2]; vals[q4 * 4 + 3] = v[3];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) vals[e] = 0.f;
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const unsigned short h = f2bf_rne(vals[e]);
+        Bh[scol][spart + e] = h;
+        Bl[scol][spart + e] = f2bf_rne(vals[e] - bf2f(h));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kb2 = 0; kb2 < 2; ++kb2) {
+      const int gkb = (kc >> 5) + kb2;
+      if (gkb * 32 < K) {
+        bf16x8 ah[RBW], al[RBW];
+#pragma unroll
+        for (int r = 0; r < RBW; ++r) {
+          const int rb = wave * RBW + r;
+          if (rb < nrb) {
+            const uint4 *f = A + ((int64_t)(rb * KB + gkb) * 2) * 64 + lane;
+            uint4 h = f[0], l = f[64];
+            ah[r] = __builtin_bit_cast(bf16x8, h);
+            al[r] = __builtin_bit_cast(bf16x8, l);
+          }
+        }
+        const int ko = kb2 * 32 + 8 * (lane >> 4);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const int col = cb * 16 + (lane & 15);
+          const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&Bh[col][ko]));
+          const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&Bl[col][ko]));
+#pragma unroll
+          for (int r = 0; r < RBW; ++r) {
+            if (wave * RBW + r < nrb) {
+              acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bh, acc[r][cb], 0, 0, 0);
+              acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bl, acc[r][cb], 0, 0, 0);
+              acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[r], bh, acc[r][cb], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const float alpha = (float)tk.alpha;
+#pragma unroll
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = wave * RBW + r;
+    if (rb >= nrb) continue;
+    const int i0 = rb * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int c = cb * 16 + (lane & 15);
+      if (c >= tk.ncol) continue;
+      float *y = Y + (int64_t)dst[tk.col0 + c] * ld + i0;
+      const floatx4 v = acc[r][cb] * alpha;
+      if (mode == GEMM_STORE) {
+        *reinterpret_cast<floatx4 *>(y) = v;
+      } else {
+        floatx4 o = *reinterpret_cast<floatx4 *>(y);
+        *reinterpret_cast<floatx4 *>(y) = o + v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Point-kernel evaluation.  KERN 0 = Laplace 1/r, 1 = Yukawa exp(-kappa r)/r.
 // g and f = -(1/r) dg/dr for a pair at squared distance r2 (0 for r2 == 0).
 // ---------------------------------------------------------------------------
@@ -663,9 +781,37 @@ static void launch_gemm_rbw(const GemmBatch &bt, const T *pool, int64_t mstride,
                      ld, nrb, bt.klen, bt.d_src, bt.d_dst, X, Y, bt.mode);
 }
 
+template <int RBW>
+static void launch_bf3_rbw(fmm_plan *P, const GemmBatch &bt, int nrb, const float *X, float *Y, hipStream_t s) {
+  const unsigned gy = (unsigned)((nrb + 4 * RBW - 1) / (4 * RBW));
+  const int KB = P->bf_kb;
+  hipLaunchKernelGGL((k_gemm_bf3<RBW>), dim3(bt.ntask, gy), dim3(256), 0, s, bt.d_tasks, (const uint4 *)P->pool_bf,
+                     (int64_t)(P->ld / 16) * KB * 2 * 64, KB, P->ld, nrb, bt.klen, bt.d_src, bt.d_dst, X, Y,
+                     bt.mode);
+}
+
 template <typename T>
 static int launch_gemm(fmm_plan *P, const GemmBatch &bt, const T *X, T *Y, hipStream_t s) {
   if (bt.ntask == 0) return FMM_OK;
+  if constexpr (std::is_same<T, float>::value) {
+    if (bt.pool == 2) {
+      const int nrb = bt.nrb;
+      const int rbw = bt.ntask >= 1024 ? (nrb + 3) / 4 : 1;
+      switch (rbw) {
+        case 1: launch_bf3_rbw<1>(P, bt, nrb, X, Y, s); break;
+        case 2: launch_bf3_rbw<2>(P, bt, nrb, X, Y, s); break;
+        case 3: launch_bf3_rbw<3>(P, bt, nrb, X, Y, s); break;
+        case 4: launch_bf3_rbw<4>(P, bt, nrb, X, Y, s); break;
+        case 5: launch_bf3_rbw<5>(P, bt, nrb, X, Y, s); break;
+        case 6: launch_bf3_rbw<6>(P, bt, nrb, X, Y, s); break;
+        case 7: launch_bf3_rbw<7>(P, bt, nrb, X, Y, s); break;
+        case 8: launch_bf3_rbw<8>(P, bt, nrb, X, Y, s); break;
+        default: set_error("expansion order too large for the GEMM kernel"); return FMM_EINVAL;
+      }
+      FMM_HIP_TRY(hipGetLastError());
+      return FMM_OK;
+    }
+  }
   const int ld = P->ld;
   const int nrb = bt.nrb;
   // Small launches (few column tiles) split the row blocks over a second grid

@@ -101,7 +101,7 @@ def test_config0_fp64_laplace_vs_direct():
 
 
 @pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp64"])
 def test_surface_cloud_vs_direct(kernel, precision):
     """Sphere-union surface cloud (40 spheres, 24k points), p=8; every
     target against the FP64 direct sum."""
@@ -131,7 +131,7 @@ def test_multi_column_matches_single_columns():
         np.testing.assert_allclose(grad[c].cpu().numpy(), g1, rtol=1e-12, atol=1e-14)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp64"])
 def test_bitwise_deterministic(precision):
     x, q = synth.unit_sphere_cloud(6000, seed=26)
     plan = _plan(x, kernel="laplace", p=6, ncrit=48, precision=precision)
