@@ -86,6 +86,17 @@ enum {
 int fmm_setup(const double *xyz_dev, int64_t n, int kernel, double kappa, int p, int ncrit,
               int precision, fmm_stream_t stream, fmm_plan **out);
 
+/* Plan for a batch of nmol independent point sets ("molecules"): molecule m
+ * is points offsets[m] .. offsets[m+1]-1 of xyz_dev (offsets: HOST array of
+ * nmol+1 nondecreasing values, offsets[0] = 0).  Points of different
+ * molecules do not interact.  Every molecule gets its own root cube, all of
+ * the same side (the largest extent in the batch), so that the translation
+ * operators are shared and each FMM pass runs as one launch for the whole
+ * batch.  fmm_eval on such a plan evaluates every molecule; densities and
+ * outputs use the concatenated order.  Otherwise as fmm_setup. */
+int fmm_setup_batch(const double *xyz_dev, const int64_t *offsets, int nmol, int kernel, double kappa, int p,
+                    int ncrit, int precision, fmm_stream_t stream, fmm_plan **out);
+
 /* Evaluate nrhs density columns.  q_dev: nrhs x n (column c at q_dev + c*n),
  * in the caller's point order, element type double (FMM_FP64) or float.
  * pot_dev: nrhs x n, same type; grad_dev: nrhs x n x 3 (gradient of point i

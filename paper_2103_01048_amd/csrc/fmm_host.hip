@@ -35,8 +35,8 @@ static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 
 int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], double mx[3], bool *finite);
-int device_morton_sort(const double *xyz, int64_t n, const double lo[3], double W, hipStream_t s,
-                       std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out);
+int device_morton_sort(const double *xyz, int64_t n, const std::vector<int64_t> &off, const std::vector<double> &lo,
+                       double W, hipStream_t s, std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out);
 int device_gather_points(const double *xyz, const int32_t *perm, int64_t n, const double shift[3], int prec,
                          void *pts, hipStream_t s);
 int eval_dispatch(fmm_plan *P, const void *q, int nrhs, void *pot, void *grad, hipStream_t s);
@@ -70,13 +70,16 @@ static int upload(fmm_plan *P, void **ptr, const std::vector<V> &h) {
 static inline int64_t prefix_of(int64_t key, int l) { return key >> (3 * (MAXLEVEL - l)); }
 
 static void build_tree(fmm_plan *P) {
-  const int64_t n = P->n;
+  // Breadth first from one root per (non-empty) molecule: boxes come out
+  // ordered by (level, molecule, key).
   const std::vector<int64_t> &K = P->keys;
-  struct B { int l; int64_t pre, b, e, par; };
+  struct B { int l; int32_t mol; int64_t pre, b, e, par; };
   std::vector<B> boxes;
-  boxes.push_back({0, 0, 0, n, -1});
+  const int nmol = (int)P->mol_off.size() - 1;
+  for (int m = 0; m < nmol; ++m)
+    if (P->mol_off[m + 1] > P->mol_off[m]) boxes.push_back({0, m, 0, P->mol_off[m], P->mol_off[m + 1], -1});
   std::vector<int64_t> lb = {0};
-  int64_t lvl_start = 0, lvl_end = 1;
+  int64_t lvl_start = 0, lvl_end = (int64_t)boxes.size();
   while (true) {
     lb.push_back(lvl_end);
     for (int64_t bi = lvl_start; bi < lvl_end; ++bi) {
@@ -86,13 +89,13 @@ static void build_tree(fmm_plan *P) {
       int64_t pos = bx.b;
       for (int c = 0; c < 8 && pos < bx.e; ++c) {
         // first key of the next octant; the last octant ends with its parent
-        // (for the root, (7 + 1) << 60 would overflow the signed key type)
+        // (for a root, (7 + 1) << 60 would overflow the signed key type)
         int64_t end = bx.e;
         if (c < 7) {
           const int64_t bound = (((bx.pre << 3) | c) + 1) << shift;
           end = std::lower_bound(K.begin() + pos, K.begin() + bx.e, bound) - K.begin();
         }
-        if (end > pos) boxes.push_back({bx.l + 1, (bx.pre << 3) | c, pos, end, bi});
+        if (end > pos) boxes.push_back({bx.l + 1, bx.mol, (bx.pre << 3) | c, pos, end, bi});
         pos = end;
       }
     }
@@ -103,10 +106,10 @@ static void build_tree(fmm_plan *P) {
   lb.push_back((int64_t)boxes.size());
   const int64_t nb = (int64_t)boxes.size();
   P->level.resize(nb); P->anchor.resize(3 * nb); P->begin.resize(nb); P->end.resize(nb);
-  P->parent.resize(nb); P->child_begin.assign(nb, -1); P->nchild.assign(nb, 0);
+  P->parent.resize(nb); P->child_begin.assign(nb, -1); P->nchild.assign(nb, 0); P->mol.resize(nb);
   for (int64_t b = 0; b < nb; ++b) {
     const B &bx = boxes[b];
-    P->level[b] = bx.l; P->begin[b] = bx.b; P->end[b] = bx.e; P->parent[b] = bx.par;
+    P->level[b] = bx.l; P->begin[b] = bx.b; P->end[b] = bx.e; P->parent[b] = bx.par; P->mol[b] = bx.mol;
     int64_t a[3] = {0, 0, 0};
     for (int k = 0; k < bx.l; ++k) {
       const int64_t dig = (bx.pre >> (3 * (bx.l - 1 - k))) & 7;
@@ -134,22 +137,34 @@ static inline int64_t interleave3(int64_t x, int64_t y, int64_t z, int l) {
 }
 
 struct Lookup {
+  // per level: the prefixes of the level's boxes (ordered by molecule, then
+  // key) and, per molecule, its range within the level
   const fmm_plan *P;
-  std::vector<std::vector<int64_t>> pre;  // per level, sorted prefixes
+  std::vector<std::vector<int64_t>> pre;
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> rng;
   explicit Lookup(const fmm_plan *p) : P(p) {
     const int nl = (int)P->level_begin.size() - 1;
+    const int nmol = (int)P->mol_off.size() - 1;
     pre.resize(nl);
+    rng.assign(nl, std::vector<std::pair<int64_t, int64_t>>(nmol, {0, 0}));
     for (int l = 0; l < nl; ++l)
-      for (int64_t b = P->level_begin[l]; b < P->level_begin[l + 1]; ++b)
+      for (int64_t b = P->level_begin[l]; b < P->level_begin[l + 1]; ++b) {
+        const int64_t i = (int64_t)pre[l].size();
         pre[l].push_back(interleave3(P->anchor[3 * b], P->anchor[3 * b + 1], P->anchor[3 * b + 2], l));
+        auto &r = rng[l][P->mol[b]];
+        if (r.second == r.first) r = {i, i + 1};
+        else r.second = i + 1;
+      }
   }
-  int64_t find(int l, int64_t x, int64_t y, int64_t z) const {
+  int64_t find(int mol, int l, int64_t x, int64_t y, int64_t z) const {
     if (l >= (int)pre.size()) return -1;
     const int64_t side = (int64_t)1 << l;
     if (x < 0 || y < 0 || z < 0 || x >= side || y >= side || z >= side) return -1;
     const int64_t k = interleave3(x, y, z, l);
-    auto it = std::lower_bound(pre[l].begin(), pre[l].end(), k);
-    if (it == pre[l].end() || *it != k) return -1;
+    const auto r = rng[l][mol];
+    auto b0 = pre[l].begin() + r.first, b1 = pre[l].begin() + r.second;
+    auto it = std::lower_bound(b0, b1, k);
+    if (it == b1 || *it != k) return -1;
     return P->level_begin[l] + (it - pre[l].begin());
   }
 };
@@ -180,7 +195,7 @@ static void build_lists(fmm_plan *P) {
       for (int dx = -1; dx <= 1; ++dx)
         for (int dy = -1; dy <= 1; ++dy)
           for (int dz = -1; dz <= 1; ++dz) {
-            const int64_t c = lk.find(l - 1, px + dx, py + dy, pz + dz);
+            const int64_t c = lk.find(P->mol[b], l - 1, px + dx, py + dy, pz + dz);
             if (c < 0) continue;
             for (int k = 0; k < P->nchild[c]; ++k) {
               const int64_t ch = P->child_begin[c] + k;
@@ -200,7 +215,7 @@ static void build_lists(fmm_plan *P) {
           int ll = l;
           int64_t box = -1;
           while (ll >= 0) {
-            box = lk.find(ll, cx, cy, cz);
+            box = lk.find(P->mol[b], ll, cx, cy, cz);
             if (box >= 0) break;
             --ll;
             cx >>= 1; cy >>= 1; cz >>= 1;
@@ -1054,11 +1069,12 @@ extern "C" {
 
 const char *fmm_last_error(void) { return g_err.c_str(); }
 
-int fmm_setup(const double *xyz_dev, int64_t n, int kernel, double kappa, int p, int ncrit, int precision,
-              fmm_stream_t stream, fmm_plan **out) {
+static int setup_common(const double *xyz_dev, const std::vector<int64_t> &off, int kernel, double kappa, int p,
+                        int ncrit, int precision, fmm_stream_t stream, fmm_plan **out) {
   auto t0 = std::chrono::steady_clock::now();
   if (!out) { set_error("fmm_setup: out is NULL"); return FMM_EINVAL; }
   *out = nullptr;
+  const int64_t n = off.back();
   if (n < 0 || n > 0x7fffffffll) { set_error("fmm_setup: n out of range"); return FMM_EINVAL; }
   if (n > 0 && !xyz_dev) { set_error("fmm_setup: xyz is NULL"); return FMM_EINVAL; }
   if (kernel != FMM_LAPLACE && kernel != FMM_YUKAWA) { set_error("fmm_setup: unknown kernel"); return FMM_EINVAL; }
@@ -1073,29 +1089,43 @@ int fmm_setup(const double *xyz_dev, int64_t n, int kernel, double kappa, int p,
   if (!P) { set_error("fmm_setup: out of host memory"); return FMM_ENOMEM; }
   P->kernel = kernel; P->kappa = kernel == FMM_YUKAWA ? kappa : 0.0; P->p = p; P->ncrit = ncrit; P->precision = precision;
   P->n = n;
+  P->mol_off = off;
   P->nsurf = 6 * (p - 1) * (p - 1) + 2;
   P->ld = ((P->nsurf + 15) / 16) * 16;
   if (P->ld / 16 > 32) { delete P; set_error("fmm_setup: p too large for the GEMM kernel"); return FMM_EINVAL; }
-  hipGetDevice(&P->device);
+  (void)hipGetDevice(&P->device);
   hipStream_t s = (hipStream_t)stream;
+  const int nmol = (int)off.size() - 1;
   int rc = FMM_OK;
   do {
     if (n == 0) {
       P->level = {0}; P->nchild = {0}; P->anchor = {0, 0, 0}; P->begin = {0}; P->end = {0}; P->parent = {-1};
-      P->child_begin = {-1}; P->level_begin = {0, 1};
+      P->child_begin = {-1}; P->level_begin = {0, 1}; P->mol = {0};
       for (int k = 0; k < 4; ++k) { P->loff[k] = {0, 0}; P->lidx[k].clear(); }
       P->dt.nbox = 1; P->dt.maxlevel = 0;
       break;
     }
-    double mn[3], mx[3];
-    bool finite = true;
-    if ((rc = device_bbox(xyz_dev, n, s, mn, mx, &finite))) break;
-    if (!finite) { set_error("fmm_setup: non-finite coordinate"); rc = FMM_EINVAL; break; }
-    double ext = 0, cen[3];
-    for (int d = 0; d < 3; ++d) { cen[d] = (mn[d] + mx[d]) * 0.5; ext = std::max(ext, mx[d] - mn[d]); }
+    // per-molecule bounding boxes; one common root side W for the batch, so
+    // that every molecule's tree has the same box sizes per level and the
+    // translation operators are shared
+    std::vector<double> cen(3 * nmol, 0.0);
+    double ext = 0;
+    for (int m = 0; m < nmol && !rc; ++m) {
+      const int64_t nm = off[m + 1] - off[m];
+      if (nm == 0) continue;
+      double mn[3], mx[3];
+      bool finite = true;
+      if ((rc = device_bbox(xyz_dev + 3 * off[m], nm, s, mn, mx, &finite))) break;
+      if (!finite) { set_error("fmm_setup: non-finite coordinate"); rc = FMM_EINVAL; break; }
+      for (int d = 0; d < 3; ++d) { cen[3 * m + d] = (mn[d] + mx[d]) * 0.5; ext = std::max(ext, mx[d] - mn[d]); }
+    }
+    if (rc) break;
     P->W = ext > 0 ? ext * (1.0 + std::ldexp(1.0, -20)) : 1.0;
-    for (int d = 0; d < 3; ++d) { P->lo[d] = cen[d] - 0.5 * P->W; P->shift[d] = P->lo[d] + 0.5 * P->W; }
-    if ((rc = device_morton_sort(xyz_dev, n, P->lo, P->W, s, P->keys, P->perm))) break;
+    P->mol_lo.assign(3 * nmol, 0.0);
+    for (int m = 0; m < nmol; ++m)
+      for (int d = 0; d < 3; ++d) P->mol_lo[3 * m + d] = cen[3 * m + d] - 0.5 * P->W;
+    for (int d = 0; d < 3; ++d) { P->lo[d] = P->mol_lo[d]; P->shift[d] = P->lo[d] + 0.5 * P->W; }
+    if ((rc = device_morton_sort(xyz_dev, n, off, P->mol_lo, P->W, s, P->keys, P->perm))) break;
     build_tree(P);
     build_lists(P);
     // device tree
@@ -1105,7 +1135,16 @@ int fmm_setup(const double *xyz_dev, int64_t n, int kernel, double kappa, int p,
     const size_t es = precision == FMM_FP64 ? 8 : 4;
     if ((rc = dev_alloc(P, &P->dt.pts, (size_t)n * 4 * es))) break;
     P->dt.n = n;
-    if ((rc = device_gather_points(xyz_dev, P->dt.perm, n, P->shift, precision, P->dt.pts, s))) break;
+    for (int m = 0; m < nmol && !rc; ++m) {
+      // points relative to their molecule's cube centre
+      const int64_t nm = off[m + 1] - off[m];
+      if (nm == 0) continue;
+      double sh[3];
+      for (int d = 0; d < 3; ++d) sh[d] = P->mol_lo[3 * m + d] + 0.5 * P->W;
+      rc = device_gather_points(xyz_dev, P->dt.perm + off[m], nm, sh, precision,
+                                (char *)P->dt.pts + (size_t)off[m] * 4 * es, s);
+    }
+    if (rc) break;
     if ((rc = upload_lists(P))) break;
     rc = precision == FMM_FP64 ? precompute_typed<double>(P) : precompute_typed<float>(P);
     if (rc) break;
@@ -1116,6 +1155,23 @@ int fmm_setup(const double *xyz_dev, int64_t n, int kernel, double kappa, int p,
   P->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = P;
   return FMM_OK;
+}
+
+int fmm_setup(const double *xyz_dev, int64_t n, int kernel, double kappa, int p, int ncrit, int precision,
+              fmm_stream_t stream, fmm_plan **out) {
+  if (n < 0) { set_error("fmm_setup: n out of range"); if (out) *out = nullptr; return FMM_EINVAL; }
+  return setup_common(xyz_dev, {0, n}, kernel, kappa, p, ncrit, precision, stream, out);
+}
+
+int fmm_setup_batch(const double *xyz_dev, const int64_t *offsets, int nmol, int kernel, double kappa, int p,
+                    int ncrit, int precision, fmm_stream_t stream, fmm_plan **out) {
+  if (out) *out = nullptr;
+  if (nmol < 1 || !offsets) { set_error("fmm_setup_batch: need nmol >= 1 and offsets"); return FMM_EINVAL; }
+  std::vector<int64_t> off(offsets, offsets + nmol + 1);
+  if (off[0] != 0) { set_error("fmm_setup_batch: offsets[0] must be 0"); return FMM_EINVAL; }
+  for (int m = 0; m < nmol; ++m)
+    if (off[m + 1] < off[m]) { set_error("fmm_setup_batch: offsets must not decrease"); return FMM_EINVAL; }
+  return setup_common(xyz_dev, off, kernel, kappa, p, ncrit, precision, stream, out);
 }
 
 int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *grad_dev, fmm_stream_t stream) {

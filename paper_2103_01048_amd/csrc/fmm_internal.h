@@ -127,6 +127,9 @@ struct fmm_plan {
   std::vector<int32_t> level, nchild;
   std::vector<int64_t> anchor, begin, end, parent, child_begin;
   std::vector<int64_t> level_begin;  // size maxlevel+2
+  std::vector<int32_t> mol;          // molecule of each box
+  std::vector<int64_t> mol_off;      // point ranges of the molecules (input order)
+  std::vector<double> mol_lo;        // lower corner of each molecule's root cube
   std::vector<int64_t> loff[4];      // U, V, W, X CSR offsets (nbox+1)
   std::vector<int64_t> lidx[4];
   std::vector<int32_t> leaf_ids;

@@ -19,6 +19,7 @@
 #include <type_traits>
 
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "fmm_internal.h"
 
@@ -87,7 +88,7 @@ __device__ inline uint64_t spread3(uint64_t v) {
 }
 
 __global__ void k_morton(const double *__restrict__ xyz, int64_t n, double lox, double loy, double loz,
-                         double W, uint64_t *__restrict__ keys, int32_t *__restrict__ idx) {
+                         double W, uint64_t *__restrict__ keys, int32_t *__restrict__ idx, int64_t base) {
   int64_t i = blockIdx.x * 256ll + threadIdx.x;
   if (i >= n) return;
   const double lo[3] = {lox, loy, loz};
@@ -99,7 +100,7 @@ __global__ void k_morton(const double *__restrict__ xyz, int64_t n, double lox, 
     c[d] = (uint64_t)f;
   }
   keys[i] = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);
-  idx[i] = (int32_t)i;
+  idx[i] = (int32_t)(base + i);
 }
 
 template <typename T>
@@ -137,12 +138,15 @@ int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], doubl
   return FMM_OK;
 }
 
-// Morton keys + stable radix sort on the device; returns sorted keys and the
-// permutation on the host.
-int device_morton_sort(const double *xyz, int64_t n, const double lo[3], double W, hipStream_t s,
-                       std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out) {
+// Morton keys (each molecule in its own root cube of side W, lower corner
+// lo[3m..3m+2]) and a stable radix sort within each molecule's range; the
+// sorted keys and the permutation (global indices) come back to the host.
+int device_morton_sort(const double *xyz, int64_t n, const std::vector<int64_t> &off, const std::vector<double> &lo,
+                       double W, hipStream_t s, std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out) {
+  const int nmol = (int)off.size() - 1;
   uint64_t *k0 = nullptr, *k1 = nullptr;
   int32_t *v0 = nullptr, *v1 = nullptr;
+  int64_t *d_off = nullptr;
   void *tmp = nullptr;
   size_t tmp_bytes = 0;
   int rc = FMM_OK;
@@ -152,13 +156,31 @@ int device_morton_sort(const double *xyz, int64_t n, const double lo[3], double 
   };
   hipError_t e;
   if ((e = hipMalloc(&k0, n * 8)) != hipSuccess || (e = hipMalloc(&k1, n * 8)) != hipSuccess ||
-      (e = hipMalloc(&v0, n * 4)) != hipSuccess || (e = hipMalloc(&v1, n * 4)) != hipSuccess) {
+      (e = hipMalloc(&v0, n * 4)) != hipSuccess || (e = hipMalloc(&v1, n * 4)) != hipSuccess ||
+      (e = hipMalloc(&d_off, (nmol + 1) * 8)) != hipSuccess) {
     fail("morton alloc", e);
   } else {
-    hipLaunchKernelGGL(k_morton, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xyz, n, lo[0], lo[1], lo[2], W, k0, v0);
-    e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, k0, k1, v0, v1, (size_t)n, 0, 63, s);
-    if (e == hipSuccess) e = hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 16));
-    if (e == hipSuccess) e = rocprim::radix_sort_pairs(tmp, tmp_bytes, k0, k1, v0, v1, (size_t)n, 0, 63, s);
+    for (int m = 0; m < nmol; ++m) {
+      const int64_t nm = off[m + 1] - off[m];
+      if (nm == 0) continue;
+      hipLaunchKernelGGL(k_morton, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, xyz + 3 * off[m], nm,
+                         lo[3 * m], lo[3 * m + 1], lo[3 * m + 2], W, k0 + off[m], v0 + off[m], off[m]);
+    }
+    e = hipMemcpyAsync(d_off, off.data(), (nmol + 1) * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      if (nmol == 1) {
+        e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, k0, k1, v0, v1, (size_t)n, 0, 63, s);
+        if (e == hipSuccess) e = hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 16));
+        if (e == hipSuccess) e = rocprim::radix_sort_pairs(tmp, tmp_bytes, k0, k1, v0, v1, (size_t)n, 0, 63, s);
+      } else {
+        e = rocprim::segmented_radix_sort_pairs(nullptr, tmp_bytes, k0, k1, v0, v1, (unsigned)n, (unsigned)nmol, d_off,
+                                                d_off + 1, 0, 63, s);
+        if (e == hipSuccess) e = hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 16));
+        if (e == hipSuccess)
+          e = rocprim::segmented_radix_sort_pairs(tmp, tmp_bytes, k0, k1, v0, v1, (unsigned)n, (unsigned)nmol, d_off,
+                                                  d_off + 1, 0, 63, s);
+      }
+    }
     std::vector<uint64_t> hk(n);
     std::vector<int32_t> hv(n);
     if (e == hipSuccess) e = hipMemcpyAsync(hk.data(), k1, n * 8, hipMemcpyDeviceToHost, s);
@@ -171,7 +193,7 @@ int device_morton_sort(const double *xyz, int64_t n, const double lo[3], double 
       for (int64_t i = 0; i < n; ++i) { keys_out[i] = (int64_t)hk[i]; perm_out[i] = hv[i]; }
     }
   }
-  (void)hipFree(k0); (void)hipFree(k1); (void)hipFree(v0); (void)hipFree(v1); (void)hipFree(tmp);
+  (void)hipFree(k0); (void)hipFree(k1); (void)hipFree(v0); (void)hipFree(v1); (void)hipFree(tmp); (void)hipFree(d_off);
   return rc;
 }
 

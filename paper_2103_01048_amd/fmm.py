@@ -25,14 +25,16 @@ def _ptr(t):
 
 
 class FMMPlan:
-    """A kernel-independent FMM plan for a fixed point set (targets = sources).
+    """A kernel-independent FMM plan for a fixed point set (targets = sources),
+    or, with `offsets`, for a batch of independent point sets (molecule m is
+    points offsets[m]:offsets[m+1]; molecules do not interact).
 
     points: (N, 3) float64 CUDA tensor (copied and sorted by the library).
     kernel: "laplace" or "yukawa"; kappa >= 0; p: points per surface edge;
     ncrit: maximum points per leaf; precision: "fp64", "fp32" or "bf16x3"."""
 
     def __init__(self, points: torch.Tensor, kernel: str = "laplace", kappa: float = 0.0, p: int = 6,
-                 ncrit: int = 64, precision: str = "fp32"):
+                 ncrit: int = 64, precision: str = "fp32", offsets=None):
         if kernel not in KERNELS:
             raise ValueError(f"unknown kernel {kernel!r}")
         if precision not in PRECISIONS:
@@ -46,8 +48,16 @@ class FMMPlan:
         self.device = pts.device
         h = ctypes.c_void_p()
         with torch.cuda.device(pts.device):
-            check(lib().fmm_setup(_ptr(pts), self.n, KERNELS[kernel], self.kappa, self.p, self.ncrit,
-                                  PRECISIONS[precision], _stream(), ctypes.byref(h)), "fmm_setup")
+            if offsets is None:
+                check(lib().fmm_setup(_ptr(pts), self.n, KERNELS[kernel], self.kappa, self.p, self.ncrit,
+                                      PRECISIONS[precision], _stream(), ctypes.byref(h)), "fmm_setup")
+            else:
+                off = np.ascontiguousarray(offsets, dtype=np.int64)
+                if off.ndim != 1 or off[0] != 0 or off[-1] != self.n:
+                    raise ValueError("offsets must start at 0 and end at the number of points")
+                check(lib().fmm_setup_batch(_ptr(pts), ctypes.c_void_p(off.ctypes.data), len(off) - 1,
+                                            KERNELS[kernel], self.kappa, self.p, self.ncrit, PRECISIONS[precision],
+                                            _stream(), ctypes.byref(h)), "fmm_setup_batch")
         self._h = h
 
     def __del__(self):

@@ -1,0 +1,68 @@
+"""A batch of independent molecules in one plan (fmm_setup_batch): every
+molecule matches its own FP64 direct sum, so no interaction leaks between
+molecules, and the batch's tree keeps each molecule apart."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct as D
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _molecules(nmol, seed):
+    rng = np.random.default_rng(seed)
+    xs, qs = [], []
+    for m in range(nmol):
+        ntri = int(np.exp(rng.uniform(np.log(300), np.log(3000))))
+        nsph = max(2, ntri // 150)
+        side = 10.0 * (nsph / 10) ** (1 / 3)
+        su = synth.sphere_union_spheres(nsph, seed=seed * 100 + m, box=side)
+        v, t = synth.sphere_union_mesh(su, ntri, seed=seed * 100 + m)
+        x = synth.three_point_cloud(v, t) + rng.uniform(-50, 50, 3)  # molecules overlap in space on purpose
+        xs.append(x)
+        qs.append(rng.standard_normal(len(x)))
+    off = np.concatenate([[0], np.cumsum([len(x) for x in xs])])
+    return xs, qs, off
+
+
+@pytest.mark.parametrize("kernel,precision,tol", [("laplace", "fp32", 1e-4), ("yukawa", "fp32", 1e-4),
+                                                  ("yukawa", "fp64", 1e-6), ("laplace", "bf16x3", 1e-4)])
+def test_batch_matches_each_molecule(kernel, precision, tol):
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    xs, qs, off = _molecules(16, seed=61)
+    X = np.concatenate(xs)
+    Q = np.concatenate(qs)
+    plan = FMMPlan(torch.tensor(X, device="cuda"), kernel=kernel, kappa=0.125, p=8, ncrit=64,
+                   precision=precision, offsets=off)
+    pot, grad = plan.eval(torch.tensor(Q, device="cuda"))
+    torch.cuda.synchronize()
+    pot = pot.double().cpu().numpy()
+    grad = grad.double().cpu().numpy()
+    worst = 0.0
+    for m in range(len(xs)):
+        s = slice(off[m], off[m + 1])
+        p0, g0 = D.direct(xs[m], xs[m], qs[m], kernel, 0.125)
+        worst = max(worst, D.rel_l2(pot[s], p0), D.rel_l2(grad[s], g0))
+    print(f"[batch] {kernel} {precision} worst molecule rel L2 {worst:.2e}", flush=True)
+    assert worst < tol
+
+
+def test_batch_tree_keeps_molecules_apart():
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    xs, qs, off = _molecules(6, seed=62)
+    X = np.concatenate(xs)
+    plan = FMMPlan(torch.tensor(X, device="cuda"), p=4, ncrit=32, precision="fp64", offsets=off)
+    g = plan.tree()
+    assert sorted(g["perm"].tolist()) == list(range(len(X)))
+    # every box's points belong to one molecule, and every list entry stays in it
+    mol_of_point = np.searchsorted(off, g["perm"], side="right") - 1
+    box_mol = np.array([mol_of_point[b] for b in g["begin"]])
+    for b in range(len(g["level"])):
+        seg = mol_of_point[g["begin"][b]:g["end"][b]]
+        assert np.all(seg == box_mol[b])
+        for lst in (g["U"], g["V"], g["W"], g["X"]):
+            assert all(box_mol[a] == box_mol[b] for a in lst[b])
