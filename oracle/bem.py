@@ -304,3 +304,73 @@ def solve(m: Mesh, qxyz, q, eps1=4.0, eps2=80.0, kappa=0.125, **kw):
     b = rhs(m, qxyz, q, eps1)
     x = np.linalg.solve(A, b)
     return x, A, b
+
+
+def matvec_rows(m: Mesh, rows, x, eps1=4.0, eps2=80.0, kappa=0.125, n_outer: int = 8, n_rem: int = 4):
+    """Rows `rows` of A x for any mesh size, each entry a plain sum over all
+    trial triangles (regular rule) with the pairs that share a vertex taken
+    by the singular rule: O(N) per row through the C direct sum."""
+    from . import direct as Dd
+    T = len(m.tris)
+    k = m.qpts.shape[1]
+    rows = np.asarray(rows)
+    u, v = x[:T], x[T:]
+    Y = m.qpts.reshape(-1, 3)
+    W = m.qw.reshape(-1)
+    n_rep = np.repeat(m.normal, k, axis=0)
+    uu = np.repeat(u, k) * W
+    vv = np.repeat(v, k) * W
+    tgt = m.qpts[rows].reshape(-1, 3)
+    wt = m.qw[rows].reshape(-1)
+    out = np.zeros((len(rows), 2))
+    # trial triangles sharing a vertex with each test triangle, ascending
+    by_row = {int(s_): np.nonzero(np.isin(m.tris, m.tris[s_]).any(axis=1))[0]
+              for s_ in rows}
+    for ki, (kern, kap) in enumerate((("laplace", 0.0), ("yukawa", kappa))):
+        Kx = np.zeros(len(tgt))
+        for d in range(3):
+            _, g = Dd.direct(tgt, Y, uu * n_rep[:, d], kern, kap)
+            Kx -= g[:, d]
+        Vx, _ = Dd.direct(tgt, Y, vv, kern, kap)
+        Kr = (wt * Kx).reshape(len(rows), k).sum(axis=1)
+        Vr = (wt * Vx).reshape(len(rows), k).sum(axis=1)
+        for i, s_ in enumerate(rows):
+            ts = by_row[int(s_)]
+            Vs, Ks = singular_entries(m, np.full(len(ts), s_), ts, kap, n_outer, n_rem)
+            for j, t_ in enumerate(ts):
+                Vreg, Kreg = regular_entries(m, s_, t_, kap)
+                Vr[i] += (Vs[j] - Vreg) * v[t_]
+                Kr[i] += (Ks[j] - Kreg) * u[t_]
+        half = 0.5 * m.area[rows] * u[rows]
+        if ki == 0:
+            out[:, 0] = half + Kr - Vr
+        else:
+            out[:, 1] = half - Kr + (eps1 / eps2) * Vr
+    return out
+
+
+def reaction_potential_direct(m: Mesh, x, qxyz):
+    """reaction_potential through the C direct sum, for meshes too large for
+    the dense kernel matrix: the double-layer term sum_j (r - y_j).n_j u_j w_j
+    / (4 pi |r - y_j|^3) is minus the target gradient of the single-layer sum
+    with densities n_j,d u_j w_j, summed over d."""
+    from . import direct as Dd
+    T = len(m.tris)
+    u, v = x[:T], x[T:]
+    k = m.qpts.shape[1]
+    Y = m.qpts.reshape(-1, 3)
+    W = m.qw.reshape(-1)
+    nY = np.repeat(m.normal, k, axis=0)
+    uu = np.repeat(u, k) * W
+    vv = np.repeat(v, k) * W
+    tgt = np.ascontiguousarray(qxyz, dtype=np.float64).reshape(-1, 3)
+    phi, _ = Dd.direct(tgt, Y, vv)
+    for d in range(3):
+        _, g = Dd.direct(tgt, Y, uu * nY[:, d])
+        phi += g[:, d]
+    return phi
+
+
+def energy_direct(m: Mesh, x, qxyz, q):
+    phi = reaction_potential_direct(m, x, qxyz)
+    return 0.5 * float(np.dot(q, phi)) * FOUR_PI * KCAL_PER_MOL

@@ -22,7 +22,7 @@ void oracle_direct(int64_t nt, const double *tx, int64_t ns, const double *sx,
                    const double *q, int yukawa, double kappa,
                    double *pot, double *grad)
 {
-#pragma omp parallel for schedule(dynamic, 64)
+#pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < nt; ++i) {
         const double xi = tx[3 * i], yi = tx[3 * i + 1], zi = tx[3 * i + 2];
         double p = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;

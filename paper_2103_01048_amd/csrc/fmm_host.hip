@@ -861,6 +861,14 @@ static int finish_batch(fmm_plan *P, GemmBatch &bt) {
   return FMM_OK;
 }
 
+// Row length of the M2L pair slots: the largest downward rank, rounded up to
+// 16 (the rows the M2L GEMM computes).
+static int pair_ld(const fmm_plan *P) {
+  int m = 16;
+  for (int l = 2; l <= P->dt.maxlevel; ++l) m = std::max(m, std::max(16, ((P->rank_d[l] + 15) / 16) * 16));
+  return m;
+}
+
 int ensure_lists(fmm_plan *P, int nr) {
   PassLists &L = P->lists_by_nr[nr];
   if (L.nr == nr) return FMM_OK;
@@ -891,7 +899,7 @@ int ensure_lists(fmm_plan *P, int nr) {
   L.vs_u.nrb = ld / 16; L.vs_u.klen = maxru;
   L.ut_dx.nrb = maxrd / 16; L.ut_dx.klen = ld; L.ut_dx.mode = GEMM_ADD;
   L.vs_d.nrb = ld / 16; L.vs_d.klen = maxrd;
-  L.m2l.nrb = maxrd / 16; L.m2l.klen = maxru;
+  L.m2l.nrb = maxrd / 16; L.m2l.klen = maxru; L.m2l.ldy = pair_ld(P);
   if (P->precision == FMM_FP32_BF16X3) {
     L.m2l.pool = 2;
     L.m2l.klen = std::min(((maxru + 31) / 32) * 32, P->bf_kb * 32);
@@ -1023,7 +1031,7 @@ int ensure_work(fmm_plan *P, int nr) {
   if ((rc = dev_alloc(P, &P->cu, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->yd, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->mslot, wbytes))) return rc;
-  if ((rc = dev_alloc(P, &P->pairbuf, (size_t)std::max<int64_t>(1, P->dt.nvpair) * nr * P->ld * es))) return rc;
+  if ((rc = dev_alloc(P, &P->pairbuf, (size_t)std::max<int64_t>(1, P->dt.nvpair) * nr * pair_ld(P) * es))) return rc;
   // padding rows/columns must hold zeros (the GEMM K dimension reads them)
   FMM_HIP_TRY(hipMemset(P->equ, 0, wbytes));
   FMM_HIP_TRY(hipMemset(P->chk, 0, wbytes));

@@ -54,6 +54,7 @@ struct GemmBatch {
   int klen = 0;                // K extent actually read (multiple of 16)
   int seg = 0;                 // K length of one segment (0: the work-array row length)
   int kq_stride = 0;           // 16-wide k groups per stored row block (0: row length / 16)
+  int ldy = 0;                 // leading dimension of the output rows (0: the work-array row length)
   int mode = GEMM_STORE;
   int pool = 0;                // 0: matrix pool, 1: stacked pool, 2: bf16x3 split pool
   int ntask = 0;

@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask *__restrict__ tasks
                                               int64_t mat_stride, int S, int seg, int KQ, int ld, int nrb,
                                               int K, const int32_t *__restrict__ src,
                                               const int32_t *__restrict__ dst, const T *__restrict__ X,
-                                              T *__restrict__ Y, int mode) {
+                                              T *__restrict__ Y, int ldy, int mode) {
   // S segments of `seg` k-values per column (segment s of column c is row
   // src[c*S+s] of X, leading dimension ld); KQ: 16-wide k groups per stored
   // row block of A; K: k-values read; nrb: 16-row blocks computed.
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask *__restrict__ tasks
       const int c = cb * 16 + (lane & 15);
       if (c >= tk.ncol) continue;
       const int64_t row = dst[tk.col0 + c];
-      T *y = Y + row * ld + i0;
+      T *y = Y + row * ldy + i0;
       V4 v = acc[r][cb] * alpha;
       if (mode == GEMM_STORE) {
         *reinterpret_cast<V4 *>(y) = v;
@@ -346,7 +346,8 @@ template <int RBW>
 __global__ __launch_bounds__(256) void k_gemm_bf3(const GemmTask *__restrict__ tasks, const uint4 *__restrict__ pool,
                                                   int64_t mat_stride16, int KB, int ld, int nrb, int K,
                                                   const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
-                                                  const float *__restrict__ X, float *__restrict__ Y, int mode) {
+                                                  const float *__restrict__ X, float *__restrict__ Y, int ldy,
+                                                  int mode) {
   const GemmTask tk = tasks[blockIdx.x];
   const uint4 *__restrict__ A = pool + (int64_t)tk.mat * mat_stride16;
   __shared__ unsigned short Bh[GEMM_NT][64 + 8], Bl[GEMM_NT][64 + 8];
@@ -429,7 +430,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf3(const GemmTask *__restrict__ t
     for (int cb = 0; cb < 4; ++cb) {
       const int c = cb * 16 + (lane & 15);
       if (c >= tk.ncol) continue;
-      float *y = Y + (int64_t)dst[tk.col0 + c] * ld + i0;
+      float *y = Y + (int64_t)dst[tk.col0 + c] * ldy + i0;
       const floatx4 v = acc[r][cb] * alpha;
       if (mode == GEMM_STORE) {
         *reinterpret_cast<floatx4 *>(y) = v;
@@ -770,22 +771,23 @@ __global__ void k_fill_zero(T *__restrict__ y, int64_t n) {
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = (T)0;
 }
 
-// y[box] = sum over the box's M2L pairs (fixed order) of pairbuf[pair],
-// first `rows` entries of each column; 4 entries per thread.
+// y[box] = sum over the box's pairs (fixed order) of pairbuf[pair], first
+// `rows` entries of each column; 4 entries per thread.  Rows of pairbuf have
+// leading dimension ldp, rows of y leading dimension ld.
 template <typename T>
 __global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ tgt, const int32_t *__restrict__ off,
                                                     const int32_t *__restrict__ pairs, const T *__restrict__ pairbuf,
-                                                    T *__restrict__ y, int nr, int ld, int rows) {
+                                                    T *__restrict__ y, int nr, int ld, int ldp, int rows) {
   using V4 = typename Vec4<T>::type;
   const int slot = blockIdx.x;
   const int b = tgt[slot];
   const int p0 = off[slot], p1 = off[slot + 1];
-  const int rq = rows >> 2, lq = ld >> 2;
+  const int rq = rows >> 2, lq = ld >> 2, pq = ldp >> 2;
   for (int e = threadIdx.x; e < nr * rq; e += 64) {
     const int r = e / rq, i = e - r * rq;
     V4 acc = V4{0, 0, 0, 0};
     for (int p = p0; p < p1; ++p)
-      acc += reinterpret_cast<const V4 *>(pairbuf)[((int64_t)pairs[p] * nr + r) * lq + i];
+      acc += reinterpret_cast<const V4 *>(pairbuf)[((int64_t)pairs[p] * nr + r) * pq + i];
     reinterpret_cast<V4 *>(y)[((int64_t)b * nr + r) * lq + i] = acc;
   }
 }
@@ -800,7 +802,7 @@ static void launch_gemm_rbw(const GemmBatch &bt, const T *pool, int64_t mstride,
   const int seg = bt.seg ? bt.seg : ld;
   const int kq = bt.kq_stride ? bt.kq_stride : ld / 16;
   hipLaunchKernelGGL((k_gemm<T, RBW>), dim3(bt.ntask, gy), dim3(256), 0, s, bt.d_tasks, pool, mstride, bt.S, seg, kq,
-                     ld, nrb, bt.klen, bt.d_src, bt.d_dst, X, Y, bt.mode);
+                     ld, nrb, bt.klen, bt.d_src, bt.d_dst, X, Y, bt.ldy ? bt.ldy : ld, bt.mode);
 }
 
 template <int RBW>
@@ -809,7 +811,7 @@ static void launch_bf3_rbw(fmm_plan *P, const GemmBatch &bt, int nrb, const floa
   const int KB = P->bf_kb;
   hipLaunchKernelGGL((k_gemm_bf3<RBW>), dim3(bt.ntask, gy), dim3(256), 0, s, bt.d_tasks, (const uint4 *)P->pool_bf,
                      (int64_t)(P->ld / 16) * KB * 2 * 64, KB, P->ld, nrb, bt.klen, bt.d_src, bt.d_dst, X, Y,
-                     bt.mode);
+                     bt.ldy ? bt.ldy : P->ld, bt.mode);
 }
 
 template <typename T>
@@ -895,7 +897,7 @@ static int eval_chunk(fmm_plan *P, const T *q, T *pot, T *grad, hipStream_t s) {
       ev = prof_begin(P, FMM_PHASE_M2M, s);
       if ((rc = launch_gemm<T>(P, L.m2m[l], cu, (T *)P->mslot, s))) return rc;
       hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.m2m_n[l]), dim3(64), 0, s, D.m2m_tgt[l], D.m2m_off[l], D.m2m_kid[l],
-                         (const T *)P->mslot, cu, NR, ld, L.m2m[l].nrb * 16);
+                         (const T *)P->mslot, cu, NR, ld, ld, L.m2m[l].nrb * 16);
       FMM_HIP_TRY(hipGetLastError());
       prof_end(P, FMM_PHASE_M2M, ev, s);
     }
@@ -910,7 +912,8 @@ static int eval_chunk(fmm_plan *P, const T *q, T *pot, T *grad, hipStream_t s) {
                          (const T *)P->surf, P->nsurf, ld, (T)ALPHA_DC, chk, 0, kappa);
     FMM_HIP_TRY(hipGetLastError());
     prof_end(P, FMM_PHASE_P2L, ev, s);
-    // M2L between singular coordinates into pair slots, then a fixed-order
+    // M2L between singular coordinates into pair slots (rows of the
+    // largest downward rank, not of the surface size), then a fixed-order
     // sum per target box (every box at level >= 2)
     ev = prof_begin(P, FMM_PHASE_M2L, s);
     if ((rc = launch_gemm<T>(P, L.m2l, cu, (T *)P->pairbuf, s))) return rc;
@@ -918,7 +921,7 @@ static int eval_chunk(fmm_plan *P, const T *q, T *pot, T *grad, hipStream_t s) {
     ev = prof_begin(P, FMM_PHASE_M2L_SUM, s);
     if (D.nvbox > 0)
       hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.nvbox), dim3(64), 0, s, D.v_tgt, D.v_off, D.v_pair,
-                         (const T *)P->pairbuf, yd, NR, ld, L.m2l.nrb * 16);
+                         (const T *)P->pairbuf, yd, NR, ld, L.m2l.ldy, L.m2l.nrb * 16);
     FMM_HIP_TRY(hipGetLastError());
     prof_end(P, FMM_PHASE_M2L_SUM, ev, s);
     ev = prof_begin(P, FMM_PHASE_DC2E, s);

@@ -24,6 +24,8 @@ __all__ = [
     "three_point_cloud",
     "charges_in_spheres",
     "random_rotation",
+    "surface_cloud",
+    "molecule_batch",
 ]
 
 
@@ -228,3 +230,35 @@ def charges_in_spheres(su: SphereUnion, n_charges: int, seed: int, frac: float =
     x = su.centers[idx] + d * rad[:, None]
     q = rng.uniform(-1.0, 1.0, n_charges)
     return np.ascontiguousarray(x), q
+
+
+def surface_cloud(n_spheres: int, n_triangles: int, seed: int, box: float | None = None,
+                  shell_radius: float | None = None):
+    """Point-cloud workload: three points per triangle of an n_triangles
+    exposed-surface mesh of n_spheres spheres (radii U[1.5, 2.0] A), centres in
+    a cube of side `box` (default 40 (n_spheres / 200)^(1/3) A, the density of
+    200 spheres in a 40 A cube) or, with shell_radius, in a 10 A thick shell;
+    densities N(0, 1).  Returns (points (3 n_triangles, 3), densities)."""
+    if box is None:
+        box = 40.0 * (n_spheres / 200.0) ** (1.0 / 3.0)
+    su = sphere_union_spheres(n_spheres, seed=seed, box=box, shell_radius=shell_radius)
+    v, t = sphere_union_mesh(su, n_triangles, seed=seed)
+    x = three_point_cloud(v, t)
+    q = np.random.default_rng(seed).standard_normal(len(x))
+    return x, q
+
+
+def molecule_batch(nmol: int = 64, seed: int = 5):
+    """nmol molecules of N_m = 3 round(exp(U[ln 5000, ln 60000]) / 3) points
+    (log-uniform sizes), each a surface_cloud of ceil(N_m / 400) spheres;
+    densities N(0, 1).  Returns (list of points, list of densities)."""
+    rng = np.random.default_rng(seed)
+    xs, qs = [], []
+    for m in range(nmol):
+        nm = 3 * int(round(math.exp(rng.uniform(math.log(5000), math.log(60000))) / 3))
+        nsph = int(math.ceil(nm / 400))
+        su = sphere_union_spheres(nsph, seed=seed * 1000 + m, box=40.0 * (nsph / 200) ** (1 / 3))
+        v, t = sphere_union_mesh(su, nm // 3, seed=seed * 1000 + m)
+        xs.append(three_point_cloud(v, t))
+        qs.append(rng.standard_normal(nm))
+    return xs, qs

@@ -1,0 +1,239 @@
+"""GPU parity at the workloads' full sizes, in the launch configurations the
+benchmark times, on sampled outputs that the FP64 oracle computes one by one
+(single rows of the N-body sums and of the boundary-element matrix, finite
+differences of the exact pair energy), plus properties that hold at any size
+(GMRES residual of the FP64 operator).
+
+Workloads (all seeded, synthetic sphere-union surfaces):
+* 393,216 points (131,072 triangles x 3) on 200 spheres, Laplace and Yukawa
+  kappa = 0.125, p = 8, each ncrit of the benchmark's sweep;
+* the same surface at 1,000,002 points (500 spheres) for the adjoint;
+* 64 molecules of 5k-60k points in one batched plan;
+* 2M triangles x 3 points on 1,000 spheres for the boundary-element solve
+  with 20,000 charges;
+* 30M points (10M triangles x 3) on a 30,000-sphere shell of radius 200 A,
+  p = 10.
+
+Tolerances: 1e-4 relative L2 over the sampled rows for every single-precision
+path (the accuracy target of the mixed-precision evaluation) and 1e-6 for
+FP64 at p = 8; position gradients of the FP32 adjoint 1e-3 (the FMM's
+gradient is one order less accurate than its potential)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bem as B
+from oracle import direct as D
+from tests.gpu_util import require_gpu
+
+pytestmark = [pytest.mark.gpu, pytest.mark.fullsize]
+KAPPA = 0.125
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _check_rows(plan, torch, x, q, rows, kernel, tol, tag):
+    pot, grad = plan.eval(torch.tensor(q, device="cuda"))
+    torch.cuda.synchronize()
+    phi, g = D.direct(x[rows], x, q, kernel, KAPPA if kernel == "yukawa" else 0.0)
+    ep = _rel(pot.cpu().numpy()[rows], phi)
+    eg = _rel(grad.cpu().numpy()[rows], g)
+    _say(f"[{tag}] pot {ep:.2e} grad {eg:.2e}")
+    assert ep < tol and eg < tol
+
+
+@pytest.fixture(scope="module")
+def surface393k():
+    _say("[fullsize] building the 393,216-point surface")
+    return synth.surface_cloud(200, 131072, seed=1, box=40.0)
+
+
+@pytest.mark.parametrize("ncrit", [64, 128, 256])
+@pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
+def test_surface393k_bf16x3_every_ncrit(surface393k, kernel, ncrit):
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    x, q = surface393k
+    plan = FMMPlan(torch.tensor(x, device="cuda"), kernel=kernel, kappa=KAPPA, p=8, ncrit=ncrit,
+                   precision="bf16x3")
+    rows = np.random.default_rng(71).choice(len(x), 2048, replace=False)
+    _check_rows(plan, torch, x, q, rows, kernel, 1e-4, f"393k {kernel} bf16x3 ncrit {ncrit}")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("fp64", 1e-6)])
+@pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
+def test_surface393k_fp32_fp64(surface393k, kernel, precision, tol):
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    x, q = surface393k
+    plan = FMMPlan(torch.tensor(x, device="cuda"), kernel=kernel, kappa=KAPPA, p=8, ncrit=128,
+                   precision=precision)
+    rows = np.random.default_rng(72).choice(len(x), 2048, replace=False)
+    _check_rows(plan, torch, x, q, rows, kernel, tol, f"393k {kernel} {precision}")
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
+def test_batch64_molecules(kernel):
+    """The 64-molecule batch in one plan: four molecules (smallest, largest,
+    two seeded) against their own direct sums on sampled rows."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    xs, qs = synth.molecule_batch(64, seed=5)
+    off = np.concatenate([[0], np.cumsum([len(x) for x in xs])])
+    X, Q = np.concatenate(xs), np.concatenate(qs)
+    plan = FMMPlan(torch.tensor(X, device="cuda"), kernel=kernel, kappa=KAPPA, p=8, ncrit=128,
+                   precision="bf16x3", offsets=off)
+    pot, grad = plan.eval(torch.tensor(Q, device="cuda"))
+    pot, grad = pot.cpu().numpy(), grad.cpu().numpy()
+    sizes = np.diff(off)
+    rng = np.random.default_rng(73)
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), *rng.choice(64, 2, replace=False).tolist()})
+    kap = KAPPA if kernel == "yukawa" else 0.0
+    for m in pick:
+        rows = rng.choice(sizes[m], min(512, sizes[m]), replace=False)
+        phi, g = D.direct(xs[m][rows], xs[m], qs[m], kernel, kap)
+        ep = _rel(pot[off[m] + rows], phi)
+        eg = _rel(grad[off[m] + rows], g)
+        _say(f"[batch64 {kernel}] molecule {m} ({sizes[m]} points) pot {ep:.2e} grad {eg:.2e}")
+        assert ep < 1e-4 and eg < 1e-4
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
+def test_adjoint_1m_points(kernel):
+    """E = 1/2 q.phi on 1,000,002 points, FP32 forward and adjoint: dE/dq =
+    phi on sampled rows, dE/dx on 64 seeded coordinates against central
+    differences (h = 1e-4 A) of the exact FP64 pair energy."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, solvation_style_energy
+    x, _ = synth.surface_cloud(500, 333334, seed=81)
+    q = np.random.default_rng(81).uniform(-1.0, 1.0, len(x))
+    kap = KAPPA if kernel == "yukawa" else 0.0
+    plan = FMMPlan(torch.tensor(x, device="cuda"), kernel=kernel, kappa=KAPPA, p=8, ncrit=128, precision="fp32")
+    qt = torch.tensor(q, device="cuda", requires_grad=True)
+    xt = torch.tensor(x, device="cuda", requires_grad=True)
+    solvation_style_energy(plan, qt, xt).backward()
+    dq, dx = qt.grad.cpu().numpy(), xt.grad.cpu().numpy()
+    rng = np.random.default_rng(82)
+    rows = rng.choice(len(x), 2048, replace=False)
+    phi, _ = D.direct(x[rows], x, q, kernel, kap)
+    edq = _rel(dq[rows], phi)
+    pick = rng.choice(len(x), 64, replace=False)
+    dims = rng.integers(0, 3, 64)
+    h = 1e-4
+    fd = np.empty(64)
+    for i, (k, d) in enumerate(zip(pick, dims)):
+        e = np.zeros(3)
+        e[d] = h
+        others = np.delete(np.arange(len(x)), k)
+        pp, _ = D.direct(x[k:k + 1] + e, x[others], q[others], kernel, kap)
+        pm, _ = D.direct(x[k:k + 1] - e, x[others], q[others], kernel, kap)
+        fd[i] = q[k] * (pp[0] - pm[0]) / (2 * h)
+    edx = _rel(dx[pick, dims], fd)
+    _say(f"[adjoint 1M {kernel}] dq {edq:.2e} dx {edx:.2e}")
+    assert edq < 1e-4 and edx < 1e-3
+
+
+@pytest.fixture(scope="module")
+def bem2m():
+    _say("[fullsize] building the 2M-triangle sphere-union mesh")
+    su = synth.sphere_union_spheres(1000, seed=91, box=40.0 * 5.0 ** (1.0 / 3.0))
+    v, t = synth.sphere_union_mesh(su, 2_000_000, seed=91)
+    qxyz, q = synth.charges_in_spheres(su, 20000, seed=91)
+    return v, t, B.make_mesh(v, t, 3), qxyz, q
+
+
+def _bem(v, t, precision):
+    require_gpu()
+    from paper_2103_01048_amd import BEMOperator
+    return BEMOperator(v, t, quad_pts=3, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=8, ncrit=128,
+                       precision=precision)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("fp64", 1e-6)])
+def test_bem2m_matvec_and_rhs_rows(bem2m, precision, tol):
+    torch = require_gpu()
+    v, t, m, qxyz, q = bem2m
+    T = len(t)
+    op = _bem(v, t, precision)
+    rng = np.random.default_rng(92)
+    x = rng.standard_normal(2 * T)
+    y = op.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
+    rows = rng.choice(T, 16, replace=False)
+    ref = B.matvec_rows(m, rows, x, 4.0, 80.0, KAPPA)
+    e = _rel(np.stack([y[rows], y[T + rows]], axis=1), ref)
+    _say(f"[bem 2M {precision}] matvec rows {e:.2e}")
+    assert e < tol
+    b = op.rhs(qxyz, q).cpu().numpy()
+    sub = B.make_mesh(v, t[rows], 3)
+    rb = B.rhs(sub, qxyz, q, 4.0)
+    er = _rel(np.concatenate([b[rows], b[T + rows]]), rb)
+    _say(f"[bem 2M {precision}] rhs rows {er:.2e}")
+    assert er < 1e-12
+
+
+def test_bem2m_gmres_energy(bem2m):
+    """GMRES to 1e-6 from the FP32 operator with FP64 refinement: the FP64
+    operator's residual, the oracle's residual on sampled rows, and the
+    energy of a sampled subset of the charges against the oracle's."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import gmres
+    from paper_2103_01048_amd import _lib
+    v, t, m, qxyz, q = bem2m
+    T = len(t)
+    op32 = _bem(v, t, "fp32")
+    op64 = _bem(v, t, "fp64")
+    b = op32.rhs(qxyz, q)
+    x, its, hist, rc = gmres(op32, b, tol=1e-6, maxiter=400, restart=100, refine=op64, inner_tol=1e-4)
+    assert rc == _lib.FMM_OK
+    r = (b - op64.matvec(x)).norm().item() / b.norm().item()
+    _say(f"[bem 2M gmres] iterations {its} residual {r:.2e}")
+    assert r <= 1e-6
+    xh, bh = x.cpu().numpy(), b.cpu().numpy()
+    rng = np.random.default_rng(93)
+    rows = rng.choice(T, 16, replace=False)
+    ax = B.matvec_rows(m, rows, xh, 4.0, 80.0, KAPPA)
+    bref = np.stack([bh[rows], bh[T + rows]], axis=1)
+    er = float(np.linalg.norm(ax - bref) / np.linalg.norm(bref))
+    _say(f"[bem 2M gmres] oracle residual on 16 rows {er:.2e}")
+    assert er < 1e-5
+    sel = rng.choice(len(q), 256, replace=False)
+    eg = op32.energy(x, qxyz[sel], q[sel])
+    eo = B.energy_direct(m, xh, qxyz[sel], q[sel])
+    _say(f"[bem 2M energy] 256 charges GPU {eg:.10f} oracle {eo:.10f} kcal/mol")
+    assert abs(eg - eo) <= 1e-9 * abs(eo)
+    e_all = op32.energy(x, qxyz, q)
+    _say(f"[bem 2M energy] all 20,000 charges {e_all:.6f} kcal/mol")
+    assert math.isfinite(e_all) and e_all < 0
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
+def test_shell_30m_points_p10(kernel):
+    """30M points on a 30,000-sphere shell (R = 200 A), p = 10, FP32 with the
+    bf16x3 M2L, against the direct sum on 512 sampled rows."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    x, q = _shell30m()
+    plan = FMMPlan(torch.tensor(x, device="cuda"), kernel=kernel, kappa=KAPPA, p=10, ncrit=128,
+                   precision="bf16x3")
+    _say(f"[shell 30M {kernel}] setup {plan.info()['setup_ms']:.0f} ms")
+    rows = np.random.default_rng(101).choice(len(x), 512, replace=False)
+    _check_rows(plan, torch, x, q, rows, kernel, 1e-4, f"shell 30M {kernel} p10")
+
+
+_SHELL = {}
+
+
+def _shell30m():
+    if "x" not in _SHELL:
+        _say("[fullsize] building the 30M-point shell")
+        _SHELL["x"] = synth.surface_cloud(30000, 10_000_000, seed=13, shell_radius=200.0)
+    return _SHELL["x"]

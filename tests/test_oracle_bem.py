@@ -121,3 +121,26 @@ def test_born_and_kirkwood_first_order_convergence():
         order = math.log(e[0] / e[1]) / math.log(4.0)
         assert 0.85 < order < 1.15, (e, order)
     assert ek[1] / abs(ref_k) < 0.015
+
+
+def test_matvec_rows_equal_dense_rows():
+    """The row routine used for large meshes reproduces the dense operator."""
+    v, t = synth.octa_sphere(2, 4.0)
+    m = bem.make_mesh(v, t, 3)
+    A_ = bem.system(m, 4.0, 80.0, KAPPA)
+    x = np.random.default_rng(33).standard_normal(2 * len(t))
+    rows = np.array([0, 5, 17, 100])
+    got = bem.matvec_rows(m, rows, x, 4.0, 80.0, KAPPA)
+    ref = A_ @ x
+    np.testing.assert_allclose(got[:, 0], ref[rows], rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(got[:, 1], ref[len(t) + rows], rtol=1e-11, atol=1e-13)
+
+
+def test_reaction_potential_direct_equals_dense():
+    v, t = synth.octa_sphere(2, 4.0)
+    m = bem.make_mesh(v, t, 3)
+    rng = np.random.default_rng(34)
+    x = rng.standard_normal(2 * len(t))
+    qx = rng.uniform(-2.0, 2.0, (7, 3))
+    np.testing.assert_allclose(bem.reaction_potential_direct(m, x, qx), bem.reaction_potential(m, x, qx),
+                               rtol=1e-12, atol=1e-13)
