@@ -126,9 +126,13 @@ def _hull_tris(n: int):
     return p, t
 
 
-def _exposed_mesh(su: SphereUnion, density: float, seed: int, cell: float):
+def _exposed_mesh(su: SphereUnion, density: float, seed: int, cell: float, gap: float | None = None):
     """Triangulate each sphere with ~density * 4 pi r^2 hull triangles and drop
-    triangles whose centroid lies inside another sphere."""
+    triangles whose centroid lies inside another sphere (gap=None), or, with
+    gap = g, every triangle with a vertex closer than g mean edge lengths to
+    the inside of another sphere: the caps of two intersecting spheres then
+    stop short of their intersection curve, about g edge lengths apart,
+    instead of crossing each other there."""
     rng = np.random.default_rng(seed + 7919)
     m = len(su.radii)
     # spatial hash of sphere centres for the "inside another sphere" test
@@ -148,6 +152,9 @@ def _exposed_mesh(su: SphereUnion, density: float, seed: int, cell: float):
         v = (p @ rot.T) * r + su.centers[i]
         cen = v[t].mean(axis=1)
         keep = np.ones(len(t), dtype=bool)
+        if gap is not None:
+            e = v[t[:, 1]] - v[t[:, 0]]
+            margin = gap * float(np.mean(np.sqrt(np.sum(e * e, axis=1))))
         k0 = keys[i]
         for dx in (-1, 0, 1):
             for dy in (-1, 0, 1):
@@ -155,8 +162,12 @@ def _exposed_mesh(su: SphereUnion, density: float, seed: int, cell: float):
                     for j in buckets.get((k0[0] + dx, k0[1] + dy, k0[2] + dz), ()):
                         if j == i:
                             continue
-                        d2 = np.sum((cen - su.centers[j]) ** 2, axis=1)
-                        keep &= d2 >= su.radii[j] ** 2
+                        if gap is None:
+                            d2 = np.sum((cen - su.centers[j]) ** 2, axis=1)
+                            keep &= d2 >= su.radii[j] ** 2
+                        else:
+                            dv2 = np.sum((v - su.centers[j]) ** 2, axis=1)
+                            keep &= ~(dv2 < (su.radii[j] + margin) ** 2)[t].any(axis=1)
         t = t[keep]
         if len(t) == 0:
             continue
@@ -171,32 +182,38 @@ def _exposed_mesh(su: SphereUnion, density: float, seed: int, cell: float):
     return np.concatenate(vs), np.concatenate(ts)
 
 
-def sphere_union_mesh(su: SphereUnion, n_triangles: int, seed: int):
+def sphere_union_mesh(su: SphereUnion, n_triangles: int, seed: int, exact: bool = True,
+                      gap: float | None = None):
     """Exposed surface of a union of spheres with exactly `n_triangles`
     triangles (counter-clockwise seen from outside).  The per-sphere
     triangle density is raised by bisection until the exposed count reaches
     the target; the surplus is dropped in a seeded shuffle order (holes are
-    harmless for point-cloud workloads).  Returns (verts, tris int32)."""
+    harmless for point-cloud workloads).  exact=False keeps the whole
+    exposed surface of the final density instead (n_triangles to 1.02
+    n_triangles triangles, no holes).  gap: see _exposed_mesh (boundary-
+    element meshes use gap=0.5, so that no two triangles of different
+    spheres cross or nearly touch).  Returns (verts, tris int32)."""
     cell = 2.0 * float(su.radii.max())
     area = float(np.sum(4.0 * math.pi * su.radii ** 2))
     lo, hi = 0.5 * n_triangles / area, 0.5 * n_triangles / area
-    v, t = _exposed_mesh(su, hi, seed, cell)
+    v, t = _exposed_mesh(su, hi, seed, cell, gap)
     while len(t) < n_triangles:
         lo = hi
         hi *= 1.6
-        v, t = _exposed_mesh(su, hi, seed, cell)
+        v, t = _exposed_mesh(su, hi, seed, cell, gap)
     for _ in range(12):
         if len(t) <= n_triangles * 1.02:
             break
         mid = 0.5 * (lo + hi)
-        v2, t2 = _exposed_mesh(su, mid, seed, cell)
+        v2, t2 = _exposed_mesh(su, mid, seed, cell, gap)
         if len(t2) >= n_triangles:
             hi, v, t = mid, v2, t2
         else:
             lo = mid
-    rng = np.random.default_rng(seed + 104729)
-    sel = np.sort(rng.permutation(len(t))[:n_triangles])
-    t = t[sel]
+    if exact:
+        rng = np.random.default_rng(seed + 104729)
+        sel = np.sort(rng.permutation(len(t))[:n_triangles])
+        t = t[sel]
     used = np.unique(t)
     remap = -np.ones(len(v), dtype=np.int64)
     remap[used] = np.arange(len(used))
