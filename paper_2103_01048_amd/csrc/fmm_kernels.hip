@@ -217,17 +217,30 @@ int device_gather_points(const double *xyz, const int32_t *perm, int64_t n, cons
 // columns) is staged through LDS 64 k-values at a time.
 // Each wave owns RBW consecutive 16-row blocks and all four 16-column blocks.
 // ---------------------------------------------------------------------------
+// Workgroups are dealt to the eight XCDs round robin (workgroup b runs on XCD
+// b % 8), each with its own L2.  Task lists keep the columns that share a
+// matrix in consecutive tasks; mapping workgroup b to task
+// (b % 8) * per + b / 8 gives every XCD one contiguous run of tasks, so a
+// matrix is fetched into one L2 rather than into all eight.  The grid is
+// 8 * per workgroups; those past the last task return at once.
+__device__ inline int xcd_task() {
+  const int per = (int)(gridDim.x >> 3);
+  return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
+
 template <typename T, int RBW>
 __global__ __launch_bounds__(256) void k_gemm(const GemmTask *__restrict__ tasks, const T *__restrict__ pool,
                                               int64_t mat_stride, int S, int seg, int KQ, int ld, int nrb,
                                               int K, const int32_t *__restrict__ src,
                                               const int32_t *__restrict__ dst, const T *__restrict__ X,
-                                              T *__restrict__ Y, int ldy, int mode) {
+                                              T *__restrict__ Y, int ldy, int mode, int ntask) {
   // S segments of `seg` k-values per column (segment s of column c is row
   // src[c*S+s] of X, leading dimension ld); KQ: 16-wide k groups per stored
   // row block of A; K: k-values read; nrb: 16-row blocks computed.
   using V4 = typename Vec4<T>::type;
-  const GemmTask tk = tasks[blockIdx.x];
+  const int task = xcd_task();
+  if (task >= ntask) return;
+  const GemmTask tk = tasks[task];
   const int KQK = K >> 4;         // k-groups actually read
   const T *__restrict__ A = pool + (int64_t)tk.mat * mat_stride;
   __shared__ T Bs[64][GEMM_NT + 1];
@@ -347,8 +360,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf3(const GemmTask *__restrict__ t
                                                   int64_t mat_stride16, int KB, int ld, int nrb, int K,
                                                   const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
                                                   const float *__restrict__ X, float *__restrict__ Y, int ldy,
-                                                  int mode) {
-  const GemmTask tk = tasks[blockIdx.x];
+                                                  int mode, int ntask) {
+  const int task = xcd_task();
+  if (task >= ntask) return;
+  const GemmTask tk = tasks[task];
   const uint4 *__restrict__ A = pool + (int64_t)tk.mat * mat_stride16;
   __shared__ unsigned short Bh[GEMM_NT][64 + 8], Bl[GEMM_NT][64 + 8];
   __shared__ int32_t s_src[GEMM_NT];
@@ -783,12 +798,23 @@ __global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ 
   const int b = tgt[slot];
   const int p0 = off[slot], p1 = off[slot + 1];
   const int rq = rows >> 2, lq = ld >> 2, pq = ldp >> 2;
+  const V4 *__restrict__ pb = reinterpret_cast<const V4 *>(pairbuf);
   for (int e = threadIdx.x; e < nr * rq; e += 64) {
     const int r = e / rq, i = e - r * rq;
-    V4 acc = V4{0, 0, 0, 0};
-    for (int p = p0; p < p1; ++p)
-      acc += reinterpret_cast<const V4 *>(pairbuf)[((int64_t)pairs[p] * nr + r) * pq + i];
-    reinterpret_cast<V4 *>(y)[((int64_t)b * nr + r) * lq + i] = acc;
+    // four independent partial sums (pairs p0 + 4k + j go to sum j) keep
+    // four loads in flight; they are added in a fixed order
+    V4 a0 = V4{0, 0, 0, 0}, a1 = a0, a2 = a0, a3 = a0;
+    int p = p0;
+    for (; p + 4 <= p1; p += 4) {
+      a0 += pb[((int64_t)pairs[p] * nr + r) * pq + i];
+      a1 += pb[((int64_t)pairs[p + 1] * nr + r) * pq + i];
+      a2 += pb[((int64_t)pairs[p + 2] * nr + r) * pq + i];
+      a3 += pb[((int64_t)pairs[p + 3] * nr + r) * pq + i];
+    }
+    if (p < p1) a0 += pb[((int64_t)pairs[p] * nr + r) * pq + i];
+    if (p + 1 < p1) a1 += pb[((int64_t)pairs[p + 1] * nr + r) * pq + i];
+    if (p + 2 < p1) a2 += pb[((int64_t)pairs[p + 2] * nr + r) * pq + i];
+    reinterpret_cast<V4 *>(y)[((int64_t)b * nr + r) * lq + i] = (a0 + a1) + (a2 + a3);
   }
 }
 
@@ -801,17 +827,18 @@ static void launch_gemm_rbw(const GemmBatch &bt, const T *pool, int64_t mstride,
   const unsigned gy = (unsigned)((nrb + 4 * RBW - 1) / (4 * RBW));
   const int seg = bt.seg ? bt.seg : ld;
   const int kq = bt.kq_stride ? bt.kq_stride : ld / 16;
-  hipLaunchKernelGGL((k_gemm<T, RBW>), dim3(bt.ntask, gy), dim3(256), 0, s, bt.d_tasks, pool, mstride, bt.S, seg, kq,
-                     ld, nrb, bt.klen, bt.d_src, bt.d_dst, X, Y, bt.ldy ? bt.ldy : ld, bt.mode);
+  hipLaunchKernelGGL((k_gemm<T, RBW>), dim3(8 * ((bt.ntask + 7) / 8), gy), dim3(256), 0, s, bt.d_tasks, pool, mstride,
+                     bt.S, seg, kq, ld, nrb, bt.klen, bt.d_src, bt.d_dst, X, Y, bt.ldy ? bt.ldy : ld, bt.mode,
+                     bt.ntask);
 }
 
 template <int RBW>
 static void launch_bf3_rbw(fmm_plan *P, const GemmBatch &bt, int nrb, const float *X, float *Y, hipStream_t s) {
   const unsigned gy = (unsigned)((nrb + 4 * RBW - 1) / (4 * RBW));
   const int KB = P->bf_kb;
-  hipLaunchKernelGGL((k_gemm_bf3<RBW>), dim3(bt.ntask, gy), dim3(256), 0, s, bt.d_tasks, (const uint4 *)P->pool_bf,
-                     (int64_t)(P->ld / 16) * KB * 2 * 64, KB, P->ld, nrb, bt.klen, bt.d_src, bt.d_dst, X, Y,
-                     bt.ldy ? bt.ldy : P->ld, bt.mode);
+  hipLaunchKernelGGL((k_gemm_bf3<RBW>), dim3(8 * ((bt.ntask + 7) / 8), gy), dim3(256), 0, s, bt.d_tasks,
+                     (const uint4 *)P->pool_bf, (int64_t)(P->ld / 16) * KB * 2 * 64, KB, P->ld, nrb, bt.klen, bt.d_src,
+                     bt.d_dst, X, Y, bt.ldy ? bt.ldy : P->ld, bt.mode, bt.ntask);
 }
 
 template <typename T>
