@@ -4,11 +4,13 @@
 Workload: 393,216 points = 131,072 triangles x 3 quadrature-like points on
 the exposed surface of 200 seeded spheres (radii U[1.5, 2.0] A, centres in a
 40 A cube), densities N(0, 1), expansion order p = 8.  A step is one Laplace
-and one Yukawa (kappa = 0.125 1/A) fmm_eval with potential and gradient,
-inputs and outputs resident in HBM.  value = points / (t_Laplace + t_Yukawa)
-in Mpoints/s for the single-precision path (by default FP32 with the M2L
-contraction on bf16x3 MFMA); plain FP32 and the plain FP64 path are timed
-beside it on the same tree.
+and one Yukawa (kappa = 0.125 1/A) evaluation with potential and gradient,
+inputs and outputs resident in HBM, as one fmm_eval_pair call (the two
+kernels share the tree; their far-field passes overlap and one launch does
+the near field of both).  value = points / t_step in Mpoints/s for the
+single-precision path (by default FP32 with the M2L contraction on bf16x3
+MFMA); two separate fmm_eval calls, plain FP32 and the plain FP64 path are
+timed beside it on the same tree.
 
 The accuracy gate (relative L2 error <= 1e-4 of potential and gradient) and
 the CPU baseline both come from the FP64 direct sum over a seeded sample of
@@ -44,7 +46,11 @@ PEAK_HBM = 8.0e12
 #            grad (6)                                                   = 20
 #   Yukawa:  d (3), r2 (5), 1/r (1), r (1), -kappa r (1), exp (1), g (1),
 #            1 + kappa r (2), f (3), pot (2), f q (1), grad (6)         = 27
-FLOP_PER_PAIR = {"laplace": 20, "yukawa": 27}
+#   both kernels of one pair evaluation (shared d, r2, 1/r, 1/r^2):
+#            d (3), r2 (5), 1/r (1), 1/r^2 (1), 1/r^3 (1), r (1),
+#            -kappa r (1), exp (1), g (1), (1 + kappa r) g / r^2 (4),
+#            per kernel pot (2) + f q (1) + grad (6)                    = 37
+FLOP_PER_PAIR = {"laplace": 20, "yukawa": 27, "pair": 37}
 
 
 def measured_traffic(kernel: str, phase: str, precision: str):
@@ -54,12 +60,14 @@ def measured_traffic(kernel: str, phase: str, precision: str):
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_2103_01048_amd", "csrc", "fmm_kernels.hip")
-    if phase != "leaf" or precision == "fp64" or not os.path.exists(path):
+    names = {"leaf": f"void fmm::k_leaf_eval<float, 1, {1 if kernel == 'yukawa' else 0}>",
+             "near": "void fmm::k_near_pair<float, 1>", "far": "void fmm::k_far_pair<float, 1>"}
+    if phase not in names or precision == "fp64" or not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernels_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
-    name = f"void fmm::k_leaf_eval<float, 1, {1 if kernel == 'yukawa' else 0}>"
+    name = names[phase]
     t = rec["traffic"].get(name)
     if not t:
         return None
@@ -164,24 +172,31 @@ def main():
         run_batch(args)
         return
     import torch
-    from paper_2103_01048_amd import FMMPlan
+    from paper_2103_01048_amd import FMMPlan, eval_pair
 
     dev = torch.device("cuda:0")
     x, q = workload()
     n = len(x)
     xt = torch.tensor(x, dtype=torch.float64, device=dev)
 
-    def make(kernel, prec, ncrit):
-        return FMMPlan(xt, kernel=kernel, kappa=KAPPA, p=P_ORDER, ncrit=ncrit, precision=prec)
+    def make(prec, ncrit):
+        return {k: FMMPlan(xt, kernel=k, kappa=KAPPA, p=P_ORDER, ncrit=ncrit, precision=prec)
+                for k in ("laplace", "yukawa")}
 
-    def time_evals(plans, qd, steps, warmup, profile=None):
-        """Run `warmup` untimed then `steps` timed steps (one eval per plan per
-        step).  profile: None, or {plan key: phases to time with HIP events}."""
+    def step_pair(plans, qd):
+        eval_pair(plans["laplace"], plans["yukawa"], qd[plans["laplace"].dtype])
+
+    def step_separate(plans, qd):
+        for pl in plans.values():
+            pl.eval(qd[pl.dtype])
+
+    def time_steps(step, plans, qd, steps, warmup, profile=None):
+        """Run `warmup` untimed then `steps` timed steps.  profile: None, or
+        {plan key: phases to time with HIP events}."""
         for pl in plans.values():
             pl.set_profiling(False)
         for _ in range(warmup):
-            for pl in plans.values():
-                pl.eval(qd[pl.dtype])
+            step(plans, qd)
         torch.cuda.synchronize()
         if profile:
             for k, pl in plans.items():
@@ -189,8 +204,7 @@ def main():
                 pl.set_profiling(profile.get(k, False))
         t0 = time.perf_counter()
         for _ in range(steps):
-            for pl in plans.values():
-                pl.eval(qd[pl.dtype])
+            step(plans, qd)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = {k: pl.phase_times() for k, pl in plans.items()} if profile else None
@@ -209,57 +223,57 @@ def main():
     qd = {torch.float32: torch.tensor(q, dtype=torch.float32, device=dev),
           torch.float64: torch.tensor(q, dtype=torch.float64, device=dev)}
 
-    # ncrit: short sweep per kernel (setup excluded from every timing)
-    ncrit = {}
+    # ncrit: short sweep of the pair step (setup excluded from every timing)
     sweep = {}
-    for kern in ("laplace", "yukawa"):
-        if args.ncrit:
-            ncrit[kern] = args.ncrit
-            continue
+    if args.ncrit:
+        ncrit = args.ncrit
+    else:
         best = None
         for nc in (64, 128, 256):
-            pl = make(kern, args.precision, nc)
-            dt, _ = time_evals({kern: pl}, qd, 5, 2)
-            sweep[f"{kern}:{nc}"] = round(dt / 5 * 1e3, 3)
+            pls = make(args.precision, nc)
+            dt, _ = time_steps(step_pair, pls, qd, 5, 2)
+            sweep[str(nc)] = round(dt / 5 * 1e3, 3)
             if best is None or dt < best[0]:
                 best = (dt, nc)
-            del pl
-        ncrit[kern] = best[1]
-        print(f"# ncrit sweep {kern}: " + ", ".join(f"{k}={v} ms" for k, v in sweep.items() if k.startswith(kern)),
-              file=sys.stderr, flush=True)
+            del pls
+        ncrit = best[1]
+        print("# ncrit sweep: " + ", ".join(f"{k}={v} ms" for k, v in sweep.items()), file=sys.stderr, flush=True)
 
-    plans = {k: make(k, args.precision, ncrit[k]) for k in ("laplace", "yukawa")}
+    plans = make(args.precision, ncrit)
     infos = {k: pl.info() for k, pl in plans.items()}
     # untimed pass with every phase timed: phase breakdown and dominant kernel
-    _, prof_all = time_evals(plans, qd, 3, 1, profile={k: True for k in plans})
+    _, prof_all = time_steps(step_pair, plans, qd, 3, 1, profile={k: True for k in plans})
     tot = {}
     for k, ph in prof_all.items():
         for name, (ms, cnt) in ph.items():
             tot[(k, name)] = (ms, cnt)
     (dk, dname), _ = max(tot.items(), key=lambda kv: kv[1][0])
     # timed region: only the dominant kernel's launches carry HIP events
-    dt, prof = time_evals(plans, qd, args.steps, args.warmup, profile={dk: [dname]})
+    dt, prof = time_steps(step_pair, plans, qd, args.steps, args.warmup, profile={dk: [dname]})
     ms_step = dt / args.steps * 1e3
     value = n / (dt / args.steps) / 1e6
     dms, dcnt = prof[dk][dname]
 
-    # the other paths on the same points and ncrit: plain FP32 (when the
-    # headline is bf16x3) and the plain FP64 form
-    others = {}
+    # the same plans as two separate fmm_eval calls, then the other paths on
+    # the same points and ncrit: plain FP32 (when the headline is bf16x3)
+    # and the plain FP64 form
+    dts, _ = time_steps(step_separate, plans, qd, args.steps, 1)
+    others = {"separate_evals": {"value": round(n / (dts / args.steps) / 1e6, 3),
+                                 "ms_per_step": round(dts / args.steps * 1e3, 4)}}
     other_plans = {}
     if args.precision != "fp32":
-        other_plans["fp32"] = {k: make(k, "fp32", ncrit[k]) for k in ("laplace", "yukawa")}
-    other_plans["fp64"] = {k: make(k, "fp64", ncrit[k]) for k in ("laplace", "yukawa")}
+        other_plans["fp32"] = make("fp32", ncrit)
+    other_plans["fp64"] = make("fp64", ncrit)
     for tag, pls in other_plans.items():
         st = args.fp64_steps if tag == "fp64" else args.steps
-        dto, _ = time_evals(pls, qd, st, 1)
+        dto, _ = time_steps(step_pair, pls, qd, st, 1)
         others[tag] = {"value": round(n / (dto / st) / 1e6, 3), "ms_per_step": round(dto / st * 1e3, 4)}
 
     # outputs for the accuracy gate
     outs = {}
     for tag, pls in [(args.precision, plans)] + list(other_plans.items()):
-        for k, pl in pls.items():
-            pot, grad = pl.eval(qd[pl.dtype])
+        (pa, ga), (pb, gb) = eval_pair(pls["laplace"], pls["yukawa"], qd[pls["laplace"].dtype])
+        for k, (pot, grad) in (("laplace", (pa, ga)), ("yukawa", (pb, gb))):
             outs[(tag, k)] = (pot.double().cpu().numpy(), grad.double().cpu().numpy())
     torch.cuda.synchronize()
 
@@ -269,8 +283,11 @@ def main():
     if dname == "m2l":
         flops = 2.0 * inf["n_v_pairs"] * inf["rank_up"] * inf["rank_down"]
         roof = {"bound": "mfma", "peak": PEAK_MFMA[args.precision], "unit": "TFLOP/s"}
-    elif dname == "leaf":
-        flops = FLOP_PER_PAIR[dk] * (inf["n_p2p_interactions"] + inf["n_far_interactions"])
+    elif dname in ("leaf", "near", "far"):
+        per = FLOP_PER_PAIR[dk] if dname == "leaf" else FLOP_PER_PAIR["pair"]
+        pairs = {"leaf": inf["n_p2p_interactions"] + inf["n_far_interactions"],
+                 "near": inf["n_p2p_interactions"], "far": inf["n_far_interactions"]}[dname]
+        flops = float(per * pairs)
         roof = {"bound": "alu", "peak": PEAK_VALU_FP32, "unit": "TFLOP/s"}
     else:
         flops = float("nan")
@@ -282,7 +299,6 @@ def main():
                 "peak": round(roof["peak"] / 1e12, 1), "unit": roof["unit"],
                 "frac": round(achieved / roof["peak"], 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_launch": flops}
-
     # CPU baseline (FP64 direct sum oracle) on a bounded sample of target rows;
     # the same sums gate the accuracy of the GPU outputs
     cpu = None
@@ -321,7 +337,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "sphere-union surface, 200 spheres, 131072 triangles x 3 points = 393216 points; "
-                               "Laplace + Yukawa (kappa 0.125) fmm_eval, potential + gradient, 1 column",
+                               "Laplace + Yukawa (kappa 0.125) fmm_eval_pair, potential + gradient, 1 column",
                    "n_points": n, "p": P_ORDER, "ncrit": ncrit, "precision": args.precision},
         "roofline": roofline, "cpu_baseline": cpu, "accuracy_gate_met": bool(errors) and all(
             v["pot"] <= 1e-4 and v["grad"] <= 1e-4 for kk, v in errors.items() if kk.startswith(args.precision)),

@@ -45,10 +45,10 @@ enum { FMM_LAPLACE = 0, FMM_YUKAWA = 1 };
  *   FMM_FP64        every stage in double precision (P2P on FP64 VALU,
  *                   translations on FP64 MFMA)
  *   FMM_FP32        single precision; translations on FP32 MFMA
- *   FMM_FP32_BF16X3 single precision; the dense translations (M2L, UC2E,
- *                   DC2E, M2M, L2L) on bf16 MFMA with each FP32 operand
+ *   FMM_FP32_BF16X3 single precision; the M2L translations (the largest
+ *                   dense contraction) on bf16 MFMA with each FP32 operand
  *                   split into a bf16 high and low part (three products,
- *                   FP32 accumulation)
+ *                   FP32 accumulation), the other translations on FP32 MFMA
  * Densities, potentials and gradients are double for FMM_FP64, float
  * otherwise. */
 enum { FMM_FP64 = 0, FMM_FP32 = 1, FMM_FP32_BF16X3 = 2 };
@@ -106,6 +106,22 @@ int fmm_setup_batch(const double *xyz_dev, const int64_t *offsets, int nmol, int
  * larger nrhs cannot be allocated; FMM_EHIP for a failed launch. */
 int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *grad_dev,
              fmm_stream_t stream);
+
+/* Evaluate two plans on the same densities: the Laplace and the Yukawa
+ * potentials that the direct formulation's operators need for one input
+ * (Methods, eq:direct and eq:bempp_fmm_matvec).  Results are those of
+ * fmm_eval(plan_a, ...) and fmm_eval(plan_b, ...), with the same layouts;
+ * grad_a_dev / grad_b_dev may be NULL.  When plan_a is a Laplace plan and
+ * plan_b a Yukawa plan built from the same points (and batch offsets) with
+ * the same p, ncrit and precision, the two share one tree: their far-field
+ * passes run concurrently on two internal streams (default priority) while
+ * the near field of both kernels runs on `stream` in one launch that
+ * computes each pair distance once; otherwise the two evaluations run one
+ * after the other on `stream`.  Asynchronous on `stream` (the internal
+ * streams are joined back into it).  Errors: as fmm_eval; FMM_EINVAL when
+ * the plans differ in point count or precision. */
+int fmm_eval_pair(fmm_plan *plan_a, fmm_plan *plan_b, const void *q_dev, int nrhs, void *pot_a_dev,
+                  void *grad_a_dev, void *pot_b_dev, void *grad_b_dev, fmm_stream_t stream);
 
 /* Adjoint of fmm_eval for a loss L(pot) with upstream gradient gbar_dev =
  * dL/dpot (nrhs x n, same type and layout as pot).  Because the kernel is
@@ -177,8 +193,10 @@ enum {
   FMM_PHASE_L2L = 7,     /* parent downward density -> child check (MFMA) */
   FMM_PHASE_DC2E = 8,    /* downward check -> equivalent (MFMA) */
   FMM_PHASE_LEAF = 9,    /* P2P + M2P + L2P at the leaves, unpermute, 1/(4 pi) */
-  FMM_PHASE_COUNT = 10,
-  FMM_PHASE_ALL = 0x3ff
+  FMM_PHASE_NEAR = 10,   /* fmm_eval_pair: P2P of both kernels (first plan's timer) */
+  FMM_PHASE_FAR = 11,    /* fmm_eval_pair: M2P + L2P of both kernels, unpermute */
+  FMM_PHASE_COUNT = 12,
+  FMM_PHASE_ALL = 0xfff
 };
 int fmm_set_profiling(fmm_plan *plan, int enable);
 int fmm_get_phase_times(fmm_plan *plan, double *ms, int64_t *launches, int nphase);

@@ -14,7 +14,7 @@ FMM_LAPLACE, FMM_YUKAWA = 0, 1
 FMM_FP64, FMM_FP32, FMM_FP32_BF16X3 = 0, 1, 2
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOTCONV, FMM_EBREAKDOWN = 0, -1, -2, -3, -4, -5
 
-PHASES = ["permute", "p2m", "uc2e", "m2m", "p2l", "m2l", "m2l_sum", "l2l", "dc2e", "leaf"]
+PHASES = ["permute", "p2m", "uc2e", "m2m", "p2l", "m2l", "m2l_sum", "l2l", "dc2e", "leaf", "near", "far"]
 
 STATUS_NAMES = {0: "FMM_OK", -1: "FMM_EINVAL", -2: "FMM_ENOMEM", -3: "FMM_EHIP", -4: "FMM_ENOTCONV",
                 -5: "FMM_EBREAKDOWN"}
@@ -47,6 +47,7 @@ P = ctypes.POINTER
 SIGNATURES = {
     "fmm_setup": (i32, [vp, i64, i32, dbl, i32, i32, i32, vp, P(vp)]),
     "fmm_eval": (i32, [vp, vp, i32, vp, vp, vp]),
+    "fmm_eval_pair": (i32, [vp, vp, vp, i32, vp, vp, vp, vp, vp]),
     "fmm_setup_batch": (i32, [vp, vp, i32, i32, dbl, i32, i32, i32, vp, P(vp)]),
     "fmm_info": (i32, [vp, P(FmmInfo)]),
     "fmm_get_tree": (i32, [vp] + [vp] * 11),

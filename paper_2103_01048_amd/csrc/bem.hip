@@ -607,8 +607,8 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
                        (float *)op->q4);
   }
   FMM_HIP_TRY(hipGetLastError());
-  if ((rc = fmm::eval_dispatch(op->fl, op->q4, 4, op->potl, op->gradl, s))) return rc;
-  if ((rc = fmm::eval_dispatch(op->fy, op->q4, 4, op->poty, op->grady, s))) return rc;
+  // both kernels on the same four columns: one tree, one near-field launch
+  if ((rc = fmm_eval_pair(op->fl, op->fy, op->q4, 4, op->potl, op->gradl, op->poty, op->grady, s))) return rc;
   if (op->precision == FMM_FP64) {
     hipLaunchKernelGGL(k_bem_p2<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const double *)op->potl,
                        (const double *)op->gradl, (const double *)op->poty, (const double *)op->grady, op->d_qw,

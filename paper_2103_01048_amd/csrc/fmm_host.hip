@@ -40,6 +40,8 @@ int device_morton_sort(const double *xyz, int64_t n, const std::vector<int64_t> 
 int device_gather_points(const double *xyz, const int32_t *perm, int64_t n, const double shift[3], int prec,
                          void *pts, hipStream_t s);
 int eval_dispatch(fmm_plan *P, const void *q, int nrhs, void *pot, void *grad, hipStream_t s);
+int eval_pair_dispatch(fmm_plan *A, fmm_plan *B, const void *q, int nrhs, void *pot_a, void *grad_a, void *pot_b,
+                       void *grad_b, hipStream_t s);
 int adjoint_combine(fmm_plan *P, int nrhs, const void *q, const void *gbar, const void *gphi, const void *gpsi,
                     void *dx, hipStream_t s);
 
@@ -1016,6 +1018,48 @@ int ensure_lists(fmm_plan *P, int nr) {
   return FMM_OK;
 }
 
+// FNV-1a over everything the leaf items depend on: point order, molecule
+// ranges, boxes, surface size and the item lists.  Two plans with equal
+// fingerprints share one tree (their near ranges and items coincide).
+static uint64_t tree_fingerprint(const fmm_plan *P) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void *data, size_t bytes) {
+    const unsigned char *c = (const unsigned char *)data;
+    for (size_t i = 0; i < bytes; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  };
+  mix(&P->n, sizeof(P->n));
+  mix(&P->nsurf, sizeof(P->nsurf));
+  mix(&P->ncrit, sizeof(P->ncrit));
+  mix(P->perm.data(), P->perm.size() * sizeof(int64_t));
+  mix(P->mol_off.data(), P->mol_off.size() * sizeof(int64_t));
+  mix(P->begin.data(), P->begin.size() * sizeof(int64_t));
+  mix(P->end.data(), P->end.size() * sizeof(int64_t));
+  mix(P->anchor.data(), P->anchor.size() * sizeof(int64_t));
+  mix(&P->dt.nitems, sizeof(P->dt.nitems));
+  mix(&P->dt.nparts, sizeof(P->dt.nparts));
+  mix(&P->dt.nsplit, sizeof(P->dt.nsplit));
+  return h;
+}
+
+// Resources of a pair evaluation (A: Laplace half, B: Yukawa half): one side
+// stream per plan (default priority), A's fork and join events, B's join
+// event, and A's buffer of near-field running sums for nr columns.
+int ensure_pair(fmm_plan *A, fmm_plan *B, int nr) {
+  for (fmm_plan *P : {A, B}) {
+    if (!P->aux) FMM_HIP_TRY(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
+    if (!P->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+    if (!P->ev_join) FMM_HIP_TRY(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+  }
+  const size_t es = A->precision == FMM_FP64 ? 8 : 4;
+  const size_t need = std::max<size_t>(1, (size_t)A->dt.nitems) * 2 * nr * 4 * 64 * es;
+  if (A->pair_acc_bytes < need) {
+    int rc;
+    if ((rc = dev_alloc(A, &A->pair_acc, need))) return rc;
+    A->pair_acc_bytes = need;
+  }
+  return FMM_OK;
+}
+
 int ensure_work(fmm_plan *P, int nr) {
   if (P->work_nr >= nr) return FMM_OK;
   const size_t es = P->precision == FMM_FP64 ? 8 : 4;
@@ -1154,6 +1198,7 @@ static int setup_common(const double *xyz_dev, const std::vector<int64_t> &off, 
     }
     if (rc) break;
     if ((rc = upload_lists(P))) break;
+    P->tree_hash = tree_fingerprint(P);
     rc = precision == FMM_FP64 ? precompute_typed<double>(P) : precompute_typed<float>(P);
     if (rc) break;
     hipError_t e = hipStreamSynchronize(s);
@@ -1188,6 +1233,29 @@ int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *g
   if (plan->n == 0) return FMM_OK;
   if (!q_dev || !pot_dev) { set_error("fmm_eval: null buffer"); return FMM_EINVAL; }
   return eval_dispatch(plan, q_dev, nrhs, pot_dev, grad_dev, (hipStream_t)stream);
+}
+
+int fmm_eval_pair(fmm_plan *A, fmm_plan *B, const void *q_dev, int nrhs, void *pot_a, void *grad_a, void *pot_b,
+                  void *grad_b, fmm_stream_t stream) {
+  if (!A || !B) { set_error("fmm_eval_pair: plan is NULL"); return FMM_EINVAL; }
+  if (A == B) { set_error("fmm_eval_pair: the two plans must differ"); return FMM_EINVAL; }
+  if (A->n != B->n || (A->precision == FMM_FP64) != (B->precision == FMM_FP64)) {
+    set_error("fmm_eval_pair: plans differ in point count or precision");
+    return FMM_EINVAL;
+  }
+  if (nrhs < 1 || nrhs > 64) { set_error("fmm_eval_pair: nrhs must be in [1, 64]"); return FMM_EINVAL; }
+  if (A->n == 0) return FMM_OK;
+  if (!q_dev || !pot_a || !pot_b) { set_error("fmm_eval_pair: null buffer"); return FMM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  const bool shared = A->kernel == FMM_LAPLACE && B->kernel == FMM_YUKAWA && A->tree_hash == B->tree_hash &&
+                      A->precision == B->precision && A->nsurf == B->nsurf && A->ncrit == B->ncrit &&
+                      A->dt.nitems == B->dt.nitems && A->dt.nparts == B->dt.nparts;
+  if (!shared) {
+    int rc;
+    if ((rc = eval_dispatch(A, q_dev, nrhs, pot_a, grad_a, s))) return rc;
+    return eval_dispatch(B, q_dev, nrhs, pot_b, grad_b, s);
+  }
+  return eval_pair_dispatch(A, B, q_dev, nrhs, pot_a, grad_a, pot_b, grad_b, s);
 }
 
 int fmm_adjoint(fmm_plan *P, const void *q, const void *gbar, const void *gfwd, int nrhs, void *dq, void *dxyz,
@@ -1297,6 +1365,12 @@ void fmm_free(fmm_plan *P) {
   if (!P) return;
   for (auto &pe : P->prof_events) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
   for (hipEvent_t e : P->event_pool) (void)hipEventDestroy(e);
+  if (P->aux) {
+    (void)hipStreamSynchronize(P->aux);
+    (void)hipStreamDestroy(P->aux);
+  }
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   for (void *p : P->allocs) (void)hipFree(p);
   delete P;
 }

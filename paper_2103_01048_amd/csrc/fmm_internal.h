@@ -168,6 +168,13 @@ struct fmm_plan {
   int profiling = 0;               // bit k set: time phase k
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_events;
   std::vector<hipEvent_t> event_pool;
+  // pair evaluation (this plan as the Laplace half): side stream, fork and
+  // join events, and the near-field running sums of both kernels
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  void *pair_acc = nullptr;
+  size_t pair_acc_bytes = 0;
+  uint64_t tree_hash = 0;           // fingerprint of points, boxes and leaf items
   void *adj = nullptr;              // adjoint scratch: psi and grad psi
   size_t adj_bytes = 0;
   int64_t device_bytes = 0;

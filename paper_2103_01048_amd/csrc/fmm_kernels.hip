@@ -699,6 +699,257 @@ __global__ __launch_bounds__(64) void k_leaf_parts(const int32_t *__restrict__ t
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pair evaluation: a Laplace and a Yukawa plan on one tree (same points,
+// ncrit and p).  One distance, one reciprocal square root and one set of
+// source loads serve both kernels.  The leaf work is split in two launches
+// over the same items: the near field (point ranges), which needs only the
+// densities and so runs while the two kernels' far-field passes run on other
+// streams, and the far field (W-list and own downward surfaces) after them.
+// The near launch leaves every lane's running sums in `acc`
+// ([item][kernel][column][pot, gx, gy, gz][lane]); the far launch continues
+// them, so each sum is accumulated in the same order as by k_leaf_eval.
+// ---------------------------------------------------------------------------
+template <typename T, bool CHECK, int NR>
+__device__ __forceinline__ void leaf_pair_ly(T xi, T yi, T zi, T sx, T sy, T sz, const T (&qa)[NR], const T (&qb)[NR],
+                                             T kappa, T kl2, T (&pa)[NR], T (&xa)[NR], T (&ya)[NR], T (&za)[NR],
+                                             T (&pb)[NR], T (&xb)[NR], T (&yb)[NR], T (&zb)[NR]) {
+  const T dx = xi - sx, dy = yi - sy, dz = zi - sz;
+  const T r2 = dx * dx + dy * dy + dz * dz;
+  T invr = dev_rsqrt(r2);
+  if (CHECK) invr = r2 > (T)0 ? invr : (T)0;
+  const T i2 = invr * invr;
+  const T fl = i2 * invr;                       // Laplace: g = 1/r, f = 1/r^3
+  const T r = r2 * invr;
+  const T gy = dev_exp2(-kl2 * r) * invr;       // Yukawa: g = e^{-kappa r}/r
+  const T fy = ((T)1 + kappa * r) * gy * i2;    //         f = (1 + kappa r) g / r^2
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    pa[c] += invr * qa[c];
+    const T fqa = fl * qa[c];
+    xa[c] -= fqa * dx;
+    ya[c] -= fqa * dy;
+    za[c] -= fqa * dz;
+    pb[c] += gy * qb[c];
+    const T fqb = fy * qb[c];
+    xb[c] -= fqb * dx;
+    yb[c] -= fqb * dy;
+    zb[c] -= fqb * dz;
+  }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_near_pair(
+    const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts,
+    const T *__restrict__ qs, int64_t N, const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end,
+    const int32_t *__restrict__ near_off, const int32_t *__restrict__ near_rng, T *__restrict__ acc, T kappa,
+    int nitems) {
+  using V4 = typename Vec4<T>::type;
+  const V4 *__restrict__ p4 = reinterpret_cast<const V4 *>(pts);
+  // one wave per item (the loop also serves a grid smaller than the item
+  // count: waves then take items round robin, longest first)
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int slot = items[4 * item];
+    const int code = items[4 * item + 1];
+    const int split = code >> 24;
+    const int b = leaves[slot];
+    const int lb = box_begin[b], le = box_end[b];
+    const int tb = lb + (code & 0xffffff);
+    const int lane = threadIdx.x;
+    const int half = split == 2 ? (lane >> 5) : 0;
+    const int tl = split == 2 ? (lane & 31) : lane;
+    const int m = min(64 / split, le - tb);
+    const bool active = tl < m;
+    const V4 xv = p4[tb + (active ? tl : 0)];
+    const T xi = xv[0], yi = xv[1], zi = xv[2];
+    const T kl2 = kappa * (T)1.4426950408889634;  // kappa * log2(e)
+    T pa[NR], xa[NR], ya[NR], za[NR], pb[NR], xb[NR], yb[NR], zb[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) pa[c] = xa[c] = ya[c] = za[c] = pb[c] = xb[c] = yb[c] = zb[c] = (T)0;
+    const int u1 = near_off[item + 1];
+    for (int u = near_off[item]; u < u1; ++u) {
+      const int j0 = near_rng[2 * u], j1 = near_rng[2 * u + 1];
+      const bool self = j0 < le && lb < j1;
+      if (split == 1) {
+        auto body = [&](int j, auto chk) {
+          const V4 sp = p4[j];
+          T qv[NR];
+          if (NR == 1) qv[0] = sp[3];
+          else {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) qv[c] = qs[(int64_t)c * N + j];
+          }
+          leaf_pair_ly<T, decltype(chk)::value, NR>(xi, yi, zi, sp[0], sp[1], sp[2], qv, qv, kappa, kl2, pa, xa, ya, za,
+                                                     pb, xb, yb, zb);
+        };
+        if (self) {
+#pragma unroll 4
+          for (int j = j0; j < j1; ++j) body(j, std::true_type());
+        } else {
+#pragma unroll 8
+          for (int j = j0; j < j1; ++j) body(j, std::false_type());
+        }
+      } else {
+        auto body = [&](int j, auto chk) {
+          const int jj = j + half;
+          const bool ok = jj < j1;
+          const V4 sp = p4[ok ? jj : j];
+          T qv[NR];
+          if (NR == 1) qv[0] = ok ? sp[3] : (T)0;
+          else {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) qv[c] = ok ? qs[(int64_t)c * N + jj] : (T)0;
+          }
+          leaf_pair_ly<T, decltype(chk)::value, NR>(xi, yi, zi, sp[0], sp[1], sp[2], qv, qv, kappa, kl2, pa, xa, ya, za,
+                                                     pb, xb, yb, zb);
+        };
+        if (self) {
+#pragma unroll 2
+          for (int j = j0; j < j1; j += 2) body(j, std::true_type());
+        } else {
+#pragma unroll 4
+          for (int j = j0; j < j1; j += 2) body(j, std::false_type());
+        }
+      }
+    }
+    T *a = acc + (int64_t)item * 2 * NR * 4 * 64;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      a[(c * 4 + 0) * 64 + lane] = pa[c];
+      a[(c * 4 + 1) * 64 + lane] = xa[c];
+      a[(c * 4 + 2) * 64 + lane] = ya[c];
+      a[(c * 4 + 3) * 64 + lane] = za[c];
+      a[((NR + c) * 4 + 0) * 64 + lane] = pb[c];
+      a[((NR + c) * 4 + 1) * 64 + lane] = xb[c];
+      a[((NR + c) * 4 + 2) * 64 + lane] = yb[c];
+      a[((NR + c) * 4 + 3) * 64 + lane] = zb[c];
+    }
+  }
+}
+
+template <typename T, int NR>
+__device__ __forceinline__ void leaf_store(int part, int half, bool active, int tl, int tb, T *__restrict__ parts,
+                                           const int32_t *__restrict__ perm, int64_t N, T *__restrict__ pot,
+                                           T *__restrict__ grad, T scale, const T (&ap)[NR], const T (&agx)[NR],
+                                           const T (&agy)[NR], const T (&agz)[NR]) {
+  if (part >= 0) {
+    if (half == 0) {
+      T *pp = parts + (int64_t)part * NR * 4 * 64;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        pp[(c * 4 + 0) * 64 + tl] = ap[c];
+        pp[(c * 4 + 1) * 64 + tl] = agx[c];
+        pp[(c * 4 + 2) * 64 + tl] = agy[c];
+        pp[(c * 4 + 3) * 64 + tl] = agz[c];
+      }
+    }
+    return;
+  }
+  if (active && half == 0) {
+    const int64_t o = perm[tb + tl];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      pot[(int64_t)c * N + o] = ap[c] * scale;
+      if (grad) {
+        T *gp = grad + ((int64_t)c * N + o) * 3;
+        gp[0] = agx[c] * scale;
+        gp[1] = agy[c] * scale;
+        gp[2] = agz[c] * scale;
+      }
+    }
+  }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_far_pair(
+    const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts, int64_t N,
+    const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end, const T *__restrict__ box_geom,
+    const T *__restrict__ surf, int nsurf, int ld, const int32_t *__restrict__ far_off,
+    const int32_t *__restrict__ far_idx, const T *__restrict__ acc, const T *__restrict__ equ_a,
+    const T *__restrict__ eqd_a, const T *__restrict__ equ_b, const T *__restrict__ eqd_b, T *__restrict__ parts_a,
+    T *__restrict__ parts_b, const int32_t *__restrict__ perm, T *__restrict__ pot_a, T *__restrict__ grad_a,
+    T *__restrict__ pot_b, T *__restrict__ grad_b, T kappa, T scale) {
+  using V4 = typename Vec4<T>::type;
+  const V4 *__restrict__ p4 = reinterpret_cast<const V4 *>(pts);
+  const V4 *__restrict__ s4 = reinterpret_cast<const V4 *>(surf);
+  const int item = blockIdx.x;
+  const int slot = items[4 * item];
+  const int code = items[4 * item + 1];
+  const int part = items[4 * item + 2];
+  const int split = code >> 24;
+  const int b = leaves[slot];
+  const int lb = box_begin[b], le = box_end[b];
+  const int tb = lb + (code & 0xffffff);
+  const int lane = threadIdx.x;
+  const int half = split == 2 ? (lane >> 5) : 0;
+  const int tl = split == 2 ? (lane & 31) : lane;
+  const int m = min(64 / split, le - tb);
+  const bool active = tl < m;
+  const V4 xv = p4[tb + (active ? tl : 0)];
+  const T xi = xv[0], yi = xv[1], zi = xv[2];
+  const T kl2 = kappa * (T)1.4426950408889634;
+  T pa[NR], xa[NR], ya[NR], za[NR], pb[NR], xb[NR], yb[NR], zb[NR];
+  const T *a = acc + (int64_t)item * 2 * NR * 4 * 64;
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    pa[c] = a[(c * 4 + 0) * 64 + lane];
+    xa[c] = a[(c * 4 + 1) * 64 + lane];
+    ya[c] = a[(c * 4 + 2) * 64 + lane];
+    za[c] = a[(c * 4 + 3) * 64 + lane];
+    pb[c] = a[((NR + c) * 4 + 0) * 64 + lane];
+    xb[c] = a[((NR + c) * 4 + 1) * 64 + lane];
+    yb[c] = a[((NR + c) * 4 + 2) * 64 + lane];
+    zb[c] = a[((NR + c) * 4 + 3) * 64 + lane];
+  }
+  const int f1 = far_off[item + 1];
+  for (int k = far_off[item]; k < f1; ++k) {
+    const int fe = far_idx[k];
+    const bool own = (fe >> 30) & 1;
+    const int bx = fe & 0x3fffffff;
+    const T cx = box_geom[bx * 4 + 0], cy = box_geom[bx * 4 + 1], cz = box_geom[bx * 4 + 2];
+    const T rr = box_geom[bx * 4 + 3] * (own ? (T)ALPHA_DE : (T)ALPHA_UE);
+    const T *__restrict__ da = (own ? eqd_a : equ_a) + (int64_t)bx * NR * ld;
+    const T *__restrict__ db = (own ? eqd_b : equ_b) + (int64_t)bx * NR * ld;
+    if (split == 1) {
+#pragma unroll 4
+      for (int j = 0; j < nsurf; ++j) {
+        const V4 g = s4[j];
+        T qa[NR], qb[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) { qa[c] = da[(int64_t)c * ld + j]; qb[c] = db[(int64_t)c * ld + j]; }
+        leaf_pair_ly<T, false, NR>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qa, qb, kappa, kl2,
+                                   pa, xa, ya, za, pb, xb, yb, zb);
+      }
+    } else {
+#pragma unroll 2
+      for (int j = 0; j < nsurf; j += 2) {
+        const int jj = j + half;
+        const bool ok = jj < nsurf;
+        const V4 g = s4[ok ? jj : j];
+        T qa[NR], qb[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          qa[c] = ok ? da[(int64_t)c * ld + jj] : (T)0;
+          qb[c] = ok ? db[(int64_t)c * ld + jj] : (T)0;
+        }
+        leaf_pair_ly<T, false, NR>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qa, qb, kappa, kl2,
+                                   pa, xa, ya, za, pb, xb, yb, zb);
+      }
+    }
+  }
+  if (split == 2) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      pa[c] += __shfl_xor(pa[c], 32); xa[c] += __shfl_xor(xa[c], 32);
+      ya[c] += __shfl_xor(ya[c], 32); za[c] += __shfl_xor(za[c], 32);
+      pb[c] += __shfl_xor(pb[c], 32); xb[c] += __shfl_xor(xb[c], 32);
+      yb[c] += __shfl_xor(yb[c], 32); zb[c] += __shfl_xor(zb[c], 32);
+    }
+  }
+  leaf_store<T, NR>(part, half, active, tl, tb, parts_a, perm, N, pot_a, grad_a, scale, pa, xa, ya, za);
+  leaf_store<T, NR>(part, half, active, tl, tb, parts_b, perm, N, pot_b, grad_b, scale, pb, xb, yb, zb);
+}
+
 // Surface kernel: potential at the surface points (radius `alpha` * h) of
 // box tbox[slot] from the points of the leaves src_idx[src_off[slot] ..].
 // Y[(box*NR + r)*ld + i] (mode 0: store, 1: add).
@@ -888,86 +1139,108 @@ static int launch_gemm(fmm_plan *P, const GemmBatch &bt, const T *X, T *Y, hipSt
 int ensure_lists(fmm_plan *P, int nr);   // host planner
 int ensure_work(fmm_plan *P, int nr);
 
+// Densities into Morton order (and, for one column, into the points' fourth
+// slot).
+template <typename T, int NR>
+static int eval_permute(fmm_plan *P, const T *q, hipStream_t s) {
+  const DevTree &D = P->dt;
+  const int64_t N = P->n;
+  hipEvent_t ev = prof_begin(P, FMM_PHASE_PERMUTE, s);
+  hipLaunchKernelGGL(k_permute<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, q, D.perm, N, NR, (T *)P->qs,
+                     (T *)D.pts);
+  FMM_HIP_TRY(hipGetLastError());
+  prof_end(P, FMM_PHASE_PERMUTE, ev, s);
+  return FMM_OK;
+}
+
+// Far-field passes: P2M, upward pass, P2L, M2L, downward pass, ending with
+// the downward equivalent densities of every box at level >= 2.
 template <typename T, int NR, int KERN>
-static int eval_chunk(fmm_plan *P, const T *q, T *pot, T *grad, hipStream_t s) {
+static int eval_passes(fmm_plan *P, hipStream_t s) {
   const DevTree &D = P->dt;
   const int64_t N = P->n;
   const int ld = P->ld;
   const PassLists &L = P->lists_by_nr[NR];
   T *qs = (T *)P->qs, *equ = (T *)P->equ, *chk = (T *)P->chk, *eqd = (T *)P->eqd, *chku = (T *)P->chku,
     *cu = (T *)P->cu, *yd = (T *)P->yd;
-  (void)equ;
   const T kappa = (T)P->kappa;
   int rc;
-  hipEvent_t ev = prof_begin(P, FMM_PHASE_PERMUTE, s);
-  hipLaunchKernelGGL(k_permute<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, q, D.perm, N, NR, qs,
-                     (T *)D.pts);
+  hipEvent_t ev;
+  if (D.maxlevel < 2) return FMM_OK;
+  // P2M: upward check potentials of the leaves at level >= 2
+  ev = prof_begin(P, FMM_PHASE_P2M, s);
+  if (P->p2m_count > 0)
+    hipLaunchKernelGGL((k_surf_eval<T, NR, KERN>), dim3(P->p2m_count), dim3(256), 0, s, P->d_p2m_box,
+                       P->d_p2m_off, P->d_p2m_box, (const T *)D.pts, qs, N, D.box_begin, D.box_end,
+                       (const T *)D.box_geom, (const T *)P->surf, P->nsurf, ld, (T)ALPHA_UC, chku, 0, kappa);
   FMM_HIP_TRY(hipGetLastError());
-  prof_end(P, FMM_PHASE_PERMUTE, ev, s);
-  const bool far = D.maxlevel >= 2;
-  if (far) {
-    // P2M: upward check potentials of the leaves at level >= 2
-    ev = prof_begin(P, FMM_PHASE_P2M, s);
-    if (P->p2m_count > 0)
-      hipLaunchKernelGGL((k_surf_eval<T, NR, KERN>), dim3(P->p2m_count), dim3(256), 0, s, P->d_p2m_box,
-                         P->d_p2m_off, P->d_p2m_box, (const T *)D.pts, qs, N, D.box_begin, D.box_end,
-                         (const T *)D.box_geom, (const T *)P->surf, P->nsurf, ld, (T)ALPHA_UC, chku, 0, kappa);
+  prof_end(P, FMM_PHASE_P2M, ev, s);
+  // upward pass in singular coordinates: every leaf's U^T projection,
+  // then M2M slots and per-parent sums, deepest level first
+  ev = prof_begin(P, FMM_PHASE_UC2E, s);
+  if ((rc = launch_gemm<T>(P, L.ut_u_all, chku, cu, s))) return rc;
+  prof_end(P, FMM_PHASE_UC2E, ev, s);
+  for (int l = D.maxlevel - 1; l >= 2; --l) {
+    if (!L.m2m[l].ntask) continue;
+    ev = prof_begin(P, FMM_PHASE_M2M, s);
+    if ((rc = launch_gemm<T>(P, L.m2m[l], cu, (T *)P->mslot, s))) return rc;
+    hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.m2m_n[l]), dim3(64), 0, s, D.m2m_tgt[l], D.m2m_off[l], D.m2m_kid[l],
+                       (const T *)P->mslot, cu, NR, ld, ld, L.m2m[l].nrb * 16);
     FMM_HIP_TRY(hipGetLastError());
-    prof_end(P, FMM_PHASE_P2M, ev, s);
-    // upward pass in singular coordinates: every leaf's U^T projection,
-    // then M2M slots and per-parent sums, deepest level first
-    ev = prof_begin(P, FMM_PHASE_UC2E, s);
-    if ((rc = launch_gemm<T>(P, L.ut_u_all, chku, cu, s))) return rc;
-    prof_end(P, FMM_PHASE_UC2E, ev, s);
-    for (int l = D.maxlevel - 1; l >= 2; --l) {
-      if (!L.m2m[l].ntask) continue;
-      ev = prof_begin(P, FMM_PHASE_M2M, s);
-      if ((rc = launch_gemm<T>(P, L.m2m[l], cu, (T *)P->mslot, s))) return rc;
-      hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.m2m_n[l]), dim3(64), 0, s, D.m2m_tgt[l], D.m2m_off[l], D.m2m_kid[l],
-                         (const T *)P->mslot, cu, NR, ld, ld, L.m2m[l].nrb * 16);
-      FMM_HIP_TRY(hipGetLastError());
-      prof_end(P, FMM_PHASE_M2M, ev, s);
-    }
-    ev = prof_begin(P, FMM_PHASE_UC2E, s);
-    if ((rc = launch_gemm<T>(P, L.vs_u, cu, equ, s))) return rc;
-    prof_end(P, FMM_PHASE_UC2E, ev, s);
-    // P2L: X-list sources on the downward check surfaces
-    ev = prof_begin(P, FMM_PHASE_P2L, s);
-    if (D.nxbox > 0)
-      hipLaunchKernelGGL((k_surf_eval<T, NR, KERN>), dim3(D.nxbox), dim3(256), 0, s, D.x_box, D.x_off, D.x_idx,
-                         (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom,
-                         (const T *)P->surf, P->nsurf, ld, (T)ALPHA_DC, chk, 0, kappa);
-    FMM_HIP_TRY(hipGetLastError());
-    prof_end(P, FMM_PHASE_P2L, ev, s);
-    // M2L between singular coordinates into pair slots (rows of the
-    // largest downward rank, not of the surface size), then a fixed-order
-    // sum per target box (every box at level >= 2)
-    ev = prof_begin(P, FMM_PHASE_M2L, s);
-    if ((rc = launch_gemm<T>(P, L.m2l, cu, (T *)P->pairbuf, s))) return rc;
-    prof_end(P, FMM_PHASE_M2L, ev, s);
-    ev = prof_begin(P, FMM_PHASE_M2L_SUM, s);
-    if (D.nvbox > 0)
-      hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.nvbox), dim3(64), 0, s, D.v_tgt, D.v_off, D.v_pair,
-                         (const T *)P->pairbuf, yd, NR, ld, L.m2l.ldy, L.m2l.nrb * 16);
-    FMM_HIP_TRY(hipGetLastError());
-    prof_end(P, FMM_PHASE_M2L_SUM, ev, s);
-    ev = prof_begin(P, FMM_PHASE_DC2E, s);
-    if ((rc = launch_gemm<T>(P, L.ut_dx, chk, yd, s))) return rc;
-    prof_end(P, FMM_PHASE_DC2E, ev, s);
-    // downward pass: L2L between singular coordinates, coarsest level first
-    for (int l = 3; l <= D.maxlevel; ++l) {
-      if (L.l2l[l].ntask) {
-        ev = prof_begin(P, FMM_PHASE_L2L, s);
-        if ((rc = launch_gemm<T>(P, L.l2l[l], yd, yd, s))) return rc;
-        prof_end(P, FMM_PHASE_L2L, ev, s);
-      }
-    }
-    ev = prof_begin(P, FMM_PHASE_DC2E, s);
-    if ((rc = launch_gemm<T>(P, L.vs_d, yd, eqd, s))) return rc;
-    prof_end(P, FMM_PHASE_DC2E, ev, s);
+    prof_end(P, FMM_PHASE_M2M, ev, s);
   }
+  ev = prof_begin(P, FMM_PHASE_UC2E, s);
+  if ((rc = launch_gemm<T>(P, L.vs_u, cu, equ, s))) return rc;
+  prof_end(P, FMM_PHASE_UC2E, ev, s);
+  // P2L: X-list sources on the downward check surfaces
+  ev = prof_begin(P, FMM_PHASE_P2L, s);
+  if (D.nxbox > 0)
+    hipLaunchKernelGGL((k_surf_eval<T, NR, KERN>), dim3(D.nxbox), dim3(256), 0, s, D.x_box, D.x_off, D.x_idx,
+                       (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom,
+                       (const T *)P->surf, P->nsurf, ld, (T)ALPHA_DC, chk, 0, kappa);
+  FMM_HIP_TRY(hipGetLastError());
+  prof_end(P, FMM_PHASE_P2L, ev, s);
+  // M2L between singular coordinates into pair slots (rows of the largest
+  // downward rank, not of the surface size), then a fixed-order sum per
+  // target box (every box at level >= 2)
+  ev = prof_begin(P, FMM_PHASE_M2L, s);
+  if ((rc = launch_gemm<T>(P, L.m2l, cu, (T *)P->pairbuf, s))) return rc;
+  prof_end(P, FMM_PHASE_M2L, ev, s);
+  ev = prof_begin(P, FMM_PHASE_M2L_SUM, s);
+  if (D.nvbox > 0)
+    hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.nvbox), dim3(64), 0, s, D.v_tgt, D.v_off, D.v_pair,
+                       (const T *)P->pairbuf, yd, NR, ld, L.m2l.ldy, L.m2l.nrb * 16);
+  FMM_HIP_TRY(hipGetLastError());
+  prof_end(P, FMM_PHASE_M2L_SUM, ev, s);
+  ev = prof_begin(P, FMM_PHASE_DC2E, s);
+  if ((rc = launch_gemm<T>(P, L.ut_dx, chk, yd, s))) return rc;
+  prof_end(P, FMM_PHASE_DC2E, ev, s);
+  // downward pass: L2L between singular coordinates, coarsest level first
+  for (int l = 3; l <= D.maxlevel; ++l) {
+    if (L.l2l[l].ntask) {
+      ev = prof_begin(P, FMM_PHASE_L2L, s);
+      if ((rc = launch_gemm<T>(P, L.l2l[l], yd, yd, s))) return rc;
+      prof_end(P, FMM_PHASE_L2L, ev, s);
+    }
+  }
+  ev = prof_begin(P, FMM_PHASE_DC2E, s);
+  if ((rc = launch_gemm<T>(P, L.vs_d, yd, eqd, s))) return rc;
+  prof_end(P, FMM_PHASE_DC2E, ev, s);
+  return FMM_OK;
+}
+
+template <typename T, int NR, int KERN>
+static int eval_chunk(fmm_plan *P, const T *q, T *pot, T *grad, hipStream_t s) {
+  const DevTree &D = P->dt;
+  const int64_t N = P->n;
+  const int ld = P->ld;
+  T *qs = (T *)P->qs, *equ = (T *)P->equ, *eqd = (T *)P->eqd;
+  const T kappa = (T)P->kappa;
+  int rc;
+  if ((rc = eval_permute<T, NR>(P, q, s))) return rc;
+  if ((rc = eval_passes<T, NR, KERN>(P, s))) return rc;
   const T scale = (T)(1.0 / (4.0 * M_PI));
-  ev = prof_begin(P, FMM_PHASE_LEAF, s);
+  hipEvent_t ev = prof_begin(P, FMM_PHASE_LEAF, s);
   if (D.nitems > 0)
     hipLaunchKernelGGL((k_leaf_eval<T, NR, KERN>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
                        (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)P->surf,
@@ -1008,6 +1281,97 @@ static int eval_typed(fmm_plan *P, const T *q, int nrhs, T *pot, T *grad, hipStr
     if (rc) return rc;
   }
   return FMM_OK;
+}
+
+int ensure_pair(fmm_plan *A, fmm_plan *B, int nr);  // host: side streams, events, near sums
+
+
+// Pair evaluation of a Laplace plan A and a Yukawa plan B on one tree:
+//   stream s:      permute (A, B) | near field (both kernels)  | wait | far field, part sums
+//   A's side:                     | A's far-field passes        |
+//   B's side:                     | B's far-field passes        |
+template <typename T, int NR>
+static int eval_pair_chunk(fmm_plan *A, fmm_plan *B, const T *q, T *pot_a, T *grad_a, T *pot_b, T *grad_b,
+                           hipStream_t s) {
+  const DevTree &D = A->dt;
+  const int64_t N = A->n;
+  int rc;
+  if ((rc = eval_permute<T, NR>(A, q, s))) return rc;
+  if ((rc = eval_permute<T, NR>(B, q, s))) return rc;
+  const bool far = D.maxlevel >= 2;
+  if (far) {
+    FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
+    FMM_HIP_TRY(hipStreamWaitEvent(A->aux, A->ev_fork, 0));
+    FMM_HIP_TRY(hipStreamWaitEvent(B->aux, A->ev_fork, 0));
+    if ((rc = eval_passes<T, NR, 0>(A, A->aux))) return rc;
+    FMM_HIP_TRY(hipEventRecord(A->ev_join, A->aux));
+    if ((rc = eval_passes<T, NR, 1>(B, B->aux))) return rc;
+    FMM_HIP_TRY(hipEventRecord(B->ev_join, B->aux));
+  }
+  const T kappa = (T)B->kappa;
+  const T scale = (T)(1.0 / (4.0 * M_PI));
+  T *acc = (T *)A->pair_acc;
+  hipEvent_t ev = prof_begin(A, FMM_PHASE_NEAR, s);
+  if (D.nitems > 0)
+    hipLaunchKernelGGL((k_near_pair<T, NR>), dim3(D.nitems), dim3(64), 0, s, D.items,
+                       D.leaves, (const T *)D.pts, (const T *)A->qs, N, D.box_begin, D.box_end, D.near_off,
+                       D.near_rng, acc, kappa, D.nitems);
+  FMM_HIP_TRY(hipGetLastError());
+  prof_end(A, FMM_PHASE_NEAR, ev, s);
+  if (far) {
+    FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
+    FMM_HIP_TRY(hipStreamWaitEvent(s, B->ev_join, 0));
+  }
+  ev = prof_begin(A, FMM_PHASE_FAR, s);
+  if (D.nitems > 0)
+    hipLaunchKernelGGL((k_far_pair<T, NR>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts, N,
+                       D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)A->surf, A->nsurf, A->ld, D.far_off,
+                       D.far_idx, (const T *)acc, (const T *)A->equ, (const T *)A->eqd, (const T *)B->equ,
+                       (const T *)B->eqd, (T *)D.parts, (T *)B->dt.parts, D.perm, pot_a, grad_a, pot_b, grad_b, kappa,
+                       scale);
+  if (D.nsplit > 0) {
+    hipLaunchKernelGGL((k_leaf_parts<T, NR>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
+                       D.box_end, (const T *)D.parts, D.perm, N, pot_a, grad_a, scale);
+    hipLaunchKernelGGL((k_leaf_parts<T, NR>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
+                       D.box_end, (const T *)B->dt.parts, D.perm, N, pot_b, grad_b, scale);
+  }
+  FMM_HIP_TRY(hipGetLastError());
+  prof_end(A, FMM_PHASE_FAR, ev, s);
+  return FMM_OK;
+}
+
+template <typename T>
+static int eval_pair_typed(fmm_plan *A, fmm_plan *B, const T *q, int nrhs, T *pot_a, T *grad_a, T *pot_b, T *grad_b,
+                           hipStream_t s) {
+  const int64_t N = A->n;
+  for (int c0 = 0; c0 < nrhs; c0 += MAX_NR) {
+    const int nr = std::min(MAX_NR, nrhs - c0);
+    int rc;
+    if ((rc = ensure_work(A, nr)) || (rc = ensure_lists(A, nr)) || (rc = ensure_work(B, nr)) ||
+        (rc = ensure_lists(B, nr)) || (rc = ensure_pair(A, B, nr)))
+      return rc;
+    const T *qc = q + (int64_t)c0 * N;
+    T *pa = pot_a + (int64_t)c0 * N, *pb = pot_b + (int64_t)c0 * N;
+    T *ga = grad_a ? grad_a + (int64_t)c0 * N * 3 : nullptr;
+    T *gb = grad_b ? grad_b + (int64_t)c0 * N * 3 : nullptr;
+    switch (nr) {
+      case 1: rc = eval_pair_chunk<T, 1>(A, B, qc, pa, ga, pb, gb, s); break;
+      case 2: rc = eval_pair_chunk<T, 2>(A, B, qc, pa, ga, pb, gb, s); break;
+      case 3: rc = eval_pair_chunk<T, 3>(A, B, qc, pa, ga, pb, gb, s); break;
+      default: rc = eval_pair_chunk<T, 4>(A, B, qc, pa, ga, pb, gb, s); break;
+    }
+    if (rc) return rc;
+  }
+  return FMM_OK;
+}
+
+int eval_pair_dispatch(fmm_plan *A, fmm_plan *B, const void *q, int nrhs, void *pot_a, void *grad_a, void *pot_b,
+                       void *grad_b, hipStream_t s) {
+  if (A->precision == FMM_FP64)
+    return eval_pair_typed<double>(A, B, (const double *)q, nrhs, (double *)pot_a, (double *)grad_a, (double *)pot_b,
+                                   (double *)grad_b, s);
+  return eval_pair_typed<float>(A, B, (const float *)q, nrhs, (float *)pot_a, (float *)grad_a, (float *)pot_b,
+                                (float *)grad_b, s);
 }
 
 // dxyz_k = sum_c gbar_ck gphi_ck + q_ck gpsi_ck  (c over density columns)

@@ -138,3 +138,29 @@ class FMMPlan:
         check(lib().fmm_get_root(self._h, ctypes.c_void_p(lo.ctypes.data), ctypes.byref(w)), "fmm_get_root")
         a["lo"], a["W_root"] = lo, w.value
         return a
+
+
+def eval_pair(plan_a: FMMPlan, plan_b: FMMPlan, q: torch.Tensor, gradient: bool = True):
+    """Both plans on the same densities (fmm_eval_pair): returns
+    ((pot_a, grad_a), (pot_b, grad_b)) with the shapes of FMMPlan.eval.  A
+    Laplace plan_a and a Yukawa plan_b on the same points, p, ncrit and
+    precision share one tree and one near-field launch."""
+    if plan_a.n != plan_b.n or plan_a.dtype != plan_b.dtype:
+        raise ValueError("plans differ in point count or precision")
+    squeeze = q.ndim == 1
+    qq = q.reshape(1, -1) if squeeze else q
+    if qq.shape[1] != plan_a.n:
+        raise ValueError("density length does not match the plans")
+    qq = qq.to(device=plan_a.device, dtype=plan_a.dtype).contiguous()
+    nrhs = int(qq.shape[0])
+    outs = []
+    for _ in range(2):
+        pot = torch.empty((nrhs, plan_a.n), dtype=plan_a.dtype, device=plan_a.device)
+        grad = torch.empty((nrhs, plan_a.n, 3), dtype=plan_a.dtype, device=plan_a.device) if gradient else None
+        outs.append((pot, grad))
+    (pa, ga), (pb, gb) = outs
+    check(lib().fmm_eval_pair(plan_a._h, plan_b._h, _ptr(qq), nrhs, _ptr(pa), _ptr(ga), _ptr(pb), _ptr(gb),
+                              _stream()), "fmm_eval_pair")
+    if squeeze:
+        return (pa[0], ga[0] if ga is not None else None), (pb[0], gb[0] if gb is not None else None)
+    return (pa, ga), (pb, gb)

@@ -1,0 +1,106 @@
+"""fmm_eval_pair: a Laplace and a Yukawa plan on one tree evaluated together
+(far-field passes on two side streams, one near-field launch for both
+kernels) give the results of two fmm_eval calls, and match the FP64 direct
+sum."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct as D
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+KAPPA = 0.125
+
+
+def _cloud(n_tri=4000, seed=111):
+    su = synth.sphere_union_spheres(30, seed=seed, box=14.0)
+    v, t = synth.sphere_union_mesh(su, n_tri, seed=seed)
+    return synth.three_point_cloud(v, t)
+
+
+def _plans(x, precision, ncrit=64, offsets=None, ncrit_b=None):
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    xt = torch.tensor(x, device="cuda")
+    a = FMMPlan(xt, kernel="laplace", p=6, ncrit=ncrit, precision=precision, offsets=offsets)
+    b = FMMPlan(xt, kernel="yukawa", kappa=KAPPA, p=6, ncrit=ncrit_b or ncrit, precision=precision, offsets=offsets)
+    return a, b
+
+
+def _rel(a, b):
+    a = a.double().cpu().numpy()
+    b = b.double().cpu().numpy()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6), ("bf16x3", 1e-6)])
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_pair_equals_two_evals(precision, tol, nrhs):
+    torch = require_gpu()
+    from paper_2103_01048_amd import eval_pair
+    x = _cloud()
+    a, b = _plans(x, precision)
+    q = torch.tensor(np.random.default_rng(112).standard_normal((nrhs, len(x))), device="cuda").to(a.dtype)
+    (pa, ga), (pb, gb) = eval_pair(a, b, q)
+    ra, rga = a.eval(q)
+    rb, rgb = b.eval(q)
+    errs = [_rel(pa, ra), _rel(ga, rga), _rel(pb, rb), _rel(gb, rgb)]
+    print(f"[pair {precision} nrhs {nrhs}] {errs}", flush=True)
+    assert max(errs) < tol
+
+
+def test_pair_matches_direct_sum_and_is_deterministic():
+    torch = require_gpu()
+    from paper_2103_01048_amd import eval_pair
+    x = _cloud(3000, seed=113)
+    q = np.random.default_rng(113).standard_normal(len(x))
+    a, b = _plans(x, "fp32")
+    qt = torch.tensor(q, device="cuda", dtype=torch.float32)
+    (pa, ga), (pb, gb) = eval_pair(a, b, qt)
+    (pa2, ga2), (pb2, gb2) = eval_pair(a, b, qt)
+    for u, w in ((pa, pa2), (ga, ga2), (pb, pb2), (gb, gb2)):
+        assert torch.equal(u, w)
+    for (pot, grad), kern, kap in (((pa, ga), "laplace", 0.0), ((pb, gb), "yukawa", KAPPA)):
+        phi, g = D.direct(x, x, q, kern, kap)
+        ep = D.rel_l2(pot.double().cpu().numpy(), phi)
+        eg = D.rel_l2(grad.double().cpu().numpy(), g)
+        print(f"[pair vs direct {kern}] pot {ep:.2e} grad {eg:.2e}", flush=True)
+        assert ep < 1e-4 and eg < 1e-4
+
+
+def test_pair_without_gradient_and_batched():
+    torch = require_gpu()
+    from paper_2103_01048_amd import eval_pair
+    xs = [_cloud(1500, seed=114 + k) + 40.0 * k for k in range(3)]
+    off = np.concatenate([[0], np.cumsum([len(x) for x in xs])])
+    X = np.concatenate(xs)
+    a, b = _plans(X, "fp32", offsets=off)
+    q = torch.tensor(np.random.default_rng(117).standard_normal(len(X)), device="cuda", dtype=torch.float32)
+    (pa, ga), (pb, gb) = eval_pair(a, b, q, gradient=False)
+    assert ga is None and gb is None
+    assert _rel(pa, a.eval(q, gradient=False)[0]) < 1e-6
+    assert _rel(pb, b.eval(q, gradient=False)[0]) < 1e-6
+
+
+def test_pair_on_different_trees_runs_one_after_the_other():
+    """Plans with different ncrit do not share a tree: the pair call falls
+    back to two evaluations and still returns both results."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import eval_pair
+    x = _cloud(2000, seed=118)
+    a, b = _plans(x, "fp32", ncrit=64, ncrit_b=32)
+    q = torch.tensor(np.random.default_rng(118).standard_normal(len(x)), device="cuda", dtype=torch.float32)
+    (pa, ga), (pb, gb) = eval_pair(a, b, q)
+    assert torch.equal(pa, a.eval(q)[0]) and torch.equal(pb, b.eval(q)[0])
+
+
+def test_pair_rejects_mismatched_plans():
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, eval_pair
+    x = _cloud(1000, seed=119)
+    a = FMMPlan(torch.tensor(x, device="cuda"), kernel="laplace", p=4, ncrit=64, precision="fp32")
+    b = FMMPlan(torch.tensor(x[:-3], device="cuda"), kernel="yukawa", kappa=KAPPA, p=4, ncrit=64, precision="fp32")
+    q = torch.zeros(len(x), device="cuda")
+    with pytest.raises(ValueError):
+        eval_pair(a, b, q)
