@@ -46,6 +46,20 @@ struct GemmTask {
 
 enum GemmMode { GEMM_STORE = 0, GEMM_ADD = 1, GEMM_ATOMIC = 2 };
 
+// Everything one gather-GEMM batch needs on the device; a launch takes two
+// (the second with ntask = 0 when unused) so that the same pass of two plans
+// sharing a tree runs as one launch.
+struct GemmArgs {
+  const GemmTask *tasks;
+  const void *pool;     // matrix pool (elements of the work type; uint4 units for bf16x3)
+  int64_t mstride;      // one matrix, in pool units
+  const int32_t *src;   // ncols*S row indices into X
+  const int32_t *dst;   // ncols row indices into Y
+  const void *X;
+  void *Y;
+  int ntask, nrb, klen, ldx, ldy, S, seg, KQ, mode;
+};
+
 // A batch of GEMM tasks that can run in one launch (no write conflicts
 // except through GEMM_ATOMIC).
 struct GemmBatch {
