@@ -123,6 +123,23 @@ int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *g
 int fmm_eval_pair(fmm_plan *plan_a, fmm_plan *plan_b, const void *q_dev, int nrhs, void *pot_a_dev,
                   void *grad_a_dev, void *pot_b_dev, void *grad_b_dev, fmm_stream_t stream);
 
+/* Potentials of monopole and dipole sources (one column, no gradients) for a
+ * Laplace plan_a and a Yukawa plan_b sharing one tree (same points, batch
+ * offsets, p, ncrit and precision; FMM_EINVAL otherwise):
+ *   pot_k(x_i) = sum_{j: r_ij > 0} [ qscale_k q_j g_k(r_ij) + dip_j . grad_y g_k(x_i, y_j) ]
+ * with grad_y g = +(x - y) (1 + kappa r) e^{-kappa r} / (4 pi r^3) (kappa = 0
+ * for Laplace).  This is the double-layer plus single-layer potential of the
+ * direct formulation in one pass per kernel (Methods, eq:single_double and
+ * eq:direct: the double layer is the normal derivative of g at the source).
+ * q_dev: n charges; dip_dev: n x 3 dipole moments (row i = point i); pot_a_dev,
+ * pot_b_dev: n each; caller's point order; element type double for FMM_FP64,
+ * float otherwise.  Equivalent densities stay monopoles, so only the source
+ * side (P2M, P2L, near field) differs from fmm_eval_pair.  Asynchronous on
+ * `stream` (internal side stream joined back).  Errors: FMM_EINVAL for null
+ * buffers, non-finite scales or plans that do not share a tree. */
+int fmm_eval_pair_md(fmm_plan *plan_a, fmm_plan *plan_b, const void *q_dev, const void *dip_dev, double qscale_a,
+                     double qscale_b, void *pot_a_dev, void *pot_b_dev, fmm_stream_t stream);
+
 /* Adjoint of fmm_eval for a loss L(pot) with upstream gradient gbar_dev =
  * dL/dpot (nrhs x n, same type and layout as pot).  Because the kernel is
  * symmetric and targets = sources, the density gradient is one more

@@ -48,6 +48,7 @@ SIGNATURES = {
     "fmm_setup": (i32, [vp, i64, i32, dbl, i32, i32, i32, vp, P(vp)]),
     "fmm_eval": (i32, [vp, vp, i32, vp, vp, vp]),
     "fmm_eval_pair": (i32, [vp, vp, vp, i32, vp, vp, vp, vp, vp]),
+    "fmm_eval_pair_md": (i32, [vp, vp, vp, vp, dbl, dbl, vp, vp, vp]),
     "fmm_setup_batch": (i32, [vp, vp, i32, i32, dbl, i32, i32, i32, vp, P(vp)]),
     "fmm_info": (i32, [vp, P(FmmInfo)]),
     "fmm_get_tree": (i32, [vp] + [vp] * 11),

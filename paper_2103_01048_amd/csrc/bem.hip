@@ -237,53 +237,48 @@ __global__ void k_precond_apply(int64_t nt, const double *__restrict__ pre, cons
   y[nt + s] = pre[4 * s + 2] * u + pre[4 * s + 3] * v;
 }
 
-// P1: densities at the quadrature points, 4 columns: W n_d u (d = 0,1,2), W v.
+// P1 for the monopole + dipole evaluation: at quadrature point i of triangle
+// t, charge W_i v_t (single layer) and dipole W_i u_t n_t (double layer).
 template <typename T>
-__global__ void k_bem_p1(int64_t nt, int nq, const double *__restrict__ x, const double *__restrict__ qw,
-                         const double *__restrict__ normal, T *__restrict__ q) {
+__global__ void k_bem_p1_md(int64_t nt, int nq, const double *__restrict__ x, const double *__restrict__ qw,
+                            const double *__restrict__ normal, T *__restrict__ q, T *__restrict__ dip) {
   const int64_t i = blockIdx.x * 256ll + threadIdx.x;
-  const int64_t N = nt * nq;
-  if (i >= N) return;
+  if (i >= nt * nq) return;
   const int64_t t = i / nq;
   const double w = qw[i], u = x[t], v = x[nt + t];
-  q[i] = (T)(w * normal[3 * t] * u);
-  q[N + i] = (T)(w * normal[3 * t + 1] * u);
-  q[2 * N + i] = (T)(w * normal[3 * t + 2] * u);
-  q[3 * N + i] = (T)(w * v);
+  q[i] = (T)(w * v);
+  dip[3 * i + 0] = (T)(w * u * normal[3 * t + 0]);
+  dip[3 * i + 1] = (T)(w * u * normal[3 * t + 1]);
+  dip[3 * i + 2] = (T)(w * u * normal[3 * t + 2]);
 }
 
-// P2^T, the sparse correction and the block assembly, one thread per test
-// triangle s.
+// P2^T and assembly for the monopole + dipole evaluation: the FMM returned,
+// per quadrature point, pot_L = K_L u - V_L v and pot_Y = K_Y u - (eps_in /
+// eps_out) V_Y v (regular parts), so
+//   y1 = M u / 2 + P2^T pot_L + (S - C) terms,  y2 = M u / 2 - P2^T pot_Y + (S - C) terms.
 template <typename T>
-__global__ void k_bem_p2(int64_t nt, int nq, const T *__restrict__ potl, const T *__restrict__ gradl,
-                         const T *__restrict__ poty, const T *__restrict__ grady, const double *__restrict__ qw,
-                         const double *__restrict__ area, const int32_t *__restrict__ sp_off,
-                         const int32_t *__restrict__ sp_idx, const double *__restrict__ Dval,
-                         const double *__restrict__ x, double eratio, double *__restrict__ y) {
+__global__ void k_bem_p2_md(int64_t nt, int nq, const T *__restrict__ potl, const T *__restrict__ poty,
+                            const double *__restrict__ qw, const double *__restrict__ area,
+                            const int32_t *__restrict__ sp_off, const int32_t *__restrict__ sp_idx,
+                            const double *__restrict__ Dval, const double *__restrict__ x, double eratio,
+                            double *__restrict__ y) {
   const int64_t s = blockIdx.x * 256ll + threadIdx.x;
   if (s >= nt) return;
-  const int64_t N = nt * nq;
-  double kl = 0, vl = 0, ky = 0, vy = 0;
+  double al = 0, ay = 0;
   for (int a = 0; a < nq; ++a) {
     const int64_t i = s * nq + a;
-    const double w = qw[i];
-    // K x = -(d/dx_0 of column 0 + d/dx_1 of column 1 + d/dx_2 of column 2)
-    kl -= w * ((double)gradl[i * 3 + 0] + (double)gradl[(N + i) * 3 + 1] + (double)gradl[(2 * N + i) * 3 + 2]);
-    ky -= w * ((double)grady[i * 3 + 0] + (double)grady[(N + i) * 3 + 1] + (double)grady[(2 * N + i) * 3 + 2]);
-    vl += w * (double)potl[3 * N + i];
-    vy += w * (double)poty[3 * N + i];
+    al += qw[i] * (double)potl[i];
+    ay += qw[i] * (double)poty[i];
   }
   for (int k = sp_off[s]; k < sp_off[s + 1]; ++k) {
     const int t = sp_idx[k];
     const double u = x[t], v = x[nt + t];
-    vl += Dval[4 * k + 0] * v;
-    kl += Dval[4 * k + 1] * u;
-    vy += Dval[4 * k + 2] * v;
-    ky += Dval[4 * k + 3] * u;
+    al += Dval[4 * k + 1] * u - Dval[4 * k + 0] * v;
+    ay += Dval[4 * k + 3] * u - eratio * Dval[4 * k + 2] * v;
   }
   const double hu = 0.5 * area[s] * x[s];
-  y[s] = hu + kl - vl;
-  y[nt + s] = hu - ky + eratio * vy;
+  y[s] = hu + al;
+  y[nt + s] = hu - ay;
 }
 
 // FP64 direct sum with monopole and dipole sources:
@@ -428,7 +423,7 @@ struct bem_op {
   double *d_tri = nullptr, *d_normal = nullptr, *d_area = nullptr, *d_qw = nullptr, *d_qpts = nullptr;
   int32_t *d_sp_off = nullptr, *d_sp_idx = nullptr;
   double *d_D = nullptr, *d_sdiag = nullptr, *d_pre = nullptr;
-  void *q4 = nullptr, *potl = nullptr, *gradl = nullptr, *poty = nullptr, *grady = nullptr;
+  void *q4 = nullptr, *potl = nullptr, *poty = nullptr;
   // GMRES / energy scratch
   double *d_partial = nullptr, *d_h = nullptr, *d_V = nullptr, *d_z = nullptr, *d_w = nullptr, *d_r = nullptr,
          *d_xc = nullptr;
@@ -575,11 +570,10 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     if ((rc = fmm_setup(op->d_qpts, op->N, FMM_LAPLACE, 0.0, p, ncrit, precision, stream, &op->fl))) break;
     if ((rc = fmm_setup(op->d_qpts, op->N, FMM_YUKAWA, kappa, p, ncrit, precision, stream, &op->fy))) break;
     const size_t es = precision == FMM_FP64 ? 8 : 4;
+    // charges (N) and dipoles (3N); one potential per point and kernel
     if ((rc = balloc(op, &op->q4, 4 * op->N * es))) break;
-    if ((rc = balloc(op, &op->potl, 4 * op->N * es))) break;
-    if ((rc = balloc(op, &op->gradl, 12 * op->N * es))) break;
-    if ((rc = balloc(op, &op->poty, 4 * op->N * es))) break;
-    if ((rc = balloc(op, &op->grady, 12 * op->N * es))) break;
+    if ((rc = balloc(op, &op->potl, op->N * es))) break;
+    if ((rc = balloc(op, &op->poty, op->N * es))) break;
     if ((rc = balloc(op, (void **)&op->d_z, 2 * nt * sizeof(double)))) break;
     if ((rc = balloc(op, (void **)&op->d_w, 2 * nt * sizeof(double)))) break;
     if ((rc = balloc(op, (void **)&op->d_r, 2 * nt * sizeof(double)))) break;
@@ -599,24 +593,30 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
   const int64_t N = op->N, nt = op->nt;
   int rc;
   const double er = op->eps_in / op->eps_out;
+  // one pass per kernel: single layer as charges, double layer as dipoles
+  // (the four-column form would need potentials and gradients of four)
+  const int64_t Nq = (int64_t)nt * op->nq;
   if (op->precision == FMM_FP64) {
-    hipLaunchKernelGGL(k_bem_p1<double>, dim3(blocks(N)), dim3(256), 0, s, nt, op->nq, x, op->d_qw, op->d_normal,
-                       (double *)op->q4);
+    double *qq = (double *)op->q4;
+    hipLaunchKernelGGL(k_bem_p1_md<double>, dim3(blocks(N)), dim3(256), 0, s, nt, op->nq, x, op->d_qw, op->d_normal,
+                       qq, qq + Nq);
   } else {
-    hipLaunchKernelGGL(k_bem_p1<float>, dim3(blocks(N)), dim3(256), 0, s, nt, op->nq, x, op->d_qw, op->d_normal,
-                       (float *)op->q4);
+    float *qq = (float *)op->q4;
+    hipLaunchKernelGGL(k_bem_p1_md<float>, dim3(blocks(N)), dim3(256), 0, s, nt, op->nq, x, op->d_qw, op->d_normal,
+                       qq, qq + Nq);
   }
   FMM_HIP_TRY(hipGetLastError());
-  // both kernels on the same four columns: one tree, one near-field launch
-  if ((rc = fmm_eval_pair(op->fl, op->fy, op->q4, 4, op->potl, op->gradl, op->poty, op->grady, s))) return rc;
+  {
+    const size_t es = op->precision == FMM_FP64 ? 8 : 4;
+    const char *qq = (const char *)op->q4;
+    if ((rc = fmm_eval_pair_md(op->fl, op->fy, qq, qq + Nq * es, -1.0, -er, op->potl, op->poty, s))) return rc;
+  }
   if (op->precision == FMM_FP64) {
-    hipLaunchKernelGGL(k_bem_p2<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const double *)op->potl,
-                       (const double *)op->gradl, (const double *)op->poty, (const double *)op->grady, op->d_qw,
-                       op->d_area, op->d_sp_off, op->d_sp_idx, op->d_D, x, er, y);
+    hipLaunchKernelGGL(k_bem_p2_md<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const double *)op->potl,
+                       (const double *)op->poty, op->d_qw, op->d_area, op->d_sp_off, op->d_sp_idx, op->d_D, x, er, y);
   } else {
-    hipLaunchKernelGGL(k_bem_p2<float>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const float *)op->potl,
-                       (const float *)op->gradl, (const float *)op->poty, (const float *)op->grady, op->d_qw,
-                       op->d_area, op->d_sp_off, op->d_sp_idx, op->d_D, x, er, y);
+    hipLaunchKernelGGL(k_bem_p2_md<float>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const float *)op->potl,
+                       (const float *)op->poty, op->d_qw, op->d_area, op->d_sp_off, op->d_sp_idx, op->d_D, x, er, y);
   }
   FMM_HIP_TRY(hipGetLastError());
   return FMM_OK;

@@ -42,6 +42,8 @@ int device_gather_points(const double *xyz, const int32_t *perm, int64_t n, cons
 int eval_dispatch(fmm_plan *P, const void *q, int nrhs, void *pot, void *grad, hipStream_t s);
 int eval_pair_dispatch(fmm_plan *A, fmm_plan *B, const void *q, int nrhs, void *pot_a, void *grad_a, void *pot_b,
                        void *grad_b, hipStream_t s);
+int eval_pair_md_dispatch(fmm_plan *A, fmm_plan *B, const void *q, const void *dip, double ca, double cb, void *pot_a,
+                          void *pot_b, hipStream_t s);
 int adjoint_combine(fmm_plan *P, int nrhs, const void *q, const void *gbar, const void *gphi, const void *gpsi,
                     void *dx, hipStream_t s);
 
@@ -1060,6 +1062,13 @@ int ensure_pair(fmm_plan *A, fmm_plan *B, int nr) {
   return FMM_OK;
 }
 
+int ensure_pair_md(fmm_plan *A, fmm_plan *B) {
+  (void)B;
+  if (A->dips) return FMM_OK;
+  const size_t es = A->precision == FMM_FP64 ? 8 : 4;
+  return dev_alloc(A, &A->dips, std::max<size_t>(1, (size_t)A->n) * 4 * es);
+}
+
 int ensure_work(fmm_plan *P, int nr) {
   if (P->work_nr >= nr) return FMM_OK;
   const size_t es = P->precision == FMM_FP64 ? 8 : 4;
@@ -1235,6 +1244,12 @@ int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *g
   return eval_dispatch(plan, q_dev, nrhs, pot_dev, grad_dev, (hipStream_t)stream);
 }
 
+static bool shares_tree(const fmm_plan *A, const fmm_plan *B) {
+  return A->kernel == FMM_LAPLACE && B->kernel == FMM_YUKAWA && A->tree_hash == B->tree_hash &&
+         A->precision == B->precision && A->nsurf == B->nsurf && A->ncrit == B->ncrit && A->n == B->n &&
+         A->dt.nitems == B->dt.nitems && A->dt.nparts == B->dt.nparts;
+}
+
 int fmm_eval_pair(fmm_plan *A, fmm_plan *B, const void *q_dev, int nrhs, void *pot_a, void *grad_a, void *pot_b,
                   void *grad_b, fmm_stream_t stream) {
   if (!A || !B) { set_error("fmm_eval_pair: plan is NULL"); return FMM_EINVAL; }
@@ -1247,15 +1262,30 @@ int fmm_eval_pair(fmm_plan *A, fmm_plan *B, const void *q_dev, int nrhs, void *p
   if (A->n == 0) return FMM_OK;
   if (!q_dev || !pot_a || !pot_b) { set_error("fmm_eval_pair: null buffer"); return FMM_EINVAL; }
   hipStream_t s = (hipStream_t)stream;
-  const bool shared = A->kernel == FMM_LAPLACE && B->kernel == FMM_YUKAWA && A->tree_hash == B->tree_hash &&
-                      A->precision == B->precision && A->nsurf == B->nsurf && A->ncrit == B->ncrit &&
-                      A->dt.nitems == B->dt.nitems && A->dt.nparts == B->dt.nparts;
+  const bool shared = shares_tree(A, B);
   if (!shared) {
     int rc;
     if ((rc = eval_dispatch(A, q_dev, nrhs, pot_a, grad_a, s))) return rc;
     return eval_dispatch(B, q_dev, nrhs, pot_b, grad_b, s);
   }
   return eval_pair_dispatch(A, B, q_dev, nrhs, pot_a, grad_a, pot_b, grad_b, s);
+}
+
+int fmm_eval_pair_md(fmm_plan *A, fmm_plan *B, const void *q_dev, const void *dip_dev, double qscale_a,
+                     double qscale_b, void *pot_a, void *pot_b, fmm_stream_t stream) {
+  if (!A || !B || A == B) { set_error("fmm_eval_pair_md: need two plans"); return FMM_EINVAL; }
+  if (!shares_tree(A, B)) {
+    set_error("fmm_eval_pair_md: plan_a must be a Laplace and plan_b a Yukawa plan on the same points, p, ncrit "
+              "and precision");
+    return FMM_EINVAL;
+  }
+  if (!std::isfinite(qscale_a) || !std::isfinite(qscale_b)) {
+    set_error("fmm_eval_pair_md: non-finite charge scale");
+    return FMM_EINVAL;
+  }
+  if (A->n == 0) return FMM_OK;
+  if (!q_dev || !dip_dev || !pot_a || !pot_b) { set_error("fmm_eval_pair_md: null buffer"); return FMM_EINVAL; }
+  return eval_pair_md_dispatch(A, B, q_dev, dip_dev, qscale_a, qscale_b, pot_a, pot_b, (hipStream_t)stream);
 }
 
 int fmm_adjoint(fmm_plan *P, const void *q, const void *gbar, const void *gfwd, int nrhs, void *dq, void *dxyz,

@@ -188,6 +188,7 @@ struct fmm_plan {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   void *pair_acc = nullptr;
   size_t pair_acc_bytes = 0;
+  void *dips = nullptr;             // monopole + dipole sources: dipole records in Morton order
   uint64_t tree_hash = 0;           // fingerprint of points, boxes and leaf items
   void *adj = nullptr;              // adjoint scratch: psi and grad psi
   size_t adj_bytes = 0;

@@ -728,7 +728,7 @@ __global__ __launch_bounds__(64) void k_leaf_parts(const int32_t *__restrict__ t
 // ([item][kernel][column][pot, gx, gy, gz][lane]); the far launch continues
 // them, so each sum is accumulated in the same order as by k_leaf_eval.
 // ---------------------------------------------------------------------------
-template <typename T, bool CHECK, int NR>
+template <typename T, bool CHECK, int NR, bool GRAD = true>
 __device__ __forceinline__ void leaf_pair_ly(T xi, T yi, T zi, T sx, T sy, T sz, const T (&qa)[NR], const T (&qb)[NR],
                                              T kappa, T kl2, T (&pa)[NR], T (&xa)[NR], T (&ya)[NR], T (&za)[NR],
                                              T (&pb)[NR], T (&xb)[NR], T (&yb)[NR], T (&zb)[NR]) {
@@ -744,15 +744,17 @@ __device__ __forceinline__ void leaf_pair_ly(T xi, T yi, T zi, T sx, T sy, T sz,
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
     pa[c] += invr * qa[c];
-    const T fqa = fl * qa[c];
-    xa[c] -= fqa * dx;
-    ya[c] -= fqa * dy;
-    za[c] -= fqa * dz;
     pb[c] += gy * qb[c];
-    const T fqb = fy * qb[c];
-    xb[c] -= fqb * dx;
-    yb[c] -= fqb * dy;
-    zb[c] -= fqb * dz;
+    if (GRAD) {
+      const T fqa = fl * qa[c];
+      xa[c] -= fqa * dx;
+      ya[c] -= fqa * dy;
+      za[c] -= fqa * dz;
+      const T fqb = fy * qb[c];
+      xb[c] -= fqb * dx;
+      yb[c] -= fqb * dy;
+      zb[c] -= fqb * dz;
+    }
   }
 }
 
@@ -878,7 +880,7 @@ __device__ __forceinline__ void leaf_store(int part, int half, bool active, int 
   }
 }
 
-template <typename T, int NR>
+template <typename T, int NR, bool GRAD>
 __global__ __launch_bounds__(64) void k_far_pair(
     const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts, int64_t N,
     const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end, const T *__restrict__ box_geom,
@@ -911,13 +913,17 @@ __global__ __launch_bounds__(64) void k_far_pair(
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
     pa[c] = a[(c * 4 + 0) * 64 + lane];
-    xa[c] = a[(c * 4 + 1) * 64 + lane];
-    ya[c] = a[(c * 4 + 2) * 64 + lane];
-    za[c] = a[(c * 4 + 3) * 64 + lane];
     pb[c] = a[((NR + c) * 4 + 0) * 64 + lane];
-    xb[c] = a[((NR + c) * 4 + 1) * 64 + lane];
-    yb[c] = a[((NR + c) * 4 + 2) * 64 + lane];
-    zb[c] = a[((NR + c) * 4 + 3) * 64 + lane];
+    if (GRAD) {
+      xa[c] = a[(c * 4 + 1) * 64 + lane];
+      ya[c] = a[(c * 4 + 2) * 64 + lane];
+      za[c] = a[(c * 4 + 3) * 64 + lane];
+      xb[c] = a[((NR + c) * 4 + 1) * 64 + lane];
+      yb[c] = a[((NR + c) * 4 + 2) * 64 + lane];
+      zb[c] = a[((NR + c) * 4 + 3) * 64 + lane];
+    } else {
+      xa[c] = ya[c] = za[c] = xb[c] = yb[c] = zb[c] = (T)0;
+    }
   }
   const int f1 = far_off[item + 1];
   for (int k = far_off[item]; k < f1; ++k) {
@@ -935,7 +941,7 @@ __global__ __launch_bounds__(64) void k_far_pair(
         T qa[NR], qb[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) { qa[c] = da[(int64_t)c * ld + j]; qb[c] = db[(int64_t)c * ld + j]; }
-        leaf_pair_ly<T, false, NR>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qa, qb, kappa, kl2,
+        leaf_pair_ly<T, false, NR, GRAD>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qa, qb, kappa, kl2,
                                    pa, xa, ya, za, pb, xb, yb, zb);
       }
     } else {
@@ -950,7 +956,7 @@ __global__ __launch_bounds__(64) void k_far_pair(
           qa[c] = ok ? da[(int64_t)c * ld + jj] : (T)0;
           qb[c] = ok ? db[(int64_t)c * ld + jj] : (T)0;
         }
-        leaf_pair_ly<T, false, NR>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qa, qb, kappa, kl2,
+        leaf_pair_ly<T, false, NR, GRAD>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qa, qb, kappa, kl2,
                                    pa, xa, ya, za, pb, xb, yb, zb);
       }
     }
@@ -1025,6 +1031,160 @@ __global__ __launch_bounds__(512) void k_surf_eval_pair(
       if (mode == 0) { *ya = accA[r]; *yb = accB[r]; }
       else { *ya += accA[r]; *yb += accB[r]; }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Monopole + dipole sources (pair evaluation, potentials only).  Source j
+// carries a charge and a dipole moment d_j; a kernel's potential at x is
+//   sum_j [ c q_j g(x, y_j) + d_j . grad_y g(x, y_j) ],
+// grad_y g = f(r) (x - y) with the f of the gradient formulas.  The charge
+// arrives pre-scaled per kernel: the points' fourth slot holds c_a q_j and the
+// dipole record's fourth slot c_b q_j.  Equivalent densities stay monopoles,
+// so only the source side (P2M, P2L, near field) changes.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_permute_md(const T *__restrict__ q, const T *__restrict__ dip, const int32_t *__restrict__ perm,
+                             int64_t N, T ca, T cb, T *__restrict__ pts, T *__restrict__ dips) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= N) return;
+  const int64_t j = perm[i];
+  const T qj = q[j];
+  pts[i * 4 + 3] = ca * qj;
+  dips[i * 4 + 0] = dip[3 * j + 0];
+  dips[i * 4 + 1] = dip[3 * j + 1];
+  dips[i * 4 + 2] = dip[3 * j + 2];
+  dips[i * 4 + 3] = cb * qj;
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_surf_eval_pair_md(
+    const int32_t *__restrict__ tbox, const int32_t *__restrict__ src_off, const int32_t *__restrict__ src_idx,
+    const T *__restrict__ pts, const T *__restrict__ dips, const int32_t *__restrict__ box_begin,
+    const int32_t *__restrict__ box_end, const T *__restrict__ box_geom, const T *__restrict__ surf, int nsurf,
+    int ld, T alpha, T *__restrict__ YA, T *__restrict__ YB, T kappa) {
+  __shared__ T sx[512], sy[512], sz[512], sqa[512], sdx[512], sdy[512], sdz[512], sqb[512];
+  const int slot = blockIdx.x;
+  const int b = tbox[slot];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const T cx = box_geom[b * 4 + 0], cy = box_geom[b * 4 + 1], cz = box_geom[b * 4 + 2];
+  const T rr = box_geom[b * 4 + 3] * alpha;
+  const int ii = tid < nsurf ? tid : 0;
+  const T tx = cx + rr * surf[ii * 4 + 0], ty = cy + rr * surf[ii * 4 + 1], tz = cz + rr * surf[ii * 4 + 2];
+  T accA = 0, accB = 0;
+  for (int k = src_off[slot]; k < src_off[slot + 1]; ++k) {
+    const int a = src_idx[k];
+    const int sb = box_begin[a], se = box_end[a];
+    for (int c0 = sb; c0 < se; c0 += nt) {
+      const int j = c0 + tid;
+      if (j < se) {
+        sx[tid] = pts[(int64_t)j * 4 + 0];
+        sy[tid] = pts[(int64_t)j * 4 + 1];
+        sz[tid] = pts[(int64_t)j * 4 + 2];
+        sqa[tid] = pts[(int64_t)j * 4 + 3];
+        sdx[tid] = dips[(int64_t)j * 4 + 0];
+        sdy[tid] = dips[(int64_t)j * 4 + 1];
+        sdz[tid] = dips[(int64_t)j * 4 + 2];
+        sqb[tid] = dips[(int64_t)j * 4 + 3];
+      }
+      __syncthreads();
+      const int cnt = min(nt, se - c0);
+      for (int j2 = 0; j2 < cnt; ++j2) {
+        const T dx = tx - sx[j2], dy = ty - sy[j2], dz = tz - sz[j2];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const T invr = r2 > (T)0 ? dev_rsqrt(r2) : (T)0;
+        const T i2 = invr * invr;
+        const T dd = sdx[j2] * dx + sdy[j2] * dy + sdz[j2] * dz;
+        const T r = r2 * invr;
+        const T gy = dev_exp(-kappa * r) * invr;
+        accA += invr * sqa[j2] + (i2 * invr) * dd;
+        accB += gy * sqb[j2] + (((T)1 + kappa * r) * gy * i2) * dd;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid < nsurf) {
+    YA[(int64_t)b * ld + tid] = accA;
+    YB[(int64_t)b * ld + tid] = accB;
+  }
+}
+
+template <typename T, bool CHECK>
+__device__ __forceinline__ void leaf_pair_md(T xi, T yi, T zi, const typename Vec4<T>::type &sp,
+                                             const typename Vec4<T>::type &sd, T kappa, T kl2, T &pa, T &pb) {
+  const T dx = xi - sp[0], dy = yi - sp[1], dz = zi - sp[2];
+  const T r2 = dx * dx + dy * dy + dz * dz;
+  T invr = dev_rsqrt(r2);
+  if (CHECK) invr = r2 > (T)0 ? invr : (T)0;
+  const T i2 = invr * invr;
+  const T dd = sd[0] * dx + sd[1] * dy + sd[2] * dz;
+  const T r = r2 * invr;
+  const T gy = dev_exp2(-kl2 * r) * invr;
+  pa += invr * sp[3] + (i2 * invr) * dd;
+  pb += gy * sd[3] + (((T)1 + kappa * r) * gy * i2) * dd;
+}
+
+// Near field of monopole + dipole sources, both kernels, potentials only;
+// running sums to acc in the layout of k_near_pair with one column.
+template <typename T>
+__global__ __launch_bounds__(64) void k_near_pair_md(
+    const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts,
+    const T *__restrict__ dips, const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end,
+    const int32_t *__restrict__ near_off, const int32_t *__restrict__ near_rng, T *__restrict__ acc, T kappa,
+    int nitems) {
+  using V4 = typename Vec4<T>::type;
+  const V4 *__restrict__ p4 = reinterpret_cast<const V4 *>(pts);
+  const V4 *__restrict__ d4 = reinterpret_cast<const V4 *>(dips);
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int slot = items[4 * item];
+    const int code = items[4 * item + 1];
+    const int split = code >> 24;
+    const int b = leaves[slot];
+    const int lb = box_begin[b], le = box_end[b];
+    const int tb = lb + (code & 0xffffff);
+    const int lane = threadIdx.x;
+    const int half = split == 2 ? (lane >> 5) : 0;
+    const int tl = split == 2 ? (lane & 31) : lane;
+    const int m = min(64 / split, le - tb);
+    const bool active = tl < m;
+    const V4 xv = p4[tb + (active ? tl : 0)];
+    const T xi = xv[0], yi = xv[1], zi = xv[2];
+    const T kl2 = kappa * (T)1.4426950408889634;
+    T pa = 0, pb = 0;
+    const int u1 = near_off[item + 1];
+    for (int u = near_off[item]; u < u1; ++u) {
+      const int j0 = near_rng[2 * u], j1 = near_rng[2 * u + 1];
+      const bool self = j0 < le && lb < j1;
+      if (split == 1) {
+        if (self) {
+#pragma unroll 4
+          for (int j = j0; j < j1; ++j) leaf_pair_md<T, true>(xi, yi, zi, p4[j], d4[j], kappa, kl2, pa, pb);
+        } else {
+#pragma unroll 8
+          for (int j = j0; j < j1; ++j) leaf_pair_md<T, false>(xi, yi, zi, p4[j], d4[j], kappa, kl2, pa, pb);
+        }
+      } else {
+        // split: lane half h takes sources j0 + h, j0 + h + 2, ...; a missing
+        // last source of the upper half counts with zero strength
+        auto body = [&](int j, auto chk) {
+          const int jj = j + half;
+          const bool ok = jj < j1;
+          V4 sp = p4[ok ? jj : j], sd = d4[ok ? jj : j];
+          if (!ok) { sp[3] = (T)0; sd = V4{0, 0, 0, 0}; }
+          leaf_pair_md<T, decltype(chk)::value>(xi, yi, zi, sp, sd, kappa, kl2, pa, pb);
+        };
+        if (self) {
+#pragma unroll 2
+          for (int j = j0; j < j1; j += 2) body(j, std::true_type());
+        } else {
+#pragma unroll 4
+          for (int j = j0; j < j1; j += 2) body(j, std::false_type());
+        }
+      }
+    }
+    T *a = acc + (int64_t)item * 2 * 4 * 64;
+    a[lane] = pa;
+    a[4 * 64 + lane] = pb;
   }
 }
 
@@ -1336,7 +1496,7 @@ static int eval_passes(fmm_plan *P, hipStream_t s) {
 // `surf_done` is recorded after them; the GEMM passes follow.
 template <typename T, int NR>
 static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t surf_done,
-                            hipEvent_t up_done) {
+                            hipEvent_t up_done, const T *dips = nullptr) {
   const DevTree &D = A->dt;
   const int64_t N = A->n;
   const int ld = A->ld;
@@ -1349,7 +1509,12 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t 
   if (D.maxlevel < 2) return FMM_OK;
   const unsigned sthreads = (unsigned)(64 * ((A->nsurf + 63) / 64));
   ev = prof_begin(A, FMM_PHASE_P2M, s);
-  if (A->p2m_count > 0)
+  if (A->p2m_count > 0 && dips)
+    hipLaunchKernelGGL((k_surf_eval_pair_md<T>), dim3(A->p2m_count), dim3(sthreads), 0, s, A->d_p2m_box,
+                       A->d_p2m_off, A->d_p2m_box, (const T *)D.pts, dips, D.box_begin, D.box_end,
+                       (const T *)D.box_geom, (const T *)A->surf, A->nsurf, ld, (T)ALPHA_UC, W(A->chku), W(B->chku),
+                       kappa);
+  else if (A->p2m_count > 0)
     hipLaunchKernelGGL((k_surf_eval_pair<T, NR>), dim3(A->p2m_count), dim3(sthreads), 0, s, A->d_p2m_box,
                        A->d_p2m_off, A->d_p2m_box, (const T *)D.pts, qs, N, D.box_begin, D.box_end,
                        (const T *)D.box_geom, (const T *)A->surf, A->nsurf, ld, (T)ALPHA_UC, W(A->chku), W(B->chku), 0,
@@ -1358,7 +1523,11 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t 
   prof_end(A, FMM_PHASE_P2M, ev, s);
   // P2L needs only the densities: run it with P2M, before the GEMM passes
   ev = prof_begin(A, FMM_PHASE_P2L, s);
-  if (D.nxbox > 0)
+  if (D.nxbox > 0 && dips)
+    hipLaunchKernelGGL((k_surf_eval_pair_md<T>), dim3(D.nxbox), dim3(sthreads), 0, s, D.x_box, D.x_off, D.x_idx,
+                       (const T *)D.pts, dips, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)A->surf,
+                       A->nsurf, ld, (T)ALPHA_DC, W(A->chk), W(B->chk), kappa);
+  else if (D.nxbox > 0)
     hipLaunchKernelGGL((k_surf_eval_pair<T, NR>), dim3(D.nxbox), dim3(sthreads), 0, s, D.x_box, D.x_off, D.x_idx,
                        (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)A->surf,
                        A->nsurf, ld, (T)ALPHA_DC, W(A->chk), W(B->chk), 0, kappa);
@@ -1503,7 +1672,7 @@ static int eval_pair_chunk(fmm_plan *A, fmm_plan *B, const T *q, T *pot_a, T *gr
   if (far) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
   ev = prof_begin(A, FMM_PHASE_FAR, s);
   if (D.nitems > 0)
-    hipLaunchKernelGGL((k_far_pair<T, NR>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts, N,
+    hipLaunchKernelGGL((k_far_pair<T, NR, true>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts, N,
                        D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)A->surf, A->nsurf, A->ld, D.far_off,
                        D.far_idx, (const T *)acc, (const T *)A->equ, (const T *)A->eqd, (const T *)B->equ,
                        (const T *)B->eqd, (T *)D.parts, (T *)B->dt.parts, D.perm, pot_a, grad_a, pot_b, grad_b, kappa,
@@ -1551,6 +1720,70 @@ int eval_pair_dispatch(fmm_plan *A, fmm_plan *B, const void *q, int nrhs, void *
                                    (double *)grad_b, s);
   return eval_pair_typed<float>(A, B, (const float *)q, nrhs, (float *)pot_a, (float *)grad_a, (float *)pot_b,
                                 (float *)grad_b, s);
+}
+
+int ensure_pair_md(fmm_plan *A, fmm_plan *B);  // host: the permuted dipole records
+
+// Pair evaluation with monopole + dipole sources, potentials only (one
+// column); the same stream layout as eval_pair_chunk.
+template <typename T>
+static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip, T ca, T cb, T *pot_a, T *pot_b,
+                              hipStream_t s) {
+  int rc;
+  if ((rc = ensure_work(A, 1)) || (rc = ensure_lists(A, 1)) || (rc = ensure_work(B, 1)) ||
+      (rc = ensure_lists(B, 1)) || (rc = ensure_pair(A, B, 1)) || (rc = ensure_pair_md(A, B)))
+    return rc;
+  const DevTree &D = A->dt;
+  const int64_t N = A->n;
+  T *dips = (T *)A->dips;
+  hipEvent_t ev = prof_begin(A, FMM_PHASE_PERMUTE, s);
+  hipLaunchKernelGGL(k_permute_md<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, q, dip, D.perm, N, ca, cb,
+                     (T *)D.pts, dips);
+  FMM_HIP_TRY(hipGetLastError());
+  prof_end(A, FMM_PHASE_PERMUTE, ev, s);
+  const bool far = D.maxlevel >= 2;
+  if (far) {
+    FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
+    FMM_HIP_TRY(hipStreamWaitEvent(A->aux, A->ev_fork, 0));
+    if ((rc = eval_passes_pair<T, 1>(A, B, A->aux, B->ev_fork, nullptr, dips))) return rc;
+    FMM_HIP_TRY(hipEventRecord(A->ev_join, A->aux));
+    FMM_HIP_TRY(hipStreamWaitEvent(s, B->ev_fork, 0));
+  }
+  const T kappa = (T)B->kappa;
+  const T scale = (T)(1.0 / (4.0 * M_PI));
+  T *acc = (T *)A->pair_acc;
+  ev = prof_begin(A, FMM_PHASE_NEAR, s);
+  if (D.nitems > 0)
+    hipLaunchKernelGGL((k_near_pair_md<T>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts,
+                       (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng, acc, kappa, D.nitems);
+  FMM_HIP_TRY(hipGetLastError());
+  prof_end(A, FMM_PHASE_NEAR, ev, s);
+  if (far) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
+  ev = prof_begin(A, FMM_PHASE_FAR, s);
+  if (D.nitems > 0)
+    hipLaunchKernelGGL((k_far_pair<T, 1, false>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts,
+                       N, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)A->surf, A->nsurf, A->ld,
+                       D.far_off, D.far_idx, (const T *)acc, (const T *)A->equ, (const T *)A->eqd, (const T *)B->equ,
+                       (const T *)B->eqd, (T *)D.parts, (T *)B->dt.parts, D.perm, pot_a, (T *)nullptr, pot_b,
+                       (T *)nullptr, kappa, scale);
+  if (D.nsplit > 0) {
+    hipLaunchKernelGGL((k_leaf_parts<T, 1>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
+                       D.box_end, (const T *)D.parts, D.perm, N, pot_a, (T *)nullptr, scale);
+    hipLaunchKernelGGL((k_leaf_parts<T, 1>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
+                       D.box_end, (const T *)B->dt.parts, D.perm, N, pot_b, (T *)nullptr, scale);
+  }
+  FMM_HIP_TRY(hipGetLastError());
+  prof_end(A, FMM_PHASE_FAR, ev, s);
+  return FMM_OK;
+}
+
+int eval_pair_md_dispatch(fmm_plan *A, fmm_plan *B, const void *q, const void *dip, double ca, double cb, void *pot_a,
+                          void *pot_b, hipStream_t s) {
+  if (A->precision == FMM_FP64)
+    return eval_pair_md_typed<double>(A, B, (const double *)q, (const double *)dip, ca, cb, (double *)pot_a,
+                                      (double *)pot_b, s);
+  return eval_pair_md_typed<float>(A, B, (const float *)q, (const float *)dip, (float)ca, (float)cb, (float *)pot_a,
+                                   (float *)pot_b, s);
 }
 
 // dxyz_k = sum_c gbar_ck gphi_ck + q_ck gpsi_ck  (c over density columns)

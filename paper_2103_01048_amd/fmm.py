@@ -164,3 +164,20 @@ def eval_pair(plan_a: FMMPlan, plan_b: FMMPlan, q: torch.Tensor, gradient: bool 
     if squeeze:
         return (pa[0], ga[0] if ga is not None else None), (pb[0], gb[0] if gb is not None else None)
     return (pa, ga), (pb, gb)
+
+
+def eval_pair_md(plan_a: FMMPlan, plan_b: FMMPlan, q: torch.Tensor, dip: torch.Tensor, qscale_a: float = 1.0,
+                 qscale_b: float = 1.0):
+    """Potentials of monopole (q, (N,)) and dipole (dip, (N, 3)) sources for a
+    Laplace plan_a and a Yukawa plan_b sharing one tree (fmm_eval_pair_md):
+    pot_k = qscale_k G_k q + sum_j dip_j . grad_y g_k.  Returns (pot_a, pot_b)."""
+    n = plan_a.n
+    qq = q.reshape(-1).to(device=plan_a.device, dtype=plan_a.dtype).contiguous()
+    dd = dip.reshape(-1, 3).to(device=plan_a.device, dtype=plan_a.dtype).contiguous()
+    if qq.numel() != n or dd.shape[0] != n:
+        raise ValueError("q and dip must have one entry per point")
+    pa = torch.empty(n, dtype=plan_a.dtype, device=plan_a.device)
+    pb = torch.empty(n, dtype=plan_a.dtype, device=plan_a.device)
+    check(lib().fmm_eval_pair_md(plan_a._h, plan_b._h, _ptr(qq), _ptr(dd), float(qscale_a), float(qscale_b),
+                                 _ptr(pa), _ptr(pb), _stream()), "fmm_eval_pair_md")
+    return pa, pb

@@ -104,3 +104,55 @@ def test_pair_rejects_mismatched_plans():
     q = torch.zeros(len(x), device="cuda")
     with pytest.raises(ValueError):
         eval_pair(a, b, q)
+
+
+def _md_reference(x, q, dip, kern, kap, cq):
+    """sum_j [cq q_j g + dip_j . grad_y g] from the oracle's N-body sum:
+    grad_y g(x, y) = -grad_x g(x, y), so the dipole part is minus the
+    divergence-like sum of the target gradients of the three dipole columns."""
+    phi, _ = D.direct(x, x, q, kern, kap)
+    out = cq * phi
+    for d in range(3):
+        _, g = D.direct(x, x, dip[:, d], kern, kap)
+        out -= g[:, d]
+    return out
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-4), ("bf16x3", 1e-4)])
+def test_pair_monopole_dipole_matches_direct_sum(precision, tol):
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, eval_pair_md
+    x = _cloud(3000, seed=121)
+    rng = np.random.default_rng(121)
+    q = rng.standard_normal(len(x))
+    dip = rng.standard_normal((len(x), 3))
+    xt = torch.tensor(x, device="cuda")
+    a = FMMPlan(xt, kernel="laplace", p=8, ncrit=64, precision=precision)
+    b = FMMPlan(xt, kernel="yukawa", kappa=KAPPA, p=8, ncrit=64, precision=precision)
+    pa, pb = eval_pair_md(a, b, torch.tensor(q, device="cuda"), torch.tensor(dip, device="cuda"), -1.0, -0.05)
+    ra = _md_reference(x, q, dip, "laplace", 0.0, -1.0)
+    rb = _md_reference(x, q, dip, "yukawa", KAPPA, -0.05)
+    ea = D.rel_l2(pa.double().cpu().numpy(), ra)
+    eb = D.rel_l2(pb.double().cpu().numpy(), rb)
+    print(f"[pair md {precision}] laplace {ea:.2e} yukawa {eb:.2e}", flush=True)
+    assert ea < tol and eb < tol
+
+
+def test_pair_monopole_dipole_without_dipoles_equals_pair_potential():
+    torch = require_gpu()
+    from paper_2103_01048_amd import eval_pair, eval_pair_md
+    x = _cloud(2000, seed=122)
+    a, b = _plans(x, "fp64")
+    q = torch.tensor(np.random.default_rng(122).standard_normal(len(x)), device="cuda")
+    pa, pb = eval_pair_md(a, b, q, torch.zeros((len(x), 3), device="cuda", dtype=torch.float64), 2.0, 3.0)
+    (ra, _), (rb, _) = eval_pair(a, b, q, gradient=False)
+    assert _rel(pa, 2.0 * ra) < 1e-13 and _rel(pb, 3.0 * rb) < 1e-13
+
+
+def test_pair_monopole_dipole_rejects_plans_without_a_shared_tree():
+    torch = require_gpu()
+    from paper_2103_01048_amd import FmmError, eval_pair_md
+    x = _cloud(1500, seed=123)
+    a, b = _plans(x, "fp32", ncrit=64, ncrit_b=32)
+    with pytest.raises(FmmError):
+        eval_pair_md(a, b, torch.zeros(len(x), device="cuda"), torch.zeros((len(x), 3), device="cuda"))
