@@ -37,8 +37,9 @@ void set_error(const std::string &msg) { g_err = msg; }
 int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], double mx[3], bool *finite);
 int device_morton_sort(const double *xyz, int64_t n, const std::vector<int64_t> &off, const std::vector<double> &lo,
                        double W, hipStream_t s, std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out);
-int device_gather_points(const double *xyz, const int32_t *perm, int64_t n, const double shift[3], int prec,
-                         void *pts, hipStream_t s);
+int device_gather_leaves(const double *xyz, const int32_t *perm, const std::vector<int64_t> &lb,
+                         const std::vector<int64_t> &le, const std::vector<double> &lsh, int prec, void *pts,
+                         hipStream_t s);
 int eval_dispatch(fmm_plan *P, const void *q, int nrhs, void *pot, void *grad, hipStream_t s);
 int eval_pair_dispatch(fmm_plan *A, fmm_plan *B, const void *q, int nrhs, void *pot_a, void *grad_a, void *pot_b,
                        void *grad_b, hipStream_t s);
@@ -66,6 +67,13 @@ static int upload(fmm_plan *P, void **ptr, const std::vector<V> &h) {
   if (rc) return rc;
   if (!h.empty()) FMM_HIP_TRY(hipMemcpy(*ptr, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
   return FMM_OK;
+}
+
+// FP64 host values to the plan's working type.
+static int upload_real(fmm_plan *P, void **ptr, const std::vector<double> &h) {
+  if (P->precision == FMM_FP64) return upload(P, ptr, h);
+  std::vector<float> f(h.begin(), h.end());
+  return upload(P, ptr, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -623,18 +631,31 @@ static int upload_lists(fmm_plan *P) {
   std::vector<int32_t> leaves, hl, p2m, p2mo = {0};
   std::vector<char> x_direct(nb, 0);
   int64_t inter = 0, far_inter = 0;
-  // per leaf slot: merged near ranges and far surface boxes (bit 30 marks
-  // the leaf's own downward surface)
-  struct LeafSrc { std::vector<std::pair<int32_t, int32_t>> near; std::vector<int32_t> far; int64_t m; };
+  // Points are stored relative to their leaf's centre, so every near range
+  // holds the points of one leaf and carries that leaf (its centre offset
+  // from the target leaf is applied once per range).  Leaves by first point,
+  // to cut the range of a non-leaf W-list box into its leaves.
+  std::vector<std::pair<int64_t, int64_t>> leaf_at;  // (first point, box)
+  for (int64_t b = 0; b < nb; ++b)
+    if (!P->nchild[b] && P->end[b] > P->begin[b]) leaf_at.push_back({P->begin[b], b});
+  std::sort(leaf_at.begin(), leaf_at.end());
+  // per leaf slot: near ranges (one source leaf each) and far surface boxes
+  // (bit 30 marks the leaf's own downward surface)
+  struct Rng { int32_t j0, j1, src; };
+  struct LeafSrc { std::vector<Rng> near; std::vector<int32_t> far; int64_t m; };
   std::vector<LeafSrc> src;
   for (int64_t b = 0; b < nb; ++b) {
     if (P->nchild[b]) continue;
     leaves.push_back((int32_t)b);
     LeafSrc L;
     L.m = P->end[b] - P->begin[b];
-    std::vector<std::pair<int32_t, int32_t>> rg;
+    std::vector<Rng> rg;
     auto add_range = [&](int64_t a) {
-      rg.push_back({(int32_t)P->begin[a], (int32_t)P->end[a]});
+      auto it = std::lower_bound(leaf_at.begin(), leaf_at.end(), std::make_pair(P->begin[a], (int64_t)-1));
+      for (; it != leaf_at.end() && it->first < P->end[a]; ++it) {
+        const int64_t lf = it->second;
+        rg.push_back({(int32_t)P->begin[lf], (int32_t)P->end[lf], (int32_t)lf});
+      }
       inter += L.m * (P->end[a] - P->begin[a]);
     };
     for (int64_t k = P->loff[0][b]; k < P->loff[0][b + 1]; ++k) add_range(P->lidx[0][k]);
@@ -648,13 +669,9 @@ static int upload_lists(fmm_plan *P) {
       for (int64_t k = P->loff[3][b]; k < P->loff[3][b + 1]; ++k) add_range(P->lidx[3][k]);
     }
     if (P->level[b] >= 2) L.far.push_back((int32_t)b | (1 << 30));
-    // sort and merge contiguous ranges (disjoint; neighbouring boxes are
-    // often adjacent along the Morton curve)
-    std::sort(rg.begin(), rg.end());
-    for (auto &x : rg) {
-      if (!L.near.empty() && L.near.back().second == x.first) L.near.back().second = x.second;
-      else L.near.push_back(x);
-    }
+    // in point order (disjoint ranges)
+    std::sort(rg.begin(), rg.end(), [](const Rng &x, const Rng &y) { return x.j0 < y.j0; });
+    L.near = std::move(rg);
     far_inter += L.m * ns * (int64_t)L.far.size();
     hl.push_back(P->level[b] >= 2 ? 1 : 0);
     if (P->level[b] >= 2) { p2m.push_back((int32_t)b); p2mo.push_back((int32_t)p2m.size()); }
@@ -672,7 +689,7 @@ static int upload_lists(fmm_plan *P) {
   double total = 0;
   for (size_t sl = 0; sl < src.size(); ++sl) {
     double c = 0;
-    for (auto &r : src[sl].near) c += r.second - r.first;
+    for (auto &r : src[sl].near) c += r.j1 - r.j0;
     c += far_w * ns * (double)src[sl].far.size();
     for (int64_t t0 = 0; t0 < src[sl].m; t0 += 64) {
       const int split = (src[sl].m - t0) <= 32 ? 2 : 1;
@@ -681,7 +698,7 @@ static int upload_lists(fmm_plan *P) {
     }
   }
   const double cap = std::max(512.0, total / 16384.0);
-  struct Item { double cost; int32_t slot, code, part; std::vector<std::pair<int32_t, int32_t>> near; std::vector<int32_t> far; };
+  struct Item { double cost; int32_t slot, code, part; std::vector<Rng> near; std::vector<int32_t> far; };
   std::vector<Item> items;
   std::vector<int32_t> split_tiles;  // (slot, code, first part, nparts)
   int32_t nparts_total = 0;
@@ -708,10 +725,10 @@ static int upload_lists(fmm_plan *P) {
       acc = 0;
     };
     for (auto r : L.near) {
-      int32_t j = r.first;
-      while (j < r.second) {
-        const int32_t take = (int32_t)std::max<double>(1.0, std::min<double>(r.second - j, per - acc));
-        cur.near.push_back({j, j + take});
+      int32_t j = r.j0;
+      while (j < r.j1) {
+        const int32_t take = (int32_t)std::max<double>(1.0, std::min<double>(r.j1 - j, per - acc));
+        cur.near.push_back({j, j + take, r.src});
         acc += take;
         j += take;
         if (acc >= per - 0.5 && made < nparts - 1) flush();
@@ -727,11 +744,32 @@ static int upload_lists(fmm_plan *P) {
   }
   // longest items first
   std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+  // centre of box b relative to its molecule's root centre (FP64)
+  auto cen = [&](int64_t b, int d) {
+    const double sd = P->W / (double)(1ll << P->level[b]);
+    return (P->anchor[3 * b + d] + 0.5) * sd - 0.5 * P->W;
+  };
+  // near_o: per range, the source leaf's centre minus the target leaf's;
+  // far_o: per far entry, the surface box centre minus the target leaf's and
+  // the surface radius
   std::vector<int32_t> it4, no = {0}, nrng, fo = {0}, far;
+  std::vector<double> near_o, far_o;
   for (const Item &it : items) {
+    const int64_t tb = leaves[it.slot];
     it4.push_back(it.slot); it4.push_back(it.code); it4.push_back(it.part); it4.push_back(0);
-    for (auto &r : it.near) { nrng.push_back(r.first); nrng.push_back(r.second); }
+    for (auto &r : it.near) {
+      nrng.push_back(r.j0); nrng.push_back(r.j1);
+      for (int d = 0; d < 3; ++d) near_o.push_back(cen(r.src, d) - cen(tb, d));
+      near_o.push_back(0.0);
+    }
     no.push_back((int32_t)(nrng.size() / 2));
+    for (int32_t f : it.far) {
+      const bool own = (f >> 30) & 1;
+      const int64_t a = f & 0x3fffffff;
+      const double h = 0.5 * P->W / (double)(1ll << P->level[a]);
+      for (int d = 0; d < 3; ++d) far_o.push_back(cen(a, d) - cen(tb, d));
+      far_o.push_back(h * (own ? ALPHA_DE : ALPHA_UE));
+    }
     far.insert(far.end(), it.far.begin(), it.far.end());
     fo.push_back((int32_t)far.size());
   }
@@ -746,6 +784,8 @@ static int upload_lists(fmm_plan *P) {
   if ((rc = upload(P, (void **)&D.items, it4))) return rc;
   if ((rc = upload(P, (void **)&D.near_off, no))) return rc;
   if ((rc = upload(P, (void **)&D.near_rng, nrng))) return rc;
+  if ((rc = upload_real(P, &D.near_o, near_o))) return rc;
+  if ((rc = upload_real(P, &D.far_o, far_o))) return rc;
   if ((rc = upload(P, (void **)&D.far_off, fo))) return rc;
   if ((rc = upload(P, (void **)&D.far_idx, far))) return rc;
   if ((rc = upload(P, (void **)&D.split_tiles, split_tiles))) return rc;
@@ -759,10 +799,16 @@ static int upload_lists(fmm_plan *P) {
   if ((rc = upload(P, (void **)&P->d_p2m_off, p2mo))) return rc;
   // P2L: X lists of the boxes whose X list is not evaluated directly
   std::vector<int32_t> xb, xo = {0}, xi;
+  std::vector<double> x_o;  // per X entry: source leaf centre minus target box centre
   for (int64_t b = 0; b < nb; ++b) {
     if (P->loff[3][b + 1] == P->loff[3][b] || x_direct[b]) continue;
     xb.push_back((int32_t)b);
-    for (int64_t k = P->loff[3][b]; k < P->loff[3][b + 1]; ++k) xi.push_back((int32_t)P->lidx[3][k]);
+    for (int64_t k = P->loff[3][b]; k < P->loff[3][b + 1]; ++k) {
+      const int64_t a = P->lidx[3][k];  // a leaf
+      xi.push_back((int32_t)a);
+      for (int d = 0; d < 3; ++d) x_o.push_back(cen(a, d) - cen(b, d));
+      x_o.push_back(0.0);
+    }
     xo.push_back((int32_t)xi.size());
   }
   D.nxbox = (int)xb.size();
@@ -770,6 +816,7 @@ static int upload_lists(fmm_plan *P) {
   if ((rc = upload(P, (void **)&D.x_box, xb))) return rc;
   if ((rc = upload(P, (void **)&D.x_off, xo))) return rc;
   if ((rc = upload(P, (void **)&D.x_idx, xi))) return rc;
+  if ((rc = upload_real(P, &D.x_o, x_o))) return rc;
   // V pairs in GEMM order: (level, offset code, target)
   struct VP { int l, code; int64_t tgt, src; };
   std::vector<VP> vp;
@@ -1196,14 +1243,22 @@ static int setup_common(const double *xyz_dev, const std::vector<int64_t> &off, 
     const size_t es = precision == FMM_FP64 ? 8 : 4;
     if ((rc = dev_alloc(P, &P->dt.pts, (size_t)n * 4 * es))) break;
     P->dt.n = n;
-    for (int m = 0; m < nmol && !rc; ++m) {
-      // points relative to their molecule's cube centre
-      const int64_t nm = off[m + 1] - off[m];
-      if (nm == 0) continue;
-      double sh[3];
-      for (int d = 0; d < 3; ++d) sh[d] = P->mol_lo[3 * m + d] + 0.5 * P->W;
-      rc = device_gather_points(xyz_dev, P->dt.perm + off[m], nm, sh, precision,
-                                (char *)P->dt.pts + (size_t)off[m] * 4 * es, s);
+    {
+      // points relative to their leaf's centre (the difference taken in FP64,
+      // rounded once): single precision then resolves a pair's separation to
+      // a fraction of a leaf width, wherever the molecule sits
+      std::vector<int64_t> lb, le;
+      std::vector<double> lsh;
+      for (int64_t b = 0; b < (int64_t)P->level.size(); ++b) {
+        if (P->nchild[b] || P->end[b] == P->begin[b]) continue;
+        const int m = P->mol[b];
+        const double sd = P->W / (double)(1ll << P->level[b]);
+        lb.push_back(P->begin[b]);
+        le.push_back(P->end[b]);
+        for (int d = 0; d < 3; ++d)
+          lsh.push_back(P->mol_lo[3 * m + d] + 0.5 * P->W + ((P->anchor[3 * b + d] + 0.5) * sd - 0.5 * P->W));
+      }
+      rc = device_gather_leaves(xyz_dev, P->dt.perm, lb, le, lsh, precision, P->dt.pts, s);
     }
     if (rc) break;
     if ((rc = upload_lists(P))) break;

@@ -98,18 +98,20 @@ struct PassLists {
 struct DevTree {
   int64_t n = 0;
   int nbox = 0, nleaf = 0, maxlevel = 0;
-  // sorted points, shifted to the root-cube centre; xyz + pad, in T
+  // sorted points relative to their leaf's centre; xyz + density slot, in T
   void *pts = nullptr;
   int32_t *perm = nullptr;      // sorted -> caller index
   // boxes
-  void *box_geom = nullptr;     // T4: centre xyz (shifted), half width
+  void *box_geom = nullptr;     // T4: centre xyz (relative to the molecule's root centre), half width
   int32_t *box_begin = nullptr, *box_end = nullptr;
   int32_t *leaves = nullptr;    // leaf box ids
   // leaf work items: (leaf slot, first target | split << 24, part or -1, 0)
   int32_t *items = nullptr;
   int nitems = 0;
   int32_t *near_off = nullptr;  // per item, into near_rng
-  int32_t *near_rng = nullptr;  // (begin, end) point ranges of near sources
+  int32_t *near_rng = nullptr;  // (begin, end) point ranges of near sources, one leaf each
+  void *near_o = nullptr;       // T4 per range: source leaf centre - target leaf centre
+  void *far_o = nullptr;        // T4 per far entry: surface box centre - target leaf centre, radius
   int32_t *far_off = nullptr;   // per item, into far_idx
   int32_t *far_idx = nullptr;   // surface boxes (bit 30: own downward surface)
   int32_t *split_tiles = nullptr;  // (slot, code, first part, nparts) per split tile
@@ -117,6 +119,7 @@ struct DevTree {
   void *parts = nullptr;        // partial sums of split tiles
   int32_t *x_box = nullptr;     // boxes with a non-empty X list
   int32_t *x_off = nullptr, *x_idx = nullptr;
+  void *x_o = nullptr;          // T4 per X entry: source leaf centre - target box centre
   int nxbox = 0;
   int32_t *v_tgt = nullptr;     // boxes at level >= 2 (M2L sums)
   int32_t *v_off = nullptr;     // pair ids of each such box (CSR)

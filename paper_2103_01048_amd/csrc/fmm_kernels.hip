@@ -103,16 +103,21 @@ __global__ void k_morton(const double *__restrict__ xyz, int64_t n, double lox, 
   idx[i] = (int32_t)(base + i);
 }
 
+// One workgroup per leaf: its sorted points minus the leaf's absolute centre
+// (lsh), in FP64, rounded once to T.
 template <typename T>
-__global__ void k_gather_points(const double *__restrict__ xyz, const int32_t *__restrict__ perm, int64_t n,
-                                double sx, double sy, double sz, T *__restrict__ pts) {
-  int64_t i = blockIdx.x * 256ll + threadIdx.x;
-  if (i >= n) return;
-  int64_t j = perm[i];
-  pts[i * 4 + 0] = (T)(xyz[j * 3 + 0] - sx);
-  pts[i * 4 + 1] = (T)(xyz[j * 3 + 1] - sy);
-  pts[i * 4 + 2] = (T)(xyz[j * 3 + 2] - sz);
-  pts[i * 4 + 3] = (T)0;
+__global__ void k_gather_leaves(const double *__restrict__ xyz, const int32_t *__restrict__ perm,
+                                const int64_t *__restrict__ lb, const int64_t *__restrict__ le,
+                                const double *__restrict__ lsh, T *__restrict__ pts) {
+  const int leaf = blockIdx.x;
+  const double sx = lsh[3 * leaf], sy = lsh[3 * leaf + 1], sz = lsh[3 * leaf + 2];
+  for (int64_t i = lb[leaf] + threadIdx.x; i < le[leaf]; i += blockDim.x) {
+    const int64_t j = perm[i];
+    pts[i * 4 + 0] = (T)(xyz[j * 3 + 0] - sx);
+    pts[i * 4 + 1] = (T)(xyz[j * 3 + 1] - sy);
+    pts[i * 4 + 2] = (T)(xyz[j * 3 + 2] - sz);
+    pts[i * 4 + 3] = (T)0;
+  }
 }
 
 int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], double mx[3], bool *finite) {
@@ -197,15 +202,36 @@ int device_morton_sort(const double *xyz, int64_t n, const std::vector<int64_t> 
   return rc;
 }
 
-int device_gather_points(const double *xyz, const int32_t *perm, int64_t n, const double shift[3], int prec,
-                         void *pts, hipStream_t s) {
-  if (n == 0) return FMM_OK;
-  dim3 g((unsigned)((n + 255) / 256));
-  if (prec == FMM_FP64)
-    hipLaunchKernelGGL(k_gather_points<double>, g, dim3(256), 0, s, xyz, perm, n, shift[0], shift[1], shift[2], (double *)pts);
-  else
-    hipLaunchKernelGGL(k_gather_points<float>, g, dim3(256), 0, s, xyz, perm, n, shift[0], shift[1], shift[2], (float *)pts);
-  FMM_HIP_TRY(hipGetLastError());
+int device_gather_leaves(const double *xyz, const int32_t *perm, const std::vector<int64_t> &lb,
+                         const std::vector<int64_t> &le, const std::vector<double> &lsh, int prec, void *pts,
+                         hipStream_t s) {
+  const size_t nl = lb.size();
+  if (nl == 0) return FMM_OK;
+  int64_t *d_lb = nullptr, *d_le = nullptr;
+  double *d_sh = nullptr;
+  hipError_t e = hipMalloc(&d_lb, nl * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&d_le, nl * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&d_sh, nl * 3 * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpyAsync(d_lb, lb.data(), nl * sizeof(int64_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_le, le.data(), nl * sizeof(int64_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_sh, lsh.data(), nl * 3 * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    if (prec == FMM_FP64)
+      hipLaunchKernelGGL(k_gather_leaves<double>, dim3((unsigned)nl), dim3(128), 0, s, xyz, perm, d_lb, d_le, d_sh,
+                         (double *)pts);
+    else
+      hipLaunchKernelGGL(k_gather_leaves<float>, dim3((unsigned)nl), dim3(128), 0, s, xyz, perm, d_lb, d_le, d_sh,
+                         (float *)pts);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_lb);
+  (void)hipFree(d_le);
+  (void)hipFree(d_sh);
+  if (e != hipSuccess) {
+    set_error(std::string("gather: ") + hipGetErrorString(e));
+    return FMM_EHIP;
+  }
   return FMM_OK;
 }
 
@@ -538,8 +564,9 @@ template <typename T, int NR, int KERN>
 __global__ __launch_bounds__(64) void k_leaf_eval(
     const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts,
     const T *__restrict__ qs, int64_t N, const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end,
-    const T *__restrict__ box_geom, const T *__restrict__ surf, int nsurf, int ld, const int32_t *__restrict__ near_off,
-    const int32_t *__restrict__ near_rng, const int32_t *__restrict__ far_off, const int32_t *__restrict__ far_idx,
+    const T *__restrict__ surf, int nsurf, int ld, const int32_t *__restrict__ near_off,
+    const int32_t *__restrict__ near_rng, const T *__restrict__ near_o, const int32_t *__restrict__ far_off,
+    const int32_t *__restrict__ far_idx, const T *__restrict__ far_o,
     const T *__restrict__ equ, const T *__restrict__ eqd, T *__restrict__ parts, const int32_t *__restrict__ perm,
     T *__restrict__ pot, T *__restrict__ grad, T kappa, T scale) {
   using V4 = typename Vec4<T>::type;
@@ -570,6 +597,8 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
   for (int u = near_off[item]; u < u1; ++u) {
     const int j0 = near_rng[2 * u], j1 = near_rng[2 * u + 1];
     const bool self = j0 < le && lb < j1;  // overlaps the tile's own leaf
+    // targets in the source leaf's frame (one shift per range)
+    const T xt = xi - near_o[4 * u], yt = yi - near_o[4 * u + 1], zt = zi - near_o[4 * u + 2];
     if (split == 1) {
       auto body = [&](int j, auto chk) {
         const V4 sp = p4[j];
@@ -579,7 +608,7 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
 #pragma unroll
           for (int c = 0; c < NR; ++c) qv[c] = qs[(int64_t)c * N + j];
         }
-        leaf_pair<T, KERN, decltype(chk)::value, NR>(xi, yi, zi, sp[0], sp[1], sp[2], qv, kappa, kl2, ap, agx, agy, agz);
+        leaf_pair<T, KERN, decltype(chk)::value, NR>(xt, yt, zt, sp[0], sp[1], sp[2], qv, kappa, kl2, ap, agx, agy, agz);
       };
       if (self) {
 #pragma unroll 4
@@ -601,7 +630,7 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
 #pragma unroll
           for (int c = 0; c < NR; ++c) qv[c] = ok ? qs[(int64_t)c * N + jj] : (T)0;
         }
-        leaf_pair<T, KERN, decltype(chk)::value, NR>(xi, yi, zi, sp[0], sp[1], sp[2], qv, kappa, kl2, ap, agx, agy, agz);
+        leaf_pair<T, KERN, decltype(chk)::value, NR>(xt, yt, zt, sp[0], sp[1], sp[2], qv, kappa, kl2, ap, agx, agy, agz);
       };
       if (self) {
 #pragma unroll 2
@@ -618,8 +647,8 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
     const int fe = far_idx[k];
     const bool own = (fe >> 30) & 1;
     const int a = fe & 0x3fffffff;
-    const T cx = box_geom[a * 4 + 0], cy = box_geom[a * 4 + 1], cz = box_geom[a * 4 + 2];
-    const T rr = box_geom[a * 4 + 3] * (own ? (T)ALPHA_DE : (T)ALPHA_UE);
+    // surface centre in the target leaf's frame, and radius
+    const T cx = far_o[4 * k], cy = far_o[4 * k + 1], cz = far_o[4 * k + 2], rr = far_o[4 * k + 3];
     const T *__restrict__ dens = (own ? eqd : equ) + (int64_t)a * NR * ld;
     if (split == 1) {
 #pragma unroll 4
@@ -762,8 +791,8 @@ template <typename T, int NR>
 __global__ __launch_bounds__(64) void k_near_pair(
     const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts,
     const T *__restrict__ qs, int64_t N, const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end,
-    const int32_t *__restrict__ near_off, const int32_t *__restrict__ near_rng, T *__restrict__ acc, T kappa,
-    int nitems) {
+    const int32_t *__restrict__ near_off, const int32_t *__restrict__ near_rng, const T *__restrict__ near_o,
+    T *__restrict__ acc, T kappa, int nitems) {
   using V4 = typename Vec4<T>::type;
   const V4 *__restrict__ p4 = reinterpret_cast<const V4 *>(pts);
   // one wave per item (the loop also serves a grid smaller than the item
@@ -790,6 +819,7 @@ __global__ __launch_bounds__(64) void k_near_pair(
     for (int u = near_off[item]; u < u1; ++u) {
       const int j0 = near_rng[2 * u], j1 = near_rng[2 * u + 1];
       const bool self = j0 < le && lb < j1;
+      const T xt = xi - near_o[4 * u], yt = yi - near_o[4 * u + 1], zt = zi - near_o[4 * u + 2];
       if (split == 1) {
         auto body = [&](int j, auto chk) {
           const V4 sp = p4[j];
@@ -799,7 +829,7 @@ __global__ __launch_bounds__(64) void k_near_pair(
 #pragma unroll
             for (int c = 0; c < NR; ++c) qv[c] = qs[(int64_t)c * N + j];
           }
-          leaf_pair_ly<T, decltype(chk)::value, NR>(xi, yi, zi, sp[0], sp[1], sp[2], qv, qv, kappa, kl2, pa, xa, ya, za,
+          leaf_pair_ly<T, decltype(chk)::value, NR>(xt, yt, zt, sp[0], sp[1], sp[2], qv, qv, kappa, kl2, pa, xa, ya, za,
                                                      pb, xb, yb, zb);
         };
         if (self) {
@@ -820,7 +850,7 @@ __global__ __launch_bounds__(64) void k_near_pair(
 #pragma unroll
             for (int c = 0; c < NR; ++c) qv[c] = ok ? qs[(int64_t)c * N + jj] : (T)0;
           }
-          leaf_pair_ly<T, decltype(chk)::value, NR>(xi, yi, zi, sp[0], sp[1], sp[2], qv, qv, kappa, kl2, pa, xa, ya, za,
+          leaf_pair_ly<T, decltype(chk)::value, NR>(xt, yt, zt, sp[0], sp[1], sp[2], qv, qv, kappa, kl2, pa, xa, ya, za,
                                                      pb, xb, yb, zb);
         };
         if (self) {
@@ -883,9 +913,9 @@ __device__ __forceinline__ void leaf_store(int part, int half, bool active, int 
 template <typename T, int NR, bool GRAD>
 __global__ __launch_bounds__(64) void k_far_pair(
     const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts, int64_t N,
-    const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end, const T *__restrict__ box_geom,
-    const T *__restrict__ surf, int nsurf, int ld, const int32_t *__restrict__ far_off,
-    const int32_t *__restrict__ far_idx, const T *__restrict__ acc, const T *__restrict__ equ_a,
+    const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end, const T *__restrict__ surf,
+    int nsurf, int ld, const int32_t *__restrict__ far_off, const int32_t *__restrict__ far_idx,
+    const T *__restrict__ far_o, const T *__restrict__ acc, const T *__restrict__ equ_a,
     const T *__restrict__ eqd_a, const T *__restrict__ equ_b, const T *__restrict__ eqd_b, T *__restrict__ parts_a,
     T *__restrict__ parts_b, const int32_t *__restrict__ perm, T *__restrict__ pot_a, T *__restrict__ grad_a,
     T *__restrict__ pot_b, T *__restrict__ grad_b, T kappa, T scale) {
@@ -930,8 +960,7 @@ __global__ __launch_bounds__(64) void k_far_pair(
     const int fe = far_idx[k];
     const bool own = (fe >> 30) & 1;
     const int bx = fe & 0x3fffffff;
-    const T cx = box_geom[bx * 4 + 0], cy = box_geom[bx * 4 + 1], cz = box_geom[bx * 4 + 2];
-    const T rr = box_geom[bx * 4 + 3] * (own ? (T)ALPHA_DE : (T)ALPHA_UE);
+    const T cx = far_o[4 * k], cy = far_o[4 * k + 1], cz = far_o[4 * k + 2], rr = far_o[4 * k + 3];
     const T *__restrict__ da = (own ? eqd_a : equ_a) + (int64_t)bx * NR * ld;
     const T *__restrict__ db = (own ? eqd_b : equ_b) + (int64_t)bx * NR * ld;
     if (split == 1) {
@@ -981,6 +1010,7 @@ __global__ __launch_bounds__(64) void k_far_pair(
 template <typename T, int NR>
 __global__ __launch_bounds__(512) void k_surf_eval_pair(
     const int32_t *__restrict__ tbox, const int32_t *__restrict__ src_off, const int32_t *__restrict__ src_idx,
+    const T *__restrict__ src_o,
     const T *__restrict__ pts, const T *__restrict__ qs, int64_t N, const int32_t *__restrict__ box_begin,
     const int32_t *__restrict__ box_end, const T *__restrict__ box_geom, const T *__restrict__ surf, int nsurf,
     int ld, T alpha, T *__restrict__ YA, T *__restrict__ YB, int mode, T kappa) {
@@ -988,7 +1018,9 @@ __global__ __launch_bounds__(512) void k_surf_eval_pair(
   const int slot = blockIdx.x;
   const int b = tbox[slot];
   const int tid = threadIdx.x, nt = blockDim.x;
-  const T cx = box_geom[b * 4 + 0], cy = box_geom[b * 4 + 1], cz = box_geom[b * 4 + 2];
+  // target surface in the box's own frame; sources (leaf frames) shifted by
+  // src_o (source leaf centre - box centre; none: the box itself)
+  const T cx = 0, cy = 0, cz = 0;
   const T rr = box_geom[b * 4 + 3] * alpha;
   const int ii = tid < nsurf ? tid : 0;
   const T tx = cx + rr * surf[ii * 4 + 0], ty = cy + rr * surf[ii * 4 + 1], tz = cz + rr * surf[ii * 4 + 2];
@@ -997,13 +1029,15 @@ __global__ __launch_bounds__(512) void k_surf_eval_pair(
   for (int r = 0; r < NR; ++r) accA[r] = accB[r] = (T)0;
   for (int k = src_off[slot]; k < src_off[slot + 1]; ++k) {
     const int a = src_idx[k];
+    const T ox = src_o ? src_o[4 * k] : (T)0, oy = src_o ? src_o[4 * k + 1] : (T)0,
+            oz = src_o ? src_o[4 * k + 2] : (T)0;
     const int sb = box_begin[a], se = box_end[a];
     for (int c0 = sb; c0 < se; c0 += nt) {
       const int j = c0 + tid;
       if (j < se) {
-        sx[tid] = pts[(int64_t)j * 4 + 0];
-        sy[tid] = pts[(int64_t)j * 4 + 1];
-        sz[tid] = pts[(int64_t)j * 4 + 2];
+        sx[tid] = pts[(int64_t)j * 4 + 0] + ox;
+        sy[tid] = pts[(int64_t)j * 4 + 1] + oy;
+        sz[tid] = pts[(int64_t)j * 4 + 2] + oz;
 #pragma unroll
         for (int r = 0; r < NR; ++r) sq[r][tid] = qs[(int64_t)r * N + j];
       }
@@ -1060,6 +1094,7 @@ __global__ void k_permute_md(const T *__restrict__ q, const T *__restrict__ dip,
 template <typename T>
 __global__ __launch_bounds__(512) void k_surf_eval_pair_md(
     const int32_t *__restrict__ tbox, const int32_t *__restrict__ src_off, const int32_t *__restrict__ src_idx,
+    const T *__restrict__ src_o,
     const T *__restrict__ pts, const T *__restrict__ dips, const int32_t *__restrict__ box_begin,
     const int32_t *__restrict__ box_end, const T *__restrict__ box_geom, const T *__restrict__ surf, int nsurf,
     int ld, T alpha, T *__restrict__ YA, T *__restrict__ YB, T kappa) {
@@ -1067,20 +1102,24 @@ __global__ __launch_bounds__(512) void k_surf_eval_pair_md(
   const int slot = blockIdx.x;
   const int b = tbox[slot];
   const int tid = threadIdx.x, nt = blockDim.x;
-  const T cx = box_geom[b * 4 + 0], cy = box_geom[b * 4 + 1], cz = box_geom[b * 4 + 2];
+  // target surface in the box's own frame; sources (leaf frames) shifted by
+  // src_o (source leaf centre - box centre; none: the box itself)
+  const T cx = 0, cy = 0, cz = 0;
   const T rr = box_geom[b * 4 + 3] * alpha;
   const int ii = tid < nsurf ? tid : 0;
   const T tx = cx + rr * surf[ii * 4 + 0], ty = cy + rr * surf[ii * 4 + 1], tz = cz + rr * surf[ii * 4 + 2];
   T accA = 0, accB = 0;
   for (int k = src_off[slot]; k < src_off[slot + 1]; ++k) {
     const int a = src_idx[k];
+    const T ox = src_o ? src_o[4 * k] : (T)0, oy = src_o ? src_o[4 * k + 1] : (T)0,
+            oz = src_o ? src_o[4 * k + 2] : (T)0;
     const int sb = box_begin[a], se = box_end[a];
     for (int c0 = sb; c0 < se; c0 += nt) {
       const int j = c0 + tid;
       if (j < se) {
-        sx[tid] = pts[(int64_t)j * 4 + 0];
-        sy[tid] = pts[(int64_t)j * 4 + 1];
-        sz[tid] = pts[(int64_t)j * 4 + 2];
+        sx[tid] = pts[(int64_t)j * 4 + 0] + ox;
+        sy[tid] = pts[(int64_t)j * 4 + 1] + oy;
+        sz[tid] = pts[(int64_t)j * 4 + 2] + oz;
         sqa[tid] = pts[(int64_t)j * 4 + 3];
         sdx[tid] = dips[(int64_t)j * 4 + 0];
         sdy[tid] = dips[(int64_t)j * 4 + 1];
@@ -1130,8 +1169,8 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_near_pair_md(
     const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts,
     const T *__restrict__ dips, const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end,
-    const int32_t *__restrict__ near_off, const int32_t *__restrict__ near_rng, T *__restrict__ acc, T kappa,
-    int nitems) {
+    const int32_t *__restrict__ near_off, const int32_t *__restrict__ near_rng, const T *__restrict__ near_o,
+    T *__restrict__ acc, T kappa, int nitems) {
   using V4 = typename Vec4<T>::type;
   const V4 *__restrict__ p4 = reinterpret_cast<const V4 *>(pts);
   const V4 *__restrict__ d4 = reinterpret_cast<const V4 *>(dips);
@@ -1155,13 +1194,14 @@ __global__ __launch_bounds__(64) void k_near_pair_md(
     for (int u = near_off[item]; u < u1; ++u) {
       const int j0 = near_rng[2 * u], j1 = near_rng[2 * u + 1];
       const bool self = j0 < le && lb < j1;
+      const T xt = xi - near_o[4 * u], yt = yi - near_o[4 * u + 1], zt = zi - near_o[4 * u + 2];
       if (split == 1) {
         if (self) {
 #pragma unroll 4
-          for (int j = j0; j < j1; ++j) leaf_pair_md<T, true>(xi, yi, zi, p4[j], d4[j], kappa, kl2, pa, pb);
+          for (int j = j0; j < j1; ++j) leaf_pair_md<T, true>(xt, yt, zt, p4[j], d4[j], kappa, kl2, pa, pb);
         } else {
 #pragma unroll 8
-          for (int j = j0; j < j1; ++j) leaf_pair_md<T, false>(xi, yi, zi, p4[j], d4[j], kappa, kl2, pa, pb);
+          for (int j = j0; j < j1; ++j) leaf_pair_md<T, false>(xt, yt, zt, p4[j], d4[j], kappa, kl2, pa, pb);
         }
       } else {
         // split: lane half h takes sources j0 + h, j0 + h + 2, ...; a missing
@@ -1171,7 +1211,7 @@ __global__ __launch_bounds__(64) void k_near_pair_md(
           const bool ok = jj < j1;
           V4 sp = p4[ok ? jj : j], sd = d4[ok ? jj : j];
           if (!ok) { sp[3] = (T)0; sd = V4{0, 0, 0, 0}; }
-          leaf_pair_md<T, decltype(chk)::value>(xi, yi, zi, sp, sd, kappa, kl2, pa, pb);
+          leaf_pair_md<T, decltype(chk)::value>(xt, yt, zt, sp, sd, kappa, kl2, pa, pb);
         };
         if (self) {
 #pragma unroll 2
@@ -1194,6 +1234,7 @@ __global__ __launch_bounds__(64) void k_near_pair_md(
 template <typename T, int NR, int KERN>
 __global__ __launch_bounds__(256) void k_surf_eval(
     const int32_t *__restrict__ tbox, const int32_t *__restrict__ src_off, const int32_t *__restrict__ src_idx,
+    const T *__restrict__ src_o,
     const T *__restrict__ pts, const T *__restrict__ qs, int64_t N, const int32_t *__restrict__ box_begin,
     const int32_t *__restrict__ box_end, const T *__restrict__ box_geom, const T *__restrict__ surf, int nsurf,
     int ld, T alpha, T *__restrict__ Y, int mode, T kappa) {
@@ -1201,7 +1242,9 @@ __global__ __launch_bounds__(256) void k_surf_eval(
   const int slot = blockIdx.x;
   const int b = tbox[slot];
   const int tid = threadIdx.x;
-  const T cx = box_geom[b * 4 + 0], cy = box_geom[b * 4 + 1], cz = box_geom[b * 4 + 2];
+  // target surface in the box's own frame; sources (leaf frames) shifted by
+  // src_o (source leaf centre - box centre; none: the box itself)
+  const T cx = 0, cy = 0, cz = 0;
   const T rr = box_geom[b * 4 + 3] * alpha;
   for (int i0 = 0; i0 < nsurf; i0 += 512) {
     T tx[2], ty[2], tz[2];
@@ -1218,13 +1261,15 @@ __global__ __launch_bounds__(256) void k_surf_eval(
     }
     for (int s = src_off[slot]; s < src_off[slot + 1]; ++s) {
       const int a = src_idx[s];
+      const T ox = src_o ? src_o[4 * s] : (T)0, oy = src_o ? src_o[4 * s + 1] : (T)0,
+              oz = src_o ? src_o[4 * s + 2] : (T)0;
       const int sb = box_begin[a], se = box_end[a];
       for (int c0 = sb; c0 < se; c0 += 256) {
         const int j = c0 + tid;
         if (j < se) {
-          sx[tid] = pts[(int64_t)j * 4 + 0];
-          sy[tid] = pts[(int64_t)j * 4 + 1];
-          sz[tid] = pts[(int64_t)j * 4 + 2];
+          sx[tid] = pts[(int64_t)j * 4 + 0] + ox;
+          sy[tid] = pts[(int64_t)j * 4 + 1] + oy;
+          sz[tid] = pts[(int64_t)j * 4 + 2] + oz;
 #pragma unroll
           for (int r = 0; r < NR; ++r) sq[r][tid] = qs[(int64_t)r * N + j];
         }
@@ -1431,7 +1476,7 @@ static int eval_passes(fmm_plan *P, hipStream_t s) {
   ev = prof_begin(P, FMM_PHASE_P2M, s);
   if (P->p2m_count > 0)
     hipLaunchKernelGGL((k_surf_eval<T, NR, KERN>), dim3(P->p2m_count), dim3(256), 0, s, P->d_p2m_box,
-                       P->d_p2m_off, P->d_p2m_box, (const T *)D.pts, qs, N, D.box_begin, D.box_end,
+                       P->d_p2m_off, P->d_p2m_box, (const T *)nullptr, (const T *)D.pts, qs, N, D.box_begin, D.box_end,
                        (const T *)D.box_geom, (const T *)P->surf, P->nsurf, ld, (T)ALPHA_UC, chku, 0, kappa);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(P, FMM_PHASE_P2M, ev, s);
@@ -1456,7 +1501,7 @@ static int eval_passes(fmm_plan *P, hipStream_t s) {
   ev = prof_begin(P, FMM_PHASE_P2L, s);
   if (D.nxbox > 0)
     hipLaunchKernelGGL((k_surf_eval<T, NR, KERN>), dim3(D.nxbox), dim3(256), 0, s, D.x_box, D.x_off, D.x_idx,
-                       (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom,
+                       (const T *)D.x_o, (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom,
                        (const T *)P->surf, P->nsurf, ld, (T)ALPHA_DC, chk, 0, kappa);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(P, FMM_PHASE_P2L, ev, s);
@@ -1511,12 +1556,12 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t 
   ev = prof_begin(A, FMM_PHASE_P2M, s);
   if (A->p2m_count > 0 && dips)
     hipLaunchKernelGGL((k_surf_eval_pair_md<T>), dim3(A->p2m_count), dim3(sthreads), 0, s, A->d_p2m_box,
-                       A->d_p2m_off, A->d_p2m_box, (const T *)D.pts, dips, D.box_begin, D.box_end,
+                       A->d_p2m_off, A->d_p2m_box, (const T *)nullptr, (const T *)D.pts, dips, D.box_begin, D.box_end,
                        (const T *)D.box_geom, (const T *)A->surf, A->nsurf, ld, (T)ALPHA_UC, W(A->chku), W(B->chku),
                        kappa);
   else if (A->p2m_count > 0)
     hipLaunchKernelGGL((k_surf_eval_pair<T, NR>), dim3(A->p2m_count), dim3(sthreads), 0, s, A->d_p2m_box,
-                       A->d_p2m_off, A->d_p2m_box, (const T *)D.pts, qs, N, D.box_begin, D.box_end,
+                       A->d_p2m_off, A->d_p2m_box, (const T *)nullptr, (const T *)D.pts, qs, N, D.box_begin, D.box_end,
                        (const T *)D.box_geom, (const T *)A->surf, A->nsurf, ld, (T)ALPHA_UC, W(A->chku), W(B->chku), 0,
                        kappa);
   FMM_HIP_TRY(hipGetLastError());
@@ -1525,11 +1570,11 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t 
   ev = prof_begin(A, FMM_PHASE_P2L, s);
   if (D.nxbox > 0 && dips)
     hipLaunchKernelGGL((k_surf_eval_pair_md<T>), dim3(D.nxbox), dim3(sthreads), 0, s, D.x_box, D.x_off, D.x_idx,
-                       (const T *)D.pts, dips, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)A->surf,
+                       (const T *)D.x_o, (const T *)D.pts, dips, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)A->surf,
                        A->nsurf, ld, (T)ALPHA_DC, W(A->chk), W(B->chk), kappa);
   else if (D.nxbox > 0)
     hipLaunchKernelGGL((k_surf_eval_pair<T, NR>), dim3(D.nxbox), dim3(sthreads), 0, s, D.x_box, D.x_off, D.x_idx,
-                       (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)A->surf,
+                       (const T *)D.x_o, (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)A->surf,
                        A->nsurf, ld, (T)ALPHA_DC, W(A->chk), W(B->chk), 0, kappa);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_P2L, ev, s);
@@ -1592,9 +1637,9 @@ static int eval_chunk(fmm_plan *P, const T *q, T *pot, T *grad, hipStream_t s) {
   hipEvent_t ev = prof_begin(P, FMM_PHASE_LEAF, s);
   if (D.nitems > 0)
     hipLaunchKernelGGL((k_leaf_eval<T, NR, KERN>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
-                       (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)P->surf,
-                       P->nsurf, ld, D.near_off, D.near_rng, D.far_off, D.far_idx, equ, eqd, (T *)D.parts, D.perm,
-                       pot, grad, kappa, scale);
+                       (const T *)D.pts, qs, N, D.box_begin, D.box_end, (const T *)P->surf, P->nsurf, ld,
+                       D.near_off, D.near_rng, (const T *)D.near_o, D.far_off, D.far_idx, (const T *)D.far_o, equ,
+                       eqd, (T *)D.parts, D.perm, pot, grad, kappa, scale);
   if (D.nsplit > 0)
     hipLaunchKernelGGL((k_leaf_parts<T, NR>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
                        D.box_end, (const T *)D.parts, D.perm, N, pot, grad, scale);
@@ -1666,15 +1711,15 @@ static int eval_pair_chunk(fmm_plan *A, fmm_plan *B, const T *q, T *pot_a, T *gr
   if (D.nitems > 0)
     hipLaunchKernelGGL((k_near_pair<T, NR>), dim3(D.nitems), dim3(64), 0, s, D.items,
                        D.leaves, (const T *)D.pts, (const T *)A->qs, N, D.box_begin, D.box_end, D.near_off,
-                       D.near_rng, acc, kappa, D.nitems);
+                       D.near_rng, (const T *)D.near_o, acc, kappa, D.nitems);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_NEAR, ev, s);
   if (far) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
   ev = prof_begin(A, FMM_PHASE_FAR, s);
   if (D.nitems > 0)
     hipLaunchKernelGGL((k_far_pair<T, NR, true>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts, N,
-                       D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)A->surf, A->nsurf, A->ld, D.far_off,
-                       D.far_idx, (const T *)acc, (const T *)A->equ, (const T *)A->eqd, (const T *)B->equ,
+                       D.box_begin, D.box_end, (const T *)A->surf, A->nsurf, A->ld, D.far_off, D.far_idx,
+                       (const T *)D.far_o, (const T *)acc, (const T *)A->equ, (const T *)A->eqd, (const T *)B->equ,
                        (const T *)B->eqd, (T *)D.parts, (T *)B->dt.parts, D.perm, pot_a, grad_a, pot_b, grad_b, kappa,
                        scale);
   if (D.nsplit > 0) {
@@ -1755,15 +1800,16 @@ static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip
   ev = prof_begin(A, FMM_PHASE_NEAR, s);
   if (D.nitems > 0)
     hipLaunchKernelGGL((k_near_pair_md<T>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts,
-                       (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng, acc, kappa, D.nitems);
+                       (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng, (const T *)D.near_o, acc,
+                       kappa, D.nitems);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_NEAR, ev, s);
   if (far) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
   ev = prof_begin(A, FMM_PHASE_FAR, s);
   if (D.nitems > 0)
     hipLaunchKernelGGL((k_far_pair<T, 1, false>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts,
-                       N, D.box_begin, D.box_end, (const T *)D.box_geom, (const T *)A->surf, A->nsurf, A->ld,
-                       D.far_off, D.far_idx, (const T *)acc, (const T *)A->equ, (const T *)A->eqd, (const T *)B->equ,
+                       N, D.box_begin, D.box_end, (const T *)A->surf, A->nsurf, A->ld, D.far_off, D.far_idx,
+                       (const T *)D.far_o, (const T *)acc, (const T *)A->equ, (const T *)A->eqd, (const T *)B->equ,
                        (const T *)B->eqd, (T *)D.parts, (T *)B->dt.parts, D.perm, pot_a, (T *)nullptr, pot_b,
                        (T *)nullptr, kappa, scale);
   if (D.nsplit > 0) {
