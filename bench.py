@@ -61,7 +61,7 @@ def measured_traffic(kernel: str, phase: str, precision: str):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_2103_01048_amd", "csrc", "fmm_kernels.hip")
     names = {"leaf": f"void fmm::k_leaf_eval<float, 1, {1 if kernel == 'yukawa' else 0}>",
-             "near": "void fmm::k_near_pair<float, 1>", "far": "void fmm::k_far_pair<float, 1>"}
+             "near": "void fmm::k_near_pair<float, 1>", "far": "void fmm::k_far_pair<float, 1, true>"}
     if phase not in names or precision == "fp64" or not os.path.exists(path):
         return None
     rec = json.load(open(path))
