@@ -297,7 +297,7 @@ def main():
         ncrit = args.ncrit
     else:
         best = None
-        for nc in (64, 128, 256):
+        for nc in (64, 96, 128, 192, 256):
             pls = make(args.precision, nc)
             dt, _ = time_steps(step_pair, pls, qd, 5, 2)
             sweep[str(nc)] = round(dt / 5 * 1e3, 3)
