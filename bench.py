@@ -205,7 +205,9 @@ def run_bem(args):
     b = op32.rhs(qxyz, q)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    xs, its, hist, rc = gmres(op32, b, tol=1e-6, maxiter=400, restart=100, refine=op64, inner_tol=1e-4)
+    # inner solves to 1e-3 with the FP32 operator, residuals with the FP64
+    # operator: two corrections reach 1e-6 in the fewest iterations
+    xs, its, hist, rc = gmres(op32, b, tol=1e-6, maxiter=400, restart=100, refine=op64, inner_tol=1e-3)
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t0
     res = ((b - op64.matvec(xs)).norm() / b.norm()).item()
@@ -222,7 +224,7 @@ def run_bem(args):
             "fmm_mpoints_per_s": round(2 * npts / t32 / 1e6, 1),
             "fp64_matvec_ms": round(t64 * 1e3, 3),
             "gmres": {"status": rc, "iterations": its, "seconds": round(t_solve, 3),
-                      "fp64_residual": res, "tol": 1e-6},
+                      "fp64_residual": res, "tol": 1e-6, "inner_tol": 1e-3},
             "energy_kcal_per_mol": energy, "setup_s": {"fp32": round(t_setup32, 2), "fp64": round(t_setup64, 2)}}
     print(json.dumps(line), flush=True)
 
