@@ -61,6 +61,15 @@ def test_eval_rejects_null_plan():
     assert L.fmm_eval(None, None, 1, None, None, None) == _lib.FMM_EINVAL
 
 
+def test_pair_entry_points_reject_null_plans():
+    L = _lib.lib()
+    assert L.fmm_eval_pair(None, None, None, 1, None, None, None, None, None) == _lib.FMM_EINVAL
+    assert "plan" in L.fmm_last_error().decode()
+    assert L.fmm_eval_pair_md(None, None, None, None, 1.0, 1.0, None, None, None) == _lib.FMM_EINVAL
+    assert "two plans" in L.fmm_last_error().decode()
+    assert L.fmm_adjoint(None, None, None, None, 1, None, None, None) == _lib.FMM_EINVAL
+
+
 @pytest.mark.parametrize("case", ["quad", "eps", "kappa", "index", "degenerate"])
 def test_bem_setup_rejects_bad_arguments(case):
     import numpy as np
