@@ -162,3 +162,26 @@ def test_nonfinite_input_rejected():
     x[3, 1] = float("nan")
     with pytest.raises(FmmError):
         FMMPlan(x)
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
+def test_expansion_order_digits_fp64(kernel):
+    """Accuracy against p on the FP64 path (sphere-union cloud, 24,000
+    points): the paper reports about 4 digits at p = 4, 5 at p = 5 and 9 at
+    p = 10; the error must fall with p and reach those levels."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    su = synth.sphere_union_spheres(40, seed=141, box=20.0)
+    v, t = synth.sphere_union_mesh(su, 8000, seed=141)
+    x = synth.three_point_cloud(v, t)
+    q = np.random.default_rng(141).standard_normal(len(x))
+    kap = 0.125 if kernel == "yukawa" else 0.0
+    phi, _ = D.direct(x, x, q, kernel, kap)
+    errs = {}
+    for p in (4, 5, 6, 8, 10):
+        plan = FMMPlan(torch.tensor(x, device="cuda"), kernel=kernel, kappa=0.125, p=p, ncrit=64, precision="fp64")
+        pot, _ = plan.eval(torch.tensor(q, device="cuda"), gradient=False)
+        errs[p] = D.rel_l2(pot.cpu().numpy(), phi)
+    print(f"[digits {kernel}] " + " ".join(f"p={p}:{e:.1e}" for p, e in errs.items()), flush=True)
+    assert errs[4] < 1e-3 and errs[5] < 1e-4 and errs[10] < 1e-8
+    assert errs[4] > errs[6] > errs[8] > errs[10]
