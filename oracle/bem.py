@@ -374,3 +374,139 @@ def reaction_potential_direct(m: Mesh, x, qxyz):
 def energy_direct(m: Mesh, x, qxyz, q):
     phi = reaction_potential_direct(m, x, qxyz)
     return 0.5 * float(np.dot(q, phi)) * FOUR_PI * KCAL_PER_MOL
+
+
+# ---------------------------------------------------------------------------
+# Derivative (Juffer) formulation, P0 Galerkin (Methods, eq:juffer and
+# eq:adj_hyp): unknowns u = phi_1 and v = d phi_1 / dn per triangle,
+#   [ (1 + e21)/2 M - (e21 K_Y - K_L)   V_Y - V_L                 ] [u]   [b1]
+#   [ W_Y - W_L                         (1 + e12)/2 M + e12 K'_Y - K'_L ] [v] = [b2]
+# e21 = eps2/eps1, e12 = eps1/eps2, b2_s = int_Ts dn_x of the charges'
+# Coulomb potential / eps1.  With P0 Galerkin and the same rule on both
+# triangles, K' is the transpose of K.  Only the difference W_Y - W_L of the
+# hypersingular operators appears; its kernel is weakly singular.
+# ---------------------------------------------------------------------------
+def _h_derivs(r, kappa):
+    """h = (exp(-kappa r) - 1)/(4 pi r) (the Yukawa minus the Laplace
+    kernel): returns h'(r), and A = h'/r - kappa^2/(8 pi r) (bounded) and
+    B = h'' - h'/r, all for r > 0."""
+    x = kappa * r
+    e = np.exp(-x)
+    N = -np.expm1(-x) - x * e               # 1 - (1 + x) e^-x
+    hp = N / (FOUR_PI * r * r)
+    # N - x^2/2 by its series where the difference cancels
+    ser = x ** 3 * (-1 / 3 + x * (1 / 8 + x * (-1 / 30 + x * (1 / 144 + x * (-1 / 840 + x / 5760)))))
+    Nm = np.where(x < 0.05, ser, N - 0.5 * x * x)
+    A_ = Nm / (FOUR_PI * r ** 3)
+    B_ = (x * x * e - 3.0 * N) / (FOUR_PI * r ** 3)
+    return hp, A_, B_
+
+
+def hyper_diff_kernel(u, nx, ny, kappa):
+    """-d^2/(dn_x dn_y) of (g_Y - g_L) at separation u = x - y (r > 0):
+    (nx.ny) h'/r + (u.nx)(u.ny)/r^2 (h'' - h'/r)."""
+    u = np.asarray(u, dtype=np.float64)
+    r = np.linalg.norm(u, axis=-1)
+    hp, _, B_ = _h_derivs(r, kappa)
+    un = np.sum(u * nx, axis=-1) * np.sum(u * ny, axis=-1) / (r * r)
+    return np.sum(nx * ny, axis=-1) * hp / r + un * B_
+
+
+def hyper_diff_regular(m: Mesh, s, t, kappa):
+    x = m.qpts[s]
+    y = m.qpts[t]
+    d = x[:, None, :] - y[None, :, :]
+    r = np.linalg.norm(d, axis=2)
+    ww = m.qw[s][:, None] * m.qw[t][None, :]
+    mask = r > 0
+    dd = np.where(mask[..., None], d, 1.0)
+    k = hyper_diff_kernel(dd, m.normal[s], m.normal[t], kappa)
+    return float(np.sum(ww * np.where(mask, k, 0.0)))
+
+
+def hyper_diff_singular(m: Mesh, s, t, kappa, n_outer: int = 8, n_rem: int = 4):
+    """Accurate W_Y - W_L for pairs sharing a vertex: the 1/r part of
+    (nx.ny) h'/r, (kappa^2/2)(nx.ny)/(4 pi r), through the closed-form
+    triangle potential and the n_outer x n_outer collapsed rule on the test
+    triangle; the rest, (nx.ny) A(r) + (u.nx)(u.ny)/r^2 B(r), on the
+    n_rem x n_rem collapsed rule on both triangles (on one flat triangle
+    u.n = 0 and A(0) = -kappa^3/(12 pi))."""
+    s = np.atleast_1d(np.asarray(s))
+    t = np.atleast_1d(np.asarray(t))
+    tri_s = m.verts[m.tris[s]]
+    tri_t = m.verts[m.tris[t]]
+    ns, nt = m.normal[s], m.normal[t]
+    nn = np.sum(ns * nt, axis=1)
+    bo, wo = collapsed_rule(n_outer)
+    xo = np.einsum("kj,pjd->pkd", bo, tri_s)
+    Wo = wo[None, :] * m.area[s][:, None]
+    P = np.sum(Wo * tri_potential(xo, tri_t, nt), axis=1) / FOUR_PI
+    out = 0.5 * kappa * kappa * nn * P
+    br, wr = collapsed_rule(n_rem)
+    xr = np.einsum("kj,pjd->pkd", br, tri_s)
+    yr = np.einsum("kj,pjd->pkd", br, tri_t)
+    d = xr[:, :, None, :] - yr[:, None, :, :]
+    r = np.linalg.norm(d, axis=-1)
+    ww = (wr[None, :] * m.area[s][:, None])[:, :, None] * (wr[None, :] * m.area[t][:, None])[:, None, :]
+    pos = r > 0
+    rr = np.where(pos, r, 1.0)
+    _, A_, B_ = _h_derivs(rr, kappa)
+    un = (np.einsum("pabd,pd->pab", d, ns) * np.einsum("pabd,pd->pab", d, nt)) / (rr * rr)
+    rem = np.where(pos, nn[:, None, None] * A_ + un * B_, -nn[:, None, None] * kappa ** 3 / (12 * math.pi))
+    return out + np.sum(ww * rem, axis=(1, 2))
+
+
+def hyper_diff_operator(m: Mesh, kappa: float, n_outer: int = 8, n_rem: int = 4, chunk: int = 64):
+    """Dense W_Y - W_L (T x T): the regular rule on every pair, the singular
+    rule on pairs that share a vertex."""
+    T = len(m.tris)
+    k = m.qpts.shape[1]
+    X = m.qpts.reshape(-1, 3)
+    Wf = m.qw.reshape(-1)
+    nq = np.repeat(m.normal, k, axis=0)
+    out = np.zeros((T, T))
+    for s0 in range(0, T, chunk):
+        s1 = min(T, s0 + chunk)
+        Xs = X[s0 * k:s1 * k]
+        d = Xs[:, None, :] - X[None, :, :]
+        r = np.sqrt(np.einsum("ijd,ijd->ij", d, d))
+        mask = r > 0
+        dd = np.where(mask[..., None], d, 1.0)
+        kk = hyper_diff_kernel(dd, nq[s0 * k:s1 * k][:, None, :], nq[None, :, :], kappa)
+        kk = np.where(mask, kk, 0.0)
+        ws = Wf[s0 * k:s1 * k]
+        out[s0:s1] = (ws[:, None] * kk * Wf[None, :]).reshape(s1 - s0, k, T, k).sum(axis=(1, 3))
+    sp = np.array(singular_pairs(m))
+    out[sp[:, 0], sp[:, 1]] = hyper_diff_singular(m, sp[:, 0], sp[:, 1], kappa, n_outer, n_rem)
+    return out
+
+
+def system_derivative(m: Mesh, eps1: float, eps2: float, kappa: float, **kw):
+    VL, KL = operators(m, 0.0, **kw)
+    VY, KY = operators(m, kappa, **kw)
+    Wd = hyper_diff_operator(m, kappa, **kw)
+    M = np.diag(m.area)
+    e21, e12 = eps2 / eps1, eps1 / eps2
+    return np.block([[0.5 * (1 + e21) * M - (e21 * KY - KL), VY - VL],
+                     [Wd, 0.5 * (1 + e12) * M + (e12 * KY.T - KL.T)]])
+
+
+def rhs_derivative(m: Mesh, qxyz, q, eps1: float):
+    """[b1; b2]: b1 as for the direct formulation; b2_s = int_Ts n_s .
+    grad_x sum_k q_k / (4 pi eps1 |x - r_k|)."""
+    X = m.qpts.reshape(-1, 3)
+    T, k = m.qw.shape
+    R = X[:, None, :] - np.asarray(qxyz)[None, :, :]
+    d = np.linalg.norm(R, axis=2)
+    qq = np.asarray(q)[None, :]
+    f1 = (qq / (FOUR_PI * eps1 * d)).sum(axis=1)
+    nX = np.repeat(m.normal, k, axis=0)
+    f2 = -(qq * np.einsum("ijd,id->ij", R, nX) / (FOUR_PI * eps1 * d ** 3)).sum(axis=1)
+    w = m.qw.reshape(-1)
+    return np.concatenate([(w * f1).reshape(T, k).sum(axis=1), (w * f2).reshape(T, k).sum(axis=1)])
+
+
+def solve_derivative(m: Mesh, qxyz, q, eps1=4.0, eps2=80.0, kappa=0.125, **kw):
+    A = system_derivative(m, eps1, eps2, kappa, **kw)
+    b = rhs_derivative(m, qxyz, q, eps1)
+    return np.linalg.solve(A, b), A, b

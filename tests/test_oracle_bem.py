@@ -144,3 +144,77 @@ def test_reaction_potential_direct_equals_dense():
     qx = rng.uniform(-2.0, 2.0, (7, 3))
     np.testing.assert_allclose(bem.reaction_potential_direct(m, x, qx), bem.reaction_potential(m, x, qx),
                                rtol=1e-12, atol=1e-13)
+
+
+# ---- derivative (Juffer) formulation -------------------------------------
+def _h(r, kappa):
+    return (math.exp(-kappa * r) - 1.0) / (4.0 * math.pi * r)
+
+
+def test_hyper_diff_kernel_against_finite_differences():
+    """-d2/(dn_x dn_y) of g_Y - g_L, against central differences of the
+    kernel along both normals."""
+    rng = np.random.default_rng(151)
+    for _ in range(6):
+        x, y = rng.standard_normal(3), 0.4 * rng.standard_normal(3)
+        nx, ny = rng.standard_normal(3), rng.standard_normal(3)
+        nx /= np.linalg.norm(nx)
+        ny /= np.linalg.norm(ny)
+        e = 1e-4
+        H = lambda a, b: _h(float(np.linalg.norm(a - b)), KAPPA)  # noqa: E731
+        fd = -(H(x + e * nx, y + e * ny) - H(x + e * nx, y - e * ny) - H(x - e * nx, y + e * ny)
+               + H(x - e * nx, y - e * ny)) / (4 * e * e)
+        assert abs(bem.hyper_diff_kernel(x - y, nx, ny, KAPPA) - fd) < 2e-5 * abs(fd) + 5e-10
+
+
+def test_h_remainder_series_matches_closed_form():
+    r = np.array([0.3, 0.39, 0.41, 1.0, 3.0])
+    _, A_, _ = bem._h_derivs(r, KAPPA)
+    hp = np.array([(1 - (1 + KAPPA * rr) * math.exp(-KAPPA * rr)) / (4 * math.pi * rr * rr) for rr in r])
+    ref = hp / r - KAPPA ** 2 / (8 * math.pi * r)
+    np.testing.assert_allclose(A_, ref, rtol=1e-6)
+    # the bounded remainder tends to -kappa^3 / (12 pi)
+    assert abs(bem._h_derivs(np.array([1e-6]), KAPPA)[1][0] + KAPPA ** 3 / (12 * math.pi)) < 1e-10
+
+
+def test_hyper_diff_singular_rule_converges():
+    v, t = synth.octa_sphere(3, 4.0)
+    m = bem.make_mesh(v, t, 3)
+    sp = np.array(bem.singular_pairs(m))[:60]
+    a = bem.hyper_diff_singular(m, sp[:, 0], sp[:, 1], KAPPA, 8, 4)
+    b = bem.hyper_diff_singular(m, sp[:, 0], sp[:, 1], KAPPA, 16, 12)
+    assert np.max(np.abs(a - b) / np.abs(b)) < 2e-3
+
+
+def test_adjoint_double_layer_is_the_transpose():
+    """K'[s,t] = int_Ts int_Tt dg/dn_x: for a few regular pairs, from the
+    definition, against K[t,s] of the dense operator."""
+    v, t = synth.octa_sphere(2, 4.0)
+    m = bem.make_mesh(v, t, 3)
+    _, K = bem.operators(m, KAPPA)
+    for s_, t_ in ((0, 40), (7, 90), (33, 2)):
+        x, y = m.qpts[s_], m.qpts[t_]
+        d = x[:, None, :] - y[None, :, :]
+        r = np.linalg.norm(d, axis=2)
+        dgdnx = -(d @ m.normal[s_]) * (1 + KAPPA * r) * np.exp(-KAPPA * r) / (4 * math.pi * r ** 3)
+        kp = float(np.sum(m.qw[s_][:, None] * m.qw[t_][None, :] * dgdnx))
+        assert abs(kp - K[t_, s_]) < 1e-12 * abs(kp) + 1e-18
+
+
+def test_derivative_formulation_converges_and_stays_conditioned():
+    """Kirkwood sphere: the derivative formulation's energy converges at
+    order 1 like the direct one, and its condition number stays flat under
+    refinement while the direct formulation's grows (Methods: the direct
+    form's condition number grows with the number of elements)."""
+    ref = A.kirkwood_energy(4.0, [1, 1, 1], [1.0], 4.0, 80.0, KAPPA)
+    err, cond_d, cond_0 = [], [], []
+    for lev in (2, 3):
+        v, t = synth.octa_sphere(lev, 4.0)
+        m = bem.make_mesh(v, t, 3)
+        x, Ad, _ = bem.solve_derivative(m, [[1, 1, 1]], [1.0])
+        err.append(abs(bem.energy(m, x, [[1, 1, 1]], [1.0]) - ref))
+        cond_d.append(np.linalg.cond(Ad))
+        cond_0.append(np.linalg.cond(bem.system(m, 4.0, 80.0, KAPPA)))
+    order = math.log(err[0] / err[1]) / math.log(4.0)
+    assert 0.85 < order < 1.15, (err, order)
+    assert cond_d[1] / cond_d[0] < 1.1 and cond_0[1] / cond_0[0] > 1.5
