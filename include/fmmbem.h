@@ -132,13 +132,18 @@ int fmm_eval_pair(fmm_plan *plan_a, fmm_plan *plan_b, const void *q_dev, int nrh
  * direct formulation in one pass per kernel (Methods, eq:single_double and
  * eq:direct: the double layer is the normal derivative of g at the source).
  * q_dev: n charges; dip_dev: n x 3 dipole moments (row i = point i); pot_a_dev,
- * pot_b_dev: n each; caller's point order; element type double for FMM_FP64,
- * float otherwise.  Equivalent densities stay monopoles, so only the source
- * side (P2M, P2L, near field) differs from fmm_eval_pair.  Asynchronous on
- * `stream` (internal side stream joined back).  Errors: FMM_EINVAL for null
- * buffers, non-finite scales or plans that do not share a tree. */
+ * pot_b_dev: n each; grad_a_dev, grad_b_dev: n x 3 gradients +grad_x pot_k
+ * (the hypersingular and adjoint double-layer terms of the derivative
+ * formulation, eq:juffer and eq:adj_hyp, come from their normal
+ * components), or both NULL for potentials only; caller's point order;
+ * element type double for FMM_FP64, float otherwise.  Equivalent densities
+ * stay monopoles, so only the source side (P2M, P2L, near field) differs
+ * from fmm_eval_pair.  Asynchronous on `stream` (internal side stream joined
+ * back).  Errors: FMM_EINVAL for null buffers, non-finite scales or plans
+ * that do not share a tree. */
 int fmm_eval_pair_md(fmm_plan *plan_a, fmm_plan *plan_b, const void *q_dev, const void *dip_dev, double qscale_a,
-                     double qscale_b, void *pot_a_dev, void *pot_b_dev, fmm_stream_t stream);
+                     double qscale_b, void *pot_a_dev, void *grad_a_dev, void *pot_b_dev, void *grad_b_dev,
+                     fmm_stream_t stream);
 
 /* Adjoint of fmm_eval for a loss L(pot) with upstream gradient gbar_dev =
  * dL/dpot (nrhs x n, same type and layout as pot).  Because the kernel is
@@ -221,45 +226,56 @@ int fmm_get_phase_times(fmm_plan *plan, double *ms, int64_t *launches, int nphas
 void fmm_free(fmm_plan *plan);
 
 /* ------------------------------------------------------------------------
- * Boundary-element operator of the direct formulation (Methods, boundary
- * integral formulation: the direct, Yoon-Lenhoff, system for the solute-side
- * potential u and its normal derivative v on the molecular surface), with
- * piecewise-constant (P0) Galerkin discretisation on a triangle mesh and the
- * matrix-vector split A x = P2^T (G - C) P1 x + S x ("FMM-accelerated
- * evaluation of integral operators"):
+ * Boundary-element operators (Methods, boundary integral formulation) for
+ * the solute-side potential u and its normal derivative v on the molecular
+ * surface, with piecewise-constant (P0) Galerkin discretisation on a
+ * triangle mesh and the matrix-vector split A x = P2^T (G - C) P1 x + S x
+ * ("FMM-accelerated evaluation of integral operators").  Two formulations:
  *
+ * FMM_BEM_DIRECT (eq:direct, Yoon-Lenhoff):
  *   [ M/2 + K_L    -V_L            ] [u]   [b]
  *   [ M/2 - K_Y    (eps1/eps2) V_Y ] [v] = [0],     M = diag(triangle areas)
  *
+ * FMM_BEM_DERIVATIVE (eq:juffer, Juffer et al.), e21 = eps2/eps1, e12 = eps1/eps2:
+ *   [ (1 + e21)/2 M - (e21 K_Y - K_L)   V_Y - V_L                        ] [u]   [b ]
+ *   [ W_Y - W_L                         (1 + e12)/2 M + e12 K'_Y - K'_L  ] [v] = [b'],
+ *   b' the normal derivative of the Coulomb term; K' the adjoint double
+ *   layer and W the hypersingular operator (eq:adj_hyp).  Only the
+ *   difference W_Y - W_L appears; its kernel is weakly singular.
+ *
  * V and K are the single- and double-layer operators of the Laplace (L) and
- * Yukawa (Y) kernels.  G is evaluated by fmm_eval on the regular quadrature
- * points (4 density columns per kernel: the three normal-weighted columns of
- * the double layer, whose gradients give K, and the single-layer column);
- * for pairs of triangles that share a vertex the regular-rule values C are
- * replaced by accurate values S (closed-form inner integrals of the Laplace
- * part over the flat triangle, Gauss rules for the bounded Yukawa remainder),
- * applied as one precomputed sparse FP64 matrix S - C.
+ * Yukawa (Y) kernels.  G is evaluated by one fmm_eval_pair_md call per
+ * product (charges W v and dipoles W u n at the regular quadrature points;
+ * the derivative formulation also takes the gradients).  For pairs of
+ * triangles that share a vertex the regular-rule values C are replaced by
+ * accurate values S (closed-form inner integrals of the Laplace part over
+ * the flat triangle, Gauss rules for the bounded or weakly singular
+ * Yukawa-minus-Laplace remainders; K' uses the transposed K pair), applied
+ * as one precomputed sparse FP64 matrix S - C.
  * ------------------------------------------------------------------------ */
+enum { FMM_BEM_DIRECT = 0, FMM_BEM_DERIVATIVE = 1 };
 
 /* Build the operator.  verts (nv x 3 doubles) and tris (nt x 3 int32, vertex
  * indices, counter-clockwise seen from the solvent so that normals point
  * out of the molecule) are HOST arrays read during the call.  quad_pts: 3 or
  * 6 (regular rule per triangle); eps_in, eps_out > 0; kappa >= 0; p, ncrit,
- * precision as for fmm_setup (the two FMM plans).  Synchronises `stream`.
- * Errors: FMM_EINVAL for bad sizes, indices or parameters, a degenerate
- * triangle; FMM_ENOMEM; FMM_EHIP. */
+ * precision as for fmm_setup (the two FMM plans); formulation:
+ * FMM_BEM_DIRECT or FMM_BEM_DERIVATIVE.  Synchronises `stream`.  Errors:
+ * FMM_EINVAL for bad sizes, indices or parameters, a degenerate triangle;
+ * FMM_ENOMEM; FMM_EHIP. */
 int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, int quad_pts, double eps_in,
-              double eps_out, double kappa, int p, int ncrit, int precision, fmm_stream_t stream,
+              double eps_out, double kappa, int p, int ncrit, int precision, int formulation, fmm_stream_t stream,
               bem_op **out);
 
 /* y = A x; x_dev, y_dev: device, 2*nt doubles ([u; v] and the two row
  * blocks).  x_dev and y_dev must not overlap.  Asynchronous. */
 int bem_matvec(bem_op *op, const double *x_dev, double *y_dev, fmm_stream_t stream);
 
-/* Right-hand side b_dev (2*nt doubles: [b; 0]) for nq point charges at
- * qxyz_dev (device, nq x 3) with charges q_dev (device, nq), e and
- * Angstrom: b_s = int_Ts (1/eps_in) sum_k q_k / (4 pi |x - r_k|), regular rule,
- * FP64 direct sum.  Asynchronous. */
+/* Right-hand side b_dev (2*nt doubles) for nq point charges at qxyz_dev
+ * (device, nq x 3) with charges q_dev (device, nq), e and Angstrom:
+ * b_s = int_Ts (1/eps_in) sum_k q_k / (4 pi |x - r_k|); second block 0
+ * (direct) or int_Ts n_s . grad of the same sum (derivative); regular rule,
+ * FP64 direct sums.  Asynchronous. */
 int bem_rhs(bem_op *op, const double *qxyz_dev, const double *q_dev, int64_t nq, double *b_dev,
             fmm_stream_t stream);
 
@@ -298,6 +314,7 @@ typedef struct {
   int64_t n_singular_pairs;   /* triangle pairs sharing a vertex (incl. identical) */
   int32_t quad_pts;
   int32_t precision;
+  int32_t formulation;
 } bem_info_t;
 int bem_info(const bem_op *op, bem_info_t *out);
 

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libfmmbem.so")
 
 FMM_LAPLACE, FMM_YUKAWA = 0, 1
 FMM_FP64, FMM_FP32, FMM_FP32_BF16X3 = 0, 1, 2
+FMM_BEM_DIRECT, FMM_BEM_DERIVATIVE = 0, 1
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOTCONV, FMM_EBREAKDOWN = 0, -1, -2, -3, -4, -5
 
 PHASES = ["permute", "p2m", "uc2e", "m2m", "p2l", "m2l", "m2l_sum", "l2l", "dc2e", "leaf", "near", "far"]
@@ -48,7 +49,7 @@ SIGNATURES = {
     "fmm_setup": (i32, [vp, i64, i32, dbl, i32, i32, i32, vp, P(vp)]),
     "fmm_eval": (i32, [vp, vp, i32, vp, vp, vp]),
     "fmm_eval_pair": (i32, [vp, vp, vp, i32, vp, vp, vp, vp, vp]),
-    "fmm_eval_pair_md": (i32, [vp, vp, vp, vp, dbl, dbl, vp, vp, vp]),
+    "fmm_eval_pair_md": (i32, [vp, vp, vp, vp, dbl, dbl, vp, vp, vp, vp, vp]),
     "fmm_setup_batch": (i32, [vp, vp, i32, i32, dbl, i32, i32, i32, vp, P(vp)]),
     "fmm_info": (i32, [vp, P(FmmInfo)]),
     "fmm_get_tree": (i32, [vp] + [vp] * 11),
@@ -57,7 +58,7 @@ SIGNATURES = {
     "fmm_last_error": (ctypes.c_char_p, []),
     "fmm_set_profiling": (i32, [vp, i32]),
     "fmm_adjoint": (i32, [vp, vp, vp, vp, i32, vp, vp, vp]),
-    "bem_setup": (i32, [vp, i64, vp, i64, i32, dbl, dbl, dbl, i32, i32, i32, vp, P(vp)]),
+    "bem_setup": (i32, [vp, i64, vp, i64, i32, dbl, dbl, dbl, i32, i32, i32, i32, vp, P(vp)]),
     "bem_matvec": (i32, [vp, vp, vp, vp]),
     "bem_rhs": (i32, [vp, vp, vp, i64, vp, vp]),
     "bem_energy": (i32, [vp, vp, vp, vp, i64, P(dbl), vp]),

@@ -14,13 +14,18 @@ from . import _lib
 from ._lib import check, lib
 from .fmm import PRECISIONS, _ptr, _stream
 
+FORMULATIONS = {"direct": _lib.FMM_BEM_DIRECT, "derivative": _lib.FMM_BEM_DERIVATIVE}
+
 
 class BEMOperator:
-    """Direct-formulation operator [[M/2 + K_L, -V_L], [M/2 - K_Y, (eps_in/eps_out) V_Y]]
-    on a triangle mesh (P0 elements, regular rule with quad_pts points)."""
+    """P0 boundary-element operator on a triangle mesh (regular rule with
+    quad_pts points): formulation "direct", [[M/2 + K_L, -V_L], [M/2 - K_Y,
+    (eps_in/eps_out) V_Y]], or "derivative" (Juffer), [[(1+e21)/2 M - (e21 K_Y -
+    K_L), V_Y - V_L], [W_Y - W_L, (1+e12)/2 M + e12 K'_Y - K'_L]]."""
 
     def __init__(self, verts, tris, quad_pts: int = 3, eps_in: float = 4.0, eps_out: float = 80.0,
-                 kappa: float = 0.125, p: int = 6, ncrit: int = 128, precision: str = "fp32", device="cuda"):
+                 kappa: float = 0.125, p: int = 6, ncrit: int = 128, precision: str = "fp32", device="cuda",
+                 formulation: str = "direct"):
         v = np.ascontiguousarray(verts, dtype=np.float64)
         t = np.ascontiguousarray(tris, dtype=np.int32)
         if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
@@ -28,11 +33,15 @@ class BEMOperator:
         self.nt = int(t.shape[0])
         self.device = torch.device(device)
         self.precision = precision
+        if formulation not in FORMULATIONS:
+            raise ValueError(f"unknown formulation {formulation!r}")
+        self.formulation = formulation
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(lib().bem_setup(ctypes.c_void_p(v.ctypes.data), v.shape[0], ctypes.c_void_p(t.ctypes.data), self.nt,
                                   int(quad_pts), float(eps_in), float(eps_out), float(kappa), int(p), int(ncrit),
-                                  PRECISIONS[precision], _stream(), ctypes.byref(h)), "bem_setup")
+                                  PRECISIONS[precision], FORMULATIONS[formulation], _stream(), ctypes.byref(h)),
+                  "bem_setup")
         self._h = h
 
     def __del__(self):
@@ -79,13 +88,12 @@ class BEMOperator:
         return out.value
 
     def info(self) -> dict:
-        buf = (ctypes.c_int64 * 3)()
         raw = ctypes.create_string_buffer(40)
         check(lib().bem_info(self._h, raw), "bem_info")
         a = np.frombuffer(raw.raw[:24], dtype=np.int64)
-        b = np.frombuffer(raw.raw[24:32], dtype=np.int32)
+        b = np.frombuffer(raw.raw[24:36], dtype=np.int32)
         return {"n_triangles": int(a[0]), "n_points": int(a[1]), "n_singular_pairs": int(a[2]),
-                "quad_pts": int(b[0]), "precision": int(b[1])}
+                "quad_pts": int(b[0]), "precision": int(b[1]), "formulation": int(b[2])}
 
 
 def gmres(op: BEMOperator, b, x0=None, tol: float = 1e-6, maxiter: int = 500, restart: int = 0,

@@ -136,12 +136,35 @@ __device__ double tri_dlp(D3 x, const D3 *v) {
   return -2.0 * atan2(num, den);
 }
 
+// Derivatives of h = (e^{-kappa r} - 1)/(4 pi r), the Yukawa minus the
+// Laplace kernel: h'(r); A = h'/r - kappa^2/(8 pi r) (bounded; the
+// difference N - x^2/2, N = 1 - (1 + x) e^{-x}, x = kappa r, by its series
+// below x = 0.05); B = h'' - h'/r.
+__device__ inline void h_derivs(double r, double kappa, double &hp, double &A, double &B) {
+  const double x = kappa * r, e = exp(-x);
+  const double N = -expm1(-x) - x * e;
+  hp = N / (FOUR_PI * r * r);
+  const double ser = x * x * x * (-1.0 / 3 + x * (1.0 / 8 + x * (-1.0 / 30 + x * (1.0 / 144 + x * (-1.0 / 840 + x / 5760)))));
+  const double Nm = x < 0.05 ? ser : N - 0.5 * x * x;
+  A = Nm / (FOUR_PI * r * r * r);
+  B = (x * x * e - 3.0 * N) / (FOUR_PI * r * r * r);
+}
+
+// -d^2/(dn_x dn_y) of (g_Y - g_L) at u = x - y, r = |u| > 0 (the kernel of
+// W_Y - W_L): (nx.ny) h'/r + (u.nx)(u.ny)/r^2 (h'' - h'/r).
+__device__ inline double hyper_diff(D3 u, double r, D3 nx, D3 ny, double kappa) {
+  double hp, A, B;
+  h_derivs(r, kappa, hp, A, B);
+  return dot(nx, ny) * hp / r + dot(u, nx) * dot(u, ny) / (r * r) * B;
+}
+
 // One thread per singular pair (s, t): D = S - C for V_L, K_L, V_Y, K_Y.
 __global__ void k_singular(int64_t npair, const int32_t *__restrict__ ps, const int32_t *__restrict__ pt,
                            const double *__restrict__ tri, const double *__restrict__ normal,
                            const double *__restrict__ area, const double *__restrict__ rule_o, int no,
                            const double *__restrict__ rule_r, int nr, const double *__restrict__ rule_q, int nq,
-                           double kappa, double *__restrict__ Dval, double *__restrict__ sdiag) {
+                           double kappa, double *__restrict__ Dval, double *__restrict__ sdiag, int deriv,
+                           double *__restrict__ Dw, double *__restrict__ sdiag_w) {
   const int64_t k = blockIdx.x * 128ll + threadIdx.x;
   if (k >= npair) return;
   const int s = ps[k], t = pt[k];
@@ -212,6 +235,60 @@ __global__ void k_singular(int64_t npair, const int32_t *__restrict__ ps, const 
     sdiag[2 * s] = sv;
     sdiag[2 * s + 1] = svy;
   }
+  if (!deriv) return;
+  // W_Y - W_L: its 1/r part (kappa^2/2)(ns.nt)/(4 pi r) through the Laplace
+  // single-layer value above, the rest on the remainder rule; minus the
+  // regular-rule value
+  const D3 ns = mk(normal[s * 3], normal[s * 3 + 1], normal[s * 3 + 2]);
+  const double nn = dot(ns, nt);
+  double ws = 0.5 * kappa * kappa * nn * sv;
+  for (int a = 0; a < nr; ++a) {
+    const D3 x = point(vs, rule_r[3 * a], rule_r[3 * a + 1]);
+    const double wa = rule_r[3 * a + 2] * As;
+    for (int b = 0; b < nr; ++b) {
+      const D3 y = point(vt, rule_r[3 * b], rule_r[3 * b + 1]);
+      const double w = wa * rule_r[3 * b + 2] * At;
+      const D3 d = sub(x, y);
+      const double r = nrm(d);
+      if (r > 0) {
+        double hp, A, B;
+        h_derivs(r, kappa, hp, A, B);
+        ws += w * (nn * A + dot(d, ns) * dot(d, nt) / (r * r) * B);
+      } else {
+        ws += w * (-nn * kappa * kappa * kappa / (12.0 * M_PI));
+      }
+    }
+  }
+  double wc = 0;
+  for (int a = 0; a < nq; ++a) {
+    const D3 x = point(vs, rule_q[3 * a], rule_q[3 * a + 1]);
+    const double wa = rule_q[3 * a + 2] * As;
+    for (int b = 0; b < nq; ++b) {
+      const D3 y = point(vt, rule_q[3 * b], rule_q[3 * b + 1]);
+      const D3 d = sub(x, y);
+      const double r = nrm(d);
+      if (r > 0) wc += wa * rule_q[3 * b + 2] * At * hyper_diff(d, r, ns, nt, kappa);
+    }
+  }
+  Dw[k] = ws - wc;
+  if (s == t) sdiag_w[s] = ws;
+}
+
+// Inverse of the 2x2 diagonal block of the derivative formulation,
+// [[(1 + e21)/2 A, V_Y,ss - V_L,ss], [(W_Y - W_L)_ss, (1 + e12)/2 A]]
+// (K_ss = K'_ss = 0 on a flat triangle).
+__global__ void k_precond_setup_deriv(int64_t nt, const double *__restrict__ area, const double *__restrict__ sdiag,
+                                      const double *__restrict__ sdiag_w, double e21, double e12,
+                                      double *__restrict__ pre) {
+  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+  if (s >= nt) return;
+  const double a = 0.5 * (1 + e21) * area[s], b = sdiag[2 * s + 1] - sdiag[2 * s], c = sdiag_w[s],
+               d = 0.5 * (1 + e12) * area[s];
+  const double det = a * d - b * c;
+  pre[4 * s + 0] = d / det;
+  pre[4 * s + 1] = -b / det;
+  pre[4 * s + 2] = -c / det;
+  pre[4 * s + 3] = a / det;
 }
 
 // Inverse of the 2x2 diagonal block [[A/2, -V_L,ss], [A/2, (e1/e2) V_Y,ss]]
@@ -279,6 +356,88 @@ __global__ void k_bem_p2_md(int64_t nt, int nq, const T *__restrict__ potl, cons
   const double hu = 0.5 * area[s] * x[s];
   y[s] = hu + al;
   y[nt + s] = hu - ay;
+}
+
+// P2^T and assembly for the derivative formulation (eq:juffer).  The FMM
+// returned pot_L = K_L u - V_L v and pot_Y = K_Y u - e12 V_Y v with their
+// gradients, so (regular parts)
+//   y1 = (1 + e21)/2 A u + P2^T (pot_L - e21 pot_Y)
+//   y2 = (1 + e12)/2 A v + P2^T n.(grad pot_L - grad pot_Y)
+// (n.grad pot_L = -W_L u - K'_L v, n.grad pot_Y = -W_Y u - e12 K'_Y v), plus
+// the S - C terms; K' corrections are those of K on the transposed pair.
+template <typename T>
+__global__ void k_bem_p2_deriv(int64_t nt, int nq, const T *__restrict__ potl, const T *__restrict__ gradl,
+                               const T *__restrict__ poty, const T *__restrict__ grady, const double *__restrict__ qw,
+                               const double *__restrict__ area, const double *__restrict__ normal,
+                               const int32_t *__restrict__ sp_off, const int32_t *__restrict__ sp_idx,
+                               const int32_t *__restrict__ sp_tr, const double *__restrict__ Dval,
+                               const double *__restrict__ Dw, const double *__restrict__ x, double e21, double e12,
+                               double *__restrict__ y) {
+  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+  if (s >= nt) return;
+  const double n0 = normal[3 * s], n1 = normal[3 * s + 1], n2 = normal[3 * s + 2];
+  double a1 = 0, a2 = 0;
+  for (int a = 0; a < nq; ++a) {
+    const int64_t i = s * nq + a;
+    a1 += qw[i] * ((double)potl[i] - e21 * (double)poty[i]);
+    a2 += qw[i] * (n0 * ((double)gradl[3 * i] - (double)grady[3 * i]) +
+                   n1 * ((double)gradl[3 * i + 1] - (double)grady[3 * i + 1]) +
+                   n2 * ((double)gradl[3 * i + 2] - (double)grady[3 * i + 2]));
+  }
+  for (int k = sp_off[s]; k < sp_off[s + 1]; ++k) {
+    const int t = sp_idx[k], kt = sp_tr[k];
+    const double u = x[t], v = x[nt + t];
+    a1 += Dval[4 * k + 1] * u - Dval[4 * k + 0] * v - e21 * Dval[4 * k + 3] * u + Dval[4 * k + 2] * v;
+    a2 += Dw[k] * u + e12 * Dval[4 * kt + 3] * v - Dval[4 * kt + 1] * v;
+  }
+  y[s] = 0.5 * (1 + e21) * area[s] * x[s] + a1;
+  y[nt + s] = 0.5 * (1 + e12) * area[s] * x[nt + s] + a2;
+}
+
+// n . grad of the FP64 Coulomb sum at the quadrature points (the derivative
+// formulation's second right-hand side): out_i = -sum_j sig_j n_i.(x_i -
+// y_j)/(4 pi r^3), n_i the normal of point i's triangle.
+__global__ __launch_bounds__(256) void k_direct_ngrad(int64_t nt, int nq, const double *__restrict__ tx,
+                                                      const double *__restrict__ normal, int64_t ns,
+                                                      const double *__restrict__ sy, const double *__restrict__ sig,
+                                                      double *__restrict__ out) {
+  __shared__ double sx[256], syy[256], sz[256], ss[256];
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  const bool act = i < nt;
+  const double xi = act ? tx[3 * i] : 0, yi = act ? tx[3 * i + 1] : 0, zi = act ? tx[3 * i + 2] : 0;
+  const int64_t tri = act ? i / nq : 0;
+  const double n0 = normal[3 * tri], n1 = normal[3 * tri + 1], n2 = normal[3 * tri + 2];
+  double acc = 0;
+  for (int64_t j0 = 0; j0 < ns; j0 += 256) {
+    const int64_t j = j0 + threadIdx.x;
+    if (j < ns) {
+      sx[threadIdx.x] = sy[3 * j];
+      syy[threadIdx.x] = sy[3 * j + 1];
+      sz[threadIdx.x] = sy[3 * j + 2];
+      ss[threadIdx.x] = sig[j];
+    }
+    __syncthreads();
+    const int cnt = (int)min<int64_t>(256, ns - j0);
+    for (int k = 0; k < cnt; ++k) {
+      const double ax = xi - sx[k], ay = yi - syy[k], az = zi - sz[k];
+      const double r2 = ax * ax + ay * ay + az * az;
+      if (r2 > 0) {
+        const double ir = 1.0 / sqrt(r2);
+        acc -= ss[k] * (n0 * ax + n1 * ay + n2 * az) * ir * ir * ir;
+      }
+    }
+    __syncthreads();
+  }
+  if (act) out[i] = acc / FOUR_PI;
+}
+
+__global__ void k_rhs_assemble2(int64_t nt, int nq, const double *__restrict__ qw, const double *__restrict__ f,
+                                double *__restrict__ b) {
+  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+  if (s >= nt) return;
+  double acc = 0;
+  for (int a = 0; a < nq; ++a) acc += qw[s * nq + a] * f[s * nq + a];
+  b[nt + s] = acc;
 }
 
 // FP64 direct sum with monopole and dipole sources:
@@ -423,7 +582,11 @@ struct bem_op {
   double *d_tri = nullptr, *d_normal = nullptr, *d_area = nullptr, *d_qw = nullptr, *d_qpts = nullptr;
   int32_t *d_sp_off = nullptr, *d_sp_idx = nullptr;
   double *d_D = nullptr, *d_sdiag = nullptr, *d_pre = nullptr;
-  void *q4 = nullptr, *potl = nullptr, *poty = nullptr;
+  // derivative formulation: W_Y - W_L corrections and diagonal, transposed pair index
+  int formulation = 0;
+  double *d_Dw = nullptr, *d_sdiag_w = nullptr;
+  int32_t *d_sp_tr = nullptr;
+  void *q4 = nullptr, *potl = nullptr, *poty = nullptr, *gradl = nullptr, *grady = nullptr;
   // GMRES / energy scratch
   double *d_partial = nullptr, *d_h = nullptr, *d_V = nullptr, *d_z = nullptr, *d_w = nullptr, *d_r = nullptr,
          *d_xc = nullptr;
@@ -480,9 +643,14 @@ int multidot(bem_op *op, const double *V, int rows, const double *w, double *h_h
 extern "C" {
 
 int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, int quad_pts, double eps_in,
-              double eps_out, double kappa, int p, int ncrit, int precision, fmm_stream_t stream, bem_op **out) {
+              double eps_out, double kappa, int p, int ncrit, int precision, int formulation, fmm_stream_t stream,
+              bem_op **out) {
   if (!out) { set_error("bem_setup: out is NULL"); return FMM_EINVAL; }
   *out = nullptr;
+  if (formulation != FMM_BEM_DIRECT && formulation != FMM_BEM_DERIVATIVE) {
+    set_error("bem_setup: unknown formulation");
+    return FMM_EINVAL;
+  }
   if (nv <= 0 || nt <= 0 || !verts || !tris) { set_error("bem_setup: empty or null mesh"); return FMM_EINVAL; }
   if (quad_pts != 3 && quad_pts != 6) { set_error("bem_setup: quad_pts must be 3 or 6"); return FMM_EINVAL; }
   if (!(eps_in > 0) || !(eps_out > 0) || !std::isfinite(eps_in) || !std::isfinite(eps_out)) {
@@ -496,6 +664,8 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
   if (!op) { set_error("bem_setup: out of host memory"); return FMM_ENOMEM; }
   op->nt = nt; op->nv = nv; op->nq = quad_pts; op->N = nt * quad_pts; op->precision = precision;
   op->eps_in = eps_in; op->eps_out = eps_out; op->kappa = kappa;
+  op->formulation = formulation;
+  const bool deriv = formulation == FMM_BEM_DERIVATIVE;
   int rc = FMM_OK;
   do {
     // geometry on the host
@@ -541,6 +711,13 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
       off[t + 1] = (int32_t)idx.size();
     }
     op->npair = (int64_t)idx.size();
+    // index of the transposed pair (t, s) of every pair (s, t)
+    std::vector<int32_t> tr(idx.size());
+    for (int64_t t = 0; t < nt; ++t)
+      for (int32_t k = off[t]; k < off[t + 1]; ++k) {
+        const int32_t u = idx[k];
+        tr[k] = (int32_t)(std::lower_bound(idx.begin() + off[u], idx.begin() + off[u + 1], (int32_t)t) - idx.begin());
+      }
     if ((rc = bupload(op, &op->d_tri, tri))) break;
     if ((rc = bupload(op, &op->d_normal, normal))) break;
     if ((rc = bupload(op, &op->d_area, area))) break;
@@ -560,11 +737,20 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     if ((rc = balloc(op, (void **)&op->d_D, op->npair * 4 * sizeof(double)))) break;
     if ((rc = balloc(op, (void **)&op->d_sdiag, nt * 2 * sizeof(double)))) break;
     if ((rc = balloc(op, (void **)&op->d_pre, nt * 4 * sizeof(double)))) break;
+    if (deriv) {
+      if ((rc = bupload(op, &op->d_sp_tr, tr))) break;
+      if ((rc = balloc(op, (void **)&op->d_Dw, op->npair * sizeof(double)))) break;
+      if ((rc = balloc(op, (void **)&op->d_sdiag_w, nt * sizeof(double)))) break;
+    }
     hipLaunchKernelGGL(k_singular, dim3(blocks(op->npair, 128)), dim3(128), 0, s, op->npair, d_ps, op->d_sp_idx,
                        op->d_tri, op->d_normal, op->d_area, d_ro, NO * NO, d_rr, NREM * NREM, d_rq, quad_pts, kappa,
-                       op->d_D, op->d_sdiag);
-    hipLaunchKernelGGL(k_precond_setup, dim3(blocks(nt)), dim3(256), 0, s, nt, op->d_area, op->d_sdiag,
-                       eps_in / eps_out, op->d_pre);
+                       op->d_D, op->d_sdiag, deriv ? 1 : 0, op->d_Dw, op->d_sdiag_w);
+    if (deriv)
+      hipLaunchKernelGGL(k_precond_setup_deriv, dim3(blocks(nt)), dim3(256), 0, s, nt, op->d_area, op->d_sdiag,
+                         op->d_sdiag_w, eps_out / eps_in, eps_in / eps_out, op->d_pre);
+    else
+      hipLaunchKernelGGL(k_precond_setup, dim3(blocks(nt)), dim3(256), 0, s, nt, op->d_area, op->d_sdiag,
+                         eps_in / eps_out, op->d_pre);
     if (hipGetLastError() != hipSuccess) { set_error("bem_setup: launch failed"); rc = FMM_EHIP; break; }
     // the two FMM plans on the quadrature points
     if ((rc = fmm_setup(op->d_qpts, op->N, FMM_LAPLACE, 0.0, p, ncrit, precision, stream, &op->fl))) break;
@@ -574,6 +760,10 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     if ((rc = balloc(op, &op->q4, 4 * op->N * es))) break;
     if ((rc = balloc(op, &op->potl, op->N * es))) break;
     if ((rc = balloc(op, &op->poty, op->N * es))) break;
+    if (deriv) {
+      if ((rc = balloc(op, &op->gradl, 3 * op->N * es))) break;
+      if ((rc = balloc(op, &op->grady, 3 * op->N * es))) break;
+    }
     if ((rc = balloc(op, (void **)&op->d_z, 2 * nt * sizeof(double)))) break;
     if ((rc = balloc(op, (void **)&op->d_w, 2 * nt * sizeof(double)))) break;
     if ((rc = balloc(op, (void **)&op->d_r, 2 * nt * sizeof(double)))) break;
@@ -609,7 +799,24 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
   {
     const size_t es = op->precision == FMM_FP64 ? 8 : 4;
     const char *qq = (const char *)op->q4;
-    if ((rc = fmm_eval_pair_md(op->fl, op->fy, qq, qq + Nq * es, -1.0, -er, op->potl, op->poty, s))) return rc;
+    if ((rc = fmm_eval_pair_md(op->fl, op->fy, qq, qq + Nq * es, -1.0, -er, op->potl, op->gradl, op->poty,
+                               op->grady, s)))
+      return rc;
+  }
+  if (op->formulation == FMM_BEM_DERIVATIVE) {
+    const double e21 = op->eps_out / op->eps_in;
+    if (op->precision == FMM_FP64)
+      hipLaunchKernelGGL(k_bem_p2_deriv<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq,
+                         (const double *)op->potl, (const double *)op->gradl, (const double *)op->poty,
+                         (const double *)op->grady, op->d_qw, op->d_area, op->d_normal, op->d_sp_off, op->d_sp_idx,
+                         op->d_sp_tr, op->d_D, op->d_Dw, x, e21, er, y);
+    else
+      hipLaunchKernelGGL(k_bem_p2_deriv<float>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq,
+                         (const float *)op->potl, (const float *)op->gradl, (const float *)op->poty,
+                         (const float *)op->grady, op->d_qw, op->d_area, op->d_normal, op->d_sp_off, op->d_sp_idx,
+                         op->d_sp_tr, op->d_D, op->d_Dw, x, e21, er, y);
+    FMM_HIP_TRY(hipGetLastError());
+    return FMM_OK;
   }
   if (op->precision == FMM_FP64) {
     hipLaunchKernelGGL(k_bem_p2_md<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const double *)op->potl,
@@ -641,6 +848,12 @@ int bem_rhs(bem_op *op, const double *qxyz, const double *q, int64_t nq, double 
   hipLaunchKernelGGL(k_direct_md, dim3(blocks(op->N)), dim3(256), 0, s, op->N, op->d_qpts, nq, qxyz, sig,
                      (const double *)nullptr, f);
   hipLaunchKernelGGL(k_rhs_assemble, dim3(blocks(op->nt)), dim3(256), 0, s, op->nt, op->nq, op->d_qw, f, b);
+  if (op->formulation == FMM_BEM_DERIVATIVE) {
+    // second block: the normal derivative of the same Coulomb sum
+    hipLaunchKernelGGL(k_direct_ngrad, dim3(blocks(op->N)), dim3(256), 0, s, op->N, op->nq, op->d_qpts, op->d_normal,
+                       nq, qxyz, sig, f);
+    hipLaunchKernelGGL(k_rhs_assemble2, dim3(blocks(op->nt)), dim3(256), 0, s, op->nt, op->nq, op->d_qw, f, b);
+  }
   FMM_HIP_TRY(hipGetLastError());
   FMM_HIP_TRY(hipFreeAsync(sig, s));
   FMM_HIP_TRY(hipFreeAsync(f, s));
@@ -797,6 +1010,7 @@ int bem_info(const bem_op *op, bem_info_t *o) {
   o->n_singular_pairs = op->npair;
   o->quad_pts = op->nq;
   o->precision = op->precision;
+  o->formulation = op->formulation;
   return FMM_OK;
 }
 

@@ -44,7 +44,7 @@ int eval_dispatch(fmm_plan *P, const void *q, int nrhs, void *pot, void *grad, h
 int eval_pair_dispatch(fmm_plan *A, fmm_plan *B, const void *q, int nrhs, void *pot_a, void *grad_a, void *pot_b,
                        void *grad_b, hipStream_t s);
 int eval_pair_md_dispatch(fmm_plan *A, fmm_plan *B, const void *q, const void *dip, double ca, double cb, void *pot_a,
-                          void *pot_b, hipStream_t s);
+                          void *grad_a, void *pot_b, void *grad_b, hipStream_t s);
 int adjoint_combine(fmm_plan *P, int nrhs, const void *q, const void *gbar, const void *gphi, const void *gpsi,
                     void *dx, hipStream_t s);
 
@@ -1327,7 +1327,7 @@ int fmm_eval_pair(fmm_plan *A, fmm_plan *B, const void *q_dev, int nrhs, void *p
 }
 
 int fmm_eval_pair_md(fmm_plan *A, fmm_plan *B, const void *q_dev, const void *dip_dev, double qscale_a,
-                     double qscale_b, void *pot_a, void *pot_b, fmm_stream_t stream) {
+                     double qscale_b, void *pot_a, void *grad_a, void *pot_b, void *grad_b, fmm_stream_t stream) {
   if (!A || !B || A == B) { set_error("fmm_eval_pair_md: need two plans"); return FMM_EINVAL; }
   if (!shares_tree(A, B)) {
     set_error("fmm_eval_pair_md: plan_a must be a Laplace and plan_b a Yukawa plan on the same points, p, ncrit "
@@ -1340,7 +1340,8 @@ int fmm_eval_pair_md(fmm_plan *A, fmm_plan *B, const void *q_dev, const void *di
   }
   if (A->n == 0) return FMM_OK;
   if (!q_dev || !dip_dev || !pot_a || !pot_b) { set_error("fmm_eval_pair_md: null buffer"); return FMM_EINVAL; }
-  return eval_pair_md_dispatch(A, B, q_dev, dip_dev, qscale_a, qscale_b, pot_a, pot_b, (hipStream_t)stream);
+  return eval_pair_md_dispatch(A, B, q_dev, dip_dev, qscale_a, qscale_b, pot_a, grad_a, pot_b, grad_b,
+                               (hipStream_t)stream);
 }
 
 int fmm_adjoint(fmm_plan *P, const void *q, const void *gbar, const void *gfwd, int nrhs, void *dq, void *dxyz,

@@ -1148,9 +1148,13 @@ __global__ __launch_bounds__(512) void k_surf_eval_pair_md(
   }
 }
 
-template <typename T, bool CHECK>
+// Gradient (GRAD): grad_x [c q g + (d.u) f] = f d + ((d.u) h - c q f) u,
+// u = x - y, h = f'(r)/r: Laplace -3/r^5, Yukawa
+// -(kappa^2 r^2 + 3 kappa r + 3) e^{-kappa r}/r^5.
+template <typename T, bool CHECK, bool GRAD = false>
 __device__ __forceinline__ void leaf_pair_md(T xi, T yi, T zi, const typename Vec4<T>::type &sp,
-                                             const typename Vec4<T>::type &sd, T kappa, T kl2, T &pa, T &pb) {
+                                             const typename Vec4<T>::type &sd, T kappa, T kl2, T &pa, T &pb,
+                                             T *ga = nullptr, T *gb = nullptr) {
   const T dx = xi - sp[0], dy = yi - sp[1], dz = zi - sp[2];
   const T r2 = dx * dx + dy * dy + dz * dz;
   T invr = dev_rsqrt(r2);
@@ -1159,13 +1163,27 @@ __device__ __forceinline__ void leaf_pair_md(T xi, T yi, T zi, const typename Ve
   const T dd = sd[0] * dx + sd[1] * dy + sd[2] * dz;
   const T r = r2 * invr;
   const T gy = dev_exp2(-kl2 * r) * invr;
-  pa += invr * sp[3] + (i2 * invr) * dd;
-  pb += gy * sd[3] + (((T)1 + kappa * r) * gy * i2) * dd;
+  const T fl = i2 * invr;
+  const T kr = kappa * r;
+  const T fy = ((T)1 + kr) * gy * i2;
+  pa += invr * sp[3] + fl * dd;
+  pb += gy * sd[3] + fy * dd;
+  if (GRAD) {
+    const T hl = (T)-3 * fl * i2;
+    const T hy = -(kr * kr + (T)3 * kr + (T)3) * gy * i2 * i2;
+    const T tl = dd * hl - fl * sp[3], ty = dd * hy - fy * sd[3];
+    ga[0] += fl * sd[0] + tl * dx;
+    ga[1] += fl * sd[1] + tl * dy;
+    ga[2] += fl * sd[2] + tl * dz;
+    gb[0] += fy * sd[0] + ty * dx;
+    gb[1] += fy * sd[1] + ty * dy;
+    gb[2] += fy * sd[2] + ty * dz;
+  }
 }
 
 // Near field of monopole + dipole sources, both kernels, potentials only;
 // running sums to acc in the layout of k_near_pair with one column.
-template <typename T>
+template <typename T, bool GRAD>
 __global__ __launch_bounds__(64) void k_near_pair_md(
     const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts,
     const T *__restrict__ dips, const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end,
@@ -1190,6 +1208,7 @@ __global__ __launch_bounds__(64) void k_near_pair_md(
     const T xi = xv[0], yi = xv[1], zi = xv[2];
     const T kl2 = kappa * (T)1.4426950408889634;
     T pa = 0, pb = 0;
+    T ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
     const int u1 = near_off[item + 1];
     for (int u = near_off[item]; u < u1; ++u) {
       const int j0 = near_rng[2 * u], j1 = near_rng[2 * u + 1];
@@ -1198,10 +1217,10 @@ __global__ __launch_bounds__(64) void k_near_pair_md(
       if (split == 1) {
         if (self) {
 #pragma unroll 4
-          for (int j = j0; j < j1; ++j) leaf_pair_md<T, true>(xt, yt, zt, p4[j], d4[j], kappa, kl2, pa, pb);
+          for (int j = j0; j < j1; ++j) leaf_pair_md<T, true, GRAD>(xt, yt, zt, p4[j], d4[j], kappa, kl2, pa, pb, ga, gb);
         } else {
 #pragma unroll 8
-          for (int j = j0; j < j1; ++j) leaf_pair_md<T, false>(xt, yt, zt, p4[j], d4[j], kappa, kl2, pa, pb);
+          for (int j = j0; j < j1; ++j) leaf_pair_md<T, false, GRAD>(xt, yt, zt, p4[j], d4[j], kappa, kl2, pa, pb, ga, gb);
         }
       } else {
         // split: lane half h takes sources j0 + h, j0 + h + 2, ...; a missing
@@ -1211,7 +1230,7 @@ __global__ __launch_bounds__(64) void k_near_pair_md(
           const bool ok = jj < j1;
           V4 sp = p4[ok ? jj : j], sd = d4[ok ? jj : j];
           if (!ok) { sp[3] = (T)0; sd = V4{0, 0, 0, 0}; }
-          leaf_pair_md<T, decltype(chk)::value>(xt, yt, zt, sp, sd, kappa, kl2, pa, pb);
+          leaf_pair_md<T, decltype(chk)::value, GRAD>(xt, yt, zt, sp, sd, kappa, kl2, pa, pb, ga, gb);
         };
         if (self) {
 #pragma unroll 2
@@ -1225,6 +1244,13 @@ __global__ __launch_bounds__(64) void k_near_pair_md(
     T *a = acc + (int64_t)item * 2 * 4 * 64;
     a[lane] = pa;
     a[4 * 64 + lane] = pb;
+    if (GRAD) {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        a[(1 + e) * 64 + lane] = ga[e];
+        a[(5 + e) * 64 + lane] = gb[e];
+      }
+    }
   }
 }
 
@@ -1772,8 +1798,9 @@ int ensure_pair_md(fmm_plan *A, fmm_plan *B);  // host: the permuted dipole reco
 // Pair evaluation with monopole + dipole sources, potentials only (one
 // column); the same stream layout as eval_pair_chunk.
 template <typename T>
-static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip, T ca, T cb, T *pot_a, T *pot_b,
-                              hipStream_t s) {
+static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip, T ca, T cb, T *pot_a, T *grad_a,
+                              T *pot_b, T *grad_b, hipStream_t s) {
+  const bool grad = grad_a || grad_b;
   int rc;
   if ((rc = ensure_work(A, 1)) || (rc = ensure_lists(A, 1)) || (rc = ensure_work(B, 1)) ||
       (rc = ensure_lists(B, 1)) || (rc = ensure_pair(A, B, 1)) || (rc = ensure_pair_md(A, B)))
@@ -1799,14 +1826,27 @@ static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip
   T *acc = (T *)A->pair_acc;
   ev = prof_begin(A, FMM_PHASE_NEAR, s);
   if (D.nitems > 0)
-    hipLaunchKernelGGL((k_near_pair_md<T>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts,
-                       (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng, (const T *)D.near_o, acc,
-                       kappa, D.nitems);
+  {
+    if (grad)
+      hipLaunchKernelGGL((k_near_pair_md<T, true>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
+                         (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
+                         (const T *)D.near_o, acc, kappa, D.nitems);
+    else
+      hipLaunchKernelGGL((k_near_pair_md<T, false>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
+                         (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
+                         (const T *)D.near_o, acc, kappa, D.nitems);
+  }
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_NEAR, ev, s);
   if (far) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
   ev = prof_begin(A, FMM_PHASE_FAR, s);
-  if (D.nitems > 0)
+  if (D.nitems > 0 && grad)
+    hipLaunchKernelGGL((k_far_pair<T, 1, true>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts,
+                       N, D.box_begin, D.box_end, (const T *)A->surf, A->nsurf, A->ld, D.far_off, D.far_idx,
+                       (const T *)D.far_o, (const T *)acc, (const T *)A->equ, (const T *)A->eqd, (const T *)B->equ,
+                       (const T *)B->eqd, (T *)D.parts, (T *)B->dt.parts, D.perm, pot_a, grad_a, pot_b, grad_b,
+                       kappa, scale);
+  else if (D.nitems > 0)
     hipLaunchKernelGGL((k_far_pair<T, 1, false>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts,
                        N, D.box_begin, D.box_end, (const T *)A->surf, A->nsurf, A->ld, D.far_off, D.far_idx,
                        (const T *)D.far_o, (const T *)acc, (const T *)A->equ, (const T *)A->eqd, (const T *)B->equ,
@@ -1814,9 +1854,9 @@ static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip
                        (T *)nullptr, kappa, scale);
   if (D.nsplit > 0) {
     hipLaunchKernelGGL((k_leaf_parts<T, 1>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
-                       D.box_end, (const T *)D.parts, D.perm, N, pot_a, (T *)nullptr, scale);
+                       D.box_end, (const T *)D.parts, D.perm, N, pot_a, grad_a, scale);
     hipLaunchKernelGGL((k_leaf_parts<T, 1>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
-                       D.box_end, (const T *)B->dt.parts, D.perm, N, pot_b, (T *)nullptr, scale);
+                       D.box_end, (const T *)B->dt.parts, D.perm, N, pot_b, grad_b, scale);
   }
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_FAR, ev, s);
@@ -1824,12 +1864,12 @@ static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip
 }
 
 int eval_pair_md_dispatch(fmm_plan *A, fmm_plan *B, const void *q, const void *dip, double ca, double cb, void *pot_a,
-                          void *pot_b, hipStream_t s) {
+                          void *grad_a, void *pot_b, void *grad_b, hipStream_t s) {
   if (A->precision == FMM_FP64)
     return eval_pair_md_typed<double>(A, B, (const double *)q, (const double *)dip, ca, cb, (double *)pot_a,
-                                      (double *)pot_b, s);
+                                      (double *)grad_a, (double *)pot_b, (double *)grad_b, s);
   return eval_pair_md_typed<float>(A, B, (const float *)q, (const float *)dip, (float)ca, (float)cb, (float *)pot_a,
-                                   (float *)pot_b, s);
+                                   (float *)grad_a, (float *)pot_b, (float *)grad_b, s);
 }
 
 // dxyz_k = sum_c gbar_ck gphi_ck + q_ck gpsi_ck  (c over density columns)

@@ -167,10 +167,11 @@ def eval_pair(plan_a: FMMPlan, plan_b: FMMPlan, q: torch.Tensor, gradient: bool 
 
 
 def eval_pair_md(plan_a: FMMPlan, plan_b: FMMPlan, q: torch.Tensor, dip: torch.Tensor, qscale_a: float = 1.0,
-                 qscale_b: float = 1.0):
+                 qscale_b: float = 1.0, gradient: bool = False):
     """Potentials of monopole (q, (N,)) and dipole (dip, (N, 3)) sources for a
     Laplace plan_a and a Yukawa plan_b sharing one tree (fmm_eval_pair_md):
-    pot_k = qscale_k G_k q + sum_j dip_j . grad_y g_k.  Returns (pot_a, pot_b)."""
+    pot_k = qscale_k G_k q + sum_j dip_j . grad_y g_k.  Returns (pot_a, pot_b),
+    or ((pot_a, grad_a), (pot_b, grad_b)) with gradient=True."""
     n = plan_a.n
     qq = q.reshape(-1).to(device=plan_a.device, dtype=plan_a.dtype).contiguous()
     dd = dip.reshape(-1, 3).to(device=plan_a.device, dtype=plan_a.dtype).contiguous()
@@ -178,6 +179,10 @@ def eval_pair_md(plan_a: FMMPlan, plan_b: FMMPlan, q: torch.Tensor, dip: torch.T
         raise ValueError("q and dip must have one entry per point")
     pa = torch.empty(n, dtype=plan_a.dtype, device=plan_a.device)
     pb = torch.empty(n, dtype=plan_a.dtype, device=plan_a.device)
+    ga = torch.empty((n, 3), dtype=plan_a.dtype, device=plan_a.device) if gradient else None
+    gb = torch.empty((n, 3), dtype=plan_a.dtype, device=plan_a.device) if gradient else None
     check(lib().fmm_eval_pair_md(plan_a._h, plan_b._h, _ptr(qq), _ptr(dd), float(qscale_a), float(qscale_b),
-                                 _ptr(pa), _ptr(pb), _stream()), "fmm_eval_pair_md")
+                                 _ptr(pa), _ptr(ga), _ptr(pb), _ptr(gb), _stream()), "fmm_eval_pair_md")
+    if gradient:
+        return (pa, ga), (pb, gb)
     return pa, pb

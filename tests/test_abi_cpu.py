@@ -65,19 +65,21 @@ def test_pair_entry_points_reject_null_plans():
     L = _lib.lib()
     assert L.fmm_eval_pair(None, None, None, 1, None, None, None, None, None) == _lib.FMM_EINVAL
     assert "plan" in L.fmm_last_error().decode()
-    assert L.fmm_eval_pair_md(None, None, None, None, 1.0, 1.0, None, None, None) == _lib.FMM_EINVAL
+    assert L.fmm_eval_pair_md(None, None, None, None, 1.0, 1.0, None, None, None, None, None) == _lib.FMM_EINVAL
     assert "two plans" in L.fmm_last_error().decode()
     assert L.fmm_adjoint(None, None, None, None, 1, None, None, None) == _lib.FMM_EINVAL
 
 
-@pytest.mark.parametrize("case", ["quad", "eps", "kappa", "index", "degenerate"])
+@pytest.mark.parametrize("case", ["quad", "eps", "kappa", "index", "degenerate", "formulation"])
 def test_bem_setup_rejects_bad_arguments(case):
     import numpy as np
     L = _lib.lib()
     v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
     t = np.array([[0, 1, 2], [0, 1, 3]], dtype=np.int32)
-    quad, eps, kap = 3, 4.0, 0.1
-    if case == "quad":
+    quad, eps, kap, form = 3, 4.0, 0.1, 0
+    if case == "formulation":
+        form = 2
+    elif case == "quad":
         quad = 4
     elif case == "eps":
         eps = -1.0
@@ -89,5 +91,5 @@ def test_bem_setup_rejects_bad_arguments(case):
         t = np.array([[0, 1, 1]], dtype=np.int32)
     h = ctypes.c_void_p()
     rc = L.bem_setup(ctypes.c_void_p(v.ctypes.data), len(v), ctypes.c_void_p(t.ctypes.data), len(t), quad, eps, 80.0,
-                     kap, 6, 64, 1, None, ctypes.byref(h))
+                     kap, 6, 64, 1, form, None, ctypes.byref(h))
     assert rc == _lib.FMM_EINVAL and not h.value
