@@ -87,6 +87,8 @@ def parse():
                     help="surface393k: the headline workload; batch64: 64 uneven molecules in one batched plan "
                          "against 64 separate plans per kernel; bem2m: boundary-element matvec and GMRES solve "
                          "on 2M triangles")
+    ap.add_argument("--formulation", default="direct", choices=["direct", "derivative"],
+                    help="boundary-element formulation of the bem2m workload")
     ap.add_argument("--p-sweep", default="4,5,6,7",
                     help="expansion orders below the workload's p also timed and checked against the sampled "
                          "direct sums (needs the CPU leg); empty to skip")
@@ -180,7 +182,8 @@ def run_bem(args):
     qxyz, q = synth.charges_in_spheres(su, 20000, seed=91)
     print(f"# mesh {len(t)} triangles in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ncrit = args.ncrit or 128
-    kw = dict(quad_pts=3, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=P_ORDER, ncrit=ncrit)
+    kw = dict(quad_pts=3, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=P_ORDER, ncrit=ncrit,
+              formulation=args.formulation)
     t0 = time.perf_counter()
     op32 = BEMOperator(v, t, precision="fp32", **kw)
     t_setup32 = time.perf_counter() - t0
@@ -213,14 +216,14 @@ def run_bem(args):
     res = ((b - op64.matvec(xs)).norm() / b.norm()).item()
     energy = op32.energy(xs, qxyz, q)
     npts = 3 * T
-    line = {"metric": "bem_matvec time, 2M triangles (Laplace + Yukawa, single + double layer as one "
-                      "monopole + dipole FMM pass per kernel)",
+    line = {"metric": f"bem_matvec time, 2M triangles, {args.formulation} formulation (Laplace + Yukawa, single + "
+                      "double layer as one monopole + dipole FMM pass per kernel)",
             "value": round(t32 * 1e3, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 2,
             "ms_per_step": round(t32 * 1e3, 3), "higher_is_better": False, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"sphere-union BEM, 1000 spheres, {T} triangles x 3 points = {npts} points, "
                                    "20000 charges, direct formulation (P0), eps 4/80, kappa 0.125",
-                       "p": P_ORDER, "ncrit": ncrit},
+                       "p": P_ORDER, "ncrit": ncrit, "formulation": args.formulation},
             "fmm_mpoints_per_s": round(2 * npts / t32 / 1e6, 1),
             "fp64_matvec_ms": round(t64 * 1e3, 3),
             "gmres": {"status": rc, "iterations": its, "seconds": round(t_solve, 3),
