@@ -222,7 +222,7 @@ def run_bem(args):
             "ms_per_step": round(t32 * 1e3, 3), "higher_is_better": False, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"sphere-union BEM, 1000 spheres, {T} triangles x 3 points = {npts} points, "
-                                   "20000 charges, direct formulation (P0), eps 4/80, kappa 0.125",
+                                   f"20000 charges, {args.formulation} formulation (P0), eps 4/80, kappa 0.125",
                        "p": P_ORDER, "ncrit": ncrit, "formulation": args.formulation},
             "fmm_mpoints_per_s": round(2 * npts / t32 / 1e6, 1),
             "fp64_matvec_ms": round(t64 * 1e3, 3),
