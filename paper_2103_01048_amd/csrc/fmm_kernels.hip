@@ -40,7 +40,18 @@ __device__ inline doublex4 mfma_16x16x4(double a, double b, doublex4 c) {
 }
 
 __device__ inline float dev_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ inline double dev_rsqrt(double x) { return 1.0 / sqrt(x); }
+// FP64 reciprocal square root: the hardware estimate refined by two
+// Newton-Raphson steps for 1/sqrt(x), y <- y (3/2 - (x/2) y^2), each of which
+// doubles the number of correct bits (the estimate's ~2^-22 relative error
+// becomes a few ulp); x = 0 gives inf like 1/sqrt(0).
+__device__ inline double dev_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  if (!(x > 0.0) || !(y < 1.0e300)) return y;
+  const double h = 0.5 * x;
+  y = y * fma(-h, y * y, 1.5);
+  y = y * fma(-h, y * y, 1.5);
+  return y;
+}
 __device__ inline float dev_exp(float x) { return __expf(x); }
 __device__ inline double dev_exp(double x) { return exp(x); }
 __device__ inline float dev_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
