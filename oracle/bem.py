@@ -385,6 +385,9 @@ def energy_direct(m: Mesh, x, qxyz, q):
 # Coulomb potential / eps1.  With P0 Galerkin and the same rule on both
 # triangles, K' is the transpose of K.  Only the difference W_Y - W_L of the
 # hypersingular operators appears; its kernel is weakly singular.
+# The exterior variant (eq:lu) is the same pair of equations scaled by
+# eps1/eps2 and solved for the solvent-side unknowns phi_2 and d phi_2/dn;
+# the interface conditions map its solution back to (u, v).
 # ---------------------------------------------------------------------------
 def _h_derivs(r, kappa):
     """h = (exp(-kappa r) - 1)/(4 pi r) (the Yukawa minus the Laplace
@@ -510,3 +513,49 @@ def solve_derivative(m: Mesh, qxyz, q, eps1=4.0, eps2=80.0, kappa=0.125, **kw):
     A = system_derivative(m, eps1, eps2, kappa, **kw)
     b = rhs_derivative(m, qxyz, q, eps1)
     return np.linalg.solve(A, b), A, b
+
+
+# ---- exterior derivative formulation (eq:lu) -------------------------------
+def system_exterior(m: Mesh, eps1: float, eps2: float, kappa: float, **kw):
+    """Exterior derivative formulation (eq:lu, the variant of Lu and
+    co-workers), unknowns phi_2 and d phi_2 / dn on the solvent side, with
+    e12 = eps1 / eps2:
+      [ (1 + e12)/2 M - (K_Y - e12 K_L)   V_Y - V_L                      ]
+      [ e12 (W_Y - W_L)                   (1 + e12)/2 M + e12 K'_Y - K'_L ]
+    (P0 Galerkin: K' is the transpose of K)."""
+    VL, KL = operators(m, 0.0, **kw)
+    VY, KY = operators(m, kappa, **kw)
+    Wd = hyper_diff_operator(m, kappa, **kw)
+    M = np.diag(m.area)
+    e12 = eps1 / eps2
+    return np.block([[0.5 * (1 + e12) * M - (KY - e12 * KL), VY - VL],
+                     [e12 * Wd, 0.5 * (1 + e12) * M + (e12 * KY.T - KL.T)]])
+
+
+def rhs_exterior(m: Mesh, qxyz, q, eps2: float):
+    """Right-hand side of eq:lu: the Coulomb term of the charges and its
+    normal derivative, divided by the solvent permittivity eps2."""
+    return rhs_derivative(m, qxyz, q, eps2)
+
+
+def interior_unknowns(x, eps1: float, eps2: float):
+    """(phi_1, d phi_1/dn) from the exterior unknowns (phi_2, d phi_2/dn) by
+    the interface conditions: the potential is continuous and eps1 d phi_1/dn
+    = eps2 d phi_2/dn.  The reaction potential and energy take these."""
+    x = np.asarray(x, dtype=np.float64)
+    T = len(x) // 2
+    return np.concatenate([x[:T], (eps2 / eps1) * x[T:]])
+
+
+def solve_exterior(m: Mesh, qxyz, q, eps1=4.0, eps2=80.0, kappa=0.125, **kw):
+    A = system_exterior(m, eps1, eps2, kappa, **kw)
+    b = rhs_exterior(m, qxyz, q, eps2)
+    return np.linalg.solve(A, b), A, b
+
+
+def mass_preconditioned(m: Mesh, A):
+    """diag(M, M)^-1 A: the mass-matrix preconditioned operator whose
+    eigenvalues the paper studies (for P0 elements the mass matrix is already
+    diagonal, so mass lumping changes nothing)."""
+    d = np.concatenate([m.area, m.area])
+    return A / d[:, None]

@@ -218,3 +218,72 @@ def test_derivative_formulation_converges_and_stays_conditioned():
     order = math.log(err[0] / err[1]) / math.log(4.0)
     assert 0.85 < order < 1.15, (err, order)
     assert cond_d[1] / cond_d[0] < 1.1 and cond_0[1] / cond_0[0] > 1.5
+
+
+# ---- exterior derivative formulation (eq:lu) ------------------------------
+def test_exterior_formulation_meets_the_interface_conditions():
+    """eq:lu is solved for the solvent-side unknowns; mapped through the
+    interface conditions (continuous potential, eps1 dphi_1/dn = eps2
+    dphi_2/dn) its solution must be the Juffer solution of eq:juffer."""
+    v, t = synth.octa_sphere(2, 4.0)
+    m = bem.make_mesh(v, t, 3)
+    qx, q = [[1.0, 1.0, 1.0], [-0.7, 0.2, 0.4]], [1.0, -0.5]
+    xe, _, _ = bem.solve_exterior(m, qx, q)
+    xj, _, _ = bem.solve_derivative(m, qx, q)
+    np.testing.assert_allclose(bem.interior_unknowns(xe, 4.0, 80.0), xj, rtol=1e-10, atol=1e-12 * np.abs(xj).max())
+
+
+def test_exterior_formulation_kirkwood_convergence():
+    ref = A.kirkwood_energy(4.0, [1, 1, 1], [1.0], 4.0, 80.0, KAPPA)
+    err = []
+    for lev in (2, 3):
+        v, t = synth.octa_sphere(lev, 4.0)
+        m = bem.make_mesh(v, t, 3)
+        xe, _, _ = bem.solve_exterior(m, [[1, 1, 1]], [1.0])
+        err.append(abs(bem.energy(m, bem.interior_unknowns(xe, 4.0, 80.0), [[1, 1, 1]], [1.0]) - ref))
+    order = math.log(err[0] / err[1]) / math.log(4.0)
+    assert 0.85 < order < 1.15, (err, order)
+
+
+def _gmres_iterations(Am, b, tol=1e-8, maxit=200):
+    """Iterations of full GMRES (no restart) to a relative residual tol."""
+    n = len(b)
+    beta = np.linalg.norm(b)
+    V = np.zeros((n, maxit + 1))
+    H = np.zeros((maxit + 1, maxit))
+    V[:, 0] = b / beta
+    for j in range(maxit):
+        w = Am @ V[:, j]
+        for _ in range(2):
+            h = V[:, :j + 1].T @ w
+            w -= V[:, :j + 1] @ h
+            H[:j + 1, j] += h
+        H[j + 1, j] = np.linalg.norm(w)
+        V[:, j + 1] = w / H[j + 1, j]
+        e1 = np.zeros(j + 2)
+        e1[0] = beta
+        y = np.linalg.lstsq(H[:j + 2, :j + 1], e1, rcond=None)[0]
+        if np.linalg.norm(H[:j + 2, :j + 1] @ y - e1) <= tol * beta:
+            return j + 1
+    return maxit
+
+
+def test_mass_preconditioned_spectra_and_iterations():
+    """Under mass-matrix preconditioning the interior (Juffer) operator's
+    eigenvalues gather at (1 + eps2/eps1)/2 and (1 + eps1/eps2)/2, the
+    exterior operator's at (1 + eps1/eps2)/2 alone, and GMRES on the exterior
+    form needs about half the iterations (Results: the two derivative
+    variants and their eigenvalues)."""
+    v, t = synth.octa_sphere(2, 4.0)
+    m = bem.make_mesh(v, t, 3)
+    lo, hi = 0.5 * (1 + 4.0 / 80.0), 0.5 * (1 + 80.0 / 4.0)
+    Aj = bem.mass_preconditioned(m, bem.system_derivative(m, 4.0, 80.0, KAPPA))
+    Ae = bem.mass_preconditioned(m, bem.system_exterior(m, 4.0, 80.0, KAPPA))
+    ej, ee = np.linalg.eigvals(Aj), np.linalg.eigvals(Ae)
+    assert np.max(np.abs(ee - lo)) < 0.5
+    assert np.mean(np.abs(ej - lo) < 0.5) > 0.45 and np.mean(np.abs(ej - hi) < 2.0) > 0.45
+    d = np.concatenate([m.area, m.area])
+    qx, q = [[1.0, 1.0, 1.0]], [1.0]
+    it_j = _gmres_iterations(Aj, bem.rhs_derivative(m, qx, q, 4.0) / d)
+    it_e = _gmres_iterations(Ae, bem.rhs_exterior(m, qx, q, 80.0) / d)
+    assert it_e <= 0.6 * it_j, (it_e, it_j)
