@@ -87,8 +87,10 @@ def parse():
                     help="surface393k: the headline workload; batch64: 64 uneven molecules in one batched plan "
                          "against 64 separate plans per kernel; bem2m: boundary-element matvec and GMRES solve "
                          "on 2M triangles")
-    ap.add_argument("--formulation", default="direct", choices=["direct", "derivative"],
+    ap.add_argument("--formulation", default="direct", choices=["direct", "derivative", "exterior"],
                     help="boundary-element formulation of the bem2m workload")
+    ap.add_argument("--precond", default="block", choices=["block", "mass"],
+                    help="GMRES preconditioner of the bem2m workload")
     ap.add_argument("--p-sweep", default="4,5,6,7",
                     help="expansion orders below the workload's p also timed and checked against the sampled "
                          "direct sums (needs the CPU leg); empty to skip")
@@ -169,7 +171,7 @@ def run_batch(args):
 
 
 def run_bem(args):
-    """Direct-formulation BEM on 2,000,000 triangles x 3 points (1,000-sphere
+    """BEM (formulation and preconditioner from the arguments) on 2,000,000 triangles x 3 points (1,000-sphere
     union, caps stopping short of the intersection curves), 20,000 charges:
     bem_matvec time (FP32 FMM, FP64 assembly), and a GMRES solve to 1e-6
     (FP32 operator, FP64 refinement) with the energy."""
@@ -183,7 +185,7 @@ def run_bem(args):
     print(f"# mesh {len(t)} triangles in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ncrit = args.ncrit or 128
     kw = dict(quad_pts=3, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=P_ORDER, ncrit=ncrit,
-              formulation=args.formulation)
+              formulation=args.formulation, preconditioner=args.precond)
     t0 = time.perf_counter()
     op32 = BEMOperator(v, t, precision="fp32", **kw)
     t_setup32 = time.perf_counter() - t0
@@ -223,7 +225,8 @@ def run_bem(args):
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"sphere-union BEM, 1000 spheres, {T} triangles x 3 points = {npts} points, "
                                    f"20000 charges, {args.formulation} formulation (P0), eps 4/80, kappa 0.125",
-                       "p": P_ORDER, "ncrit": ncrit, "formulation": args.formulation},
+                       "p": P_ORDER, "ncrit": ncrit, "formulation": args.formulation,
+                       "preconditioner": args.precond},
             "fmm_mpoints_per_s": round(2 * npts / t32 / 1e6, 1),
             "fp64_matvec_ms": round(t64 * 1e3, 3),
             "gmres": {"status": rc, "iterations": its, "seconds": round(t_solve, 3),

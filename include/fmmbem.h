@@ -243,6 +243,13 @@ void fmm_free(fmm_plan *plan);
  *   layer and W the hypersingular operator (eq:adj_hyp).  Only the
  *   difference W_Y - W_L appears; its kernel is weakly singular.
  *
+ * FMM_BEM_EXTERIOR (eq:lu, the exterior variant of Lu and co-workers): the
+ *   same equations scaled by e12 and solved for the solvent-side unknowns
+ *   u = phi_2 and v = d phi_2/dn:
+ *   [ (1 + e12)/2 M - (K_Y - e12 K_L)   V_Y - V_L                        ] [u]   [b ]
+ *   [ e12 (W_Y - W_L)                   (1 + e12)/2 M + e12 K'_Y - K'_L  ] [v] = [b'],
+ *   b and b' with 1/eps_out in place of 1/eps_in.
+ *
  * V and K are the single- and double-layer operators of the Laplace (L) and
  * Yukawa (Y) kernels.  G is evaluated by one fmm_eval_pair_md call per
  * product (charges W v and dipoles W u n at the regular quadrature points;
@@ -253,14 +260,20 @@ void fmm_free(fmm_plan *plan);
  * Yukawa-minus-Laplace remainders; K' uses the transposed K pair), applied
  * as one precomputed sparse FP64 matrix S - C.
  * ------------------------------------------------------------------------ */
-enum { FMM_BEM_DIRECT = 0, FMM_BEM_DERIVATIVE = 1 };
+enum { FMM_BEM_DIRECT = 0, FMM_BEM_DERIVATIVE = 1, FMM_BEM_EXTERIOR = 2 };
+/* Preconditioners (Results, the preconditioners of the two formulation
+ * families): per-triangle 2 x 2 block-diagonal (the inverse of A's block on
+ * the identical pair, after Altman and co-workers) or the mass matrix
+ * diag(M, M) (diagonal for P0 elements, so mass lumping is exact). */
+enum { FMM_BEM_PRECOND_BLOCK = 0, FMM_BEM_PRECOND_MASS = 1 };
 
 /* Build the operator.  verts (nv x 3 doubles) and tris (nt x 3 int32, vertex
  * indices, counter-clockwise seen from the solvent so that normals point
  * out of the molecule) are HOST arrays read during the call.  quad_pts: 3 or
  * 6 (regular rule per triangle); eps_in, eps_out > 0; kappa >= 0; p, ncrit,
  * precision as for fmm_setup (the two FMM plans); formulation:
- * FMM_BEM_DIRECT or FMM_BEM_DERIVATIVE.  Synchronises `stream`.  Errors:
+ * FMM_BEM_DIRECT, FMM_BEM_DERIVATIVE or FMM_BEM_EXTERIOR.  The preconditioner
+ * starts as FMM_BEM_PRECOND_BLOCK.  Synchronises `stream`.  Errors:
  * FMM_EINVAL for bad sizes, indices or parameters, a degenerate triangle;
  * FMM_ENOMEM; FMM_EHIP. */
 int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, int quad_pts, double eps_in,
@@ -273,13 +286,16 @@ int bem_matvec(bem_op *op, const double *x_dev, double *y_dev, fmm_stream_t stre
 
 /* Right-hand side b_dev (2*nt doubles) for nq point charges at qxyz_dev
  * (device, nq x 3) with charges q_dev (device, nq), e and Angstrom:
- * b_s = int_Ts (1/eps_in) sum_k q_k / (4 pi |x - r_k|); second block 0
- * (direct) or int_Ts n_s . grad of the same sum (derivative); regular rule,
+ * b_s = int_Ts (1/eps) sum_k q_k / (4 pi |x - r_k|), eps = eps_out for the
+ * exterior formulation and eps_in otherwise; second block 0 (direct) or
+ * int_Ts n_s . grad of the same sum (derivative, exterior); regular rule,
  * FP64 direct sums.  Asynchronous. */
 int bem_rhs(bem_op *op, const double *qxyz_dev, const double *q_dev, int64_t nq, double *b_dev,
             fmm_stream_t stream);
 
-/* Polar solvation energy (kcal/mol) of the charges for the solution x_dev:
+/* Polar solvation energy (kcal/mol) of the charges for the solution x_dev of
+ * the operator's formulation (exterior unknowns are first mapped to the
+ * solute side, v -> (eps_out/eps_in) v, by the interface conditions):
  * reaction potential phi_reac(r_k) = -K_L u + V_L v evaluated at the charges
  * (eq. of the reaction potential, FP64 direct sum over the quadrature
  * points), dG = 1/2 sum_k q_k phi_reac(r_k) * 4 pi * 332.0637 (FP64
@@ -287,12 +303,17 @@ int bem_rhs(bem_op *op, const double *qxyz_dev, const double *q_dev, int64_t nq,
 int bem_energy(bem_op *op, const double *x_dev, const double *qxyz_dev, const double *q_dev, int64_t nq,
                double *dG, fmm_stream_t stream);
 
-/* Apply the block-diagonal preconditioner (per triangle, the inverse of the
- * 2 x 2 block of A on the identical-pair entries): y = P^-1 x.  Device
- * vectors of 2*nt doubles.  Asynchronous. */
+/* Select the preconditioner used by bem_precondition and gmres_solve:
+ * FMM_BEM_PRECOND_BLOCK or FMM_BEM_PRECOND_MASS (FMM_EINVAL otherwise).
+ * Asynchronous on `stream`. */
+int bem_set_preconditioner(bem_op *op, int kind, fmm_stream_t stream);
+
+/* Apply the selected preconditioner (per triangle a 2 x 2 block: the inverse
+ * of A's block on the identical pair, or diag(1/area, 1/area)): y = P^-1 x.
+ * Device vectors of 2*nt doubles.  Asynchronous. */
 int bem_precondition(bem_op *op, const double *x_dev, double *y_dev, fmm_stream_t stream);
 
-/* FP64 GMRES on A x = b with right block-diagonal preconditioning,
+/* FP64 GMRES on A x = b with right preconditioning (bem_precondition),
  * classical Gram-Schmidt with reorthogonalisation on the device and Givens
  * rotations on the host.  restart: Krylov dimension before a restart
  * (<= 0: maxiter, full GMRES).  Stops when the recomputed residual
@@ -315,6 +336,7 @@ typedef struct {
   int32_t quad_pts;
   int32_t precision;
   int32_t formulation;
+  int32_t preconditioner;
 } bem_info_t;
 int bem_info(const bem_op *op, bem_info_t *out);
 

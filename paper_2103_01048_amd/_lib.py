@@ -12,7 +12,8 @@ LIB_PATH = os.path.join(HERE, "libfmmbem.so")
 
 FMM_LAPLACE, FMM_YUKAWA = 0, 1
 FMM_FP64, FMM_FP32, FMM_FP32_BF16X3 = 0, 1, 2
-FMM_BEM_DIRECT, FMM_BEM_DERIVATIVE = 0, 1
+FMM_BEM_DIRECT, FMM_BEM_DERIVATIVE, FMM_BEM_EXTERIOR = 0, 1, 2
+FMM_BEM_PRECOND_BLOCK, FMM_BEM_PRECOND_MASS = 0, 1
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOTCONV, FMM_EBREAKDOWN = 0, -1, -2, -3, -4, -5
 
 PHASES = ["permute", "p2m", "uc2e", "m2m", "p2l", "m2l", "m2l_sum", "l2l", "dc2e", "leaf", "near", "far"]
@@ -63,6 +64,7 @@ SIGNATURES = {
     "bem_rhs": (i32, [vp, vp, vp, i64, vp, vp]),
     "bem_energy": (i32, [vp, vp, vp, vp, i64, P(dbl), vp]),
     "bem_precondition": (i32, [vp, vp, vp, vp]),
+    "bem_set_preconditioner": (i32, [vp, i32, vp]),
     "gmres_solve": (i32, [vp, vp, vp, vp, dbl, dbl, i32, i32, P(i32), vp, vp]),
     "bem_info": (i32, [vp, vp]),
     "bem_fmm_plan": (vp, [vp, i32]),

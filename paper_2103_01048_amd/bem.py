@@ -14,18 +14,23 @@ from . import _lib
 from ._lib import check, lib
 from .fmm import PRECISIONS, _ptr, _stream
 
-FORMULATIONS = {"direct": _lib.FMM_BEM_DIRECT, "derivative": _lib.FMM_BEM_DERIVATIVE}
+FORMULATIONS = {"direct": _lib.FMM_BEM_DIRECT, "derivative": _lib.FMM_BEM_DERIVATIVE,
+                "exterior": _lib.FMM_BEM_EXTERIOR}
+PRECONDITIONERS = {"block": _lib.FMM_BEM_PRECOND_BLOCK, "mass": _lib.FMM_BEM_PRECOND_MASS}
 
 
 class BEMOperator:
     """P0 boundary-element operator on a triangle mesh (regular rule with
     quad_pts points): formulation "direct", [[M/2 + K_L, -V_L], [M/2 - K_Y,
-    (eps_in/eps_out) V_Y]], or "derivative" (Juffer), [[(1+e21)/2 M - (e21 K_Y -
-    K_L), V_Y - V_L], [W_Y - W_L, (1+e12)/2 M + e12 K'_Y - K'_L]]."""
+    (eps_in/eps_out) V_Y]], "derivative" (Juffer), [[(1+e21)/2 M - (e21 K_Y -
+    K_L), V_Y - V_L], [W_Y - W_L, (1+e12)/2 M + e12 K'_Y - K'_L]], or "exterior"
+    (Lu), [[(1+e12)/2 M - (K_Y - e12 K_L), V_Y - V_L], [e12 (W_Y - W_L), (1+e12)/2
+    M + e12 K'_Y - K'_L]] for the solvent-side unknowns.  preconditioner:
+    "block" (per-triangle 2 x 2 block-diagonal) or "mass" (diag(M, M))."""
 
     def __init__(self, verts, tris, quad_pts: int = 3, eps_in: float = 4.0, eps_out: float = 80.0,
                  kappa: float = 0.125, p: int = 6, ncrit: int = 128, precision: str = "fp32", device="cuda",
-                 formulation: str = "direct"):
+                 formulation: str = "direct", preconditioner: str = "block"):
         v = np.ascontiguousarray(verts, dtype=np.float64)
         t = np.ascontiguousarray(tris, dtype=np.int32)
         if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
@@ -43,6 +48,7 @@ class BEMOperator:
                                   PRECISIONS[precision], FORMULATIONS[formulation], _stream(), ctypes.byref(h)),
                   "bem_setup")
         self._h = h
+        self.set_preconditioner(preconditioner)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -64,6 +70,12 @@ class BEMOperator:
         y = torch.empty_like(x)
         check(lib().bem_matvec(self._h, _ptr(x), _ptr(y), _stream()), "bem_matvec")
         return y
+
+    def set_preconditioner(self, kind: str):
+        if kind not in PRECONDITIONERS:
+            raise ValueError(f"unknown preconditioner {kind!r}")
+        check(lib().bem_set_preconditioner(self._h, PRECONDITIONERS[kind], _stream()), "bem_set_preconditioner")
+        self.preconditioner = kind
 
     def precondition(self, x):
         x = self._vec(x)
@@ -91,9 +103,10 @@ class BEMOperator:
         raw = ctypes.create_string_buffer(40)
         check(lib().bem_info(self._h, raw), "bem_info")
         a = np.frombuffer(raw.raw[:24], dtype=np.int64)
-        b = np.frombuffer(raw.raw[24:36], dtype=np.int32)
+        b = np.frombuffer(raw.raw[24:40], dtype=np.int32)
         return {"n_triangles": int(a[0]), "n_points": int(a[1]), "n_singular_pairs": int(a[2]),
-                "quad_pts": int(b[0]), "precision": int(b[1]), "formulation": int(b[2])}
+                "quad_pts": int(b[0]), "precision": int(b[1]), "formulation": int(b[2]),
+                "preconditioner": int(b[3])}
 
 
 def gmres(op: BEMOperator, b, x0=None, tol: float = 1e-6, maxiter: int = 500, restart: int = 0,

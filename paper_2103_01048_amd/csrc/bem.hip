@@ -274,21 +274,49 @@ __global__ void k_singular(int64_t npair, const int32_t *__restrict__ ps, const 
   if (s == t) sdiag_w[s] = ws;
 }
 
-// Inverse of the 2x2 diagonal block of the derivative formulation,
-// [[(1 + e21)/2 A, V_Y,ss - V_L,ss], [(W_Y - W_L)_ss, (1 + e12)/2 A]]
+// Coefficients of the two derivative formulations.  The monopole + dipole
+// FMM pass returns pot_L = K_L u + sL V_L v and pot_Y = K_Y u + sY V_Y v (charge
+// scales sL, sY) with their gradients; the rows are then
+//   y1 = d1 A u + c1L pot_L - c1Y pot_Y
+//   y2 = d2 A v + c2 n.(grad pot_L - grad pot_Y)
+// since n.grad pot = -W u + s K' v.  With e21 = eps2/eps1, e12 = eps1/eps2:
+//   interior (eq:juffer): sL = -1,   sY = -e12, d1 = (1 + e21)/2, c1L = 1,   c1Y = e21, d2 = (1 + e12)/2, c2 = 1
+//   exterior (eq:lu):     sL = -e21, sY = -1,   d1 = (1 + e12)/2, c1L = e12, c1Y = 1,   d2 = (1 + e12)/2, c2 = e12
+struct DerivCoef {
+  double sL, sY, d1, c1L, c1Y, d2, c2;
+};
+
+DerivCoef deriv_coef(int formulation, double eps_in, double eps_out) {
+  const double e21 = eps_out / eps_in, e12 = eps_in / eps_out;
+  if (formulation == FMM_BEM_EXTERIOR) return {-e21, -1.0, 0.5 * (1 + e12), e12, 1.0, 0.5 * (1 + e12), e12};
+  return {-1.0, -e12, 0.5 * (1 + e21), 1.0, e21, 0.5 * (1 + e12), 1.0};
+}
+
+// Inverse of the 2x2 diagonal block of a derivative formulation,
+// [[d1 A, c1L sL V_L,ss - c1Y sY V_Y,ss], [c2 (W_Y - W_L)_ss, d2 A]]
 // (K_ss = K'_ss = 0 on a flat triangle).
 __global__ void k_precond_setup_deriv(int64_t nt, const double *__restrict__ area, const double *__restrict__ sdiag,
-                                      const double *__restrict__ sdiag_w, double e21, double e12,
-                                      double *__restrict__ pre) {
+                                      const double *__restrict__ sdiag_w, DerivCoef c, double *__restrict__ pre) {
   const int64_t s = blockIdx.x * 256ll + threadIdx.x;
   if (s >= nt) return;
-  const double a = 0.5 * (1 + e21) * area[s], b = sdiag[2 * s + 1] - sdiag[2 * s], c = sdiag_w[s],
-               d = 0.5 * (1 + e12) * area[s];
-  const double det = a * d - b * c;
+  const double a = c.d1 * area[s], b = c.c1L * c.sL * sdiag[2 * s] - c.c1Y * c.sY * sdiag[2 * s + 1],
+               cw = c.c2 * sdiag_w[s], d = c.d2 * area[s];
+  const double det = a * d - b * cw;
   pre[4 * s + 0] = d / det;
   pre[4 * s + 1] = -b / det;
-  pre[4 * s + 2] = -c / det;
+  pre[4 * s + 2] = -cw / det;
   pre[4 * s + 3] = a / det;
+}
+
+// Mass-matrix preconditioner: P = diag(M, M), M = diag(areas) (the Galerkin
+// mass matrix of P0 elements is diagonal, so mass lumping is exact).
+__global__ void k_precond_setup_mass(int64_t nt, const double *__restrict__ area, double *__restrict__ pre) {
+  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+  if (s >= nt) return;
+  pre[4 * s + 0] = 1.0 / area[s];
+  pre[4 * s + 1] = 0.0;
+  pre[4 * s + 2] = 0.0;
+  pre[4 * s + 3] = 1.0 / area[s];
 }
 
 // Inverse of the 2x2 diagonal block [[A/2, -V_L,ss], [A/2, (e1/e2) V_Y,ss]]
@@ -358,20 +386,16 @@ __global__ void k_bem_p2_md(int64_t nt, int nq, const T *__restrict__ potl, cons
   y[nt + s] = hu - ay;
 }
 
-// P2^T and assembly for the derivative formulation (eq:juffer).  The FMM
-// returned pot_L = K_L u - V_L v and pot_Y = K_Y u - e12 V_Y v with their
-// gradients, so (regular parts)
-//   y1 = (1 + e21)/2 A u + P2^T (pot_L - e21 pot_Y)
-//   y2 = (1 + e12)/2 A v + P2^T n.(grad pot_L - grad pot_Y)
-// (n.grad pot_L = -W_L u - K'_L v, n.grad pot_Y = -W_Y u - e12 K'_Y v), plus
-// the S - C terms; K' corrections are those of K on the transposed pair.
+// P2^T and assembly for the derivative formulations (coefficients in
+// DerivCoef), regular parts from the FMM plus the S - C terms; the K'
+// corrections are those of K on the transposed pair.
 template <typename T>
 __global__ void k_bem_p2_deriv(int64_t nt, int nq, const T *__restrict__ potl, const T *__restrict__ gradl,
                                const T *__restrict__ poty, const T *__restrict__ grady, const double *__restrict__ qw,
                                const double *__restrict__ area, const double *__restrict__ normal,
                                const int32_t *__restrict__ sp_off, const int32_t *__restrict__ sp_idx,
                                const int32_t *__restrict__ sp_tr, const double *__restrict__ Dval,
-                               const double *__restrict__ Dw, const double *__restrict__ x, double e21, double e12,
+                               const double *__restrict__ Dw, const double *__restrict__ x, DerivCoef c,
                                double *__restrict__ y) {
   const int64_t s = blockIdx.x * 256ll + threadIdx.x;
   if (s >= nt) return;
@@ -379,19 +403,21 @@ __global__ void k_bem_p2_deriv(int64_t nt, int nq, const T *__restrict__ potl, c
   double a1 = 0, a2 = 0;
   for (int a = 0; a < nq; ++a) {
     const int64_t i = s * nq + a;
-    a1 += qw[i] * ((double)potl[i] - e21 * (double)poty[i]);
+    a1 += qw[i] * (c.c1L * (double)potl[i] - c.c1Y * (double)poty[i]);
     a2 += qw[i] * (n0 * ((double)gradl[3 * i] - (double)grady[3 * i]) +
                    n1 * ((double)gradl[3 * i + 1] - (double)grady[3 * i + 1]) +
                    n2 * ((double)gradl[3 * i + 2] - (double)grady[3 * i + 2]));
   }
+  double b1 = 0, b2 = 0;
   for (int k = sp_off[s]; k < sp_off[s + 1]; ++k) {
     const int t = sp_idx[k], kt = sp_tr[k];
     const double u = x[t], v = x[nt + t];
-    a1 += Dval[4 * k + 1] * u - Dval[4 * k + 0] * v - e21 * Dval[4 * k + 3] * u + Dval[4 * k + 2] * v;
-    a2 += Dw[k] * u + e12 * Dval[4 * kt + 3] * v - Dval[4 * kt + 1] * v;
+    b1 += c.c1L * (Dval[4 * k + 1] * u + c.sL * Dval[4 * k + 0] * v) -
+          c.c1Y * (Dval[4 * k + 3] * u + c.sY * Dval[4 * k + 2] * v);
+    b2 += Dw[k] * u + c.sL * Dval[4 * kt + 1] * v - c.sY * Dval[4 * kt + 3] * v;
   }
-  y[s] = 0.5 * (1 + e21) * area[s] * x[s] + a1;
-  y[nt + s] = 0.5 * (1 + e12) * area[s] * x[nt + s] + a2;
+  y[s] = c.d1 * area[s] * x[s] + a1 + b1;
+  y[nt + s] = c.d2 * area[s] * x[nt + s] + c.c2 * (a2 + b2);
 }
 
 // n . grad of the FP64 Coulomb sum at the quadrature points (the derivative
@@ -486,12 +512,13 @@ __global__ void k_rhs_assemble(int64_t nt, int nq, const double *__restrict__ qw
   b[nt + s] = 0.0;
 }
 
-__global__ void k_energy_sources(int64_t nt, int nq, const double *__restrict__ x, const double *__restrict__ qw,
-                                 const double *__restrict__ normal, double *__restrict__ sig, double *__restrict__ dip) {
+__global__ void k_energy_sources(int64_t nt, int nq, const double *__restrict__ x, double vscale,
+                                 const double *__restrict__ qw, const double *__restrict__ normal,
+                                 double *__restrict__ sig, double *__restrict__ dip) {
   const int64_t i = blockIdx.x * 256ll + threadIdx.x;
   if (i >= nt * nq) return;
   const int64_t t = i / nq;
-  sig[i] = qw[i] * x[nt + t];
+  sig[i] = qw[i] * vscale * x[nt + t];
   const double mu = qw[i] * x[t];
   dip[3 * i] = mu * normal[3 * t];
   dip[3 * i + 1] = mu * normal[3 * t + 1];
@@ -583,7 +610,7 @@ struct bem_op {
   int32_t *d_sp_off = nullptr, *d_sp_idx = nullptr;
   double *d_D = nullptr, *d_sdiag = nullptr, *d_pre = nullptr;
   // derivative formulation: W_Y - W_L corrections and diagonal, transposed pair index
-  int formulation = 0;
+  int formulation = 0, precond = 0;
   double *d_Dw = nullptr, *d_sdiag_w = nullptr;
   int32_t *d_sp_tr = nullptr;
   void *q4 = nullptr, *potl = nullptr, *poty = nullptr, *gradl = nullptr, *grady = nullptr;
@@ -638,6 +665,22 @@ int multidot(bem_op *op, const double *V, int rows, const double *w, double *h_h
   return FMM_OK;
 }
 
+// (Re)build the per-triangle 2 x 2 preconditioner blocks of kind `kind`.
+int precond_setup(bem_op *op, int kind, hipStream_t s) {
+  const int64_t nt = op->nt;
+  if (kind == FMM_BEM_PRECOND_MASS)
+    hipLaunchKernelGGL(k_precond_setup_mass, dim3(blocks(nt)), dim3(256), 0, s, nt, op->d_area, op->d_pre);
+  else if (op->formulation != FMM_BEM_DIRECT)
+    hipLaunchKernelGGL(k_precond_setup_deriv, dim3(blocks(nt)), dim3(256), 0, s, nt, op->d_area, op->d_sdiag,
+                       op->d_sdiag_w, deriv_coef(op->formulation, op->eps_in, op->eps_out), op->d_pre);
+  else
+    hipLaunchKernelGGL(k_precond_setup, dim3(blocks(nt)), dim3(256), 0, s, nt, op->d_area, op->d_sdiag,
+                       op->eps_in / op->eps_out, op->d_pre);
+  FMM_HIP_TRY(hipGetLastError());
+  op->precond = kind;
+  return FMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -647,7 +690,7 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
               bem_op **out) {
   if (!out) { set_error("bem_setup: out is NULL"); return FMM_EINVAL; }
   *out = nullptr;
-  if (formulation != FMM_BEM_DIRECT && formulation != FMM_BEM_DERIVATIVE) {
+  if (formulation != FMM_BEM_DIRECT && formulation != FMM_BEM_DERIVATIVE && formulation != FMM_BEM_EXTERIOR) {
     set_error("bem_setup: unknown formulation");
     return FMM_EINVAL;
   }
@@ -665,7 +708,7 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
   op->nt = nt; op->nv = nv; op->nq = quad_pts; op->N = nt * quad_pts; op->precision = precision;
   op->eps_in = eps_in; op->eps_out = eps_out; op->kappa = kappa;
   op->formulation = formulation;
-  const bool deriv = formulation == FMM_BEM_DERIVATIVE;
+  const bool deriv = formulation != FMM_BEM_DIRECT;
   int rc = FMM_OK;
   do {
     // geometry on the host
@@ -745,13 +788,8 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     hipLaunchKernelGGL(k_singular, dim3(blocks(op->npair, 128)), dim3(128), 0, s, op->npair, d_ps, op->d_sp_idx,
                        op->d_tri, op->d_normal, op->d_area, d_ro, NO * NO, d_rr, NREM * NREM, d_rq, quad_pts, kappa,
                        op->d_D, op->d_sdiag, deriv ? 1 : 0, op->d_Dw, op->d_sdiag_w);
-    if (deriv)
-      hipLaunchKernelGGL(k_precond_setup_deriv, dim3(blocks(nt)), dim3(256), 0, s, nt, op->d_area, op->d_sdiag,
-                         op->d_sdiag_w, eps_out / eps_in, eps_in / eps_out, op->d_pre);
-    else
-      hipLaunchKernelGGL(k_precond_setup, dim3(blocks(nt)), dim3(256), 0, s, nt, op->d_area, op->d_sdiag,
-                         eps_in / eps_out, op->d_pre);
     if (hipGetLastError() != hipSuccess) { set_error("bem_setup: launch failed"); rc = FMM_EHIP; break; }
+    if ((rc = precond_setup(op, FMM_BEM_PRECOND_BLOCK, s))) break;
     // the two FMM plans on the quadrature points
     if ((rc = fmm_setup(op->d_qpts, op->N, FMM_LAPLACE, 0.0, p, ncrit, precision, stream, &op->fl))) break;
     if ((rc = fmm_setup(op->d_qpts, op->N, FMM_YUKAWA, kappa, p, ncrit, precision, stream, &op->fy))) break;
@@ -783,6 +821,8 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
   const int64_t N = op->N, nt = op->nt;
   int rc;
   const double er = op->eps_in / op->eps_out;
+  const DerivCoef dc = deriv_coef(op->formulation, op->eps_in, op->eps_out);
+  const bool deriv = op->formulation != FMM_BEM_DIRECT;
   // one pass per kernel: single layer as charges, double layer as dipoles
   // (the four-column form would need potentials and gradients of four)
   const int64_t Nq = (int64_t)nt * op->nq;
@@ -799,22 +839,21 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
   {
     const size_t es = op->precision == FMM_FP64 ? 8 : 4;
     const char *qq = (const char *)op->q4;
-    if ((rc = fmm_eval_pair_md(op->fl, op->fy, qq, qq + Nq * es, -1.0, -er, op->potl, op->gradl, op->poty,
-                               op->grady, s)))
+    if ((rc = fmm_eval_pair_md(op->fl, op->fy, qq, qq + Nq * es, deriv ? dc.sL : -1.0, deriv ? dc.sY : -er,
+                               op->potl, op->gradl, op->poty, op->grady, s)))
       return rc;
   }
-  if (op->formulation == FMM_BEM_DERIVATIVE) {
-    const double e21 = op->eps_out / op->eps_in;
+  if (deriv) {
     if (op->precision == FMM_FP64)
       hipLaunchKernelGGL(k_bem_p2_deriv<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq,
                          (const double *)op->potl, (const double *)op->gradl, (const double *)op->poty,
                          (const double *)op->grady, op->d_qw, op->d_area, op->d_normal, op->d_sp_off, op->d_sp_idx,
-                         op->d_sp_tr, op->d_D, op->d_Dw, x, e21, er, y);
+                         op->d_sp_tr, op->d_D, op->d_Dw, x, dc, y);
     else
       hipLaunchKernelGGL(k_bem_p2_deriv<float>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq,
                          (const float *)op->potl, (const float *)op->gradl, (const float *)op->poty,
                          (const float *)op->grady, op->d_qw, op->d_area, op->d_normal, op->d_sp_off, op->d_sp_idx,
-                         op->d_sp_tr, op->d_D, op->d_Dw, x, e21, er, y);
+                         op->d_sp_tr, op->d_D, op->d_Dw, x, dc, y);
     FMM_HIP_TRY(hipGetLastError());
     return FMM_OK;
   }
@@ -827,6 +866,15 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
   }
   FMM_HIP_TRY(hipGetLastError());
   return FMM_OK;
+}
+
+int bem_set_preconditioner(bem_op *op, int kind, fmm_stream_t stream) {
+  if (!op) { set_error("bem_set_preconditioner: null operator"); return FMM_EINVAL; }
+  if (kind != FMM_BEM_PRECOND_BLOCK && kind != FMM_BEM_PRECOND_MASS) {
+    set_error("bem_set_preconditioner: unknown preconditioner");
+    return FMM_EINVAL;
+  }
+  return precond_setup(op, kind, (hipStream_t)stream);
 }
 
 int bem_precondition(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
@@ -842,13 +890,13 @@ int bem_rhs(bem_op *op, const double *qxyz, const double *q, int64_t nq, double 
   double *sig = nullptr, *f = nullptr;
   FMM_HIP_TRY(hipMallocAsync((void **)&sig, std::max<int64_t>(1, nq) * sizeof(double), s));
   FMM_HIP_TRY(hipMallocAsync((void **)&f, op->N * sizeof(double), s));
-  // sigma_k = q_k / eps_in
-  hipLaunchKernelGGL(k_axpby, dim3(blocks(std::max<int64_t>(1, nq))), dim3(256), 0, s, nq, 1.0 / op->eps_in, q, 0.0, q,
-                     sig);
+  // sigma_k = q_k / eps_in (q_k / eps_out for the exterior formulation)
+  const double eps = op->formulation == FMM_BEM_EXTERIOR ? op->eps_out : op->eps_in;
+  hipLaunchKernelGGL(k_axpby, dim3(blocks(std::max<int64_t>(1, nq))), dim3(256), 0, s, nq, 1.0 / eps, q, 0.0, q, sig);
   hipLaunchKernelGGL(k_direct_md, dim3(blocks(op->N)), dim3(256), 0, s, op->N, op->d_qpts, nq, qxyz, sig,
                      (const double *)nullptr, f);
   hipLaunchKernelGGL(k_rhs_assemble, dim3(blocks(op->nt)), dim3(256), 0, s, op->nt, op->nq, op->d_qw, f, b);
-  if (op->formulation == FMM_BEM_DERIVATIVE) {
+  if (op->formulation != FMM_BEM_DIRECT) {
     // second block: the normal derivative of the same Coulomb sum
     hipLaunchKernelGGL(k_direct_ngrad, dim3(blocks(op->N)), dim3(256), 0, s, op->N, op->nq, op->d_qpts, op->d_normal,
                        nq, qxyz, sig, f);
@@ -871,7 +919,10 @@ int bem_energy(bem_op *op, const double *x, const double *qxyz, const double *q,
   FMM_HIP_TRY(hipMallocAsync((void **)&dip, op->N * 3 * sizeof(double), s));
   FMM_HIP_TRY(hipMallocAsync((void **)&phi, nq * sizeof(double), s));
   FMM_HIP_TRY(hipMallocAsync((void **)&res, sizeof(double), s));
-  hipLaunchKernelGGL(k_energy_sources, dim3(blocks(op->N)), dim3(256), 0, s, op->nt, op->nq, x, op->d_qw,
+  // the exterior unknowns map to (phi_1, d phi_1/dn) by the interface
+  // conditions: phi_1 = phi_2, eps_in d phi_1/dn = eps_out d phi_2/dn
+  const double vscale = op->formulation == FMM_BEM_EXTERIOR ? op->eps_out / op->eps_in : 1.0;
+  hipLaunchKernelGGL(k_energy_sources, dim3(blocks(op->N)), dim3(256), 0, s, op->nt, op->nq, x, vscale, op->d_qw,
                      op->d_normal, sig, dip);
   hipLaunchKernelGGL(k_direct_md, dim3(blocks(nq)), dim3(256), 0, s, nq, qxyz, op->N, op->d_qpts, sig, dip, phi);
   hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(1024), 0, s, nq, q, phi, res);
@@ -1011,6 +1062,7 @@ int bem_info(const bem_op *op, bem_info_t *o) {
   o->quad_pts = op->nq;
   o->precision = op->precision;
   o->formulation = op->formulation;
+  o->preconditioner = op->precond;
   return FMM_OK;
 }
 

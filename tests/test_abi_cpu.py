@@ -61,6 +61,12 @@ def test_eval_rejects_null_plan():
     assert L.fmm_eval(None, None, 1, None, None, None) == _lib.FMM_EINVAL
 
 
+def test_bem_set_preconditioner_rejects_null_operator():
+    L = _lib.lib()
+    assert L.bem_set_preconditioner(None, _lib.FMM_BEM_PRECOND_MASS, None) == _lib.FMM_EINVAL
+    assert "null" in L.fmm_last_error().decode()
+
+
 def test_pair_entry_points_reject_null_plans():
     L = _lib.lib()
     assert L.fmm_eval_pair(None, None, None, 1, None, None, None, None, None) == _lib.FMM_EINVAL
@@ -78,7 +84,7 @@ def test_bem_setup_rejects_bad_arguments(case):
     t = np.array([[0, 1, 2], [0, 1, 3]], dtype=np.int32)
     quad, eps, kap, form = 3, 4.0, 0.1, 0
     if case == "formulation":
-        form = 2
+        form = 3
     elif case == "quad":
         quad = 4
     elif case == "eps":
