@@ -677,8 +677,8 @@ static int upload_lists(fmm_plan *P) {
     if (P->level[b] >= 2) { p2m.push_back((int32_t)b); p2mo.push_back((int32_t)p2m.size()); }
     src.push_back(std::move(L));
   }
-  // Tiles of 64 targets (a tile of at most 32 targets runs split: both
-  // half-waves take the same targets and alternate sources).  A tile whose
+  // Tiles of 64 targets (a tile of at most 32 or 16 targets runs split: 2 or
+  // 4 sub-waves take the same targets and the sources in turn).  A tile whose
   // source work exceeds `cap` is cut into parts of about `cap` (near ranges
   // cut at point boundaries, surfaces whole); parts write partial sums that
   // k_leaf_parts adds in part order.  With the waves of one launch resident
@@ -692,7 +692,8 @@ static int upload_lists(fmm_plan *P) {
     for (auto &r : src[sl].near) c += r.j1 - r.j0;
     c += far_w * ns * (double)src[sl].far.size();
     for (int64_t t0 = 0; t0 < src[sl].m; t0 += 64) {
-      const int split = (src[sl].m - t0) <= 32 ? 2 : 1;
+      const int64_t rem = src[sl].m - t0;
+      const int split = rem <= 16 ? 4 : (rem <= 32 ? 2 : 1);
       tiles.push_back({c / split, (int32_t)sl, (int32_t)t0, split});
       total += c / split;
     }

@@ -536,9 +536,10 @@ __device__ inline void pair_gf(T r2, T kappa, T &g, T &f) {
 //   near point ranges (U list, small W-list boxes, direct X list): P2P
 //   W-list upward equivalent surfaces: M2P
 //   the leaf's own downward equivalent surface: L2P
-// A tile of at most 32 targets runs split: both half-waves hold the same
-// targets and take alternate sources (vector loads, one per half), and the
-// halves are added at the end.  With one density column the source charge
+// A tile of at most 32 (16) targets runs split into 2 (4) sub-waves that
+// hold the same targets and take sources in turn (vector loads, one per
+// sub-wave); the sub-wave sums are added at the end, the upper half onto the
+// lower first, then (split 4) the upper quarter of what is left.  With one density column the source charge
 // travels in the fourth component of the point record.  Only a range that
 // contains the tile's own leaf can hold a source at zero distance, so only
 // that range pays for the exclusion test (points in different leaves have
@@ -592,8 +593,8 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
   const int lb = box_begin[b], le = box_end[b];
   const int tb = lb + (code & 0xffffff);
   const int lane = threadIdx.x;
-  const int half = split == 2 ? (lane >> 5) : 0;
-  const int tl = split == 2 ? (lane & 31) : lane;
+  const int sub = split == 1 ? 0 : lane / (64 / split);  // sub-wave
+  const int tl = lane & (64 / split - 1);
   const int m = min(64 / split, le - tb);
   const bool active = tl < m;
   const V4 xv = p4[tb + (active ? tl : 0)];
@@ -629,10 +630,11 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
         for (int j = j0; j < j1; ++j) body(j, std::false_type());
       }
     } else {
-      // split: lane half h takes sources j0 + h, j0 + h + 2, ...; an odd
-      // count leaves the last upper-half step with a zero charge
+      // split into 2 or 4 sub-waves: sub-wave h takes sources j0 + h,
+      // j0 + h + split, ...; a count that is not a multiple of split leaves
+      // the last steps of the upper sub-waves with a zero charge
       auto body = [&](int j, auto chk) {
-        const int jj = j + half;
+        const int jj = j + sub;
         const bool ok = jj < j1;
         const V4 sp = p4[ok ? jj : j];
         T qv[NR];
@@ -645,10 +647,10 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
       };
       if (self) {
 #pragma unroll 2
-        for (int j = j0; j < j1; j += 2) body(j, std::true_type());
+        for (int j = j0; j < j1; j += split) body(j, std::true_type());
       } else {
 #pragma unroll 4
-        for (int j = j0; j < j1; j += 2) body(j, std::false_type());
+        for (int j = j0; j < j1; j += split) body(j, std::false_type());
       }
     }
   }
@@ -673,8 +675,8 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
       }
     } else {
 #pragma unroll 2
-      for (int j = 0; j < nsurf; j += 2) {
-        const int jj = j + half;
+      for (int j = 0; j < nsurf; j += split) {
+        const int jj = j + sub;
         const bool ok = jj < nsurf;
         const V4 g = s4[ok ? jj : j];
         T qv[NR];
@@ -685,7 +687,7 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
       }
     }
   }
-  if (split == 2) {
+  if (split >= 2) {
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
       ap[c] += __shfl_xor(ap[c], 32);
@@ -694,9 +696,18 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
       agz[c] += __shfl_xor(agz[c], 32);
     }
   }
+  if (split == 4) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      ap[c] += __shfl_xor(ap[c], 16);
+      agx[c] += __shfl_xor(agx[c], 16);
+      agy[c] += __shfl_xor(agy[c], 16);
+      agz[c] += __shfl_xor(agz[c], 16);
+    }
+  }
   if (part >= 0) {
     // partial sums of a split tile: [part][column][component][lane]
-    if (half == 0) {
+    if (sub == 0) {
       T *pp = parts + (int64_t)part * NR * 4 * 64;
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
@@ -708,7 +719,7 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
     }
     return;
   }
-  if (active && half == 0) {
+  if (active && sub == 0) {
     const int64_t o = perm[tb + tl];
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
@@ -816,8 +827,8 @@ __global__ __launch_bounds__(64) void k_near_pair(
     const int lb = box_begin[b], le = box_end[b];
     const int tb = lb + (code & 0xffffff);
     const int lane = threadIdx.x;
-    const int half = split == 2 ? (lane >> 5) : 0;
-    const int tl = split == 2 ? (lane & 31) : lane;
+    const int sub = split == 1 ? 0 : lane / (64 / split);  // sub-wave
+    const int tl = lane & (64 / split - 1);
     const int m = min(64 / split, le - tb);
     const bool active = tl < m;
     const V4 xv = p4[tb + (active ? tl : 0)];
@@ -852,7 +863,7 @@ __global__ __launch_bounds__(64) void k_near_pair(
         }
       } else {
         auto body = [&](int j, auto chk) {
-          const int jj = j + half;
+          const int jj = j + sub;
           const bool ok = jj < j1;
           const V4 sp = p4[ok ? jj : j];
           T qv[NR];
@@ -866,10 +877,10 @@ __global__ __launch_bounds__(64) void k_near_pair(
         };
         if (self) {
 #pragma unroll 2
-          for (int j = j0; j < j1; j += 2) body(j, std::true_type());
+          for (int j = j0; j < j1; j += split) body(j, std::true_type());
         } else {
 #pragma unroll 4
-          for (int j = j0; j < j1; j += 2) body(j, std::false_type());
+          for (int j = j0; j < j1; j += split) body(j, std::false_type());
         }
       }
     }
@@ -889,12 +900,12 @@ __global__ __launch_bounds__(64) void k_near_pair(
 }
 
 template <typename T, int NR>
-__device__ __forceinline__ void leaf_store(int part, int half, bool active, int tl, int tb, T *__restrict__ parts,
+__device__ __forceinline__ void leaf_store(int part, int sub, bool active, int tl, int tb, T *__restrict__ parts,
                                            const int32_t *__restrict__ perm, int64_t N, T *__restrict__ pot,
                                            T *__restrict__ grad, T scale, const T (&ap)[NR], const T (&agx)[NR],
                                            const T (&agy)[NR], const T (&agz)[NR]) {
   if (part >= 0) {
-    if (half == 0) {
+    if (sub == 0) {
       T *pp = parts + (int64_t)part * NR * 4 * 64;
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
@@ -906,7 +917,7 @@ __device__ __forceinline__ void leaf_store(int part, int half, bool active, int 
     }
     return;
   }
-  if (active && half == 0) {
+  if (active && sub == 0) {
     const int64_t o = perm[tb + tl];
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
@@ -942,8 +953,8 @@ __global__ __launch_bounds__(64) void k_far_pair(
   const int lb = box_begin[b], le = box_end[b];
   const int tb = lb + (code & 0xffffff);
   const int lane = threadIdx.x;
-  const int half = split == 2 ? (lane >> 5) : 0;
-  const int tl = split == 2 ? (lane & 31) : lane;
+  const int sub = split == 1 ? 0 : lane / (64 / split);  // sub-wave
+  const int tl = lane & (64 / split - 1);
   const int m = min(64 / split, le - tb);
   const bool active = tl < m;
   const V4 xv = p4[tb + (active ? tl : 0)];
@@ -986,8 +997,8 @@ __global__ __launch_bounds__(64) void k_far_pair(
       }
     } else {
 #pragma unroll 2
-      for (int j = 0; j < nsurf; j += 2) {
-        const int jj = j + half;
+      for (int j = 0; j < nsurf; j += split) {
+        const int jj = j + sub;
         const bool ok = jj < nsurf;
         const V4 g = s4[ok ? jj : j];
         T qa[NR], qb[NR];
@@ -1001,7 +1012,7 @@ __global__ __launch_bounds__(64) void k_far_pair(
       }
     }
   }
-  if (split == 2) {
+  if (split >= 2) {
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
       pa[c] += __shfl_xor(pa[c], 32); xa[c] += __shfl_xor(xa[c], 32);
@@ -1010,8 +1021,17 @@ __global__ __launch_bounds__(64) void k_far_pair(
       yb[c] += __shfl_xor(yb[c], 32); zb[c] += __shfl_xor(zb[c], 32);
     }
   }
-  leaf_store<T, NR>(part, half, active, tl, tb, parts_a, perm, N, pot_a, grad_a, scale, pa, xa, ya, za);
-  leaf_store<T, NR>(part, half, active, tl, tb, parts_b, perm, N, pot_b, grad_b, scale, pb, xb, yb, zb);
+  if (split == 4) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      pa[c] += __shfl_xor(pa[c], 16); xa[c] += __shfl_xor(xa[c], 16);
+      ya[c] += __shfl_xor(ya[c], 16); za[c] += __shfl_xor(za[c], 16);
+      pb[c] += __shfl_xor(pb[c], 16); xb[c] += __shfl_xor(xb[c], 16);
+      yb[c] += __shfl_xor(yb[c], 16); zb[c] += __shfl_xor(zb[c], 16);
+    }
+  }
+  leaf_store<T, NR>(part, sub, active, tl, tb, parts_a, perm, N, pot_a, grad_a, scale, pa, xa, ya, za);
+  leaf_store<T, NR>(part, sub, active, tl, tb, parts_b, perm, N, pot_b, grad_b, scale, pb, xb, yb, zb);
 }
 
 // Surface kernel of a pair evaluation: the Laplace (YA) and Yukawa (YB)
@@ -1211,8 +1231,8 @@ __global__ __launch_bounds__(64) void k_near_pair_md(
     const int lb = box_begin[b], le = box_end[b];
     const int tb = lb + (code & 0xffffff);
     const int lane = threadIdx.x;
-    const int half = split == 2 ? (lane >> 5) : 0;
-    const int tl = split == 2 ? (lane & 31) : lane;
+    const int sub = split == 1 ? 0 : lane / (64 / split);  // sub-wave
+    const int tl = lane & (64 / split - 1);
     const int m = min(64 / split, le - tb);
     const bool active = tl < m;
     const V4 xv = p4[tb + (active ? tl : 0)];
@@ -1234,10 +1254,10 @@ __global__ __launch_bounds__(64) void k_near_pair_md(
           for (int j = j0; j < j1; ++j) leaf_pair_md<T, false, GRAD>(xt, yt, zt, p4[j], d4[j], kappa, kl2, pa, pb, ga, gb);
         }
       } else {
-        // split: lane half h takes sources j0 + h, j0 + h + 2, ...; a missing
-        // last source of the upper half counts with zero strength
+        // split into sub-waves: sub-wave h takes sources j0 + h, j0 + h +
+        // split, ...; a missing last source counts with zero strength
         auto body = [&](int j, auto chk) {
-          const int jj = j + half;
+          const int jj = j + sub;
           const bool ok = jj < j1;
           V4 sp = p4[ok ? jj : j], sd = d4[ok ? jj : j];
           if (!ok) { sp[3] = (T)0; sd = V4{0, 0, 0, 0}; }
@@ -1245,10 +1265,10 @@ __global__ __launch_bounds__(64) void k_near_pair_md(
         };
         if (self) {
 #pragma unroll 2
-          for (int j = j0; j < j1; j += 2) body(j, std::true_type());
+          for (int j = j0; j < j1; j += split) body(j, std::true_type());
         } else {
 #pragma unroll 4
-          for (int j = j0; j < j1; j += 2) body(j, std::false_type());
+          for (int j = j0; j < j1; j += split) body(j, std::false_type());
         }
       }
     }
