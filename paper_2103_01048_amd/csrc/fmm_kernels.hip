@@ -560,7 +560,7 @@ __device__ __forceinline__ void leaf_pair(T xi, T yi, T zi, T sx, T sy, T sz, co
   } else {
     const T r = r2 * invr;
     g = dev_exp2(-kl2 * r) * invr;
-    f = ((T)1 + kappa * r) * g * (invr * invr);
+    f = g * (invr * invr + kappa * invr);  // (1 + kappa r) g / r^2
   }
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
@@ -791,7 +791,7 @@ __device__ __forceinline__ void leaf_pair_ly(T xi, T yi, T zi, T sx, T sy, T sz,
   const T fl = i2 * invr;                       // Laplace: g = 1/r, f = 1/r^3
   const T r = r2 * invr;
   const T gy = dev_exp2(-kl2 * r) * invr;       // Yukawa: g = e^{-kappa r}/r
-  const T fy = ((T)1 + kappa * r) * gy * i2;    //         f = (1 + kappa r) g / r^2
+  const T fy = gy * (i2 + kappa * invr);        //         f = (1 + kappa r) g / r^2
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
     pa[c] += invr * qa[c];
