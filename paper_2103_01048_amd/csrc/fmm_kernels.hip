@@ -662,6 +662,9 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
     const int a = fe & 0x3fffffff;
     // surface centre in the target leaf's frame, and radius
     const T cx = far_o[4 * k], cy = far_o[4 * k + 1], cz = far_o[4 * k + 2], rr = far_o[4 * k + 3];
+    // targets relative to the surface centre (one shift per surface; each
+    // source then costs one fused multiply-add per coordinate)
+    const T xt = xi - cx, yt = yi - cy, zt = zi - cz;
     const T *__restrict__ dens = (own ? eqd : equ) + (int64_t)a * NR * ld;
     if (split == 1) {
 #pragma unroll 4
@@ -670,7 +673,7 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
         T qv[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) qv[c] = dens[(int64_t)c * ld + j];
-        leaf_pair<T, KERN, false, NR>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qv, kappa, kl2, ap,
+        leaf_pair<T, KERN, false, NR>(xt, yt, zt, rr * g[0], rr * g[1], rr * g[2], qv, kappa, kl2, ap,
                                       agx, agy, agz);
       }
     } else {
@@ -682,7 +685,7 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
         T qv[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) qv[c] = ok ? dens[(int64_t)c * ld + jj] : (T)0;
-        leaf_pair<T, KERN, false, NR>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qv, kappa, kl2, ap,
+        leaf_pair<T, KERN, false, NR>(xt, yt, zt, rr * g[0], rr * g[1], rr * g[2], qv, kappa, kl2, ap,
                                       agx, agy, agz);
       }
     }
@@ -983,6 +986,9 @@ __global__ __launch_bounds__(64) void k_far_pair(
     const bool own = (fe >> 30) & 1;
     const int bx = fe & 0x3fffffff;
     const T cx = far_o[4 * k], cy = far_o[4 * k + 1], cz = far_o[4 * k + 2], rr = far_o[4 * k + 3];
+    // targets relative to the surface centre (one shift per surface; each
+    // source then costs one fused multiply-add per coordinate)
+    const T xt = xi - cx, yt = yi - cy, zt = zi - cz;
     const T *__restrict__ da = (own ? eqd_a : equ_a) + (int64_t)bx * NR * ld;
     const T *__restrict__ db = (own ? eqd_b : equ_b) + (int64_t)bx * NR * ld;
     if (split == 1) {
@@ -992,7 +998,7 @@ __global__ __launch_bounds__(64) void k_far_pair(
         T qa[NR], qb[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) { qa[c] = da[(int64_t)c * ld + j]; qb[c] = db[(int64_t)c * ld + j]; }
-        leaf_pair_ly<T, false, NR, GRAD>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qa, qb, kappa, kl2,
+        leaf_pair_ly<T, false, NR, GRAD>(xt, yt, zt, rr * g[0], rr * g[1], rr * g[2], qa, qb, kappa, kl2,
                                    pa, xa, ya, za, pb, xb, yb, zb);
       }
     } else {
@@ -1007,7 +1013,7 @@ __global__ __launch_bounds__(64) void k_far_pair(
           qa[c] = ok ? da[(int64_t)c * ld + jj] : (T)0;
           qb[c] = ok ? db[(int64_t)c * ld + jj] : (T)0;
         }
-        leaf_pair_ly<T, false, NR, GRAD>(xi, yi, zi, cx + rr * g[0], cy + rr * g[1], cz + rr * g[2], qa, qb, kappa, kl2,
+        leaf_pair_ly<T, false, NR, GRAD>(xt, yt, zt, rr * g[0], rr * g[1], rr * g[2], qa, qb, kappa, kl2,
                                    pa, xa, ya, za, pb, xb, yb, zb);
       }
     }
