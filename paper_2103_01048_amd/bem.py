@@ -99,6 +99,11 @@ class BEMOperator:
               "bem_energy")
         return out.value
 
+    def solve(self, b, x0=None, tol: float = 1e-6, maxiter: int = 500, restart: int = 0,
+              refine: "BEMOperator | None" = None, inner_tol: float = 1e-4):
+        """gmres(self, b, ...): (x, iterations, residual history, status)."""
+        return gmres(self, b, x0=x0, tol=tol, maxiter=maxiter, restart=restart, refine=refine, inner_tol=inner_tol)
+
     def info(self) -> dict:
         raw = ctypes.create_string_buffer(40)
         check(lib().bem_info(self._h, raw), "bem_info")

@@ -88,6 +88,8 @@ class FMMPlan:
             return pot[0], (grad[0] if grad is not None else None)
         return pot, grad
 
+    __call__ = eval
+
     def set_profiling(self, enable=True):
         """enable: True (every phase), False, or an iterable of phase names."""
         if enable is True:
