@@ -171,10 +171,11 @@ def run_batch(args):
 
 
 def run_bem(args):
-    """BEM (formulation and preconditioner from the arguments) on 2,000,000 triangles x 3 points (1,000-sphere
-    union, caps stopping short of the intersection curves), 20,000 charges:
-    bem_matvec time (FP32 FMM, FP64 assembly), and a GMRES solve to 1e-6
-    (FP32 operator, FP64 refinement) with the energy."""
+    """BEM (formulation, preconditioner and single precision from the
+    arguments) on 2,000,000 triangles x 3 points (1,000-sphere union, caps
+    stopping short of the intersection curves), 20,000 charges: bem_matvec
+    time (single-precision FMM, FP64 assembly), and a GMRES solve to 1e-6
+    (single-precision operator, FP64 refinement) with the energy."""
     import torch
     import synth
     from paper_2103_01048_amd import BEMOperator, gmres
@@ -187,7 +188,7 @@ def run_bem(args):
     kw = dict(quad_pts=3, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=P_ORDER, ncrit=ncrit,
               formulation=args.formulation, preconditioner=args.precond)
     t0 = time.perf_counter()
-    op32 = BEMOperator(v, t, precision="fp32", **kw)
+    op32 = BEMOperator(v, t, precision=args.precision, **kw)
     t_setup32 = time.perf_counter() - t0
     t0 = time.perf_counter()
     op64 = BEMOperator(v, t, precision="fp64", **kw)
@@ -228,12 +229,12 @@ def run_bem(args):
             "config": {"workload": f"sphere-union BEM, 1000 spheres, {T} triangles x 3 points = {npts} points, "
                                    f"20000 charges, {args.formulation} formulation (P0), eps 4/80, kappa 0.125",
                        "p": P_ORDER, "ncrit": ncrit, "formulation": args.formulation,
-                       "preconditioner": args.precond},
+                       "preconditioner": args.precond, "precision": args.precision},
             "fmm_mpoints_per_s": round(2 * npts / t32 / 1e6, 1),
             "fp64_matvec_ms": round(t64 * 1e3, 3),
             "gmres": {"status": rc, "iterations": its, "seconds": round(t_solve, 3),
                       "fp64_residual": res, "tol": 1e-6, "inner_tol": 1e-3},
-            "energy_kcal_per_mol": energy, "energy_s": round(t_energy, 3), "setup_s": {"fp32": round(t_setup32, 2), "fp64": round(t_setup64, 2)}}
+            "energy_kcal_per_mol": energy, "energy_s": round(t_energy, 3), "setup_s": {args.precision: round(t_setup32, 2), "fp64": round(t_setup64, 2)}}
     print(json.dumps(line), flush=True)
 
 

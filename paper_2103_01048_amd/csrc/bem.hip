@@ -420,6 +420,17 @@ __global__ void k_bem_p2_deriv(int64_t nt, int nq, const T *__restrict__ potl, c
   y[nt + s] = c.d2 * area[s] * x[nt + s] + c.c2 * (a2 + b2);
 }
 
+// FP64 1/sqrt(x) for x > 0: the hardware estimate refined by two
+// Newton-Raphson steps y <- y (3/2 - (x/2) y^2) (each roughly doubles the
+// number of correct bits of the ~23-bit estimate).
+__device__ inline double rsqrt_fp64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h, y * y, 1.5);
+  y = y * fma(-h, y * y, 1.5);
+  return y;
+}
+
 // n . grad of the FP64 Coulomb sum at the quadrature points (the derivative
 // formulation's second right-hand side): out_i = -sum_j sig_j n_i.(x_i -
 // y_j)/(4 pi r^3), n_i the normal of point i's triangle.
@@ -448,7 +459,7 @@ __global__ __launch_bounds__(256) void k_direct_ngrad(int64_t nt, int nq, const 
       const double ax = xi - sx[k], ay = yi - syy[k], az = zi - sz[k];
       const double r2 = ax * ax + ay * ay + az * az;
       if (r2 > 0) {
-        const double ir = 1.0 / sqrt(r2);
+        const double ir = rsqrt_fp64(r2);
         acc -= ss[k] * (n0 * ax + n1 * ay + n2 * az) * ir * ir * ir;
       }
     }
@@ -467,18 +478,23 @@ __global__ void k_rhs_assemble2(int64_t nt, int nq, const double *__restrict__ q
 }
 
 // FP64 direct sum with monopole and dipole sources:
-//   out_i = sum_j sig_j / (4 pi r) - dip_j . (x_i - y_j) / (4 pi r^3), r > 0.
+//   out_i = sum_j sig_j / (4 pi r) - dip_j . (x_i - y_j) / (4 pi r^3), r > 0,
+// over the source chunk [blockIdx.y * chunk, (blockIdx.y + 1) * chunk) into
+// out[blockIdx.y * nt + i] (a few targets and many sources run as many
+// chunks, summed in chunk order by k_sum_chunks).
 __global__ __launch_bounds__(256) void k_direct_md(int64_t nt, const double *__restrict__ tx, int64_t ns,
                                                    const double *__restrict__ sy, const double *__restrict__ sig,
-                                                   const double *__restrict__ dip, double *__restrict__ out) {
+                                                   const double *__restrict__ dip, int64_t chunk,
+                                                   double *__restrict__ out) {
   __shared__ double sx[256], syy[256], sz[256], ss[256], dx[256], dyy[256], dz[256];
   const int64_t i = blockIdx.x * 256ll + threadIdx.x;
   const bool act = i < nt;
   const double xi = act ? tx[3 * i] : 0, yi = act ? tx[3 * i + 1] : 0, zi = act ? tx[3 * i + 2] : 0;
+  const int64_t jb = (int64_t)blockIdx.y * chunk, je = min(ns, jb + chunk);
   double acc = 0;
-  for (int64_t j0 = 0; j0 < ns; j0 += 256) {
+  for (int64_t j0 = jb; j0 < je; j0 += 256) {
     const int64_t j = j0 + threadIdx.x;
-    if (j < ns) {
+    if (j < je) {
       sx[threadIdx.x] = sy[3 * j];
       syy[threadIdx.x] = sy[3 * j + 1];
       sz[threadIdx.x] = sy[3 * j + 2];
@@ -488,18 +504,27 @@ __global__ __launch_bounds__(256) void k_direct_md(int64_t nt, const double *__r
       dz[threadIdx.x] = dip ? dip[3 * j + 2] : 0.0;
     }
     __syncthreads();
-    const int cnt = (int)min<int64_t>(256, ns - j0);
+    const int cnt = (int)min<int64_t>(256, je - j0);
     for (int k = 0; k < cnt; ++k) {
       const double ax = xi - sx[k], ay = yi - syy[k], az = zi - sz[k];
       const double r2 = ax * ax + ay * ay + az * az;
       if (r2 > 0) {
-        const double ir = 1.0 / sqrt(r2);
+        const double ir = rsqrt_fp64(r2);
         acc += ss[k] * ir - (dx[k] * ax + dyy[k] * ay + dz[k] * az) * ir * ir * ir;
       }
     }
     __syncthreads();
   }
-  if (act) out[i] = acc / FOUR_PI;
+  if (act) out[(int64_t)blockIdx.y * nt + i] = acc / FOUR_PI;
+}
+
+// out[i] = sum over c < nchunk of part[c * n + i], in chunk order.
+__global__ void k_sum_chunks(int64_t n, int nchunk, const double *__restrict__ part, double *__restrict__ out) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0;
+  for (int c = 0; c < nchunk; ++c) acc += part[(int64_t)c * n + i];
+  out[i] = acc;
 }
 
 __global__ void k_rhs_assemble(int64_t nt, int nq, const double *__restrict__ qw, const double *__restrict__ f,
@@ -893,8 +918,8 @@ int bem_rhs(bem_op *op, const double *qxyz, const double *q, int64_t nq, double 
   // sigma_k = q_k / eps_in (q_k / eps_out for the exterior formulation)
   const double eps = op->formulation == FMM_BEM_EXTERIOR ? op->eps_out : op->eps_in;
   hipLaunchKernelGGL(k_axpby, dim3(blocks(std::max<int64_t>(1, nq))), dim3(256), 0, s, nq, 1.0 / eps, q, 0.0, q, sig);
-  hipLaunchKernelGGL(k_direct_md, dim3(blocks(op->N)), dim3(256), 0, s, op->N, op->d_qpts, nq, qxyz, sig,
-                     (const double *)nullptr, f);
+  hipLaunchKernelGGL(k_direct_md, dim3(blocks(op->N), 1), dim3(256), 0, s, op->N, op->d_qpts, nq, qxyz, sig,
+                     (const double *)nullptr, std::max<int64_t>(1, nq), f);
   hipLaunchKernelGGL(k_rhs_assemble, dim3(blocks(op->nt)), dim3(256), 0, s, op->nt, op->nq, op->d_qw, f, b);
   if (op->formulation != FMM_BEM_DIRECT) {
     // second block: the normal derivative of the same Coulomb sum
@@ -924,13 +949,23 @@ int bem_energy(bem_op *op, const double *x, const double *qxyz, const double *q,
   const double vscale = op->formulation == FMM_BEM_EXTERIOR ? op->eps_out / op->eps_in : 1.0;
   hipLaunchKernelGGL(k_energy_sources, dim3(blocks(op->N)), dim3(256), 0, s, op->nt, op->nq, x, vscale, op->d_qw,
                      op->d_normal, sig, dip);
-  hipLaunchKernelGGL(k_direct_md, dim3(blocks(nq)), dim3(256), 0, s, nq, qxyz, op->N, op->d_qpts, sig, dip, phi);
+  // few targets, many sources: the sources in chunks (at least ~2,048
+  // workgroups in all), partial sums added in chunk order
+  const int64_t tb = blocks(nq);
+  const int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>((op->N + 4095) / 4096, (2048 + tb - 1) / tb));
+  const int64_t chunk = (op->N + nchunk - 1) / nchunk;
+  double *part = phi;
+  if (nchunk > 1) FMM_HIP_TRY(hipMallocAsync((void **)&part, (size_t)nchunk * nq * sizeof(double), s));
+  hipLaunchKernelGGL(k_direct_md, dim3(tb, nchunk), dim3(256), 0, s, nq, qxyz, op->N, op->d_qpts, sig, dip, chunk,
+                     part);
+  if (nchunk > 1) hipLaunchKernelGGL(k_sum_chunks, dim3(tb), dim3(256), 0, s, nq, nchunk, part, phi);
   hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(1024), 0, s, nq, q, phi, res);
   FMM_HIP_TRY(hipGetLastError());
   FMM_HIP_TRY(hipMemcpyAsync(dG, res, sizeof(double), hipMemcpyDeviceToHost, s));
   FMM_HIP_TRY(hipStreamSynchronize(s));
   (void)hipFreeAsync(sig, s);
   (void)hipFreeAsync(dip, s);
+  if (part != phi) (void)hipFreeAsync(part, s);
   (void)hipFreeAsync(phi, s);
   (void)hipFreeAsync(res, s);
   return FMM_OK;
