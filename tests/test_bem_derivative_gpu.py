@@ -34,7 +34,7 @@ def sphere512():
     return v, t, m, B.system_derivative(m, 4.0, 80.0, KAPPA)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-4), ("bf16x3", 1e-4)])
 def test_derivative_matvec_matches_dense_oracle(sphere512, precision, tol):
     torch = require_gpu()
     v, t, m, A_ = sphere512
@@ -121,7 +121,7 @@ def sphere512_ext():
     return v, t, m, B.system_exterior(m, 4.0, 80.0, KAPPA)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-4), ("bf16x3", 1e-4)])
 def test_exterior_matvec_matches_dense_oracle(sphere512_ext, precision, tol):
     torch = require_gpu()
     v, t, m, A_ = sphere512_ext

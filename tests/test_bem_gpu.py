@@ -40,7 +40,7 @@ def sphere512():
     return v, t, m, A_
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-4), ("bf16x3", 1e-4)])
 def test_matvec_matches_dense_oracle(sphere512, precision, tol):
     torch = require_gpu()
     v, t, m, A_ = sphere512
