@@ -208,8 +208,11 @@ def run_bem(args):
 
     t32 = timed(op32, args.steps)
     t64 = timed(op64, max(2, args.steps // 4))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     b = op32.rhs(qxyz, q)
     torch.cuda.synchronize()
+    t_rhs = time.perf_counter() - t0
     t0 = time.perf_counter()
     # inner solves to 1e-3 with the FP32 operator, residuals with the FP64
     # operator: two corrections reach 1e-6 in the fewest iterations
@@ -234,7 +237,7 @@ def run_bem(args):
             "fp64_matvec_ms": round(t64 * 1e3, 3),
             "gmres": {"status": rc, "iterations": its, "seconds": round(t_solve, 3),
                       "fp64_residual": res, "tol": 1e-6, "inner_tol": 1e-3},
-            "energy_kcal_per_mol": energy, "energy_s": round(t_energy, 3), "setup_s": {args.precision: round(t_setup32, 2), "fp64": round(t_setup64, 2)}}
+            "energy_kcal_per_mol": energy, "energy_s": round(t_energy, 3), "rhs_s": round(t_rhs, 3), "setup_s": {args.precision: round(t_setup32, 2), "fp64": round(t_setup64, 2)}}
     print(json.dumps(line), flush=True)
 
 
