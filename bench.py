@@ -83,10 +83,12 @@ def workload(seed: int = 1):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="surface393k", choices=["surface393k", "batch64", "bem2m"],
+    ap.add_argument("--workload", default="surface393k",
+                    choices=["surface393k", "batch64", "bem2m", "adjoint1m", "shell30m"],
                     help="surface393k: the headline workload; batch64: 64 uneven molecules in one batched plan "
                          "against 64 separate plans per kernel; bem2m: boundary-element matvec and GMRES solve "
-                         "on 2M triangles")
+                         "on 2M triangles; adjoint1m: adjoint against forward time on 1M points; shell30m: "
+                         "the 30M-point shell at p = 10")
     ap.add_argument("--formulation", default="direct", choices=["direct", "derivative", "exterior"],
                     help="boundary-element formulation of the bem2m workload")
     ap.add_argument("--precond", default="block", choices=["block", "mass"],
@@ -141,12 +143,14 @@ def run_batch(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    t_b = timed(lambda: [pl.eval(qt) for pl in batched], args.steps, args.warmup)
+    from paper_2103_01048_amd import eval_pair
+    t_b = timed(lambda: eval_pair(batched[0], batched[1], qt), args.steps, args.warmup)
+    t_e = timed(lambda: [pl.eval(qt) for pl in batched], args.steps, args.warmup)
     t_s = timed(lambda: [pl.eval(qm) for pl, qm in separate], args.steps, args.warmup)
     errors = {}
     if not args.no_cpu:
         from oracle import direct as D
-        outs = [pl.eval(qt) for pl in batched]
+        outs = eval_pair(batched[0], batched[1], qt)
         torch.cuda.synchronize()
         for k, (pot, grad) in zip(("laplace", "yukawa"), outs):
             pot = pot.double().cpu().numpy()
@@ -157,16 +161,96 @@ def run_batch(args):
                 p0, g0 = D.direct(xs[m], xs[m], qs[m], k, KAPPA)
                 worst = max(worst, D.rel_l2(pot[s_], p0), D.rel_l2(grad[s_], g0))
             errors[k] = worst
-    line = {"metric": "batched FMM matvec Mpoints/s (Laplace+Yukawa), 64 uneven molecules",
+    line = {"metric": "batched FMM matvec Mpoints/s (Laplace+Yukawa as one fmm_eval_pair), 64 uneven molecules",
             "value": round(n / t_b / 1e6, 3), "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(t_b * 1e3, 4), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"{len(xs)} sphere-union molecules, {n} points "
                                    f"({min(len(x) for x in xs)}..{max(len(x) for x in xs)} per molecule)",
                        "p": P_ORDER, "ncrit": ncrit, "precision": prec},
+            "batched_separate_evals": {"value": round(n / t_e / 1e6, 3), "ms_per_step": round(t_e * 1e3, 4),
+                                       "launches": "2 fmm_eval calls on the batched plans"},
             "separate_plans": {"value": round(n / t_s / 1e6, 3), "ms_per_step": round(t_s * 1e3, 4),
                                "launches": "2 x 64 fmm_eval calls"},
             "worst_sampled_molecule_rel_err": errors}
+    print(json.dumps(line), flush=True)
+
+
+def _timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_adjoint(args):
+    """E = 1/2 q.G q on 1,000,002 surface points (500 spheres), Laplace, FP32
+    (the configuration the full-size adjoint test checks): forward fmm_eval
+    with gradient, and forward + fmm_adjoint through torch.autograd; reports
+    the adjoint's time against the forward's."""
+    import torch
+    import synth
+    from paper_2103_01048_amd import FMMPlan, solvation_style_energy
+    dev = torch.device("cuda:0")
+    x, _ = synth.surface_cloud(500, 333334, seed=81)
+    q = np.random.default_rng(81).uniform(-1.0, 1.0, len(x))
+    ncrit = args.ncrit or 128
+    xt = torch.tensor(x, device=dev)
+    plan = FMMPlan(xt, kernel="laplace", p=P_ORDER, ncrit=ncrit, precision="fp32")
+    qf = torch.tensor(q, device=dev, dtype=torch.float32)
+
+    def both():
+        qq = qf.clone().requires_grad_(True)
+        xx = xt.clone().requires_grad_(True)
+        solvation_style_energy(plan, qq, xx).backward()
+
+    t_f = _timed(torch, lambda: plan.eval(qf), args.steps, args.warmup)
+    t_fb = _timed(torch, both, args.steps, args.warmup)
+    n = len(x)
+    line = {"metric": "adjoint (dE/dq and dE/dx) time against forward time, E = 1/2 q.phi, 1M points",
+            "value": round((t_fb - t_f) * 1e3, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(t_fb * 1e3, 3), "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"sphere-union surface, 500 spheres, {n} points, Laplace, E = 1/2 q.phi",
+                       "p": P_ORDER, "ncrit": ncrit, "precision": "fp32"},
+            "forward_ms": round(t_f * 1e3, 3), "adjoint_over_forward": round((t_fb - t_f) / t_f, 3),
+            "forward_mpoints_per_s": round(n / t_f / 1e6, 1)}
+    print(json.dumps(line), flush=True)
+
+
+def run_shell(args):
+    """30M points (10M triangles x 3) on a 30,000-sphere shell of radius
+    200 A, p = 10: one fmm_eval_pair (Laplace + Yukawa, potential and
+    gradient) per step.  Accuracy on sampled rows is checked by the
+    full-size tests."""
+    import torch
+    import synth
+    from paper_2103_01048_amd import FMMPlan, eval_pair
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    x, q = synth.surface_cloud(30000, 10_000_000, seed=13, shell_radius=200.0)
+    print(f"# shell of {len(x)} points in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    ncrit = args.ncrit or 128
+    xt = torch.tensor(x, device=dev)
+    t0 = time.perf_counter()
+    plans = [FMMPlan(xt, kernel=k, kappa=KAPPA, p=10, ncrit=ncrit, precision=args.precision)
+             for k in ("laplace", "yukawa")]
+    t_setup = time.perf_counter() - t0
+    qt = torch.tensor(q, device=dev, dtype=torch.float32)
+    t = _timed(torch, lambda: eval_pair(plans[0], plans[1], qt), args.steps, args.warmup)
+    n = len(x)
+    line = {"metric": "FMM matvec Mpoints/s (Laplace+Yukawa), 30M-point shell",
+            "value": round(n / t / 1e6, 3), "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(t * 1e3, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"30,000-sphere shell, radius 200 A, {n} points; Laplace + Yukawa (kappa 0.125) "
+                                   "fmm_eval_pair, potential + gradient",
+                       "p": 10, "ncrit": ncrit, "precision": args.precision},
+            "setup_s_both_plans": round(t_setup, 2), "tree": plans[0].info()}
     print(json.dumps(line), flush=True)
 
 
@@ -252,6 +336,12 @@ def main():
         return
     if args.workload == "bem2m":
         run_bem(args)
+        return
+    if args.workload == "adjoint1m":
+        run_adjoint(args)
+        return
+    if args.workload == "shell30m":
+        run_shell(args)
         return
     import torch
     from paper_2103_01048_amd import FMMPlan, eval_pair

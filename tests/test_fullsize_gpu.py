@@ -71,6 +71,26 @@ def test_surface393k_bf16x3_every_ncrit(surface393k, kernel, ncrit):
     _check_rows(plan, torch, x, q, rows, kernel, 1e-4, f"393k {kernel} bf16x3 ncrit {ncrit}")
 
 
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-4), ("fp32", 1e-4), ("fp64", 1e-6)])
+def test_surface393k_pair(surface393k, precision, tol):
+    """The benchmark's step: one fmm_eval_pair of a Laplace and a Yukawa
+    plan (p = 8, ncrit 128) against the direct sums on sampled rows."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, eval_pair
+    x, q = surface393k
+    xt = torch.tensor(x, device="cuda")
+    plans = [FMMPlan(xt, kernel=k, kappa=KAPPA, p=8, ncrit=128, precision=precision) for k in ("laplace", "yukawa")]
+    outs = eval_pair(plans[0], plans[1], torch.tensor(q, device="cuda"))
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(74).choice(len(x), 2048, replace=False)
+    for kernel, (pot, grad) in zip(("laplace", "yukawa"), outs):
+        phi, g = D.direct(x[rows], x, q, kernel, KAPPA if kernel == "yukawa" else 0.0)
+        ep = _rel(pot.cpu().numpy()[rows], phi)
+        eg = _rel(grad.cpu().numpy()[rows], g)
+        _say(f"[393k pair {precision} {kernel}] pot {ep:.2e} grad {eg:.2e}")
+        assert ep < tol and eg < tol
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("fp64", 1e-6)])
 @pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
 def test_surface393k_fp32_fp64(surface393k, kernel, precision, tol):
@@ -85,16 +105,19 @@ def test_surface393k_fp32_fp64(surface393k, kernel, precision, tol):
 
 @pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
 def test_batch64_molecules(kernel):
-    """The 64-molecule batch in one plan: four molecules (smallest, largest,
-    two seeded) against their own direct sums on sampled rows."""
+    """The 64-molecule batch in one Laplace and one Yukawa plan evaluated as a
+    pair (as the benchmark times it): four molecules (smallest, largest, two
+    seeded) against their own direct sums on sampled rows."""
     torch = require_gpu()
-    from paper_2103_01048_amd import FMMPlan
+    from paper_2103_01048_amd import FMMPlan, eval_pair
     xs, qs = synth.molecule_batch(64, seed=5)
     off = np.concatenate([[0], np.cumsum([len(x) for x in xs])])
     X, Q = np.concatenate(xs), np.concatenate(qs)
-    plan = FMMPlan(torch.tensor(X, device="cuda"), kernel=kernel, kappa=KAPPA, p=8, ncrit=128,
-                   precision="bf16x3", offsets=off)
-    pot, grad = plan.eval(torch.tensor(Q, device="cuda"))
+    xt = torch.tensor(X, device="cuda")
+    plans = [FMMPlan(xt, kernel=k, kappa=KAPPA, p=8, ncrit=128, precision="bf16x3", offsets=off)
+             for k in ("laplace", "yukawa")]
+    outs = eval_pair(plans[0], plans[1], torch.tensor(Q, device="cuda"))
+    pot, grad = outs[0 if kernel == "laplace" else 1]
     pot, grad = pot.cpu().numpy(), grad.cpu().numpy()
     sizes = np.diff(off)
     rng = np.random.default_rng(73)
