@@ -71,15 +71,17 @@ def test_surface393k_bf16x3_every_ncrit(surface393k, kernel, ncrit):
     _check_rows(plan, torch, x, q, rows, kernel, 1e-4, f"393k {kernel} bf16x3 ncrit {ncrit}")
 
 
-@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-4), ("fp32", 1e-4), ("fp64", 1e-6)])
-def test_surface393k_pair(surface393k, precision, tol):
+@pytest.mark.parametrize("precision,tol,ncrit", [("bf16x3", 1e-4, nc) for nc in (64, 96, 128, 192, 256)]
+                         + [("fp32", 1e-4, 128), ("fp64", 1e-6, 128)])
+def test_surface393k_pair(surface393k, precision, tol, ncrit):
     """The benchmark's step: one fmm_eval_pair of a Laplace and a Yukawa
-    plan (p = 8, ncrit 128) against the direct sums on sampled rows."""
+    plan (p = 8, every ncrit of the benchmark's sweep) against the direct
+    sums on sampled rows."""
     torch = require_gpu()
     from paper_2103_01048_amd import FMMPlan, eval_pair
     x, q = surface393k
     xt = torch.tensor(x, device="cuda")
-    plans = [FMMPlan(xt, kernel=k, kappa=KAPPA, p=8, ncrit=128, precision=precision) for k in ("laplace", "yukawa")]
+    plans = [FMMPlan(xt, kernel=k, kappa=KAPPA, p=8, ncrit=ncrit, precision=precision) for k in ("laplace", "yukawa")]
     outs = eval_pair(plans[0], plans[1], torch.tensor(q, device="cuda"))
     torch.cuda.synchronize()
     rows = np.random.default_rng(74).choice(len(x), 2048, replace=False)
@@ -87,7 +89,7 @@ def test_surface393k_pair(surface393k, precision, tol):
         phi, g = D.direct(x[rows], x, q, kernel, KAPPA if kernel == "yukawa" else 0.0)
         ep = _rel(pot.cpu().numpy()[rows], phi)
         eg = _rel(grad.cpu().numpy()[rows], g)
-        _say(f"[393k pair {precision} {kernel}] pot {ep:.2e} grad {eg:.2e}")
+        _say(f"[393k pair {precision} ncrit {ncrit} {kernel}] pot {ep:.2e} grad {eg:.2e}")
         assert ep < tol and eg < tol
 
 
