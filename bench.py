@@ -400,15 +400,17 @@ def main():
     if args.ncrit:
         ncrit = args.ncrit
     else:
-        best = None
+        times = {}
         for nc in (64, 96, 128, 192, 256):
             pls = make(args.precision, nc)
             dt, _ = time_steps(step_pair, pls, qd, 5, 2)
             sweep[str(nc)] = round(dt / 5 * 1e3, 3)
-            if best is None or dt < best[0]:
-                best = (dt, nc)
+            times[nc] = dt
             del pls
-        ncrit = best[1]
+        # the smallest ncrit within 2% of the fastest: near-ties (128 and 192
+        # differ by well under 1% here) then resolve the same way every run
+        fastest = min(times.values())
+        ncrit = min(nc for nc, dt in times.items() if dt <= 1.02 * fastest)
         print("# ncrit sweep: " + ", ".join(f"{k}={v} ms" for k, v in sweep.items()), file=sys.stderr, flush=True)
 
     plans = make(args.precision, ncrit)
