@@ -113,12 +113,12 @@ int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *g
  * fmm_eval(plan_a, ...) and fmm_eval(plan_b, ...), with the same layouts;
  * grad_a_dev / grad_b_dev may be NULL.  When plan_a is a Laplace plan and
  * plan_b a Yukawa plan built from the same points (and batch offsets) with
- * the same p, ncrit and precision, the two share one tree: their far-field
- * passes run concurrently on two internal streams (default priority) while
- * the near field of both kernels runs on `stream` in one launch that
- * computes each pair distance once; otherwise the two evaluations run one
- * after the other on `stream`.  Asynchronous on `stream` (the internal
- * streams are joined back into it).  Errors: as fmm_eval; FMM_EINVAL when
+ * the same p, ncrit and precision, the two share one tree: the far-field
+ * passes of both kernels run as shared launches on an internal stream
+ * (default priority, owned by plan_a) while the near field of both kernels
+ * runs on `stream` in one launch that computes each pair distance once;
+ * otherwise the two evaluations run one after the other on `stream`.
+ * Asynchronous on `stream` (the internal stream is joined back into it).  Errors: as fmm_eval; FMM_EINVAL when
  * the plans differ in point count or precision. */
 int fmm_eval_pair(fmm_plan *plan_a, fmm_plan *plan_b, const void *q_dev, int nrhs, void *pot_a_dev,
                   void *grad_a_dev, void *pot_b_dev, void *grad_b_dev, fmm_stream_t stream);

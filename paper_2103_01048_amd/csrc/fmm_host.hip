@@ -1091,15 +1091,15 @@ static uint64_t tree_fingerprint(const fmm_plan *P) {
   return h;
 }
 
-// Resources of a pair evaluation (A: Laplace half, B: Yukawa half): one side
-// stream per plan (default priority), A's fork and join events, B's join
-// event, and A's buffer of near-field running sums for nr columns.
+// Resources of a pair evaluation (A: Laplace half, B: Yukawa half): A's side
+// stream (default priority) that runs both kernels' passes, A's fork and join
+// events, B's event marking the end of the surface passes, and A's buffer of
+// near-field running sums for nr columns.
 int ensure_pair(fmm_plan *A, fmm_plan *B, int nr) {
-  for (fmm_plan *P : {A, B}) {
-    if (!P->aux) FMM_HIP_TRY(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
-    if (!P->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
-    if (!P->ev_join) FMM_HIP_TRY(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
-  }
+  if (!A->aux) FMM_HIP_TRY(hipStreamCreateWithFlags(&A->aux, hipStreamNonBlocking));
+  if (!A->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_fork, hipEventDisableTiming));
+  if (!A->ev_join) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_join, hipEventDisableTiming));
+  if (!B->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
   const size_t es = A->precision == FMM_FP64 ? 8 : 4;
   const size_t need = std::max<size_t>(1, (size_t)A->dt.nitems) * 2 * nr * 4 * 64 * es;
   if (A->pair_acc_bytes < need) {
