@@ -194,3 +194,35 @@ def test_exterior_converges_in_fewer_iterations_under_mass_preconditioning():
         order = math.log(a / b) / math.log(4.0)
         assert 0.85 < order < 1.15, errs
     assert all(e <= 0.6 * d for e, d in zip(its["exterior"], its["derivative"])), its
+
+
+def test_exterior_refinement_from_the_bf16x3_operator(sphere512_ext):
+    """GMRES on the bf16x3 exterior operator with FP64 residuals (iterative
+    refinement against the FP64 operator) reaches the dense solution."""
+    require_gpu()
+    from paper_2103_01048_amd import gmres
+    v, t, m, A_ = sphere512_ext
+    qx, q = [[1.0, 1.0, 1.0]], [1.0]
+    op = _op(v, t, "bf16x3", formulation="exterior")
+    ref = _op(v, t, "fp64", formulation="exterior")
+    op.set_preconditioner("mass")
+    b = ref.rhs(qx, q)
+    x, it, _, rc = gmres(op, b, tol=1e-9, maxiter=300, refine=ref, inner_tol=1e-3)
+    assert rc == 0
+    x_lu = np.linalg.solve(A_, B.rhs_exterior(m, qx, q, 80.0))
+    e = _rel(x.cpu().numpy(), x_lu)
+    print(f"[exterior refinement] iterations {it} rel {e:.2e}", flush=True)
+    assert e < 1e-6
+
+
+def test_set_preconditioner_rejects_unknown_kind():
+    require_gpu()
+    from paper_2103_01048_amd import _lib
+    from paper_2103_01048_amd._lib import lib
+    v, t = synth.octa_sphere(2, 4.0)
+    op = _op(v, t, "fp32", formulation="exterior")
+    assert lib().bem_set_preconditioner(op._h, 7, None) == _lib.FMM_EINVAL
+    assert "preconditioner" in lib().fmm_last_error().decode()
+    with pytest.raises(ValueError):
+        op.set_preconditioner("jacobi")
+    assert op.info()["preconditioner"] == 0
