@@ -437,6 +437,12 @@ def main():
     dts, _ = time_steps(step_separate, plans, qd, args.steps, 1)
     others = {"separate_evals": {"value": round(n / (dts / args.steps) / 1e6, 3),
                                  "ms_per_step": round(dts / args.steps * 1e3, 4)}}
+    # each kernel alone (one fmm_eval per step)
+    per_kernel = {}
+    for k, pl in plans.items():
+        dtk, _ = time_steps(lambda p_, q_, pl=pl: pl.eval(q_[pl.dtype]), plans, qd, args.steps, 1)
+        per_kernel[k] = {"value": round(n / (dtk / args.steps) / 1e6, 3), "ms_per_eval": round(dtk / args.steps * 1e3, 4)}
+    others["per_kernel"] = per_kernel
     other_plans = {}
     if args.precision != "fp32":
         other_plans["fp32"] = make("fp32", ncrit)
