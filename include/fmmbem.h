@@ -75,7 +75,7 @@ enum {
 
 /* Build a plan for the points xyz_dev (device, n x 3 doubles, row-major,
  * read during the call only).  kernel: FMM_LAPLACE or FMM_YUKAWA; kappa >= 0
- * (used by Yukawa only); p in [2, 16]; ncrit >= 1; precision: FMM_FP64,
+ * (used by Yukawa only); p in [2, 10]; ncrit >= 1; precision: FMM_FP64,
  * FMM_FP32 or FMM_FP32_BF16X3.  Sorts the points along a Morton curve on the
  * device, builds the tree and interaction lists on the host, precomputes the
  * translation operators in FP64 (truncated-SVD pseudo-inverses of the

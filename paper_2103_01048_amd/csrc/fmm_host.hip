@@ -1188,7 +1188,9 @@ static int setup_common(const double *xyz_dev, const std::vector<int64_t> &off, 
   if (n > 0 && !xyz_dev) { set_error("fmm_setup: xyz is NULL"); return FMM_EINVAL; }
   if (kernel != FMM_LAPLACE && kernel != FMM_YUKAWA) { set_error("fmm_setup: unknown kernel"); return FMM_EINVAL; }
   if (!(kappa >= 0.0) || !std::isfinite(kappa)) { set_error("fmm_setup: kappa must be finite and >= 0"); return FMM_EINVAL; }
-  if (p < 2 || p > 16) { set_error("fmm_setup: p must be in [2, 16]"); return FMM_EINVAL; }
+  // p <= 10: the surface kernels hold one surface point per thread of a
+  // workgroup of at most 512 (n_surf = 488 at p = 10)
+  if (p < 2 || p > 10) { set_error("fmm_setup: p must be in [2, 10]"); return FMM_EINVAL; }
   if (ncrit < 1) { set_error("fmm_setup: ncrit must be >= 1"); return FMM_EINVAL; }
   if (precision != FMM_FP64 && precision != FMM_FP32 && precision != FMM_FP32_BF16X3) {
     set_error("fmm_setup: unknown precision");

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol():
     ((1, 10, 1, -0.1, 6, 64, 1), "kappa"),
     ((1, 10, 1, float("nan"), 6, 64, 1), "kappa"),
     ((1, 10, 0, 0.0, 1, 64, 1), "p must"),
-    ((1, 10, 0, 0.0, 17, 64, 1), "p must"),
+    ((1, 10, 0, 0.0, 11, 64, 1), "p must"),
     ((1, 10, 0, 0.0, 6, 0, 1), "ncrit"),
     ((1, 10, 0, 0.0, 6, 64, 9), "precision"),
 ])
