@@ -66,3 +66,25 @@ def test_batch_tree_keeps_molecules_apart():
         assert np.all(seg == box_mol[b])
         for lst in (g["U"], g["V"], g["W"], g["X"]):
             assert all(box_mol[a] == box_mol[b] for a in lst[b])
+
+
+def test_batch_with_empty_and_single_point_molecules():
+    """Empty molecules (repeated offsets) get no boxes; a one-point molecule
+    sees nothing; the others still match their own direct sums."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    xs, qs, _ = _molecules(3, seed=63)
+    one = np.array([[3.0, -2.0, 1.0]])
+    parts = [xs[0], np.zeros((0, 3)), one, xs[1], np.zeros((0, 3)), xs[2], np.zeros((0, 3))]
+    qparts = [qs[0], np.zeros(0), np.array([0.7]), qs[1], np.zeros(0), qs[2], np.zeros(0)]
+    off = np.concatenate([[0], np.cumsum([len(x) for x in parts])])
+    X, Q = np.concatenate(parts), np.concatenate(qparts)
+    plan = FMMPlan(torch.tensor(X, device="cuda"), kernel="yukawa", kappa=0.125, p=6, ncrit=32,
+                   precision="fp64", offsets=off)
+    pot, grad = plan.eval(torch.tensor(Q, device="cuda"))
+    pot, grad = pot.cpu().numpy(), grad.cpu().numpy()
+    assert pot[off[2]] == 0.0 and np.all(grad[off[2]] == 0.0)
+    for k in (0, 3, 5):
+        s = slice(off[k], off[k + 1])
+        p0, g0 = D.direct(parts[k], parts[k], qparts[k], "yukawa", 0.125)
+        assert D.rel_l2(pot[s], p0) < 1e-6 and D.rel_l2(grad[s], g0) < 1e-6
