@@ -79,7 +79,7 @@ def test_batch_with_empty_and_single_point_molecules():
     qparts = [qs[0], np.zeros(0), np.array([0.7]), qs[1], np.zeros(0), qs[2], np.zeros(0)]
     off = np.concatenate([[0], np.cumsum([len(x) for x in parts])])
     X, Q = np.concatenate(parts), np.concatenate(qparts)
-    plan = FMMPlan(torch.tensor(X, device="cuda"), kernel="yukawa", kappa=0.125, p=6, ncrit=32,
+    plan = FMMPlan(torch.tensor(X, device="cuda"), kernel="yukawa", kappa=0.125, p=8, ncrit=32,
                    precision="fp64", offsets=off)
     pot, grad = plan.eval(torch.tensor(Q, device="cuda"))
     pot, grad = pot.cpu().numpy(), grad.cpu().numpy()
