@@ -886,7 +886,7 @@ static void add_columns(GemmBatch &bt, int mat, double alpha, const std::vector<
     t.mat = mat;
     t.col0 = base + c0;
     t.ncol = std::min(GEMM_NT, nc - c0);
-    t.pad_ = 0;
+    t.nrb = 0;
     t.alpha = alpha;
     bt.h_tasks.push_back(t);
   }
@@ -1059,11 +1059,21 @@ int ensure_lists(fmm_plan *P, int nr) {
         }
         ++j;
       }
+      const size_t t0 = L.m2l.h_tasks.size();
       add_columns(L.m2l, P->m2l_id[l][code], 1.0, src, dst);
+      // only the rows of this level's downward rank (the rest of the
+      // operator is zero padding)
+      for (size_t t = t0; t < L.m2l.h_tasks.size(); ++t) L.m2l.h_tasks[t].nrb = r16(P->rank_d[l]) / 16;
       i = j;
     }
   }
   if ((rc = finish_batch(P, L.m2l))) return rc;
+  if (!P->d_m2l_rows) {
+    std::vector<int32_t> rows(std::max<int64_t>(1, nb), 16);
+    for (int64_t b = 0; b < nb; ++b)
+      if (P->level[b] >= 2) rows[b] = r16(P->rank_d[P->level[b]]);
+    if ((rc = upload(P, (void **)&P->d_m2l_rows, rows))) return rc;
+  }
   L.nr = nr;
   return FMM_OK;
 }

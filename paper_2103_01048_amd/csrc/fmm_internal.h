@@ -40,7 +40,7 @@ struct GemmTask {
   int32_t mat;
   int32_t col0;
   int32_t ncol;
-  int32_t pad_;
+  int32_t nrb;     // 16-row blocks this task computes (0: the batch's nrb)
   double alpha;
 };
 
@@ -181,6 +181,7 @@ struct fmm_plan {
   int32_t *d_p2m_box = nullptr;   // box ids
   int32_t *d_p2m_off = nullptr;   // 0..p2m_count (each box is its own source)
   int32_t *d_has_local = nullptr; // per leaf slot: level >= 2
+  int32_t *d_m2l_rows = nullptr;  // per box: rows of its M2L sums (its level's downward rank, to 16)
   // profiling: event pairs per phase, recorded during fmm_eval
   int profiling = 0;               // bit k set: time phase k
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_events;

@@ -288,14 +288,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g0, GemmArgs g1) {
   __builtin_amdgcn_s_setprio(3);
   // g.S segments of g.seg k-values per column (segment s of column c is row
   // src[c*S+s] of X, row length g.ldx); g.KQ: 16-wide k groups per stored
-  // row block of A; g.klen: k-values read; g.nrb: 16-row blocks computed;
+  // row block of A; g.klen: k-values read; g.nrb: 16-row blocks computed
+  // (a task's nrb, when set, computes fewer: the M2L rank of its level);
   // output rows have length g.ldy.
   using V4 = typename Vec4<T>::type;
   GemmArgs g;
   int task;
   if (!gemm_pick(g0, g1, g, task)) return;
   const GemmTask tk = g.tasks[task];
-  const int S = g.S, seg = g.seg, KQ = g.KQ, nrb = g.nrb, K = g.klen, ld = g.ldx, ldy = g.ldy, mode = g.mode;
+  const int S = g.S, seg = g.seg, KQ = g.KQ, K = g.klen, ld = g.ldx, ldy = g.ldy, mode = g.mode;
+  const int nrb = tk.nrb > 0 ? min(tk.nrb, g.nrb) : g.nrb;
   const int32_t *__restrict__ src = g.src;
   const int32_t *__restrict__ dst = g.dst;
   const T *__restrict__ X = (const T *)g.X;
@@ -421,7 +423,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf3(GemmArgs g0, GemmArgs g1, int 
   int task;
   if (!gemm_pick(g0, g1, g, task)) return;
   const GemmTask tk = g.tasks[task];
-  const int ld = g.ldx, nrb = g.nrb, K = g.klen, ldy = g.ldy, mode = g.mode;
+  const int ld = g.ldx, K = g.klen, ldy = g.ldy, mode = g.mode;
+  const int nrb = tk.nrb > 0 ? min(tk.nrb, g.nrb) : g.nrb;
   const int32_t *__restrict__ src = g.src;
   const int32_t *__restrict__ dst = g.dst;
   const float *__restrict__ X = (const float *)g.X;
@@ -1400,20 +1403,29 @@ __global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ 
                                                     const int32_t *__restrict__ pairs, const T *__restrict__ pairbuf0,
                                                     T *__restrict__ y0, int nr, int ld, int ldp0, int rows0,
                                                     const T *__restrict__ pairbuf1, T *__restrict__ y1, int ldp1,
-                                                    int rows1) {
+                                                    int rows1, const int32_t *__restrict__ brows0,
+                                                    const int32_t *__restrict__ brows1) {
   __builtin_amdgcn_s_setprio(3);
   using V4 = typename Vec4<T>::type;
   const bool second = blockIdx.y != 0;
   const T *__restrict__ pairbuf = second ? pairbuf1 : pairbuf0;
   T *__restrict__ y = second ? y1 : y0;
   const int ldp = second ? ldp1 : ldp0, rows = second ? rows1 : rows0;
+  const int32_t *__restrict__ brows = second ? brows1 : brows0;
   const int slot = blockIdx.x;
   const int b = tgt[slot];
   const int p0 = off[slot], p1 = off[slot + 1];
   const int rq = rows >> 2, lq = ld >> 2, pq = ldp >> 2;
+  // rows of this box's slots that hold data (its level's rank); the rows
+  // above it, up to `rows`, are set to zero
+  const int bq = brows ? min(rq, brows[b] >> 2) : rq;
   const V4 *__restrict__ pb = reinterpret_cast<const V4 *>(pairbuf);
   for (int e = threadIdx.x; e < nr * rq; e += 64) {
     const int r = e / rq, i = e - r * rq;
+    if (i >= bq) {
+      reinterpret_cast<V4 *>(y)[((int64_t)b * nr + r) * lq + i] = V4{0, 0, 0, 0};
+      continue;
+    }
     // four independent partial sums (pairs p0 + 4k + j go to sum j) keep
     // four loads in flight; they are added in a fixed order
     V4 a0 = V4{0, 0, 0, 0}, a1 = a0, a2 = a0, a3 = a0;
@@ -1561,7 +1573,8 @@ static int eval_passes(fmm_plan *P, hipStream_t s) {
     ev = prof_begin(P, FMM_PHASE_M2M, s);
     if ((rc = launch_gemm<T>(P, L.m2m[l], cu, (T *)P->mslot, s))) return rc;
     hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.m2m_n[l]), dim3(64), 0, s, D.m2m_tgt[l], D.m2m_off[l], D.m2m_kid[l],
-                       (const T *)P->mslot, cu, NR, ld, ld, L.m2m[l].nrb * 16, (const T *)nullptr, (T *)nullptr, 0, 0);
+                       (const T *)P->mslot, cu, NR, ld, ld, L.m2m[l].nrb * 16, (const T *)nullptr, (T *)nullptr, 0, 0,
+                       (const int32_t *)nullptr, (const int32_t *)nullptr);
     FMM_HIP_TRY(hipGetLastError());
     prof_end(P, FMM_PHASE_M2M, ev, s);
   }
@@ -1586,7 +1599,7 @@ static int eval_passes(fmm_plan *P, hipStream_t s) {
   if (D.nvbox > 0)
     hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.nvbox), dim3(64), 0, s, D.v_tgt, D.v_off, D.v_pair,
                        (const T *)P->pairbuf, yd, NR, ld, L.m2l.ldy, L.m2l.nrb * 16, (const T *)nullptr, (T *)nullptr,
-                       0, 0);
+                       0, 0, (const int32_t *)P->d_m2l_rows, (const int32_t *)nullptr);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(P, FMM_PHASE_M2L_SUM, ev, s);
   ev = prof_begin(P, FMM_PHASE_DC2E, s);
@@ -1661,7 +1674,8 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t 
       return rc;
     hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.m2m_n[l], 2), dim3(64), 0, s, D.m2m_tgt[l], D.m2m_off[l],
                        D.m2m_kid[l], (const T *)A->mslot, W(A->cu), NR, ld, ld, LA.m2m[l].nrb * 16,
-                       (const T *)B->mslot, W(B->cu), ld, LB.m2m[l].nrb * 16);
+                       (const T *)B->mslot, W(B->cu), ld, LB.m2m[l].nrb * 16, (const int32_t *)nullptr,
+                       (const int32_t *)nullptr);
     FMM_HIP_TRY(hipGetLastError());
     prof_end(A, FMM_PHASE_M2M, ev, s);
   }
@@ -1676,7 +1690,8 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t 
   if (D.nvbox > 0)
     hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.nvbox, 2), dim3(64), 0, s, D.v_tgt, D.v_off, D.v_pair,
                        (const T *)A->pairbuf, W(A->yd), NR, ld, LA.m2l.ldy, LA.m2l.nrb * 16, (const T *)B->pairbuf,
-                       W(B->yd), LB.m2l.ldy, LB.m2l.nrb * 16);
+                       W(B->yd), LB.m2l.ldy, LB.m2l.nrb * 16, (const int32_t *)A->d_m2l_rows,
+                       (const int32_t *)B->d_m2l_rows);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_M2L_SUM, ev, s);
   ev = prof_begin(A, FMM_PHASE_DC2E, s);
