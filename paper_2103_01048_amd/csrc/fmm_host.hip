@@ -887,6 +887,7 @@ static void add_columns(GemmBatch &bt, int mat, double alpha, const std::vector<
     t.col0 = base + c0;
     t.ncol = std::min(GEMM_NT, nc - c0);
     t.nrb = 0;
+    t.klen = 0;
     t.alpha = alpha;
     bt.h_tasks.push_back(t);
   }
@@ -1061,9 +1062,14 @@ int ensure_lists(fmm_plan *P, int nr) {
       }
       const size_t t0 = L.m2l.h_tasks.size();
       add_columns(L.m2l, P->m2l_id[l][code], 1.0, src, dst);
-      // only the rows of this level's downward rank (the rest of the
-      // operator is zero padding)
-      for (size_t t = t0; t < L.m2l.h_tasks.size(); ++t) L.m2l.h_tasks[t].nrb = r16(P->rank_d[l]) / 16;
+      // only the rows of this level's downward rank and the columns of its
+      // upward rank (the rest of the operator is zero padding; the bf16x3
+      // kernel steps k by 32)
+      const int kl = L.m2l.pool == 2 ? ((r16(P->rank_u[l]) + 31) / 32) * 32 : r16(P->rank_u[l]);
+      for (size_t t = t0; t < L.m2l.h_tasks.size(); ++t) {
+        L.m2l.h_tasks[t].nrb = r16(P->rank_d[l]) / 16;
+        L.m2l.h_tasks[t].klen = kl;
+      }
       i = j;
     }
   }

@@ -41,6 +41,7 @@ struct GemmTask {
   int32_t col0;
   int32_t ncol;
   int32_t nrb;     // 16-row blocks this task computes (0: the batch's nrb)
+  int32_t klen;    // k-values this task reads (0: the batch's klen)
   double alpha;
 };
 

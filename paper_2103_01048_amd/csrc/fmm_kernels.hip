@@ -289,15 +289,17 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g0, GemmArgs g1) {
   // g.S segments of g.seg k-values per column (segment s of column c is row
   // src[c*S+s] of X, row length g.ldx); g.KQ: 16-wide k groups per stored
   // row block of A; g.klen: k-values read; g.nrb: 16-row blocks computed
-  // (a task's nrb, when set, computes fewer: the M2L rank of its level);
+  // (a task's nrb and klen, when set, are smaller: the M2L ranks of its
+  // level);
   // output rows have length g.ldy.
   using V4 = typename Vec4<T>::type;
   GemmArgs g;
   int task;
   if (!gemm_pick(g0, g1, g, task)) return;
   const GemmTask tk = g.tasks[task];
-  const int S = g.S, seg = g.seg, KQ = g.KQ, K = g.klen, ld = g.ldx, ldy = g.ldy, mode = g.mode;
+  const int S = g.S, seg = g.seg, KQ = g.KQ, ld = g.ldx, ldy = g.ldy, mode = g.mode;
   const int nrb = tk.nrb > 0 ? min(tk.nrb, g.nrb) : g.nrb;
+  const int K = tk.klen > 0 ? min(tk.klen, g.klen) : g.klen;
   const int32_t *__restrict__ src = g.src;
   const int32_t *__restrict__ dst = g.dst;
   const T *__restrict__ X = (const T *)g.X;
@@ -423,8 +425,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf3(GemmArgs g0, GemmArgs g1, int 
   int task;
   if (!gemm_pick(g0, g1, g, task)) return;
   const GemmTask tk = g.tasks[task];
-  const int ld = g.ldx, K = g.klen, ldy = g.ldy, mode = g.mode;
+  const int ld = g.ldx, ldy = g.ldy, mode = g.mode;
   const int nrb = tk.nrb > 0 ? min(tk.nrb, g.nrb) : g.nrb;
+  const int K = tk.klen > 0 ? min(tk.klen, g.klen) : g.klen;
   const int32_t *__restrict__ src = g.src;
   const int32_t *__restrict__ dst = g.dst;
   const float *__restrict__ X = (const float *)g.X;
