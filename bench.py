@@ -328,8 +328,8 @@ def run_bem(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1 "
-              "(the multi-GPU sharding is a design note, not code)", file=sys.stderr)
+        print("bench.py: runs on one GPU; --gpus must be 1 "
+              "(the multi-GPU sharding is described, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch64":
         run_batch(args)
