@@ -559,3 +559,83 @@ def mass_preconditioned(m: Mesh, A):
     diagonal, so mass lumping changes nothing)."""
     d = np.concatenate([m.area, m.area])
     return A / d[:, None]
+
+
+def matvec_rows_derivative(m: Mesh, rows, x, eps1=4.0, eps2=80.0, kappa=0.125, formulation="interior",
+                           n_outer: int = 8, n_rem: int = 4, chunk: int = 1 << 20):
+    """Rows `rows` of A x of the interior (eq:juffer) or exterior (eq:lu)
+    derivative formulation for any mesh size: every operator row is a plain
+    sum over all trial triangles (regular rule; V, K and K' through the C
+    direct sum, K' as n_s . grad of the single-layer potential, W_Y - W_L in
+    NumPy over source chunks), and the pairs that share a vertex take the
+    singular rule (K' from the transposed K pair).  Returns (len(rows), 2)."""
+    from . import direct as Dd
+    T = len(m.tris)
+    k = m.qpts.shape[1]
+    rows = np.asarray(rows)
+    u, v = x[:T], x[T:]
+    Y = m.qpts.reshape(-1, 3)
+    W = m.qw.reshape(-1)
+    n_rep = np.repeat(m.normal, k, axis=0)
+    uu = np.repeat(u, k) * W
+    vv = np.repeat(v, k) * W
+    tgt = m.qpts[rows].reshape(-1, 3)
+    wt = m.qw[rows].reshape(-1)
+    nt = np.repeat(m.normal[rows], k, axis=0)
+    by_row = {int(s_): np.nonzero(np.isin(m.tris, m.tris[s_]).any(axis=1))[0] for s_ in rows}
+    ops = {}
+    for kern, kap in (("laplace", 0.0), ("yukawa", kappa)):
+        Kx = np.zeros(len(tgt))
+        for d in range(3):
+            _, g = Dd.direct(tgt, Y, uu * n_rep[:, d], kern, kap)
+            Kx -= g[:, d]
+        Vx, gv = Dd.direct(tgt, Y, vv, kern, kap)
+        Kpx = np.sum(nt * gv, axis=1)
+        Kr = (wt * Kx).reshape(len(rows), k).sum(axis=1)
+        Vr = (wt * Vx).reshape(len(rows), k).sum(axis=1)
+        Kpr = (wt * Kpx).reshape(len(rows), k).sum(axis=1)
+        for i, s_ in enumerate(rows):
+            ts = by_row[int(s_)]
+            Vs, Ks = singular_entries(m, np.full(len(ts), s_), ts, kap, n_outer, n_rem)
+            _, Kts = singular_entries(m, ts, np.full(len(ts), s_), kap, n_outer, n_rem)
+            for j, t_ in enumerate(ts):
+                Vreg, Kreg = regular_entries(m, s_, t_, kap)
+                _, Ktreg = regular_entries(m, t_, s_, kap)
+                Vr[i] += (Vs[j] - Vreg) * v[t_]
+                Kr[i] += (Ks[j] - Kreg) * u[t_]
+                Kpr[i] += (Kts[j] - Ktreg) * v[t_]
+        ops[kern] = (Vr, Kr, Kpr)
+    # W_Y - W_L: regular rule over all quadrature points, then the singular pairs
+    Wr = np.zeros(len(rows))
+    for i, s_ in enumerate(rows):
+        acc = 0.0
+        for a in range(k):
+            xa = m.qpts[s_, a]
+            tot = 0.0
+            for c0 in range(0, len(Y), chunk):
+                dd = xa[None, :] - Y[c0:c0 + chunk]
+                r = np.linalg.norm(dd, axis=1)
+                mask = r > 0
+                dd = np.where(mask[:, None], dd, 1.0)
+                kv = hyper_diff_kernel(dd, m.normal[s_], n_rep[c0:c0 + chunk], kappa)
+                tot += float(np.sum(np.where(mask, kv, 0.0) * uu[c0:c0 + chunk]))
+            acc += m.qw[s_, a] * tot
+        ts = by_row[int(s_)]
+        Ws = hyper_diff_singular(m, np.full(len(ts), s_), ts, kappa, n_outer, n_rem)
+        for j, t_ in enumerate(ts):
+            acc += (Ws[j] - hyper_diff_regular(m, s_, t_, kappa)) * u[t_]
+        Wr[i] = acc
+    VL, KL, KpL = ops["laplace"]
+    VY, KY, KpY = ops["yukawa"]
+    e12, e21 = eps1 / eps2, eps2 / eps1
+    A_ = m.area[rows]
+    out = np.zeros((len(rows), 2))
+    if formulation == "interior":
+        out[:, 0] = 0.5 * (1 + e21) * A_ * u[rows] - (e21 * KY - KL) + (VY - VL)
+        out[:, 1] = Wr + 0.5 * (1 + e12) * A_ * v[rows] + (e12 * KpY - KpL)
+    elif formulation == "exterior":
+        out[:, 0] = 0.5 * (1 + e12) * A_ * u[rows] - (KY - e12 * KL) + (VY - VL)
+        out[:, 1] = e12 * Wr + 0.5 * (1 + e12) * A_ * v[rows] + (e12 * KpY - KpL)
+    else:
+        raise ValueError(formulation)
+    return out

@@ -296,3 +296,25 @@ def test_bem2m_derivative_formulation_solve(bem2m):
     e_all = op32.energy(x, qxyz, q)
     _say(f"[bem 2M derivative] residual {r:.2e} energy {e_all:.4f} kcal/mol")
     assert e_all < 0
+
+
+@pytest.mark.parametrize("formulation", ["derivative", "exterior"])
+def test_bem2m_derivative_matvec_rows(bem2m, formulation):
+    """bem_matvec of the interior (eq:juffer) and exterior (eq:lu)
+    derivative formulations on the 2M-triangle mesh, bf16x3 as the
+    benchmark runs it, against oracle rows on 8 sampled triangles."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import BEMOperator
+    v, t, m, qxyz, q = bem2m
+    T = len(t)
+    op = BEMOperator(v, t, quad_pts=3, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=8, ncrit=128,
+                     precision="bf16x3", formulation=formulation)
+    rng = np.random.default_rng(94)
+    x = rng.standard_normal(2 * T)
+    y = op.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
+    rows = rng.choice(T, 8, replace=False)
+    ref = B.matvec_rows_derivative(m, rows, x, 4.0, 80.0, KAPPA,
+                                   formulation="interior" if formulation == "derivative" else "exterior")
+    e = _rel(np.stack([y[rows], y[T + rows]], axis=1), ref)
+    _say(f"[bem 2M {formulation} bf16x3] matvec rows {e:.2e}")
+    assert e < 1e-4

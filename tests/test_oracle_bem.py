@@ -287,3 +287,18 @@ def test_mass_preconditioned_spectra_and_iterations():
     it_j = _gmres_iterations(Aj, bem.rhs_derivative(m, qx, q, 4.0) / d)
     it_e = _gmres_iterations(Ae, bem.rhs_exterior(m, qx, q, 80.0) / d)
     assert it_e <= 0.6 * it_j, (it_e, it_j)
+
+
+@pytest.mark.parametrize("formulation", ["interior", "exterior"])
+def test_derivative_matvec_rows_equal_dense_rows(formulation):
+    """The row routine used at full size reproduces the dense derivative
+    systems (eq:juffer and eq:lu)."""
+    v, t = synth.octa_sphere(2, 4.0)
+    m = bem.make_mesh(v, t, 3)
+    A_ = (bem.system_derivative if formulation == "interior" else bem.system_exterior)(m, 4.0, 80.0, KAPPA)
+    x = np.random.default_rng(35).standard_normal(2 * len(t))
+    rows = np.array([0, 9, 64, 127])
+    got = bem.matvec_rows_derivative(m, rows, x, 4.0, 80.0, KAPPA, formulation=formulation)
+    ref = A_ @ x
+    np.testing.assert_allclose(got[:, 0], ref[rows], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(got[:, 1], ref[len(t) + rows], rtol=1e-10, atol=1e-12)
