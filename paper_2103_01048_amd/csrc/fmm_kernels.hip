@@ -1682,10 +1682,6 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t 
     FMM_HIP_TRY(hipGetLastError());
     prof_end(A, FMM_PHASE_M2M, ev, s);
   }
-  ev = prof_begin(A, FMM_PHASE_UC2E, s);
-  if ((rc = launch_gemm2<T>(A, LA.vs_u, W(A->cu), W(A->equ), B, &LB.vs_u, W(B->cu), W(B->equ), s))) return rc;
-  prof_end(A, FMM_PHASE_UC2E, ev, s);
-  if (up_done) FMM_HIP_TRY(hipEventRecord(up_done, s));
   ev = prof_begin(A, FMM_PHASE_M2L, s);
   if ((rc = launch_gemm2<T>(A, LA.m2l, W(A->cu), W(A->pairbuf), B, &LB.m2l, W(B->cu), W(B->pairbuf), s))) return rc;
   prof_end(A, FMM_PHASE_M2L, ev, s);
@@ -1697,6 +1693,13 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t 
                        (const int32_t *)B->d_m2l_rows);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_M2L_SUM, ev, s);
+  // upward equivalent densities of the M2P sources: needed only by the far
+  // field, so they go after the M2L, which heads the critical path (while
+  // the near field holds the GPU, the first pass launched after it waits)
+  ev = prof_begin(A, FMM_PHASE_UC2E, s);
+  if ((rc = launch_gemm2<T>(A, LA.vs_u, W(A->cu), W(A->equ), B, &LB.vs_u, W(B->cu), W(B->equ), s))) return rc;
+  prof_end(A, FMM_PHASE_UC2E, ev, s);
+  if (up_done) FMM_HIP_TRY(hipEventRecord(up_done, s));
   ev = prof_begin(A, FMM_PHASE_DC2E, s);
   if ((rc = launch_gemm2<T>(A, LA.ut_dx, W(A->chk), W(A->yd), B, &LB.ut_dx, W(B->chk), W(B->yd), s))) return rc;
   prof_end(A, FMM_PHASE_DC2E, ev, s);
