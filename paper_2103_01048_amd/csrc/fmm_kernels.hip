@@ -751,12 +751,18 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
 }
 
 // Sum of the parts of split tiles, in part order; one wave per tile.
+// blockIdx.y = 1 takes a second plan's parts and outputs (pair evaluation).
 template <typename T, int NR>
 __global__ __launch_bounds__(64) void k_leaf_parts(const int32_t *__restrict__ tiles, const int32_t *__restrict__ leaves,
                                                    const int32_t *__restrict__ box_begin,
-                                                   const int32_t *__restrict__ box_end, const T *__restrict__ parts,
-                                                   const int32_t *__restrict__ perm, int64_t N, T *__restrict__ pot,
-                                                   T *__restrict__ grad, T scale) {
+                                                   const int32_t *__restrict__ box_end, const T *__restrict__ parts0,
+                                                   const int32_t *__restrict__ perm, int64_t N, T *__restrict__ pot0,
+                                                   T *__restrict__ grad0, T scale, const T *__restrict__ parts1,
+                                                   T *__restrict__ pot1, T *__restrict__ grad1) {
+  const bool second = blockIdx.y != 0;
+  const T *__restrict__ parts = second ? parts1 : parts0;
+  T *__restrict__ pot = second ? pot1 : pot0;
+  T *__restrict__ grad = second ? grad1 : grad0;
   const int slot = tiles[4 * blockIdx.x], code = tiles[4 * blockIdx.x + 1];
   const int p0 = tiles[4 * blockIdx.x + 2], np = tiles[4 * blockIdx.x + 3];
   const int split = code >> 24;
@@ -1733,8 +1739,9 @@ static int eval_chunk(fmm_plan *P, const T *q, T *pot, T *grad, hipStream_t s) {
                        D.near_off, D.near_rng, (const T *)D.near_o, D.far_off, D.far_idx, (const T *)D.far_o, equ,
                        eqd, (T *)D.parts, D.perm, pot, grad, kappa, scale);
   if (D.nsplit > 0)
-    hipLaunchKernelGGL((k_leaf_parts<T, NR>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
-                       D.box_end, (const T *)D.parts, D.perm, N, pot, grad, scale);
+    hipLaunchKernelGGL((k_leaf_parts<T, NR>), dim3(D.nsplit, 1), dim3(64), 0, s, D.split_tiles, D.leaves,
+                       D.box_begin, D.box_end, (const T *)D.parts, D.perm, N, pot, grad, scale, (const T *)nullptr,
+                       (T *)nullptr, (T *)nullptr);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(P, FMM_PHASE_LEAF, ev, s);
   return FMM_OK;
@@ -1815,10 +1822,9 @@ static int eval_pair_chunk(fmm_plan *A, fmm_plan *B, const T *q, T *pot_a, T *gr
                        (const T *)B->eqd, (T *)D.parts, (T *)B->dt.parts, D.perm, pot_a, grad_a, pot_b, grad_b, kappa,
                        scale);
   if (D.nsplit > 0) {
-    hipLaunchKernelGGL((k_leaf_parts<T, NR>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
-                       D.box_end, (const T *)D.parts, D.perm, N, pot_a, grad_a, scale);
-    hipLaunchKernelGGL((k_leaf_parts<T, NR>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
-                       D.box_end, (const T *)B->dt.parts, D.perm, N, pot_b, grad_b, scale);
+    hipLaunchKernelGGL((k_leaf_parts<T, NR>), dim3(D.nsplit, 2), dim3(64), 0, s, D.split_tiles, D.leaves,
+                       D.box_begin, D.box_end, (const T *)D.parts, D.perm, N, pot_a, grad_a, scale,
+                       (const T *)B->dt.parts, pot_b, grad_b);
   }
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_FAR, ev, s);
@@ -1919,10 +1925,9 @@ static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip
                        (const T *)B->eqd, (T *)D.parts, (T *)B->dt.parts, D.perm, pot_a, (T *)nullptr, pot_b,
                        (T *)nullptr, kappa, scale);
   if (D.nsplit > 0) {
-    hipLaunchKernelGGL((k_leaf_parts<T, 1>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
-                       D.box_end, (const T *)D.parts, D.perm, N, pot_a, grad_a, scale);
-    hipLaunchKernelGGL((k_leaf_parts<T, 1>), dim3(D.nsplit), dim3(64), 0, s, D.split_tiles, D.leaves, D.box_begin,
-                       D.box_end, (const T *)B->dt.parts, D.perm, N, pot_b, grad_b, scale);
+    hipLaunchKernelGGL((k_leaf_parts<T, 1>), dim3(D.nsplit, 2), dim3(64), 0, s, D.split_tiles, D.leaves,
+                       D.box_begin, D.box_end, (const T *)D.parts, D.perm, N, pot_a, grad_a, scale,
+                       (const T *)B->dt.parts, pot_b, grad_b);
   }
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_FAR, ev, s);
