@@ -950,7 +950,7 @@ int ensure_lists(fmm_plan *P, int nr) {
   L.ut_u_all = GemmBatch(); L.vs_u = GemmBatch(); L.ut_dx = GemmBatch(); L.vs_d = GemmBatch(); L.m2l = GemmBatch();
   L.ut_u_all.nrb = maxru / 16; L.ut_u_all.klen = ld;
   L.vs_u.nrb = ld / 16; L.vs_u.klen = maxru;
-  L.ut_dx.nrb = maxrd / 16; L.ut_dx.klen = ld; L.ut_dx.mode = GEMM_ADD;
+  L.ut_dx.nrb = maxrd / 16; L.ut_dx.klen = ld;
   L.vs_d.nrb = ld / 16; L.vs_d.klen = maxrd;
   L.m2l.nrb = maxrd / 16; L.m2l.klen = maxru; L.m2l.ldy = pair_ld(P);
   if (P->precision == FMM_FP32_BF16X3) {
@@ -1109,13 +1109,14 @@ static uint64_t tree_fingerprint(const fmm_plan *P) {
 
 // Resources of a pair evaluation (A: Laplace half, B: Yukawa half): A's side
 // stream (default priority) that runs both kernels' passes, A's fork and join
-// events, B's event marking the end of the surface passes, and A's buffer of
-// near-field running sums for nr columns.
+// events, B's events marking the end of the surface passes and of the P2L
+// projections, and A's buffer of near-field running sums for nr columns.
 int ensure_pair(fmm_plan *A, fmm_plan *B, int nr) {
   if (!A->aux) FMM_HIP_TRY(hipStreamCreateWithFlags(&A->aux, hipStreamNonBlocking));
   if (!A->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_fork, hipEventDisableTiming));
   if (!A->ev_join) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_join, hipEventDisableTiming));
   if (!B->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+  if (!B->ev_join) FMM_HIP_TRY(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
   const size_t es = A->precision == FMM_FP64 ? 8 : 4;
   const size_t need = std::max<size_t>(1, (size_t)A->dt.nitems) * 2 * nr * 4 * 64 * es;
   if (A->pair_acc_bytes < need) {
@@ -1148,6 +1149,7 @@ int ensure_work(fmm_plan *P, int nr) {
   if ((rc = dev_alloc(P, &P->cu, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->yd, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->mslot, wbytes))) return rc;
+  if ((rc = dev_alloc(P, &P->ydx, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->pairbuf, (size_t)std::max<int64_t>(1, P->dt.nvpair) * nr * pair_ld(P) * es))) return rc;
   // padding rows/columns must hold zeros (the GEMM K dimension reads them)
   FMM_HIP_TRY(hipMemset(P->equ, 0, wbytes));
@@ -1156,6 +1158,8 @@ int ensure_work(fmm_plan *P, int nr) {
   FMM_HIP_TRY(hipMemset(P->chku, 0, wbytes));
   FMM_HIP_TRY(hipMemset(P->cu, 0, wbytes));
   FMM_HIP_TRY(hipMemset(P->yd, 0, wbytes));
+  // rows of boxes without an X list stay zero: the M2L sums add this array
+  FMM_HIP_TRY(hipMemset(P->ydx, 0, wbytes));
   P->work_nr = nr;
   return FMM_OK;
 }

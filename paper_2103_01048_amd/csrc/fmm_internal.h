@@ -91,7 +91,7 @@ struct PassLists {
   GemmBatch ut_u_all;           // leaf upward check -> c_u, all levels
   std::vector<GemmBatch> l2l;   // child c_d += L2L * parent c_d (levels >= 3)
   GemmBatch vs_u;               // c_u -> upward equivalent (M2P sources), all levels
-  GemmBatch ut_dx;              // P2L check -> c_d (added), all levels
+  GemmBatch ut_dx;              // P2L check -> its own c_d array (added by the M2L sums), all levels
   GemmBatch vs_d;               // c_d -> downward equivalent (leaves), all levels
   GemmBatch m2l;                // all levels, c_u -> pair slots of c_d
 };
@@ -173,7 +173,7 @@ struct fmm_plan {
   // work arrays, sized for work_nr columns
   int work_nr = 0;
   void *qs = nullptr, *equ = nullptr, *chk = nullptr, *eqd = nullptr, *chku = nullptr,
-       *cu = nullptr, *yd = nullptr, *pairbuf = nullptr, *mslot = nullptr;
+       *cu = nullptr, *yd = nullptr, *pairbuf = nullptr, *mslot = nullptr, *ydx = nullptr;
   // cu: upward check in singular coordinates (U_u^T chk); yd: downward
   // check in singular coordinates (M2L sums + U_d^T chk)
   fmm::PassLists lists_by_nr[fmm::MAX_NR + 1];  // task lists per column count

@@ -1413,7 +1413,8 @@ __global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ 
                                                     T *__restrict__ y0, int nr, int ld, int ldp0, int rows0,
                                                     const T *__restrict__ pairbuf1, T *__restrict__ y1, int ldp1,
                                                     int rows1, const int32_t *__restrict__ brows0,
-                                                    const int32_t *__restrict__ brows1) {
+                                                    const int32_t *__restrict__ brows1, const T *__restrict__ add0,
+                                                    const T *__restrict__ add1) {
   __builtin_amdgcn_s_setprio(3);
   using V4 = typename Vec4<T>::type;
   const bool second = blockIdx.y != 0;
@@ -1421,6 +1422,9 @@ __global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ 
   T *__restrict__ y = second ? y1 : y0;
   const int ldp = second ? ldp1 : ldp0, rows = second ? rows1 : rows0;
   const int32_t *__restrict__ brows = second ? brows1 : brows0;
+  // add (may be null): a per-box array added after the sum (the M2L sums
+  // take the P2L projections this way)
+  const V4 *__restrict__ add = reinterpret_cast<const V4 *>(second ? add1 : add0);
   const int slot = blockIdx.x;
   const int b = tgt[slot];
   const int p0 = off[slot], p1 = off[slot + 1];
@@ -1432,7 +1436,8 @@ __global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ 
   for (int e = threadIdx.x; e < nr * rq; e += 64) {
     const int r = e / rq, i = e - r * rq;
     if (i >= bq) {
-      reinterpret_cast<V4 *>(y)[((int64_t)b * nr + r) * lq + i] = V4{0, 0, 0, 0};
+      reinterpret_cast<V4 *>(y)[((int64_t)b * nr + r) * lq + i] =
+          add ? add[((int64_t)b * nr + r) * lq + i] : V4{0, 0, 0, 0};
       continue;
     }
     // four independent partial sums (pairs p0 + 4k + j go to sum j) keep
@@ -1448,7 +1453,9 @@ __global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ 
     if (p < p1) a0 += pb[((int64_t)pairs[p] * nr + r) * pq + i];
     if (p + 1 < p1) a1 += pb[((int64_t)pairs[p + 1] * nr + r) * pq + i];
     if (p + 2 < p1) a2 += pb[((int64_t)pairs[p + 2] * nr + r) * pq + i];
-    reinterpret_cast<V4 *>(y)[((int64_t)b * nr + r) * lq + i] = (a0 + a1) + (a2 + a3);
+    V4 sum = (a0 + a1) + (a2 + a3);
+    if (add) sum = sum + add[((int64_t)b * nr + r) * lq + i];
+    reinterpret_cast<V4 *>(y)[((int64_t)b * nr + r) * lq + i] = sum;
   }
 }
 
@@ -1583,7 +1590,7 @@ static int eval_passes(fmm_plan *P, hipStream_t s) {
     if ((rc = launch_gemm<T>(P, L.m2m[l], cu, (T *)P->mslot, s))) return rc;
     hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.m2m_n[l]), dim3(64), 0, s, D.m2m_tgt[l], D.m2m_off[l], D.m2m_kid[l],
                        (const T *)P->mslot, cu, NR, ld, ld, L.m2m[l].nrb * 16, (const T *)nullptr, (T *)nullptr, 0, 0,
-                       (const int32_t *)nullptr, (const int32_t *)nullptr);
+                       (const int32_t *)nullptr, (const int32_t *)nullptr, (const T *)nullptr, (const T *)nullptr);
     FMM_HIP_TRY(hipGetLastError());
     prof_end(P, FMM_PHASE_M2M, ev, s);
   }
@@ -1598,6 +1605,10 @@ static int eval_passes(fmm_plan *P, hipStream_t s) {
                        (const T *)P->surf, P->nsurf, ld, (T)ALPHA_DC, chk, 0, kappa);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(P, FMM_PHASE_P2L, ev, s);
+  // the P2L checks' projections go to their own array, added by the M2L sums
+  ev = prof_begin(P, FMM_PHASE_DC2E, s);
+  if ((rc = launch_gemm<T>(P, L.ut_dx, chk, (T *)P->ydx, s))) return rc;
+  prof_end(P, FMM_PHASE_DC2E, ev, s);
   // M2L between singular coordinates into pair slots (rows of the largest
   // downward rank, not of the surface size), then a fixed-order sum per
   // target box (every box at level >= 2)
@@ -1608,12 +1619,10 @@ static int eval_passes(fmm_plan *P, hipStream_t s) {
   if (D.nvbox > 0)
     hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.nvbox), dim3(64), 0, s, D.v_tgt, D.v_off, D.v_pair,
                        (const T *)P->pairbuf, yd, NR, ld, L.m2l.ldy, L.m2l.nrb * 16, (const T *)nullptr, (T *)nullptr,
-                       0, 0, (const int32_t *)P->d_m2l_rows, (const int32_t *)nullptr);
+                       0, 0, (const int32_t *)P->d_m2l_rows, (const int32_t *)nullptr, (const T *)P->ydx,
+                       (const T *)nullptr);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(P, FMM_PHASE_M2L_SUM, ev, s);
-  ev = prof_begin(P, FMM_PHASE_DC2E, s);
-  if ((rc = launch_gemm<T>(P, L.ut_dx, chk, yd, s))) return rc;
-  prof_end(P, FMM_PHASE_DC2E, ev, s);
   // downward pass: L2L between singular coordinates, coarsest level first
   for (int l = 3; l <= D.maxlevel; ++l) {
     if (L.l2l[l].ntask) {
@@ -1633,7 +1642,7 @@ static int eval_passes(fmm_plan *P, hipStream_t s) {
 // two surface-evaluation passes (P2M, P2L; VALU work) come first and
 // `surf_done` is recorded after them; the GEMM passes follow.
 template <typename T, int NR>
-static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t surf_done,
+static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, hipEvent_t surf_done,
                             hipEvent_t up_done, const T *dips = nullptr) {
   const DevTree &D = A->dt;
   const int64_t N = A->n;
@@ -1645,6 +1654,8 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t 
   int rc;
   hipEvent_t ev;
   if (D.maxlevel < 2) return FMM_OK;
+  if (part == 2) goto down;
+  {
   const unsigned sthreads = (unsigned)(64 * ((A->nsurf + 63) / 64));
   ev = prof_begin(A, FMM_PHASE_P2M, s);
   if (A->p2m_count > 0 && dips)
@@ -1684,19 +1695,24 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t 
     hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.m2m_n[l], 2), dim3(64), 0, s, D.m2m_tgt[l], D.m2m_off[l],
                        D.m2m_kid[l], (const T *)A->mslot, W(A->cu), NR, ld, ld, LA.m2m[l].nrb * 16,
                        (const T *)B->mslot, W(B->cu), ld, LB.m2m[l].nrb * 16, (const int32_t *)nullptr,
-                       (const int32_t *)nullptr);
+                       (const int32_t *)nullptr, (const T *)nullptr, (const T *)nullptr);
     FMM_HIP_TRY(hipGetLastError());
     prof_end(A, FMM_PHASE_M2M, ev, s);
   }
   ev = prof_begin(A, FMM_PHASE_M2L, s);
   if ((rc = launch_gemm2<T>(A, LA.m2l, W(A->cu), W(A->pairbuf), B, &LB.m2l, W(B->cu), W(B->pairbuf), s))) return rc;
   prof_end(A, FMM_PHASE_M2L, ev, s);
+  }
+  if (part == 1) return FMM_OK;
+down:
+  // the M2L sums add the P2L projections (`ydx`, computed on another stream
+  // by pair_p2l_projection and waited for by the caller)
   ev = prof_begin(A, FMM_PHASE_M2L_SUM, s);
   if (D.nvbox > 0)
     hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.nvbox, 2), dim3(64), 0, s, D.v_tgt, D.v_off, D.v_pair,
                        (const T *)A->pairbuf, W(A->yd), NR, ld, LA.m2l.ldy, LA.m2l.nrb * 16, (const T *)B->pairbuf,
                        W(B->yd), LB.m2l.ldy, LB.m2l.nrb * 16, (const int32_t *)A->d_m2l_rows,
-                       (const int32_t *)B->d_m2l_rows);
+                       (const int32_t *)B->d_m2l_rows, (const T *)A->ydx, (const T *)B->ydx);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_M2L_SUM, ev, s);
   // upward equivalent densities of the M2P sources: needed only by the far
@@ -1706,9 +1722,6 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, hipEvent_t 
   if ((rc = launch_gemm2<T>(A, LA.vs_u, W(A->cu), W(A->equ), B, &LB.vs_u, W(B->cu), W(B->equ), s))) return rc;
   prof_end(A, FMM_PHASE_UC2E, ev, s);
   if (up_done) FMM_HIP_TRY(hipEventRecord(up_done, s));
-  ev = prof_begin(A, FMM_PHASE_DC2E, s);
-  if ((rc = launch_gemm2<T>(A, LA.ut_dx, W(A->chk), W(A->yd), B, &LB.ut_dx, W(B->chk), W(B->yd), s))) return rc;
-  prof_end(A, FMM_PHASE_DC2E, ev, s);
   for (int l = 3; l <= D.maxlevel; ++l) {
     if (!LA.l2l[l].ntask) continue;
     ev = prof_begin(A, FMM_PHASE_L2L, s);
@@ -1786,6 +1799,46 @@ int ensure_pair(fmm_plan *A, fmm_plan *B, int nr);  // host: side streams, event
 // (B's fork event marks the end of the surface passes.)  Measured on the
 // 393k-point workload: 1.64 ms per pair against 1.70 ms with no overlap and
 // 1.66 ms with the near field started at once.
+// The P2L checks' projections of both plans into their own arrays, on
+// stream s after the near field (the M2L sums on the side stream add them):
+// off the side stream's chain, which bounds the step.
+template <typename T, int NR>
+static int pair_p2l_projection(fmm_plan *A, fmm_plan *B, hipStream_t s) {
+  const PassLists &LA = A->lists_by_nr[NR], &LB = B->lists_by_nr[NR];
+  hipEvent_t ev = prof_begin(A, FMM_PHASE_DC2E, s);
+  int rc = launch_gemm2<T>(A, LA.ut_dx, (const T *)A->chk, (T *)A->ydx, B, &LB.ut_dx, (const T *)B->chk, (T *)B->ydx, s);
+  if (rc) return rc;
+  prof_end(A, FMM_PHASE_DC2E, ev, s);
+  return FMM_OK;
+}
+
+// Fork and join of a pair evaluation around the near-field launch `near`:
+//   side stream: surface passes | upward GEMMs, M2L      | wait P2L | M2L sums, downward GEMMs
+//   stream s:    wait surfaces  | near field, P2L proj.  | wait side stream | far field
+template <typename T, int NR, typename Near>
+static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips, Near near) {
+  int rc;
+  const bool far = A->dt.maxlevel >= 2;
+  if (far) {
+    FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
+    FMM_HIP_TRY(hipStreamWaitEvent(A->aux, A->ev_fork, 0));
+    if ((rc = eval_passes_pair<T, NR>(A, B, A->aux, 1, B->ev_fork, nullptr, dips))) return rc;
+    // the near field starts once the two surface passes (VALU, like the near
+    // field) are done, and shares the GPU with the GEMM passes
+    FMM_HIP_TRY(hipStreamWaitEvent(s, B->ev_fork, 0));
+  }
+  if ((rc = near())) return rc;
+  if (far) {
+    if ((rc = pair_p2l_projection<T, NR>(A, B, s))) return rc;
+    FMM_HIP_TRY(hipEventRecord(B->ev_join, s));
+    FMM_HIP_TRY(hipStreamWaitEvent(A->aux, B->ev_join, 0));
+    if ((rc = eval_passes_pair<T, NR>(A, B, A->aux, 2, nullptr, nullptr, dips))) return rc;
+    FMM_HIP_TRY(hipEventRecord(A->ev_join, A->aux));
+    FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
+  }
+  return FMM_OK;
+}
+
 template <typename T, int NR>
 static int eval_pair_chunk(fmm_plan *A, fmm_plan *B, const T *q, T *pot_a, T *grad_a, T *pot_b, T *grad_b,
                            hipStream_t s) {
@@ -1793,28 +1846,21 @@ static int eval_pair_chunk(fmm_plan *A, fmm_plan *B, const T *q, T *pot_a, T *gr
   const int64_t N = A->n;
   int rc;
   if ((rc = eval_permute<T, NR>(A, q, s))) return rc;
-  const bool far = D.maxlevel >= 2;
-  if (far) {
-    FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
-    FMM_HIP_TRY(hipStreamWaitEvent(A->aux, A->ev_fork, 0));
-    if ((rc = eval_passes_pair<T, NR>(A, B, A->aux, B->ev_fork, nullptr))) return rc;
-    FMM_HIP_TRY(hipEventRecord(A->ev_join, A->aux));
-    // the near field starts once the two surface passes (VALU, like the near
-    // field) are done, and shares the GPU with the GEMM passes
-    FMM_HIP_TRY(hipStreamWaitEvent(s, B->ev_fork, 0));
-  }
   const T kappa = (T)B->kappa;
   const T scale = (T)(1.0 / (4.0 * M_PI));
   T *acc = (T *)A->pair_acc;
-  hipEvent_t ev = prof_begin(A, FMM_PHASE_NEAR, s);
-  if (D.nitems > 0)
-    hipLaunchKernelGGL((k_near_pair<T, NR>), dim3(D.nitems), dim3(64), 0, s, D.items,
-                       D.leaves, (const T *)D.pts, (const T *)A->qs, N, D.box_begin, D.box_end, D.near_off,
-                       D.near_rng, (const T *)D.near_o, acc, kappa, D.nitems);
-  FMM_HIP_TRY(hipGetLastError());
-  prof_end(A, FMM_PHASE_NEAR, ev, s);
-  if (far) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
-  ev = prof_begin(A, FMM_PHASE_FAR, s);
+  auto near = [&]() -> int {
+    hipEvent_t e = prof_begin(A, FMM_PHASE_NEAR, s);
+    if (D.nitems > 0)
+      hipLaunchKernelGGL((k_near_pair<T, NR>), dim3(D.nitems), dim3(64), 0, s, D.items,
+                         D.leaves, (const T *)D.pts, (const T *)A->qs, N, D.box_begin, D.box_end, D.near_off,
+                         D.near_rng, (const T *)D.near_o, acc, kappa, D.nitems);
+    FMM_HIP_TRY(hipGetLastError());
+    prof_end(A, FMM_PHASE_NEAR, e, s);
+    return FMM_OK;
+  };
+  if ((rc = pair_fork_join<T, NR>(A, B, s, (const T *)nullptr, near))) return rc;
+  hipEvent_t ev = prof_begin(A, FMM_PHASE_FAR, s);
   if (D.nitems > 0)
     hipLaunchKernelGGL((k_far_pair<T, NR, true>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts, N,
                        D.box_begin, D.box_end, (const T *)A->surf, A->nsurf, A->ld, D.far_off, D.far_idx,
@@ -1885,32 +1931,26 @@ static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip
                      (T *)D.pts, dips);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_PERMUTE, ev, s);
-  const bool far = D.maxlevel >= 2;
-  if (far) {
-    FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
-    FMM_HIP_TRY(hipStreamWaitEvent(A->aux, A->ev_fork, 0));
-    if ((rc = eval_passes_pair<T, 1>(A, B, A->aux, B->ev_fork, nullptr, dips))) return rc;
-    FMM_HIP_TRY(hipEventRecord(A->ev_join, A->aux));
-    FMM_HIP_TRY(hipStreamWaitEvent(s, B->ev_fork, 0));
-  }
   const T kappa = (T)B->kappa;
   const T scale = (T)(1.0 / (4.0 * M_PI));
   T *acc = (T *)A->pair_acc;
-  ev = prof_begin(A, FMM_PHASE_NEAR, s);
-  if (D.nitems > 0)
-  {
-    if (grad)
-      hipLaunchKernelGGL((k_near_pair_md<T, true>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
-                         (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
-                         (const T *)D.near_o, acc, kappa, D.nitems);
-    else
-      hipLaunchKernelGGL((k_near_pair_md<T, false>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
-                         (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
-                         (const T *)D.near_o, acc, kappa, D.nitems);
-  }
-  FMM_HIP_TRY(hipGetLastError());
-  prof_end(A, FMM_PHASE_NEAR, ev, s);
-  if (far) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
+  auto near = [&]() -> int {
+    hipEvent_t e = prof_begin(A, FMM_PHASE_NEAR, s);
+    if (D.nitems > 0) {
+      if (grad)
+        hipLaunchKernelGGL((k_near_pair_md<T, true>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
+                           (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
+                           (const T *)D.near_o, acc, kappa, D.nitems);
+      else
+        hipLaunchKernelGGL((k_near_pair_md<T, false>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
+                           (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
+                           (const T *)D.near_o, acc, kappa, D.nitems);
+    }
+    FMM_HIP_TRY(hipGetLastError());
+    prof_end(A, FMM_PHASE_NEAR, e, s);
+    return FMM_OK;
+  };
+  if ((rc = pair_fork_join<T, 1>(A, B, s, (const T *)dips, near))) return rc;
   ev = prof_begin(A, FMM_PHASE_FAR, s);
   if (D.nitems > 0 && grad)
     hipLaunchKernelGGL((k_far_pair<T, 1, true>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves, (const T *)D.pts,
