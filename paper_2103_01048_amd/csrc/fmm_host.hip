@@ -1109,12 +1109,14 @@ static uint64_t tree_fingerprint(const fmm_plan *P) {
 
 // Resources of a pair evaluation (A: Laplace half, B: Yukawa half): A's side
 // stream (default priority) that runs both kernels' passes, A's fork and join
-// events, B's events marking the end of the surface passes and of the P2L
-// projections, and A's buffer of near-field running sums for nr columns.
+// events and its event marking the end of the upward pass, B's events marking
+// the end of the surface passes and of the P2L projections, and A's buffer of
+// near-field running sums for nr columns.
 int ensure_pair(fmm_plan *A, fmm_plan *B, int nr) {
   if (!A->aux) FMM_HIP_TRY(hipStreamCreateWithFlags(&A->aux, hipStreamNonBlocking));
   if (!A->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_fork, hipEventDisableTiming));
   if (!A->ev_join) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_join, hipEventDisableTiming));
+  if (!A->ev_up) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_up, hipEventDisableTiming));
   if (!B->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
   if (!B->ev_join) FMM_HIP_TRY(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
   const size_t es = A->precision == FMM_FP64 ? 8 : 4;
@@ -1480,6 +1482,7 @@ void fmm_free(fmm_plan *P) {
   }
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+  if (P->ev_up) (void)hipEventDestroy(P->ev_up);
   for (void *p : P->allocs) (void)hipFree(p);
   delete P;
 }

@@ -190,7 +190,7 @@ struct fmm_plan {
   // pair evaluation (this plan as the Laplace half): side stream, fork and
   // join events, and the near-field running sums of both kernels
   hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_up = nullptr;
   void *pair_acc = nullptr;
   size_t pair_acc_bytes = 0;
   void *dips = nullptr;             // monopole + dipole sources: dipole records in Morton order

@@ -1699,6 +1699,7 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, h
     FMM_HIP_TRY(hipGetLastError());
     prof_end(A, FMM_PHASE_M2M, ev, s);
   }
+  if (up_done) FMM_HIP_TRY(hipEventRecord(up_done, s));
   ev = prof_begin(A, FMM_PHASE_M2L, s);
   if ((rc = launch_gemm2<T>(A, LA.m2l, W(A->cu), W(A->pairbuf), B, &LB.m2l, W(B->cu), W(B->pairbuf), s))) return rc;
   prof_end(A, FMM_PHASE_M2L, ev, s);
@@ -1715,13 +1716,6 @@ down:
                        (const int32_t *)B->d_m2l_rows, (const T *)A->ydx, (const T *)B->ydx);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_M2L_SUM, ev, s);
-  // upward equivalent densities of the M2P sources: needed only by the far
-  // field, so they go after the M2L, which heads the critical path (while
-  // the near field holds the GPU, the first pass launched after it waits)
-  ev = prof_begin(A, FMM_PHASE_UC2E, s);
-  if ((rc = launch_gemm2<T>(A, LA.vs_u, W(A->cu), W(A->equ), B, &LB.vs_u, W(B->cu), W(B->equ), s))) return rc;
-  prof_end(A, FMM_PHASE_UC2E, ev, s);
-  if (up_done) FMM_HIP_TRY(hipEventRecord(up_done, s));
   for (int l = 3; l <= D.maxlevel; ++l) {
     if (!LA.l2l[l].ntask) continue;
     ev = prof_begin(A, FMM_PHASE_L2L, s);
@@ -1799,22 +1793,30 @@ int ensure_pair(fmm_plan *A, fmm_plan *B, int nr);  // host: side streams, event
 // (B's fork event marks the end of the surface passes.)  Measured on the
 // 393k-point workload: 1.64 ms per pair against 1.70 ms with no overlap and
 // 1.66 ms with the near field started at once.
-// The P2L checks' projections of both plans into their own arrays, on
-// stream s after the near field (the M2L sums on the side stream add them):
-// off the side stream's chain, which bounds the step.
+// The P2L checks' projections of both plans into their own arrays (the M2L
+// sums on the side stream add them), and, once the upward pass is done, the
+// M2P sources' equivalent densities (only the far field reads them): on
+// stream s after the near field, off the side stream's chain, which bounds
+// the step.
 template <typename T, int NR>
-static int pair_p2l_projection(fmm_plan *A, fmm_plan *B, hipStream_t s) {
+static int pair_off_chain(fmm_plan *A, fmm_plan *B, hipStream_t s) {
   const PassLists &LA = A->lists_by_nr[NR], &LB = B->lists_by_nr[NR];
   hipEvent_t ev = prof_begin(A, FMM_PHASE_DC2E, s);
   int rc = launch_gemm2<T>(A, LA.ut_dx, (const T *)A->chk, (T *)A->ydx, B, &LB.ut_dx, (const T *)B->chk, (T *)B->ydx, s);
   if (rc) return rc;
   prof_end(A, FMM_PHASE_DC2E, ev, s);
+  FMM_HIP_TRY(hipEventRecord(B->ev_join, s));
+  FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_up, 0));
+  ev = prof_begin(A, FMM_PHASE_UC2E, s);
+  if ((rc = launch_gemm2<T>(A, LA.vs_u, (const T *)A->cu, (T *)A->equ, B, &LB.vs_u, (const T *)B->cu, (T *)B->equ, s)))
+    return rc;
+  prof_end(A, FMM_PHASE_UC2E, ev, s);
   return FMM_OK;
 }
 
 // Fork and join of a pair evaluation around the near-field launch `near`:
-//   side stream: surface passes | upward GEMMs, M2L      | wait P2L | M2L sums, downward GEMMs
-//   stream s:    wait surfaces  | near field, P2L proj.  | wait side stream | far field
+//   side stream: surface passes | upward GEMMs, M2L            | wait P2L | M2L sums, downward GEMMs
+//   stream s:    wait surfaces  | near field, P2L proj., M2P eq. | wait side stream | far field
 template <typename T, int NR, typename Near>
 static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips, Near near) {
   int rc;
@@ -1822,15 +1824,14 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   if (far) {
     FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
     FMM_HIP_TRY(hipStreamWaitEvent(A->aux, A->ev_fork, 0));
-    if ((rc = eval_passes_pair<T, NR>(A, B, A->aux, 1, B->ev_fork, nullptr, dips))) return rc;
+    if ((rc = eval_passes_pair<T, NR>(A, B, A->aux, 1, B->ev_fork, A->ev_up, dips))) return rc;
     // the near field starts once the two surface passes (VALU, like the near
     // field) are done, and shares the GPU with the GEMM passes
     FMM_HIP_TRY(hipStreamWaitEvent(s, B->ev_fork, 0));
   }
   if ((rc = near())) return rc;
   if (far) {
-    if ((rc = pair_p2l_projection<T, NR>(A, B, s))) return rc;
-    FMM_HIP_TRY(hipEventRecord(B->ev_join, s));
+    if ((rc = pair_off_chain<T, NR>(A, B, s))) return rc;
     FMM_HIP_TRY(hipStreamWaitEvent(A->aux, B->ev_join, 0));
     if ((rc = eval_passes_pair<T, NR>(A, B, A->aux, 2, nullptr, nullptr, dips))) return rc;
     FMM_HIP_TRY(hipEventRecord(A->ev_join, A->aux));
