@@ -185,3 +185,21 @@ def test_expansion_order_digits_fp64(kernel):
     print(f"[digits {kernel}] " + " ".join(f"p={p}:{e:.1e}" for p, e in errs.items()), flush=True)
     assert errs[4] < 1e-3 and errs[5] < 1e-4 and errs[10] < 1e-8
     assert errs[4] > errs[6] > errs[8] > errs[10]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_lowest_expansion_orders(precision):
+    """p = 2 and 3 (8 and 26 surface points) run on every path, and the
+    error falls from p = 2 to 3 to 4."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan
+    x, q = synth.unit_sphere_cloud(4000, seed=142)
+    phi, _ = D.direct(x, x, q, "yukawa", 0.125)
+    errs = []
+    for p in (2, 3, 4):
+        plan = FMMPlan(torch.tensor(x, device="cuda"), kernel="yukawa", kappa=0.125, p=p, ncrit=32,
+                       precision=precision)
+        pot, _ = plan.eval(torch.tensor(q, device="cuda"))
+        errs.append(D.rel_l2(pot.double().cpu().numpy(), phi))
+    print(f"[low p {precision}] {errs}", flush=True)
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-2
