@@ -1518,7 +1518,13 @@ static int launch_gemm2(fmm_plan *P, const GemmBatch &bt, const T *X, T *Y, fmm_
   const int nrb = std::max(g0.nrb, g1.ntask ? g1.nrb : 0);
   // Small launches (few column tiles) split the row blocks over a second grid
   // dimension so that more workgroups share the work.
-  const int rbw = g0.ntask + g1.ntask >= 1024 ? (nrb + 3) / 4 : 1;
+  int rbw = g0.ntask + g1.ntask >= 1024 ? (nrb + 3) / 4 : 1;
+  // FP64: at most two row blocks per wave (more y-groups, fewer registers,
+  // more resident waves); measured on the FP64 pair evaluation: 2 -> 59.5,
+  // 3 -> 54.7, 4 -> 44.5, 5 (the one-group default at p = 8) -> 53.5
+  // Mpoints/s, 1 -> 47.0.  Single precision keeps one group of up to 8
+  // (two blocks per wave cost 3% there).
+  if (std::is_same<T, double>::value) rbw = std::min(rbw, 2);
   const int KB = P->bf_kb;
   switch (rbw) {
     case 1: launch_gemm_rbw<T, 1>(g0, g1, bf3, KB, s); break;
