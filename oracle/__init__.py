@@ -11,6 +11,9 @@ Contents
   analytic  -- Born ion and Kirkwood sphere solvation energies (closed forms)
   tree      -- adaptive octree, Morton keys and the U/V/W/X interaction lists
   kifmm     -- the kernel-independent FMM, pass by pass, in FP64
-  bem       -- dense P0 Galerkin boundary-element operators, direct formulation,
-               reaction potential and solvation energy
+  bem       -- dense P0 Galerkin boundary-element operators: direct, interior
+               and exterior derivative formulations, reaction potential and
+               solvation energy
+  bem_p1    -- dense P1 (piecewise-linear) operators and the exterior
+               derivative formulation on them, lumped-mass preconditioner
 """
