@@ -250,6 +250,18 @@ void fmm_free(fmm_plan *plan);
  *   [ e12 (W_Y - W_L)                   (1 + e12)/2 M + e12 K'_Y - K'_L  ] [v] = [b'],
  *   b and b' with 1/eps_out in place of 1/eps_in.
  *
+ * FMM_BEM_EXTERIOR_P1: the exterior formulation on continuous piecewise-
+ *   linear elements (Results: the exterior variant with P1 elements and
+ *   mass-matrix preconditioning).  Unknowns per VERTEX (u = phi_2, v =
+ *   d phi_2/dn at each vertex; vectors of 2*nv doubles, every vertex on a
+ *   triangle); the hat function of a vertex is the barycentric coordinate of
+ *   its corner on each triangle.  Quadrature-point densities interpolate the
+ *   vertex values; test integrals weight by the hat functions and are added
+ *   per vertex in a fixed order; M is the P1 mass matrix (A/12 (1 + delta_ab)
+ *   per triangle); the S - C corrections are 3 x 3 blocks per pair with the
+ *   Laplace inner integral of a linear density in closed form.  Only the
+ *   lumped mass preconditioner (FMM_BEM_PRECOND_MASS) applies.
+ *
  * V and K are the single- and double-layer operators of the Laplace (L) and
  * Yukawa (Y) kernels.  G is evaluated by one fmm_eval_pair_md call per
  * product (charges W v and dipoles W u n at the regular quadrature points;
@@ -260,11 +272,13 @@ void fmm_free(fmm_plan *plan);
  * Yukawa-minus-Laplace remainders; K' uses the transposed K pair), applied
  * as one precomputed sparse FP64 matrix S - C.
  * ------------------------------------------------------------------------ */
-enum { FMM_BEM_DIRECT = 0, FMM_BEM_DERIVATIVE = 1, FMM_BEM_EXTERIOR = 2 };
+enum { FMM_BEM_DIRECT = 0, FMM_BEM_DERIVATIVE = 1, FMM_BEM_EXTERIOR = 2, FMM_BEM_EXTERIOR_P1 = 3 };
 /* Preconditioners (Results, the preconditioners of the two formulation
  * families): per-triangle 2 x 2 block-diagonal (the inverse of A's block on
- * the identical pair, after Altman and co-workers) or the mass matrix
- * diag(M, M) (diagonal for P0 elements, so mass lumping is exact). */
+ * the identical pair, after Altman and co-workers; P0 only) or the mass
+ * matrix diag(M, M) (diagonal for P0 elements, so mass lumping is exact; for
+ * P1 elements its lumped form, per vertex the sum of area/3 over its
+ * triangles). */
 enum { FMM_BEM_PRECOND_BLOCK = 0, FMM_BEM_PRECOND_MASS = 1 };
 
 /* Build the operator.  verts (nv x 3 doubles) and tris (nt x 3 int32, vertex
@@ -272,19 +286,20 @@ enum { FMM_BEM_PRECOND_BLOCK = 0, FMM_BEM_PRECOND_MASS = 1 };
  * out of the molecule) are HOST arrays read during the call.  quad_pts: 3 or
  * 6 (regular rule per triangle); eps_in, eps_out > 0; kappa >= 0; p, ncrit,
  * precision as for fmm_setup (the two FMM plans); formulation:
- * FMM_BEM_DIRECT, FMM_BEM_DERIVATIVE or FMM_BEM_EXTERIOR.  The preconditioner
- * starts as FMM_BEM_PRECOND_BLOCK.  Synchronises `stream`.  Errors:
+ * FMM_BEM_DIRECT, FMM_BEM_DERIVATIVE, FMM_BEM_EXTERIOR or FMM_BEM_EXTERIOR_P1.
+ * The preconditioner starts as FMM_BEM_PRECOND_BLOCK (FMM_BEM_PRECOND_MASS
+ * for P1).  Synchronises `stream`.  Errors:
  * FMM_EINVAL for bad sizes, indices or parameters, a degenerate triangle;
  * FMM_ENOMEM; FMM_EHIP. */
 int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, int quad_pts, double eps_in,
               double eps_out, double kappa, int p, int ncrit, int precision, int formulation, fmm_stream_t stream,
               bem_op **out);
 
-/* y = A x; x_dev, y_dev: device, 2*nt doubles ([u; v] and the two row
- * blocks).  x_dev and y_dev must not overlap.  Asynchronous. */
+/* y = A x; x_dev, y_dev: device, 2*n doubles ([u; v] and the two row
+ * blocks; n = nt, or nv for P1 elements: bem_info's n_unknowns).  x_dev and y_dev must not overlap.  Asynchronous. */
 int bem_matvec(bem_op *op, const double *x_dev, double *y_dev, fmm_stream_t stream);
 
-/* Right-hand side b_dev (2*nt doubles) for nq point charges at qxyz_dev
+/* Right-hand side b_dev (2*n doubles, P1: tested with the hat functions) for nq point charges at qxyz_dev
  * (device, nq x 3) with charges q_dev (device, nq), e and Angstrom:
  * b_s = int_Ts (1/eps) sum_k q_k / (4 pi |x - r_k|), eps = eps_out for the
  * exterior formulation and eps_in otherwise; second block 0 (direct) or
@@ -304,13 +319,15 @@ int bem_energy(bem_op *op, const double *x_dev, const double *qxyz_dev, const do
                double *dG, fmm_stream_t stream);
 
 /* Select the preconditioner used by bem_precondition and gmres_solve:
- * FMM_BEM_PRECOND_BLOCK or FMM_BEM_PRECOND_MASS (FMM_EINVAL otherwise).
+ * FMM_BEM_PRECOND_BLOCK or FMM_BEM_PRECOND_MASS (FMM_EINVAL otherwise, and
+ * for BLOCK on P1 elements).
  * Asynchronous on `stream`. */
 int bem_set_preconditioner(bem_op *op, int kind, fmm_stream_t stream);
 
 /* Apply the selected preconditioner (per triangle a 2 x 2 block: the inverse
- * of A's block on the identical pair, or diag(1/area, 1/area)): y = P^-1 x.
- * Device vectors of 2*nt doubles.  Asynchronous. */
+ * of A's block on the identical pair, or diag(1/area, 1/area); P1: per
+ * vertex 1 / its lumped mass): y = P^-1 x.  Device vectors of 2*n doubles.
+ * Asynchronous. */
 int bem_precondition(bem_op *op, const double *x_dev, double *y_dev, fmm_stream_t stream);
 
 /* FP64 GMRES on A x = b with right preconditioning (bem_precondition),
@@ -337,6 +354,7 @@ typedef struct {
   int32_t precision;
   int32_t formulation;
   int32_t preconditioner;
+  int64_t n_unknowns;         /* per block: nt (P0) or nv (P1); vectors hold 2x this */
 } bem_info_t;
 int bem_info(const bem_op *op, bem_info_t *out);
 

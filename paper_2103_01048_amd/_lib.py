@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "libfmmbem.so")
 
 FMM_LAPLACE, FMM_YUKAWA = 0, 1
 FMM_FP64, FMM_FP32, FMM_FP32_BF16X3 = 0, 1, 2
-FMM_BEM_DIRECT, FMM_BEM_DERIVATIVE, FMM_BEM_EXTERIOR = 0, 1, 2
+FMM_BEM_DIRECT, FMM_BEM_DERIVATIVE, FMM_BEM_EXTERIOR, FMM_BEM_EXTERIOR_P1 = 0, 1, 2, 3
 FMM_BEM_PRECOND_BLOCK, FMM_BEM_PRECOND_MASS = 0, 1
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOTCONV, FMM_EBREAKDOWN = 0, -1, -2, -3, -4, -5
 

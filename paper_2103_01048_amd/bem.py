@@ -2,7 +2,8 @@
 bem_matvec, bem_rhs, bem_energy, bem_precondition, gmres_solve).
 
 The mesh is passed as host arrays; vectors are float64 CUDA tensors of
-length 2 * n_triangles ([u; v]).  Every step runs in libfmmbem.so."""
+length 2 * n_unknowns ([u; v]): n_triangles for P0 elements, n_vertices for
+P1.  Every step runs in libfmmbem.so."""
 from __future__ import annotations
 
 import ctypes
@@ -15,7 +16,7 @@ from ._lib import check, lib
 from .fmm import PRECISIONS, _ptr, _stream
 
 FORMULATIONS = {"direct": _lib.FMM_BEM_DIRECT, "derivative": _lib.FMM_BEM_DERIVATIVE,
-                "exterior": _lib.FMM_BEM_EXTERIOR}
+                "exterior": _lib.FMM_BEM_EXTERIOR, "exterior_p1": _lib.FMM_BEM_EXTERIOR_P1}
 PRECONDITIONERS = {"block": _lib.FMM_BEM_PRECOND_BLOCK, "mass": _lib.FMM_BEM_PRECOND_MASS}
 
 
@@ -25,12 +26,15 @@ class BEMOperator:
     (eps_in/eps_out) V_Y]], "derivative" (Juffer), [[(1+e21)/2 M - (e21 K_Y -
     K_L), V_Y - V_L], [W_Y - W_L, (1+e12)/2 M + e12 K'_Y - K'_L]], or "exterior"
     (Lu), [[(1+e12)/2 M - (K_Y - e12 K_L), V_Y - V_L], [e12 (W_Y - W_L), (1+e12)/2
-    M + e12 K'_Y - K'_L]] for the solvent-side unknowns.  preconditioner:
-    "block" (per-triangle 2 x 2 block-diagonal) or "mass" (diag(M, M))."""
+    M + e12 K'_Y - K'_L]] for the solvent-side unknowns; "exterior_p1": the
+    same on continuous piecewise-linear elements (unknowns per vertex, P1 mass
+    matrix).  preconditioner: "block" (per-triangle 2 x 2 block-diagonal, P0
+    only) or "mass" (diag(M, M), lumped for P1); None: "mass" for P1, "block"
+    otherwise."""
 
     def __init__(self, verts, tris, quad_pts: int = 3, eps_in: float = 4.0, eps_out: float = 80.0,
                  kappa: float = 0.125, p: int = 6, ncrit: int = 128, precision: str = "fp32", device="cuda",
-                 formulation: str = "direct", preconditioner: str = "block"):
+                 formulation: str = "direct", preconditioner: str | None = None):
         v = np.ascontiguousarray(verts, dtype=np.float64)
         t = np.ascontiguousarray(tris, dtype=np.int32)
         if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
@@ -48,6 +52,9 @@ class BEMOperator:
                                   PRECISIONS[precision], FORMULATIONS[formulation], _stream(), ctypes.byref(h)),
                   "bem_setup")
         self._h = h
+        self.nu = self.info()["n_unknowns"]
+        if preconditioner is None:
+            preconditioner = "mass" if formulation == "exterior_p1" else "block"
         self.set_preconditioner(preconditioner)
 
     def __del__(self):
@@ -61,8 +68,8 @@ class BEMOperator:
 
     def _vec(self, x):
         x = x.to(device=self.device, dtype=torch.float64).contiguous()
-        if x.shape != (2 * self.nt,):
-            raise ValueError(f"expected a vector of length {2 * self.nt}")
+        if x.shape != (2 * self.nu,):
+            raise ValueError(f"expected a vector of length {2 * self.nu}")
         return x
 
     def matvec(self, x):
@@ -86,7 +93,7 @@ class BEMOperator:
     def rhs(self, qxyz, q):
         qx = torch.as_tensor(qxyz, dtype=torch.float64).to(self.device).contiguous().reshape(-1, 3)
         qq = torch.as_tensor(q, dtype=torch.float64).to(self.device).contiguous().reshape(-1)
-        b = torch.empty(2 * self.nt, dtype=torch.float64, device=self.device)
+        b = torch.empty(2 * self.nu, dtype=torch.float64, device=self.device)
         check(lib().bem_rhs(self._h, _ptr(qx), _ptr(qq), qq.numel(), _ptr(b), _stream()), "bem_rhs")
         return b
 
@@ -105,13 +112,14 @@ class BEMOperator:
         return gmres(self, b, x0=x0, tol=tol, maxiter=maxiter, restart=restart, refine=refine, inner_tol=inner_tol)
 
     def info(self) -> dict:
-        raw = ctypes.create_string_buffer(40)
+        raw = ctypes.create_string_buffer(48)
         check(lib().bem_info(self._h, raw), "bem_info")
         a = np.frombuffer(raw.raw[:24], dtype=np.int64)
         b = np.frombuffer(raw.raw[24:40], dtype=np.int32)
+        c = np.frombuffer(raw.raw[40:48], dtype=np.int64)
         return {"n_triangles": int(a[0]), "n_points": int(a[1]), "n_singular_pairs": int(a[2]),
                 "quad_pts": int(b[0]), "precision": int(b[1]), "formulation": int(b[2]),
-                "preconditioner": int(b[3])}
+                "preconditioner": int(b[3]), "n_unknowns": int(c[0])}
 
 
 def gmres(op: BEMOperator, b, x0=None, tol: float = 1e-6, maxiter: int = 500, restart: int = 0,

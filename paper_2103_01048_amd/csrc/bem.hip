@@ -288,8 +288,332 @@ struct DerivCoef {
 
 DerivCoef deriv_coef(int formulation, double eps_in, double eps_out) {
   const double e21 = eps_out / eps_in, e12 = eps_in / eps_out;
-  if (formulation == FMM_BEM_EXTERIOR) return {-e21, -1.0, 0.5 * (1 + e12), e12, 1.0, 0.5 * (1 + e12), e12};
+  if (formulation == FMM_BEM_EXTERIOR || formulation == FMM_BEM_EXTERIOR_P1)
+    return {-e21, -1.0, 0.5 * (1 + e12), e12, 1.0, 0.5 * (1 + e12), e12};
   return {-1.0, -e12, 0.5 * (1 + e21), 1.0, e21, 0.5 * (1 + e12), 1.0};
+}
+
+// ---------------------------------------------------------------------------
+// P1 (continuous piecewise-linear) elements: hat function of vertex i is the
+// barycentric coordinate lambda_a of the corner a with tri[a] = i
+// ---------------------------------------------------------------------------
+
+// In-plane moments of the flat triangle v[3] (unit normal n) seen from x,
+// with d = n.(x - v0), rho = x - d n, R = |x - y|:
+//   G  = int_T (y - rho)/R dy,   dH = d int_T (y - rho)/R^3 dy.
+// (y - rho)/R is the in-plane gradient of R and (y - rho)/R^3 that of -1/R,
+// so by the divergence theorem in the plane each is a sum over the edges of
+// the outward edge normal m times int_e R dl = (l R + c^2 log(l + R))/2,
+// resp. -int_e dl/R = -log(l + R), between the edge's end coordinates
+// (R^2 = l^2 + c^2 along the edge).  With them a linear density lambda has
+//   int_T lambda/R = lambda(rho) P + grad lambda . G,
+//   int_T lambda d/R^3 = lambda(rho) D + grad lambda . dH
+// (P, D the uniform-density values of tri_pot and tri_dlp).
+__device__ void tri_lin_moments(D3 x, const D3 *v, D3 n, D3 &G, D3 &dH) {
+  const double d = dot(sub(x, v[0]), n);
+  const D3 rho = sub(x, scl(n, d));
+  G = mk(0, 0, 0);
+  dH = mk(0, 0, 0);
+  for (int i = 0; i < 3; ++i) {
+    const D3 a = v[i], b = v[(i + 1) % 3];
+    const D3 e = sub(b, a);
+    const double L = nrm(e);
+    const D3 lh = scl(e, 1.0 / L);
+    const D3 m = cross(lh, n);
+    const double t0 = dot(sub(a, rho), m);
+    const double lp = dot(sub(b, rho), lh), lm = dot(sub(a, rho), lh);
+    const double Rp = nrm(sub(x, b)), Rm = nrm(sub(x, a));
+    const double c2 = t0 * t0 + d * d;
+    double lg = 0;  // log((lp + Rp)/(lm + Rm)); l + R = c^2/(R - l) for l < 0
+    if (c2 > 1e-28 * L * L) {
+      if (lm >= 0) lg = log((lp + Rp) / (lm + Rm));
+      else if (lp <= 0) lg = log((Rm - lm) / (Rp - lp));
+      else lg = log((lp + Rp) * (Rm - lm) / c2);
+    }
+    G = add(G, scl(m, 0.5 * (lp * Rp - lm * Rm + c2 * lg)));
+    dH = sub(dH, scl(m, d * lg));
+  }
+}
+
+// One thread per singular pair (s, t): the 3 x 3 blocks [corner of s][corner
+// of t] of S - C for V_L, K_L, V_Y, K_Y and W_Y - W_L with hat-function
+// weights, B[k][op][a][b] (45 doubles per pair).  S: the Laplace inner
+// integral in closed form for the linear density on t, the outer integral on
+// the collapsed rule; the bounded Yukawa-minus-Laplace remainders (and the
+// non-1/r part of W_Y - W_L) on the collapsed rule on both triangles.  C:
+// the regular rule, zero-distance point pairs left out.
+__global__ __launch_bounds__(128) void k_singular_p1(int64_t npair, const int32_t *__restrict__ ps,
+                                                     const int32_t *__restrict__ pt, const double *__restrict__ tri,
+                                                     const double *__restrict__ normal,
+                                                     const double *__restrict__ area,
+                                                     const double *__restrict__ rule_o, int no,
+                                                     const double *__restrict__ rule_r, int nr,
+                                                     const double *__restrict__ rule_q, int nq, double kappa,
+                                                     double *__restrict__ B) {
+  const int64_t k = blockIdx.x * 128ll + threadIdx.x;
+  if (k >= npair) return;
+  const int s = ps[k], t = pt[k];
+  D3 vs[3], vt[3];
+  for (int i = 0; i < 3; ++i) {
+    vs[i] = mk(tri[s * 9 + 3 * i], tri[s * 9 + 3 * i + 1], tri[s * 9 + 3 * i + 2]);
+    vt[i] = mk(tri[t * 9 + 3 * i], tri[t * 9 + 3 * i + 1], tri[t * 9 + 3 * i + 2]);
+  }
+  const D3 nt = mk(normal[t * 3], normal[t * 3 + 1], normal[t * 3 + 2]);
+  const D3 ns = mk(normal[s * 3], normal[s * 3 + 1], normal[s * 3 + 2]);
+  const double As = area[s], At = area[t], nn = dot(ns, nt);
+  const bool same = s == t;
+  D3 gt[3];  // gradients of t's hat functions
+  for (int b = 0; b < 3; ++b) gt[b] = scl(cross(nt, sub(vt[(b + 2) % 3], vt[(b + 1) % 3])), 0.5 / At);
+  auto point = [](const D3 *v, double l1, double l2) {
+    return add(add(scl(v[0], 1 - l1 - l2), scl(v[1], l1)), scl(v[2], l2));
+  };
+  double VL[9], KL[9], VY[9], KY[9], W[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) VL[i] = KL[i] = 0;
+  for (int c = 0; c < no; ++c) {
+    const double l1 = rule_o[3 * c], l2 = rule_o[3 * c + 1];
+    const D3 x = point(vs, l1, l2);
+    const double w = rule_o[3 * c + 2] * As;
+    const double la[3] = {1 - l1 - l2, l1, l2};
+    const double P = tri_pot(x, vt, nt);
+    const double D = same ? 0.0 : tri_dlp(x, vt);
+    D3 G, dH;
+    tri_lin_moments(x, vt, nt, G, dH);
+    const D3 rho = sub(x, scl(nt, dot(sub(x, vt[0]), nt)));
+    const D3 rr = sub(rho, vt[0]);
+    double iv[3], ik[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double lr = (b == 0 ? 1.0 : 0.0) + dot(gt[b], rr);
+      iv[b] = lr * P + dot(gt[b], G);
+      ik[b] = lr * D + dot(gt[b], dH);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        VL[3 * a + b] += w * la[a] * iv[b];
+        KL[3 * a + b] += w * la[a] * ik[b];
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    VL[i] /= FOUR_PI;
+    KL[i] = same ? 0.0 : KL[i] / FOUR_PI;
+    VY[i] = VL[i];
+    KY[i] = KL[i];
+    W[i] = 0.5 * kappa * kappa * nn * VL[i];  // the 1/r part of W_Y - W_L
+  }
+  for (int a = 0; a < nr; ++a) {
+    const double l1 = rule_r[3 * a], l2 = rule_r[3 * a + 1];
+    const D3 x = point(vs, l1, l2);
+    const double wa = rule_r[3 * a + 2] * As;
+    const double la[3] = {1 - l1 - l2, l1, l2};
+    for (int b = 0; b < nr; ++b) {
+      const double m1 = rule_r[3 * b], m2 = rule_r[3 * b + 1];
+      const D3 y = point(vt, m1, m2);
+      const double w = wa * rule_r[3 * b + 2] * At;
+      const double lb[3] = {1 - m1 - m2, m1, m2};
+      const D3 d = sub(x, y);
+      const double r = nrm(d);
+      double rv, rk = 0, rw;
+      if (r > 0) {
+        const double kr = kappa * r;
+        rv = expm1(-kr) / (FOUR_PI * r);
+        if (!same) rk = dot(d, nt) * ((1 + kr) * exp(-kr) - 1.0) / (FOUR_PI * r * r * r);
+        double hp, A, Bh;
+        h_derivs(r, kappa, hp, A, Bh);
+        rw = nn * A + dot(d, ns) * dot(d, nt) / (r * r) * Bh;
+      } else {
+        rv = -kappa / FOUR_PI;
+        rw = -nn * kappa * kappa * kappa / (12.0 * M_PI);
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const double ww = w * la[i] * lb[j];
+          VY[3 * i + j] += ww * rv;
+          KY[3 * i + j] += ww * rk;
+          W[3 * i + j] += ww * rw;
+        }
+    }
+  }
+  // minus the regular-rule values the quadrature-point sums contain
+  for (int a = 0; a < nq; ++a) {
+    const double l1 = rule_q[3 * a], l2 = rule_q[3 * a + 1];
+    const D3 x = point(vs, l1, l2);
+    const double wa = rule_q[3 * a + 2] * As;
+    const double la[3] = {1 - l1 - l2, l1, l2};
+    for (int b = 0; b < nq; ++b) {
+      const double m1 = rule_q[3 * b], m2 = rule_q[3 * b + 1];
+      const D3 y = point(vt, m1, m2);
+      const D3 d = sub(x, y);
+      const double r = nrm(d);
+      if (!(r > 0)) continue;
+      const double w = wa * rule_q[3 * b + 2] * At;
+      const double lb[3] = {1 - m1 - m2, m1, m2};
+      const double e = exp(-kappa * r), dn = dot(d, nt);
+      const double gl = 1.0 / (FOUR_PI * r), kl = dn / (FOUR_PI * r * r * r);
+      const double gy = e * gl, ky = (1 + kappa * r) * e * kl, hw = hyper_diff(d, r, ns, nt, kappa);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const double ww = w * la[i] * lb[j];
+          VL[3 * i + j] -= ww * gl;
+          KL[3 * i + j] -= ww * kl;
+          VY[3 * i + j] -= ww * gy;
+          KY[3 * i + j] -= ww * ky;
+          W[3 * i + j] -= ww * hw;
+        }
+    }
+  }
+  double *o = B + k * 45;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    o[i] = VL[i];
+    o[9 + i] = KL[i];
+    o[18 + i] = VY[i];
+    o[27 + i] = KY[i];
+    o[36 + i] = W[i];
+  }
+}
+
+// P1 sources at quadrature point i of triangle t: the vertex values
+// interpolated, u(x_i) = sum_a lambda_a(xi_i) u[tri_a]; charge W_i vscale
+// v(x_i), dipole W_i u(x_i) n_t.
+template <typename T>
+__global__ void k_p1_src(int64_t nt, int nq, const int32_t *__restrict__ tris, const double *__restrict__ rule_q,
+                         const double *__restrict__ x, int64_t nv, double vscale, const double *__restrict__ qw,
+                         const double *__restrict__ normal, T *__restrict__ q, T *__restrict__ dip) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= nt * nq) return;
+  const int64_t t = i / nq;
+  const int a = (int)(i - t * nq);
+  const double l1 = rule_q[3 * a], l2 = rule_q[3 * a + 1];
+  const double la[3] = {1 - l1 - l2, l1, l2};
+  double u = 0, v = 0;
+  for (int c = 0; c < 3; ++c) {
+    const int32_t vi = tris[3 * t + c];
+    u += la[c] * x[vi];
+    v += la[c] * x[nv + vi];
+  }
+  const double w = qw[i];
+  q[i] = (T)(w * vscale * v);
+  dip[3 * i + 0] = (T)(w * u * normal[3 * t + 0]);
+  dip[3 * i + 1] = (T)(w * u * normal[3 * t + 1]);
+  dip[3 * i + 2] = (T)(w * u * normal[3 * t + 2]);
+}
+
+// Exterior formulation on P1 elements, per triangle s and corner a (the
+// test function lambda_a on s): the quadrature-point fields weighted by
+// W_j lambda_a(xi_j), the S - C blocks of s's singular pairs (K' from the
+// transposed pair's K block), and s's part of the mass matrix
+// (A/12 (1 + delta_ab)); cb[s][a][0..1] for the two rows, added into the
+// vertices by k_p1_gather.  Coefficients as k_bem_p2_deriv.
+template <typename T>
+__global__ void k_p1_corner(int64_t nt, int nq, const T *__restrict__ potl, const T *__restrict__ gradl,
+                            const T *__restrict__ poty, const T *__restrict__ grady, const double *__restrict__ qw,
+                            const double *__restrict__ rule_q, const double *__restrict__ area,
+                            const double *__restrict__ normal, const int32_t *__restrict__ tris,
+                            const int32_t *__restrict__ sp_off, const int32_t *__restrict__ sp_idx,
+                            const int32_t *__restrict__ sp_tr, const double *__restrict__ B,
+                            const double *__restrict__ x, int64_t nv, DerivCoef c, double *__restrict__ cb) {
+  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+  if (s >= nt) return;
+  const double n0 = normal[3 * s], n1 = normal[3 * s + 1], n2 = normal[3 * s + 2];
+  double r1[3] = {0, 0, 0}, r2[3] = {0, 0, 0};
+  for (int j = 0; j < nq; ++j) {
+    const int64_t i = s * nq + j;
+    const double l1 = rule_q[3 * j], l2 = rule_q[3 * j + 1];
+    const double la[3] = {1 - l1 - l2, l1, l2};
+    const double f1 = qw[i] * (c.c1L * (double)potl[i] - c.c1Y * (double)poty[i]);
+    const double f2 = qw[i] * (n0 * ((double)gradl[3 * i] - (double)grady[3 * i]) +
+                               n1 * ((double)gradl[3 * i + 1] - (double)grady[3 * i + 1]) +
+                               n2 * ((double)gradl[3 * i + 2] - (double)grady[3 * i + 2]));
+    for (int a = 0; a < 3; ++a) {
+      r1[a] += la[a] * f1;
+      r2[a] += la[a] * f2;
+    }
+  }
+  double b1[3] = {0, 0, 0}, b2[3] = {0, 0, 0};
+  for (int k = sp_off[s]; k < sp_off[s + 1]; ++k) {
+    const int t = sp_idx[k], kt = sp_tr[k];
+    const double *Bk = B + (int64_t)k * 45, *Bt = B + (int64_t)kt * 45;
+    for (int b = 0; b < 3; ++b) {
+      const int32_t vb = tris[3 * t + b];
+      const double u = x[vb], v = x[nv + vb];
+      for (int a = 0; a < 3; ++a) {
+        const int ab = 3 * a + b, ba = 3 * b + a;
+        b1[a] += c.c1L * (Bk[9 + ab] * u + c.sL * Bk[ab] * v) - c.c1Y * (Bk[27 + ab] * u + c.sY * Bk[18 + ab] * v);
+        b2[a] += Bk[36 + ab] * u + c.sL * Bt[9 + ba] * v - c.sY * Bt[27 + ba] * v;
+      }
+    }
+  }
+  double us = 0, vs = 0, ua[3], va[3];
+  for (int a = 0; a < 3; ++a) {
+    const int32_t vi = tris[3 * s + a];
+    ua[a] = x[vi];
+    va[a] = x[nv + vi];
+    us += ua[a];
+    vs += va[a];
+  }
+  const double m = area[s] / 12.0;
+  for (int a = 0; a < 3; ++a) {
+    cb[(s * 3 + a) * 2 + 0] = c.d1 * m * (ua[a] + us) + r1[a] + b1[a];
+    cb[(s * 3 + a) * 2 + 1] = c.d2 * m * (va[a] + vs) + c.c2 * (r2[a] + b2[a]);
+  }
+}
+
+// cb[s][a][col] = sum_j W_j lambda_a(xi_j) f_j (a field tested with the hat
+// functions, per triangle corner).
+__global__ void k_p1_project(int64_t nt, int nq, const double *__restrict__ qw, const double *__restrict__ rule_q,
+                             const double *__restrict__ f, int col, double *__restrict__ cb) {
+  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+  if (s >= nt) return;
+  double r[3] = {0, 0, 0};
+  for (int j = 0; j < nq; ++j) {
+    const double l1 = rule_q[3 * j], l2 = rule_q[3 * j + 1];
+    const double wf = qw[s * nq + j] * f[s * nq + j];
+    r[0] += (1 - l1 - l2) * wf;
+    r[1] += l1 * wf;
+    r[2] += l2 * wf;
+  }
+  for (int a = 0; a < 3; ++a) cb[(s * 3 + a) * 2 + col] = r[a];
+}
+
+// y[i] = sum over the corners (s, a) at vertex i (ascending s) of cb[s][a][0],
+// y[nv + i] the same of cb[s][a][1]: a fixed order, so results do not depend
+// on scheduling.
+__global__ void k_p1_gather(int64_t nv, const int32_t *__restrict__ vt_off, const int32_t *__restrict__ vt_list,
+                            const double *__restrict__ cb, double *__restrict__ y) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= nv) return;
+  double a0 = 0, a1 = 0;
+  for (int k = vt_off[i]; k < vt_off[i + 1]; ++k) {
+    const int32_t c = vt_list[k];
+    a0 += cb[2 * (int64_t)c];
+    a1 += cb[2 * (int64_t)c + 1];
+  }
+  y[i] = a0;
+  y[nv + i] = a1;
+}
+
+// Lumped mass preconditioner on P1 elements: per vertex diag(1/Ml, 1/Ml),
+// Ml = sum over the triangles at the vertex of area/3 (the mass matrix's row
+// sum); stored as 2 x 2 blocks for k_precond_apply.
+__global__ void k_precond_setup_lumped(int64_t nv, const int32_t *__restrict__ vt_off,
+                                       const int32_t *__restrict__ vt_list, const double *__restrict__ area,
+                                       double *__restrict__ pre) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= nv) return;
+  double ml = 0;
+  for (int k = vt_off[i]; k < vt_off[i + 1]; ++k) ml += area[vt_list[k] / 3] / 3.0;
+  pre[4 * i + 0] = 1.0 / ml;
+  pre[4 * i + 1] = 0.0;
+  pre[4 * i + 2] = 0.0;
+  pre[4 * i + 3] = 1.0 / ml;
 }
 
 // Inverse of the 2x2 diagonal block of a derivative formulation,
@@ -638,6 +962,14 @@ struct bem_op {
   int formulation = 0, precond = 0;
   double *d_Dw = nullptr, *d_sdiag_w = nullptr;
   int32_t *d_sp_tr = nullptr;
+  // P1 elements (FMM_BEM_EXTERIOR_P1): nu = nv unknowns per block (nt for
+  // P0), the triangles' vertex indices, per vertex its corners (3 s + a,
+  // ascending), the regular rule, the S - C blocks (45 per pair) and the
+  // per-corner row sums
+  bool p1 = false;
+  int64_t nu = 0;
+  int32_t *d_tris = nullptr, *d_vt_off = nullptr, *d_vt_list = nullptr;
+  double *d_rq = nullptr, *d_B = nullptr, *d_cb = nullptr;
   void *q4 = nullptr, *potl = nullptr, *poty = nullptr, *gradl = nullptr, *grady = nullptr;
   // GMRES / energy scratch
   double *d_partial = nullptr, *d_h = nullptr, *d_V = nullptr, *d_z = nullptr, *d_w = nullptr, *d_r = nullptr,
@@ -669,7 +1001,7 @@ int bupload(bem_op *op, V **p, const std::vector<V> &h) {
 
 int ensure_krylov(bem_op *op, int64_t rows) {
   if (op->V_rows >= rows) return FMM_OK;
-  const int64_t n = 2 * op->nt;
+  const int64_t n = 2 * op->nu;
   int rc;
   if ((rc = balloc(op, (void **)&op->d_V, (size_t)rows * n * sizeof(double)))) return rc;
   if ((rc = balloc(op, (void **)&op->d_partial, (size_t)rows * RED_BLOCKS * sizeof(double)))) return rc;
@@ -681,7 +1013,7 @@ int ensure_krylov(bem_op *op, int64_t rows) {
 // dot products of the first `rows` Krylov vectors (or any rows-by-n block)
 // with w; result on the host
 int multidot(bem_op *op, const double *V, int rows, const double *w, double *h_host, hipStream_t s) {
-  const int64_t n = 2 * op->nt;
+  const int64_t n = 2 * op->nu;
   hipLaunchKernelGGL(k_multidot, dim3(RED_BLOCKS, rows), dim3(256), 0, s, V, n, w, op->d_partial);
   hipLaunchKernelGGL(k_sum_partials, dim3(blocks(rows, 64)), dim3(64), 0, s, rows, op->d_partial, op->d_h);
   FMM_HIP_TRY(hipGetLastError());
@@ -693,7 +1025,14 @@ int multidot(bem_op *op, const double *V, int rows, const double *w, double *h_h
 // (Re)build the per-triangle 2 x 2 preconditioner blocks of kind `kind`.
 int precond_setup(bem_op *op, int kind, hipStream_t s) {
   const int64_t nt = op->nt;
-  if (kind == FMM_BEM_PRECOND_MASS)
+  if (op->p1) {
+    if (kind != FMM_BEM_PRECOND_MASS) {
+      set_error("bem: P1 elements take the (lumped) mass preconditioner only");
+      return FMM_EINVAL;
+    }
+    hipLaunchKernelGGL(k_precond_setup_lumped, dim3(blocks(op->nv)), dim3(256), 0, s, op->nv, op->d_vt_off,
+                       op->d_vt_list, op->d_area, op->d_pre);
+  } else if (kind == FMM_BEM_PRECOND_MASS)
     hipLaunchKernelGGL(k_precond_setup_mass, dim3(blocks(nt)), dim3(256), 0, s, nt, op->d_area, op->d_pre);
   else if (op->formulation != FMM_BEM_DIRECT)
     hipLaunchKernelGGL(k_precond_setup_deriv, dim3(blocks(nt)), dim3(256), 0, s, nt, op->d_area, op->d_sdiag,
@@ -715,7 +1054,8 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
               bem_op **out) {
   if (!out) { set_error("bem_setup: out is NULL"); return FMM_EINVAL; }
   *out = nullptr;
-  if (formulation != FMM_BEM_DIRECT && formulation != FMM_BEM_DERIVATIVE && formulation != FMM_BEM_EXTERIOR) {
+  if (formulation != FMM_BEM_DIRECT && formulation != FMM_BEM_DERIVATIVE && formulation != FMM_BEM_EXTERIOR &&
+      formulation != FMM_BEM_EXTERIOR_P1) {
     set_error("bem_setup: unknown formulation");
     return FMM_EINVAL;
   }
@@ -733,6 +1073,8 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
   op->nt = nt; op->nv = nv; op->nq = quad_pts; op->N = nt * quad_pts; op->precision = precision;
   op->eps_in = eps_in; op->eps_out = eps_out; op->kappa = kappa;
   op->formulation = formulation;
+  op->p1 = formulation == FMM_BEM_EXTERIOR_P1;
+  op->nu = op->p1 ? nv : nt;
   const bool deriv = formulation != FMM_BEM_DIRECT;
   int rc = FMM_OK;
   do {
@@ -802,19 +1144,43 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
     if ((rc = bupload(op, &d_ro, ro))) break;
     if ((rc = bupload(op, &d_rr, rr))) break;
     if ((rc = bupload(op, &d_rq, rq))) break;
-    if ((rc = balloc(op, (void **)&op->d_D, op->npair * 4 * sizeof(double)))) break;
-    if ((rc = balloc(op, (void **)&op->d_sdiag, nt * 2 * sizeof(double)))) break;
-    if ((rc = balloc(op, (void **)&op->d_pre, nt * 4 * sizeof(double)))) break;
-    if (deriv) {
-      if ((rc = bupload(op, &op->d_sp_tr, tr))) break;
-      if ((rc = balloc(op, (void **)&op->d_Dw, op->npair * sizeof(double)))) break;
-      if ((rc = balloc(op, (void **)&op->d_sdiag_w, nt * sizeof(double)))) break;
+    op->d_rq = d_rq;
+    if ((rc = balloc(op, (void **)&op->d_pre, op->nu * 4 * sizeof(double)))) break;
+    if (deriv && (rc = bupload(op, &op->d_sp_tr, tr))) break;
+    if (op->p1) {
+      // per vertex its triangle corners 3 s + a, ascending; every vertex
+      // must belong to a triangle (it carries two unknowns)
+      std::vector<int32_t> tv(tris, tris + 3 * nt), voff(nv + 1, 0), vlist(3 * nt);
+      for (int64_t c = 0; c < 3 * nt; ++c) ++voff[tv[c] + 1];
+      bool lone = false;
+      for (int64_t i = 0; i < nv; ++i) {
+        lone = lone || voff[i + 1] == 0;
+        voff[i + 1] += voff[i];
+      }
+      if (lone) { set_error("bem_setup: P1 elements need every vertex on a triangle"); rc = FMM_EINVAL; break; }
+      std::vector<int32_t> fill(voff.begin(), voff.end() - 1);
+      for (int64_t c = 0; c < 3 * nt; ++c) vlist[fill[tv[c]]++] = (int32_t)c;
+      if ((rc = bupload(op, &op->d_tris, tv))) break;
+      if ((rc = bupload(op, &op->d_vt_off, voff))) break;
+      if ((rc = bupload(op, &op->d_vt_list, vlist))) break;
+      if ((rc = balloc(op, (void **)&op->d_B, op->npair * 45 * sizeof(double)))) break;
+      if ((rc = balloc(op, (void **)&op->d_cb, nt * 6 * sizeof(double)))) break;
+      hipLaunchKernelGGL(k_singular_p1, dim3(blocks(op->npair, 128)), dim3(128), 0, s, op->npair, d_ps,
+                         op->d_sp_idx, op->d_tri, op->d_normal, op->d_area, d_ro, NO * NO, d_rr, NREM * NREM, d_rq,
+                         quad_pts, kappa, op->d_B);
+    } else {
+      if ((rc = balloc(op, (void **)&op->d_D, op->npair * 4 * sizeof(double)))) break;
+      if ((rc = balloc(op, (void **)&op->d_sdiag, nt * 2 * sizeof(double)))) break;
+      if (deriv) {
+        if ((rc = balloc(op, (void **)&op->d_Dw, op->npair * sizeof(double)))) break;
+        if ((rc = balloc(op, (void **)&op->d_sdiag_w, nt * sizeof(double)))) break;
+      }
+      hipLaunchKernelGGL(k_singular, dim3(blocks(op->npair, 128)), dim3(128), 0, s, op->npair, d_ps, op->d_sp_idx,
+                         op->d_tri, op->d_normal, op->d_area, d_ro, NO * NO, d_rr, NREM * NREM, d_rq, quad_pts,
+                         kappa, op->d_D, op->d_sdiag, deriv ? 1 : 0, op->d_Dw, op->d_sdiag_w);
     }
-    hipLaunchKernelGGL(k_singular, dim3(blocks(op->npair, 128)), dim3(128), 0, s, op->npair, d_ps, op->d_sp_idx,
-                       op->d_tri, op->d_normal, op->d_area, d_ro, NO * NO, d_rr, NREM * NREM, d_rq, quad_pts, kappa,
-                       op->d_D, op->d_sdiag, deriv ? 1 : 0, op->d_Dw, op->d_sdiag_w);
     if (hipGetLastError() != hipSuccess) { set_error("bem_setup: launch failed"); rc = FMM_EHIP; break; }
-    if ((rc = precond_setup(op, FMM_BEM_PRECOND_BLOCK, s))) break;
+    if ((rc = precond_setup(op, op->p1 ? FMM_BEM_PRECOND_MASS : FMM_BEM_PRECOND_BLOCK, s))) break;
     // the two FMM plans on the quadrature points
     if ((rc = fmm_setup(op->d_qpts, op->N, FMM_LAPLACE, 0.0, p, ncrit, precision, stream, &op->fl))) break;
     if ((rc = fmm_setup(op->d_qpts, op->N, FMM_YUKAWA, kappa, p, ncrit, precision, stream, &op->fy))) break;
@@ -827,10 +1193,10 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
       if ((rc = balloc(op, &op->gradl, 3 * op->N * es))) break;
       if ((rc = balloc(op, &op->grady, 3 * op->N * es))) break;
     }
-    if ((rc = balloc(op, (void **)&op->d_z, 2 * nt * sizeof(double)))) break;
-    if ((rc = balloc(op, (void **)&op->d_w, 2 * nt * sizeof(double)))) break;
-    if ((rc = balloc(op, (void **)&op->d_r, 2 * nt * sizeof(double)))) break;
-    if ((rc = balloc(op, (void **)&op->d_xc, 2 * nt * sizeof(double)))) break;
+    if ((rc = balloc(op, (void **)&op->d_z, 2 * op->nu * sizeof(double)))) break;
+    if ((rc = balloc(op, (void **)&op->d_w, 2 * op->nu * sizeof(double)))) break;
+    if ((rc = balloc(op, (void **)&op->d_r, 2 * op->nu * sizeof(double)))) break;
+    if ((rc = balloc(op, (void **)&op->d_xc, 2 * op->nu * sizeof(double)))) break;
     if ((rc = ensure_krylov(op, 2))) break;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) { set_error(std::string("bem_setup: ") + hipGetErrorString(e)); rc = FMM_EHIP; }
@@ -851,6 +1217,34 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
   // one pass per kernel: single layer as charges, double layer as dipoles
   // (the four-column form would need potentials and gradients of four)
   const int64_t Nq = (int64_t)nt * op->nq;
+  if (op->p1) {
+    const size_t es = op->precision == FMM_FP64 ? 8 : 4;
+    const char *qq = (const char *)op->q4;
+    if (op->precision == FMM_FP64)
+      hipLaunchKernelGGL(k_p1_src<double>, dim3(blocks(N)), dim3(256), 0, s, nt, op->nq, op->d_tris, op->d_rq, x,
+                         op->nv, 1.0, op->d_qw, op->d_normal, (double *)op->q4, (double *)op->q4 + Nq);
+    else
+      hipLaunchKernelGGL(k_p1_src<float>, dim3(blocks(N)), dim3(256), 0, s, nt, op->nq, op->d_tris, op->d_rq, x,
+                         op->nv, 1.0, op->d_qw, op->d_normal, (float *)op->q4, (float *)op->q4 + Nq);
+    FMM_HIP_TRY(hipGetLastError());
+    if ((rc = fmm_eval_pair_md(op->fl, op->fy, qq, qq + Nq * es, dc.sL, dc.sY, op->potl, op->gradl, op->poty,
+                               op->grady, s)))
+      return rc;
+    if (op->precision == FMM_FP64)
+      hipLaunchKernelGGL(k_p1_corner<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const double *)op->potl,
+                         (const double *)op->gradl, (const double *)op->poty, (const double *)op->grady, op->d_qw,
+                         op->d_rq, op->d_area, op->d_normal, op->d_tris, op->d_sp_off, op->d_sp_idx, op->d_sp_tr,
+                         op->d_B, x, op->nv, dc, op->d_cb);
+    else
+      hipLaunchKernelGGL(k_p1_corner<float>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const float *)op->potl,
+                         (const float *)op->gradl, (const float *)op->poty, (const float *)op->grady, op->d_qw,
+                         op->d_rq, op->d_area, op->d_normal, op->d_tris, op->d_sp_off, op->d_sp_idx, op->d_sp_tr,
+                         op->d_B, x, op->nv, dc, op->d_cb);
+    hipLaunchKernelGGL(k_p1_gather, dim3(blocks(op->nv)), dim3(256), 0, s, op->nv, op->d_vt_off, op->d_vt_list,
+                       op->d_cb, y);
+    FMM_HIP_TRY(hipGetLastError());
+    return FMM_OK;
+  }
   if (op->precision == FMM_FP64) {
     double *qq = (double *)op->q4;
     hipLaunchKernelGGL(k_bem_p1_md<double>, dim3(blocks(N)), dim3(256), 0, s, nt, op->nq, x, op->d_qw, op->d_normal,
@@ -904,7 +1298,7 @@ int bem_set_preconditioner(bem_op *op, int kind, fmm_stream_t stream) {
 
 int bem_precondition(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
   if (!op || !x || !y) { set_error("bem_precondition: null argument"); return FMM_EINVAL; }
-  hipLaunchKernelGGL(k_precond_apply, dim3(blocks(op->nt)), dim3(256), 0, (hipStream_t)stream, op->nt, op->d_pre, x, y);
+  hipLaunchKernelGGL(k_precond_apply, dim3(blocks(op->nu)), dim3(256), 0, (hipStream_t)stream, op->nu, op->d_pre, x, y);
   FMM_HIP_TRY(hipGetLastError());
   return FMM_OK;
 }
@@ -916,12 +1310,24 @@ int bem_rhs(bem_op *op, const double *qxyz, const double *q, int64_t nq, double 
   FMM_HIP_TRY(hipMallocAsync((void **)&sig, std::max<int64_t>(1, nq) * sizeof(double), s));
   FMM_HIP_TRY(hipMallocAsync((void **)&f, op->N * sizeof(double), s));
   // sigma_k = q_k / eps_in (q_k / eps_out for the exterior formulation)
-  const double eps = op->formulation == FMM_BEM_EXTERIOR ? op->eps_out : op->eps_in;
+  const double eps = op->formulation == FMM_BEM_EXTERIOR || op->p1 ? op->eps_out : op->eps_in;
   hipLaunchKernelGGL(k_axpby, dim3(blocks(std::max<int64_t>(1, nq))), dim3(256), 0, s, nq, 1.0 / eps, q, 0.0, q, sig);
   hipLaunchKernelGGL(k_direct_md, dim3(blocks(op->N), 1), dim3(256), 0, s, op->N, op->d_qpts, nq, qxyz, sig,
                      (const double *)nullptr, std::max<int64_t>(1, nq), f);
-  hipLaunchKernelGGL(k_rhs_assemble, dim3(blocks(op->nt)), dim3(256), 0, s, op->nt, op->nq, op->d_qw, f, b);
-  if (op->formulation != FMM_BEM_DIRECT) {
+  if (op->p1) {
+    // both fields tested with the hat functions, then added into the vertices
+    hipLaunchKernelGGL(k_p1_project, dim3(blocks(op->nt)), dim3(256), 0, s, op->nt, op->nq, op->d_qw, op->d_rq, f, 0,
+                       op->d_cb);
+    hipLaunchKernelGGL(k_direct_ngrad, dim3(blocks(op->N)), dim3(256), 0, s, op->N, op->nq, op->d_qpts, op->d_normal,
+                       nq, qxyz, sig, f);
+    hipLaunchKernelGGL(k_p1_project, dim3(blocks(op->nt)), dim3(256), 0, s, op->nt, op->nq, op->d_qw, op->d_rq, f, 1,
+                       op->d_cb);
+    hipLaunchKernelGGL(k_p1_gather, dim3(blocks(op->nv)), dim3(256), 0, s, op->nv, op->d_vt_off, op->d_vt_list,
+                       op->d_cb, b);
+  } else {
+    hipLaunchKernelGGL(k_rhs_assemble, dim3(blocks(op->nt)), dim3(256), 0, s, op->nt, op->nq, op->d_qw, f, b);
+  }
+  if (op->formulation != FMM_BEM_DIRECT && !op->p1) {
     // second block: the normal derivative of the same Coulomb sum
     hipLaunchKernelGGL(k_direct_ngrad, dim3(blocks(op->N)), dim3(256), 0, s, op->N, op->nq, op->d_qpts, op->d_normal,
                        nq, qxyz, sig, f);
@@ -946,9 +1352,13 @@ int bem_energy(bem_op *op, const double *x, const double *qxyz, const double *q,
   FMM_HIP_TRY(hipMallocAsync((void **)&res, sizeof(double), s));
   // the exterior unknowns map to (phi_1, d phi_1/dn) by the interface
   // conditions: phi_1 = phi_2, eps_in d phi_1/dn = eps_out d phi_2/dn
-  const double vscale = op->formulation == FMM_BEM_EXTERIOR ? op->eps_out / op->eps_in : 1.0;
-  hipLaunchKernelGGL(k_energy_sources, dim3(blocks(op->N)), dim3(256), 0, s, op->nt, op->nq, x, vscale, op->d_qw,
-                     op->d_normal, sig, dip);
+  const double vscale = op->formulation == FMM_BEM_EXTERIOR || op->p1 ? op->eps_out / op->eps_in : 1.0;
+  if (op->p1)
+    hipLaunchKernelGGL(k_p1_src<double>, dim3(blocks(op->N)), dim3(256), 0, s, op->nt, op->nq, op->d_tris, op->d_rq,
+                       x, op->nv, vscale, op->d_qw, op->d_normal, sig, dip);
+  else
+    hipLaunchKernelGGL(k_energy_sources, dim3(blocks(op->N)), dim3(256), 0, s, op->nt, op->nq, x, vscale, op->d_qw,
+                       op->d_normal, sig, dip);
   // few targets, many sources: the sources in chunks (at least ~2,048
   // workgroups in all), partial sums added in chunk order
   const int64_t tb = blocks(nq);
@@ -975,7 +1385,7 @@ int bem_energy(bem_op *op, const double *x, const double *qxyz, const double *q,
 // residual tol (relative to bnorm) measured with the recomputed residual.
 static int gmres_core(bem_op *op, const double *b, double *x, double bnorm, double tol, int maxiter, int restart,
                       int *it_total, double *hist, int hist_cap, hipStream_t s) {
-  const int64_t n = 2 * op->nt;
+  const int64_t n = 2 * op->nu;
   int rc;
   if (restart <= 0 || restart > maxiter) restart = maxiter;
   if ((rc = ensure_krylov(op, restart + 1))) return rc;
@@ -1049,9 +1459,12 @@ static int gmres_core(bem_op *op, const double *b, double *x, double bnorm, doub
 int gmres_solve(bem_op *op, bem_op *refine, const double *b, double *x, double tol, double inner_tol, int maxiter,
                 int restart, int *iters, double *hist, fmm_stream_t stream) {
   if (!op || !b || !x || !(tol > 0) || maxiter < 1) { set_error("gmres_solve: bad argument"); return FMM_EINVAL; }
-  if (refine && refine->nt != op->nt) { set_error("gmres_solve: refine operator on another mesh"); return FMM_EINVAL; }
+  if (refine && (refine->nt != op->nt || refine->nu != op->nu)) {
+    set_error("gmres_solve: refine operator on another mesh or element type");
+    return FMM_EINVAL;
+  }
   hipStream_t s = (hipStream_t)stream;
-  const int64_t n = 2 * op->nt;
+  const int64_t n = 2 * op->nu;
   int it = 0, rc;
   double bb;
   if ((rc = multidot(op, b, 1, b, &bb, s))) return rc;
@@ -1098,6 +1511,7 @@ int bem_info(const bem_op *op, bem_info_t *o) {
   o->precision = op->precision;
   o->formulation = op->formulation;
   o->preconditioner = op->precond;
+  o->n_unknowns = op->nu;
   return FMM_OK;
 }
 

@@ -26,6 +26,7 @@ __all__ = [
     "random_rotation",
     "surface_cloud",
     "molecule_batch",
+    "used_vertices_only",
 ]
 
 
@@ -218,6 +219,18 @@ def sphere_union_mesh(su: SphereUnion, n_triangles: int, seed: int, exact: bool 
     remap = -np.ones(len(v), dtype=np.int64)
     remap[used] = np.arange(len(used))
     return np.ascontiguousarray(v[used]), np.ascontiguousarray(remap[t].astype(np.int32))
+
+
+def used_vertices_only(verts, tris):
+    """(verts, tris) without the vertices no triangle uses (the sphere-union
+    meshes drop buried triangles but keep every lattice point), triangle
+    indices renumbered in order."""
+    verts = np.asarray(verts)
+    tris = np.asarray(tris)
+    used = np.zeros(len(verts), dtype=bool)
+    used[tris.reshape(-1)] = True
+    new = np.cumsum(used) - 1
+    return np.ascontiguousarray(verts[used]), new[tris].astype(tris.dtype)
 
 
 def three_point_cloud(verts: np.ndarray, tris: np.ndarray) -> np.ndarray:

@@ -84,7 +84,7 @@ def test_bem_setup_rejects_bad_arguments(case):
     t = np.array([[0, 1, 2], [0, 1, 3]], dtype=np.int32)
     quad, eps, kap, form = 3, 4.0, 0.1, 0
     if case == "formulation":
-        form = 3
+        form = 4
     elif case == "quad":
         quad = 4
     elif case == "eps":
