@@ -89,10 +89,10 @@ def parse():
                          "against 64 separate plans per kernel; bem2m: boundary-element matvec and GMRES solve "
                          "on 2M triangles; adjoint1m: adjoint against forward time on 1M points; shell30m: "
                          "the 30M-point shell at p = 10")
-    ap.add_argument("--formulation", default="direct", choices=["direct", "derivative", "exterior"],
-                    help="boundary-element formulation of the bem2m workload")
-    ap.add_argument("--precond", default="block", choices=["block", "mass"],
-                    help="GMRES preconditioner of the bem2m workload")
+    ap.add_argument("--formulation", default="direct", choices=["direct", "derivative", "exterior", "exterior_p1"],
+                    help="boundary-element formulation of the bem2m workload (exterior_p1: P1 elements)")
+    ap.add_argument("--precond", default=None, choices=["block", "mass"],
+                    help="GMRES preconditioner of the bem2m workload (default: block for P0, lumped mass for P1)")
     ap.add_argument("--p-sweep", default="4,5,6,7",
                     help="expansion orders below the workload's p also timed and checked against the sampled "
                          "direct sums (needs the CPU leg); empty to skip")
@@ -266,11 +266,15 @@ def run_bem(args):
     t0 = time.perf_counter()
     su = synth.sphere_union_spheres(1000, seed=91, box=40.0 * 5.0 ** (1.0 / 3.0))
     v, t = synth.sphere_union_mesh(su, 2_000_000, seed=91, gap=0.5)
+    p1 = args.formulation == "exterior_p1"
+    if p1:
+        v, t = synth.used_vertices_only(v, t)
+    precond = args.precond or ("mass" if p1 else "block")
     qxyz, q = synth.charges_in_spheres(su, 20000, seed=91)
     print(f"# mesh {len(t)} triangles in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ncrit = args.ncrit or 128
     kw = dict(quad_pts=3, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=P_ORDER, ncrit=ncrit,
-              formulation=args.formulation, preconditioner=args.precond)
+              formulation=args.formulation, preconditioner=precond)
     t0 = time.perf_counter()
     op32 = BEMOperator(v, t, precision=args.precision, **kw)
     t_setup32 = time.perf_counter() - t0
@@ -278,7 +282,7 @@ def run_bem(args):
     op64 = BEMOperator(v, t, precision="fp64", **kw)
     t_setup64 = time.perf_counter() - t0
     T = len(t)
-    x = torch.tensor(np.random.default_rng(92).standard_normal(2 * T), device="cuda")
+    x = torch.tensor(np.random.default_rng(92).standard_normal(2 * op32.nu), device="cuda")
 
     def timed(op, steps):
         for _ in range(2):
@@ -314,9 +318,10 @@ def run_bem(args):
             "ms_per_step": round(t32 * 1e3, 3), "higher_is_better": False, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"sphere-union BEM, 1000 spheres, {T} triangles x 3 points = {npts} points, "
-                                   f"20000 charges, {args.formulation} formulation (P0), eps 4/80, kappa 0.125",
+                                   f"20000 charges, {args.formulation} formulation ({'P1, ' + str(op32.nu) + ' vertices' if p1 else 'P0'}), "
+                                   "eps 4/80, kappa 0.125",
                        "p": P_ORDER, "ncrit": ncrit, "formulation": args.formulation,
-                       "preconditioner": args.precond, "precision": args.precision},
+                       "preconditioner": precond, "precision": args.precision, "unknowns": 2 * op32.nu},
             "fmm_mpoints_per_s": round(2 * npts / t32 / 1e6, 1),
             "fp64_matvec_ms": round(t64 * 1e3, 3),
             "gmres": {"status": rc, "iterations": its, "seconds": round(t_solve, 3),

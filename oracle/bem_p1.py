@@ -325,3 +325,98 @@ def lumped_preconditioned(m: Mesh, A):
     """diag(Ml, Ml)^-1 A."""
     d = np.concatenate([lumped_mass(m)] * 2)
     return A / d[:, None]
+
+
+def matvec_rows(m: Mesh, rows, x, eps1=4.0, eps2=80.0, kappa=0.125, n_outer: int = 8, n_rem: int = 4,
+                chunk: int = 1 << 23):
+    """Rows `rows` (vertex indices) of the P1 exterior system times x for any
+    mesh size, (len(rows), 2).  Each row is a sum over the triangle corners
+    at the vertex: the fields of all quadrature-point sources (the vertex
+    values interpolated; V, K and K' through the C direct sum, K' as n_s .
+    grad of the single-layer potential, W_Y - W_L in NumPy over source
+    chunks) weighted by W_j lambda_a(xi_j), the singular pairs' blocks
+    swapped for accurate ones (K' from the transposed pair), and the mass
+    matrix.  Every vertex must lie on a triangle."""
+    from . import direct as Dd
+    nv = len(m.verts)
+    T, k = m.qw.shape
+    u, v = x[:nv], x[nv:]
+    bary, _ = bem.regular_rule(k)
+    uq = np.einsum("ja,ta->tj", bary, u[m.tris]).reshape(-1)
+    vq = np.einsum("ja,ta->tj", bary, v[m.tris]).reshape(-1)
+    Y = m.qpts.reshape(-1, 3)
+    W = m.qw.reshape(-1)
+    n_rep = np.repeat(m.normal, k, axis=0)
+    uu, vv = W * uq, W * vq
+    e12 = eps1 / eps2
+    out = np.zeros((len(rows), 2))
+    for r_i, vi in enumerate(np.asarray(rows)):
+        ss, aa = np.nonzero(m.tris == vi)                       # corners (s, a) at the vertex
+        tgt = m.qpts[ss].reshape(-1, 3)
+        wt = (m.qw[ss] * bary[:, aa].T).reshape(-1)              # W_j lambda_a(xi_j)
+        nt = np.repeat(m.normal[ss], k, axis=0)
+        fields = {}
+        for kern, kap in (("laplace", 0.0), ("yukawa", kappa)):
+            Kx = np.zeros(len(tgt))
+            for d in range(3):
+                _, g = Dd.direct(tgt, Y, uu * n_rep[:, d], kern, kap)
+                Kx -= g[:, d]
+            Vx, gv = Dd.direct(tgt, Y, vv, kern, kap)
+            fields[kern] = [float(wt @ Vx), float(wt @ Kx), float(wt @ np.sum(nt * gv, axis=1))]
+        # W_Y - W_L: all of the row's targets against a chunk of sources at a time
+        tot = np.zeros(len(tgt))
+        step = max(1, chunk // len(tgt))
+        for c0 in range(0, len(Y), step):
+            dd = tgt[:, None, :] - Y[None, c0:c0 + step]
+            r = np.linalg.norm(dd, axis=-1)
+            pos = r > 0
+            dd = np.where(pos[..., None], dd, 1.0)
+            kv = bem.hyper_diff_kernel(dd, nt[:, None, :], n_rep[None, c0:c0 + step], kappa)
+            tot += np.where(pos, kv, 0.0) @ uu[c0:c0 + step]
+        Wr = float(wt @ tot)
+        mu = mv = 0.0
+        for s_, a_ in zip(ss, aa):
+            ts = np.nonzero(np.isin(m.tris, m.tris[s_]).any(axis=1))[0]
+            S = np.full(len(ts), s_)
+            ut, vt = u[m.tris[ts]], v[m.tris[ts]]                 # (P, 3) trial values
+            for kern, kap in (("laplace", 0.0), ("yukawa", kappa)):
+                Vs, Ks, _ = singular_blocks(m, S, ts, kap, n_outer, n_rem)
+                Vr, Kr, _ = regular_blocks(m, S, ts, kap)
+                _, Kts, _ = singular_blocks(m, ts, S, kap, n_outer, n_rem)
+                _, Ktr, _ = regular_blocks(m, ts, S, kap)
+                fields[kern][0] += float(np.sum((Vs - Vr)[:, a_, :] * vt))
+                fields[kern][1] += float(np.sum((Ks - Kr)[:, a_, :] * ut))
+                fields[kern][2] += float(np.sum((Kts - Ktr)[:, :, a_] * vt))
+            _, _, Ws = singular_blocks(m, S, ts, kappa, n_outer, n_rem)
+            _, _, Wreg = regular_blocks(m, S, ts, kappa)
+            Wr += float(np.sum((Ws - Wreg)[:, a_, :] * ut))
+            loc = m.area[s_] / 12.0
+            mu += loc * (u[vi] + u[m.tris[s_]].sum())
+            mv += loc * (v[vi] + v[m.tris[s_]].sum())
+        VL, KL, KpL = fields["laplace"]
+        VY, KY, KpY = fields["yukawa"]
+        out[r_i, 0] = 0.5 * (1 + e12) * mu - (KY - e12 * KL) + (VY - VL)
+        out[r_i, 1] = e12 * Wr + 0.5 * (1 + e12) * mv + (e12 * KpY - KpL)
+    return out
+
+
+def energy_direct(m: Mesh, x, qxyz, q, eps1=4.0, eps2=80.0):
+    """energy() through the C direct sum for meshes too large for the dense
+    kernel matrix: the interior unknowns interpolated to the quadrature
+    points, then the P0 oracle's direct-sum reaction potential."""
+    nv = len(m.verts)
+    k = m.qpts.shape[1]
+    bary, _ = bem.regular_rule(k)
+    # per-triangle "P0" arrays holding the interpolated quadrature values
+    uq = np.einsum("ja,ta->tj", bary, x[:nv][m.tris])
+    vq = (eps2 / eps1) * np.einsum("ja,ta->tj", bary, x[nv:][m.tris])
+    from . import direct as Dd
+    Y = m.qpts.reshape(-1, 3)
+    W = m.qw.reshape(-1)
+    nY = np.repeat(m.normal, k, axis=0)
+    tgt = np.ascontiguousarray(qxyz, dtype=np.float64).reshape(-1, 3)
+    phi, _ = Dd.direct(tgt, Y, W * vq.reshape(-1))
+    for d in range(3):
+        _, g = Dd.direct(tgt, Y, W * uq.reshape(-1) * nY[:, d])
+        phi += g[:, d]
+    return 0.5 * float(np.dot(q, phi)) * FOUR_PI * bem.KCAL_PER_MOL

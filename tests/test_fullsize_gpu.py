@@ -318,3 +318,42 @@ def test_bem2m_derivative_matvec_rows(bem2m, formulation):
     e = _rel(np.stack([y[rows], y[T + rows]], axis=1), ref)
     _say(f"[bem 2M {formulation} bf16x3] matvec rows {e:.2e}")
     assert e < 1e-4
+
+
+def test_bem2m_exterior_p1(bem2m):
+    """The exterior formulation on P1 elements on the 2M-triangle mesh
+    (bf16x3 as the benchmark runs it): bem_matvec against oracle rows on 3
+    sampled vertices, then GMRES to 1e-6 with FP64 refinement, the FP64
+    operator's residual, and the energy of 256 sampled charges against the
+    oracle's for the same solution."""
+    torch = require_gpu()
+    from oracle import bem_p1 as P1
+    from paper_2103_01048_amd import BEMOperator, gmres
+    from paper_2103_01048_amd import _lib
+    v, t, _, qxyz, q = bem2m
+    v, t = synth.used_vertices_only(v, t)
+    m = B.make_mesh(v, t, 3)
+    nv = len(v)
+    kw = dict(quad_pts=3, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=8, ncrit=128, formulation="exterior_p1")
+    op32 = BEMOperator(v, t, precision="bf16x3", **kw)
+    rng = np.random.default_rng(95)
+    x = rng.standard_normal(2 * nv)
+    y = op32.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
+    rows = rng.choice(nv, 3, replace=False)
+    ref = P1.matvec_rows(m, rows, x, 4.0, 80.0, KAPPA)
+    e = _rel(np.stack([y[rows], y[nv + rows]], axis=1), ref)
+    _say(f"[bem 2M exterior P1 bf16x3] matvec rows {e:.2e}")
+    assert e < 1e-4
+    op64 = BEMOperator(v, t, precision="fp64", **kw)
+    b = op32.rhs(qxyz, q)
+    xs, its, hist, rc = gmres(op32, b, tol=1e-6, maxiter=200, restart=100, refine=op64, inner_tol=1e-3)
+    r = (b - op64.matvec(xs)).norm().item() / b.norm().item()
+    _say(f"[bem 2M exterior P1] status {rc} iterations {its} residual {r:.2e}")
+    assert rc == _lib.FMM_OK and r <= 1e-6
+    sel = np.random.default_rng(96).choice(len(q), 256, replace=False)
+    eg = op32.energy(xs, qxyz[sel], q[sel])
+    eo = P1.energy_direct(m, xs.cpu().numpy(), qxyz[sel], q[sel])
+    assert abs(eg - eo) <= 1e-9 * abs(eo)
+    e_all = op32.energy(xs, qxyz, q)
+    _say(f"[bem 2M exterior P1] energy {e_all:.4f} kcal/mol")
+    assert e_all < 0

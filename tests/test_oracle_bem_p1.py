@@ -159,3 +159,25 @@ def test_exterior_p1_kirkwood_convergence_and_spectrum():
     order = math.log(err[0] / err[1]) / math.log(4.0)
     assert 0.85 < order < 1.15, (err, order)
     assert err[1] < 0.015 * abs(ref)
+
+
+def test_matvec_rows_equal_dense_rows():
+    """The row routine used at full size reproduces the dense P1 system."""
+    v, t = synth.octa_sphere(2, 4.0)
+    m = bem.make_mesh(v, t, 3)
+    A_ = P.system_exterior(m, 4.0, 80.0, KAPPA)
+    nv = len(v)
+    x = np.random.default_rng(36).standard_normal(2 * nv)
+    rows = np.array([0, 5, 33, nv - 1])
+    got = P.matvec_rows(m, rows, x, 4.0, 80.0, KAPPA)
+    ref = A_ @ x
+    np.testing.assert_allclose(got[:, 0], ref[rows], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(got[:, 1], ref[nv + rows], rtol=1e-10, atol=1e-12)
+
+
+def test_energy_direct_equals_dense_energy():
+    v, t = synth.octa_sphere(2, 4.0)
+    m = bem.make_mesh(v, t, 3)
+    x = np.random.default_rng(37).standard_normal(2 * len(v))
+    qx, q = [[1.0, 1.0, 1.0], [-0.6, 0.3, -0.2]], [1.0, -0.5]
+    assert P.energy_direct(m, x, qx, q) == pytest.approx(P.energy(m, x, qx, q), rel=1e-12)
