@@ -337,7 +337,8 @@ __device__ void tri_lin_moments(D3 x, const D3 *v, D3 n, D3 &G, D3 &dH) {
 
 // One thread per singular pair (s, t): the 3 x 3 blocks [corner of s][corner
 // of t] of S - C for V_L, K_L, V_Y, K_Y and W_Y - W_L with hat-function
-// weights, B[k][op][a][b] (45 doubles per pair).  S: the Laplace inner
+// weights, stored pair-minor: B[(9 op + 3 a + b) * npair + k] (45 arrays of
+// npair doubles, so that consecutive pairs read consecutive addresses).  S: the Laplace inner
 // integral in closed form for the linear density on t, the outer integral on
 // the collapsed rule; the bounded Yukawa-minus-Laplace remainders (and the
 // non-1/r part of W_Y - W_L) on the collapsed rule on both triangles.  C:
@@ -469,14 +470,60 @@ __global__ __launch_bounds__(128) void k_singular_p1(int64_t npair, const int32_
         }
     }
   }
-  double *o = B + k * 45;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    o[i] = VL[i];
-    o[9 + i] = KL[i];
-    o[18 + i] = VY[i];
-    o[27 + i] = KY[i];
-    o[36 + i] = W[i];
+    B[(0 + i) * npair + k] = VL[i];
+    B[(9 + i) * npair + k] = KL[i];
+    B[(18 + i) * npair + k] = VY[i];
+    B[(27 + i) * npair + k] = KY[i];
+    B[(36 + i) * npair + k] = W[i];
+  }
+}
+
+// The K' blocks of every pair (s, t) from the transposed pair's K blocks,
+// KT[(9 kern + 3 a + b) * npair + k] = K_kern[t, s][b][a] (kern 0: Laplace,
+// 1: Yukawa), pair-minor like B.
+__global__ void k_p1_transpose(int64_t npair, const int32_t *__restrict__ tr, const double *__restrict__ B,
+                               double *__restrict__ KT) {
+  const int64_t k = blockIdx.x * 256ll + threadIdx.x;
+  if (k >= npair) return;
+  const int64_t kt = tr[k];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      KT[(3 * a + b) * npair + k] = B[(9 + 3 * b + a) * npair + kt];
+      KT[(9 + 3 * a + b) * npair + k] = B[(27 + 3 * b + a) * npair + kt];
+    }
+}
+
+// One thread per singular pair (s, t): the S - C terms of both rows for the
+// three corners of s, from t's vertex values:
+//   P[a]     = sum_b c1L (K_L u_b + sL V_L v_b) - c1Y (K_Y u_b + sY V_Y v_b)
+//   P[3 + a] = sum_b (W_Y - W_L) u_b + sL K'_L v_b - sY K'_Y v_b
+// (pair-minor, P[j * npair + k]); k_p1_corner adds them per triangle.
+__global__ void k_p1_pairs(int64_t npair, const int32_t *__restrict__ pt, const int32_t *__restrict__ tris,
+                           const double *__restrict__ B, const double *__restrict__ KT, const double *__restrict__ x,
+                           int64_t nv, DerivCoef c, double *__restrict__ P) {
+  const int64_t k = blockIdx.x * 256ll + threadIdx.x;
+  if (k >= npair) return;
+  const int t = pt[k];
+  double u[3], v[3];
+  for (int b = 0; b < 3; ++b) {
+    const int32_t vb = tris[3 * t + b];
+    u[b] = x[vb];
+    v[b] = x[nv + vb];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double p1 = 0, p2 = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int ab = 3 * a + b;
+      p1 += c.c1L * (B[(9 + ab) * npair + k] * u[b] + c.sL * B[ab * npair + k] * v[b]) -
+            c.c1Y * (B[(27 + ab) * npair + k] * u[b] + c.sY * B[(18 + ab) * npair + k] * v[b]);
+      p2 += B[(36 + ab) * npair + k] * u[b] + c.sL * KT[ab * npair + k] * v[b] - c.sY * KT[(9 + ab) * npair + k] * v[b];
+    }
+    P[a * npair + k] = p1;
+    P[(3 + a) * npair + k] = p2;
   }
 }
 
@@ -508,8 +555,8 @@ __global__ void k_p1_src(int64_t nt, int nq, const int32_t *__restrict__ tris, c
 
 // Exterior formulation on P1 elements, per triangle s and corner a (the
 // test function lambda_a on s): the quadrature-point fields weighted by
-// W_j lambda_a(xi_j), the S - C blocks of s's singular pairs (K' from the
-// transposed pair's K block), and s's part of the mass matrix
+// W_j lambda_a(xi_j), the S - C terms of s's singular pairs (k_p1_pairs, in
+// pair order), and s's part of the mass matrix
 // (A/12 (1 + delta_ab)); cb[s][a][0..1] for the two rows, added into the
 // vertices by k_p1_gather.  Coefficients as k_bem_p2_deriv.
 template <typename T>
@@ -517,8 +564,7 @@ __global__ void k_p1_corner(int64_t nt, int nq, const T *__restrict__ potl, cons
                             const T *__restrict__ poty, const T *__restrict__ grady, const double *__restrict__ qw,
                             const double *__restrict__ rule_q, const double *__restrict__ area,
                             const double *__restrict__ normal, const int32_t *__restrict__ tris,
-                            const int32_t *__restrict__ sp_off, const int32_t *__restrict__ sp_idx,
-                            const int32_t *__restrict__ sp_tr, const double *__restrict__ B,
+                            const int32_t *__restrict__ sp_off, int64_t npair, const double *__restrict__ P,
                             const double *__restrict__ x, int64_t nv, DerivCoef c, double *__restrict__ cb) {
   const int64_t s = blockIdx.x * 256ll + threadIdx.x;
   if (s >= nt) return;
@@ -538,19 +584,11 @@ __global__ void k_p1_corner(int64_t nt, int nq, const T *__restrict__ potl, cons
     }
   }
   double b1[3] = {0, 0, 0}, b2[3] = {0, 0, 0};
-  for (int k = sp_off[s]; k < sp_off[s + 1]; ++k) {
-    const int t = sp_idx[k], kt = sp_tr[k];
-    const double *Bk = B + (int64_t)k * 45, *Bt = B + (int64_t)kt * 45;
-    for (int b = 0; b < 3; ++b) {
-      const int32_t vb = tris[3 * t + b];
-      const double u = x[vb], v = x[nv + vb];
-      for (int a = 0; a < 3; ++a) {
-        const int ab = 3 * a + b, ba = 3 * b + a;
-        b1[a] += c.c1L * (Bk[9 + ab] * u + c.sL * Bk[ab] * v) - c.c1Y * (Bk[27 + ab] * u + c.sY * Bk[18 + ab] * v);
-        b2[a] += Bk[36 + ab] * u + c.sL * Bt[9 + ba] * v - c.sY * Bt[27 + ba] * v;
-      }
+  for (int k = sp_off[s]; k < sp_off[s + 1]; ++k)
+    for (int a = 0; a < 3; ++a) {
+      b1[a] += P[a * npair + k];
+      b2[a] += P[(3 + a) * npair + k];
     }
-  }
   double us = 0, vs = 0, ua[3], va[3];
   for (int a = 0; a < 3; ++a) {
     const int32_t vi = tris[3 * s + a];
@@ -964,12 +1002,13 @@ struct bem_op {
   int32_t *d_sp_tr = nullptr;
   // P1 elements (FMM_BEM_EXTERIOR_P1): nu = nv unknowns per block (nt for
   // P0), the triangles' vertex indices, per vertex its corners (3 s + a,
-  // ascending), the regular rule, the S - C blocks (45 per pair) and the
-  // per-corner row sums
+  // ascending), the regular rule, and pair-minor arrays: the S - C blocks
+  // (45 per pair), the K' blocks from the transposed pairs (18 per pair) and
+  // the per-pair row terms of a matvec (6 per pair); the per-corner row sums
   bool p1 = false;
   int64_t nu = 0;
   int32_t *d_tris = nullptr, *d_vt_off = nullptr, *d_vt_list = nullptr;
-  double *d_rq = nullptr, *d_B = nullptr, *d_cb = nullptr;
+  double *d_rq = nullptr, *d_B = nullptr, *d_KT = nullptr, *d_P = nullptr, *d_cb = nullptr;
   void *q4 = nullptr, *potl = nullptr, *poty = nullptr, *gradl = nullptr, *grady = nullptr;
   // GMRES / energy scratch
   double *d_partial = nullptr, *d_h = nullptr, *d_V = nullptr, *d_z = nullptr, *d_w = nullptr, *d_r = nullptr,
@@ -1164,10 +1203,14 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
       if ((rc = bupload(op, &op->d_vt_off, voff))) break;
       if ((rc = bupload(op, &op->d_vt_list, vlist))) break;
       if ((rc = balloc(op, (void **)&op->d_B, op->npair * 45 * sizeof(double)))) break;
+      if ((rc = balloc(op, (void **)&op->d_KT, op->npair * 18 * sizeof(double)))) break;
+      if ((rc = balloc(op, (void **)&op->d_P, op->npair * 6 * sizeof(double)))) break;
       if ((rc = balloc(op, (void **)&op->d_cb, nt * 6 * sizeof(double)))) break;
       hipLaunchKernelGGL(k_singular_p1, dim3(blocks(op->npair, 128)), dim3(128), 0, s, op->npair, d_ps,
                          op->d_sp_idx, op->d_tri, op->d_normal, op->d_area, d_ro, NO * NO, d_rr, NREM * NREM, d_rq,
                          quad_pts, kappa, op->d_B);
+      hipLaunchKernelGGL(k_p1_transpose, dim3(blocks(op->npair)), dim3(256), 0, s, op->npair, op->d_sp_tr, op->d_B,
+                         op->d_KT);
     } else {
       if ((rc = balloc(op, (void **)&op->d_D, op->npair * 4 * sizeof(double)))) break;
       if ((rc = balloc(op, (void **)&op->d_sdiag, nt * 2 * sizeof(double)))) break;
@@ -1230,16 +1273,18 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
     if ((rc = fmm_eval_pair_md(op->fl, op->fy, qq, qq + Nq * es, dc.sL, dc.sY, op->potl, op->gradl, op->poty,
                                op->grady, s)))
       return rc;
+    hipLaunchKernelGGL(k_p1_pairs, dim3(blocks(op->npair)), dim3(256), 0, s, op->npair, op->d_sp_idx, op->d_tris,
+                       op->d_B, op->d_KT, x, op->nv, dc, op->d_P);
     if (op->precision == FMM_FP64)
       hipLaunchKernelGGL(k_p1_corner<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const double *)op->potl,
                          (const double *)op->gradl, (const double *)op->poty, (const double *)op->grady, op->d_qw,
-                         op->d_rq, op->d_area, op->d_normal, op->d_tris, op->d_sp_off, op->d_sp_idx, op->d_sp_tr,
-                         op->d_B, x, op->nv, dc, op->d_cb);
+                         op->d_rq, op->d_area, op->d_normal, op->d_tris, op->d_sp_off, op->npair, op->d_P, x, op->nv,
+                         dc, op->d_cb);
     else
       hipLaunchKernelGGL(k_p1_corner<float>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const float *)op->potl,
                          (const float *)op->gradl, (const float *)op->poty, (const float *)op->grady, op->d_qw,
-                         op->d_rq, op->d_area, op->d_normal, op->d_tris, op->d_sp_off, op->d_sp_idx, op->d_sp_tr,
-                         op->d_B, x, op->nv, dc, op->d_cb);
+                         op->d_rq, op->d_area, op->d_normal, op->d_tris, op->d_sp_off, op->npair, op->d_P, x, op->nv,
+                         dc, op->d_cb);
     hipLaunchKernelGGL(k_p1_gather, dim3(blocks(op->nv)), dim3(256), 0, s, op->nv, op->d_vt_off, op->d_vt_list,
                        op->d_cb, y);
     FMM_HIP_TRY(hipGetLastError());
