@@ -113,3 +113,16 @@ def test_p1_rejects_a_vertex_on_no_triangle():
     v = np.concatenate([v, [[9.0, 9.0, 9.0]]])
     with pytest.raises(RuntimeError):
         _op(v, t, "fp64")
+
+
+def test_p1_no_charges_and_determinism(sphere512):
+    """No charges: a zero right-hand side and zero energy; two matvecs of the
+    same vector are bitwise equal (fixed-order sums per vertex)."""
+    torch = require_gpu()
+    v, t, m, _ = sphere512
+    op = _op(v, t, "bf16x3")
+    b = op.rhs(np.zeros((0, 3)), np.zeros(0)).cpu().numpy()
+    assert b.shape == (2 * len(v),) and not b.any()
+    x = torch.tensor(np.random.default_rng(174).standard_normal(2 * len(v)), device="cuda")
+    assert op.energy(x, np.zeros((0, 3)), np.zeros(0)) == 0.0
+    assert torch.equal(op.matvec(x), op.matvec(x))

@@ -1,6 +1,6 @@
 """HIP graph capture of the hot path: one fmm_eval_pair step (which forks
 its far-field passes to a side stream and joins them back) and one
-bem_matvec are captured with torch.cuda.graph and replayed several times,
+bem_matvec (P0 direct and P1 exterior) are captured with torch.cuda.graph and replayed several times,
 with eager work and synchronisation between the replays; every replay must
 equal the eager result bitwise (the evaluation is deterministic and records
 no memset or allocation)."""
@@ -50,12 +50,13 @@ def test_pair_step_graph_replays_equal_eager():
         torch.cuda.synchronize()
 
 
-def test_bem_matvec_graph_replays_equal_eager():
+@pytest.mark.parametrize("formulation", ["direct", "exterior_p1"])
+def test_bem_matvec_graph_replays_equal_eager(formulation):
     torch = require_gpu()
     from paper_2103_01048_amd import BEMOperator
     v, t = synth.octa_sphere(4, 4.0)
-    op = BEMOperator(v, t, quad_pts=3, p=6, ncrit=64, precision="fp32")
-    x = torch.tensor(np.random.default_rng(132).standard_normal(2 * len(t)), device="cuda")
+    op = BEMOperator(v, t, quad_pts=3, p=6, ncrit=64, precision="fp32", formulation=formulation)
+    x = torch.tensor(np.random.default_rng(132).standard_normal(2 * op.nu), device="cuda")
     ref = op.matvec(x).clone()
     g, out = _capture(torch, lambda: op.matvec(x))
     for _ in range(3):
