@@ -560,14 +560,36 @@ __global__ void k_p1_src(int64_t nt, int nq, const int32_t *__restrict__ tris, c
 // (A/12 (1 + delta_ab)); cb[s][a][0..1] for the two rows, added into the
 // vertices by k_p1_gather.  Coefficients as k_bem_p2_deriv.
 template <typename T>
-__global__ void k_p1_corner(int64_t nt, int nq, const T *__restrict__ potl, const T *__restrict__ gradl,
-                            const T *__restrict__ poty, const T *__restrict__ grady, const double *__restrict__ qw,
-                            const double *__restrict__ rule_q, const double *__restrict__ area,
-                            const double *__restrict__ normal, const int32_t *__restrict__ tris,
-                            const int32_t *__restrict__ sp_off, int64_t npair, const double *__restrict__ P,
-                            const double *__restrict__ x, int64_t nv, DerivCoef c, double *__restrict__ cb) {
-  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
-  if (s >= nt) return;
+__global__ __launch_bounds__(64) void k_p1_corner(int64_t nt, int nq, const T *__restrict__ potl,
+                                                  const T *__restrict__ gradl, const T *__restrict__ poty,
+                                                  const T *__restrict__ grady, const double *__restrict__ qw,
+                                                  const double *__restrict__ rule_q, const double *__restrict__ area,
+                                                  const double *__restrict__ normal, const int32_t *__restrict__ tris,
+                                                  const int32_t *__restrict__ sp_off, int64_t npair,
+                                                  const double *__restrict__ P, const double *__restrict__ x,
+                                                  int64_t nv, DerivCoef c, double *__restrict__ cb) {
+  // one wave per 64 consecutive triangles; their pairs are one contiguous
+  // range, staged through LDS 256 pairs at a time with coalesced loads, each
+  // lane adding its own pairs in ascending order
+  __shared__ double sP[6][256];
+  const int64_t s0 = (int64_t)blockIdx.x * 64, s = s0 + threadIdx.x;
+  const bool act = s < nt;
+  const int k_lo = sp_off[s0], k_hi = sp_off[min(nt, s0 + 64)];
+  const int my0 = act ? sp_off[s] : 0, my1 = act ? sp_off[s + 1] : 0;
+  double b1[3] = {0, 0, 0}, b2[3] = {0, 0, 0};
+  for (int c0 = k_lo; c0 < k_hi; c0 += 256) {
+    const int c1 = min(k_hi, c0 + 256);
+    for (int i = threadIdx.x; i < c1 - c0; i += 64)
+      for (int j = 0; j < 6; ++j) sP[j][i] = P[j * npair + c0 + i];
+    __syncthreads();
+    for (int k = max(my0, c0); k < min(my1, c1); ++k)
+      for (int a = 0; a < 3; ++a) {
+        b1[a] += sP[a][k - c0];
+        b2[a] += sP[3 + a][k - c0];
+      }
+    __syncthreads();
+  }
+  if (!act) return;
   const double n0 = normal[3 * s], n1 = normal[3 * s + 1], n2 = normal[3 * s + 2];
   double r1[3] = {0, 0, 0}, r2[3] = {0, 0, 0};
   for (int j = 0; j < nq; ++j) {
@@ -583,12 +605,6 @@ __global__ void k_p1_corner(int64_t nt, int nq, const T *__restrict__ potl, cons
       r2[a] += la[a] * f2;
     }
   }
-  double b1[3] = {0, 0, 0}, b2[3] = {0, 0, 0};
-  for (int k = sp_off[s]; k < sp_off[s + 1]; ++k)
-    for (int a = 0; a < 3; ++a) {
-      b1[a] += P[a * npair + k];
-      b2[a] += P[(3 + a) * npair + k];
-    }
   double us = 0, vs = 0, ua[3], va[3];
   for (int a = 0; a < 3; ++a) {
     const int32_t vi = tris[3 * s + a];
@@ -1276,12 +1292,12 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
     hipLaunchKernelGGL(k_p1_pairs, dim3(blocks(op->npair)), dim3(256), 0, s, op->npair, op->d_sp_idx, op->d_tris,
                        op->d_B, op->d_KT, x, op->nv, dc, op->d_P);
     if (op->precision == FMM_FP64)
-      hipLaunchKernelGGL(k_p1_corner<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const double *)op->potl,
+      hipLaunchKernelGGL(k_p1_corner<double>, dim3(blocks(nt, 64)), dim3(64), 0, s, nt, op->nq, (const double *)op->potl,
                          (const double *)op->gradl, (const double *)op->poty, (const double *)op->grady, op->d_qw,
                          op->d_rq, op->d_area, op->d_normal, op->d_tris, op->d_sp_off, op->npair, op->d_P, x, op->nv,
                          dc, op->d_cb);
     else
-      hipLaunchKernelGGL(k_p1_corner<float>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const float *)op->potl,
+      hipLaunchKernelGGL(k_p1_corner<float>, dim3(blocks(nt, 64)), dim3(64), 0, s, nt, op->nq, (const float *)op->potl,
                          (const float *)op->gradl, (const float *)op->poty, (const float *)op->grady, op->d_qw,
                          op->d_rq, op->d_area, op->d_normal, op->d_tris, op->d_sp_off, op->npair, op->d_P, x, op->nv,
                          dc, op->d_cb);
