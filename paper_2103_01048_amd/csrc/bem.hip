@@ -740,25 +740,43 @@ __global__ void k_bem_p1_md(int64_t nt, int nq, const double *__restrict__ x, co
 // eps_out) V_Y v (regular parts), so
 //   y1 = M u / 2 + P2^T pot_L + (S - C) terms,  y2 = M u / 2 - P2^T pot_Y + (S - C) terms.
 template <typename T>
-__global__ void k_bem_p2_md(int64_t nt, int nq, const T *__restrict__ potl, const T *__restrict__ poty,
-                            const double *__restrict__ qw, const double *__restrict__ area,
-                            const int32_t *__restrict__ sp_off, const int32_t *__restrict__ sp_idx,
-                            const double *__restrict__ Dval, const double *__restrict__ x, double eratio,
-                            double *__restrict__ y) {
-  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
-  if (s >= nt) return;
+__global__ __launch_bounds__(64) void k_bem_p2_md(int64_t nt, int nq, const T *__restrict__ potl,
+                                                  const T *__restrict__ poty, const double *__restrict__ qw,
+                                                  const double *__restrict__ area, const int32_t *__restrict__ sp_off,
+                                                  const int32_t *__restrict__ sp_idx, const double *__restrict__ Dval,
+                                                  const double *__restrict__ x, double eratio,
+                                                  double *__restrict__ y) {
+  // one wave per 64 consecutive triangles: their singular pairs are one
+  // contiguous range, staged through LDS 256 pairs at a time with coalesced
+  // loads; each lane adds its own pairs in ascending order
+  __shared__ double sD[256 * 4];
+  __shared__ int32_t sT[256];
+  const int64_t s0 = (int64_t)blockIdx.x * 64, s = s0 + threadIdx.x;
+  const bool act = s < nt;
+  const int k_lo = sp_off[s0], k_hi = sp_off[min(nt, s0 + 64)];
+  const int my0 = act ? sp_off[s] : 0, my1 = act ? sp_off[s + 1] : 0;
   double al = 0, ay = 0;
-  for (int a = 0; a < nq; ++a) {
-    const int64_t i = s * nq + a;
-    al += qw[i] * (double)potl[i];
-    ay += qw[i] * (double)poty[i];
+  if (act)
+    for (int a = 0; a < nq; ++a) {
+      const int64_t i = s * nq + a;
+      al += qw[i] * (double)potl[i];
+      ay += qw[i] * (double)poty[i];
+    }
+  for (int c0 = k_lo; c0 < k_hi; c0 += 256) {
+    const int c1 = min(k_hi, c0 + 256);
+    for (int i = threadIdx.x; i < 4 * (c1 - c0); i += 64) sD[i] = Dval[4 * (int64_t)c0 + i];
+    for (int i = threadIdx.x; i < c1 - c0; i += 64) sT[i] = sp_idx[c0 + i];
+    __syncthreads();
+    for (int k = max(my0, c0); k < min(my1, c1); ++k) {
+      const int t = sT[k - c0];
+      const double *D = sD + 4 * (k - c0);
+      const double u = x[t], v = x[nt + t];
+      al += D[1] * u - D[0] * v;
+      ay += D[3] * u - eratio * D[2] * v;
+    }
+    __syncthreads();
   }
-  for (int k = sp_off[s]; k < sp_off[s + 1]; ++k) {
-    const int t = sp_idx[k];
-    const double u = x[t], v = x[nt + t];
-    al += Dval[4 * k + 1] * u - Dval[4 * k + 0] * v;
-    ay += Dval[4 * k + 3] * u - eratio * Dval[4 * k + 2] * v;
-  }
+  if (!act) return;
   const double hu = 0.5 * area[s] * x[s];
   y[s] = hu + al;
   y[nt + s] = hu - ay;
@@ -768,32 +786,53 @@ __global__ void k_bem_p2_md(int64_t nt, int nq, const T *__restrict__ potl, cons
 // DerivCoef), regular parts from the FMM plus the S - C terms; the K'
 // corrections are those of K on the transposed pair.
 template <typename T>
-__global__ void k_bem_p2_deriv(int64_t nt, int nq, const T *__restrict__ potl, const T *__restrict__ gradl,
-                               const T *__restrict__ poty, const T *__restrict__ grady, const double *__restrict__ qw,
-                               const double *__restrict__ area, const double *__restrict__ normal,
-                               const int32_t *__restrict__ sp_off, const int32_t *__restrict__ sp_idx,
-                               const int32_t *__restrict__ sp_tr, const double *__restrict__ Dval,
-                               const double *__restrict__ Dw, const double *__restrict__ x, DerivCoef c,
-                               double *__restrict__ y) {
-  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
-  if (s >= nt) return;
-  const double n0 = normal[3 * s], n1 = normal[3 * s + 1], n2 = normal[3 * s + 2];
+__global__ __launch_bounds__(64) void k_bem_p2_deriv(
+    int64_t nt, int nq, const T *__restrict__ potl, const T *__restrict__ gradl, const T *__restrict__ poty,
+    const T *__restrict__ grady, const double *__restrict__ qw, const double *__restrict__ area,
+    const double *__restrict__ normal, const int32_t *__restrict__ sp_off, const int32_t *__restrict__ sp_idx,
+    const int32_t *__restrict__ sp_tr, const double *__restrict__ Dval, const double *__restrict__ Dw,
+    const double *__restrict__ x, DerivCoef c, double *__restrict__ y) {
+  // staging as in k_bem_p2_md; the loading lanes also fetch the transposed
+  // pairs' K values
+  __shared__ double sD[256 * 4], sW[256], sKt[256 * 2];
+  __shared__ int32_t sT[256];
+  const int64_t s0 = (int64_t)blockIdx.x * 64, s = s0 + threadIdx.x;
+  const bool act = s < nt;
+  const int k_lo = sp_off[s0], k_hi = sp_off[min(nt, s0 + 64)];
+  const int my0 = act ? sp_off[s] : 0, my1 = act ? sp_off[s + 1] : 0;
   double a1 = 0, a2 = 0;
-  for (int a = 0; a < nq; ++a) {
-    const int64_t i = s * nq + a;
-    a1 += qw[i] * (c.c1L * (double)potl[i] - c.c1Y * (double)poty[i]);
-    a2 += qw[i] * (n0 * ((double)gradl[3 * i] - (double)grady[3 * i]) +
-                   n1 * ((double)gradl[3 * i + 1] - (double)grady[3 * i + 1]) +
-                   n2 * ((double)gradl[3 * i + 2] - (double)grady[3 * i + 2]));
+  if (act) {
+    const double n0 = normal[3 * s], n1 = normal[3 * s + 1], n2 = normal[3 * s + 2];
+    for (int a = 0; a < nq; ++a) {
+      const int64_t i = s * nq + a;
+      a1 += qw[i] * (c.c1L * (double)potl[i] - c.c1Y * (double)poty[i]);
+      a2 += qw[i] * (n0 * ((double)gradl[3 * i] - (double)grady[3 * i]) +
+                     n1 * ((double)gradl[3 * i + 1] - (double)grady[3 * i + 1]) +
+                     n2 * ((double)gradl[3 * i + 2] - (double)grady[3 * i + 2]));
+    }
   }
   double b1 = 0, b2 = 0;
-  for (int k = sp_off[s]; k < sp_off[s + 1]; ++k) {
-    const int t = sp_idx[k], kt = sp_tr[k];
-    const double u = x[t], v = x[nt + t];
-    b1 += c.c1L * (Dval[4 * k + 1] * u + c.sL * Dval[4 * k + 0] * v) -
-          c.c1Y * (Dval[4 * k + 3] * u + c.sY * Dval[4 * k + 2] * v);
-    b2 += Dw[k] * u + c.sL * Dval[4 * kt + 1] * v - c.sY * Dval[4 * kt + 3] * v;
+  for (int c0 = k_lo; c0 < k_hi; c0 += 256) {
+    const int c1 = min(k_hi, c0 + 256);
+    for (int i = threadIdx.x; i < 4 * (c1 - c0); i += 64) sD[i] = Dval[4 * (int64_t)c0 + i];
+    for (int i = threadIdx.x; i < c1 - c0; i += 64) {
+      const int k = c0 + i, kt = sp_tr[k];
+      sT[i] = sp_idx[k];
+      sW[i] = Dw[k];
+      sKt[2 * i] = Dval[4 * (int64_t)kt + 1];
+      sKt[2 * i + 1] = Dval[4 * (int64_t)kt + 3];
+    }
+    __syncthreads();
+    for (int k = max(my0, c0); k < min(my1, c1); ++k) {
+      const int i = k - c0, t = sT[i];
+      const double *D = sD + 4 * i;
+      const double u = x[t], v = x[nt + t];
+      b1 += c.c1L * (D[1] * u + c.sL * D[0] * v) - c.c1Y * (D[3] * u + c.sY * D[2] * v);
+      b2 += sW[i] * u + c.sL * sKt[2 * i] * v - c.sY * sKt[2 * i + 1] * v;
+    }
+    __syncthreads();
   }
+  if (!act) return;
   y[s] = c.d1 * area[s] * x[s] + a1 + b1;
   y[nt + s] = c.d2 * area[s] * x[nt + s] + c.c2 * (a2 + b2);
 }
@@ -1325,12 +1364,12 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
   }
   if (deriv) {
     if (op->precision == FMM_FP64)
-      hipLaunchKernelGGL(k_bem_p2_deriv<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq,
+      hipLaunchKernelGGL(k_bem_p2_deriv<double>, dim3(blocks(nt, 64)), dim3(64), 0, s, nt, op->nq,
                          (const double *)op->potl, (const double *)op->gradl, (const double *)op->poty,
                          (const double *)op->grady, op->d_qw, op->d_area, op->d_normal, op->d_sp_off, op->d_sp_idx,
                          op->d_sp_tr, op->d_D, op->d_Dw, x, dc, y);
     else
-      hipLaunchKernelGGL(k_bem_p2_deriv<float>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq,
+      hipLaunchKernelGGL(k_bem_p2_deriv<float>, dim3(blocks(nt, 64)), dim3(64), 0, s, nt, op->nq,
                          (const float *)op->potl, (const float *)op->gradl, (const float *)op->poty,
                          (const float *)op->grady, op->d_qw, op->d_area, op->d_normal, op->d_sp_off, op->d_sp_idx,
                          op->d_sp_tr, op->d_D, op->d_Dw, x, dc, y);
@@ -1338,10 +1377,10 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
     return FMM_OK;
   }
   if (op->precision == FMM_FP64) {
-    hipLaunchKernelGGL(k_bem_p2_md<double>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const double *)op->potl,
+    hipLaunchKernelGGL(k_bem_p2_md<double>, dim3(blocks(nt, 64)), dim3(64), 0, s, nt, op->nq, (const double *)op->potl,
                        (const double *)op->poty, op->d_qw, op->d_area, op->d_sp_off, op->d_sp_idx, op->d_D, x, er, y);
   } else {
-    hipLaunchKernelGGL(k_bem_p2_md<float>, dim3(blocks(nt)), dim3(256), 0, s, nt, op->nq, (const float *)op->potl,
+    hipLaunchKernelGGL(k_bem_p2_md<float>, dim3(blocks(nt, 64)), dim3(64), 0, s, nt, op->nq, (const float *)op->potl,
                        (const float *)op->poty, op->d_qw, op->d_area, op->d_sp_off, op->d_sp_idx, op->d_D, x, er, y);
   }
   FMM_HIP_TRY(hipGetLastError());
