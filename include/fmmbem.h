@@ -299,12 +299,13 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
  * blocks; n = nt, or nv for P1 elements: bem_info's n_unknowns).  x_dev and y_dev must not overlap.  Asynchronous. */
 int bem_matvec(bem_op *op, const double *x_dev, double *y_dev, fmm_stream_t stream);
 
-/* Right-hand side b_dev (2*n doubles, P1: tested with the hat functions) for nq point charges at qxyz_dev
+/* Right-hand side b_dev (2*n doubles) for nq point charges at qxyz_dev
  * (device, nq x 3) with charges q_dev (device, nq), e and Angstrom:
  * b_s = int_Ts (1/eps) sum_k q_k / (4 pi |x - r_k|), eps = eps_out for the
- * exterior formulation and eps_in otherwise; second block 0 (direct) or
- * int_Ts n_s . grad of the same sum (derivative, exterior); regular rule,
- * FP64 direct sums.  Asynchronous. */
+ * exterior formulations (P0 and P1) and eps_in otherwise; second block 0
+ * (direct) or int_Ts n_s . grad of the same sum (derivative, exterior); P1:
+ * the same fields tested with the hat functions, b_i summed over the
+ * triangles at vertex i; regular rule, FP64 direct sums.  Asynchronous. */
 int bem_rhs(bem_op *op, const double *qxyz_dev, const double *q_dev, int64_t nq, double *b_dev,
             fmm_stream_t stream);
 
@@ -313,7 +314,7 @@ int bem_rhs(bem_op *op, const double *qxyz_dev, const double *q_dev, int64_t nq,
  * solute side, v -> (eps_out/eps_in) v, by the interface conditions):
  * reaction potential phi_reac(r_k) = -K_L u + V_L v evaluated at the charges
  * (eq. of the reaction potential, FP64 direct sum over the quadrature
- * points), dG = 1/2 sum_k q_k phi_reac(r_k) * 4 pi * 332.0637 (FP64
+ * points; P1 vertex values interpolated to them), dG = 1/2 sum_k q_k phi_reac(r_k) * 4 pi * 332.0637 (FP64
  * reduction on the device).  Synchronises `stream`; result in *dG. */
 int bem_energy(bem_op *op, const double *x_dev, const double *qxyz_dev, const double *q_dev, int64_t nq,
                double *dG, fmm_stream_t stream);
