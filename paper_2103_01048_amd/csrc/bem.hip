@@ -337,12 +337,15 @@ __device__ void tri_lin_moments(D3 x, const D3 *v, D3 n, D3 &G, D3 &dH) {
 
 // One thread per singular pair (s, t): the 3 x 3 blocks [corner of s][corner
 // of t] of S - C for V_L, K_L, V_Y, K_Y and W_Y - W_L with hat-function
-// weights, stored pair-minor: B[(9 op + 3 a + b) * npair + k] (45 arrays of
-// npair doubles, so that consecutive pairs read consecutive addresses).  S: the Laplace inner
-// integral in closed form for the linear density on t, the outer integral on
-// the collapsed rule; the bounded Yukawa-minus-Laplace remainders (and the
-// non-1/r part of W_Y - W_L) on the collapsed rule on both triangles.  C:
-// the regular rule, zero-distance point pairs left out.
+// weights.  S: the Laplace inner integral in closed form for the linear
+// density on t, the outer integral on the collapsed rule; the bounded
+// Yukawa-minus-Laplace remainders (and the non-1/r part of W_Y - W_L) on
+// the collapsed rule on both triangles.  C: the regular rule, zero-distance
+// point pairs left out.  Computed in FP64 and stored pair-minor as SV (FP32
+// for single-precision operators, whose quadrature-point sums are FP32
+// anyway): B[(9 op + 3 a + b) * npair + k], 45 arrays of npair values, so
+// that consecutive pairs read consecutive addresses.
+template <typename SV>
 __global__ __launch_bounds__(128) void k_singular_p1(int64_t npair, const int32_t *__restrict__ ps,
                                                      const int32_t *__restrict__ pt, const double *__restrict__ tri,
                                                      const double *__restrict__ normal,
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(128) void k_singular_p1(int64_t npair, const int32_
                                                      const double *__restrict__ rule_o, int no,
                                                      const double *__restrict__ rule_r, int nr,
                                                      const double *__restrict__ rule_q, int nq, double kappa,
-                                                     double *__restrict__ B) {
+                                                     SV *__restrict__ B) {
   const int64_t k = blockIdx.x * 128ll + threadIdx.x;
   if (k >= npair) return;
   const int s = ps[k], t = pt[k];
@@ -472,19 +475,20 @@ __global__ __launch_bounds__(128) void k_singular_p1(int64_t npair, const int32_
   }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    B[(0 + i) * npair + k] = VL[i];
-    B[(9 + i) * npair + k] = KL[i];
-    B[(18 + i) * npair + k] = VY[i];
-    B[(27 + i) * npair + k] = KY[i];
-    B[(36 + i) * npair + k] = W[i];
+    B[(0 + i) * npair + k] = (SV)VL[i];
+    B[(9 + i) * npair + k] = (SV)KL[i];
+    B[(18 + i) * npair + k] = (SV)VY[i];
+    B[(27 + i) * npair + k] = (SV)KY[i];
+    B[(36 + i) * npair + k] = (SV)W[i];
   }
 }
 
 // The K' blocks of every pair (s, t) from the transposed pair's K blocks,
 // KT[(9 kern + 3 a + b) * npair + k] = K_kern[t, s][b][a] (kern 0: Laplace,
 // 1: Yukawa), pair-minor like B.
-__global__ void k_p1_transpose(int64_t npair, const int32_t *__restrict__ tr, const double *__restrict__ B,
-                               double *__restrict__ KT) {
+template <typename SV>
+__global__ void k_p1_transpose(int64_t npair, const int32_t *__restrict__ tr, const SV *__restrict__ B,
+                               SV *__restrict__ KT) {
   const int64_t k = blockIdx.x * 256ll + threadIdx.x;
   if (k >= npair) return;
   const int64_t kt = tr[k];
@@ -500,8 +504,9 @@ __global__ void k_p1_transpose(int64_t npair, const int32_t *__restrict__ tr, co
 //   P[a]     = sum_b c1L (K_L u_b + sL V_L v_b) - c1Y (K_Y u_b + sY V_Y v_b)
 //   P[3 + a] = sum_b (W_Y - W_L) u_b + sL K'_L v_b - sY K'_Y v_b
 // (pair-minor, P[j * npair + k]); k_p1_corner adds them per triangle.
+template <typename SV>
 __global__ void k_p1_pairs(int64_t npair, const int32_t *__restrict__ pt, const int32_t *__restrict__ tris,
-                           const double *__restrict__ B, const double *__restrict__ KT, const double *__restrict__ x,
+                           const SV *__restrict__ B, const SV *__restrict__ KT, const double *__restrict__ x,
                            int64_t nv, DerivCoef c, double *__restrict__ P) {
   const int64_t k = blockIdx.x * 256ll + threadIdx.x;
   if (k >= npair) return;
@@ -518,9 +523,12 @@ __global__ void k_p1_pairs(int64_t npair, const int32_t *__restrict__ pt, const 
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       const int ab = 3 * a + b;
-      p1 += c.c1L * (B[(9 + ab) * npair + k] * u[b] + c.sL * B[ab * npair + k] * v[b]) -
-            c.c1Y * (B[(27 + ab) * npair + k] * u[b] + c.sY * B[(18 + ab) * npair + k] * v[b]);
-      p2 += B[(36 + ab) * npair + k] * u[b] + c.sL * KT[ab * npair + k] * v[b] - c.sY * KT[(9 + ab) * npair + k] * v[b];
+      const double vl = (double)B[ab * npair + k], kl = (double)B[(9 + ab) * npair + k];
+      const double vy = (double)B[(18 + ab) * npair + k], ky = (double)B[(27 + ab) * npair + k];
+      const double w = (double)B[(36 + ab) * npair + k];
+      const double ktl = (double)KT[ab * npair + k], kty = (double)KT[(9 + ab) * npair + k];
+      p1 += c.c1L * (kl * u[b] + c.sL * vl * v[b]) - c.c1Y * (ky * u[b] + c.sY * vy * v[b]);
+      p2 += w * u[b] + c.sL * ktl * v[b] - c.sY * kty * v[b];
     }
     P[a * npair + k] = p1;
     P[(3 + a) * npair + k] = p2;
@@ -1058,12 +1066,14 @@ struct bem_op {
   // P1 elements (FMM_BEM_EXTERIOR_P1): nu = nv unknowns per block (nt for
   // P0), the triangles' vertex indices, per vertex its corners (3 s + a,
   // ascending), the regular rule, and pair-minor arrays: the S - C blocks
-  // (45 per pair), the K' blocks from the transposed pairs (18 per pair) and
+  // (45 per pair; FP32 for single-precision operators), the K' blocks from
+  // the transposed pairs (18 per pair, same type) and
   // the per-pair row terms of a matvec (6 per pair); the per-corner row sums
   bool p1 = false;
   int64_t nu = 0;
   int32_t *d_tris = nullptr, *d_vt_off = nullptr, *d_vt_list = nullptr;
-  double *d_rq = nullptr, *d_B = nullptr, *d_KT = nullptr, *d_P = nullptr, *d_cb = nullptr;
+  double *d_rq = nullptr, *d_P = nullptr, *d_cb = nullptr;
+  void *d_B = nullptr, *d_KT = nullptr;  // FP64 for FP64 operators, FP32 otherwise
   void *q4 = nullptr, *potl = nullptr, *poty = nullptr, *gradl = nullptr, *grady = nullptr;
   // GMRES / energy scratch
   double *d_partial = nullptr, *d_h = nullptr, *d_V = nullptr, *d_z = nullptr, *d_w = nullptr, *d_r = nullptr,
@@ -1257,15 +1267,24 @@ int bem_setup(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, 
       if ((rc = bupload(op, &op->d_tris, tv))) break;
       if ((rc = bupload(op, &op->d_vt_off, voff))) break;
       if ((rc = bupload(op, &op->d_vt_list, vlist))) break;
-      if ((rc = balloc(op, (void **)&op->d_B, op->npair * 45 * sizeof(double)))) break;
-      if ((rc = balloc(op, (void **)&op->d_KT, op->npair * 18 * sizeof(double)))) break;
+      const size_t bs = precision == FMM_FP64 ? sizeof(double) : sizeof(float);
+      if ((rc = balloc(op, &op->d_B, op->npair * 45 * bs))) break;
+      if ((rc = balloc(op, &op->d_KT, op->npair * 18 * bs))) break;
       if ((rc = balloc(op, (void **)&op->d_P, op->npair * 6 * sizeof(double)))) break;
       if ((rc = balloc(op, (void **)&op->d_cb, nt * 6 * sizeof(double)))) break;
-      hipLaunchKernelGGL(k_singular_p1, dim3(blocks(op->npair, 128)), dim3(128), 0, s, op->npair, d_ps,
-                         op->d_sp_idx, op->d_tri, op->d_normal, op->d_area, d_ro, NO * NO, d_rr, NREM * NREM, d_rq,
-                         quad_pts, kappa, op->d_B);
-      hipLaunchKernelGGL(k_p1_transpose, dim3(blocks(op->npair)), dim3(256), 0, s, op->npair, op->d_sp_tr, op->d_B,
-                         op->d_KT);
+      if (precision == FMM_FP64) {
+        hipLaunchKernelGGL(k_singular_p1<double>, dim3(blocks(op->npair, 128)), dim3(128), 0, s, op->npair, d_ps,
+                           op->d_sp_idx, op->d_tri, op->d_normal, op->d_area, d_ro, NO * NO, d_rr, NREM * NREM,
+                           d_rq, quad_pts, kappa, (double *)op->d_B);
+        hipLaunchKernelGGL(k_p1_transpose<double>, dim3(blocks(op->npair)), dim3(256), 0, s, op->npair,
+                           op->d_sp_tr, (const double *)op->d_B, (double *)op->d_KT);
+      } else {
+        hipLaunchKernelGGL(k_singular_p1<float>, dim3(blocks(op->npair, 128)), dim3(128), 0, s, op->npair, d_ps,
+                           op->d_sp_idx, op->d_tri, op->d_normal, op->d_area, d_ro, NO * NO, d_rr, NREM * NREM,
+                           d_rq, quad_pts, kappa, (float *)op->d_B);
+        hipLaunchKernelGGL(k_p1_transpose<float>, dim3(blocks(op->npair)), dim3(256), 0, s, op->npair,
+                           op->d_sp_tr, (const float *)op->d_B, (float *)op->d_KT);
+      }
     } else {
       if ((rc = balloc(op, (void **)&op->d_D, op->npair * 4 * sizeof(double)))) break;
       if ((rc = balloc(op, (void **)&op->d_sdiag, nt * 2 * sizeof(double)))) break;
@@ -1328,8 +1347,12 @@ int bem_matvec(bem_op *op, const double *x, double *y, fmm_stream_t stream) {
     if ((rc = fmm_eval_pair_md(op->fl, op->fy, qq, qq + Nq * es, dc.sL, dc.sY, op->potl, op->gradl, op->poty,
                                op->grady, s)))
       return rc;
-    hipLaunchKernelGGL(k_p1_pairs, dim3(blocks(op->npair)), dim3(256), 0, s, op->npair, op->d_sp_idx, op->d_tris,
-                       op->d_B, op->d_KT, x, op->nv, dc, op->d_P);
+    if (op->precision == FMM_FP64)
+      hipLaunchKernelGGL(k_p1_pairs<double>, dim3(blocks(op->npair)), dim3(256), 0, s, op->npair, op->d_sp_idx,
+                         op->d_tris, (const double *)op->d_B, (const double *)op->d_KT, x, op->nv, dc, op->d_P);
+    else
+      hipLaunchKernelGGL(k_p1_pairs<float>, dim3(blocks(op->npair)), dim3(256), 0, s, op->npair, op->d_sp_idx,
+                         op->d_tris, (const float *)op->d_B, (const float *)op->d_KT, x, op->nv, dc, op->d_P);
     if (op->precision == FMM_FP64)
       hipLaunchKernelGGL(k_p1_corner<double>, dim3(blocks(nt, 64)), dim3(64), 0, s, nt, op->nq, (const double *)op->potl,
                          (const double *)op->gradl, (const double *)op->poty, (const double *)op->grady, op->d_qw,
