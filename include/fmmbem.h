@@ -336,8 +336,9 @@ int bem_precondition(bem_op *op, const double *x_dev, double *y_dev, fmm_stream_
  * rotations on the host.  restart: Krylov dimension before a restart
  * (<= 0: maxiter, full GMRES).  Stops when the recomputed residual
  * |b - A x| / |b| <= tol.  x_dev holds the initial guess and receives the
- * solution.  refine (may be NULL): an operator on the same mesh, usually
- * FMM_FP64 with a higher order; then the solve is an iterative refinement:
+ * solution.  refine (may be NULL): an operator on the same mesh with the
+ * same formulation (FMM_EINVAL otherwise), usually FMM_FP64 with a higher
+ * order; then the solve is an iterative refinement:
  * residuals are computed with `refine` and each correction is solved with
  * `op` to a relative tolerance inner_tol.  iters (may be NULL) receives the
  * total number of inner iterations; resid_hist (host, may be NULL, maxiter

@@ -1582,8 +1582,8 @@ static int gmres_core(bem_op *op, const double *b, double *x, double bnorm, doub
 int gmres_solve(bem_op *op, bem_op *refine, const double *b, double *x, double tol, double inner_tol, int maxiter,
                 int restart, int *iters, double *hist, fmm_stream_t stream) {
   if (!op || !b || !x || !(tol > 0) || maxiter < 1) { set_error("gmres_solve: bad argument"); return FMM_EINVAL; }
-  if (refine && (refine->nt != op->nt || refine->nu != op->nu)) {
-    set_error("gmres_solve: refine operator on another mesh or element type");
+  if (refine && (refine->nt != op->nt || refine->nu != op->nu || refine->formulation != op->formulation)) {
+    set_error("gmres_solve: refine operator on another mesh, element type or formulation");
     return FMM_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;

@@ -107,6 +107,12 @@ def test_refinement_recovers_fp64_solution(sphere512):
     x, it, hist, rc = gmres(lo, b, tol=1e-8, maxiter=400, refine=hi, inner_tol=1e-4)
     assert rc == 0
     assert _rel(x.cpu().numpy(), x_lu) < 1e-6
+    # a refinement operator of another formulation is refused
+    from paper_2103_01048_amd import BEMOperator
+    other = BEMOperator(v, t, quad_pts=3, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=5, ncrit=64, precision="fp64",
+                        formulation="derivative")
+    with pytest.raises(RuntimeError):
+        gmres(lo, b, tol=1e-8, maxiter=10, refine=other)
 
 
 def test_zero_rhs_and_maxiter(sphere512):
