@@ -402,10 +402,12 @@ static int precompute_typed(fmm_plan *P) {
   const int p = P->p, n = P->nsurf, ld = P->ld;
   const int yuk = P->kernel == FMM_YUKAWA;
   const int maxl = (int)P->level_begin.size() - 2;
-  // singular values kept above tau * s_max: FP64 1e-11; single precision
-  // 1e-6 (components below that are at the FP32 rounding level of the data
-  // that flows through them)
-  const double tau = P->precision == FMM_FP64 ? 1e-11 : 1e-6;
+  // singular values kept above tau * s_max: FP64 1e-11 up to p = 7 and
+  // 10^-(p+1) from p = 8 (1e-9 at p = 8: more than an order of magnitude
+  // below the expansion error there, about 3e-8, and ranks of 247-262
+  // instead of 287-292 of 296); single precision 1e-6 (components below
+  // that are at the FP32 rounding level of the data that flows through them)
+  const double tau = P->precision == FMM_FP64 ? (p >= 8 ? std::pow(10.0, -(p + 1)) : 1e-11) : 1e-6;
   const std::vector<double> grid = surface_grid(p);
   const double zero[3] = {0, 0, 0};
   auto h_of = [&](int l) { return P->W / (double)(1ll << (l + 1)); };
