@@ -181,3 +181,15 @@ def test_energy_direct_equals_dense_energy():
     x = np.random.default_rng(37).standard_normal(2 * len(v))
     qx, q = [[1.0, 1.0, 1.0], [-0.6, 0.3, -0.2]], [1.0, -0.5]
     assert P.energy_direct(m, x, qx, q) == pytest.approx(P.energy(m, x, qx, q), rel=1e-12)
+
+
+def test_used_vertices_only_keeps_the_geometry():
+    """The input helper that drops vertices no triangle uses (P1 unknowns
+    live on vertices) renumbers triangles without moving them."""
+    v, t = synth.octa_sphere(1, 2.0)
+    extra = np.array([[9.0, 9.0, 9.0], [8.0, 8.0, 8.0]])
+    v2 = np.concatenate([extra[:1], v, extra[1:]])
+    t2 = t + 1
+    v3, t3 = synth.used_vertices_only(v2, t2)
+    assert len(v3) == len(v)
+    np.testing.assert_array_equal(v3[t3], v2[t2])
