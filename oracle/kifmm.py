@@ -21,11 +21,16 @@ Readings (the paper leaves these open):
     M2L, W-list boxes through their upward equivalent densities (M2P),
     X-list boxes through their sources evaluated on the downward check
     surface (P2L), U-list leaves directly (P2P).
-  * With direct_small=True (the default), a W-list box holding at most n
-    points contributes its points directly instead of its n equivalent
-    points, and a leaf with at most n points takes its X-list sources
-    directly at its points instead of through its check surface: both are
-    exact and cheaper than the surface they replace.
+  * The default (direct_small=False) is the plain method: every W-list box
+    acts through its upward equivalent density (M2P) and every X-list box
+    through its sources evaluated on the downward check surface (P2L).
+    With direct_small=True a W-list box holding at most n points contributes
+    its points directly instead of its n equivalent points, and a leaf with
+    at most n points takes its X-list sources directly at its points instead
+    of through its check surface: both replace an approximation by the exact
+    sum it approximates, so the two variants agree to within the expansion
+    error (a pinned property); the GPU library takes the same shortcut, and
+    its per-pass parity test asks for this variant explicitly.
 """
 from __future__ import annotations
 
@@ -136,7 +141,7 @@ class FMMResult:
 
 
 def evaluate(x, q, kernel="laplace", kappa=0.0, p=6, ncrit=64, tau=1e-14, t=None, ops=None,
-             direct_small=True):
+             direct_small=False):
     """FMM potential and gradient at every point from densities q (targets =
     sources = x; zero-distance pairs excluded).  Returns FMMResult in the
     caller's point order."""

@@ -1,7 +1,11 @@
 """Pins of the octree/list oracle (exactly-once coverage of every target-
 source pair, leaf sizes, Morton order) and of the FP64 KIFMM oracle (error
-against the direct sum falls with the expansion order; a single leaf is the
-exact direct sum)."""
+of the potential and of the gradient against the direct sum falls with the
+expansion order, on the plain method and on a deep adaptive tree whose W and
+X lists hold boxes larger than the surfaces; the variant that takes small
+W/X boxes directly agrees with the plain one to within the expansion error;
+dropping a far-field stage is detected; a single leaf is the exact direct
+sum)."""
 import numpy as np
 import pytest
 
@@ -92,12 +96,70 @@ def test_error_falls_with_order(kernel, kappa):
     p0, g0 = D.direct(x, x, q, kernel, kappa)
     t = T.build_tree(x, 32)
     assert int(t.level.max()) >= 3 and sum(len(v) for v in t.V) > 1000
-    errs = []
+    errs, gerrs = [], []
     for p in (3, 5, 7):
         r = kifmm.evaluate(x, q, kernel, kappa, p=p, ncrit=32, t=t, tau=1e-11)
         errs.append(D.rel_l2(r.pot, p0))
+        gerrs.append(D.rel_l2(r.grad, g0))
     assert errs[0] < 2e-2 and errs[1] < 1e-4 and errs[2] < 2e-6, errs
     assert errs[0] > 5 * errs[1] > 25 * errs[2], errs
+    # the gradient (L2P and M2P through the kernel's gradient) converges too
+    assert gerrs[0] < 5e-2 and gerrs[1] < 5e-4 and gerrs[2] < 2e-5, gerrs
+    assert gerrs[0] > 5 * gerrs[1] > 25 * gerrs[2], gerrs
+
+
+def _clustered():
+    """A dense cluster inside a sparse cloud: a deep tree (8 levels at ncrit
+    24) whose W and X lists are long and hold boxes of more than the 56
+    surface points of p = 4, so both the surface (M2P, P2L) and the direct
+    forms of those lists are exercised."""
+    rng = np.random.default_rng(21)
+    x = np.concatenate([rng.normal(0, 0.02, (800, 3)), rng.uniform(-1, 1, (1200, 3))])
+    return x, rng.standard_normal(len(x))
+
+
+@pytest.mark.parametrize("kernel,kappa", [("laplace", 0.0), ("yukawa", 2.0)])
+def test_plain_method_on_adaptive_tree(kernel, kappa):
+    """The plain method (every W box through M2P from its upward equivalent
+    surface, every X box through P2L on the downward check surface) on a
+    tree with 2,278 W and X entries: potential and gradient errors fall with
+    p; the shortcut variant agrees with it to within the expansion error."""
+    x, q = _clustered()
+    t = T.build_tree(x, 24)
+    nw = sum(len(v) for v in t.W_)
+    assert int(t.level.max()) >= 7 and nw > 2000 and nw == sum(len(v) for v in t.X)
+    p0, g0 = D.direct(x, x, q, kernel, kappa)
+    errs, gerrs = [], []
+    for p in (3, 5):
+        r = kifmm.evaluate(x, q, kernel, kappa, p=p, ncrit=24, t=t, tau=1e-11)
+        errs.append(D.rel_l2(r.pot, p0))
+        gerrs.append(D.rel_l2(r.grad, g0))
+    # measured: pot 3.1e-3, 3.8e-5; grad 3.1e-3, 7.9e-5 (both kernels)
+    assert errs[0] < 1e-2 and errs[1] < 1e-4 and errs[0] > 20 * errs[1], errs
+    assert gerrs[0] < 1e-2 and gerrs[1] < 2e-4 and gerrs[0] > 10 * gerrs[1], gerrs
+    rs = kifmm.evaluate(x, q, kernel, kappa, p=5, ncrit=24, t=t, tau=1e-11, direct_small=True)
+    es, gs = D.rel_l2(rs.pot, p0), D.rel_l2(rs.grad, g0)
+    assert es < 1e-4 and gs < 2e-4
+    # the two variants differ by less than either one's expansion error
+    assert D.rel_l2(r.pot, rs.pot) < max(errs[1], es)
+    assert D.rel_l2(r.grad, rs.grad) < max(gerrs[1], gs)
+
+
+@pytest.mark.parametrize("drop", ["W", "X", "WX"])
+def test_dropping_w_or_x_is_detected(drop):
+    """Dropping the M2P (W) or the P2L (X) contributions of the plain method
+    leaves an error far outside what the expansion order allows."""
+    x, q = _clustered()
+    t = T.build_tree(x, 24)
+    p0, g0 = D.direct(x, x, q)
+    saved = t.W_, t.X
+    if "W" in drop:
+        t.W_ = [[] for _ in saved[0]]
+    if "X" in drop:
+        t.X = [[] for _ in saved[1]]
+    r = kifmm.evaluate(x, q, p=4, ncrit=24, t=t, tau=1e-11)
+    t.W_, t.X = saved
+    assert max(D.rel_l2(r.pot, p0), D.rel_l2(r.grad, g0)) > 1e-2
 
 
 def test_dropping_m2l_is_detected():
