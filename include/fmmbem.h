@@ -13,7 +13,12 @@
  *     formulation): Laplace g = 1/(4 pi r), Yukawa g = exp(-kappa r)/(4 pi r).
  *   - "gradient" is +grad_x of the potential at the target (not the field).
  *   - A pair of points at zero distance (bitwise-equal coordinates)
- *     contributes nothing.
+ *     contributes nothing.  Bitwise-equal points always share a leaf (equal
+ *     Morton keys).  Single precision (FMM_FP32, FMM_FP32_BF16X3) stores each
+ *     point relative to the centre of its leaf, so two DISTINCT points in
+ *     different leaves must be more than about 2^-21 of their leaf's width
+ *     apart (1e-7 A for leaves of 0.5 A); closer pairs may round to zero
+ *     separation and give non-finite results.  FMM_FP64 resolves them.
  *   - Device pointers are HIP device allocations owned by the caller; the
  *     library never frees them.  Plans and operators own their internal
  *     buffers and release them in *_free.
@@ -75,7 +80,9 @@ enum {
 
 /* Build a plan for the points xyz_dev (device, n x 3 doubles, row-major,
  * read during the call only).  kernel: FMM_LAPLACE or FMM_YUKAWA; kappa >= 0
- * (used by Yukawa only); p in [2, 10]; ncrit >= 1; precision: FMM_FP64,
+ * (used by Yukawa only); p in [2, 10] (the paper's runs use p = 3 ... 10;
+ * the surface kernels keep one surface point per thread of a workgroup of
+ * at most 512 threads, n_surf = 488 at p = 10); ncrit >= 1; precision: FMM_FP64,
  * FMM_FP32 or FMM_FP32_BF16X3.  Sorts the points along a Morton curve on the
  * device, builds the tree and interaction lists on the host, precomputes the
  * translation operators in FP64 (truncated-SVD pseudo-inverses of the
@@ -336,9 +343,10 @@ int bem_precondition(bem_op *op, const double *x_dev, double *y_dev, fmm_stream_
  * rotations on the host.  restart: Krylov dimension before a restart
  * (<= 0: maxiter, full GMRES).  Stops when the recomputed residual
  * |b - A x| / |b| <= tol.  x_dev holds the initial guess and receives the
- * solution.  refine (may be NULL): an operator on the same mesh with the
- * same formulation (FMM_EINVAL otherwise), usually FMM_FP64 with a higher
- * order; then the solve is an iterative refinement:
+ * solution.  refine (may be NULL): an operator other than op on the same
+ * mesh with the same formulation, quadrature rule, permittivities and kappa
+ * (FMM_EINVAL otherwise), usually FMM_FP64 with a higher order; then the
+ * solve is an iterative refinement:
  * residuals are computed with `refine` and each correction is solved with
  * `op` to a relative tolerance inner_tol.  iters (may be NULL) receives the
  * total number of inner iterations; resid_hist (host, may be NULL, maxiter

@@ -3,8 +3,9 @@
 
     pot = fmm_potential(plan, q, xyz)
 
-`xyz` must be the tensor the plan was built from (the plan holds the tree
-and translation operators for those points); its gradient is
+`xyz` must hold the points the plan was built from (the plan holds the tree
+and translation operators for those points; forward raises ValueError
+otherwise, FMMPlan.check_points); its gradient is
   dL/dx_k = sum_c gbar_ck grad(phi_c)_k + q_ck grad(psi_c)_k,  psi = G gbar,
 and the density gradient is G gbar (the kernel is symmetric)."""
 from __future__ import annotations
@@ -20,12 +21,15 @@ from .fmm import FMMPlan, _ptr, _stream
 class FMMPotential(torch.autograd.Function):
     @staticmethod
     def forward(ctx, q, xyz, plan: FMMPlan):
+        if xyz is not None:
+            plan.check_points(xyz)
         squeeze = q.ndim == 1
         qq = (q.reshape(1, -1) if squeeze else q).to(plan.dtype).contiguous()
         pot, grad = plan.eval(qq, gradient=True)
         ctx.plan = plan
         ctx.squeeze = squeeze
-        ctx.q_dtype, ctx.x_dtype = q.dtype, xyz.dtype
+        ctx.q_dtype = q.dtype
+        ctx.x_dtype = xyz.dtype if xyz is not None else plan.dtype
         ctx.save_for_backward(qq, grad)
         return pot[0] if squeeze else pot
 
@@ -36,7 +40,7 @@ class FMMPotential(torch.autograd.Function):
         gb = (gpot.reshape(1, -1) if ctx.squeeze else gpot).to(plan.dtype).contiguous()
         nrhs = qq.shape[0]
         need_q = ctx.needs_input_grad[0]
-        need_x = ctx.needs_input_grad[1]
+        need_x = len(ctx.needs_input_grad) > 1 and ctx.needs_input_grad[1]
         dq = torch.empty_like(qq) if need_q else None
         dx = torch.empty((plan.n, 3), dtype=plan.dtype, device=qq.device) if need_x else None
         if need_q or need_x:
@@ -50,9 +54,9 @@ class FMMPotential(torch.autograd.Function):
 
 
 def fmm_potential(plan: FMMPlan, q, xyz=None):
-    """Differentiable FMM potential (targets = sources = the plan's points)."""
-    if xyz is None:
-        xyz = torch.zeros((plan.n, 3), dtype=plan.dtype, device=plan.device)
+    """Differentiable FMM potential (targets = sources = the plan's points).
+    xyz: None (no position gradient) or the plan's points, which then
+    receive dE/dx."""
     return FMMPotential.apply(q, xyz, plan)
 
 

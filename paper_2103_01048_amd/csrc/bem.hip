@@ -1582,8 +1582,17 @@ static int gmres_core(bem_op *op, const double *b, double *x, double bnorm, doub
 int gmres_solve(bem_op *op, bem_op *refine, const double *b, double *x, double tol, double inner_tol, int maxiter,
                 int restart, int *iters, double *hist, fmm_stream_t stream) {
   if (!op || !b || !x || !(tol > 0) || maxiter < 1) { set_error("gmres_solve: bad argument"); return FMM_EINVAL; }
-  if (refine && (refine->nt != op->nt || refine->nu != op->nu || refine->formulation != op->formulation)) {
-    set_error("gmres_solve: refine operator on another mesh, element type or formulation");
+  if (refine == op) {
+    // the refinement loop keeps its residual in the refine operator's
+    // buffers, which the inner solve on `op` would overwrite
+    set_error("gmres_solve: the refine operator must differ from op");
+    return FMM_EINVAL;
+  }
+  if (refine && (refine->nt != op->nt || refine->nu != op->nu || refine->formulation != op->formulation ||
+                 refine->nq != op->nq || refine->eps_in != op->eps_in || refine->eps_out != op->eps_out ||
+                 refine->kappa != op->kappa)) {
+    set_error("gmres_solve: refine operator on another mesh, element type, formulation, quadrature rule, "
+              "permittivities or kappa");
     return FMM_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;

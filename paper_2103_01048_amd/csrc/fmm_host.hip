@@ -34,7 +34,8 @@ namespace fmm {
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 
-int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], double mx[3], bool *finite);
+int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], double mx[3], bool *finite,
+                uint64_t *hash);
 int device_morton_sort(const double *xyz, int64_t n, const std::vector<int64_t> &off, const std::vector<double> &lo,
                        double W, hipStream_t s, std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out);
 int device_gather_leaves(const double *xyz, const int32_t *perm, const std::vector<int64_t> &lb,
@@ -1086,15 +1087,20 @@ int ensure_lists(fmm_plan *P, int nr) {
   return FMM_OK;
 }
 
-// FNV-1a over everything the leaf items depend on: point order, molecule
-// ranges, boxes, surface size and the item lists.  Two plans with equal
-// fingerprints share one tree (their near ranges and items coincide).
+// FNV-1a over everything the shared launches of a pair evaluation depend on:
+// the input coordinates (their checksum from the bounding-box pass), the root
+// cube side and the molecules' corners, point order, molecule ranges, boxes,
+// surface size and the item lists.  Two plans with equal fingerprints share
+// one tree: the same sorted points, box geometry, near ranges and items.
 static uint64_t tree_fingerprint(const fmm_plan *P) {
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](const void *data, size_t bytes) {
     const unsigned char *c = (const unsigned char *)data;
     for (size_t i = 0; i < bytes; ++i) { h ^= c[i]; h *= 1099511628211ull; }
   };
+  mix(&P->coord_hash, sizeof(P->coord_hash));
+  mix(&P->W, sizeof(P->W));
+  mix(P->mol_lo.data(), P->mol_lo.size() * sizeof(double));
   mix(&P->n, sizeof(P->n));
   mix(&P->nsurf, sizeof(P->nsurf));
   mix(&P->ncrit, sizeof(P->ncrit));
@@ -1250,7 +1256,10 @@ static int setup_common(const double *xyz_dev, const std::vector<int64_t> &off, 
       if (nm == 0) continue;
       double mn[3], mx[3];
       bool finite = true;
-      if ((rc = device_bbox(xyz_dev + 3 * off[m], nm, s, mn, mx, &finite))) break;
+      uint64_t hm = 0;
+      if ((rc = device_bbox(xyz_dev + 3 * off[m], nm, s, mn, mx, &finite, &hm))) break;
+      // molecule m's coordinate checksum, tied to its index and size
+      P->coord_hash = P->coord_hash * 0x100000001b3ull + (hm ^ ((uint64_t)m << 32) ^ (uint64_t)nm);
       if (!finite) { set_error("fmm_setup: non-finite coordinate"); rc = FMM_EINVAL; break; }
       for (int d = 0; d < 3; ++d) { cen[3 * m + d] = (mn[d] + mx[d]) * 0.5; ext = std::max(ext, mx[d] - mn[d]); }
     }

@@ -194,7 +194,8 @@ struct fmm_plan {
   void *pair_acc = nullptr;
   size_t pair_acc_bytes = 0;
   void *dips = nullptr;             // monopole + dipole sources: dipole records in Morton order
-  uint64_t tree_hash = 0;           // fingerprint of points, boxes and leaf items
+  uint64_t coord_hash = 0;          // checksum of the FP64 input coordinates (per molecule, chained)
+  uint64_t tree_hash = 0;           // fingerprint of coordinates, points, boxes and leaf items
   void *adj = nullptr;              // adjoint scratch: psi and grad psi
   size_t adj_bytes = 0;
   int64_t device_bytes = 0;

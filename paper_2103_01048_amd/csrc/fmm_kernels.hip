@@ -60,32 +60,54 @@ __device__ inline double dev_exp2(double x) { return exp2(x); }
 // ---------------------------------------------------------------------------
 // Setup helpers: bounding box, Morton keys, point gather.
 // ---------------------------------------------------------------------------
+// splitmix64 finaliser (a bijective 64-bit mix)
+__device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Per block: the coordinate minima and maxima (NaN minimum when a coordinate
+// is not finite) and a checksum of the coordinates' bit patterns at their
+// positions (wrapping sum over points of a mix of index and bits; integer
+// addition, so the total does not depend on the order of the sum).  part
+// holds 7 doubles per block: 3 minima, 3 maxima, the checksum's bits.
 __global__ void k_bbox_partial(const double *__restrict__ xyz, int64_t n, double *__restrict__ part) {
   __shared__ double smin[3][256], smax[3][256];
+  __shared__ unsigned long long shash[256];
   double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
   int bad = 0;
+  uint64_t hsum = 0;
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    uint64_t h = mix64((uint64_t)i + 0x9e3779b97f4a7c15ull);
     for (int d = 0; d < 3; ++d) {
       double v = xyz[i * 3 + d];
       if (!isfinite(v)) bad = 1;
       mn[d] = fmin(mn[d], v);
       mx[d] = fmax(mx[d], v);
+      h = mix64(h ^ (uint64_t)__double_as_longlong(v));
     }
+    hsum += h;
   }
+  shash[threadIdx.x] = hsum;
   if (bad) { mn[0] = NAN; }
   for (int d = 0; d < 3; ++d) { smin[d][threadIdx.x] = mn[d]; smax[d][threadIdx.x] = mx[d]; }
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
+    if ((int)threadIdx.x < s) {
       for (int d = 0; d < 3; ++d) {
         double a = smin[d][threadIdx.x], b = smin[d][threadIdx.x + s];
         smin[d][threadIdx.x] = (isnan(a) || isnan(b)) ? NAN : fmin(a, b);
         smax[d][threadIdx.x] = fmax(smax[d][threadIdx.x], smax[d][threadIdx.x + s]);
       }
+      shash[threadIdx.x] += shash[threadIdx.x + s];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0)
-    for (int d = 0; d < 3; ++d) { part[blockIdx.x * 6 + d] = smin[d][0]; part[blockIdx.x * 6 + 3 + d] = smax[d][0]; }
+  if (threadIdx.x == 0) {
+    for (int d = 0; d < 3; ++d) { part[blockIdx.x * 7 + d] = smin[d][0]; part[blockIdx.x * 7 + 3 + d] = smax[d][0]; }
+    part[blockIdx.x * 7 + 6] = __longlong_as_double((long long)shash[0]);
+  }
 }
 
 __device__ inline uint64_t spread3(uint64_t v) {
@@ -131,26 +153,33 @@ __global__ void k_gather_leaves(const double *__restrict__ xyz, const int32_t *_
   }
 }
 
-int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], double mx[3], bool *finite) {
+int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], double mx[3], bool *finite,
+                uint64_t *hash) {
   int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
   double *part = nullptr;
-  FMM_HIP_TRY(hipMalloc(&part, sizeof(double) * 6 * nb));
+  FMM_HIP_TRY(hipMalloc(&part, sizeof(double) * 7 * nb));
   hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(256), 0, s, xyz, n, part);
-  std::vector<double> h(6 * nb);
+  std::vector<double> h(7 * nb);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, sizeof(double) * 7 * nb, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(part);
   if (e != hipSuccess) { set_error(std::string("bbox: ") + hipGetErrorString(e)); return FMM_EHIP; }
   *finite = true;
   for (int d = 0; d < 3; ++d) { mn[d] = INFINITY; mx[d] = -INFINITY; }
-  for (int b = 0; b < nb; ++b)
+  uint64_t hs = 0;
+  for (int b = 0; b < nb; ++b) {
     for (int d = 0; d < 3; ++d) {
-      double a = h[b * 6 + d], c = h[b * 6 + 3 + d];
+      double a = h[b * 7 + d], c = h[b * 7 + 3 + d];
       if (std::isnan(a) || std::isinf(a) || std::isinf(c)) *finite = false;
       mn[d] = std::min(mn[d], a);
       mx[d] = std::max(mx[d], c);
     }
+    uint64_t hb;
+    std::memcpy(&hb, &h[b * 7 + 6], 8);
+    hs += hb;
+  }
+  if (hash) *hash = hs;
   return FMM_OK;
 }
 

@@ -59,6 +59,23 @@ class FMMPlan:
                                             KERNELS[kernel], self.kappa, self.p, self.ncrit, PRECISIONS[precision],
                                             _stream(), ctypes.byref(h)), "fmm_setup_batch")
         self._h = h
+        # the FP64 points the tree was built from (the caller's tensor itself
+        # when it already was contiguous FP64), for check_points
+        self._points = pts
+        self._points_version = pts._version
+
+    def check_points(self, xyz: torch.Tensor):
+        """Raise ValueError unless xyz holds exactly the points this plan was
+        built from (same shape and device, equal values, not modified in place
+        since the setup)."""
+        if self._points._version != self._points_version:
+            raise ValueError("the plan's points were modified in place after the plan was built")
+        if tuple(xyz.shape) != (self.n, 3) or xyz.device != self.device:
+            raise ValueError(f"xyz must be an ({self.n}, 3) tensor on {self.device}, the plan's points")
+        if (xyz.dtype == torch.float64 and xyz.is_contiguous() and xyz.data_ptr() == self._points.data_ptr()):
+            return
+        if not torch.equal(xyz.detach().to(torch.float64), self._points):
+            raise ValueError("xyz differs from the points the plan was built from; build a new plan")
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -27,8 +27,28 @@ def test_density_gradcheck_single_leaf():
     x, q = synth.unit_sphere_cloud(120, seed=51)
     plan = _plan(x, kernel="yukawa", kappa=0.5, p=4, ncrit=512, precision="fp64")
     qt = torch.tensor(q, device="cuda", requires_grad=True)
-    xt = torch.zeros((len(x), 3), dtype=torch.float64, device="cuda")
-    assert torch.autograd.gradcheck(lambda qq: FMMPotential.apply(qq, xt, plan), (qt,), eps=1e-6, atol=1e-8)
+    assert torch.autograd.gradcheck(lambda qq: FMMPotential.apply(qq, None, plan), (qt,), eps=1e-6, atol=1e-8)
+
+
+def test_points_must_be_the_plans():
+    """The position gradient belongs to the plan's points: other points (a
+    moved copy, another shape) and the plan's own tensor modified in place
+    after the setup are rejected; an equal copy is accepted."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, fmm_potential
+    x, q = synth.unit_sphere_cloud(500, seed=54)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    plan = FMMPlan(xt, kernel="laplace", p=4, ncrit=64, precision="fp64")
+    qt = torch.tensor(q, device="cuda")
+    ok = fmm_potential(plan, qt, xt.clone().requires_grad_(True))
+    assert torch.isfinite(ok).all()
+    with pytest.raises(ValueError):
+        fmm_potential(plan, qt, (xt + 0.1).requires_grad_(True))
+    with pytest.raises(ValueError):
+        fmm_potential(plan, qt, xt[:-1].clone().requires_grad_(True))
+    xt[0, 0] += 0.5
+    with pytest.raises(ValueError):
+        fmm_potential(plan, qt, xt.clone().requires_grad_(True))
 
 
 @pytest.mark.parametrize("kernel", ["laplace", "yukawa"])

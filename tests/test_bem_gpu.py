@@ -113,6 +113,15 @@ def test_refinement_recovers_fp64_solution(sphere512):
                         formulation="derivative")
     with pytest.raises(RuntimeError):
         gmres(lo, b, tol=1e-8, maxiter=10, refine=other)
+    # the operator itself as its refinement, and refinement operators with
+    # other permittivities, kappa or quadrature rule, are refused
+    with pytest.raises(RuntimeError):
+        gmres(lo, b, tol=1e-8, maxiter=10, refine=lo)
+    for kw in ({"eps_in": 2.0}, {"eps_out": 40.0}, {"kappa": 0.25}, {"quad_pts": 6}):
+        args = dict(quad_pts=3, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=5, ncrit=64, precision="fp64")
+        args.update(kw)
+        with pytest.raises(RuntimeError):
+            gmres(lo, b, tol=1e-8, maxiter=10, refine=BEMOperator(v, t, **args))
 
 
 def test_zero_rhs_and_maxiter(sphere512):

@@ -160,6 +160,48 @@ def test_empty_and_duplicates():
     assert D.rel_l2(pot, p0) < 1e-4
 
 
+def _straddling_pair(sep):
+    """A unit-sphere cloud plus two points `sep` apart on either side of
+    the plane x = centre of the bounding box, which is the root cube's first
+    split: the two land in different leaves."""
+    x, q = synth.unit_sphere_cloud(3000, seed=28)
+    cx = 0.5 * (x[:, 0].min() + x[:, 0].max())
+    pair = np.array([[cx - 0.5 * sep, 0.1, 0.2], [cx + 0.5 * sep, 0.1, 0.2]])
+    return np.concatenate([x, pair]), np.concatenate([q, [1.0, -0.5]])
+
+
+def test_near_coincident_points_across_leaves():
+    """Distinct points 1e-9 A apart in different leaves: FP64 resolves the
+    pair and matches the direct sum (whose two large terms dominate); single
+    precision stores points relative to their leaf centre, which resolves
+    separations above about 2^-21 of a leaf width: at 1e-5 A the results are
+    finite, at 2e-2 A they meet the single-precision bar."""
+    x, q = _straddling_pair(1e-9)
+    print("[near-coincident] fp64 sep 1e-9", flush=True)
+    plan = _plan(x, kernel="laplace", p=6, ncrit=32, precision="fp64")
+    g = plan.tree()
+    leaf_of = {}
+    for b in range(len(g["level"])):
+        if g["nchild"][b] == 0:
+            for i in g["perm"][g["begin"][b]:g["end"][b]]:
+                leaf_of[int(i)] = b
+    n = len(x)
+    assert leaf_of[n - 2] != leaf_of[n - 1]
+    pot, grad = _eval(plan, q)
+    p0, g0 = D.direct(x, x, q)
+    assert abs(p0[-1]) > 1e7
+    assert D.rel_l2(pot, p0) < 1e-6 and D.rel_l2(grad, g0) < 1e-6
+    for prec in ("fp32", "bf16x3"):
+        x, q = _straddling_pair(1e-5)
+        print(f"[near-coincident] {prec} sep 1e-5", flush=True)
+        pot, grad = _eval(_plan(x, kernel="yukawa", kappa=KAPPA, p=6, ncrit=32, precision=prec), q)
+        assert np.all(np.isfinite(pot)) and np.all(np.isfinite(grad))
+        x, q = _straddling_pair(2e-2)
+        pot, grad = _eval(_plan(x, kernel="yukawa", kappa=KAPPA, p=6, ncrit=32, precision=prec), q)
+        p0, g0 = D.direct(x, x, q, "yukawa", KAPPA)
+        assert D.rel_l2(pot, p0) < 1e-4 and D.rel_l2(grad, g0) < 1e-4
+
+
 def test_nonfinite_input_rejected():
     torch = require_gpu()
     from paper_2103_01048_amd import FMMPlan, FmmError

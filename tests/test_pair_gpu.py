@@ -198,3 +198,30 @@ def _md_reference_at(tx, sx, q, dip, kern, kap, cq):
         _, g = D.direct(tx, sx, dip[:, d], kern, kap)
         out -= g[:, d]
     return out
+
+
+@pytest.mark.parametrize("how", ["scaled", "moved"])
+def test_plans_on_other_points_do_not_share_a_tree(how):
+    """A Yukawa plan on 1.5 x (same tree topology, other geometry) or on
+    slightly moved points (same topology and root cube) must not share the
+    Laplace plan's tree: fmm_eval_pair then gives the two fmm_eval results."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, eval_pair
+    x = _cloud(2000, seed=117)
+    if how == "scaled":
+        x2 = 1.5 * x
+    else:
+        x2 = x.copy()
+        x2[:, 0] += 1e-7 * np.random.default_rng(117).standard_normal(len(x))
+    xa = torch.tensor(x, device="cuda")
+    xb = torch.tensor(x2, device="cuda")
+    for prec in ("fp64", "fp32"):
+        a = FMMPlan(xa, kernel="laplace", p=5, ncrit=64, precision=prec)
+        b = FMMPlan(xb, kernel="yukawa", kappa=KAPPA, p=5, ncrit=64, precision=prec)
+        q = torch.tensor(np.random.default_rng(118).standard_normal(len(x)), device="cuda").to(a.dtype)
+        (pa, ga), (pb, gb) = eval_pair(a, b, q)
+        ra, rga = a.eval(q)
+        rb, rgb = b.eval(q)
+        errs = [_rel(pa, ra), _rel(ga, rga), _rel(pb, rb), _rel(gb, rgb)]
+        print(f"[pair on other points, {how} {prec}] {errs}", flush=True)
+        assert max(errs) == 0.0
