@@ -316,6 +316,22 @@ int bem_matvec(bem_op *op, const double *x_dev, double *y_dev, fmm_stream_t stre
 int bem_rhs(bem_op *op, const double *qxyz_dev, const double *q_dev, int64_t nq, double *b_dev,
             fmm_stream_t stream);
 
+/* bem_rhs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * same launches as bem_rhs (bitwise equal result) with no allocation and no
+ * free: its two temporary arrays (nq scaled charges, rounded up to 32, then
+ * the field at the operator's n_points quadrature points) live in one static
+ * device array of BEM_RHS_SCRATCH_DOUBLES doubles (64 MiB) per GPU, which the
+ * library holds until the process ends.  Requires
+ * roundup32(max(nq, 1)) + n_points <= BEM_RHS_SCRATCH_DOUBLES (bem_info's
+ * n_points), FMM_EINVAL otherwise, before any launch.  Every call on one GPU
+ * uses that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Asynchronous on `stream`; other errors as bem_rhs. */
+#define BEM_RHS_SCRATCH_DOUBLES (1 << 23)
+int bem_rhs_noalloc(bem_op *op, const double *qxyz_dev, const double *q_dev, int64_t nq, double *b_dev,
+                    fmm_stream_t stream);
+
 /* Polar solvation energy (kcal/mol) of the charges for the solution x_dev of
  * the operator's formulation (exterior unknowns are first mapped to the
  * solute side, v -> (eps_out/eps_in) v, by the interface conditions):

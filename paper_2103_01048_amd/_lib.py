@@ -15,6 +15,7 @@ FMM_FP64, FMM_FP32, FMM_FP32_BF16X3 = 0, 1, 2
 FMM_BEM_DIRECT, FMM_BEM_DERIVATIVE, FMM_BEM_EXTERIOR, FMM_BEM_EXTERIOR_P1 = 0, 1, 2, 3
 FMM_BEM_PRECOND_BLOCK, FMM_BEM_PRECOND_MASS = 0, 1
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOTCONV, FMM_EBREAKDOWN = 0, -1, -2, -3, -4, -5
+BEM_RHS_SCRATCH_DOUBLES = 1 << 23
 
 PHASES = ["permute", "p2m", "uc2e", "m2m", "p2l", "m2l", "m2l_sum", "l2l", "dc2e", "leaf", "near", "far"]
 
@@ -62,6 +63,7 @@ SIGNATURES = {
     "bem_setup": (i32, [vp, i64, vp, i64, i32, dbl, dbl, dbl, i32, i32, i32, i32, vp, P(vp)]),
     "bem_matvec": (i32, [vp, vp, vp, vp]),
     "bem_rhs": (i32, [vp, vp, vp, i64, vp, vp]),
+    "bem_rhs_noalloc": (i32, [vp, vp, vp, i64, vp, vp]),
     "bem_energy": (i32, [vp, vp, vp, vp, i64, P(dbl), vp]),
     "bem_precondition": (i32, [vp, vp, vp, vp]),
     "bem_set_preconditioner": (i32, [vp, i32, vp]),

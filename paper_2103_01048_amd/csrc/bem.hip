@@ -14,6 +14,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "fmm_internal.h"
@@ -1426,12 +1428,11 @@ int bem_precondition(bem_op *op, const double *x, double *y, fmm_stream_t stream
   return FMM_OK;
 }
 
-int bem_rhs(bem_op *op, const double *qxyz, const double *q, int64_t nq, double *b, fmm_stream_t stream) {
-  if (!op || !b || nq < 0 || (nq > 0 && (!qxyz || !q))) { set_error("bem_rhs: bad argument"); return FMM_EINVAL; }
-  hipStream_t s = (hipStream_t)stream;
-  double *sig = nullptr, *f = nullptr;
-  FMM_HIP_TRY(hipMallocAsync((void **)&sig, std::max<int64_t>(1, nq) * sizeof(double), s));
-  FMM_HIP_TRY(hipMallocAsync((void **)&f, op->N * sizeof(double), s));
+// The right-hand side's launches; sig (nq) and f (the operator's N
+// quadrature points) are temporary arrays that every launch writes before
+// it is read.
+static int rhs_core(bem_op *op, const double *qxyz, const double *q, int64_t nq, double *b, double *sig, double *f,
+                    hipStream_t s) {
   // sigma_k = q_k / eps_in (q_k / eps_out for the exterior formulation)
   const double eps = op->formulation == FMM_BEM_EXTERIOR || op->p1 ? op->eps_out : op->eps_in;
   hipLaunchKernelGGL(k_axpby, dim3(blocks(std::max<int64_t>(1, nq))), dim3(256), 0, s, nq, 1.0 / eps, q, 0.0, q, sig);
@@ -1457,9 +1458,65 @@ int bem_rhs(bem_op *op, const double *qxyz, const double *q, int64_t nq, double 
     hipLaunchKernelGGL(k_rhs_assemble2, dim3(blocks(op->nt)), dim3(256), 0, s, op->nt, op->nq, op->d_qw, f, b);
   }
   FMM_HIP_TRY(hipGetLastError());
-  FMM_HIP_TRY(hipFreeAsync(sig, s));
-  FMM_HIP_TRY(hipFreeAsync(f, s));
   return FMM_OK;
+}
+
+int bem_rhs(bem_op *op, const double *qxyz, const double *q, int64_t nq, double *b, fmm_stream_t stream) {
+  if (!op || !b || nq < 0 || (nq > 0 && (!qxyz || !q))) { set_error("bem_rhs: bad argument"); return FMM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  double *sig = nullptr, *f = nullptr;
+  FMM_HIP_TRY(hipMallocAsync((void **)&sig, std::max<int64_t>(1, nq) * sizeof(double), s));
+  FMM_HIP_TRY(hipMallocAsync((void **)&f, op->N * sizeof(double), s));
+  const int rc = rhs_core(op, qxyz, q, nq, b, sig, f, s);
+  (void)hipFreeAsync(sig, s);
+  (void)hipFreeAsync(f, s);
+  return rc;
+}
+
+// Scratch of bem_rhs_noalloc: its two temporary arrays (scaled charges, then
+// the field at the quadrature points, 256-byte aligned) in one static device
+// array per GPU, held until the process ends.  Host code never passes the
+// array's name (a host-side stand-in) to a launch: the device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) double scratch[BEM_RHS_SCRATCH_DOUBLES];
+
+static std::mutex g_scratch_mu;
+static std::vector<double *> g_scratch_dev;  // per device ordinal
+
+static int scratch_address(double **out) {
+  int dev = 0;
+  FMM_HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("bem_rhs_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+      return FMM_EHIP;
+    }
+    g_scratch_dev[dev] = (double *)p;
+  }
+  *out = g_scratch_dev[dev];
+  return FMM_OK;
+}
+
+int bem_rhs_noalloc(bem_op *op, const double *qxyz, const double *q, int64_t nq, double *b, fmm_stream_t stream) {
+  if (!op || !b || nq < 0 || (nq > 0 && (!qxyz || !q))) {
+    set_error("bem_rhs_noalloc: bad argument");
+    return FMM_EINVAL;
+  }
+  const int64_t nsig = (std::max<int64_t>(1, nq) + 31) / 32 * 32;  // f starts 256-byte aligned
+  if (nq > BEM_RHS_SCRATCH_DOUBLES || nsig + op->N > BEM_RHS_SCRATCH_DOUBLES) {
+    set_error("bem_rhs_noalloc: " + std::to_string(nq) + " charges and " + std::to_string(op->N) +
+              " quadrature points need " + std::to_string(nsig + op->N) + " doubles of scratch, more than the " +
+              std::to_string(BEM_RHS_SCRATCH_DOUBLES) + " it holds");
+    return FMM_EINVAL;
+  }
+  double *base = nullptr;
+  int rc;
+  if ((rc = scratch_address(&base))) return rc;
+  return rhs_core(op, qxyz, q, nq, b, base, base + nsig, (hipStream_t)stream);
 }
 
 int bem_energy(bem_op *op, const double *x, const double *qxyz, const double *q, int64_t nq, double *dG,

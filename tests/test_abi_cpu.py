@@ -99,3 +99,15 @@ def test_bem_setup_rejects_bad_arguments(case):
     rc = L.bem_setup(ctypes.c_void_p(v.ctypes.data), len(v), ctypes.c_void_p(t.ctypes.data), len(t), quad, eps, 80.0,
                      kap, 6, 64, 1, form, None, ctypes.byref(h))
     assert rc == _lib.FMM_EINVAL and not h.value
+
+
+def test_rhs_noalloc_rejects_null_operator_and_states_its_limit():
+    """bem_rhs_noalloc refuses a null operator before any GPU call; its
+    scratch limit is the header's BEM_RHS_SCRATCH_DOUBLES."""
+    L = _lib.lib()
+    b = ctypes.c_void_p(16)
+    assert L.bem_rhs_noalloc(None, None, None, 0, b, None) == _lib.FMM_EINVAL
+    assert "bad argument" in L.fmm_last_error().decode()
+    hdr = open(os.path.join(ROOT, "include", "fmmbem.h")).read()
+    m = re.search(r"#define BEM_RHS_SCRATCH_DOUBLES \(1 << (\d+)\)", hdr)
+    assert m and (1 << int(m.group(1))) == _lib.BEM_RHS_SCRATCH_DOUBLES
