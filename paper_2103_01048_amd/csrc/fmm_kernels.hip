@@ -1034,11 +1034,18 @@ __global__ __launch_bounds__(64) void k_far_pair(
     const bool own = (fe >> 30) & 1;
     const int bx = fe & 0x3fffffff;
     const T cx = far_o[4 * k], cy = far_o[4 * k + 1], cz = far_o[4 * k + 2], rr = far_o[4 * k + 3];
-    // targets relative to the surface centre (one shift per surface; each
-    // source then costs one fused multiply-add per coordinate)
-    const T xt = xi - cx, yt = yi - cy, zt = zi - cz;
+    // In units of the surface radius rr (targets u = (x - c) / rr, sources
+    // the unit grid g, kappa rr): g(rr s) = g_unit(s) / rr and the gradient
+    // scales by 1 / rr^2, so each surface is summed in unit coordinates and
+    // scaled once; a source then costs no multiply for its position.
+    const T irr = (T)1 / rr;
+    const T xt = (xi - cx) * irr, yt = (yi - cy) * irr, zt = (zi - cz) * irr;
+    const T ku = kappa * rr, ku2 = kl2 * rr;
     const T *__restrict__ da = (own ? eqd_a : equ_a) + (int64_t)bx * NR * ld;
     const T *__restrict__ db = (own ? eqd_b : equ_b) + (int64_t)bx * NR * ld;
+    T ua[NR], uxa[NR], uya[NR], uza[NR], ub[NR], uxb[NR], uyb[NR], uzb[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) ua[c] = uxa[c] = uya[c] = uza[c] = ub[c] = uxb[c] = uyb[c] = uzb[c] = (T)0;
     if (split == 1) {
 #pragma unroll 4
       for (int j = 0; j < nsurf; ++j) {
@@ -1046,8 +1053,8 @@ __global__ __launch_bounds__(64) void k_far_pair(
         T qa[NR], qb[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) { qa[c] = da[(int64_t)c * ld + j]; qb[c] = db[(int64_t)c * ld + j]; }
-        leaf_pair_ly<T, false, NR, GRAD>(xt, yt, zt, rr * g[0], rr * g[1], rr * g[2], qa, qb, kappa, kl2,
-                                   pa, xa, ya, za, pb, xb, yb, zb);
+        leaf_pair_ly<T, false, NR, GRAD>(xt, yt, zt, g[0], g[1], g[2], qa, qb, ku, ku2,
+                                   ua, uxa, uya, uza, ub, uxb, uyb, uzb);
       }
     } else {
 #pragma unroll 2
@@ -1061,8 +1068,18 @@ __global__ __launch_bounds__(64) void k_far_pair(
           qa[c] = ok ? da[(int64_t)c * ld + jj] : (T)0;
           qb[c] = ok ? db[(int64_t)c * ld + jj] : (T)0;
         }
-        leaf_pair_ly<T, false, NR, GRAD>(xt, yt, zt, rr * g[0], rr * g[1], rr * g[2], qa, qb, kappa, kl2,
-                                   pa, xa, ya, za, pb, xb, yb, zb);
+        leaf_pair_ly<T, false, NR, GRAD>(xt, yt, zt, g[0], g[1], g[2], qa, qb, ku, ku2,
+                                   ua, uxa, uya, uza, ub, uxb, uyb, uzb);
+      }
+    }
+    const T irr2 = irr * irr;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      pa[c] += ua[c] * irr;
+      pb[c] += ub[c] * irr;
+      if (GRAD) {
+        xa[c] += uxa[c] * irr2; ya[c] += uya[c] * irr2; za[c] += uza[c] * irr2;
+        xb[c] += uxb[c] * irr2; yb[c] += uyb[c] * irr2; zb[c] += uzb[c] * irr2;
       }
     }
   }
