@@ -182,6 +182,14 @@ typedef struct {
   int64_t n_far_interactions; /* leaf targets x surface points (M2P + L2P) */
   int32_t rank_up;       /* kept singular values of the upward check-to-equivalent map (max over levels) */
   int32_t rank_down;     /* same, downward */
+  /* wall time of the stages of fmm_setup, milliseconds */
+  double setup_sort_ms;  /* bounding box, Morton keys, radix sort on the device, sorted keys to the host */
+  double setup_tree_ms;  /* octree levels */
+  double setup_lists_ms; /* U, V, W, X lists */
+  double setup_items_ms; /* points into leaf order, leaf work items, near and far ranges, upload */
+  double setup_ops_ms;   /* translation operators (FP64 truncated SVDs and products), upload */
+  int32_t tree_on_device; /* 1: octree and lists built by device kernels */
+  int32_t tree_shared;    /* 1: tree, lists and leaf items taken from a live plan on the same points */
 } fmm_info_t;
 
 int fmm_info(const fmm_plan *plan, fmm_info_t *out);

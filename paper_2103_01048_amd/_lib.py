@@ -36,6 +36,9 @@ class FmmInfo(ctypes.Structure):
         ("n_v_pairs", ctypes.c_int64), ("n_w_pairs", ctypes.c_int64), ("n_x_pairs", ctypes.c_int64),
         ("n_p2p_interactions", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double),
         ("n_far_interactions", ctypes.c_int64), ("rank_up", ctypes.c_int32), ("rank_down", ctypes.c_int32),
+        ("setup_sort_ms", ctypes.c_double), ("setup_tree_ms", ctypes.c_double), ("setup_lists_ms", ctypes.c_double),
+        ("setup_items_ms", ctypes.c_double), ("setup_ops_ms", ctypes.c_double), ("tree_on_device", ctypes.c_int32),
+        ("tree_shared", ctypes.c_int32),
     ]
 
 

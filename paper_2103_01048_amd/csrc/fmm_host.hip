@@ -25,6 +25,7 @@
 #include <cstring>
 #include <atomic>
 #include <map>
+#include <mutex>
 #include <thread>
 
 #include "fmm_internal.h"
@@ -37,7 +38,9 @@ void set_error(const std::string &msg) { g_err = msg; }
 int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], double mx[3], bool *finite,
                 uint64_t *hash);
 int device_morton_sort(const double *xyz, int64_t n, const std::vector<int64_t> &off, const std::vector<double> &lo,
-                       double W, hipStream_t s, std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out);
+                       double W, hipStream_t s, std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out,
+                       uint64_t **keys_dev);
+int device_tree(fmm_plan *P, const uint64_t *d_keys, hipStream_t s, double *ms_tree, double *ms_lists);
 int device_gather_leaves(const double *xyz, const int32_t *perm, const std::vector<int64_t> &lb,
                          const std::vector<int64_t> &le, const std::vector<double> &lsh, int prec, void *pts,
                          hipStream_t s);
@@ -57,7 +60,7 @@ static int dev_alloc(fmm_plan *P, void **ptr, size_t bytes) {
     *ptr = nullptr;
     return FMM_ENOMEM;
   }
-  P->allocs.push_back(*ptr);
+  (P->alloc_sink ? *P->alloc_sink : P->allocs).push_back(*ptr);
   P->device_bytes += (int64_t)bytes;
   return FMM_OK;
 }
@@ -80,65 +83,6 @@ static int upload_real(fmm_plan *P, void **ptr, const std::vector<double> &h) {
 // ---------------------------------------------------------------------------
 // Tree
 // ---------------------------------------------------------------------------
-static inline int64_t prefix_of(int64_t key, int l) { return key >> (3 * (MAXLEVEL - l)); }
-
-static void build_tree(fmm_plan *P) {
-  // Breadth first from one root per (non-empty) molecule: boxes come out
-  // ordered by (level, molecule, key).
-  const std::vector<int64_t> &K = P->keys;
-  struct B { int l; int32_t mol; int64_t pre, b, e, par; };
-  std::vector<B> boxes;
-  const int nmol = (int)P->mol_off.size() - 1;
-  for (int m = 0; m < nmol; ++m)
-    if (P->mol_off[m + 1] > P->mol_off[m]) boxes.push_back({0, m, 0, P->mol_off[m], P->mol_off[m + 1], -1});
-  std::vector<int64_t> lb = {0};
-  int64_t lvl_start = 0, lvl_end = (int64_t)boxes.size();
-  while (true) {
-    lb.push_back(lvl_end);
-    for (int64_t bi = lvl_start; bi < lvl_end; ++bi) {
-      const B bx = boxes[bi];
-      if (bx.e - bx.b <= P->ncrit || bx.l >= MAXLEVEL) continue;
-      const int shift = 3 * (MAXLEVEL - (bx.l + 1));
-      int64_t pos = bx.b;
-      for (int c = 0; c < 8 && pos < bx.e; ++c) {
-        // first key of the next octant; the last octant ends with its parent
-        // (for a root, (7 + 1) << 60 would overflow the signed key type)
-        int64_t end = bx.e;
-        if (c < 7) {
-          const int64_t bound = (((bx.pre << 3) | c) + 1) << shift;
-          end = std::lower_bound(K.begin() + pos, K.begin() + bx.e, bound) - K.begin();
-        }
-        if (end > pos) boxes.push_back({bx.l + 1, bx.mol, (bx.pre << 3) | c, pos, end, bi});
-        pos = end;
-      }
-    }
-    if ((int64_t)boxes.size() == lvl_end) { lb.pop_back(); break; }
-    lvl_start = lvl_end;
-    lvl_end = (int64_t)boxes.size();
-  }
-  lb.push_back((int64_t)boxes.size());
-  const int64_t nb = (int64_t)boxes.size();
-  P->level.resize(nb); P->anchor.resize(3 * nb); P->begin.resize(nb); P->end.resize(nb);
-  P->parent.resize(nb); P->child_begin.assign(nb, -1); P->nchild.assign(nb, 0); P->mol.resize(nb);
-  for (int64_t b = 0; b < nb; ++b) {
-    const B &bx = boxes[b];
-    P->level[b] = bx.l; P->begin[b] = bx.b; P->end[b] = bx.e; P->parent[b] = bx.par; P->mol[b] = bx.mol;
-    int64_t a[3] = {0, 0, 0};
-    for (int k = 0; k < bx.l; ++k) {
-      const int64_t dig = (bx.pre >> (3 * (bx.l - 1 - k))) & 7;
-      a[0] = (a[0] << 1) | ((dig >> 2) & 1);
-      a[1] = (a[1] << 1) | ((dig >> 1) & 1);
-      a[2] = (a[2] << 1) | (dig & 1);
-    }
-    P->anchor[3 * b] = a[0]; P->anchor[3 * b + 1] = a[1]; P->anchor[3 * b + 2] = a[2];
-    if (bx.par >= 0) {
-      if (P->child_begin[bx.par] < 0) P->child_begin[bx.par] = b;
-      P->nchild[bx.par]++;
-    }
-  }
-  P->level_begin = lb;  // level l boxes: [lb[l], lb[l+1])
-}
-
 static inline int64_t interleave3(int64_t x, int64_t y, int64_t z, int l) {
   int64_t k = 0;
   for (int b = 0; b < l; ++b) {
@@ -793,10 +737,6 @@ static int upload_lists(fmm_plan *P) {
   if ((rc = upload(P, (void **)&D.far_off, fo))) return rc;
   if ((rc = upload(P, (void **)&D.far_idx, far))) return rc;
   if ((rc = upload(P, (void **)&D.split_tiles, split_tiles))) return rc;
-  {
-    const size_t es = P->precision == FMM_FP64 ? 8 : 4;
-    if ((rc = dev_alloc(P, &D.parts, std::max<size_t>(1, (size_t)nparts_total) * MAX_NR * 4 * 64 * es))) return rc;
-  }
   if ((rc = upload(P, (void **)&P->d_has_local, hl))) return rc;
   P->p2m_count = (int)p2m.size();
   if ((rc = upload(P, (void **)&P->d_p2m_box, p2m))) return rc;
@@ -1200,6 +1140,62 @@ void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
   P->prof_events.push_back({phase, {begin, e}});
 }
 
+// Live plans whose tree later plans on the same points may share.
+static std::mutex g_tree_mu;
+static std::vector<fmm_plan *> g_tree_plans;
+
+// A live plan whose tree P can take: the same input coordinates (checksum
+// over their bits, point count and molecule ranges), root cube, ncrit,
+// surface size (the leaf items depend on it), working type and device.
+static fmm_plan *find_tree(const fmm_plan *P) {
+  std::lock_guard<std::mutex> lock(g_tree_mu);
+  for (fmm_plan *A : g_tree_plans)
+    if (A->coord_hash == P->coord_hash && A->n == P->n && A->mol_off == P->mol_off && A->W == P->W &&
+        A->mol_lo == P->mol_lo && A->ncrit == P->ncrit && A->nsurf == P->nsurf &&
+        (A->precision == FMM_FP64) == (P->precision == FMM_FP64) && A->device == P->device && A->tree_mem)
+      return A;
+  return nullptr;
+}
+
+static void register_tree(fmm_plan *P) {
+  if (!P->tree_mem) return;
+  std::lock_guard<std::mutex> lock(g_tree_mu);
+  g_tree_plans.push_back(P);
+}
+
+static void unregister_tree(fmm_plan *P) {
+  std::lock_guard<std::mutex> lock(g_tree_mu);
+  g_tree_plans.erase(std::remove(g_tree_plans.begin(), g_tree_plans.end(), P), g_tree_plans.end());
+}
+
+// P takes A's host tree and lists and A's read-only device buffers (sorted
+// order, boxes, lists, leaf items, ranges); the sorted points (their fourth
+// slot takes densities during an evaluation) and the split-tile partial
+// sums are P's own.
+static int share_tree(fmm_plan *P, const fmm_plan *A, hipStream_t s) {
+  P->keys = A->keys; P->perm = A->perm;
+  P->level = A->level; P->nchild = A->nchild; P->anchor = A->anchor; P->begin = A->begin; P->end = A->end;
+  P->parent = A->parent; P->child_begin = A->child_begin; P->level_begin = A->level_begin; P->mol = A->mol;
+  for (int k = 0; k < 4; ++k) { P->loff[k] = A->loff[k]; P->lidx[k] = A->lidx[k]; }
+  P->leaf_ids = A->leaf_ids; P->vpair_src = A->vpair_src; P->vpair_tgt = A->vpair_tgt; P->p2l_boxes = A->p2l_boxes;
+  P->p2p_inter = A->p2p_inter; P->far_inter = A->far_inter;
+  P->tree_mem = A->tree_mem;
+  P->dt = A->dt;
+  P->dt.pts = nullptr;
+  P->dt.parts = nullptr;
+  P->dt.box_geom = nullptr;
+  P->d_has_local = A->d_has_local; P->d_p2m_box = A->d_p2m_box; P->d_p2m_off = A->d_p2m_off;
+  P->p2m_count = A->p2m_count;
+  P->tree_on_device = A->tree_on_device;
+  P->tree_shared = 1;
+  const size_t es = P->precision == FMM_FP64 ? 8 : 4;
+  int rc;
+  if ((rc = dev_alloc(P, &P->dt.pts, (size_t)P->n * 4 * es))) return rc;
+  FMM_HIP_TRY(hipMemcpyAsync(P->dt.pts, A->dt.pts, (size_t)P->n * 4 * es, hipMemcpyDeviceToDevice, s));
+  if ((rc = dev_alloc(P, &P->dt.parts, std::max<size_t>(1, (size_t)P->dt.nparts) * MAX_NR * 4 * 64 * es))) return rc;
+  return FMM_OK;
+}
+
 }  // namespace fmm
 
 using namespace fmm;
@@ -1238,6 +1234,12 @@ static int setup_common(const double *xyz_dev, const std::vector<int64_t> &off, 
   hipStream_t s = (hipStream_t)stream;
   const int nmol = (int)off.size() - 1;
   int rc = FMM_OK;
+  auto tl = std::chrono::steady_clock::now();
+  auto lap = [&](int stage) {  // time since the previous stage into setup_split[stage]
+    const auto now = std::chrono::steady_clock::now();
+    P->setup_split[stage] += std::chrono::duration<double, std::milli>(now - tl).count();
+    tl = now;
+  };
   do {
     if (n == 0) {
       P->level = {0}; P->nchild = {0}; P->anchor = {0, 0, 0}; P->begin = {0}; P->end = {0}; P->parent = {-1};
@@ -1269,13 +1271,38 @@ static int setup_common(const double *xyz_dev, const std::vector<int64_t> &off, 
     for (int m = 0; m < nmol; ++m)
       for (int d = 0; d < 3; ++d) P->mol_lo[3 * m + d] = cen[3 * m + d] - 0.5 * P->W;
     for (int d = 0; d < 3; ++d) { P->lo[d] = P->mol_lo[d]; P->shift[d] = P->lo[d] + 0.5 * P->W; }
-    if ((rc = device_morton_sort(xyz_dev, n, off, P->mol_lo, P->W, s, P->keys, P->perm))) break;
-    build_tree(P);
-    build_lists(P);
-    // device tree
+    if (fmm_plan *A = find_tree(P)) {
+      // a live plan on the same points, ncrit, surface size and working
+      // type: take its tree, lists and leaf items instead of building them
+      if ((rc = share_tree(P, A, s))) break;
+      lap(3);
+    } else {
+    P->tree_mem = std::make_shared<SharedAllocs>();
+    uint64_t *d_keys = nullptr;
+    if ((rc = device_morton_sort(xyz_dev, n, off, P->mol_lo, P->W, s, P->keys, P->perm, &d_keys))) break;
+    lap(0);
+    // octree levels and lists on the device; the host build remains for a
+    // tree whose U/W traversal outgrows the device stack
+    double ms_tree = 0, ms_lists = 0;
+    const int trc = device_tree(P, d_keys, s, &ms_tree, &ms_lists);
+    (void)hipFree(d_keys);
+    if (trc < 0) { rc = trc; break; }
+    lap(1);
+    P->setup_split[1] -= ms_lists;
+    P->setup_split[2] += ms_lists;
+    P->tree_on_device = 1;
+    if (trc == 1) {
+      build_lists(P);
+      P->tree_on_device = 0;
+      lap(2);
+    }
+    // device tree (buffers shared with later plans on the same points)
+    P->alloc_sink = &P->tree_mem->ptrs;
     std::vector<int32_t> perm32(n);
     for (int64_t i = 0; i < n; ++i) perm32[i] = (int32_t)P->perm[i];
-    if ((rc = upload(P, (void **)&P->dt.perm, perm32))) break;
+    rc = upload(P, (void **)&P->dt.perm, perm32);
+    P->alloc_sink = nullptr;
+    if (rc) break;
     const size_t es = precision == FMM_FP64 ? 8 : 4;
     if ((rc = dev_alloc(P, &P->dt.pts, (size_t)n * 4 * es))) break;
     P->dt.n = n;
@@ -1297,15 +1324,24 @@ static int setup_common(const double *xyz_dev, const std::vector<int64_t> &off, 
       rc = device_gather_leaves(xyz_dev, P->dt.perm, lb, le, lsh, precision, P->dt.pts, s);
     }
     if (rc) break;
-    if ((rc = upload_lists(P))) break;
+    P->alloc_sink = &P->tree_mem->ptrs;
+    rc = upload_lists(P);
+    P->alloc_sink = nullptr;
+    if (rc) break;
+    // per-plan scratch: partial sums of split leaf tiles
+    if ((rc = dev_alloc(P, &P->dt.parts, std::max<size_t>(1, (size_t)P->dt.nparts) * MAX_NR * 4 * 64 * es))) break;
+    lap(3);
+    }
     P->tree_hash = tree_fingerprint(P);
     rc = precision == FMM_FP64 ? precompute_typed<double>(P) : precompute_typed<float>(P);
     if (rc) break;
     hipError_t e = hipStreamSynchronize(s);
+    lap(4);
     if (e != hipSuccess) { set_error(std::string("fmm_setup: ") + hipGetErrorString(e)); rc = FMM_EHIP; }
   } while (0);
   if (rc) { fmm_free(P); return rc; }
   P->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  register_tree(P);
   *out = P;
   return FMM_OK;
 }
@@ -1420,6 +1456,13 @@ int fmm_info(const fmm_plan *P, fmm_info_t *o) {
   o->device_bytes = P->device_bytes;
   o->setup_ms = P->setup_ms;
   o->n_far_interactions = P->far_inter;
+  o->setup_sort_ms = P->setup_split[0];
+  o->setup_tree_ms = P->setup_split[1];
+  o->setup_lists_ms = P->setup_split[2];
+  o->setup_items_ms = P->setup_split[3];
+  o->setup_ops_ms = P->setup_split[4];
+  o->tree_on_device = P->tree_on_device;
+  o->tree_shared = P->tree_shared;
   for (size_t l = 0; l < P->rank_u.size(); ++l) o->rank_up = std::max(o->rank_up, (int32_t)P->rank_u[l]);
   for (size_t l = 0; l < P->rank_d.size(); ++l) o->rank_down = std::max(o->rank_down, (int32_t)P->rank_d[l]);
   return FMM_OK;
@@ -1485,6 +1528,7 @@ int fmm_get_phase_times(fmm_plan *P, double *ms, int64_t *launches, int nphase) 
 
 void fmm_free(fmm_plan *P) {
   if (!P) return;
+  unregister_tree(P);
   for (auto &pe : P->prof_events) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
   for (hipEvent_t e : P->event_pool) (void)hipEventDestroy(e);
   if (P->aux) {

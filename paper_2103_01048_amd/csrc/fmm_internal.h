@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -132,6 +133,15 @@ struct DevTree {
   std::vector<int> m2m_n;
 };
 
+// Device buffers of a tree (sorted order, boxes, lists, leaf items) that
+// plans on the same points share; freed when the last plan holding them is.
+struct SharedAllocs {
+  std::vector<void *> ptrs;
+  ~SharedAllocs() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+};
+
 }  // namespace fmm
 
 struct fmm_plan {
@@ -200,5 +210,9 @@ struct fmm_plan {
   size_t adj_bytes = 0;
   int64_t device_bytes = 0;
   double setup_ms = 0;
+  double setup_split[5] = {0, 0, 0, 0, 0};  // sort, tree, lists, items, operators (ms)
+  int tree_on_device = 0, tree_shared = 0;
   std::vector<void *> allocs;      // everything to free
+  std::shared_ptr<fmm::SharedAllocs> tree_mem;  // the tree's device buffers (shared with plans on the same points)
+  std::vector<void *> *alloc_sink = nullptr;    // where dev_alloc records a buffer (null: allocs)
 };

@@ -185,9 +185,12 @@ int device_bbox(const double *xyz, int64_t n, hipStream_t s, double mn[3], doubl
 
 // Morton keys (each molecule in its own root cube of side W, lower corner
 // lo[3m..3m+2]) and a stable radix sort within each molecule's range; the
-// sorted keys and the permutation (global indices) come back to the host.
+// sorted keys and the permutation (global indices) come back to the host,
+// and with keys_dev the device copy of the sorted keys is kept (the caller
+// frees it).
 int device_morton_sort(const double *xyz, int64_t n, const std::vector<int64_t> &off, const std::vector<double> &lo,
-                       double W, hipStream_t s, std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out) {
+                       double W, hipStream_t s, std::vector<int64_t> &keys_out, std::vector<int64_t> &perm_out,
+                       uint64_t **keys_dev) {
   const int nmol = (int)off.size() - 1;
   uint64_t *k0 = nullptr, *k1 = nullptr;
   int32_t *v0 = nullptr, *v1 = nullptr;
@@ -237,6 +240,11 @@ int device_morton_sort(const double *xyz, int64_t n, const std::vector<int64_t> 
       perm_out.resize(n);
       for (int64_t i = 0; i < n; ++i) { keys_out[i] = (int64_t)hk[i]; perm_out[i] = hv[i]; }
     }
+  }
+  // the sorted keys stay on the device for the tree build when asked for
+  if (keys_dev && rc == FMM_OK) {
+    *keys_dev = k1;
+    k1 = nullptr;
   }
   (void)hipFree(k0); (void)hipFree(k1); (void)hipFree(v0); (void)hipFree(v1); (void)hipFree(tmp); (void)hipFree(d_off);
   return rc;

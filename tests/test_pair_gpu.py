@@ -225,3 +225,38 @@ def test_plans_on_other_points_do_not_share_a_tree(how):
         errs = [_rel(pa, ra), _rel(ga, rga), _rel(pb, rb), _rel(gb, rgb)]
         print(f"[pair on other points, {how} {prec}] {errs}", flush=True)
         assert max(errs) == 0.0
+
+
+def test_second_plan_shares_the_tree_and_outlives_the_first():
+    """A Yukawa plan built while a Laplace plan on the same points (same
+    ncrit, p, working type) is alive takes that plan's tree, lists and leaf
+    items (fmm_info: tree_shared); freeing the Laplace plan leaves the Yukawa
+    plan's results unchanged.  Plans on other points, or with another ncrit,
+    build their own tree on the device."""
+    torch = require_gpu()
+    import gc
+    from paper_2103_01048_amd import FMMPlan
+    x = _cloud(3000, seed=119)
+    xt = torch.tensor(x, device="cuda")
+    q = torch.tensor(np.random.default_rng(119).standard_normal(len(x)), device="cuda", dtype=torch.float32)
+    a = FMMPlan(xt, kernel="laplace", p=6, ncrit=64, precision="bf16x3")
+    b = FMMPlan(xt, kernel="yukawa", kappa=KAPPA, p=6, ncrit=64, precision="bf16x3")
+    ia, ib = a.info(), b.info()
+    assert ia["tree_on_device"] == 1 and ia["tree_shared"] == 0
+    assert ib["tree_shared"] == 1 and ib["n_boxes"] == ia["n_boxes"]
+    ta, tb = a.tree(), b.tree()
+    for k in ("perm", "keys", "level", "anchor", "begin", "end", "list_off", "list_idx"):
+        assert np.array_equal(ta[k], tb[k]), k
+    pb0, gb0 = b.eval(q)
+    torch.cuda.synchronize()
+    pb0, gb0 = pb0.clone(), gb0.clone()
+    del a
+    gc.collect()
+    pb1, gb1 = b.eval(q)
+    torch.cuda.synchronize()
+    assert torch.equal(pb0, pb1) and torch.equal(gb0, gb1)
+    c = FMMPlan(xt, kernel="yukawa", kappa=KAPPA, p=6, ncrit=48, precision="bf16x3")
+    d = FMMPlan(torch.tensor(1.01 * x, device="cuda"), kernel="laplace", p=6, ncrit=64, precision="bf16x3")
+    e = FMMPlan(xt, kernel="laplace", p=6, ncrit=64, precision="bf16x3")
+    assert c.info()["tree_shared"] == 0 and d.info()["tree_shared"] == 0
+    assert e.info()["tree_shared"] == 1  # from b, which holds the tree alone now
