@@ -598,6 +598,11 @@ static int upload_lists(fmm_plan *P) {
     L.m = P->end[b] - P->begin[b];
     std::vector<Rng> rg;
     auto add_range = [&](int64_t a) {
+      if (!P->nchild[a]) {  // a leaf is its own range
+        if (P->end[a] > P->begin[a]) rg.push_back({(int32_t)P->begin[a], (int32_t)P->end[a], (int32_t)a});
+        inter += L.m * (P->end[a] - P->begin[a]);
+        return;
+      }
       auto it = std::lower_bound(leaf_at.begin(), leaf_at.end(), std::make_pair(P->begin[a], (int64_t)-1));
       for (; it != leaf_at.end() && it->first < P->end[a]; ++it) {
         const int64_t lf = it->second;
@@ -646,7 +651,9 @@ static int upload_lists(fmm_plan *P) {
     }
   }
   const double cap = std::max(512.0, total / 16384.0);
-  struct Item { double cost; int32_t slot, code, part; std::vector<Rng> near; std::vector<int32_t> far; };
+  // an item of a whole tile reads its leaf's range lists (whole = true);
+  // the parts of a split tile carry their own cut lists
+  struct Item { double cost; int32_t slot, code, part; bool whole; std::vector<Rng> near; std::vector<int32_t> far; };
   std::vector<Item> items;
   std::vector<int32_t> split_tiles;  // (slot, code, first part, nparts)
   int32_t nparts_total = 0;
@@ -655,21 +662,21 @@ static int upload_lists(fmm_plan *P) {
     const int32_t code = t.t0 | (t.split << 24);
     const int nparts = (int)std::ceil(t.cost / cap - 1e-9);
     if (nparts <= 1) {
-      items.push_back({t.cost, t.slot, code, -1, L.near, L.far});
+      items.push_back({t.cost, t.slot, code, -1, true, {}, {}});
       continue;
     }
     const double per = t.cost * t.split / nparts;  // unsplit-source units per part
     split_tiles.push_back(t.slot); split_tiles.push_back(code);
     split_tiles.push_back(nparts_total);
     int made = 0;
-    Item cur{0, t.slot, code, nparts_total, {}, {}};
+    Item cur{0, t.slot, code, nparts_total, false, {}, {}};
     double acc = 0;
     auto flush = [&]() {
       cur.cost = acc / t.split;
       cur.part = nparts_total++;
-      items.push_back(cur);
+      items.push_back(std::move(cur));
       ++made;
-      cur = Item{0, t.slot, code, 0, {}, {}};
+      cur = Item{0, t.slot, code, 0, false, {}, {}};
       acc = 0;
     };
     for (auto r : L.near) {
@@ -690,8 +697,10 @@ static int upload_lists(fmm_plan *P) {
     if (!cur.near.empty() || !cur.far.empty() || made == 0) flush();
     split_tiles.push_back(made);
   }
-  // longest items first
-  std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+  // longest items first (a stable sort of their indices)
+  std::vector<int32_t> order(items.size());
+  for (size_t i = 0; i < items.size(); ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return items[x].cost > items[y].cost; });
   // centre of box b relative to its molecule's root centre (FP64)
   auto cen = [&](int64_t b, int d) {
     const double sd = P->W / (double)(1ll << P->level[b]);
@@ -702,23 +711,26 @@ static int upload_lists(fmm_plan *P) {
   // the surface radius
   std::vector<int32_t> it4, no = {0}, nrng, fo = {0}, far;
   std::vector<double> near_o, far_o;
-  for (const Item &it : items) {
+  for (const int32_t io : order) {
+    const Item &it = items[io];
     const int64_t tb = leaves[it.slot];
+    const std::vector<Rng> &inear = it.whole ? src[it.slot].near : it.near;
+    const std::vector<int32_t> &ifar = it.whole ? src[it.slot].far : it.far;
     it4.push_back(it.slot); it4.push_back(it.code); it4.push_back(it.part); it4.push_back(0);
-    for (auto &r : it.near) {
+    for (auto &r : inear) {
       nrng.push_back(r.j0); nrng.push_back(r.j1);
       for (int d = 0; d < 3; ++d) near_o.push_back(cen(r.src, d) - cen(tb, d));
       near_o.push_back(0.0);
     }
     no.push_back((int32_t)(nrng.size() / 2));
-    for (int32_t f : it.far) {
+    for (int32_t f : ifar) {
       const bool own = (f >> 30) & 1;
       const int64_t a = f & 0x3fffffff;
       const double h = 0.5 * P->W / (double)(1ll << P->level[a]);
       for (int d = 0; d < 3; ++d) far_o.push_back(cen(a, d) - cen(tb, d));
       far_o.push_back(h * (own ? ALPHA_DE : ALPHA_UE));
     }
-    far.insert(far.end(), it.far.begin(), it.far.end());
+    far.insert(far.end(), ifar.begin(), ifar.end());
     fo.push_back((int32_t)far.size());
   }
   P->leaf_ids = leaves;
@@ -761,37 +773,54 @@ static int upload_lists(fmm_plan *P) {
   if ((rc = upload(P, (void **)&D.x_off, xo))) return rc;
   if ((rc = upload(P, (void **)&D.x_idx, xi))) return rc;
   if ((rc = upload_real(P, &D.x_o, x_o))) return rc;
-  // V pairs in GEMM order: (level, offset code, target)
-  struct VP { int l, code; int64_t tgt, src; };
-  std::vector<VP> vp;
-  for (int64_t b = 0; b < nb; ++b)
-    for (int64_t k = P->loff[1][b]; k < P->loff[1][b + 1]; ++k) {
-      const int64_t a = P->lidx[1][k];
-      vp.push_back({P->level[b], m2l_code((int)(P->anchor[3 * a] - P->anchor[3 * b]), (int)(P->anchor[3 * a + 1] - P->anchor[3 * b + 1]),
-                                          (int)(P->anchor[3 * a + 2] - P->anchor[3 * b + 2])), b, a});
+  // V pairs in GEMM order, (level, offset code, target): a counting sort over
+  // the 343 offset codes of each level, stable in target order (boxes and
+  // their V lists are visited in order).  vpp gives, per V-list entry in
+  // target-major order (the order of each box's sum: its V list, ascending
+  // source id), the pair's position in GEMM order.
+  {
+    const int64_t nv = P->loff[1][nb];
+    const int nbucket = (MAXLEVEL + 1) * 343;
+    std::vector<int32_t> bucket((size_t)nv);
+    std::vector<int64_t> cursor((size_t)nbucket + 1, 0);
+    for (int64_t b = 0; b < nb; ++b)
+      for (int64_t k = P->loff[1][b]; k < P->loff[1][b + 1]; ++k) {
+        const int64_t a = P->lidx[1][k];
+        const int c = m2l_code((int)(P->anchor[3 * a] - P->anchor[3 * b]),
+                               (int)(P->anchor[3 * a + 1] - P->anchor[3 * b + 1]),
+                               (int)(P->anchor[3 * a + 2] - P->anchor[3 * b + 2]));
+        bucket[k] = P->level[b] * 343 + c;
+        cursor[bucket[k] + 1]++;
+      }
+    for (int i = 0; i < nbucket; ++i) cursor[i + 1] += cursor[i];
+    P->vpair_src.resize((size_t)nv);
+    P->vpair_tgt.resize((size_t)nv);
+    std::vector<int32_t> vpp((size_t)nv);
+    for (int64_t b = 0; b < nb; ++b)
+      for (int64_t k = P->loff[1][b]; k < P->loff[1][b + 1]; ++k) {
+        const int64_t pos = cursor[bucket[k]]++;
+        P->vpair_src[pos] = (int32_t)P->lidx[1][k];
+        P->vpair_tgt[pos] = (int32_t)b;
+        vpp[k] = (int32_t)pos;
+      }
+    // every box at level >= 2 gets its sum (possibly empty); those boxes
+    // are the last ones (boxes are ordered by level) and hold every V entry
+    std::vector<int32_t> vt, vo;
+    const int64_t b2 = P->level_begin.size() > 2 ? P->level_begin[2] : nb;
+    for (int64_t b = b2; b < nb; ++b) {
+      vt.push_back((int32_t)b);
+      vo.push_back((int32_t)(P->loff[1][b] - P->loff[1][b2]));
     }
-  std::stable_sort(vp.begin(), vp.end(), [](const VP &x, const VP &y) {
-    if (x.l != y.l) return x.l < y.l;
-    if (x.code != y.code) return x.code < y.code;
-    return x.tgt < y.tgt;
-  });
-  P->vpair_src.resize(vp.size());
-  P->vpair_tgt.resize(vp.size());
-  std::vector<std::vector<int32_t>> per_tgt(nb);
-  for (size_t i = 0; i < vp.size(); ++i) {
-    P->vpair_src[i] = (int32_t)vp[i].src;
-    P->vpair_tgt[i] = (int32_t)vp[i].tgt;
-    per_tgt[vp[i].tgt].push_back((int32_t)i);
-  }
-  std::vector<int32_t> vt, vo = {0}, vpp;
-  for (int64_t b = 0; b < nb; ++b) {
-    if (P->level[b] < 2) continue;  // every box at level >= 2 gets its sum (possibly empty)
-    // reduction order: by source box id (the V-list order)
-    std::sort(per_tgt[b].begin(), per_tgt[b].end(),
-              [&](int32_t x, int32_t y) { return P->vpair_src[x] < P->vpair_src[y]; });
-    vt.push_back((int32_t)b);
-    vpp.insert(vpp.end(), per_tgt[b].begin(), per_tgt[b].end());
-    vo.push_back((int32_t)vpp.size());
+    vo.push_back((int32_t)(P->loff[1][nb] - P->loff[1][b2]));
+    if (P->loff[1][b2] != 0) {
+      set_error("internal: V lists above level 2");
+      return FMM_EINVAL;
+    }
+    D.nvbox = (int)vt.size();
+    D.nvpair = nv;
+    if ((rc = upload(P, (void **)&D.v_tgt, vt))) return rc;
+    if ((rc = upload(P, (void **)&D.v_off, vo))) return rc;
+    if ((rc = upload(P, (void **)&D.v_pair, vpp))) return rc;
   }
   // M2M sums: per level, the non-leaf boxes and their children (octant order)
   D.m2m_tgt.assign(D.maxlevel + 1, nullptr);
@@ -811,11 +840,6 @@ static int upload_lists(fmm_plan *P) {
     if ((rc = upload(P, (void **)&D.m2m_off[l], of))) return rc;
     if ((rc = upload(P, (void **)&D.m2m_kid[l], kd))) return rc;
   }
-  D.nvbox = (int)vt.size();
-  D.nvpair = (int64_t)vp.size();
-  if ((rc = upload(P, (void **)&D.v_tgt, vt))) return rc;
-  if ((rc = upload(P, (void **)&D.v_off, vo))) return rc;
-  if ((rc = upload(P, (void **)&D.v_pair, vpp))) return rc;
   return FMM_OK;
 }
 
