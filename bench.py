@@ -39,7 +39,9 @@ METRIC = "FMM matvec Mpoints/s (Laplace+Yukawa) at rel err ≤1e-4; FP32 vs FP64
 KAPPA = 0.125
 P_ORDER = 8
 PEAK_VALU_FP32 = 157.3e12  # MI355X vector FP32 (packed) FLOP/s
+PEAK_VALU_FP32_UNPACKED = 78.6e12  # the same without packed FP32 instructions (disabled in this build)
 PEAK_MFMA = {"fp32": 157.3e12, "fp64": 78.6e12, "bf16x3": 2.5e15}
+PEAK_BF16X3_USEFUL = 2.5e15 / 3  # three bf16 products per useful product
 PEAK_HBM = 8.0e12
 
 # Algorithmic flops per kernel evaluation (one target-source pair, one
@@ -54,6 +56,64 @@ PEAK_HBM = 8.0e12
 #            -kappa r (1), exp (1), g (1), (1 + kappa r) g / r^2 (4),
 #            per kernel pot (2) + f q (1) + grad (6)                    = 37
 FLOP_PER_PAIR = {"laplace": 20, "yukawa": 27, "pair": 37}
+# The survey's count for one pair of both kernels (potential and gradient):
+# Laplace 18 flop + 1 rsqrt, Yukawa about 24 flop + rsqrt + exp2 = 45; the
+# roofline fractions use it, the fused count (37, shared distance) is
+# reported beside it.
+FLOP_PER_PAIR_SURVEY = 45
+# Surface evaluation (P2M, P2L): potential of both kernels from one
+# distance: d (3), r2 (5), rsqrt (1), Laplace q/r (2), r (1), -kappa r (1),
+# exp2 (1), g (1), Yukawa q g (2)
+FLOP_PER_SURF_PAIR = 17
+
+
+def phase_work(plan_l, plan_y, infos):
+    """Algorithmic work of each phase of one pair step (both kernels, one
+    column) and the peak that bounds it.  Translation counts use each plan's
+    largest rank (an upper bound where the ranks vary by level)."""
+    tl = plan_l.tree()
+    lev = tl["level"]
+    nch = tl["nchild"]
+    size = tl["end"] - tl["begin"]
+    X = tl["X"]
+    inf_l, inf_y = infos["laplace"], infos["yukawa"]
+    ns = inf_l["n_surf"]
+    leaf = nch == 0
+    p2m_pairs = int(ns * size[leaf & (lev >= 2)].sum())
+    p2l_pairs = 0
+    p2l_boxes = 0
+    for b in range(len(lev)):
+        if X[b] and not (leaf[b] and size[b] <= ns):
+            p2l_boxes += 1
+            p2l_pairs += ns * int(sum(size[a] for a in X[b]))
+    nleaf2 = int((leaf & (lev >= 2)).sum())
+    child2 = int((lev >= 3).sum())  # boxes with a parent at level >= 2 (M2M, L2L)
+    ranks = [(inf_l["rank_up"], inf_l["rank_down"]), (inf_y["rank_up"], inf_y["rank_down"])]
+    gemm = lambda f: float(sum(f(ru, rd) for ru, rd in ranks))
+    nv = inf_l["n_v_pairs"]
+    work = {
+        "p2m": (p2m_pairs * FLOP_PER_SURF_PAIR, PEAK_VALU_FP32, "flop"),
+        "uc2e": (gemm(lambda ru, rd: 2.0 * ru * ns * nleaf2), PEAK_MFMA["fp32"], "flop"),
+        "m2m": (gemm(lambda ru, rd: 2.0 * ru * ru * child2), PEAK_MFMA["fp32"], "flop"),
+        "m2l": (gemm(lambda ru, rd: 2.0 * ru * rd * nv), PEAK_BF16X3_USEFUL, "flop"),
+        "m2l_sum": (gemm(lambda ru, rd: 4.0 * rd * nv), PEAK_HBM, "byte"),
+        "p2l": (p2l_pairs * FLOP_PER_SURF_PAIR, PEAK_VALU_FP32, "flop"),
+        "dc2e": (gemm(lambda ru, rd: 2.0 * rd * ns * (p2l_boxes + nleaf2)), PEAK_MFMA["fp32"], "flop"),
+        "l2l": (gemm(lambda ru, rd: 2.0 * rd * rd * child2), PEAK_MFMA["fp32"], "flop"),
+        "near": (float(inf_l["n_p2p_interactions"]) * FLOP_PER_PAIR_SURVEY, PEAK_VALU_FP32, "flop"),
+        "far": (float(inf_l["n_far_interactions"]) * FLOP_PER_PAIR_SURVEY, PEAK_VALU_FP32, "flop"),
+    }
+    return work
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def measured_traffic(kernel: str, phase: str, precision: str):
@@ -106,7 +166,8 @@ def parse():
                     help="single-precision path timed for `value` (bf16x3: FP32 with the M2L contraction as "
                          "three bf16 MFMA products and FP32 accumulation)")
     ap.add_argument("--fp64-steps", type=int, default=5)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=6.0,
+                    help="CPU time of one run of the sampled oracle rows (three runs are timed)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (reference for HBM byte counters)")
@@ -423,15 +484,30 @@ def main():
 
     plans = make(args.precision, ncrit)
     infos = {k: pl.info() for k, pl in plans.items()}
-    # untimed pass with every phase timed: phase breakdown and dominant kernel
-    _, prof_all = time_steps(step_pair, plans, qd, 3, 1, profile={k: True for k in plans})
+    # untimed pass with every phase timed, every pass on the caller's stream
+    # one after the other (FMM_PROFILE_SERIAL): each phase's own time, not
+    # stretched by the passes that share the GPU with it in the timed step
+    for pl in plans.values():
+        pl.set_profiling(False)
+    for _ in range(2):
+        step_pair(plans, qd)
+    torch.cuda.synchronize()
+    plans["laplace"].phase_times()
+    plans["laplace"].set_profiling(True, serial=True)
+    nser = 5
+    t0 = time.perf_counter()
+    for _ in range(nser):
+        step_pair(plans, qd)
+    torch.cuda.synchronize()
+    t_serial = (time.perf_counter() - t0) / nser
+    prof_all = {"laplace": plans["laplace"].phase_times()}
+    plans["laplace"].set_profiling(False)
     tot = {}
     for k, ph in prof_all.items():
         for name, (ms, cnt) in ph.items():
             tot[(k, name)] = (ms, cnt)
     # the dominant kernel: the larger of the two leaf launches on the caller's
-    # stream (the far-field passes share the GPU with the near field, so their
-    # event times stretch to its length and do not measure their own work)
+    # stream
     (dk, dname), _ = max(((k, v) for k, v in tot.items() if k[1] in ("near", "far")), key=lambda kv: kv[1][0])
     # timed region: only the dominant kernel's launches carry HIP events
     dt, prof = time_steps(step_pair, plans, qd, args.steps, args.warmup, profile={dk: [dname]})
@@ -475,7 +551,7 @@ def main():
         flops = 2.0 * inf["n_v_pairs"] * inf["rank_up"] * inf["rank_down"]
         roof = {"bound": "mfma", "peak": PEAK_MFMA[args.precision], "unit": "TFLOP/s"}
     elif dname in ("leaf", "near", "far"):
-        per = FLOP_PER_PAIR[dk] if dname == "leaf" else FLOP_PER_PAIR["pair"]
+        per = FLOP_PER_PAIR[dk] if dname == "leaf" else FLOP_PER_PAIR_SURVEY
         pairs = {"leaf": inf["n_p2p_interactions"] + inf["n_far_interactions"],
                  "near": inf["n_p2p_interactions"], "far": inf["n_far_interactions"]}[dname]
         flops = float(per * pairs)
@@ -490,6 +566,30 @@ def main():
                 "peak": round(roof["peak"] / 1e12, 1), "unit": roof["unit"],
                 "frac": round(achieved / roof["peak"], 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_launch": flops}
+    if dname in ("near", "far"):
+        fused = flops / FLOP_PER_PAIR_SURVEY * FLOP_PER_PAIR["pair"]
+        roofline.update({
+            "flop_per_pair": FLOP_PER_PAIR_SURVEY, "flop_per_pair_fused": FLOP_PER_PAIR["pair"],
+            "achieved_fused": round(fused / (avg_ms * 1e-3) / 1e12, 3),
+            "peak_unpacked": round(PEAK_VALU_FP32_UNPACKED / 1e12, 1),
+            "frac_unpacked": round(achieved / PEAK_VALU_FP32_UNPACKED, 4)})
+    # every phase: its algorithmic work, its own time (serial mode, HIP
+    # events around its launches) and the fraction of its bounding peak; the
+    # whole call: sum over phases of work / peak, over the timed step
+    work = phase_work(plans["laplace"], plans["yukawa"], infos)
+    phases_out = {}
+    ideal = 0.0
+    for name, (w, peak, unit) in work.items():
+        ms_ph = tot.get(("laplace", name), (0.0, 0))[0] / nser
+        ideal += w / peak
+        phases_out[name] = {"work": w, "unit": unit, "ms": round(ms_ph, 4),
+                            "rate": round(w / (ms_ph * 1e-3) / (1e9 if unit == "byte" else 1e12), 3) if ms_ph else None,
+                            "rate_unit": "GB/s" if unit == "byte" else "TFLOP/s",
+                            "peak_frac": round(w / peak / (ms_ph * 1e-3), 4) if ms_ph else None}
+    whole = {"ideal_ms": round(ideal * 1e3, 4), "step_ms": round(ms_step, 4),
+             "frac": round(ideal / (ms_step * 1e-3), 4), "serial_step_ms": round(t_serial * 1e3, 4),
+             "note": "sum over phases of algorithmic work / that phase's peak (VALU 157.3 TF, FP32 MFMA 157.3 TF, "
+                     "bf16x3 useful 833 TF, HBM 8 TB/s) divided by the timed step; phase ms from the serial mode"}
     # CPU baseline (FP64 direct sum oracle) on a bounded sample of target rows;
     # the same sums gate the accuracy of the GPU outputs
     cpu = None
@@ -505,17 +605,21 @@ def main():
         t_probe = time.perf_counter() - t0
         rows = int(min(n, max(1024, 1024 * args.cpu_seconds / 2.0 / max(t_probe, 1e-3))))
         sample = np.sort(rng.choice(n, rows, replace=False))
-        tk = {}
+        # median of three runs of the sampled rows (both kernels per run)
+        runs = []
         ref = {}
-        for k in ("laplace", "yukawa"):
+        for _ in range(3):
             t0 = time.perf_counter()
-            ref[k] = D.direct(x[sample], x, q, k, KAPPA)
-            tk[k] = time.perf_counter() - t0
-        t_full = sum(tk.values()) * n / rows
+            for k in ("laplace", "yukawa"):
+                ref[k] = D.direct(x[sample], x, q, k, KAPPA)
+            runs.append(time.perf_counter() - t0)
+        t_rows = float(np.median(runs))
+        t_full = t_rows * n / rows
         cpu = {"value": round(n / t_full / 1e6, 5), "unit": "Mpoints/s", "cores": D.num_threads(),
-               "kind": "oracle",
-               "sample": f"FP64 direct sum, potential+gradient, Laplace and Yukawa, {rows} of {n} target rows "
-                         f"x all {n} sources, extrapolated by N/rows"}
+               "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(), "kind": "oracle",
+               "gpairs_per_s": round(2.0 * rows * n / t_rows / 1e9, 4), "runs_s": [round(r, 3) for r in runs],
+               "sample": f"FP64 direct sum (C, OpenMP), potential+gradient, Laplace and Yukawa, {rows} of {n} "
+                         f"target rows x all {n} sources, median of 3 runs, extrapolated by N/rows"}
         for (tag, k), (pot, grad) in outs.items():
             errors[f"{tag}:{k}"] = {"pot": float(np.linalg.norm(pot[sample] - ref[k][0]) / np.linalg.norm(ref[k][0])),
                                     "grad": float(np.linalg.norm(grad[sample] - ref[k][1]) / np.linalg.norm(ref[k][1]))}
@@ -566,7 +670,6 @@ def main():
                                        "ms_per_step": round(dtp / st * 1e3, 4), "errors": errp}
                     break
 
-    phases = {k: {name: round(ms / 3, 4) for name, (ms, cnt) in ph.items() if cnt} for k, ph in prof_all.items()}
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -574,10 +677,14 @@ def main():
         "config": {"workload": "sphere-union surface, 200 spheres, 131072 triangles x 3 points = 393216 points; "
                                "Laplace + Yukawa (kappa 0.125) fmm_eval_pair, potential + gradient, 1 column",
                    "n_points": n, "p": P_ORDER, "ncrit": ncrit, "precision": args.precision},
-        "roofline": roofline, "cpu_baseline": cpu, "accuracy_gate_met": bool(errors) and all(
+        "roofline": roofline, "roofline_whole_call": whole, "phases": phases_out,
+        "cpu_baseline": cpu, "accuracy_gate_met": bool(errors) and all(
             v["pot"] <= 1e-4 and v["grad"] <= 1e-4 for kk, v in errors.items() if kk.startswith(args.precision)),
         **others,
-        "errors": errors, "lower_p": psweep, "smallest_p_meeting_1e-4": smallest_p, "phase_ms_per_eval_with_events": phases, "ncrit_sweep_ms": sweep,
+        "errors": errors, "lower_p": psweep, "smallest_p_meeting_1e-4": smallest_p, "ncrit_sweep_ms": sweep,
+        "setup_ms": {k: {kk: round(infos[k][kk], 2) for kk in ("setup_ms", "setup_sort_ms", "setup_tree_ms",
+                                                                "setup_lists_ms", "setup_items_ms", "setup_ops_ms")}
+                     | {"tree_shared": infos[k]["tree_shared"]} for k in infos},
         "tree": {k: {kk: infos[k][kk] for kk in ("n_boxes", "n_leaves", "max_level", "n_v_pairs", "n_u_pairs",
                                                    "n_w_pairs", "n_x_pairs", "n_p2p_interactions", "n_far_interactions",
                                                    "rank_up", "rank_down")} for k in infos},

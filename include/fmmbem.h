@@ -233,7 +233,12 @@ enum {
   FMM_PHASE_NEAR = 10,   /* fmm_eval_pair: P2P of both kernels (first plan's timer) */
   FMM_PHASE_FAR = 11,    /* fmm_eval_pair: M2P + L2P of both kernels, unpermute */
   FMM_PHASE_COUNT = 12,
-  FMM_PHASE_ALL = 0xfff
+  FMM_PHASE_ALL = 0xfff,
+  /* flag in the fmm_set_profiling mask: pair evaluations led by this plan
+   * run every pass on the caller's stream, one after the other (no side
+   * stream), so that each phase's time is its own and not stretched by the
+   * passes that otherwise share the GPU with it; for measurement only */
+  FMM_PROFILE_SERIAL = 0x10000
 };
 int fmm_set_profiling(fmm_plan *plan, int enable);
 int fmm_get_phase_times(fmm_plan *plan, double *ms, int64_t *launches, int nphase);

@@ -16,6 +16,7 @@ FMM_BEM_DIRECT, FMM_BEM_DERIVATIVE, FMM_BEM_EXTERIOR, FMM_BEM_EXTERIOR_P1 = 0, 1
 FMM_BEM_PRECOND_BLOCK, FMM_BEM_PRECOND_MASS = 0, 1
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOTCONV, FMM_EBREAKDOWN = 0, -1, -2, -3, -4, -5
 BEM_RHS_SCRATCH_DOUBLES = 1 << 23
+FMM_PROFILE_SERIAL = 0x10000
 
 PHASES = ["permute", "p2m", "uc2e", "m2m", "p2l", "m2l", "m2l_sum", "l2l", "dc2e", "leaf", "near", "far"]
 

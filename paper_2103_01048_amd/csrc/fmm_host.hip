@@ -413,16 +413,19 @@ static int precompute_typed(fmm_plan *P) {
     std::vector<std::pair<int, int>> pj;
     for (int gl : glevels) { pj.push_back({0, gl}); pj.push_back({1, gl}); }
     std::vector<int> ranks(pj.size());
+    // the host threads split between the SVDs that run at once
+    const int hw = (int)std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    const int per_svd = std::max(1, hw / (int)std::max<size_t>(1, pj.size()));
     parallel_for((int64_t)pj.size(), [&](int64_t i) {
       const int kind = pj[i].first, gl = pj[i].second;
       const double h = gh(gl);
       std::vector<double> Km((size_t)n * n);
       if (kind == 0) {
         kernel_matrix(grid, n, zero, ALPHA_UC * h, zero, ALPHA_UE * h, yuk, P->kappa, Km.data(), n);
-        ranks[i] = tsvd_factors(n, Km.data(), tau, ut_u[gl].data(), vs_u[gl].data());
+        ranks[i] = tsvd_factors(n, Km.data(), tau, ut_u[gl].data(), vs_u[gl].data(), per_svd);
       } else {
         kernel_matrix(grid, n, zero, ALPHA_DC * h, zero, ALPHA_DE * h, yuk, P->kappa, Km.data(), n);
-        ranks[i] = tsvd_factors(n, Km.data(), tau, ut_d[gl].data(), vs_d[gl].data());
+        ranks[i] = tsvd_factors(n, Km.data(), tau, ut_d[gl].data(), vs_d[gl].data(), per_svd);
       }
     });
     for (size_t i = 0; i < pj.size(); ++i) (pj[i].first == 0 ? rk_u : rk_d)[pj[i].second] = ranks[i];
@@ -1525,7 +1528,7 @@ int fmm_get_root(const fmm_plan *P, double *lo3, double *width) {
 
 int fmm_set_profiling(fmm_plan *P, int enable) {
   if (!P) { set_error("fmm_set_profiling: plan is NULL"); return FMM_EINVAL; }
-  P->profiling = enable & ((1 << FMM_PHASE_COUNT) - 1);
+  P->profiling = enable & (((1 << FMM_PHASE_COUNT) - 1) | FMM_PROFILE_SERIAL);
   return FMM_OK;
 }
 

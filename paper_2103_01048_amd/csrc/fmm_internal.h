@@ -24,7 +24,7 @@ void set_error(const std::string &msg);
 hipEvent_t prof_begin(fmm_plan *P, int phase, hipStream_t s);
 void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s);
 void pinv_tsvd(int n, const double *A, double tau, double *out);
-int tsvd_factors(int n, const double *A, double tau, double *UT, double *VS);
+int tsvd_factors(int n, const double *A, double tau, double *UT, double *VS, int nthreads);
 
 #define FMM_HIP_TRY(call)                                                        \
   do {                                                                           \

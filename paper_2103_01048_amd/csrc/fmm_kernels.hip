@@ -1898,10 +1898,12 @@ template <typename T, int NR, typename Near>
 static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips, Near near) {
   int rc;
   const bool far = A->dt.maxlevel >= 2;
+  // FMM_PROFILE_SERIAL: the side stream's passes run on s, in the same order
+  const hipStream_t side = (A->profiling & FMM_PROFILE_SERIAL) ? s : A->aux;
   if (far) {
     FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
-    FMM_HIP_TRY(hipStreamWaitEvent(A->aux, A->ev_fork, 0));
-    if ((rc = eval_passes_pair<T, NR>(A, B, A->aux, 1, B->ev_fork, A->ev_up, dips))) return rc;
+    FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_fork, 0));
+    if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips))) return rc;
     // the near field starts once P2M (VALU, like the near field) is done,
     // and shares the GPU with the GEMM passes
     FMM_HIP_TRY(hipStreamWaitEvent(s, B->ev_fork, 0));
@@ -1909,9 +1911,9 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   if ((rc = near())) return rc;
   if (far) {
     if ((rc = pair_off_chain<T, NR>(A, B, s, dips))) return rc;
-    FMM_HIP_TRY(hipStreamWaitEvent(A->aux, B->ev_join, 0));
-    if ((rc = eval_passes_pair<T, NR>(A, B, A->aux, 2, nullptr, nullptr, dips))) return rc;
-    FMM_HIP_TRY(hipEventRecord(A->ev_join, A->aux));
+    FMM_HIP_TRY(hipStreamWaitEvent(side, B->ev_join, 0));
+    if ((rc = eval_passes_pair<T, NR>(A, B, side, 2, nullptr, nullptr, dips))) return rc;
+    FMM_HIP_TRY(hipEventRecord(A->ev_join, side));
     FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
   }
   return FMM_OK;

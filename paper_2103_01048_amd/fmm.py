@@ -107,8 +107,11 @@ class FMMPlan:
 
     __call__ = eval
 
-    def set_profiling(self, enable=True):
-        """enable: True (every phase), False, or an iterable of phase names."""
+    def set_profiling(self, enable=True, serial=False):
+        """enable: True (every phase), False, or an iterable of phase names.
+        serial: pair evaluations led by this plan run every pass on the
+        caller's stream one after the other (phase times not stretched by
+        overlap; for measurement)."""
         if enable is True:
             mask = (1 << len(_lib.PHASES)) - 1
         elif not enable:
@@ -117,6 +120,8 @@ class FMMPlan:
             mask = 0
             for name in enable:
                 mask |= 1 << _lib.PHASES.index(name)
+        if serial:
+            mask |= _lib.FMM_PROFILE_SERIAL
         check(lib().fmm_set_profiling(self._h, mask), "fmm_set_profiling")
 
     def phase_times(self) -> dict:
