@@ -161,7 +161,8 @@ def parse():
                          "direct sums (needs the CPU leg); empty to skip")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--ncrit", type=int, default=0, help="0: pick per kernel from a short sweep")
+    ap.add_argument("--ncrit", type=int, default=0,
+                    help="0: ncrit and the library tunables from the package autotuner on this workload")
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"],
                     help="single-precision path timed for `value` (bf16x3: FP32 with the M2L contraction as "
                          "three bf16 MFMA products and FP32 accumulation)")
@@ -464,23 +465,19 @@ def main():
     qd = {torch.float32: torch.tensor(q, dtype=torch.float32, device=dev),
           torch.float64: torch.tensor(q, dtype=torch.float64, device=dev)}
 
-    # ncrit: short sweep of the pair step (setup excluded from every timing)
-    sweep = {}
+    # ncrit and the library's tunables from the package's autotuner (pair
+    # steps on this workload; setup excluded from every timing)
+    tuned = None
     if args.ncrit:
         ncrit = args.ncrit
     else:
-        times = {}
-        for nc in (64, 96, 128, 192, 256):
-            pls = make(args.precision, nc)
-            dt, _ = time_steps(step_pair, pls, qd, 5, 2)
-            sweep[str(nc)] = round(dt / 5 * 1e3, 3)
-            times[nc] = dt
-            del pls
-        # the smallest ncrit within 2% of the fastest: near-ties (128 and 192
-        # differ by well under 1% here) then resolve the same way every run
-        fastest = min(times.values())
-        ncrit = min(nc for nc, dt in times.items() if dt <= 1.02 * fastest)
-        print("# ncrit sweep: " + ", ".join(f"{k}={v} ms" for k, v in sweep.items()), file=sys.stderr, flush=True)
+        from paper_2103_01048_amd import autotune as at
+        res = at.autotune(xt, p=P_ORDER, precision=args.precision, kappa=KAPPA, q=qd[torch.float32],
+                          cache_path=None, steps=5, warmup=2,
+                          log=lambda m: print("# autotune " + m, file=sys.stderr, flush=True))
+        ncrit = at.apply(res)
+        tuned = {"ncrit": ncrit, "tuning": res["tuning"], "ms": res["ms"], "trials": len(res["trials"]),
+                 "ncrit_ms": {str(t["ncrit"]): t["ms"] for t in res["trials"] if t["stage"] == "ncrit"}}
 
     plans = make(args.precision, ncrit)
     infos = {k: pl.info() for k, pl in plans.items()}
@@ -681,7 +678,7 @@ def main():
         "cpu_baseline": cpu, "accuracy_gate_met": bool(errors) and all(
             v["pot"] <= 1e-4 and v["grad"] <= 1e-4 for kk, v in errors.items() if kk.startswith(args.precision)),
         **others,
-        "errors": errors, "lower_p": psweep, "smallest_p_meeting_1e-4": smallest_p, "ncrit_sweep_ms": sweep,
+        "errors": errors, "lower_p": psweep, "smallest_p_meeting_1e-4": smallest_p, "autotune": tuned,
         "setup_ms": {k: {kk: round(infos[k][kk], 2) for kk in ("setup_ms", "setup_sort_ms", "setup_tree_ms",
                                                                 "setup_lists_ms", "setup_items_ms", "setup_ops_ms")}
                      | {"tree_shared": infos[k]["tree_shared"]} for k in infos},

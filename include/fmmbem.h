@@ -165,6 +165,33 @@ int fmm_eval_pair_md(fmm_plan *plan_a, fmm_plan *plan_b, const void *q_dev, cons
 int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const void *grad_fwd_dev, int nrhs,
                 void *dq_dev, void *dxyz_dev, fmm_stream_t stream);
 
+/* Tunable parameters of the plans set up afterwards (process-wide; each plan
+ * keeps the values it was set up with).  The defaults are the values below;
+ * paper_2103_01048_amd.autotune picks them, with ncrit, per expansion order
+ * and point count on the device at hand.
+ *   tile_split2   a leaf tile of at most this many targets (<= 32) runs as
+ *                 2 half-waves that take the sources in turn (32; 0: never)
+ *   tile_split4   ... of at most this many (<= 16) as 4 quarter-waves (16; 0: never)
+ *   work_cap_min, work_cap_div
+ *                 a leaf tile whose source work exceeds
+ *                 max(work_cap_min, total work / work_cap_div) point-source
+ *                 evaluations is cut into parts of about that size (512, 16384)
+ *   far_weight    work of one surface source relative to a point source when
+ *                 items are cut and ordered (1.15)
+ *   gemm_rbw      16-row blocks per wave in the single-precision translation
+ *                 GEMMs (0: automatic, 1 .. 8)
+ * FMM_EINVAL for values out of range. */
+typedef struct {
+  int32_t tile_split2;
+  int32_t tile_split4;
+  int32_t work_cap_min;
+  int32_t work_cap_div;
+  double far_weight;
+  int32_t gemm_rbw;
+} fmm_tuning_t;
+int fmm_set_tuning(const fmm_tuning_t *tuning);
+int fmm_get_tuning(fmm_tuning_t *tuning);
+
 /* Sizes of the plan's tree, for tests and reports. */
 typedef struct {
   int64_t n_points;

@@ -9,3 +9,4 @@ from ._lib import FmmError, lib  # noqa: F401
 from .fmm import FMMPlan, eval_pair, eval_pair_md  # noqa: F401
 from .bem import BEMOperator, gmres  # noqa: F401,E402
 from .autograd import FMMPotential, fmm_potential, solvation_style_energy  # noqa: F401,E402
+from . import autotune  # noqa: F401,E402

@@ -43,6 +43,13 @@ class FmmInfo(ctypes.Structure):
     ]
 
 
+class FmmTuning(ctypes.Structure):
+    _fields_ = [
+        ("tile_split2", ctypes.c_int32), ("tile_split4", ctypes.c_int32), ("work_cap_min", ctypes.c_int32),
+        ("work_cap_div", ctypes.c_int32), ("far_weight", ctypes.c_double), ("gemm_rbw", ctypes.c_int32),
+    ]
+
+
 _LIB = None
 
 vp = ctypes.c_void_p
@@ -76,6 +83,8 @@ SIGNATURES = {
     "bem_fmm_plan": (vp, [vp, i32]),
     "bem_free": (None, [vp]),
     "fmm_get_phase_times": (i32, [vp, vp, vp, i32]),
+    "fmm_set_tuning": (i32, [P(FmmTuning)]),
+    "fmm_get_tuning": (i32, [P(FmmTuning)]),
 }
 
 

@@ -1,0 +1,172 @@
+"""Autotuner of the FMM plans: picks ncrit and the library's tunable
+parameters for a point set, expansion order and precision by timing pair
+evaluations (Laplace + Yukawa, potential and gradient, the step of the
+direct formulation's matvec) on the device at hand, and caches the choice
+per (device, precision, p, point-count range).
+
+Tunables (fmm_set_tuning; defaults in DEFAULTS):
+  tile_split2 / tile_split4   leaf tiles of at most this many targets run as
+                              2 half-waves / 4 quarter-waves
+  work_cap_min / work_cap_div leaf tiles with more source work than
+                              max(min, total / div) are cut into parts
+  far_weight                  cost of a surface source against a point source
+  gemm_rbw                    16-row blocks per wave in the translation GEMMs
+
+The search is coordinate descent: ncrit first (with the defaults), then the
+work cap, the tile splits, the surface weight and the GEMM row blocks, each
+stage keeping the fastest value when it beats the current one by more than
+1% (the spread of repeated timings).  Plans built during a stage share their tree
+(same ncrit and item parameters) or their operators (same ncrit) with the
+live plans of the search, so a trial costs little more than its timing."""
+from __future__ import annotations
+
+import contextlib
+import ctypes
+import json
+import math
+import os
+import time
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+from .fmm import FMMPlan, eval_pair
+
+DEFAULTS = {"tile_split2": 32, "tile_split4": 16, "work_cap_min": 512, "work_cap_div": 16384, "far_weight": 1.15,
+            "gemm_rbw": 0}
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2103_01048_amd", "tuning.json")
+
+STAGES = (
+    ("work_cap_div", [{"work_cap_div": v} for v in (8192, 16384, 32768, 65536, 131072)]),
+    ("tile_split", [{"tile_split2": a, "tile_split4": b} for a, b in ((32, 16), (32, 0), (24, 12), (0, 0))]),
+    ("far_weight", [{"far_weight": v} for v in (1.0, 1.15, 1.3)]),
+    ("gemm_rbw", [{"gemm_rbw": v} for v in (0, 1, 2, 4)]),
+)
+
+
+def get_tuning() -> dict:
+    t = _lib.FmmTuning()
+    check(lib().fmm_get_tuning(ctypes.byref(t)), "fmm_get_tuning")
+    return {k: getattr(t, k) for k, _ in _lib.FmmTuning._fields_}
+
+
+def set_tuning(**kw) -> dict:
+    """Set tunables for plans set up from now on (unnamed ones keep their
+    current values); returns the full set in force."""
+    cur = get_tuning()
+    unknown = set(kw) - set(cur)
+    if unknown:
+        raise ValueError(f"unknown tunables {sorted(unknown)}")
+    cur.update(kw)
+    t = _lib.FmmTuning(**cur)
+    check(lib().fmm_set_tuning(ctypes.byref(t)), "fmm_set_tuning")
+    return cur
+
+
+@contextlib.contextmanager
+def tuning(**kw):
+    """Tunables in force inside the block, restored afterwards."""
+    old = get_tuning()
+    set_tuning(**kw)
+    try:
+        yield
+    finally:
+        set_tuning(**old)
+
+
+def cache_key(n: int, p: int, precision: str, device=None) -> str:
+    name = torch.cuda.get_device_name(device) if torch.cuda.is_available() else "cpu"
+    return f"{name}|{precision}|p{p}|n~2^{round(math.log2(max(n, 1)))}"
+
+
+def _time_pair(xt, q, p, ncrit, precision, kappa, steps, warmup, keep):
+    pls = [FMMPlan(xt, kernel=k, kappa=kappa, p=p, ncrit=ncrit, precision=precision) for k in ("laplace", "yukawa")]
+    keep.extend(pls)  # live plans let later trials share their tree and operators
+    for _ in range(warmup):
+        eval_pair(pls[0], pls[1], q)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(2):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            eval_pair(pls[0], pls[1], q)
+        torch.cuda.synchronize()
+        best = min(best, (time.perf_counter() - t0) / steps * 1e3)
+    return best
+
+
+def autotune(points: torch.Tensor, p: int = 8, precision: str = "bf16x3", kappa: float = 0.125,
+             ncrit_candidates=(64, 96, 128, 160, 192, 256), q: torch.Tensor | None = None, steps: int = 5,
+             warmup: int = 2, cache_path: str | None = DEFAULT_CACHE, use_cache: bool = True,
+             log=None) -> dict:
+    """Fastest (ncrit, tunables) for pair evaluations on `points` ((N, 3)
+    float64 CUDA tensor).  Returns {"key", "ncrit", "tuning", "ms", "trials",
+    "cached"}; the tunables in force are left unchanged (see apply)."""
+    n = int(points.shape[0])
+    key = cache_key(n, p, precision, points.device)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        try:
+            cache = json.load(open(cache_path))
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        return {**cache[key], "key": key, "cached": True}
+    xt = points.detach().to(torch.float64).contiguous()
+    if q is None:
+        g = torch.Generator(device="cpu").manual_seed(0)
+        q = torch.randn(n, generator=g, dtype=torch.float64)
+    q = q.to(device=xt.device, dtype=torch.float64 if precision == "fp64" else torch.float32)
+    trials = []
+    old = get_tuning()
+    keep = []
+    try:
+        best_t = dict(DEFAULTS)
+        set_tuning(**best_t)
+        best_ms, best_nc = float("inf"), None
+        for nc in ncrit_candidates:
+            ms = _time_pair(xt, q, p, nc, precision, kappa, steps, warmup, keep)
+            trials.append({"stage": "ncrit", "ncrit": nc, "tuning": dict(best_t), "ms": round(ms, 4)})
+            if log:
+                log(f"ncrit {nc}: {ms:.4f} ms")
+            if best_nc is None or ms < 0.99 * best_ms:
+                best_ms, best_nc = ms, nc
+        for stage, cands in STAGES:
+            keep = [pl for pl in keep if pl.ncrit == best_nc]
+            stage_best = (best_ms, None)
+            for c in cands:
+                t = {**best_t, **c}
+                if t == best_t:
+                    continue
+                set_tuning(**t)
+                ms = _time_pair(xt, q, p, best_nc, precision, kappa, steps, warmup, keep)
+                trials.append({"stage": stage, "ncrit": best_nc, "tuning": t, "ms": round(ms, 4)})
+                if log:
+                    log(f"{stage} {c}: {ms:.4f} ms")
+                if ms < 0.99 * stage_best[0]:
+                    stage_best = (ms, t)
+            if stage_best[1] is not None:
+                best_ms, best_t = stage_best
+            set_tuning(**best_t)
+    finally:
+        del keep
+        set_tuning(**old)
+    res = {"ncrit": best_nc, "tuning": best_t, "ms": round(best_ms, 4), "trials": trials}
+    if cache_path:
+        cache[key] = {k: res[k] for k in ("ncrit", "tuning", "ms")}
+        try:
+            os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+            tmp = cache_path + ".tmp"
+            json.dump(cache, open(tmp, "w"), indent=1)
+            os.replace(tmp, cache_path)
+        except OSError:
+            pass
+    return {**res, "key": key, "cached": False}
+
+
+def apply(result: dict) -> int:
+    """Put the tuned parameters in force for plans set up from now on;
+    returns the tuned ncrit."""
+    set_tuning(**result["tuning"])
+    return int(result["ncrit"])

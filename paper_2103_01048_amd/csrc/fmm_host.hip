@@ -638,7 +638,7 @@ static int upload_lists(fmm_plan *P) {
   // cut at point boundaries, surfaces whole); parts write partial sums that
   // k_leaf_parts adds in part order.  With the waves of one launch resident
   // at once, capping the work per wave is what balances the SIMDs.
-  const double far_w = 1.15;  // a surface source also computes its position
+  const double far_w = P->tune.far_weight;  // a surface source also computes its position
   struct Tile { double cost; int32_t slot, t0, split; };
   std::vector<Tile> tiles;
   double total = 0;
@@ -648,12 +648,12 @@ static int upload_lists(fmm_plan *P) {
     c += far_w * ns * (double)src[sl].far.size();
     for (int64_t t0 = 0; t0 < src[sl].m; t0 += 64) {
       const int64_t rem = src[sl].m - t0;
-      const int split = rem <= 16 ? 4 : (rem <= 32 ? 2 : 1);
+      const int split = rem <= P->tune.tile_split4 ? 4 : (rem <= P->tune.tile_split2 ? 2 : 1);
       tiles.push_back({c / split, (int32_t)sl, (int32_t)t0, split});
       total += c / split;
     }
   }
-  const double cap = std::max(512.0, total / 16384.0);
+  const double cap = std::max((double)P->tune.work_cap_min, total / (double)P->tune.work_cap_div);
   // an item of a whole tile reads its leaf's range lists (whole = true);
   // the parts of a split tile carry their own cut lists
   struct Item { double cost; int32_t slot, code, part; bool whole; std::vector<Rng> near; std::vector<int32_t> far; };
@@ -1167,6 +1167,10 @@ void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
   P->prof_events.push_back({phase, {begin, e}});
 }
 
+// Tunables for plans set up from now on (fmm_set_tuning).
+static std::mutex g_tune_mu;
+static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0};
+
 // Live plans whose tree later plans on the same points may share.
 static std::mutex g_tree_mu;
 static std::vector<fmm_plan *> g_tree_plans;
@@ -1179,9 +1183,42 @@ static fmm_plan *find_tree(const fmm_plan *P) {
   for (fmm_plan *A : g_tree_plans)
     if (A->coord_hash == P->coord_hash && A->n == P->n && A->mol_off == P->mol_off && A->W == P->W &&
         A->mol_lo == P->mol_lo && A->ncrit == P->ncrit && A->nsurf == P->nsurf &&
-        (A->precision == FMM_FP64) == (P->precision == FMM_FP64) && A->device == P->device && A->tree_mem)
+        (A->precision == FMM_FP64) == (P->precision == FMM_FP64) && A->device == P->device && A->tree_mem &&
+        A->tune.tile_split2 == P->tune.tile_split2 && A->tune.tile_split4 == P->tune.tile_split4 &&
+        A->tune.work_cap_min == P->tune.work_cap_min && A->tune.work_cap_div == P->tune.work_cap_div &&
+        A->tune.far_weight == P->tune.far_weight)
       return A;
   return nullptr;
+}
+
+// A live plan whose translation operators P can take: the same kernel,
+// kappa, order and working type on a tree of the same points, root cube and
+// ncrit (the operators depend on the level sizes and on the offsets the V
+// lists use, not on the leaf items).
+static fmm_plan *find_ops(const fmm_plan *P) {
+  std::lock_guard<std::mutex> lock(g_tree_mu);
+  for (fmm_plan *A : g_tree_plans)
+    if (A->ops_mem && A->kernel == P->kernel && A->kappa == P->kappa && A->p == P->p &&
+        A->precision == P->precision && A->coord_hash == P->coord_hash && A->n == P->n &&
+        A->mol_off == P->mol_off && A->W == P->W && A->mol_lo == P->mol_lo && A->ncrit == P->ncrit &&
+        A->device == P->device && A->level_begin == P->level_begin && A->loff[1] == P->loff[1] &&
+        A->lidx[1] == P->lidx[1])
+      return A;
+  return nullptr;
+}
+
+static void share_ops(fmm_plan *P, const fmm_plan *A) {
+  P->ops_mem = A->ops_mem;
+  P->pool1 = A->pool1; P->pool8 = A->pool8; P->pool_bf = A->pool_bf;
+  P->pool1_count = A->pool1_count; P->pool8_count = A->pool8_count; P->poolbf_count = A->poolbf_count;
+  P->bf_kb = A->bf_kb;
+  P->utu_id = A->utu_id; P->vsu_id = A->vsu_id; P->utd_id = A->utd_id; P->vsd_id = A->vsd_id;
+  P->rank_u = A->rank_u; P->rank_d = A->rank_d;
+  P->m2m_id = A->m2m_id; P->l2l_id = A->l2l_id; P->m2l_id = A->m2l_id;
+  P->vs_alpha = A->vs_alpha; P->k_alpha = A->k_alpha;
+  P->surf = A->surf;
+  P->dt.box_geom = A->dt.box_geom;
+  P->ops_shared = 1;
 }
 
 static void register_tree(fmm_plan *P) {
@@ -1252,6 +1289,10 @@ static int setup_common(const double *xyz_dev, const std::vector<int64_t> &off, 
   fmm_plan *P = new (std::nothrow) fmm_plan();
   if (!P) { set_error("fmm_setup: out of host memory"); return FMM_ENOMEM; }
   P->kernel = kernel; P->kappa = kernel == FMM_YUKAWA ? kappa : 0.0; P->p = p; P->ncrit = ncrit; P->precision = precision;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    P->tune = g_tune;
+  }
   P->n = n;
   P->mol_off = off;
   P->nsurf = 6 * (p - 1) * (p - 1) + 2;
@@ -1360,8 +1401,17 @@ static int setup_common(const double *xyz_dev, const std::vector<int64_t> &off, 
     lap(3);
     }
     P->tree_hash = tree_fingerprint(P);
-    rc = precision == FMM_FP64 ? precompute_typed<double>(P) : precompute_typed<float>(P);
-    if (rc) break;
+    if (fmm_plan *A = find_ops(P)) {
+      // a live plan of the same kernel, kappa, order and working type on the
+      // same tree: its operators (they do not depend on the leaf items)
+      share_ops(P, A);
+    } else {
+      P->ops_mem = std::make_shared<SharedAllocs>();
+      P->alloc_sink = &P->ops_mem->ptrs;
+      rc = precision == FMM_FP64 ? precompute_typed<double>(P) : precompute_typed<float>(P);
+      P->alloc_sink = nullptr;
+      if (rc) break;
+    }
     hipError_t e = hipStreamSynchronize(s);
     lap(4);
     if (e != hipSuccess) { set_error(std::string("fmm_setup: ") + hipGetErrorString(e)); rc = FMM_EHIP; }
@@ -1523,6 +1573,26 @@ int fmm_get_root(const fmm_plan *P, double *lo3, double *width) {
   if (!P) { set_error("fmm_get_root: plan is NULL"); return FMM_EINVAL; }
   if (lo3) for (int d = 0; d < 3; ++d) lo3[d] = P->lo[d];
   if (width) *width = P->W;
+  return FMM_OK;
+}
+
+int fmm_set_tuning(const fmm_tuning_t *t) {
+  if (!t) { set_error("fmm_set_tuning: null argument"); return FMM_EINVAL; }
+  if (t->tile_split2 < 0 || t->tile_split2 > 32 || t->tile_split4 < 0 || t->tile_split4 > 16 ||
+      t->work_cap_min < 1 || t->work_cap_div < 1 || !(t->far_weight > 0.0) || !std::isfinite(t->far_weight) ||
+      t->gemm_rbw < 0 || t->gemm_rbw > 8) {
+    set_error("fmm_set_tuning: value out of range");
+    return FMM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune = *t;
+  return FMM_OK;
+}
+
+int fmm_get_tuning(fmm_tuning_t *t) {
+  if (!t) { set_error("fmm_get_tuning: null argument"); return FMM_EINVAL; }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  *t = g_tune;
   return FMM_OK;
 }
 

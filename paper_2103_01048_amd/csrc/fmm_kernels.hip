@@ -1573,6 +1573,7 @@ static int launch_gemm2(fmm_plan *P, const GemmBatch &bt, const T *X, T *Y, fmm_
   // Small launches (few column tiles) split the row blocks over a second grid
   // dimension so that more workgroups share the work.
   int rbw = g0.ntask + g1.ntask >= 1024 ? (nrb + 3) / 4 : 1;
+  if (P->tune.gemm_rbw > 0) rbw = std::min(P->tune.gemm_rbw, std::max(1, (nrb + 3) / 4));
   // FP64: at most two row blocks per wave (more y-groups, fewer registers,
   // more resident waves); measured on the FP64 pair evaluation: 2 -> 59.5,
   // 3 -> 54.7, 4 -> 44.5, 5 (the one-group default at p = 8) -> 53.5

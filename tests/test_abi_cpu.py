@@ -111,3 +111,23 @@ def test_rhs_noalloc_rejects_null_operator_and_states_its_limit():
     hdr = open(os.path.join(ROOT, "include", "fmmbem.h")).read()
     m = re.search(r"#define BEM_RHS_SCRATCH_DOUBLES \(1 << (\d+)\)", hdr)
     assert m and (1 << int(m.group(1))) == _lib.BEM_RHS_SCRATCH_DOUBLES
+
+
+def test_tuning_roundtrip_and_range_checks():
+    """The tunables of later plans (fmm_set_tuning) round-trip, out-of-range
+    values are refused, and the context manager restores the previous set."""
+    from paper_2103_01048_amd import autotune as at
+    before = at.get_tuning()
+    assert before == at.DEFAULTS
+    with at.tuning(work_cap_div=4096, tile_split2=24, far_weight=1.3, gemm_rbw=2):
+        cur = at.get_tuning()
+        assert cur["work_cap_div"] == 4096 and cur["tile_split2"] == 24 and cur["gemm_rbw"] == 2
+        assert cur["far_weight"] == 1.3 and cur["tile_split4"] == before["tile_split4"]
+    assert at.get_tuning() == before
+    for bad in ({"tile_split2": 33}, {"tile_split4": 17}, {"work_cap_div": 0}, {"work_cap_min": 0},
+                {"far_weight": 0.0}, {"far_weight": float("nan")}, {"gemm_rbw": 9}, {"gemm_rbw": -1}):
+        with pytest.raises(_lib.FmmError):
+            at.set_tuning(**bad)
+        assert at.get_tuning() == before
+    with pytest.raises(ValueError):
+        at.set_tuning(no_such_parameter=1)
