@@ -180,6 +180,12 @@ int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const v
  *                 items are cut and ordered (1.15)
  *   gemm_rbw      16-row blocks per wave in the single-precision translation
  *                 GEMMs (0: automatic, 1 .. 8)
+ *   m2l_factored  1: each M2L operator (per level and offset, in the
+ *                 truncated-SVD coordinates) is split by its own truncated
+ *                 SVD, M ~ L R with rank k (singular values above 1e-7 of the
+ *                 largest in single precision, 1e-11 in FP64), and applied in
+ *                 two gather-GEMM passes (R to a k-value intermediate per
+ *                 pair, then L); 0: one dense pass (the default)
  * FMM_EINVAL for values out of range. */
 typedef struct {
   int32_t tile_split2;
@@ -188,6 +194,7 @@ typedef struct {
   int32_t work_cap_div;
   double far_weight;
   int32_t gemm_rbw;
+  int32_t m2l_factored;
 } fmm_tuning_t;
 int fmm_set_tuning(const fmm_tuning_t *tuning);
 int fmm_get_tuning(fmm_tuning_t *tuning);

@@ -437,17 +437,28 @@ static int precompute_typed(fmm_plan *P) {
   std::vector<int> id1(jobs.size(), -1), id8(jobs.size(), -1);
   int64_t c1 = 0, c8 = 0;
   for (size_t j = 0; j < jobs.size(); ++j) id1[j] = (int)c1++;
+  // factored M2L: each M2L job also stores its right factor R (id1 then holds
+  // the left factor L); rank per job
+  const bool fact = P->tune.m2l_factored != 0;
+  std::vector<int> idr(jobs.size(), -1), rankf(jobs.size(), 0);
+  if (fact)
+    for (size_t j = 0; j < jobs.size(); ++j)
+      if (jobs[j].kind == 6) idr[j] = (int)c1++;
+  const double tau_f = P->precision == FMM_FP64 ? 1e-11 : 1e-7;
   const size_t m1 = (size_t)ld * ld, m8 = (size_t)ld * ld * 8;
   std::vector<T> pool1(std::max<size_t>(1, c1 * m1)), pool8(std::max<size_t>(1, c8 * m8));
   // bf16x3 mode: the M2L operators also in split bf16 form (K padded to 32)
   const bool bf3 = P->precision == FMM_FP32_BF16X3;
   const int KB = (ld + 31) / 32;
   const size_t mbf = (size_t)(ld / 16) * KB * 2 * 64 * 8;
-  std::vector<int> idbf(jobs.size(), -1);
+  std::vector<int> idbf(jobs.size(), -1), idbfr(jobs.size(), -1);
   int64_t cbf = 0;
   if (bf3)
     for (size_t j = 0; j < jobs.size(); ++j)
-      if (jobs[j].kind == 6) idbf[j] = (int)cbf++;
+      if (jobs[j].kind == 6) {
+        idbf[j] = (int)cbf++;
+        if (fact) idbfr[j] = (int)cbf++;
+      }
   std::vector<uint16_t> poolbf(std::max<size_t>(1, cbf * mbf));
   parallel_for((int64_t)jobs.size(), [&](int64_t j) {
     const Job &jb = jobs[j];
@@ -495,8 +506,22 @@ static int precompute_typed(fmm_plan *P) {
         kernel_matrix(grid, n, zero, ALPHA_DC * h, o, ALPHA_UE * h, yuk, P->kappa, Km.data(), n);
         matmul_rect(n, n, ru, Km.data(), n, vs_u[jb.l].data(), n, KV.data(), ru);
         matmul_rect(rd, n, ru, ut_d[jb.l].data(), n, KV.data(), ru, M.data(), ru);
-        swizzle<T>(M.data(), rd, ru, ru, ld, ld, dst);
-        if (idbf[j] >= 0) swizzle_bf3(M.data(), rd, ru, ru, ld, KB, poolbf.data() + idbf[j] * mbf);
+        if (fact) {
+          // M ~ L R (rank k): L (rd x k) where the operator was, R (k x ru)
+          // in its own slot
+          std::vector<double> Lf((size_t)rd * rd, 0.0), Rf((size_t)std::min(rd, ru) * ru, 0.0);
+          const int kf = std::max(1, tsvd_split(rd, ru, M.data(), tau_f, Lf.data(), rd, Rf.data(), ru));
+          rankf[j] = kf;
+          swizzle<T>(Lf.data(), rd, kf, rd, ld, ld, dst);
+          swizzle<T>(Rf.data(), kf, ru, ru, ld, ld, pool1.data() + idr[j] * m1);
+          if (bf3) {
+            swizzle_bf3(Lf.data(), rd, kf, rd, ld, KB, poolbf.data() + idbf[j] * mbf);
+            swizzle_bf3(Rf.data(), kf, ru, ru, ld, KB, poolbf.data() + idbfr[j] * mbf);
+          }
+        } else {
+          swizzle<T>(M.data(), rd, ru, ru, ld, ld, dst);
+          if (idbf[j] >= 0) swizzle_bf3(M.data(), rd, ru, ru, ld, KB, poolbf.data() + idbf[j] * mbf);
+        }
       }
     }
   });
@@ -509,6 +534,8 @@ static int precompute_typed(fmm_plan *P) {
   P->m2m_id.assign(L1, std::vector<int>(8, -1));
   P->l2l_id.assign(L1, std::vector<int>(8, -1));
   P->m2l_id.assign(L1, std::vector<int>(343, -1));
+  P->m2l_r_id.assign(L1, std::vector<int>(343, -1));
+  P->m2l_k.assign(L1, std::vector<int>(343, 0));
   P->vs_alpha.assign(L1, 1); P->k_alpha.assign(L1, 1);
   for (int l = 2; l <= maxl; ++l) {
     const int gl = yuk ? l : -1;
@@ -527,12 +554,22 @@ static int precompute_typed(fmm_plan *P) {
         case 3: P->vsd_id[l] = id1[j]; break;
         case 4: P->m2m_id[l][jb.oct] = id1[j]; break;
         case 5: P->l2l_id[l][jb.oct] = id1[j]; break;
-        case 6: P->m2l_id[l][jb.code] = bf3 ? idbf[j] : id1[j]; break;
+        case 6:
+          P->m2l_id[l][jb.code] = bf3 ? idbf[j] : id1[j];
+          P->m2l_r_id[l][jb.code] = bf3 ? idbfr[j] : idr[j];
+          P->m2l_k[l][jb.code] = rankf[j];
+          break;
       }
     }
   }
   P->pool1_count = c1;
   P->pool8_count = c8;
+  P->m2l_ldt = 0;
+  if (fact) {
+    int kmax = 1;
+    for (size_t j = 0; j < jobs.size(); ++j) kmax = std::max(kmax, rankf[j]);
+    P->m2l_ldt = ((kmax + 31) / 32) * 32;
+  }
   int rc;
   if ((rc = upload(P, &P->pool1, pool1))) return rc;
   if ((rc = upload(P, &P->pool8, pool8))) return rc;
@@ -927,6 +964,18 @@ int ensure_lists(fmm_plan *P, int nr) {
     L.m2l.pool = 2;
     L.m2l.klen = std::min(((maxru + 31) / 32) * 32, P->bf_kb * 32);
   }
+  // factored M2L: R maps upward coordinates (k <= maxru) to intermediates of
+  // m2l_ldt values per pair; L reads those rows
+  const bool fact = P->tune.m2l_factored != 0;
+  L.m2l_r = GemmBatch();
+  if (fact) {
+    L.m2l_r.pool = L.m2l.pool;
+    L.m2l_r.klen = L.m2l.klen;
+    L.m2l_r.nrb = P->m2l_ldt / 16;
+    L.m2l_r.ldy = P->m2l_ldt;
+    L.m2l.ldx = P->m2l_ldt;
+    L.m2l.klen = P->m2l_ldt;
+  }
   // boxes whose upward equivalent density is evaluated (M2P sources)
   std::vector<char> need_equ(nb, 0);
   for (int64_t b = 0; b < nb; ++b) {
@@ -1030,20 +1079,40 @@ int ensure_lists(fmm_plan *P, int nr) {
         }
         ++j;
       }
-      const size_t t0 = L.m2l.h_tasks.size();
-      add_columns(L.m2l, P->m2l_id[l][code], 1.0, src, dst);
       // only the rows of this level's downward rank and the columns of its
       // upward rank (the rest of the operator is zero padding; the bf16x3
       // kernel steps k by 32)
-      const int kl = L.m2l.pool == 2 ? ((r16(P->rank_u[l]) + 31) / 32) * 32 : r16(P->rank_u[l]);
-      for (size_t t = t0; t < L.m2l.h_tasks.size(); ++t) {
-        L.m2l.h_tasks[t].nrb = r16(P->rank_d[l]) / 16;
-        L.m2l.h_tasks[t].klen = kl;
+      auto kround = [&](int r) { return L.m2l.pool == 2 ? ((r16(r) + 31) / 32) * 32 : r16(r); };
+      if (fact) {
+        // R: upward coordinates -> the pair's k-value intermediate (row j);
+        // L: intermediate -> the pair's slot
+        const int kf = P->m2l_k[l][code];
+        std::vector<int32_t> mid(dst);
+        size_t t0 = L.m2l_r.h_tasks.size();
+        add_columns(L.m2l_r, P->m2l_r_id[l][code], 1.0, src, mid);
+        for (size_t t = t0; t < L.m2l_r.h_tasks.size(); ++t) {
+          L.m2l_r.h_tasks[t].nrb = r16(kf) / 16;
+          L.m2l_r.h_tasks[t].klen = kround(P->rank_u[l]);
+        }
+        t0 = L.m2l.h_tasks.size();
+        add_columns(L.m2l, P->m2l_id[l][code], 1.0, mid, dst);
+        for (size_t t = t0; t < L.m2l.h_tasks.size(); ++t) {
+          L.m2l.h_tasks[t].nrb = r16(P->rank_d[l]) / 16;
+          L.m2l.h_tasks[t].klen = kround(kf);
+        }
+      } else {
+        const size_t t0 = L.m2l.h_tasks.size();
+        add_columns(L.m2l, P->m2l_id[l][code], 1.0, src, dst);
+        for (size_t t = t0; t < L.m2l.h_tasks.size(); ++t) {
+          L.m2l.h_tasks[t].nrb = r16(P->rank_d[l]) / 16;
+          L.m2l.h_tasks[t].klen = kround(P->rank_u[l]);
+        }
       }
       i = j;
     }
   }
   if ((rc = finish_batch(P, L.m2l))) return rc;
+  if (fact && (rc = finish_batch(P, L.m2l_r))) return rc;
   if (!P->d_m2l_rows) {
     std::vector<int32_t> rows(std::max<int64_t>(1, nb), 16);
     for (int64_t b = 0; b < nb; ++b)
@@ -1128,6 +1197,9 @@ int ensure_work(fmm_plan *P, int nr) {
   if ((rc = dev_alloc(P, &P->mslot, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->ydx, wbytes))) return rc;
   if ((rc = dev_alloc(P, &P->pairbuf, (size_t)std::max<int64_t>(1, P->dt.nvpair) * nr * pair_ld(P) * es))) return rc;
+  if (P->m2l_ldt > 0 &&
+      (rc = dev_alloc(P, &P->m2l_t, (size_t)std::max<int64_t>(1, P->dt.nvpair) * nr * P->m2l_ldt * es)))
+    return rc;
   // padding rows/columns must hold zeros (the GEMM K dimension reads them)
   FMM_HIP_TRY(hipMemset(P->equ, 0, wbytes));
   FMM_HIP_TRY(hipMemset(P->chk, 0, wbytes));
@@ -1169,7 +1241,7 @@ void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
 
 // Tunables for plans set up from now on (fmm_set_tuning).
 static std::mutex g_tune_mu;
-static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0};
+static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0};
 
 // Live plans whose tree later plans on the same points may share.
 static std::mutex g_tree_mu;
@@ -1199,6 +1271,7 @@ static fmm_plan *find_ops(const fmm_plan *P) {
   std::lock_guard<std::mutex> lock(g_tree_mu);
   for (fmm_plan *A : g_tree_plans)
     if (A->ops_mem && A->kernel == P->kernel && A->kappa == P->kappa && A->p == P->p &&
+        A->tune.m2l_factored == P->tune.m2l_factored &&
         A->precision == P->precision && A->coord_hash == P->coord_hash && A->n == P->n &&
         A->mol_off == P->mol_off && A->W == P->W && A->mol_lo == P->mol_lo && A->ncrit == P->ncrit &&
         A->device == P->device && A->level_begin == P->level_begin && A->loff[1] == P->loff[1] &&
@@ -1215,6 +1288,7 @@ static void share_ops(fmm_plan *P, const fmm_plan *A) {
   P->utu_id = A->utu_id; P->vsu_id = A->vsu_id; P->utd_id = A->utd_id; P->vsd_id = A->vsd_id;
   P->rank_u = A->rank_u; P->rank_d = A->rank_d;
   P->m2m_id = A->m2m_id; P->l2l_id = A->l2l_id; P->m2l_id = A->m2l_id;
+  P->m2l_r_id = A->m2l_r_id; P->m2l_k = A->m2l_k; P->m2l_ldt = A->m2l_ldt;
   P->vs_alpha = A->vs_alpha; P->k_alpha = A->k_alpha;
   P->surf = A->surf;
   P->dt.box_geom = A->dt.box_geom;
@@ -1580,7 +1654,7 @@ int fmm_set_tuning(const fmm_tuning_t *t) {
   if (!t) { set_error("fmm_set_tuning: null argument"); return FMM_EINVAL; }
   if (t->tile_split2 < 0 || t->tile_split2 > 32 || t->tile_split4 < 0 || t->tile_split4 > 16 ||
       t->work_cap_min < 1 || t->work_cap_div < 1 || !(t->far_weight > 0.0) || !std::isfinite(t->far_weight) ||
-      t->gemm_rbw < 0 || t->gemm_rbw > 8) {
+      t->gemm_rbw < 0 || t->gemm_rbw > 8 || t->m2l_factored < 0 || t->m2l_factored > 1) {
     set_error("fmm_set_tuning: value out of range");
     return FMM_EINVAL;
   }

@@ -25,6 +25,7 @@ hipEvent_t prof_begin(fmm_plan *P, int phase, hipStream_t s);
 void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s);
 void pinv_tsvd(int n, const double *A, double tau, double *out);
 int tsvd_factors(int n, const double *A, double tau, double *UT, double *VS, int nthreads);
+int tsvd_split(int rows, int cols, const double *A, double tau, double *L, int ldl, double *R, int ldr);
 
 #define FMM_HIP_TRY(call)                                                        \
   do {                                                                           \
@@ -73,6 +74,7 @@ struct GemmBatch {
   int ldy = 0;                 // leading dimension of the output rows (0: the work-array row length)
   int mode = GEMM_STORE;
   int pool = 0;                // 0: matrix pool, 1: stacked pool, 2: bf16x3 split pool
+  int ldx = 0;                 // row length of X (0: the work-array row length)
   int ntask = 0;
   GemmTask *d_tasks = nullptr;
   int32_t *d_src = nullptr;    // ncols*S  (row index into X, already * nr + r)
@@ -94,7 +96,8 @@ struct PassLists {
   GemmBatch vs_u;               // c_u -> upward equivalent (M2P sources), all levels
   GemmBatch ut_dx;              // P2L check -> its own c_d array (added by the M2L sums), all levels
   GemmBatch vs_d;               // c_d -> downward equivalent (leaves), all levels
-  GemmBatch m2l;                // all levels, c_u -> pair slots of c_d
+  GemmBatch m2l;                // all levels, c_u -> pair slots of c_d (factored: intermediate -> slots)
+  GemmBatch m2l_r;              // factored M2L: c_u -> per-pair intermediate (R factors)
 };
 
 struct DevTree {
@@ -178,12 +181,15 @@ struct fmm_plan {
   std::vector<int> rank_u, rank_d;                  // their ranks
   std::vector<std::vector<int>> m2m_id;             // [parent level][octant]
   std::vector<std::vector<int>> l2l_id;             // [parent level][octant]
-  std::vector<std::vector<int>> m2l_id;             // [level][343 offset code]
+  std::vector<std::vector<int>> m2l_id;             // [level][343 offset code] (factored: the left factor L)
+  std::vector<std::vector<int>> m2l_r_id;           // factored M2L: the right factor R, same indexing
+  std::vector<std::vector<int>> m2l_k;              // factored M2L: rank k per (level, offset)
+  int m2l_ldt = 0;                                  // factored M2L: row length of the per-pair intermediate
   std::vector<double> vs_alpha, k_alpha;            // Laplace level scaling
   // work arrays, sized for work_nr columns
   int work_nr = 0;
   void *qs = nullptr, *equ = nullptr, *chk = nullptr, *eqd = nullptr, *chku = nullptr,
-       *cu = nullptr, *yd = nullptr, *pairbuf = nullptr, *mslot = nullptr, *ydx = nullptr;
+       *cu = nullptr, *yd = nullptr, *pairbuf = nullptr, *mslot = nullptr, *ydx = nullptr, *m2l_t = nullptr;
   // cu: upward check in singular coordinates (U_u^T chk); yd: downward
   // check in singular coordinates (M2L sums + U_d^T chk)
   fmm::PassLists lists_by_nr[fmm::MAX_NR + 1];  // task lists per column count
@@ -212,7 +218,7 @@ struct fmm_plan {
   double setup_ms = 0;
   double setup_split[5] = {0, 0, 0, 0, 0};  // sort, tree, lists, items, operators (ms)
   int tree_on_device = 0, tree_shared = 0;
-  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0};  // tunables in force at setup
+  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0, 0};  // tunables in force at setup
   std::vector<void *> allocs;      // everything to free
   std::shared_ptr<fmm::SharedAllocs> tree_mem;  // the tree's device buffers (shared with plans on the same points)
   std::shared_ptr<fmm::SharedAllocs> ops_mem;   // translation operators (shared with plans of the same kernel on the same tree)

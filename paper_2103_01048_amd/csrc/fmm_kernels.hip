@@ -1526,7 +1526,7 @@ static GemmArgs gemm_args(const fmm_plan *P, const GemmBatch &bt, const void *X,
   g.ntask = bt.ntask;
   g.nrb = bt.nrb;
   g.klen = bt.klen;
-  g.ldx = P->ld;
+  g.ldx = bt.ldx ? bt.ldx : P->ld;
   g.ldy = bt.ldy ? bt.ldy : P->ld;
   g.S = bt.S;
   g.seg = bt.seg ? bt.seg : P->ld;
@@ -1674,7 +1674,12 @@ static int eval_passes(fmm_plan *P, hipStream_t s) {
   // downward rank, not of the surface size), then a fixed-order sum per
   // target box (every box at level >= 2)
   ev = prof_begin(P, FMM_PHASE_M2L, s);
-  if ((rc = launch_gemm<T>(P, L.m2l, cu, (T *)P->pairbuf, s))) return rc;
+  if (L.m2l_r.ntask) {  // factored: R then L through the per-pair intermediate
+    if ((rc = launch_gemm<T>(P, L.m2l_r, cu, (T *)P->m2l_t, s))) return rc;
+    if ((rc = launch_gemm<T>(P, L.m2l, (const T *)P->m2l_t, (T *)P->pairbuf, s))) return rc;
+  } else if ((rc = launch_gemm<T>(P, L.m2l, cu, (T *)P->pairbuf, s))) {
+    return rc;
+  }
   prof_end(P, FMM_PHASE_M2L, ev, s);
   ev = prof_begin(P, FMM_PHASE_M2L_SUM, s);
   if (D.nvbox > 0)
@@ -1774,7 +1779,19 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, h
   }
   if (up_done) FMM_HIP_TRY(hipEventRecord(up_done, s));
   ev = prof_begin(A, FMM_PHASE_M2L, s);
-  if ((rc = launch_gemm2<T>(A, LA.m2l, W(A->cu), W(A->pairbuf), B, &LB.m2l, W(B->cu), W(B->pairbuf), s))) return rc;
+  {
+    // a factored plan first maps its upward coordinates through R (one
+    // launch for the factored plans), then every plan's L (or dense operator)
+    // writes the pair slots
+    const bool fa = LA.m2l_r.ntask > 0, fb = LB.m2l_r.ntask > 0;
+    rc = FMM_OK;
+    if (fa) rc = launch_gemm2<T>(A, LA.m2l_r, W(A->cu), W(A->m2l_t), fb ? B : nullptr, &LB.m2l_r, W(B->cu), W(B->m2l_t), s);
+    else if (fb) rc = launch_gemm<T>(B, LB.m2l_r, W(B->cu), W(B->m2l_t), s);
+    if (rc) return rc;
+    if ((rc = launch_gemm2<T>(A, LA.m2l, fa ? W(A->m2l_t) : W(A->cu), W(A->pairbuf), B, &LB.m2l,
+                              fb ? W(B->m2l_t) : W(B->cu), W(B->pairbuf), s)))
+      return rc;
+  }
   prof_end(A, FMM_PHASE_M2L, ev, s);
   }
   if (part == 1) return FMM_OK;

@@ -158,6 +158,40 @@ int tsvd_factors(int n, const double *A, double tau, double *UT, double *VS, int
   return r;
 }
 
+// Low-rank split of A (rows x cols, row-major): with A = U S V^T and the k
+// singular values above tau * s_max kept (decreasing order),
+// L = U_k S_k^{1/2} (rows x k, row-major, leading dimension ldl) and
+// R = S_k^{1/2} V_k^T (k x cols, row-major, leading dimension ldr), so that
+// A ~ L R.  Returns k (0 for a zero matrix).
+int tsvd_split(int rows, int cols, const double *A, double tau, double *L, int ldl, double *R, int ldr) {
+  // the one-sided Jacobi SVD wants at least as many rows as columns: work on
+  // the transpose when A is wide
+  const bool tr = rows < cols;
+  const int m = tr ? cols : rows, n = tr ? rows : cols;
+  std::vector<double> B((size_t)m * n);
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < cols; ++j) {
+      if (tr) B[(size_t)j * n + i] = A[(size_t)i * cols + j];
+      else B[(size_t)i * n + j] = A[(size_t)i * cols + j];
+    }
+  std::vector<double> U, s, V;
+  jacobi_svd(m, n, B.data(), U, s, V, 1);
+  std::vector<int> order(n);
+  for (int j = 0; j < n; ++j) order[j] = j;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return s[a] > s[b]; });
+  const double smax = n ? s[order[0]] : 0.0;
+  int k = 0;
+  while (k < n && s[order[k]] > tau * smax && s[order[k]] > 0.0) ++k;
+  // B = U S V^T (m x n); A = B or B^T
+  for (int c = 0; c < k; ++c) {
+    const int j = order[c];
+    const double h = std::sqrt(s[j]);
+    for (int i = 0; i < rows; ++i) L[(size_t)i * ldl + c] = h * (tr ? V[(size_t)i * n + j] : U[(size_t)i * n + j]);
+    for (int i = 0; i < cols; ++i) R[(size_t)c * ldr + i] = h * (tr ? U[(size_t)i * n + j] : V[(size_t)i * n + j]);
+  }
+  return k;
+}
+
 // out (n x n row-major) = pinv(A) with singular values <= tau * s_max dropped.
 void pinv_tsvd(int n, const double *A, double tau, double *out) {
   std::vector<double> U, s, V;

@@ -84,3 +84,36 @@ def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
         assert D.rel_l2(pb[rows], p0) < 1e-4 and D.rel_l2(gb[rows], g0) < 1e-4
     finally:
         at.set_tuning(**before)
+
+
+@pytest.mark.parametrize("precision,tol,tol_dense", [("bf16x3", 1e-4, 1e-5), ("fp32", 1e-4, 1e-5),
+                                                      ("fp64", 1e-6, 1e-9)])
+def test_factored_m2l(precision, tol, tol_dense):
+    """M2L with each offset's operator split by its own truncated SVD
+    (m2l_factored): against the direct sum at the precision's bar and against
+    the dense M2L within the truncation, for the pair evaluation and for one
+    plan alone."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, autotune as at, eval_pair
+    x = _cloud()
+    q = np.random.default_rng(134).standard_normal(len(x))
+    xt = torch.tensor(x, device="cuda")
+    qt = torch.tensor(q, device="cuda", dtype=torch.float64 if precision == "fp64" else torch.float32)
+    mk = lambda k: FMMPlan(xt, kernel=k, kappa=KAPPA, p=8, ncrit=48, precision=precision)
+    dense = [mk("laplace"), mk("yukawa")]
+    with at.tuning(m2l_factored=1):
+        fact = [mk("laplace"), mk("yukawa")]
+    print(f"[factored m2l] {precision}", flush=True)
+    outs_d = eval_pair(dense[0], dense[1], qt)
+    outs_f = eval_pair(fact[0], fact[1], qt)
+    alone = fact[1].eval(qt)
+    rows = np.arange(0, len(x), 5)
+    for k, od, of in zip(("laplace", "yukawa"), outs_d, outs_f):
+        p0, g0 = D.direct(x[rows], x, q, k, KAPPA)
+        pf, gf = of[0].double().cpu().numpy(), of[1].double().cpu().numpy()
+        pd, gd = od[0].double().cpu().numpy(), od[1].double().cpu().numpy()
+        print(f"  {k}: direct pot {D.rel_l2(pf[rows], p0):.2e} grad {D.rel_l2(gf[rows], g0):.2e}; "
+              f"dense pot {D.rel_l2(pf, pd):.2e} grad {D.rel_l2(gf, gd):.2e}", flush=True)
+        assert D.rel_l2(pf[rows], p0) < tol and D.rel_l2(gf[rows], g0) < tol
+        assert D.rel_l2(pf, pd) < tol_dense and D.rel_l2(gf, gd) < tol_dense
+    assert D.rel_l2(alone[0].double().cpu().numpy(), outs_f[1][0].double().cpu().numpy()) < 1e-6

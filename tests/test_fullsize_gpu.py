@@ -93,6 +93,33 @@ def test_surface393k_pair(surface393k, precision, tol, ncrit):
         assert ep < tol and eg < tol
 
 
+@pytest.mark.parametrize("precision,tol,tuning", [
+    ("bf16x3", 1e-4, {"work_cap_div": 32768}),
+    ("bf16x3", 1e-4, {"work_cap_div": 32768, "m2l_factored": 1}),
+    ("fp64", 1e-6, {"work_cap_div": 32768, "m2l_factored": 1}),
+])
+def test_surface393k_pair_tuned_and_factored(surface393k, precision, tol, tuning):
+    """The benchmark's step in the autotuned configuration (ncrit 160, leaf
+    items cut at total/32768) and with the per-offset factored M2L, against
+    the direct sums on sampled rows."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, autotune as at, eval_pair
+    x, q = surface393k
+    xt = torch.tensor(x, device="cuda")
+    with at.tuning(**tuning):
+        plans = [FMMPlan(xt, kernel=k, kappa=KAPPA, p=8, ncrit=160, precision=precision)
+                 for k in ("laplace", "yukawa")]
+    outs = eval_pair(plans[0], plans[1], torch.tensor(q, device="cuda"))
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(75).choice(len(x), 2048, replace=False)
+    for kernel, (pot, grad) in zip(("laplace", "yukawa"), outs):
+        phi, g = D.direct(x[rows], x, q, kernel, KAPPA if kernel == "yukawa" else 0.0)
+        ep = _rel(pot.cpu().numpy()[rows], phi)
+        eg = _rel(grad.cpu().numpy()[rows], g)
+        _say(f"[393k pair {precision} {tuning} {kernel}] pot {ep:.2e} grad {eg:.2e}")
+        assert ep < tol and eg < tol
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("fp64", 1e-6)])
 @pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
 def test_surface393k_fp32_fp64(surface393k, kernel, precision, tol):
