@@ -186,6 +186,10 @@ int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const v
  *                 largest in single precision, 1e-11 in FP64), and applied in
  *                 two gather-GEMM passes (R to a k-value intermediate per
  *                 pair, then L); 0: one dense pass (the default)
+ *   near_late     pair evaluations: 0 starts the near field once P2M is
+ *                 done (beside the upward GEMMs; P2L after it); 1 runs P2L
+ *                 beside the upward GEMMs and starts the near field once the
+ *                 upward pass is done (beside M2L and the downward pass)
  * FMM_EINVAL for values out of range. */
 typedef struct {
   int32_t tile_split2;
@@ -195,6 +199,7 @@ typedef struct {
   double far_weight;
   int32_t gemm_rbw;
   int32_t m2l_factored;
+  int32_t near_late;
 } fmm_tuning_t;
 int fmm_set_tuning(const fmm_tuning_t *tuning);
 int fmm_get_tuning(fmm_tuning_t *tuning);

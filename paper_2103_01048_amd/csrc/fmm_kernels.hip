@@ -1888,8 +1888,10 @@ int ensure_pair(fmm_plan *A, fmm_plan *B, int nr);  // host: side streams, event
 // M2P sources' equivalent densities (only the far field reads them): on
 // stream s after the near field, off the side stream's chain, which bounds
 // the step.
+// P2L and the projection of its check potentials (added by the M2L sums);
+// B's join event marks their end.
 template <typename T, int NR>
-static int pair_off_chain(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips) {
+static int pair_p2l_proj(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips) {
   const PassLists &LA = A->lists_by_nr[NR], &LB = B->lists_by_nr[NR];
   int rc = pair_p2l<T, NR>(A, B, s, dips);
   if (rc) return rc;
@@ -1898,7 +1900,16 @@ static int pair_off_chain(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   if (rc) return rc;
   prof_end(A, FMM_PHASE_DC2E, ev, s);
   FMM_HIP_TRY(hipEventRecord(B->ev_join, s));
+  return FMM_OK;
+}
+
+template <typename T, int NR>
+static int pair_off_chain(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips, bool p2l) {
+  const PassLists &LA = A->lists_by_nr[NR], &LB = B->lists_by_nr[NR];
+  int rc;
+  if (p2l && (rc = pair_p2l_proj<T, NR>(A, B, s, dips))) return rc;
   FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_up, 0));
+  hipEvent_t ev;
   ev = prof_begin(A, FMM_PHASE_UC2E, s);
   if ((rc = launch_gemm2<T>(A, LA.vs_u, (const T *)A->cu, (T *)A->equ, B, &LB.vs_u, (const T *)B->cu, (T *)B->equ, s)))
     return rc;
@@ -1918,17 +1929,24 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   const bool far = A->dt.maxlevel >= 2;
   // FMM_PROFILE_SERIAL: the side stream's passes run on s, in the same order
   const hipStream_t side = (A->profiling & FMM_PROFILE_SERIAL) ? s : A->aux;
+  const bool late = A->tune.near_late != 0;
   if (far) {
     FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
     FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_fork, 0));
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips))) return rc;
     // the near field starts once P2M (VALU, like the near field) is done,
-    // and shares the GPU with the GEMM passes
+    // and shares the GPU with the GEMM passes; or (near_late) P2L and its
+    // projection run beside the upward GEMMs and the near field starts with
+    // the M2L and the downward pass
     FMM_HIP_TRY(hipStreamWaitEvent(s, B->ev_fork, 0));
+    if (late) {
+      if ((rc = pair_p2l_proj<T, NR>(A, B, s, dips))) return rc;
+      FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_up, 0));
+    }
   }
   if ((rc = near())) return rc;
   if (far) {
-    if ((rc = pair_off_chain<T, NR>(A, B, s, dips))) return rc;
+    if ((rc = pair_off_chain<T, NR>(A, B, s, dips, !late))) return rc;
     FMM_HIP_TRY(hipStreamWaitEvent(side, B->ev_join, 0));
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 2, nullptr, nullptr, dips))) return rc;
     FMM_HIP_TRY(hipEventRecord(A->ev_join, side));

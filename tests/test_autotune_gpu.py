@@ -1,6 +1,6 @@
 """Tunables of the plans and the autotuner: every setting of the tunables
 (leaf-tile splits, work cap of leaf items, weight of surface sources, GEMM
-row blocks per wave) gives the same FMM within rounding (single precision
+row blocks per wave, the order of the pair evaluation's passes) gives the same FMM within rounding (single precision
 against the default setting 1e-6, and the FP64 direct sum 1e-4); the
 autotuner returns a setting from its candidate lists that meets the same
 bar, and caches it."""
@@ -39,6 +39,7 @@ def _pair(xt, q, ncrit=48):
     {"far_weight": 3.0},
     {"gemm_rbw": 1},
     {"gemm_rbw": 4},
+    {"near_late": 1},
 ])
 def test_every_setting_gives_the_same_fmm(setting):
     torch = require_gpu()
