@@ -186,10 +186,18 @@ int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const v
  *                 largest in single precision, 1e-11 in FP64), and applied in
  *                 two gather-GEMM passes (R to a k-value intermediate per
  *                 pair, then L); 0: one dense pass (the default)
- *   near_late     pair evaluations: 0 starts the near field once P2M is
- *                 done (beside the upward GEMMs; P2L after it); 1 runs P2L
- *                 beside the upward GEMMs and starts the near field once the
- *                 upward pass is done (beside M2L and the downward pass)
+ *   pair_order    pair evaluations, the caller's stream (the far-field
+ *                 passes run on a side stream meanwhile): 0 near field once
+ *                 P2M is done, then P2L; 1 P2L once P2M is done, near field
+ *                 once the upward pass is done; 2 P2L, then the near field,
+ *                 both once P2M is done
+ *   near_lds      pair evaluations: LDS bytes (0..65536, unused by the
+ *                 kernel) reserved per near-field wave, which caps the
+ *                 near-field waves per compute unit so that the far-field
+ *                 passes on the side stream find room beside them; 0: none
+ *   gemm_lat      translation GEMM launches of at most this many workgroups
+ *                 (0..1<<20) run the latency-bound form (all operands of a
+ *                 workgroup fetched at once); 0: never; default 512
  * FMM_EINVAL for values out of range. */
 typedef struct {
   int32_t tile_split2;
@@ -199,7 +207,9 @@ typedef struct {
   double far_weight;
   int32_t gemm_rbw;
   int32_t m2l_factored;
-  int32_t near_late;
+  int32_t pair_order;
+  int32_t near_lds;
+  int32_t gemm_lat;
 } fmm_tuning_t;
 int fmm_set_tuning(const fmm_tuning_t *tuning);
 int fmm_get_tuning(fmm_tuning_t *tuning);

@@ -47,7 +47,8 @@ class FmmTuning(ctypes.Structure):
     _fields_ = [
         ("tile_split2", ctypes.c_int32), ("tile_split4", ctypes.c_int32), ("work_cap_min", ctypes.c_int32),
         ("work_cap_div", ctypes.c_int32), ("far_weight", ctypes.c_double), ("gemm_rbw", ctypes.c_int32),
-        ("m2l_factored", ctypes.c_int32), ("near_late", ctypes.c_int32),
+        ("m2l_factored", ctypes.c_int32), ("pair_order", ctypes.c_int32),
+        ("near_lds", ctypes.c_int32), ("gemm_lat", ctypes.c_int32),
     ]
 
 

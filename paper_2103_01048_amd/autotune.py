@@ -13,8 +13,12 @@ Tunables (fmm_set_tuning; defaults in DEFAULTS):
   gemm_rbw                    16-row blocks per wave in the translation GEMMs
   m2l_factored                M2L operators split per offset by a truncated
                               SVD and applied in two passes
-  near_late                   the pair evaluation's near field beside the
-                              downward chain instead of the upward one
+  pair_order                  order of the pair evaluation's near field and
+                              P2L against the far-field passes (0, 1, 2)
+  near_lds                    LDS bytes held per near-field wave of a pair
+                              evaluation (caps its waves per compute unit)
+  gemm_lat                    translation GEMM launches of at most this many
+                              workgroups use the latency-bound kernel
 
 The search is coordinate descent: ncrit first (with the defaults), then the
 work cap, the tile splits, the surface weight and the GEMM row blocks, each
@@ -38,7 +42,8 @@ from ._lib import check, lib
 from .fmm import FMMPlan, eval_pair
 
 DEFAULTS = {"tile_split2": 32, "tile_split4": 16, "work_cap_min": 512, "work_cap_div": 16384, "far_weight": 1.15,
-            "gemm_rbw": 0, "m2l_factored": 0, "near_late": 0}
+            "gemm_rbw": 0, "m2l_factored": 0, "pair_order": 0,
+            "near_lds": 0, "gemm_lat": 512}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2103_01048_amd", "tuning.json")
 
 STAGES = (
@@ -47,7 +52,9 @@ STAGES = (
     ("far_weight", [{"far_weight": v} for v in (1.0, 1.15, 1.3)]),
     ("gemm_rbw", [{"gemm_rbw": v} for v in (0, 1, 2, 4)]),
     ("m2l_factored", [{"m2l_factored": v} for v in (0, 1)]),
-    ("near_late", [{"near_late": v} for v in (0, 1)]),
+    ("pair_order", [{"pair_order": v} for v in (0, 1, 2)]),
+    ("near_lds", [{"near_lds": v} for v in (0, 8192, 13312)]),
+    ("gemm_lat", [{"gemm_lat": v} for v in (0, 256, 512, 1024)]),
 )
 
 

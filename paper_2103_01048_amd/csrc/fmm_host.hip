@@ -1241,7 +1241,7 @@ void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
 
 // Tunables for plans set up from now on (fmm_set_tuning).
 static std::mutex g_tune_mu;
-static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 0};
+static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 0, 0, 512};
 
 // Live plans whose tree later plans on the same points may share.
 static std::mutex g_tree_mu;
@@ -1654,8 +1654,9 @@ int fmm_set_tuning(const fmm_tuning_t *t) {
   if (!t) { set_error("fmm_set_tuning: null argument"); return FMM_EINVAL; }
   if (t->tile_split2 < 0 || t->tile_split2 > 32 || t->tile_split4 < 0 || t->tile_split4 > 16 ||
       t->work_cap_min < 1 || t->work_cap_div < 1 || !(t->far_weight > 0.0) || !std::isfinite(t->far_weight) ||
-      t->gemm_rbw < 0 || t->gemm_rbw > 8 || t->m2l_factored < 0 || t->m2l_factored > 1 || t->near_late < 0 ||
-      t->near_late > 1) {
+      t->gemm_rbw < 0 || t->gemm_rbw > 8 || t->m2l_factored < 0 || t->m2l_factored > 1 || t->pair_order < 0 ||
+      t->pair_order > 2 || t->near_lds < 0 || t->near_lds > 65536 ||
+      t->gemm_lat < 0 || t->gemm_lat > (1 << 20)) {
     set_error("fmm_set_tuning: value out of range");
     return FMM_EINVAL;
   }

@@ -436,6 +436,100 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g0, GemmArgs g1) {
   }
 }
 
+// Latency-bound launches (fewer workgroups than the device has compute
+// units: the M2M and L2L levels, the surface projections): the same
+// gather-GEMM with one 16-row block per wave, every A fragment of the wave
+// loaded before the first MFMA and the whole K extent (KCH 64-wide chunks)
+// of the 64 gathered columns staged to LDS at once, so that a workgroup
+// waits for memory once instead of once per chunk.  The MFMAs run in the
+// same k order as k_gemm, so the results are the same bit for bit.
+template <typename T, int KCH>
+__global__ __launch_bounds__(256) void k_gemm_lat(GemmArgs g0, GemmArgs g1) {
+  __builtin_amdgcn_s_setprio(3);
+  using V4 = typename Vec4<T>::type;
+  GemmArgs g;
+  int task;
+  if (!gemm_pick(g0, g1, g, task)) return;
+  const GemmTask tk = g.tasks[task];
+  const int S = g.S, seg = g.seg, KQ = g.KQ, ld = g.ldx, ldy = g.ldy, mode = g.mode;
+  const int nrb = tk.nrb > 0 ? min(tk.nrb, g.nrb) : g.nrb;
+  const int K = tk.klen > 0 ? min(tk.klen, g.klen) : g.klen;  // <= 64 KCH (checked by the launcher)
+  const int KQK = K >> 4;
+  const int32_t *__restrict__ src = g.src;
+  const int32_t *__restrict__ dst = g.dst;
+  const T *__restrict__ X = (const T *)g.X;
+  T *__restrict__ Y = (T *)g.Y;
+  __shared__ T Bs[64 * KCH][GEMM_NT + 1];
+  __shared__ int32_t s_src[GEMM_NT * 8];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int rb = (int)blockIdx.y * 4 + (tid >> 6);  // this wave's row block
+  const bool live = rb < nrb;
+  const T *__restrict__ A = (const T *)g.pool + (int64_t)tk.mat * g.mstride + ((int64_t)rb * KQ * 64 + lane) * 4;
+  V4 a[4 * KCH];
+#pragma unroll
+  for (int q = 0; q < 4 * KCH; ++q) a[q] = (live && q < KQK) ? *reinterpret_cast<const V4 *>(A + (int64_t)q * 256) : V4{0, 0, 0, 0};
+  for (int i = tid; i < GEMM_NT * S; i += 256) {
+    int c = i / S;
+    s_src[i] = (c < tk.ncol) ? src[(int64_t)(tk.col0 + c) * S + (i - c * S)] : -1;
+  }
+  __syncthreads();
+  const int scol = tid >> 2, spart = (tid & 3) * 16;
+  V4 v[KCH][4];
+#pragma unroll
+  for (int ch = 0; ch < KCH; ++ch) {
+    const int k0 = ch * 64 + spart;
+    int row = -1, kk = 0;
+    if (k0 < K) {
+      const int sg = k0 / seg;
+      kk = k0 - sg * seg;
+      row = s_src[scol * S + sg];
+    }
+    const V4 *p = reinterpret_cast<const V4 *>(X + (int64_t)(row >= 0 ? row : 0) * ld + kk);
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) v[ch][q4] = row >= 0 ? p[q4] : V4{0, 0, 0, 0};
+  }
+#pragma unroll
+  for (int ch = 0; ch < KCH; ++ch)
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Bs[ch * 64 + spart + q4 * 4 + e][scol] = v[ch][q4][e];
+  __syncthreads();
+  if (!live) return;
+  V4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = V4{0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 4 * KCH; ++q) {
+    if (q < KQK) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int kl = (q * 4 + t) * 4 + (lane >> 4);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = mfma_16x16x4(a[q][t], Bs[kl][cb * 16 + (lane & 15)], acc[cb]);
+      }
+    }
+  }
+  const T alpha = (T)tk.alpha;
+  const int i0 = rb * 16 + 4 * (lane >> 4);
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int c = cb * 16 + (lane & 15);
+    if (c >= tk.ncol) continue;
+    const int64_t row = dst[tk.col0 + c];
+    T *y = Y + row * ldy + i0;
+    V4 r = acc[cb] * alpha;
+    if (mode == GEMM_STORE) {
+      *reinterpret_cast<V4 *>(y) = r;
+    } else if (mode == GEMM_ADD) {
+      V4 o = *reinterpret_cast<V4 *>(y);
+      *reinterpret_cast<V4 *>(y) = o + r;
+    } else {
+      atomicAdd(y + 0, r[0]); atomicAdd(y + 1, r[1]); atomicAdd(y + 2, r[2]); atomicAdd(y + 3, r[3]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The same gather-GEMM with each FP32 operand split into bf16 high and low
 // parts (x = hi + lo, hi = bf16(x), lo = bf16(x - hi)) and three
@@ -910,8 +1004,8 @@ __global__ __launch_bounds__(64) void k_near_pair(
 #pragma unroll
             for (int c = 0; c < NR; ++c) qv[c] = qs[(int64_t)c * N + j];
           }
-          leaf_pair_ly<T, decltype(chk)::value, NR>(xt, yt, zt, sp[0], sp[1], sp[2], qv, qv, kappa, kl2, pa, xa, ya, za,
-                                                     pb, xb, yb, zb);
+          leaf_pair_ly<T, decltype(chk)::value, NR>(xt, yt, zt, sp[0], sp[1], sp[2], qv, qv, kappa, kl2, pa, xa, ya,
+                                                     za, pb, xb, yb, zb);
         };
         if (self) {
 #pragma unroll 4
@@ -931,8 +1025,8 @@ __global__ __launch_bounds__(64) void k_near_pair(
 #pragma unroll
             for (int c = 0; c < NR; ++c) qv[c] = ok ? qs[(int64_t)c * N + jj] : (T)0;
           }
-          leaf_pair_ly<T, decltype(chk)::value, NR>(xt, yt, zt, sp[0], sp[1], sp[2], qv, qv, kappa, kl2, pa, xa, ya, za,
-                                                     pb, xb, yb, zb);
+          leaf_pair_ly<T, decltype(chk)::value, NR>(xt, yt, zt, sp[0], sp[1], sp[2], qv, qv, kappa, kl2, pa, xa, ya,
+                                                     za, pb, xb, yb, zb);
         };
         if (self) {
 #pragma unroll 2
@@ -1115,8 +1209,13 @@ __global__ __launch_bounds__(64) void k_far_pair(
 
 // Surface kernel of a pair evaluation: the Laplace (YA) and Yukawa (YB)
 // potentials at the surface points of box tbox[slot] from the same sources,
-// one distance per pair.  One surface point per thread (blockDim.x = 64
-// ceil(nsurf / 64) <= 512); sources staged through LDS blockDim.x at a time.
+// one distance per pair.  One surface point per lane, a wave per 64 surface
+// points (blockDim.x = 64 ceil(nsurf / 64) <= 512).  Every wave reads the
+// sources itself with wave-uniform addresses (scalar loads, no LDS and no
+// barrier), and the target point is moved into each source leaf's frame
+// once per leaf.  Surfaces never hold a source point (check surfaces lie
+// outside the boxes whose points they see, and X-list leaves are not
+// adjacent to the boxes they feed), so no pair is at zero distance.
 template <typename T, int NR>
 __global__ __launch_bounds__(512) void k_surf_eval_pair(
     const int32_t *__restrict__ tbox, const int32_t *__restrict__ src_off, const int32_t *__restrict__ src_idx,
@@ -1124,47 +1223,39 @@ __global__ __launch_bounds__(512) void k_surf_eval_pair(
     const T *__restrict__ pts, const T *__restrict__ qs, int64_t N, const int32_t *__restrict__ box_begin,
     const int32_t *__restrict__ box_end, const T *__restrict__ box_geom, const T *__restrict__ surf, int nsurf,
     int ld, T alpha, T *__restrict__ YA, T *__restrict__ YB, int mode, T kappa) {
-  __shared__ T sx[512], sy[512], sz[512], sq[NR][512];
+  using V4 = typename Vec4<T>::type;
+  const V4 *__restrict__ p4 = reinterpret_cast<const V4 *>(pts);
   const int slot = blockIdx.x;
   const int b = tbox[slot];
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
   // target surface in the box's own frame; sources (leaf frames) shifted by
   // src_o (source leaf centre - box centre; none: the box itself)
-  const T cx = 0, cy = 0, cz = 0;
   const T rr = box_geom[b * 4 + 3] * alpha;
   const int ii = tid < nsurf ? tid : 0;
-  const T tx = cx + rr * surf[ii * 4 + 0], ty = cy + rr * surf[ii * 4 + 1], tz = cz + rr * surf[ii * 4 + 2];
+  const T tx = rr * surf[ii * 4 + 0], ty = rr * surf[ii * 4 + 1], tz = rr * surf[ii * 4 + 2];
+  const T kl2 = kappa * (T)1.4426950408889634;  // kappa * log2(e)
   T accA[NR], accB[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) accA[r] = accB[r] = (T)0;
-  for (int k = src_off[slot]; k < src_off[slot + 1]; ++k) {
+  const int k1 = src_off[slot + 1];
+  for (int k = src_off[slot]; k < k1; ++k) {
     const int a = src_idx[k];
-    const T ox = src_o ? src_o[4 * k] : (T)0, oy = src_o ? src_o[4 * k + 1] : (T)0,
-            oz = src_o ? src_o[4 * k + 2] : (T)0;
+    const T xt = src_o ? tx - src_o[4 * k] : tx, yt = src_o ? ty - src_o[4 * k + 1] : ty,
+            zt = src_o ? tz - src_o[4 * k + 2] : tz;
     const int sb = box_begin[a], se = box_end[a];
-    for (int c0 = sb; c0 < se; c0 += nt) {
-      const int j = c0 + tid;
-      if (j < se) {
-        sx[tid] = pts[(int64_t)j * 4 + 0] + ox;
-        sy[tid] = pts[(int64_t)j * 4 + 1] + oy;
-        sz[tid] = pts[(int64_t)j * 4 + 2] + oz;
+#pragma unroll 8
+    for (int j = sb; j < se; ++j) {
+      const V4 sp = p4[j];
+      const T dx = xt - sp[0], dy = yt - sp[1], dz = zt - sp[2];
+      const T r2 = dx * dx + dy * dy + dz * dz;
+      const T invr = dev_rsqrt(r2);
+      const T gy = dev_exp2(-kl2 * (r2 * invr)) * invr;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) sq[r][tid] = qs[(int64_t)r * N + j];
+      for (int r = 0; r < NR; ++r) {
+        const T q = qs[(int64_t)r * N + j];
+        accA[r] += invr * q;
+        accB[r] += gy * q;
       }
-      __syncthreads();
-      const int cnt = min(nt, se - c0);
-      for (int j2 = 0; j2 < cnt; ++j2) {
-        const T dx = tx - sx[j2], dy = ty - sy[j2], dz = tz - sz[j2];
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        const T invr = r2 > (T)0 ? dev_rsqrt(r2) : (T)0;
-        const T gy = dev_exp(-kappa * (r2 * invr)) * invr;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          accA[r] += invr * sq[r][j2];
-          accB[r] += gy * sq[r][j2];
-        }
-      }
-      __syncthreads();
     }
   }
   if (tid < nsurf) {
@@ -1557,6 +1648,24 @@ static void launch_gemm_rbw(const GemmArgs &g0, const GemmArgs &g1, bool bf3, in
   hipLaunchKernelGGL((k_gemm<T, RBW>), dim3(gx, gy), dim3(256), 0, s, g0, g1);
 }
 
+template <typename T>
+static void launch_gemm_lat(const GemmArgs &g0, const GemmArgs &g1, int kch, hipStream_t s) {
+  const int nrb = std::max(g0.nrb, g1.ntask ? g1.nrb : 0);
+  const dim3 grid(8u * (unsigned)((g0.ntask + 7) / 8 + (g1.ntask + 7) / 8), (unsigned)((nrb + 3) / 4));
+  if constexpr (std::is_same<T, double>::value) {
+    if (kch <= 1) hipLaunchKernelGGL((k_gemm_lat<T, 1>), grid, dim3(256), 0, s, g0, g1);
+    else hipLaunchKernelGGL((k_gemm_lat<T, 2>), grid, dim3(256), 0, s, g0, g1);
+  } else {
+    switch (kch) {
+      case 1: hipLaunchKernelGGL((k_gemm_lat<T, 1>), grid, dim3(256), 0, s, g0, g1); break;
+      case 2: hipLaunchKernelGGL((k_gemm_lat<T, 2>), grid, dim3(256), 0, s, g0, g1); break;
+      case 3: hipLaunchKernelGGL((k_gemm_lat<T, 3>), grid, dim3(256), 0, s, g0, g1); break;
+      case 4: hipLaunchKernelGGL((k_gemm_lat<T, 4>), grid, dim3(256), 0, s, g0, g1); break;
+      default: hipLaunchKernelGGL((k_gemm_lat<T, 5>), grid, dim3(256), 0, s, g0, g1); break;
+    }
+  }
+}
+
 // One launch for batch bt of plan P and, when Q is given, the same batch
 // bq of plan Q (a plan sharing P's tree and precision).
 template <typename T>
@@ -1570,6 +1679,16 @@ static int launch_gemm2(fmm_plan *P, const GemmBatch &bt, const T *X, T *Y, fmm_
   if (g0.ntask == 0) { std::swap(g0, g1); g1.ntask = 0; }
   const bool bf3 = bt.pool == 2;
   const int nrb = std::max(g0.nrb, g1.ntask ? g1.nrb : 0);
+  // launches of at most tune.gemm_lat workgroups (about one per compute
+  // unit: the latency kernel holds many registers and much LDS) whose K
+  // extent fits its staging (320 single, 128 double precision values)
+  const int kch = (std::max(g0.klen, g1.ntask ? g1.klen : 0) + 63) / 64;
+  const int64_t lat_wg = 8 * (int64_t)((g0.ntask + 7) / 8 + (g1.ntask + 7) / 8) * ((nrb + 3) / 4);
+  if (!bf3 && lat_wg <= P->tune.gemm_lat && kch <= (std::is_same<T, double>::value ? 2 : 5)) {
+    launch_gemm_lat<T>(g0, g1, kch, s);
+    FMM_HIP_TRY(hipGetLastError());
+    return FMM_OK;
+  }
   // Small launches (few column tiles) split the row blocks over a second grid
   // dimension so that more workgroups share the work.
   int rbw = g0.ntask + g1.ntask >= 1024 ? (nrb + 3) / 4 : 1;
@@ -1929,24 +2048,24 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   const bool far = A->dt.maxlevel >= 2;
   // FMM_PROFILE_SERIAL: the side stream's passes run on s, in the same order
   const hipStream_t side = (A->profiling & FMM_PROFILE_SERIAL) ? s : A->aux;
-  const bool late = A->tune.near_late != 0;
+  const int order = A->tune.pair_order;
   if (far) {
     FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
     FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_fork, 0));
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips))) return rc;
-    // the near field starts once P2M (VALU, like the near field) is done,
-    // and shares the GPU with the GEMM passes; or (near_late) P2L and its
-    // projection run beside the upward GEMMs and the near field starts with
-    // the M2L and the downward pass
+    // the near field starts once P2M (VALU, like the near field) is done and
+    // shares the GPU with the GEMM passes; P2L and its projection (which the
+    // M2L sums wait for) run after it (order 0) or before it (1: the near
+    // field then also waits for the upward pass; 2: it does not)
     FMM_HIP_TRY(hipStreamWaitEvent(s, B->ev_fork, 0));
-    if (late) {
+    if (order != 0) {
       if ((rc = pair_p2l_proj<T, NR>(A, B, s, dips))) return rc;
-      FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_up, 0));
+      if (order == 1) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_up, 0));
     }
   }
   if ((rc = near())) return rc;
   if (far) {
-    if ((rc = pair_off_chain<T, NR>(A, B, s, dips, !late))) return rc;
+    if ((rc = pair_off_chain<T, NR>(A, B, s, dips, order == 0))) return rc;
     FMM_HIP_TRY(hipStreamWaitEvent(side, B->ev_join, 0));
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 2, nullptr, nullptr, dips))) return rc;
     FMM_HIP_TRY(hipEventRecord(A->ev_join, side));
@@ -1968,7 +2087,7 @@ static int eval_pair_chunk(fmm_plan *A, fmm_plan *B, const T *q, T *pot_a, T *gr
   auto near = [&]() -> int {
     hipEvent_t e = prof_begin(A, FMM_PHASE_NEAR, s);
     if (D.nitems > 0)
-      hipLaunchKernelGGL((k_near_pair<T, NR>), dim3(D.nitems), dim3(64), 0, s, D.items,
+      hipLaunchKernelGGL((k_near_pair<T, NR>), dim3(D.nitems), dim3(64), A->tune.near_lds, s, D.items,
                          D.leaves, (const T *)D.pts, (const T *)A->qs, N, D.box_begin, D.box_end, D.near_off,
                          D.near_rng, (const T *)D.near_o, acc, kappa, D.nitems);
     FMM_HIP_TRY(hipGetLastError());
@@ -2054,11 +2173,11 @@ static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip
     hipEvent_t e = prof_begin(A, FMM_PHASE_NEAR, s);
     if (D.nitems > 0) {
       if (grad)
-        hipLaunchKernelGGL((k_near_pair_md<T, true>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
+        hipLaunchKernelGGL((k_near_pair_md<T, true>), dim3(D.nitems), dim3(64), A->tune.near_lds, s, D.items, D.leaves,
                            (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
                            (const T *)D.near_o, acc, kappa, D.nitems);
       else
-        hipLaunchKernelGGL((k_near_pair_md<T, false>), dim3(D.nitems), dim3(64), 0, s, D.items, D.leaves,
+        hipLaunchKernelGGL((k_near_pair_md<T, false>), dim3(D.nitems), dim3(64), A->tune.near_lds, s, D.items, D.leaves,
                            (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
                            (const T *)D.near_o, acc, kappa, D.nitems);
     }

@@ -39,7 +39,11 @@ def _pair(xt, q, ncrit=48):
     {"far_weight": 3.0},
     {"gemm_rbw": 1},
     {"gemm_rbw": 4},
-    {"near_late": 1},
+    {"pair_order": 1},
+    {"pair_order": 2},
+    {"gemm_lat": 0},
+    {"gemm_lat": 1 << 20},
+    {"near_lds": 13312},
 ])
 def test_every_setting_gives_the_same_fmm(setting):
     torch = require_gpu()
