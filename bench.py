@@ -172,6 +172,17 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (reference for HBM byte counters)")
+    ap.add_argument("--tuning", default="",
+                    help="with --ncrit: library tunables as JSON (e.g. the autotuner's choice), instead of the "
+                         "defaults")
+    ap.add_argument("--summarize-profile", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write a profile summary from rocprofv3 output (kernel-trace --stats, then --pmc "
+                         "FETCH_SIZE and --pmc WRITE_SIZE runs of the same command) and the per-kernel HBM "
+                         "bytes the bench line reads; no GPU work")
+    ap.add_argument("--summary-out", default="profiles/fmm_eval_pair_sphere_union_393k_p8.md")
+    ap.add_argument("--summary-title", default="")
+    ap.add_argument("--summary-cmd", action="append", default=[],
+                    help="the command of each rocprofv3 run, recorded in the summary (repeat)")
     return ap.parse_args()
 
 
@@ -395,8 +406,100 @@ def run_bem(args):
     print(json.dumps(line), flush=True)
 
 
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        rows += list(csv.DictReader(open(f)))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return rows
+
+
+def _kname(name: str) -> str:
+    """Kernel name without its argument list."""
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i].strip()
+    return name.strip()
+
+
+def summarize_profile(args):
+    """Profile summary (markdown) and per-kernel HBM bytes (profiles/traffic.json)
+    from three rocprofv3 runs of one command: --kernel-trace --stats, --pmc
+    FETCH_SIZE, --pmc WRITE_SIZE.  Counter bytes are scaled by what the same
+    counters read for the 256 MiB device copy of --copy-probe."""
+    import hashlib
+    trace_dir, fetch_dir, write_dir = args.summarize_profile
+    stats = _csv_rows(trace_dir, "kernel_stats.csv")
+    per = {}
+    for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if r["Counter_Name"] != counter:
+                continue
+            k = _kname(r["Kernel_Name"])
+            per.setdefault(k, {}).setdefault(tag, {})[r["Dispatch_Id"]] = float(r["Counter_Value"])
+    copy_bytes = 256 << 20
+    ref = None
+    for k, v in per.items():
+        if "copyBuffer" in k or "direct_copy" in k:
+            for disp, w in v.get("write", {}).items():
+                if abs(w * 1024 - copy_bytes) < 0.02 * copy_bytes and disp in v.get("fetch", {}):
+                    ref = (k, v["fetch"][disp], w)
+    if ref is None:
+        raise SystemExit("no 256 MiB copy dispatch in the counter runs (run the command with --copy-probe)")
+    f_scale = copy_bytes / (ref[1] * 1024)
+    w_scale = copy_bytes / (ref[2] * 1024)
+    med = lambda xs: float(np.median(list(xs))) if xs else 0.0
+    traffic = {}
+    for k, v in sorted(per.items()):
+        if "fetch" in v and "write" in v:
+            traffic[k] = {"read_bytes": med(v["fetch"].values()) * 1024 * f_scale,
+                          "write_bytes": med(v["write"].values()) * 1024 * w_scale,
+                          "dispatches": len(v["fetch"])}
+    src = os.path.join(ROOT, "paper_2103_01048_amd", "csrc", "fmm_kernels.hip")
+    out_md = args.summary_out
+    lines = [f"# rocprofv3 summary: {args.summary_title or os.path.basename(out_md)}", "",
+             "Commands (from the repository root, TMPDIR=/tmp):", ""]
+    lines += [f"    {c}" for c in args.summary_cmd] + [""]
+    lines += ["## Kernel time (kernel-trace --stats)", "", "| total ms | calls | avg us | kernel |", "|---:|---:|---:|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        if float(r["TotalDurationNs"]) < 0.002 * sum(float(x["TotalDurationNs"]) for x in stats):
+            continue
+        lines.append(f"| {float(r['TotalDurationNs']) / 1e6:.3f} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"`{_kname(r['Name'])[:160]}` |")
+    lines += ["", "## HBM traffic (--pmc, KiB per dispatch, median over dispatches)", "",
+              f"Reference: the 256 MiB device copy (`{ref[0][:80]}`) reads FETCH_SIZE {ref[1]:.0f} KiB and writes "
+              f"WRITE_SIZE {ref[2]:.0f} KiB, so bytes = FETCH_SIZE x {f_scale:.3f} KiB and WRITE_SIZE x "
+              f"{w_scale:.3f} KiB.", "",
+              "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled MB read | scaled MB written |",
+              "|---|---:|---:|---:|---:|---:|"]
+    for k, t in traffic.items():
+        if t["read_bytes"] + t["write_bytes"] < 1e6:
+            continue
+        lines.append(f"| `{k[:140]}` | {t['dispatches']} | {t['read_bytes'] / 1024 / f_scale:.0f} | "
+                     f"{t['write_bytes'] / 1024 / w_scale:.0f} | {t['read_bytes'] / 1e6:.1f} | "
+                     f"{t['write_bytes'] / 1e6:.1f} |")
+    os.makedirs(os.path.dirname(os.path.abspath(out_md)), exist_ok=True)
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    rec = {"kernels_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+           "profile": os.path.basename(out_md), "fetch_scale": f_scale, "write_scale": w_scale,
+           "traffic": {k: {"read_bytes": t["read_bytes"], "write_bytes": t["write_bytes"]} for k, t in traffic.items()}}
+    json.dump(rec, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
+    print(f"wrote {out_md} and profiles/traffic.json ({len(traffic)} kernels)")
+
+
 def main():
     args = parse()
+    if args.summarize_profile:
+        summarize_profile(args)
+        return
     if args.gpus != 1:
         print("bench.py: runs on one GPU; --gpus must be 1 "
               "(the multi-GPU sharding is described, not implemented)", file=sys.stderr)
@@ -470,6 +573,9 @@ def main():
     tuned = None
     if args.ncrit:
         ncrit = args.ncrit
+        if args.tuning:
+            from paper_2103_01048_amd import autotune as at
+            tuned = {"ncrit": ncrit, "tuning": at.set_tuning(**json.loads(args.tuning)), "given": True}
     else:
         from paper_2103_01048_amd import autotune as at
         res = at.autotune(xt, p=P_ORDER, precision=args.precision, kappa=KAPPA, q=qd[torch.float32],

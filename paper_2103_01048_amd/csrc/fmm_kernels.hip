@@ -906,11 +906,24 @@ __global__ __launch_bounds__(64) void k_leaf_parts(const int32_t *__restrict__ t
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
     T acc[4] = {0, 0, 0, 0};
-    for (int k = 0; k < np; ++k) {
-      const T *pp = parts + (int64_t)(p0 + k) * NR * 4 * 64;
+    const T *pp = parts + (int64_t)p0 * NR * 4 * 64 + c * 4 * 64 + lane;
+    const int64_t ps = (int64_t)NR * 4 * 64;  // one part
+    // eight parts' loads in flight at a time; the sums still run in part order
+    int k = 0;
+    for (; k + 8 <= np; k += 8) {
+      T v[8][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc[e] += pp[(c * 4 + e) * 64 + lane];
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[j][e] = pp[(k + j) * ps + e * 64];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] += v[j][e];
     }
+    for (; k < np; ++k)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] += pp[k * ps + e * 64];
     pot[(int64_t)c * N + o] = acc[0] * scale;
     if (grad) {
       T *gp = grad + ((int64_t)c * N + o) * 3;
