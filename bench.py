@@ -419,6 +419,7 @@ def _csv_rows(d, suffix):
 
 def _kname(name: str) -> str:
     """Kernel name without its argument list."""
+    name = name.replace("(anonymous namespace)", "{anon}")
     depth = 0
     for i, ch in enumerate(name):
         if ch == "<":
