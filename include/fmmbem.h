@@ -198,6 +198,10 @@ int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const v
  *   gemm_lat      translation GEMM launches of at most this many workgroups
  *                 (0..1<<20) run the latency-bound form (all operands of a
  *                 workgroup fetched at once); 0: never; default 512
+ *   gemm_chain    pair evaluations: 1 runs the M2M levels of both plans in
+ *                 one launch and the L2L levels in another (tasks in
+ *                 dependency order, each level waiting on counters of the
+ *                 one before, bounded waits); 0: one launch per level
  * FMM_EINVAL for values out of range. */
 typedef struct {
   int32_t tile_split2;
@@ -210,6 +214,7 @@ typedef struct {
   int32_t pair_order;
   int32_t near_lds;
   int32_t gemm_lat;
+  int32_t gemm_chain;
 } fmm_tuning_t;
 int fmm_set_tuning(const fmm_tuning_t *tuning);
 int fmm_get_tuning(fmm_tuning_t *tuning);
@@ -239,6 +244,9 @@ typedef struct {
   double setup_ops_ms;   /* translation operators (FP64 truncated SVDs and products), upload */
   int32_t tree_on_device; /* 1: octree and lists built by device kernels */
   int32_t tree_shared;    /* 1: tree, lists and leaf items taken from a live plan on the same points */
+  int32_t chain_timeouts; /* nonzero: a wait of a chained launch (gemm_chain) led by this plan hit its
+                             bound, and the evaluation it belonged to is not valid (never expected:
+                             the chain drains by construction; fmm_info synchronises to read it) */
 } fmm_info_t;
 
 int fmm_info(const fmm_plan *plan, fmm_info_t *out);

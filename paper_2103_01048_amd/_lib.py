@@ -39,7 +39,7 @@ class FmmInfo(ctypes.Structure):
         ("n_far_interactions", ctypes.c_int64), ("rank_up", ctypes.c_int32), ("rank_down", ctypes.c_int32),
         ("setup_sort_ms", ctypes.c_double), ("setup_tree_ms", ctypes.c_double), ("setup_lists_ms", ctypes.c_double),
         ("setup_items_ms", ctypes.c_double), ("setup_ops_ms", ctypes.c_double), ("tree_on_device", ctypes.c_int32),
-        ("tree_shared", ctypes.c_int32),
+        ("tree_shared", ctypes.c_int32), ("chain_timeouts", ctypes.c_int32),
     ]
 
 
@@ -49,6 +49,7 @@ class FmmTuning(ctypes.Structure):
         ("work_cap_div", ctypes.c_int32), ("far_weight", ctypes.c_double), ("gemm_rbw", ctypes.c_int32),
         ("m2l_factored", ctypes.c_int32), ("pair_order", ctypes.c_int32),
         ("near_lds", ctypes.c_int32), ("gemm_lat", ctypes.c_int32),
+        ("gemm_chain", ctypes.c_int32),
     ]
 
 

@@ -19,6 +19,9 @@ Tunables (fmm_set_tuning; defaults in DEFAULTS):
                               evaluation (caps its waves per compute unit)
   gemm_lat                    translation GEMM launches of at most this many
                               workgroups use the latency-bound kernel
+  gemm_chain                  the M2M levels, and the L2L levels, of a pair
+                              evaluation in one launch each (not searched:
+                              slower on every workload measured)
 
 The search is coordinate descent: ncrit first (with the defaults), then the
 work cap, the tile splits, the surface weight and the GEMM row blocks, each
@@ -43,7 +46,8 @@ from .fmm import FMMPlan, eval_pair
 
 DEFAULTS = {"tile_split2": 32, "tile_split4": 16, "work_cap_min": 512, "work_cap_div": 16384, "far_weight": 1.15,
             "gemm_rbw": 0, "m2l_factored": 0, "pair_order": 0,
-            "near_lds": 0, "gemm_lat": 512}
+            "near_lds": 0, "gemm_lat": 512,
+            "gemm_chain": 0}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2103_01048_amd", "tuning.json")
 
 STAGES = (

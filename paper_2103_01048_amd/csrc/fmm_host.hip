@@ -65,6 +65,15 @@ static int dev_alloc(fmm_plan *P, void **ptr, size_t bytes) {
   return FMM_OK;
 }
 
+// A device copy of `bytes` host bytes owned by plan P (freed by fmm_free);
+// with h null, an uninitialised allocation.
+int plan_upload(fmm_plan *P, void **ptr, const void *h, size_t bytes) {
+  int rc = dev_alloc(P, ptr, bytes);
+  if (rc) return rc;
+  if (bytes && h) FMM_HIP_TRY(hipMemcpy(*ptr, h, bytes, hipMemcpyHostToDevice));
+  return FMM_OK;
+}
+
 template <typename V>
 static int upload(fmm_plan *P, void **ptr, const std::vector<V> &h) {
   int rc = dev_alloc(P, ptr, h.size() * sizeof(V));
@@ -1241,7 +1250,7 @@ void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
 
 // Tunables for plans set up from now on (fmm_set_tuning).
 static std::mutex g_tune_mu;
-static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 0, 0, 512};
+static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 0, 0, 512, 0};
 
 // Live plans whose tree later plans on the same points may share.
 static std::mutex g_tree_mu;
@@ -1614,6 +1623,12 @@ int fmm_info(const fmm_plan *P, fmm_info_t *o) {
   o->setup_ops_ms = P->setup_split[4];
   o->tree_on_device = P->tree_on_device;
   o->tree_shared = P->tree_shared;
+  if (P->chain_ctr && P->chain_ctr_n > 0) {
+    int32_t e = 0;
+    FMM_HIP_TRY(hipDeviceSynchronize());
+    FMM_HIP_TRY(hipMemcpy(&e, P->chain_ctr + P->chain_ctr_n - 1, sizeof(e), hipMemcpyDeviceToHost));
+    o->chain_timeouts = e;
+  }
   for (size_t l = 0; l < P->rank_u.size(); ++l) o->rank_up = std::max(o->rank_up, (int32_t)P->rank_u[l]);
   for (size_t l = 0; l < P->rank_d.size(); ++l) o->rank_down = std::max(o->rank_down, (int32_t)P->rank_d[l]);
   return FMM_OK;
@@ -1656,7 +1671,7 @@ int fmm_set_tuning(const fmm_tuning_t *t) {
       t->work_cap_min < 1 || t->work_cap_div < 1 || !(t->far_weight > 0.0) || !std::isfinite(t->far_weight) ||
       t->gemm_rbw < 0 || t->gemm_rbw > 8 || t->m2l_factored < 0 || t->m2l_factored > 1 || t->pair_order < 0 ||
       t->pair_order > 2 || t->near_lds < 0 || t->near_lds > 65536 ||
-      t->gemm_lat < 0 || t->gemm_lat > (1 << 20)) {
+      t->gemm_lat < 0 || t->gemm_lat > (1 << 20) || t->gemm_chain < 0 || t->gemm_chain > 1) {
     set_error("fmm_set_tuning: value out of range");
     return FMM_EINVAL;
   }

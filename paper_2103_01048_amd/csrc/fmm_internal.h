@@ -21,6 +21,7 @@ constexpr int MAX_NR = 4;     // density columns handled by one kernel pass
 constexpr double ALPHA_UE = 1.05, ALPHA_UC = 2.95, ALPHA_DE = 2.95, ALPHA_DC = 1.05;
 
 void set_error(const std::string &msg);
+int plan_upload(fmm_plan *P, void **ptr, const void *h, size_t bytes);
 hipEvent_t prof_begin(fmm_plan *P, int phase, hipStream_t s);
 void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s);
 void pinv_tsvd(int n, const double *A, double tau, double *out);
@@ -87,6 +88,21 @@ struct GemmBatch {
 
 // Per-nrhs-chunk task lists.  Row indices in the work arrays are
 // box * nr + r, so the lists depend on nr.
+// One task of a chained launch (k_chain): kind 0 runs GEMM task idx >> 4,
+// row group idx & 15, of GemmArgs arg; kind 1 sums the M2M slots of the
+// four boxes idx .. idx + 3 of ReduceArgs arg.  Tasks of phase p > 0 start
+// once every task of phase p - 1 has finished.
+struct ChainTask {
+  int32_t kind, phase, arg, idx;
+};
+
+// Device task list of a chained launch and what it was built from.
+struct Chain {
+  std::vector<const void *> key;  // plans, column count and work arrays it was built for
+  int ntask = 0, nphase = 0, kch = 0;
+  void *tasks = nullptr, *gargs = nullptr, *rargs = nullptr, *need = nullptr;
+};
+
 struct PassLists {
   int nr = 0;
   // per level l (index l, levels >= 2), in singular coordinates c = U^T chk
@@ -210,6 +226,12 @@ struct fmm_plan {
   void *pair_acc = nullptr;
   size_t pair_acc_bytes = 0;
   void *dips = nullptr;             // monopole + dipole sources: dipole records in Morton order
+  // chained launches of a pair evaluation led by this plan: the M2M levels
+  // and the L2L levels of both plans, each in one launch; counters (ticket,
+  // finished tasks per phase, error flag) cleared before each launch
+  fmm::Chain chain_up, chain_down;
+  int32_t *chain_ctr = nullptr;
+  int chain_ctr_n = 0;
   uint64_t coord_hash = 0;          // checksum of the FP64 input coordinates (per molecule, chained)
   uint64_t tree_hash = 0;           // fingerprint of coordinates, points, boxes and leaf items
   void *adj = nullptr;              // adjoint scratch: psi and grad psi
@@ -218,7 +240,7 @@ struct fmm_plan {
   double setup_ms = 0;
   double setup_split[5] = {0, 0, 0, 0, 0};  // sort, tree, lists, items, operators (ms)
   int tree_on_device = 0, tree_shared = 0;
-  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0, 0, 0, 0, 512};  // tunables in force at setup
+  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0, 0, 0, 0, 512, 0};  // tunables in force at setup
   std::vector<void *> allocs;      // everything to free
   std::shared_ptr<fmm::SharedAllocs> tree_mem;  // the tree's device buffers (shared with plans on the same points)
   std::shared_ptr<fmm::SharedAllocs> ops_mem;   // translation operators (shared with plans of the same kernel on the same tree)

@@ -444,12 +444,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g0, GemmArgs g1) {
 // waits for memory once instead of once per chunk.  The MFMAs run in the
 // same k order as k_gemm, so the results are the same bit for bit.
 template <typename T, int KCH>
-__global__ __launch_bounds__(256) void k_gemm_lat(GemmArgs g0, GemmArgs g1) {
-  __builtin_amdgcn_s_setprio(3);
+__device__ __forceinline__ void gemm_lat_tile(const GemmArgs &g, int task, int yg) {
   using V4 = typename Vec4<T>::type;
-  GemmArgs g;
-  int task;
-  if (!gemm_pick(g0, g1, g, task)) return;
   const GemmTask tk = g.tasks[task];
   const int S = g.S, seg = g.seg, KQ = g.KQ, ld = g.ldx, ldy = g.ldy, mode = g.mode;
   const int nrb = tk.nrb > 0 ? min(tk.nrb, g.nrb) : g.nrb;
@@ -462,7 +458,7 @@ __global__ __launch_bounds__(256) void k_gemm_lat(GemmArgs g0, GemmArgs g1) {
   __shared__ T Bs[64 * KCH][GEMM_NT + 1];
   __shared__ int32_t s_src[GEMM_NT * 8];
   const int tid = threadIdx.x, lane = tid & 63;
-  const int rb = (int)blockIdx.y * 4 + (tid >> 6);  // this wave's row block
+  const int rb = yg * 4 + (tid >> 6);  // this wave's row block
   const bool live = rb < nrb;
   const T *__restrict__ A = (const T *)g.pool + (int64_t)tk.mat * g.mstride + ((int64_t)rb * KQ * 64 + lane) * 4;
   V4 a[4 * KCH];
@@ -528,6 +524,15 @@ __global__ __launch_bounds__(256) void k_gemm_lat(GemmArgs g0, GemmArgs g1) {
       atomicAdd(y + 0, r[0]); atomicAdd(y + 1, r[1]); atomicAdd(y + 2, r[2]); atomicAdd(y + 3, r[3]);
     }
   }
+}
+
+template <typename T, int KCH>
+__global__ __launch_bounds__(256) void k_gemm_lat(GemmArgs g0, GemmArgs g1) {
+  __builtin_amdgcn_s_setprio(3);
+  GemmArgs g;
+  int task;
+  if (!gemm_pick(g0, g1, g, task)) return;
+  gemm_lat_tile<T, KCH>(g, task, (int)blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1565,25 +1570,17 @@ __global__ void k_fill_zero(T *__restrict__ y, int64_t n) {
 // leading dimension ldp, rows of y leading dimension ld.
 // blockIdx.y = 1 selects a second plan's (pairbuf, y, ldp, rows) on the same
 // tree (pair evaluation).
+// One box's sum (one wave, lane = 0..63).
 template <typename T>
-__global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ tgt, const int32_t *__restrict__ off,
-                                                    const int32_t *__restrict__ pairs, const T *__restrict__ pairbuf0,
-                                                    T *__restrict__ y0, int nr, int ld, int ldp0, int rows0,
-                                                    const T *__restrict__ pairbuf1, T *__restrict__ y1, int ldp1,
-                                                    int rows1, const int32_t *__restrict__ brows0,
-                                                    const int32_t *__restrict__ brows1, const T *__restrict__ add0,
-                                                    const T *__restrict__ add1) {
-  __builtin_amdgcn_s_setprio(3);
+__device__ __forceinline__ void pair_reduce_box(int slot, int lane, const int32_t *__restrict__ tgt,
+                                                const int32_t *__restrict__ off, const int32_t *__restrict__ pairs,
+                                                const T *__restrict__ pairbuf, T *__restrict__ y, int nr, int ld,
+                                                int ldp, int rows, const int32_t *__restrict__ brows,
+                                                const T *__restrict__ add_) {
   using V4 = typename Vec4<T>::type;
-  const bool second = blockIdx.y != 0;
-  const T *__restrict__ pairbuf = second ? pairbuf1 : pairbuf0;
-  T *__restrict__ y = second ? y1 : y0;
-  const int ldp = second ? ldp1 : ldp0, rows = second ? rows1 : rows0;
-  const int32_t *__restrict__ brows = second ? brows1 : brows0;
   // add (may be null): a per-box array added after the sum (the M2L sums
   // take the P2L projections this way)
-  const V4 *__restrict__ add = reinterpret_cast<const V4 *>(second ? add1 : add0);
-  const int slot = blockIdx.x;
+  const V4 *__restrict__ add = reinterpret_cast<const V4 *>(add_);
   const int b = tgt[slot];
   const int p0 = off[slot], p1 = off[slot + 1];
   const int rq = rows >> 2, lq = ld >> 2, pq = ldp >> 2;
@@ -1591,7 +1588,7 @@ __global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ 
   // above it, up to `rows`, are set to zero
   const int bq = brows ? min(rq, brows[b] >> 2) : rq;
   const V4 *__restrict__ pb = reinterpret_cast<const V4 *>(pairbuf);
-  for (int e = threadIdx.x; e < nr * rq; e += 64) {
+  for (int e = lane; e < nr * rq; e += 64) {
     const int r = e / rq, i = e - r * rq;
     if (i >= bq) {
       reinterpret_cast<V4 *>(y)[((int64_t)b * nr + r) * lq + i] =
@@ -1614,6 +1611,94 @@ __global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ 
     V4 sum = (a0 + a1) + (a2 + a3);
     if (add) sum = sum + add[((int64_t)b * nr + r) * lq + i];
     reinterpret_cast<V4 *>(y)[((int64_t)b * nr + r) * lq + i] = sum;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_pair_reduce(const int32_t *__restrict__ tgt, const int32_t *__restrict__ off,
+                                                    const int32_t *__restrict__ pairs, const T *__restrict__ pairbuf0,
+                                                    T *__restrict__ y0, int nr, int ld, int ldp0, int rows0,
+                                                    const T *__restrict__ pairbuf1, T *__restrict__ y1, int ldp1,
+                                                    int rows1, const int32_t *__restrict__ brows0,
+                                                    const int32_t *__restrict__ brows1, const T *__restrict__ add0,
+                                                    const T *__restrict__ add1) {
+  __builtin_amdgcn_s_setprio(3);
+  const bool second = blockIdx.y != 0;
+  pair_reduce_box<T>((int)blockIdx.x, (int)threadIdx.x, tgt, off, pairs, second ? pairbuf1 : pairbuf0,
+                     second ? y1 : y0, nr, ld, second ? ldp1 : ldp0, second ? rows1 : rows0,
+                     second ? brows1 : brows0, second ? add1 : add0);
+}
+
+// Arguments of one plan's M2M sums at one level, for a chained launch.
+template <typename T>
+struct ReduceArgs {
+  const int32_t *tgt, *off, *pairs;
+  const T *pairbuf;
+  T *y;
+  int nr, ld, ldp, rows, nbox;
+};
+
+// Chained launch: tasks in dependency order (phase by phase); a workgroup
+// takes the next task by an atomic ticket and, for a task of phase p > 0,
+// first waits until every task of phase p - 1 has finished (ctr[p] counts
+// them; thread 0 polls with a bounded number of sleeps and, past the bound,
+// sets *err and goes on).  Tickets are taken in task order by workgroups
+// that are already running, and a workgroup waits only on tasks with smaller
+// tickets, so the chain drains whatever the number of resident workgroups.
+// Results and stores of a task are made visible (release fence) before its
+// phase counter is raised, and a waiting workgroup fences (acquire) before
+// it reads them; data written in the launch is read with vector loads only.
+template <typename T, int KCH>
+__global__ __launch_bounds__(256) void k_chain(const ChainTask *__restrict__ tasks, int ntask,
+                                               const GemmArgs *__restrict__ ga, const ReduceArgs<T> *__restrict__ ra,
+                                               const int32_t *__restrict__ need, int32_t *ctr, int32_t *err,
+                                               unsigned spin_limit) {
+  __builtin_amdgcn_s_setprio(3);
+  __shared__ int s_ticket;
+  const int tid = threadIdx.x;
+  // Control flow: the ticket goes through a scalar register, so the exit
+  // test and every branch on the task are uniform, and each thread-0 block
+  // is followed by a barrier before anything else, so no path from the end
+  // of one task to the next skips a barrier (all threads reach every barrier
+  // together; a loop whose latch could be reached around the thread-0 block
+  // compiles into lanes that retry the old ticket forever).
+  if (tid == 0) s_ticket = atomicAdd(&ctr[0], 1);
+  __syncthreads();
+  for (;;) {
+    const int t = __builtin_amdgcn_readfirstlane(s_ticket);
+    if (t >= ntask) break;
+    const ChainTask tk = tasks[t];
+    if (tk.phase > 0) {
+      if (tid == 0) {
+        const int want = need[tk.phase - 1];
+        unsigned n = 0;
+        while (__hip_atomic_load(&ctr[tk.phase], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < want) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++n > spin_limit) {
+            atomicOr(err, 1);
+            break;
+          }
+        }
+      }
+      __syncthreads();
+      __threadfence();
+    }
+    if (tk.kind == 0) {
+      gemm_lat_tile<T, KCH>(ga[tk.arg], tk.idx >> 4, tk.idx & 15);
+    } else {
+      const ReduceArgs<T> r = ra[tk.arg];
+      const int slot = tk.idx + (tid >> 6);
+      if (slot < r.nbox)
+        pair_reduce_box<T>(slot, tid & 63, r.tgt, r.off, r.pairs, r.pairbuf, r.y, r.nr, r.ld, r.ldp, r.rows,
+                           (const int32_t *)nullptr, (const T *)nullptr);
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      atomicAdd(&ctr[1 + tk.phase], 1);
+      s_ticket = atomicAdd(&ctr[0], 1);
+    }
+    __syncthreads();
   }
 }
 
@@ -1863,6 +1948,121 @@ static int pair_p2l(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips) {
 // surface-evaluation pass P2M (VALU work) comes first and `surf_done` is
 // recorded after it; the GEMM passes follow.  P2L runs on the caller's
 // stream (pair_off_chain).
+// Chained launches of a pair evaluation (tunable gemm_chain): the M2M
+// levels of both plans (GEMM into the child slots, then the sums per parent,
+// level by level) in one k_chain launch, and the L2L levels in another.
+constexpr unsigned CHAIN_SPIN_LIMIT = 1u << 18;  // polls (a memory round trip and ~128 cycles each)
+
+template <typename T, int NR>
+static int build_chain(fmm_plan *A, fmm_plan *B, bool up, Chain &C) {
+  const PassLists &LA = A->lists_by_nr[NR], &LB = B->lists_by_nr[NR];
+  const DevTree &D = A->dt;
+  std::vector<ChainTask> tasks;
+  std::vector<GemmArgs> ga;
+  std::vector<ReduceArgs<T>> ra;
+  std::vector<int32_t> need;
+  const int kmax = std::is_same<T, double>::value ? 2 : 5;
+  int kch = 1, phase = 0;
+  bool fits = true;
+  auto add_gemm = [&](fmm_plan *P, const GemmBatch &bt, const void *X, void *Y) {
+    if (!bt.ntask) return;
+    const GemmArgs g = gemm_args(P, bt, X, Y);
+    const int kc = (g.klen + 63) / 64;
+    if (kc > kmax || bt.pool == 2 || g.nrb > 64) fits = false;
+    kch = std::max(kch, kc);
+    const int id = (int)ga.size();
+    ga.push_back(g);
+    const int gy = (g.nrb + 3) / 4;
+    for (int t = 0; t < g.ntask; ++t)
+      for (int y = 0; y < gy; ++y) tasks.push_back({0, phase, id, t * 16 + y});
+  };
+  auto end_phase = [&]() {
+    int n = 0;
+    for (const ChainTask &t : tasks) n += t.phase == phase;
+    if (n == 0) return;
+    need.push_back(n);
+    ++phase;
+  };
+  if (up) {
+    for (int l = D.maxlevel - 1; l >= 2; --l) {
+      if (!LA.m2m[l].ntask) continue;
+      add_gemm(A, LA.m2m[l], A->cu, A->mslot);
+      add_gemm(B, LB.m2m[l], B->cu, B->mslot);
+      end_phase();
+      const fmm_plan *PP[2] = {A, B};
+      const PassLists *LL[2] = {&LA, &LB};
+      for (int k = 0; k < 2; ++k) {
+        const int id = (int)ra.size();
+        ra.push_back({D.m2m_tgt[l], D.m2m_off[l], D.m2m_kid[l], (const T *)PP[k]->mslot, (T *)PP[k]->cu, NR, A->ld,
+                      A->ld, LL[k]->m2m[l].nrb * 16, D.m2m_n[l]});
+        for (int b = 0; b < D.m2m_n[l]; b += 4) tasks.push_back({1, phase, id, b});
+      }
+      end_phase();
+    }
+  } else {
+    for (int l = 3; l <= D.maxlevel; ++l) {
+      if (!LA.l2l[l].ntask) continue;
+      add_gemm(A, LA.l2l[l], A->yd, A->yd);
+      add_gemm(B, LB.l2l[l], B->yd, B->yd);
+      end_phase();
+    }
+  }
+  C = Chain();
+  if (!fits || tasks.empty()) return FMM_OK;  // ntask = 0: the per-level launches
+  int rc;
+  if ((rc = plan_upload(A, &C.tasks, tasks.data(), tasks.size() * sizeof(ChainTask)))) return rc;
+  if ((rc = plan_upload(A, &C.gargs, ga.data(), std::max<size_t>(1, ga.size()) * sizeof(GemmArgs)))) return rc;
+  if ((rc = plan_upload(A, &C.rargs, ra.data(), std::max<size_t>(1, ra.size()) * sizeof(ReduceArgs<T>)))) return rc;
+  if ((rc = plan_upload(A, &C.need, need.data(), std::max<size_t>(1, need.size()) * sizeof(int32_t)))) return rc;
+  C.ntask = (int)tasks.size();
+  C.nphase = phase;
+  C.kch = kch;
+  return FMM_OK;
+}
+
+// Both chains current for (A, B, NR) and a counter array for them (ticket
+// and phase counters of each chain, then the error flag).
+template <typename T, int NR>
+static int ensure_chains(fmm_plan *A, fmm_plan *B) {
+  const std::vector<const void *> key = {B, (const void *)(intptr_t)NR, A->cu, A->mslot, A->yd, B->cu, B->mslot, B->yd};
+  int rc;
+  if (A->chain_up.key != key) {
+    if ((rc = build_chain<T, NR>(A, B, true, A->chain_up))) return rc;
+    if ((rc = build_chain<T, NR>(A, B, false, A->chain_down))) return rc;
+    A->chain_up.key = A->chain_down.key = key;
+  }
+  const int n = 2 + A->chain_up.nphase + A->chain_down.nphase + 1;
+  if (A->chain_ctr_n < n) {
+    std::vector<int32_t> z(n, 0);
+    if ((rc = plan_upload(A, (void **)&A->chain_ctr, z.data(), z.size() * sizeof(int32_t)))) return rc;
+    A->chain_ctr_n = n;
+  }
+  return FMM_OK;
+}
+
+template <typename T>
+static int launch_chain(const Chain &C, int32_t *ctr, int32_t *err, hipStream_t s) {
+  const unsigned grid = (unsigned)std::min(C.ntask, 1024);
+  const ChainTask *t = (const ChainTask *)C.tasks;
+  const GemmArgs *g = (const GemmArgs *)C.gargs;
+  const ReduceArgs<T> *r = (const ReduceArgs<T> *)C.rargs;
+  const int32_t *nd = (const int32_t *)C.need;
+  if constexpr (std::is_same<T, double>::value) {
+    if (C.kch <= 1) hipLaunchKernelGGL((k_chain<T, 1>), dim3(grid), dim3(256), 0, s, t, C.ntask, g, r, nd, ctr, err, CHAIN_SPIN_LIMIT);
+    else hipLaunchKernelGGL((k_chain<T, 2>), dim3(grid), dim3(256), 0, s, t, C.ntask, g, r, nd, ctr, err, CHAIN_SPIN_LIMIT);
+  } else {
+    switch (C.kch) {
+      case 1: hipLaunchKernelGGL((k_chain<T, 1>), dim3(grid), dim3(256), 0, s, t, C.ntask, g, r, nd, ctr, err, CHAIN_SPIN_LIMIT); break;
+      case 2: hipLaunchKernelGGL((k_chain<T, 2>), dim3(grid), dim3(256), 0, s, t, C.ntask, g, r, nd, ctr, err, CHAIN_SPIN_LIMIT); break;
+      case 3: hipLaunchKernelGGL((k_chain<T, 3>), dim3(grid), dim3(256), 0, s, t, C.ntask, g, r, nd, ctr, err, CHAIN_SPIN_LIMIT); break;
+      case 4: hipLaunchKernelGGL((k_chain<T, 4>), dim3(grid), dim3(256), 0, s, t, C.ntask, g, r, nd, ctr, err, CHAIN_SPIN_LIMIT); break;
+      default: hipLaunchKernelGGL((k_chain<T, 5>), dim3(grid), dim3(256), 0, s, t, C.ntask, g, r, nd, ctr, err, CHAIN_SPIN_LIMIT); break;
+    }
+  }
+  FMM_HIP_TRY(hipGetLastError());
+  return FMM_OK;
+}
+
 template <typename T, int NR>
 static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, hipEvent_t surf_done,
                             hipEvent_t up_done, const T *dips = nullptr) {
@@ -1876,8 +2076,17 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, h
   int rc;
   hipEvent_t ev;
   if (D.maxlevel < 2) return FMM_OK;
+  // chained M2M and L2L launches (built for this pair and column count)
+  const bool chain = A->tune.gemm_chain && A->chain_ctr && !A->chain_up.key.empty() && A->chain_up.key[0] == B &&
+                     A->chain_up.key[1] == (const void *)(intptr_t)NR;
+  int32_t *ctr_up = A->chain_ctr, *ctr_down = A->chain_ctr + 1 + A->chain_up.nphase,
+          *chain_err = A->chain_ctr + A->chain_ctr_n - 1;
   if (part == 2) goto down;
   {
+  if (chain) {
+    hipLaunchKernelGGL(k_fill_zero<int32_t>, dim3(1), dim3(256), 0, s, A->chain_ctr, (int64_t)A->chain_ctr_n - 1);
+    FMM_HIP_TRY(hipGetLastError());
+  }
   const unsigned sthreads = (unsigned)(64 * ((A->nsurf + 63) / 64));
   ev = prof_begin(A, FMM_PHASE_P2M, s);
   if (A->p2m_count > 0 && dips)
@@ -1897,7 +2106,12 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, h
   if ((rc = launch_gemm2<T>(A, LA.ut_u_all, W(A->chku), W(A->cu), B, &LB.ut_u_all, W(B->chku), W(B->cu), s)))
     return rc;
   prof_end(A, FMM_PHASE_UC2E, ev, s);
-  for (int l = D.maxlevel - 1; l >= 2; --l) {
+  if (chain && A->chain_up.ntask) {
+    ev = prof_begin(A, FMM_PHASE_M2M, s);
+    if ((rc = launch_chain<T>(A->chain_up, ctr_up, chain_err, s))) return rc;
+    prof_end(A, FMM_PHASE_M2M, ev, s);
+  }
+  for (int l = D.maxlevel - 1; l >= 2 && !(chain && A->chain_up.ntask); --l) {
     if (!LA.m2m[l].ntask) continue;
     ev = prof_begin(A, FMM_PHASE_M2M, s);
     if ((rc = launch_gemm2<T>(A, LA.m2m[l], W(A->cu), W(A->mslot), B, &LB.m2m[l], W(B->cu), W(B->mslot), s)))
@@ -1938,7 +2152,12 @@ down:
                        (const int32_t *)B->d_m2l_rows, (const T *)A->ydx, (const T *)B->ydx);
   FMM_HIP_TRY(hipGetLastError());
   prof_end(A, FMM_PHASE_M2L_SUM, ev, s);
-  for (int l = 3; l <= D.maxlevel; ++l) {
+  if (chain && A->chain_down.ntask) {
+    ev = prof_begin(A, FMM_PHASE_L2L, s);
+    if ((rc = launch_chain<T>(A->chain_down, ctr_down, chain_err, s))) return rc;
+    prof_end(A, FMM_PHASE_L2L, ev, s);
+  }
+  for (int l = 3; l <= D.maxlevel && !(chain && A->chain_down.ntask); ++l) {
     if (!LA.l2l[l].ntask) continue;
     ev = prof_begin(A, FMM_PHASE_L2L, s);
     if ((rc = launch_gemm2<T>(A, LA.l2l[l], W(A->yd), W(A->yd), B, &LB.l2l[l], W(B->yd), W(B->yd), s))) return rc;
@@ -2107,6 +2326,7 @@ static int eval_pair_chunk(fmm_plan *A, fmm_plan *B, const T *q, T *pot_a, T *gr
     prof_end(A, FMM_PHASE_NEAR, e, s);
     return FMM_OK;
   };
+  if (A->tune.gemm_chain && D.maxlevel >= 2 && (rc = ensure_chains<T, NR>(A, B))) return rc;
   if ((rc = pair_fork_join<T, NR>(A, B, s, (const T *)nullptr, near))) return rc;
   hipEvent_t ev = prof_begin(A, FMM_PHASE_FAR, s);
   if (D.nitems > 0)
@@ -2198,6 +2418,7 @@ static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip
     prof_end(A, FMM_PHASE_NEAR, e, s);
     return FMM_OK;
   };
+  if (A->tune.gemm_chain && D.maxlevel >= 2 && (rc = ensure_chains<T, 1>(A, B))) return rc;
   if ((rc = pair_fork_join<T, 1>(A, B, s, (const T *)dips, near))) return rc;
   ev = prof_begin(A, FMM_PHASE_FAR, s);
   if (D.nitems > 0 && grad)

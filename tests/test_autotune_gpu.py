@@ -122,3 +122,37 @@ def test_factored_m2l(precision, tol, tol_dense):
         assert D.rel_l2(pf[rows], p0) < tol and D.rel_l2(gf[rows], g0) < tol
         assert D.rel_l2(pf, pd) < tol_dense and D.rel_l2(gf, gd) < tol_dense
     assert D.rel_l2(alone[0].double().cpu().numpy(), outs_f[1][0].double().cpu().numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("precision,p", [("bf16x3", 6), ("fp32", 8), ("fp64", 4)])
+def test_chained_level_launches_equal_per_level_launches(precision, p):
+    """The M2M levels and the L2L levels of a pair evaluation in one chained
+    launch each (gemm_chain): the same GEMM tiles and sums in the same order
+    as one launch per level, so the results are equal bit for bit, on every
+    repeat; no chained wait hits its bound."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, autotune as at, eval_pair
+    x = _cloud()
+    q = np.random.default_rng(135).standard_normal(len(x))
+    xt = torch.tensor(x, device="cuda")
+    qt = torch.tensor(q, device="cuda", dtype=torch.float64 if precision == "fp64" else torch.float32)
+    mk = lambda k: FMMPlan(xt, kernel=k, kappa=KAPPA, p=p, ncrit=32, precision=precision)
+    per_level = [mk("laplace"), mk("yukawa")]
+    with at.tuning(gemm_chain=1):
+        chained = [mk("laplace"), mk("yukawa")]
+    print(f"[chain] {precision} p={p} levels {per_level[0].info()['max_level']}", flush=True)
+    ref = [t.cpu().numpy() for o in eval_pair(per_level[0], per_level[1], qt) for t in o]
+    for _ in range(3):
+        got = [t.cpu().numpy() for o in eval_pair(chained[0], chained[1], qt) for t in o]
+        for r, g in zip(ref, got):
+            assert np.array_equal(r, g)
+    assert chained[0].info()["chain_timeouts"] == 0
+    # one launch each for the M2M and the L2L levels (the per-level path has
+    # one per level)
+    for pls, one in ((chained, True), (per_level, False)):
+        pls[0].set_profiling(True)
+        pls[0].phase_times()
+        eval_pair(pls[0], pls[1], qt)
+        ph = pls[0].phase_times()
+        pls[0].set_profiling(False)
+        assert (ph["m2m"][1] == 1 and ph["l2l"][1] == 1) == one, ph
