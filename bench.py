@@ -196,10 +196,19 @@ def run_batch(args):
     X, Q = np.concatenate(xs), np.concatenate(qs)
     n = len(X)
     prec = args.precision
-    ncrit = args.ncrit or 128
     dt = torch.float32
     xt = torch.tensor(X, device=dev)
     qt = torch.tensor(Q, dtype=dt, device=dev)
+    tuned = None
+    if args.ncrit:
+        ncrit = args.ncrit
+    else:
+        from paper_2103_01048_amd import autotune as at
+        res = at.autotune(xt, p=P_ORDER, precision=prec, kappa=KAPPA, q=qt, cache_path=None, offsets=off,
+                          ncrit_candidates=(64, 96, 128, 160, 192),
+                          log=lambda m: print("# autotune " + m, file=sys.stderr, flush=True))
+        ncrit = at.apply(res)
+        tuned = {"ncrit": ncrit, "tuning": res["tuning"], "ms": res["ms"], "trials": len(res["trials"])}
     batched = [FMMPlan(xt, kernel=k, kappa=KAPPA, p=P_ORDER, ncrit=ncrit, precision=prec, offsets=off)
                for k in ("laplace", "yukawa")]
     separate = []
@@ -248,7 +257,7 @@ def run_batch(args):
                                        "launches": "2 fmm_eval calls on the batched plans"},
             "separate_plans": {"value": round(n / t_s / 1e6, 3), "ms_per_step": round(t_s * 1e3, 4),
                                "launches": "2 x 64 fmm_eval calls"},
-            "worst_sampled_molecule_rel_err": errors}
+            "worst_sampled_molecule_rel_err": errors, "autotune": tuned}
     print(json.dumps(line), flush=True)
 
 
@@ -580,7 +589,7 @@ def main():
     else:
         from paper_2103_01048_amd import autotune as at
         res = at.autotune(xt, p=P_ORDER, precision=args.precision, kappa=KAPPA, q=qd[torch.float32],
-                          cache_path=None, steps=5, warmup=2,
+                          cache_path=None,
                           log=lambda m: print("# autotune " + m, file=sys.stderr, flush=True))
         ncrit = at.apply(res)
         tuned = {"ncrit": ncrit, "tuning": res["tuning"], "ms": res["ms"], "trials": len(res["trials"]),

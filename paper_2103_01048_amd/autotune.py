@@ -92,19 +92,21 @@ def tuning(**kw):
         set_tuning(**old)
 
 
-def cache_key(n: int, p: int, precision: str, device=None) -> str:
+def cache_key(n: int, p: int, precision: str, device=None, nmol: int = 1) -> str:
     name = torch.cuda.get_device_name(device) if torch.cuda.is_available() else "cpu"
-    return f"{name}|{precision}|p{p}|n~2^{round(math.log2(max(n, 1)))}"
+    batch = f"|mol~2^{round(math.log2(nmol))}" if nmol > 1 else ""
+    return f"{name}|{precision}|p{p}|n~2^{round(math.log2(max(n, 1)))}{batch}"
 
 
-def _time_pair(xt, q, p, ncrit, precision, kappa, steps, warmup, keep):
-    pls = [FMMPlan(xt, kernel=k, kappa=kappa, p=p, ncrit=ncrit, precision=precision) for k in ("laplace", "yukawa")]
+def _time_pair(xt, q, p, ncrit, precision, kappa, steps, warmup, keep, offsets=None, repeats=3):
+    pls = [FMMPlan(xt, kernel=k, kappa=kappa, p=p, ncrit=ncrit, precision=precision, offsets=offsets)
+           for k in ("laplace", "yukawa")]
     keep.extend(pls)  # live plans let later trials share their tree and operators
     for _ in range(warmup):
         eval_pair(pls[0], pls[1], q)
     torch.cuda.synchronize()
     best = float("inf")
-    for _ in range(2):
+    for _ in range(repeats):
         t0 = time.perf_counter()
         for _ in range(steps):
             eval_pair(pls[0], pls[1], q)
@@ -114,14 +116,17 @@ def _time_pair(xt, q, p, ncrit, precision, kappa, steps, warmup, keep):
 
 
 def autotune(points: torch.Tensor, p: int = 8, precision: str = "bf16x3", kappa: float = 0.125,
-             ncrit_candidates=(64, 96, 128, 160, 192, 256), q: torch.Tensor | None = None, steps: int = 5,
+             ncrit_candidates=(64, 96, 128, 160, 192, 256), q: torch.Tensor | None = None, steps: int = 10,
              warmup: int = 2, cache_path: str | None = DEFAULT_CACHE, use_cache: bool = True,
-             log=None) -> dict:
+             log=None, offsets=None, repeats: int = 3) -> dict:
     """Fastest (ncrit, tunables) for pair evaluations on `points` ((N, 3)
-    float64 CUDA tensor).  Returns {"key", "ncrit", "tuning", "ms", "trials",
+    float64 CUDA tensor; with `offsets`, a batch of molecules as FMMPlan
+    takes it).  Each trial is the best of `repeats` timings of `steps` pair
+    evaluations.  Returns {"key", "ncrit", "tuning", "ms", "trials",
     "cached"}; the tunables in force are left unchanged (see apply)."""
     n = int(points.shape[0])
-    key = cache_key(n, p, precision, points.device)
+    nmol = 1 if offsets is None else len(offsets) - 1
+    key = cache_key(n, p, precision, points.device, nmol)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         try:
@@ -143,7 +148,7 @@ def autotune(points: torch.Tensor, p: int = 8, precision: str = "bf16x3", kappa:
         set_tuning(**best_t)
         best_ms, best_nc = float("inf"), None
         for nc in ncrit_candidates:
-            ms = _time_pair(xt, q, p, nc, precision, kappa, steps, warmup, keep)
+            ms = _time_pair(xt, q, p, nc, precision, kappa, steps, warmup, keep, offsets, repeats)
             trials.append({"stage": "ncrit", "ncrit": nc, "tuning": dict(best_t), "ms": round(ms, 4)})
             if log:
                 log(f"ncrit {nc}: {ms:.4f} ms")
@@ -157,7 +162,7 @@ def autotune(points: torch.Tensor, p: int = 8, precision: str = "bf16x3", kappa:
                 if t == best_t:
                     continue
                 set_tuning(**t)
-                ms = _time_pair(xt, q, p, best_nc, precision, kappa, steps, warmup, keep)
+                ms = _time_pair(xt, q, p, best_nc, precision, kappa, steps, warmup, keep, offsets, repeats)
                 trials.append({"stage": stage, "ncrit": best_nc, "tuning": t, "ms": round(ms, 4)})
                 if log:
                     log(f"{stage} {c}: {ms:.4f} ms")
