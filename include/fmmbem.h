@@ -202,6 +202,8 @@ int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const v
  *                 one launch and the L2L levels in another (tasks in
  *                 dependency order, each level waiting on counters of the
  *                 one before, bounded waits); 0: one launch per level
+ *   m2l_cols      bf16x3 M2L columns (V pairs) per workgroup sharing one
+ *                 operator fetch: 64 (default) or 128
  * FMM_EINVAL for values out of range. */
 typedef struct {
   int32_t tile_split2;
@@ -215,6 +217,7 @@ typedef struct {
   int32_t near_lds;
   int32_t gemm_lat;
   int32_t gemm_chain;
+  int32_t m2l_cols;
 } fmm_tuning_t;
 int fmm_set_tuning(const fmm_tuning_t *tuning);
 int fmm_get_tuning(fmm_tuning_t *tuning);

@@ -49,7 +49,7 @@ class FmmTuning(ctypes.Structure):
         ("work_cap_div", ctypes.c_int32), ("far_weight", ctypes.c_double), ("gemm_rbw", ctypes.c_int32),
         ("m2l_factored", ctypes.c_int32), ("pair_order", ctypes.c_int32),
         ("near_lds", ctypes.c_int32), ("gemm_lat", ctypes.c_int32),
-        ("gemm_chain", ctypes.c_int32),
+        ("gemm_chain", ctypes.c_int32), ("m2l_cols", ctypes.c_int32),
     ]
 
 

@@ -19,6 +19,8 @@ Tunables (fmm_set_tuning; defaults in DEFAULTS):
                               evaluation (caps its waves per compute unit)
   gemm_lat                    translation GEMM launches of at most this many
                               workgroups use the latency-bound kernel
+  m2l_cols                    bf16x3 M2L columns per workgroup (64 or 128;
+                              not searched: 128 halves the occupancy)
   gemm_chain                  the M2M levels, and the L2L levels, of a pair
                               evaluation in one launch each (not searched:
                               slower on every workload measured)
@@ -47,7 +49,7 @@ from .fmm import FMMPlan, eval_pair
 DEFAULTS = {"tile_split2": 32, "tile_split4": 16, "work_cap_min": 512, "work_cap_div": 16384, "far_weight": 1.15,
             "gemm_rbw": 0, "m2l_factored": 0, "pair_order": 0,
             "near_lds": 0, "gemm_lat": 512,
-            "gemm_chain": 0}
+            "gemm_chain": 0, "m2l_cols": 64}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2103_01048_amd", "tuning.json")
 
 STAGES = (

@@ -894,14 +894,14 @@ static int upload_lists(fmm_plan *P) {
 
 static void add_columns(GemmBatch &bt, int mat, double alpha, const std::vector<int32_t> &src,
                         const std::vector<int32_t> &dst) {
-  // src has S entries per column; split into tasks of GEMM_NT columns
+  // src has S entries per column; split into tasks of bt.nt columns
   const int nc = (int)dst.size();
   const int base = (int)bt.h_dst.size();
-  for (int c0 = 0; c0 < nc; c0 += GEMM_NT) {
+  for (int c0 = 0; c0 < nc; c0 += bt.nt) {
     GemmTask t;
     t.mat = mat;
     t.col0 = base + c0;
-    t.ncol = std::min(GEMM_NT, nc - c0);
+    t.ncol = std::min(bt.nt, nc - c0);
     t.nrb = 0;
     t.klen = 0;
     t.alpha = alpha;
@@ -972,6 +972,7 @@ int ensure_lists(fmm_plan *P, int nr) {
   if (P->precision == FMM_FP32_BF16X3) {
     L.m2l.pool = 2;
     L.m2l.klen = std::min(((maxru + 31) / 32) * 32, P->bf_kb * 32);
+    if (P->tune.m2l_cols == 2 * GEMM_NT && !P->tune.m2l_factored) L.m2l.nt = 2 * GEMM_NT;
   }
   // factored M2L: R maps upward coordinates (k <= maxru) to intermediates of
   // m2l_ldt values per pair; L reads those rows
@@ -1250,7 +1251,7 @@ void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
 
 // Tunables for plans set up from now on (fmm_set_tuning).
 static std::mutex g_tune_mu;
-static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 0, 0, 512, 0};
+static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 0, 0, 512, 0, 64};
 
 // Live plans whose tree later plans on the same points may share.
 static std::mutex g_tree_mu;
@@ -1671,7 +1672,8 @@ int fmm_set_tuning(const fmm_tuning_t *t) {
       t->work_cap_min < 1 || t->work_cap_div < 1 || !(t->far_weight > 0.0) || !std::isfinite(t->far_weight) ||
       t->gemm_rbw < 0 || t->gemm_rbw > 8 || t->m2l_factored < 0 || t->m2l_factored > 1 || t->pair_order < 0 ||
       t->pair_order > 2 || t->near_lds < 0 || t->near_lds > 65536 ||
-      t->gemm_lat < 0 || t->gemm_lat > (1 << 20) || t->gemm_chain < 0 || t->gemm_chain > 1) {
+      t->gemm_lat < 0 || t->gemm_lat > (1 << 20) || t->gemm_chain < 0 || t->gemm_chain > 1 ||
+      (t->m2l_cols != 64 && t->m2l_cols != 128)) {
     set_error("fmm_set_tuning: value out of range");
     return FMM_EINVAL;
   }

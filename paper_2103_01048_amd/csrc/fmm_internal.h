@@ -61,7 +61,7 @@ struct GemmArgs {
   const int32_t *dst;   // ncols row indices into Y
   const void *X;
   void *Y;
-  int ntask, nrb, klen, ldx, ldy, S, seg, KQ, mode;
+  int ntask, nrb, klen, ldx, ldy, S, seg, KQ, mode, nt;
 };
 
 // A batch of GEMM tasks that can run in one launch (no write conflicts
@@ -76,6 +76,7 @@ struct GemmBatch {
   int mode = GEMM_STORE;
   int pool = 0;                // 0: matrix pool, 1: stacked pool, 2: bf16x3 split pool
   int ldx = 0;                 // row length of X (0: the work-array row length)
+  int nt = GEMM_NT;            // columns per task (the bf16x3 kernel also takes 2 GEMM_NT)
   int ntask = 0;
   GemmTask *d_tasks = nullptr;
   int32_t *d_src = nullptr;    // ncols*S  (row index into X, already * nr + r)
@@ -240,7 +241,7 @@ struct fmm_plan {
   double setup_ms = 0;
   double setup_split[5] = {0, 0, 0, 0, 0};  // sort, tree, lists, items, operators (ms)
   int tree_on_device = 0, tree_shared = 0;
-  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0, 0, 0, 0, 512, 0};  // tunables in force at setup
+  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0, 0, 0, 0, 512, 0, 64};  // tunables in force at setup
   std::vector<void *> allocs;      // everything to free
   std::shared_ptr<fmm::SharedAllocs> tree_mem;  // the tree's device buffers (shared with plans on the same points)
   std::shared_ptr<fmm::SharedAllocs> ops_mem;   // translation operators (shared with plans of the same kernel on the same tree)

@@ -554,7 +554,7 @@ __device__ inline unsigned short f2bf_rne(float x) {
 }
 __device__ inline float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
-template <int RBW>
+template <int RBW, int NT = GEMM_NT>
 __global__ __launch_bounds__(256) void k_gemm_bf3(GemmArgs g0, GemmArgs g1, int KB) {
   __builtin_amdgcn_s_setprio(3);
   GemmArgs g;
@@ -569,20 +569,22 @@ __global__ __launch_bounds__(256) void k_gemm_bf3(GemmArgs g0, GemmArgs g1, int 
   const float *__restrict__ X = (const float *)g.X;
   float *__restrict__ Y = (float *)g.Y;
   const uint4 *__restrict__ A = (const uint4 *)g.pool + (int64_t)tk.mat * g.mstride;
-  __shared__ unsigned short Bh[GEMM_NT][64 + 8], Bl[GEMM_NT][64 + 8];
-  __shared__ int32_t s_src[GEMM_NT];
+  __shared__ unsigned short Bh[NT][64 + 8], Bl[NT][64 + 8];
+  __shared__ int32_t s_src[NT];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = (int)blockIdx.y * 4 + (tid >> 6);
-  if (tid < GEMM_NT) s_src[tid] = tid < tk.ncol ? src[tk.col0 + tid] : -1;
-  floatx4 acc[RBW][4];
+  for (int i = tid; i < NT; i += 256) s_src[i] = i < tk.ncol ? src[tk.col0 + i] : -1;
+  floatx4 acc[RBW][NT / 16];
 #pragma unroll
   for (int r = 0; r < RBW; ++r)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) acc[r][cb] = floatx4{0, 0, 0, 0};
+    for (int cb = 0; cb < NT / 16; ++cb) acc[r][cb] = floatx4{0, 0, 0, 0};
   __syncthreads();
-  const int scol = tid >> 2, spart = (tid & 3) * 16;
+  const int spart = (tid & 3) * 16;
   for (int kc = 0; kc < K; kc += 64) {
-    {
+#pragma unroll
+    for (int sp = 0; sp < NT / 64; ++sp) {
+      const int scol = sp * 64 + (tid >> 2);
       const int k0 = kc + spart;
       const int row = s_src[scol];
       float vals[16];
@@ -622,7 +624,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf3(GemmArgs g0, GemmArgs g1, int 
         }
         const int ko = kb2 * 32 + 8 * (lane >> 4);
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
+        for (int cb = 0; cb < NT / 16; ++cb) {
           const int col = cb * 16 + (lane & 15);
           const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&Bh[col][ko]));
           const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&Bl[col][ko]));
@@ -646,7 +648,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf3(GemmArgs g0, GemmArgs g1, int 
     if (rb >= nrb) continue;
     const int i0 = rb * 16 + 4 * (lane >> 4);
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
+    for (int cb = 0; cb < NT / 16; ++cb) {
       const int c = cb * 16 + (lane & 15);
       if (c >= tk.ncol) continue;
       float *y = Y + (int64_t)dst[tk.col0 + c] * ldy + i0;
@@ -1721,6 +1723,7 @@ static GemmArgs gemm_args(const fmm_plan *P, const GemmBatch &bt, const void *X,
   g.seg = bt.seg ? bt.seg : P->ld;
   g.KQ = bt.kq_stride ? bt.kq_stride : P->ld / 16;
   g.mode = bt.mode;
+  g.nt = bt.nt;
   if (bt.pool == 2) {
     g.pool = P->pool_bf;
     g.mstride = (int64_t)(P->ld / 16) * P->bf_kb * 2 * 64;
@@ -1738,7 +1741,10 @@ static void launch_gemm_rbw(const GemmArgs &g0, const GemmArgs &g1, bool bf3, in
   const unsigned gx = 8u * (unsigned)((g0.ntask + 7) / 8 + (g1.ntask + 7) / 8);
   if constexpr (std::is_same<T, float>::value) {
     if (bf3) {
-      hipLaunchKernelGGL((k_gemm_bf3<RBW>), dim3(gx, gy), dim3(256), 0, s, g0, g1, KB);
+      if (g0.nt == 2 * GEMM_NT)
+        hipLaunchKernelGGL((k_gemm_bf3<RBW, 2 * GEMM_NT>), dim3(gx, gy), dim3(256), 0, s, g0, g1, KB);
+      else
+        hipLaunchKernelGGL((k_gemm_bf3<RBW>), dim3(gx, gy), dim3(256), 0, s, g0, g1, KB);
       return;
     }
   }

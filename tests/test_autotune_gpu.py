@@ -44,6 +44,7 @@ def _pair(xt, q, ncrit=48):
     {"gemm_lat": 0},
     {"gemm_lat": 1 << 20},
     {"near_lds": 13312},
+    {"m2l_cols": 128},
 ])
 def test_every_setting_gives_the_same_fmm(setting):
     torch = require_gpu()
