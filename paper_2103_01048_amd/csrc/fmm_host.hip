@@ -444,7 +444,7 @@ static int precompute_typed(fmm_plan *P) {
   // with the child factors scaled by 1/2 below)
   auto child_of = [&](int gl) { return gl < 0 ? gl : gl + 1; };
   std::vector<int> id1(jobs.size(), -1), id8(jobs.size(), -1);
-  int64_t c1 = 0, c8 = 0;
+  int64_t c1 = 0;
   for (size_t j = 0; j < jobs.size(); ++j) id1[j] = (int)c1++;
   // factored M2L: each M2L job also stores its right factor R (id1 then holds
   // the left factor L); rank per job
@@ -454,8 +454,8 @@ static int precompute_typed(fmm_plan *P) {
     for (size_t j = 0; j < jobs.size(); ++j)
       if (jobs[j].kind == 6) idr[j] = (int)c1++;
   const double tau_f = P->precision == FMM_FP64 ? 1e-11 : 1e-7;
-  const size_t m1 = (size_t)ld * ld, m8 = (size_t)ld * ld * 8;
-  std::vector<T> pool1(std::max<size_t>(1, c1 * m1)), pool8(std::max<size_t>(1, c8 * m8));
+  const size_t m1 = (size_t)ld * ld;
+  std::vector<T> pool1(std::max<size_t>(1, c1 * m1));
   // bf16x3 mode: the M2L operators also in split bf16 form (K padded to 32)
   const bool bf3 = P->precision == FMM_FP32_BF16X3;
   const int KB = (ld + 31) / 32;
@@ -572,7 +572,6 @@ static int precompute_typed(fmm_plan *P) {
     }
   }
   P->pool1_count = c1;
-  P->pool8_count = c8;
   P->m2l_ldt = 0;
   if (fact) {
     int kmax = 1;
@@ -581,7 +580,6 @@ static int precompute_typed(fmm_plan *P) {
   }
   int rc;
   if ((rc = upload(P, &P->pool1, pool1))) return rc;
-  if ((rc = upload(P, &P->pool8, pool8))) return rc;
   P->bf_kb = KB;
   P->poolbf_count = cbf;
   if (bf3 && (rc = upload(P, &P->pool_bf, poolbf))) return rc;
@@ -912,7 +910,7 @@ static void add_columns(GemmBatch &bt, int mat, double alpha, const std::vector<
 }
 
 static int finish_batch(fmm_plan *P, GemmBatch &bt) {
-  const int64_t nmat = bt.pool == 0 ? P->pool1_count : (bt.pool == 1 ? P->pool8_count : P->poolbf_count);
+  const int64_t nmat = bt.pool == 0 ? P->pool1_count : P->poolbf_count;
   for (const GemmTask &t : bt.h_tasks)
     if (t.mat < 0 || t.mat >= nmat) {
       set_error("internal: GEMM task references a missing operator");
@@ -1292,8 +1290,8 @@ static fmm_plan *find_ops(const fmm_plan *P) {
 
 static void share_ops(fmm_plan *P, const fmm_plan *A) {
   P->ops_mem = A->ops_mem;
-  P->pool1 = A->pool1; P->pool8 = A->pool8; P->pool_bf = A->pool_bf;
-  P->pool1_count = A->pool1_count; P->pool8_count = A->pool8_count; P->poolbf_count = A->poolbf_count;
+  P->pool1 = A->pool1; P->pool_bf = A->pool_bf;
+  P->pool1_count = A->pool1_count; P->poolbf_count = A->poolbf_count;
   P->bf_kb = A->bf_kb;
   P->utu_id = A->utu_id; P->vsu_id = A->vsu_id; P->utd_id = A->utd_id; P->vsd_id = A->vsd_id;
   P->rank_u = A->rank_u; P->rank_d = A->rank_d;

@@ -48,7 +48,7 @@ struct GemmTask {
   double alpha;
 };
 
-enum GemmMode { GEMM_STORE = 0, GEMM_ADD = 1, GEMM_ATOMIC = 2 };
+enum GemmMode { GEMM_STORE = 0, GEMM_ADD = 1 };
 
 // Everything one gather-GEMM batch needs on the device; a launch takes two
 // (the second with ntask = 0 when unused) so that the same pass of two plans
@@ -64,8 +64,8 @@ struct GemmArgs {
   int ntask, nrb, klen, ldx, ldy, S, seg, KQ, mode, nt;
 };
 
-// A batch of GEMM tasks that can run in one launch (no write conflicts
-// except through GEMM_ATOMIC).
+// A batch of GEMM tasks that can run in one launch (no two tasks write the
+// same output rows).
 struct GemmBatch {
   int S = 1;                   // K segments per column
   int nrb = 0;                 // 16-row blocks of A that are computed
@@ -74,7 +74,7 @@ struct GemmBatch {
   int kq_stride = 0;           // 16-wide k groups per stored row block (0: row length / 16)
   int ldy = 0;                 // leading dimension of the output rows (0: the work-array row length)
   int mode = GEMM_STORE;
-  int pool = 0;                // 0: matrix pool, 1: stacked pool, 2: bf16x3 split pool
+  int pool = 0;                // 0: matrix pool, 2: bf16x3 split pool
   int ldx = 0;                 // row length of X (0: the work-array row length)
   int nt = GEMM_NT;            // columns per task (the bf16x3 kernel also takes 2 GEMM_NT)
   int ntask = 0;
@@ -189,8 +189,7 @@ struct fmm_plan {
   fmm::DevTree dt;
   void *surf = nullptr;            // T4 grid offsets in [-1,1]^3, nsurf entries
   void *pool1 = nullptr;           // swizzled ld x ld matrices
-  void *pool8 = nullptr;           // swizzled ld x 8ld matrices (M2M)
-  int64_t pool1_count = 0, pool8_count = 0, poolbf_count = 0;
+  int64_t pool1_count = 0, poolbf_count = 0;
   void *pool_bf = nullptr;         // bf16x3 mode: split M2L operators
   int bf_kb = 0;                   // 32-wide k blocks per row block in pool_bf
   // matrix ids (pool1 unless noted) per level; -1 when absent

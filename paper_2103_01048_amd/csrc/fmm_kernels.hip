@@ -426,11 +426,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g0, GemmArgs g1) {
       V4 v = acc[r][cb] * alpha;
       if (mode == GEMM_STORE) {
         *reinterpret_cast<V4 *>(y) = v;
-      } else if (mode == GEMM_ADD) {
+      } else {
         V4 o = *reinterpret_cast<V4 *>(y);
         *reinterpret_cast<V4 *>(y) = o + v;
-      } else {
-        atomicAdd(y + 0, v[0]); atomicAdd(y + 1, v[1]); atomicAdd(y + 2, v[2]); atomicAdd(y + 3, v[3]);
       }
     }
   }
@@ -517,11 +515,9 @@ __device__ __forceinline__ void gemm_lat_tile(const GemmArgs &g, int task, int y
     V4 r = acc[cb] * alpha;
     if (mode == GEMM_STORE) {
       *reinterpret_cast<V4 *>(y) = r;
-    } else if (mode == GEMM_ADD) {
+    } else {
       V4 o = *reinterpret_cast<V4 *>(y);
       *reinterpret_cast<V4 *>(y) = o + r;
-    } else {
-      atomicAdd(y + 0, r[0]); atomicAdd(y + 1, r[1]); atomicAdd(y + 2, r[2]); atomicAdd(y + 3, r[3]);
     }
   }
 }
@@ -1728,8 +1724,8 @@ static GemmArgs gemm_args(const fmm_plan *P, const GemmBatch &bt, const void *X,
     g.pool = P->pool_bf;
     g.mstride = (int64_t)(P->ld / 16) * P->bf_kb * 2 * 64;
   } else {
-    g.pool = bt.pool == 0 ? P->pool1 : P->pool8;
-    g.mstride = (int64_t)P->ld * P->ld * (bt.pool == 0 ? 1 : 8);
+    g.pool = P->pool1;
+    g.mstride = (int64_t)P->ld * P->ld;
   }
   return g;
 }
