@@ -190,7 +190,10 @@ int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const v
  *                 passes run on a side stream meanwhile): 0 near field once
  *                 P2M is done, then P2L; 1 P2L once P2M is done, near field
  *                 once the upward pass is done; 2 P2L, then the near field,
- *                 both once P2M is done
+ *                 both once P2M is done; 3 (the default) P2L, its projection
+ *                 and the M2P sources' equivalent densities once P2M is done
+ *                 (beside the upward GEMMs and the M2L), the near field once
+ *                 the M2L is done (beside the M2L sums and the downward pass)
  *   near_lds      pair evaluations: LDS bytes (0..65536, unused by the
  *                 kernel) reserved per near-field wave, which caps the
  *                 near-field waves per compute unit so that the far-field
@@ -204,6 +207,9 @@ int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const v
  *                 one before, bounded waits); 0: one launch per level
  *   m2l_cols      bf16x3 M2L columns (V pairs) per workgroup sharing one
  *                 operator fetch: 64 (default) or 128
+ *   gemm_narrow   pair evaluations in single precision: 1 runs the L2L and
+ *                 the leaves' downward projections as one-wave workgroups
+ *                 (room beside the near field's waves); 0: 256-thread ones
  * FMM_EINVAL for values out of range. */
 typedef struct {
   int32_t tile_split2;
@@ -218,6 +224,7 @@ typedef struct {
   int32_t gemm_lat;
   int32_t gemm_chain;
   int32_t m2l_cols;
+  int32_t gemm_narrow;
 } fmm_tuning_t;
 int fmm_set_tuning(const fmm_tuning_t *tuning);
 int fmm_get_tuning(fmm_tuning_t *tuning);

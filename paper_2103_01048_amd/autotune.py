@@ -14,7 +14,7 @@ Tunables (fmm_set_tuning; defaults in DEFAULTS):
   m2l_factored                M2L operators split per offset by a truncated
                               SVD and applied in two passes
   pair_order                  order of the pair evaluation's near field and
-                              P2L against the far-field passes (0, 1, 2)
+                              P2L against the far-field passes (0..3)
   near_lds                    LDS bytes held per near-field wave of a pair
                               evaluation (caps its waves per compute unit)
   gemm_lat                    translation GEMM launches of at most this many
@@ -47,9 +47,10 @@ from ._lib import check, lib
 from .fmm import FMMPlan, eval_pair
 
 DEFAULTS = {"tile_split2": 32, "tile_split4": 16, "work_cap_min": 512, "work_cap_div": 16384, "far_weight": 1.15,
-            "gemm_rbw": 0, "m2l_factored": 0, "pair_order": 0,
+            "gemm_rbw": 0, "m2l_factored": 0, "pair_order": 3,
             "near_lds": 0, "gemm_lat": 512,
-            "gemm_chain": 0, "m2l_cols": 64}
+            "gemm_chain": 0, "m2l_cols": 64,
+            "gemm_narrow": 0}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2103_01048_amd", "tuning.json")
 
 STAGES = (
@@ -58,7 +59,8 @@ STAGES = (
     ("far_weight", [{"far_weight": v} for v in (1.0, 1.15, 1.3)]),
     ("gemm_rbw", [{"gemm_rbw": v} for v in (0, 1, 2, 4)]),
     ("m2l_factored", [{"m2l_factored": v} for v in (0, 1)]),
-    ("pair_order", [{"pair_order": v} for v in (0, 1, 2)]),
+    ("gemm_narrow", [{"gemm_narrow": v} for v in (0, 1)]),
+    ("pair_order", [{"pair_order": v} for v in (0, 1, 2, 3)]),
     ("near_lds", [{"near_lds": v} for v in (0, 8192, 13312)]),
     ("gemm_lat", [{"gemm_lat": v} for v in (0, 256, 512, 1024)]),
 )

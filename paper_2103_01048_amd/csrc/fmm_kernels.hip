@@ -434,6 +434,83 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g0, GemmArgs g1) {
   }
 }
 
+// One wave per (64-column task, 16-row block), for the passes that run beside
+// the near field: a 64-thread workgroup with few registers fits beside the
+// near field's waves as they retire, where a 256-thread one waits for a whole
+// compute unit's worth of them.  Each wave stages its own 64 columns (lane c
+// loads column c) to LDS; the MFMAs run in k_gemm's k order, so the results
+// are the same bit for bit.
+template <typename T>
+__global__ __launch_bounds__(64) void k_gemm_narrow(GemmArgs g0, GemmArgs g1) {
+  __builtin_amdgcn_s_setprio(3);
+  using V4 = typename Vec4<T>::type;
+  GemmArgs g;
+  int task;
+  if (!gemm_pick(g0, g1, g, task)) return;
+  const GemmTask tk = g.tasks[task];
+  const int nrb = tk.nrb > 0 ? min(tk.nrb, g.nrb) : g.nrb;
+  const int rb = (int)blockIdx.y;
+  if (rb >= nrb) return;
+  const int S = g.S, seg = g.seg, KQ = g.KQ, ld = g.ldx, ldy = g.ldy, mode = g.mode;
+  const int K = tk.klen > 0 ? min(tk.klen, g.klen) : g.klen;
+  const int KQK = K >> 4;
+  const int32_t *__restrict__ src = g.src;
+  const T *__restrict__ X = (const T *)g.X;
+  T *__restrict__ Y = (T *)g.Y;
+  const int lane = threadIdx.x;
+  const T *__restrict__ A = (const T *)g.pool + (int64_t)tk.mat * g.mstride + ((int64_t)rb * KQ * 64 + lane) * 4;
+  __shared__ T Bs[64][GEMM_NT + 1];
+  V4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = V4{0, 0, 0, 0};
+  for (int kc = 0; kc < K; kc += 64) {
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {
+      const int k0 = kc + q * 4;
+      V4 v = V4{0, 0, 0, 0};
+      if (lane < tk.ncol && k0 < K) {
+        const int sg = k0 / seg, kk = k0 - sg * seg;
+        const int row = src[(int64_t)(tk.col0 + lane) * S + sg];
+        if (row >= 0) v = *reinterpret_cast<const V4 *>(X + (int64_t)row * ld + kk);
+      }
+      Bs[q * 4 + 0][lane] = v[0];
+      Bs[q * 4 + 1][lane] = v[1];
+      Bs[q * 4 + 2][lane] = v[2];
+      Bs[q * 4 + 3][lane] = v[3];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) {
+      const int gkq = (kc >> 4) + kq;
+      if (gkq < KQK) {
+        const V4 a = *reinterpret_cast<const V4 *>(A + (int64_t)gkq * 256);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int kl = (kq * 4 + t) * 4 + (lane >> 4);
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) acc[cb] = mfma_16x16x4(a[t], Bs[kl][cb * 16 + (lane & 15)], acc[cb]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const T alpha = (T)tk.alpha;
+  const int i0 = rb * 16 + 4 * (lane >> 4);
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int c = cb * 16 + (lane & 15);
+    if (c >= tk.ncol) continue;
+    T *y = Y + (int64_t)g.dst[tk.col0 + c] * ldy + i0;
+    const V4 r = acc[cb] * alpha;
+    if (mode == GEMM_STORE) {
+      *reinterpret_cast<V4 *>(y) = r;
+    } else {
+      V4 o = *reinterpret_cast<V4 *>(y);
+      *reinterpret_cast<V4 *>(y) = o + r;
+    }
+  }
+}
+
 // Latency-bound launches (fewer workgroups than the device has compute
 // units: the M2M and L2L levels, the surface projections): the same
 // gather-GEMM with one 16-row block per wave, every A fragment of the wave
@@ -1815,6 +1892,28 @@ static int launch_gemm2(fmm_plan *P, const GemmBatch &bt, const T *X, T *Y, fmm_
   return FMM_OK;
 }
 
+// The same launch with one wave per (task, row block) (k_gemm_narrow), for
+// single precision; double precision takes launch_gemm2.
+template <typename T>
+static int launch_gemm2_narrow(fmm_plan *P, const GemmBatch &bt, const T *X, T *Y, fmm_plan *Q, const GemmBatch *bq,
+                               const T *XQ, T *YQ, hipStream_t s) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return launch_gemm2<T>(P, bt, X, Y, Q, bq, XQ, YQ, s);
+  }
+  if (bt.pool == 2) return launch_gemm2<T>(P, bt, X, Y, Q, bq, XQ, YQ, s);
+  GemmArgs g0 = gemm_args(P, bt, X, Y);
+  GemmArgs g1 = g0;
+  g1.ntask = 0;
+  if (Q && bq && bq->ntask) g1 = gemm_args(Q, *bq, XQ, YQ);
+  if (g0.ntask == 0 && g1.ntask == 0) return FMM_OK;
+  if (g0.ntask == 0) { std::swap(g0, g1); g1.ntask = 0; }
+  const int nrb = std::max(g0.nrb, g1.ntask ? g1.nrb : 0);
+  const dim3 grid(8u * (unsigned)((g0.ntask + 7) / 8 + (g1.ntask + 7) / 8), (unsigned)nrb);
+  hipLaunchKernelGGL((k_gemm_narrow<T>), grid, dim3(64), 0, s, g0, g1);
+  FMM_HIP_TRY(hipGetLastError());
+  return FMM_OK;
+}
+
 template <typename T>
 static int launch_gemm(fmm_plan *P, const GemmBatch &bt, const T *X, T *Y, hipStream_t s) {
   return launch_gemm2<T>(P, bt, X, Y, nullptr, nullptr, nullptr, nullptr, s);
@@ -2159,14 +2258,22 @@ down:
     if ((rc = launch_chain<T>(A->chain_down, ctr_down, chain_err, s))) return rc;
     prof_end(A, FMM_PHASE_L2L, ev, s);
   }
+  // with gemm_narrow the downward passes use one-wave workgroups, which
+  // find room beside the near field's waves (pass order 3 runs them there)
   for (int l = 3; l <= D.maxlevel && !(chain && A->chain_down.ntask); ++l) {
     if (!LA.l2l[l].ntask) continue;
     ev = prof_begin(A, FMM_PHASE_L2L, s);
-    if ((rc = launch_gemm2<T>(A, LA.l2l[l], W(A->yd), W(A->yd), B, &LB.l2l[l], W(B->yd), W(B->yd), s))) return rc;
+    rc = A->tune.gemm_narrow
+             ? launch_gemm2_narrow<T>(A, LA.l2l[l], W(A->yd), W(A->yd), B, &LB.l2l[l], W(B->yd), W(B->yd), s)
+             : launch_gemm2<T>(A, LA.l2l[l], W(A->yd), W(A->yd), B, &LB.l2l[l], W(B->yd), W(B->yd), s);
+    if (rc) return rc;
     prof_end(A, FMM_PHASE_L2L, ev, s);
   }
   ev = prof_begin(A, FMM_PHASE_DC2E, s);
-  if ((rc = launch_gemm2<T>(A, LA.vs_d, W(A->yd), W(A->eqd), B, &LB.vs_d, W(B->yd), W(B->eqd), s))) return rc;
+  rc = A->tune.gemm_narrow
+           ? launch_gemm2_narrow<T>(A, LA.vs_d, W(A->yd), W(A->eqd), B, &LB.vs_d, W(B->yd), W(B->eqd), s)
+           : launch_gemm2<T>(A, LA.vs_d, W(A->yd), W(A->eqd), B, &LB.vs_d, W(B->yd), W(B->eqd), s);
+  if (rc) return rc;
   prof_end(A, FMM_PHASE_DC2E, ev, s);
   return FMM_OK;
 }
@@ -2257,10 +2364,11 @@ static int pair_p2l_proj(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips)
 }
 
 template <typename T, int NR>
-static int pair_off_chain(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips, bool p2l) {
+static int pair_off_chain(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips, bool p2l, bool vsu = true) {
   const PassLists &LA = A->lists_by_nr[NR], &LB = B->lists_by_nr[NR];
   int rc;
   if (p2l && (rc = pair_p2l_proj<T, NR>(A, B, s, dips))) return rc;
+  if (!vsu) return FMM_OK;
   FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_up, 0));
   hipEvent_t ev;
   ev = prof_begin(A, FMM_PHASE_UC2E, s);
@@ -2287,19 +2395,27 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
     FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
     FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_fork, 0));
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips))) return rc;
+    if (order == 3) FMM_HIP_TRY(hipEventRecord(A->ev_m2l, side));
     // the near field starts once P2M (VALU, like the near field) is done and
     // shares the GPU with the GEMM passes; P2L and its projection (which the
     // M2L sums wait for) run after it (order 0) or before it (1: the near
-    // field then also waits for the upward pass; 2: it does not)
+    // field then also waits for the upward pass; 2: it does not; 3: it
+    // waits for the M2L, so that the upward pass and the M2L have the GPU to
+    // themselves and the near field shares it with the downward pass)
     FMM_HIP_TRY(hipStreamWaitEvent(s, B->ev_fork, 0));
-    if (order != 0) {
+    if (order == 3) {
+      // P2L, its projection and the M2P sources' equivalent densities beside
+      // the upward GEMMs and the M2L
+      if ((rc = pair_off_chain<T, NR>(A, B, s, dips, true, true))) return rc;
+      FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_m2l, 0));
+    } else if (order != 0) {
       if ((rc = pair_p2l_proj<T, NR>(A, B, s, dips))) return rc;
       if (order == 1) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_up, 0));
     }
   }
   if ((rc = near())) return rc;
   if (far) {
-    if ((rc = pair_off_chain<T, NR>(A, B, s, dips, order == 0))) return rc;
+    if (order != 3 && (rc = pair_off_chain<T, NR>(A, B, s, dips, order == 0))) return rc;
     FMM_HIP_TRY(hipStreamWaitEvent(side, B->ev_join, 0));
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 2, nullptr, nullptr, dips))) return rc;
     FMM_HIP_TRY(hipEventRecord(A->ev_join, side));

@@ -41,10 +41,13 @@ def _pair(xt, q, ncrit=48):
     {"gemm_rbw": 4},
     {"pair_order": 1},
     {"pair_order": 2},
+    {"pair_order": 3},
     {"gemm_lat": 0},
     {"gemm_lat": 1 << 20},
     {"near_lds": 13312},
     {"m2l_cols": 128},
+    {"gemm_narrow": 1},
+    {"gemm_narrow": 1, "pair_order": 3},
 ])
 def test_every_setting_gives_the_same_fmm(setting):
     torch = require_gpu()
