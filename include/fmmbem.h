@@ -210,6 +210,12 @@ int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const v
  *   gemm_narrow   pair evaluations in single precision: 1 runs the L2L and
  *                 the leaves' downward projections as one-wave workgroups
  *                 (room beside the near field's waves); 0: 256-thread ones
+ *   near_early, near_early_grid
+ *                 pair evaluations with pair_order 3: the last near_early
+ *                 per mille (0..900) of the near-field items (the shortest)
+ *                 start at once on a second side stream, on a grid of
+ *                 near_early_grid waves (64..65536) that loop over them,
+ *                 beside the upward passes and the M2L; 0: none
  * FMM_EINVAL for values out of range. */
 typedef struct {
   int32_t tile_split2;
@@ -225,6 +231,8 @@ typedef struct {
   int32_t gemm_chain;
   int32_t m2l_cols;
   int32_t gemm_narrow;
+  int32_t near_early;
+  int32_t near_early_grid;
 } fmm_tuning_t;
 int fmm_set_tuning(const fmm_tuning_t *tuning);
 int fmm_get_tuning(fmm_tuning_t *tuning);

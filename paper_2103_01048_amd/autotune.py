@@ -19,6 +19,9 @@ Tunables (fmm_set_tuning; defaults in DEFAULTS):
                               evaluation (caps its waves per compute unit)
   gemm_lat                    translation GEMM launches of at most this many
                               workgroups use the latency-bound kernel
+  near_early, near_early_grid per mille of the near-field items (the
+                              shortest) started at once on a small grid
+                              beside the upward passes and the M2L (order 3)
   m2l_cols                    bf16x3 M2L columns per workgroup (64 or 128;
                               not searched: 128 halves the occupancy)
   gemm_chain                  the M2M levels, and the L2L levels, of a pair
@@ -50,7 +53,7 @@ DEFAULTS = {"tile_split2": 32, "tile_split4": 16, "work_cap_min": 512, "work_cap
             "gemm_rbw": 0, "m2l_factored": 0, "pair_order": 3,
             "near_lds": 0, "gemm_lat": 512,
             "gemm_chain": 0, "m2l_cols": 64,
-            "gemm_narrow": 0}
+            "gemm_narrow": 0, "near_early": 0, "near_early_grid": 1024}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2103_01048_amd", "tuning.json")
 
 STAGES = (
@@ -60,6 +63,7 @@ STAGES = (
     ("gemm_rbw", [{"gemm_rbw": v} for v in (0, 1, 2, 4)]),
     ("m2l_factored", [{"m2l_factored": v} for v in (0, 1)]),
     ("gemm_narrow", [{"gemm_narrow": v} for v in (0, 1)]),
+    ("near_early", [{"near_early": v} for v in (0, 350, 450, 500, 550)]),
     ("pair_order", [{"pair_order": v} for v in (0, 1, 2, 3)]),
     ("near_lds", [{"near_lds": v} for v in (0, 8192, 13312)]),
     ("gemm_lat", [{"gemm_lat": v} for v in (0, 256, 512, 1024)]),

@@ -1166,6 +1166,8 @@ static uint64_t tree_fingerprint(const fmm_plan *P) {
 // near-field running sums for nr columns.
 int ensure_pair(fmm_plan *A, fmm_plan *B, int nr) {
   if (!A->aux) FMM_HIP_TRY(hipStreamCreateWithFlags(&A->aux, hipStreamNonBlocking));
+  if (!A->aux2) FMM_HIP_TRY(hipStreamCreateWithFlags(&A->aux2, hipStreamNonBlocking));
+  if (!A->ev_near) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_near, hipEventDisableTiming));
   if (!A->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_fork, hipEventDisableTiming));
   if (!A->ev_join) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_join, hipEventDisableTiming));
   if (!A->ev_up) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_up, hipEventDisableTiming));
@@ -1250,7 +1252,7 @@ void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
 
 // Tunables for plans set up from now on (fmm_set_tuning).
 static std::mutex g_tune_mu;
-static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0};
+static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0, 0, 1024};
 
 // Live plans whose tree later plans on the same points may share.
 static std::mutex g_tree_mu;
@@ -1672,7 +1674,8 @@ int fmm_set_tuning(const fmm_tuning_t *t) {
       t->gemm_rbw < 0 || t->gemm_rbw > 8 || t->m2l_factored < 0 || t->m2l_factored > 1 || t->pair_order < 0 ||
       t->pair_order > 3 || t->near_lds < 0 || t->near_lds > 65536 ||
       t->gemm_lat < 0 || t->gemm_lat > (1 << 20) || t->gemm_chain < 0 || t->gemm_chain > 1 ||
-      (t->m2l_cols != 64 && t->m2l_cols != 128) || t->gemm_narrow < 0 || t->gemm_narrow > 1) {
+      (t->m2l_cols != 64 && t->m2l_cols != 128) || t->gemm_narrow < 0 || t->gemm_narrow > 1 ||
+      t->near_early < 0 || t->near_early > 900 || t->near_early_grid < 64 || t->near_early_grid > 65536) {
     set_error("fmm_set_tuning: value out of range");
     return FMM_EINVAL;
   }
@@ -1720,13 +1723,13 @@ void fmm_free(fmm_plan *P) {
   unregister_tree(P);
   for (auto &pe : P->prof_events) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
   for (hipEvent_t e : P->event_pool) (void)hipEventDestroy(e);
-  if (P->aux) {
-    (void)hipStreamSynchronize(P->aux);
-    (void)hipStreamDestroy(P->aux);
-  }
-  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
-  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
-  if (P->ev_up) (void)hipEventDestroy(P->ev_up);
+  for (hipStream_t st : {P->aux, P->aux2})
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  for (hipEvent_t e : {P->ev_fork, P->ev_join, P->ev_up, P->ev_m2l, P->ev_near})
+    if (e) (void)hipEventDestroy(e);
   for (void *p : P->allocs) (void)hipFree(p);
   delete P;
 }

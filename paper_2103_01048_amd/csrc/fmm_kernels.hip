@@ -1060,12 +1060,13 @@ __global__ __launch_bounds__(64) void k_near_pair(
     const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts,
     const T *__restrict__ qs, int64_t N, const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end,
     const int32_t *__restrict__ near_off, const int32_t *__restrict__ near_rng, const T *__restrict__ near_o,
-    T *__restrict__ acc, T kappa, int nitems) {
+    T *__restrict__ acc, T kappa, int nitems, int item0) {
   using V4 = typename Vec4<T>::type;
   const V4 *__restrict__ p4 = reinterpret_cast<const V4 *>(pts);
   // one wave per item (the loop also serves a grid smaller than the item
   // count: waves then take items round robin, longest first)
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+  // items item0 .. item0 + nitems - 1
+  for (int item = item0 + (int)blockIdx.x; item < item0 + nitems; item += gridDim.x) {
     const int slot = items[4 * item];
     const int code = items[4 * item + 1];
     const int split = code >> 24;
@@ -1482,11 +1483,12 @@ __global__ __launch_bounds__(64) void k_near_pair_md(
     const int32_t *__restrict__ items, const int32_t *__restrict__ leaves, const T *__restrict__ pts,
     const T *__restrict__ dips, const int32_t *__restrict__ box_begin, const int32_t *__restrict__ box_end,
     const int32_t *__restrict__ near_off, const int32_t *__restrict__ near_rng, const T *__restrict__ near_o,
-    T *__restrict__ acc, T kappa, int nitems) {
+    T *__restrict__ acc, T kappa, int nitems, int item0) {
   using V4 = typename Vec4<T>::type;
   const V4 *__restrict__ p4 = reinterpret_cast<const V4 *>(pts);
   const V4 *__restrict__ d4 = reinterpret_cast<const V4 *>(dips);
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+  // items item0 .. item0 + nitems - 1
+  for (int item = item0 + (int)blockIdx.x; item < item0 + nitems; item += gridDim.x) {
     const int slot = items[4 * item];
     const int code = items[4 * item + 1];
     const int split = code >> 24;
@@ -2391,9 +2393,23 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   // FMM_PROFILE_SERIAL: the side stream's passes run on s, in the same order
   const hipStream_t side = (A->profiling & FMM_PROFILE_SERIAL) ? s : A->aux;
   const int order = A->tune.pair_order;
+  // order 3 with near_early: the shortest items (the tail of the item list)
+  // on a second side stream from the start, on a small grid of waves that
+  // loop over them, beside the upward passes and the M2L
+  const int nit = A->dt.nitems;
+  const int nearly = (far && order == 3 && A->tune.near_early > 0)
+                         ? std::min(nit, (int)((int64_t)nit * A->tune.near_early / 1000))
+                         : 0;
+  const int nmain = nit - nearly;
+  const hipStream_t side2 = (A->profiling & FMM_PROFILE_SERIAL) ? s : A->aux2;
   if (far) {
     FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
     FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_fork, 0));
+    if (nearly > 0) {
+      FMM_HIP_TRY(hipStreamWaitEvent(side2, A->ev_fork, 0));
+      if ((rc = near(side2, nmain, nearly, std::min(nearly, A->tune.near_early_grid)))) return rc;
+      FMM_HIP_TRY(hipEventRecord(A->ev_near, side2));
+    }
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips))) return rc;
     if (order == 3) FMM_HIP_TRY(hipEventRecord(A->ev_m2l, side));
     // the near field starts once P2M (VALU, like the near field) is done and
@@ -2413,13 +2429,14 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
       if (order == 1) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_up, 0));
     }
   }
-  if ((rc = near())) return rc;
+  if ((rc = near(s, 0, nmain, nmain))) return rc;
   if (far) {
     if (order != 3 && (rc = pair_off_chain<T, NR>(A, B, s, dips, order == 0))) return rc;
     FMM_HIP_TRY(hipStreamWaitEvent(side, B->ev_join, 0));
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 2, nullptr, nullptr, dips))) return rc;
     FMM_HIP_TRY(hipEventRecord(A->ev_join, side));
     FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
+    if (nearly > 0) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_near, 0));
   }
   return FMM_OK;
 }
@@ -2434,16 +2451,17 @@ static int eval_pair_chunk(fmm_plan *A, fmm_plan *B, const T *q, T *pot_a, T *gr
   const T kappa = (T)B->kappa;
   const T scale = (T)(1.0 / (4.0 * M_PI));
   T *acc = (T *)A->pair_acc;
-  auto near = [&]() -> int {
-    hipEvent_t e = prof_begin(A, FMM_PHASE_NEAR, s);
-    if (D.nitems > 0)
-      hipLaunchKernelGGL((k_near_pair<T, NR>), dim3(D.nitems), dim3(64), A->tune.near_lds, s, D.items,
+  auto near = [&](hipStream_t st, int i0, int cnt, int grid) -> int {
+    hipEvent_t e = prof_begin(A, FMM_PHASE_NEAR, st);
+    if (cnt > 0)
+      hipLaunchKernelGGL((k_near_pair<T, NR>), dim3(grid), dim3(64), A->tune.near_lds, st, D.items,
                          D.leaves, (const T *)D.pts, (const T *)A->qs, N, D.box_begin, D.box_end, D.near_off,
-                         D.near_rng, (const T *)D.near_o, acc, kappa, D.nitems);
+                         D.near_rng, (const T *)D.near_o, acc, kappa, cnt, i0);
     FMM_HIP_TRY(hipGetLastError());
-    prof_end(A, FMM_PHASE_NEAR, e, s);
+    prof_end(A, FMM_PHASE_NEAR, e, st);
     return FMM_OK;
   };
+
   if (A->tune.gemm_chain && D.maxlevel >= 2 && (rc = ensure_chains<T, NR>(A, B))) return rc;
   if ((rc = pair_fork_join<T, NR>(A, B, s, (const T *)nullptr, near))) return rc;
   hipEvent_t ev = prof_begin(A, FMM_PHASE_FAR, s);
@@ -2520,20 +2538,20 @@ static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip
   const T kappa = (T)B->kappa;
   const T scale = (T)(1.0 / (4.0 * M_PI));
   T *acc = (T *)A->pair_acc;
-  auto near = [&]() -> int {
-    hipEvent_t e = prof_begin(A, FMM_PHASE_NEAR, s);
-    if (D.nitems > 0) {
+  auto near = [&](hipStream_t st, int i0, int cnt, int grid) -> int {
+    hipEvent_t e = prof_begin(A, FMM_PHASE_NEAR, st);
+    if (cnt > 0) {
       if (grad)
-        hipLaunchKernelGGL((k_near_pair_md<T, true>), dim3(D.nitems), dim3(64), A->tune.near_lds, s, D.items, D.leaves,
+        hipLaunchKernelGGL((k_near_pair_md<T, true>), dim3(grid), dim3(64), A->tune.near_lds, st, D.items, D.leaves,
                            (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
-                           (const T *)D.near_o, acc, kappa, D.nitems);
+                           (const T *)D.near_o, acc, kappa, cnt, i0);
       else
-        hipLaunchKernelGGL((k_near_pair_md<T, false>), dim3(D.nitems), dim3(64), A->tune.near_lds, s, D.items, D.leaves,
+        hipLaunchKernelGGL((k_near_pair_md<T, false>), dim3(grid), dim3(64), A->tune.near_lds, st, D.items, D.leaves,
                            (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
-                           (const T *)D.near_o, acc, kappa, D.nitems);
+                           (const T *)D.near_o, acc, kappa, cnt, i0);
     }
     FMM_HIP_TRY(hipGetLastError());
-    prof_end(A, FMM_PHASE_NEAR, e, s);
+    prof_end(A, FMM_PHASE_NEAR, e, st);
     return FMM_OK;
   };
   if (A->tune.gemm_chain && D.maxlevel >= 2 && (rc = ensure_chains<T, 1>(A, B))) return rc;

@@ -48,6 +48,8 @@ def _pair(xt, q, ncrit=48):
     {"m2l_cols": 128},
     {"gemm_narrow": 1},
     {"gemm_narrow": 1, "pair_order": 3},
+    {"near_early": 300},
+    {"near_early": 900, "near_early_grid": 64},
 ])
 def test_every_setting_gives_the_same_fmm(setting):
     torch = require_gpu()
