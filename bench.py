@@ -160,7 +160,7 @@ def parse():
                     help="expansion orders below the workload's p also timed and checked against the sampled "
                          "direct sums (needs the CPU leg); empty to skip")
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--ncrit", type=int, default=0,
                     help="0: ncrit and the library tunables from the package autotuner on this workload")
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"],

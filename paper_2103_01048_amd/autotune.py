@@ -125,7 +125,7 @@ def _time_pair(xt, q, p, ncrit, precision, kappa, steps, warmup, keep, offsets=N
 
 def autotune(points: torch.Tensor, p: int = 8, precision: str = "bf16x3", kappa: float = 0.125,
              ncrit_candidates=(64, 96, 128, 160, 192, 256), q: torch.Tensor | None = None, steps: int = 10,
-             warmup: int = 2, cache_path: str | None = DEFAULT_CACHE, use_cache: bool = True,
+             warmup: int = 10, cache_path: str | None = DEFAULT_CACHE, use_cache: bool = True,
              log=None, offsets=None, repeats: int = 3) -> dict:
     """Fastest (ncrit, tunables) for pair evaluations on `points` ((N, 3)
     float64 CUDA tensor; with `offsets`, a batch of molecules as FMMPlan
