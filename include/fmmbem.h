@@ -122,11 +122,17 @@ int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *g
  * plan_b a Yukawa plan built from the same points (and batch offsets) with
  * the same p, ncrit and precision, the two share one tree: the far-field
  * passes of both kernels run as shared launches on an internal stream
- * (default priority, owned by plan_a) while the near field of both kernels
- * runs on `stream` in one launch that computes each pair distance once;
- * otherwise the two evaluations run one after the other on `stream`.
- * Asynchronous on `stream` (the internal stream is joined back into it).  Errors: as fmm_eval; FMM_EINVAL when
- * the plans differ in point count or precision. */
+ * while the near field of both kernels runs on `stream` in one launch that
+ * computes each pair distance once; otherwise the two evaluations run one
+ * after the other on `stream`.  The internal streams (two, default priority)
+ * belong to the device, not to the plans: every pair evaluation on a device
+ * uses the same two, so the hardware queues taken do not grow with the number
+ * of plans, pair evaluations issued from different caller streams at once
+ * queue their side passes one after the other, and a pair evaluation must not
+ * be captured into a graph while another thread evaluates a pair on the same
+ * device.  They live until the process ends.  Asynchronous on `stream` (the
+ * internal streams are joined back into it).  Errors: as fmm_eval; FMM_EINVAL
+ * when the plans differ in point count or precision. */
 int fmm_eval_pair(fmm_plan *plan_a, fmm_plan *plan_b, const void *q_dev, int nrhs, void *pot_a_dev,
                   void *grad_a_dev, void *pot_b_dev, void *grad_b_dev, fmm_stream_t stream);
 

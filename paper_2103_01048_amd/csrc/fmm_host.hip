@@ -1159,14 +1159,50 @@ static uint64_t tree_fingerprint(const fmm_plan *P) {
   return h;
 }
 
-// Resources of a pair evaluation (A: Laplace half, B: Yukawa half): A's side
-// stream (default priority) that runs both kernels' passes, A's fork and join
+// Side streams of pair evaluations: two per device for the whole process
+// (default priority, created on first use, kept until the process ends).
+// Every plan pair on a device queues its far-field passes and its early
+// near-field items on the same two streams, so the hardware queues the
+// library takes do not grow with the number of live plans.  HIP spreads
+// streams over a small pool of hardware queues (four by default); with
+// streams of their own, the plans set up after enough others had theirs land
+// on the caller's queue, and their side passes then wait behind the near
+// field instead of running beside it.
+static std::mutex g_side_mu;
+static std::map<int, std::pair<hipStream_t, hipStream_t>> g_side;
+
+static int side_streams(int device, hipStream_t *aux, hipStream_t *aux2) {
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  auto it = g_side.find(device);
+  if (it == g_side.end()) {
+    int cur = 0;
+    FMM_HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) FMM_HIP_TRY(hipSetDevice(device));
+    hipStream_t a = nullptr, b = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b, hipStreamNonBlocking);
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+      if (a) (void)hipStreamDestroy(a);
+      FMM_HIP_TRY(e);
+    }
+    it = g_side.emplace(device, std::make_pair(a, b)).first;
+  }
+  *aux = it->second.first;
+  *aux2 = it->second.second;
+  return FMM_OK;
+}
+
+// Resources of a pair evaluation (A: Laplace half, B: Yukawa half): the
+// device's side streams that run both kernels' passes, A's fork and join
 // events and its event marking the end of the upward pass, B's events marking
 // the end of the surface passes and of the P2L projections, and A's buffer of
 // near-field running sums for nr columns.
 int ensure_pair(fmm_plan *A, fmm_plan *B, int nr) {
-  if (!A->aux) FMM_HIP_TRY(hipStreamCreateWithFlags(&A->aux, hipStreamNonBlocking));
-  if (!A->aux2) FMM_HIP_TRY(hipStreamCreateWithFlags(&A->aux2, hipStreamNonBlocking));
+  if (!A->aux || !A->aux2) {
+    int rc;
+    if ((rc = side_streams(A->device, &A->aux, &A->aux2))) return rc;
+  }
   if (!A->ev_near) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_near, hipEventDisableTiming));
   if (!A->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_fork, hipEventDisableTiming));
   if (!A->ev_join) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_join, hipEventDisableTiming));
@@ -1723,11 +1759,8 @@ void fmm_free(fmm_plan *P) {
   unregister_tree(P);
   for (auto &pe : P->prof_events) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
   for (hipEvent_t e : P->event_pool) (void)hipEventDestroy(e);
-  for (hipStream_t st : {P->aux, P->aux2})
-    if (st) {
-      (void)hipStreamSynchronize(st);
-      (void)hipStreamDestroy(st);
-    }
+  for (hipStream_t st : {P->aux, P->aux2})  // the device's shared side streams: wait, keep
+    if (st) (void)hipStreamSynchronize(st);
   for (hipEvent_t e : {P->ev_fork, P->ev_join, P->ev_up, P->ev_m2l, P->ev_near})
     if (e) (void)hipEventDestroy(e);
   for (void *p : P->allocs) (void)hipFree(p);

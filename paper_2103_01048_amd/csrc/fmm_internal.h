@@ -221,7 +221,7 @@ struct fmm_plan {
   std::vector<hipEvent_t> event_pool;
   // pair evaluation (this plan as the Laplace half): side stream, fork and
   // join events, and the near-field running sums of both kernels
-  hipStream_t aux = nullptr, aux2 = nullptr;  // side streams: far-field passes; early near-field items
+  hipStream_t aux = nullptr, aux2 = nullptr;  // the device's shared side streams: far passes; early near items
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_up = nullptr, ev_m2l = nullptr, ev_near = nullptr;
   void *pair_acc = nullptr;
   size_t pair_acc_bytes = 0;
