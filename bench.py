@@ -100,7 +100,9 @@ def phase_work(plan_l, plan_y, infos):
         "p2l": (p2l_pairs * FLOP_PER_SURF_PAIR, PEAK_VALU_FP32, "flop"),
         "dc2e": (gemm(lambda ru, rd: 2.0 * rd * ns * (p2l_boxes + nleaf2)), PEAK_MFMA["fp32"], "flop"),
         "l2l": (gemm(lambda ru, rd: 2.0 * rd * rd * child2), PEAK_MFMA["fp32"], "flop"),
-        "near": (float(inf_l["n_p2p_interactions"]) * FLOP_PER_PAIR_SURVEY, PEAK_VALU_FP32, "flop"),
+        "near": (float(inf_l["n_p2p_interactions"] - inf_l["n_p2p_early"]) * FLOP_PER_PAIR_SURVEY, PEAK_VALU_FP32,
+                 "flop"),
+        "near_early": (float(inf_l["n_p2p_early"]) * FLOP_PER_PAIR_SURVEY, PEAK_VALU_FP32, "flop"),
         "far": (float(inf_l["n_far_interactions"]) * FLOP_PER_PAIR_SURVEY, PEAK_VALU_FP32, "flop"),
     }
     return work
@@ -116,10 +118,16 @@ def cpu_model():
     return "unknown"
 
 
-def measured_traffic(kernel: str, phase: str, precision: str):
+# kernels whose launches differ in grid (the main and the early near-field
+# launch): the profile summary and traffic.json also list them per grid
+GRID_SPLIT = ("k_near_pair<",)
+
+
+def measured_traffic(kernel: str, phase: str, precision: str, grid: int | None = None):
     """HBM bytes per launch (read + write) of the dominant kernel, from the
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in profiles/, or None
-    when the kernel source changed since those counters were taken."""
+    when the kernel source changed since those counters were taken.  grid:
+    only its launches of that many workgroups (for a kernel in GRID_SPLIT)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_2103_01048_amd", "csrc", "fmm_kernels.hip")
@@ -131,6 +139,8 @@ def measured_traffic(kernel: str, phase: str, precision: str):
     if rec.get("kernels_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
     name = names[phase]
+    if grid is not None and any(g in name for g in GRID_SPLIT):
+        name = f"{name} @{grid}"
     t = rec["traffic"].get(name)
     if not t:
         return None
@@ -162,7 +172,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--ncrit", type=int, default=0,
-                    help="0: ncrit and the library tunables from the package autotuner on this workload")
+                    help="0: ncrit and the library tunables from the package autotuner on this workload "
+                         "(its shipped table entry for the device when there is one, else a search)")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the autotuner's search even where the shipped table has an entry")
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"],
                     help="single-precision path timed for `value` (bf16x3: FP32 with the M2L contraction as "
                          "three bf16 MFMA products and FP32 accumulation)")
@@ -208,7 +221,8 @@ def run_batch(args):
                           ncrit_candidates=(64, 96, 128, 160, 192),
                           log=lambda m: print("# autotune " + m, file=sys.stderr, flush=True))
         ncrit = at.apply(res)
-        tuned = {"ncrit": ncrit, "tuning": res["tuning"], "ms": res["ms"], "trials": len(res["trials"])}
+        tuned = {"ncrit": ncrit, "tuning": res["tuning"], "ms": res["ms"], "trials": len(res.get("trials", [])),
+                 "source": res.get("source", "search")}
     batched = [FMMPlan(xt, kernel=k, kappa=KAPPA, p=P_ORDER, ncrit=ncrit, precision=prec, offsets=off)
                for k in ("laplace", "yukawa")]
     separate = []
@@ -455,6 +469,9 @@ def summarize_profile(args):
                 continue
             k = _kname(r["Kernel_Name"])
             per.setdefault(k, {}).setdefault(tag, {})[r["Dispatch_Id"]] = float(r["Counter_Value"])
+            if any(g in k for g in GRID_SPLIT):
+                wgs = int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"]))
+                per.setdefault(f"{k} @{wgs}", {}).setdefault(tag, {})[r["Dispatch_Id"]] = float(r["Counter_Value"])
     copy_bytes = 256 << 20
     ref = None
     for k, v in per.items():
@@ -484,6 +501,19 @@ def summarize_profile(args):
             continue
         lines.append(f"| {float(r['TotalDurationNs']) / 1e6:.3f} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"`{_kname(r['Name'])[:160]}` |")
+    # launches of one kernel with different grids (the main and the early
+    # near-field launch) apart, from the kernel trace
+    by_grid = {}
+    for r in _csv_rows(trace_dir, "kernel_trace.csv"):
+        k = _kname(r["Kernel_Name"])
+        if any(g in k for g in GRID_SPLIT):
+            wgs = int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))
+            by_grid.setdefault((k, wgs), []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    if by_grid:
+        lines += ["", "## Near-field launches by grid (kernel trace)", "",
+                  "| kernel | workgroups | calls | avg us | min us | max us |", "|---|---:|---:|---:|---:|---:|"]
+        for (k, wgs), d in sorted(by_grid.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
+            lines.append(f"| `{k[:100]}` | {wgs} | {len(d)} | {np.mean(d):.2f} | {min(d):.2f} | {max(d):.2f} |")
     lines += ["", "## HBM traffic (--pmc, KiB per dispatch, median over dispatches)", "",
               f"Reference: the 256 MiB device copy (`{ref[0][:80]}`) reads FETCH_SIZE {ref[1]:.0f} KiB and writes "
               f"WRITE_SIZE {ref[2]:.0f} KiB, so bytes = FETCH_SIZE x {f_scale:.3f} KiB and WRITE_SIZE x "
@@ -589,11 +619,15 @@ def main():
     else:
         from paper_2103_01048_amd import autotune as at
         res = at.autotune(xt, p=P_ORDER, precision=args.precision, kappa=KAPPA, q=qd[torch.float32],
-                          cache_path=None,
+                          cache_path=None, use_cache=not args.retune,
                           log=lambda m: print("# autotune " + m, file=sys.stderr, flush=True))
         ncrit = at.apply(res)
-        tuned = {"ncrit": ncrit, "tuning": res["tuning"], "ms": res["ms"], "trials": len(res["trials"]),
-                 "ncrit_ms": {str(t["ncrit"]): t["ms"] for t in res["trials"] if t["stage"] == "ncrit"}}
+        tuned = {"ncrit": ncrit, "tuning": res["tuning"], "ms": res["ms"], "key": res["key"]}
+        if res["cached"]:
+            tuned["source"] = res["source"]
+        else:
+            tuned.update({"source": "search", "trials": len(res["trials"]),
+                          "ncrit_ms": {str(t["ncrit"]): t["ms"] for t in res["trials"] if t["stage"] == "ncrit"}})
 
     plans = make(args.precision, ncrit)
     infos = {k: pl.info() for k, pl in plans.items()}
@@ -622,10 +656,15 @@ def main():
     # the dominant kernel: the larger of the two leaf launches on the caller's
     # stream
     (dk, dname), _ = max(((k, v) for k, v in tot.items() if k[1] in ("near", "far")), key=lambda kv: kv[1][0])
-    # timed region: only the dominant kernel's launches carry HIP events
-    dt, prof = time_steps(step_pair, plans, qd, args.steps, args.warmup, profile={dk: [dname]})
+    # timed region of the headline: no HIP events on any stream (timing
+    # events on a launch, as markers or carried by the launch, cost 0.03-0.06
+    # ms of the ~1.3 ms step); then the same steps again with the dominant
+    # kernel's launches carrying HIP events, for its average duration
+    dt, _ = time_steps(step_pair, plans, qd, args.steps, args.warmup)
     ms_step = dt / args.steps * 1e3
     value = n / (dt / args.steps) / 1e6
+    timed_phases = [dname] + (["near_early"] if dname == "near" else [])
+    dt_ev, prof = time_steps(step_pair, plans, qd, args.steps, 2, profile={dk: timed_phases})
     dms, dcnt = prof[dk][dname]
 
     # the same plans as two separate fmm_eval calls, then the other paths on
@@ -665,8 +704,9 @@ def main():
         roof = {"bound": "mfma", "peak": PEAK_MFMA[args.precision], "unit": "TFLOP/s"}
     elif dname in ("leaf", "near", "far"):
         per = FLOP_PER_PAIR[dk] if dname == "leaf" else FLOP_PER_PAIR_SURVEY
+        # the main near-field launch: the items not started early
         pairs = {"leaf": inf["n_p2p_interactions"] + inf["n_far_interactions"],
-                 "near": inf["n_p2p_interactions"], "far": inf["n_far_interactions"]}[dname]
+                 "near": inf["n_p2p_interactions"] - inf["n_p2p_early"], "far": inf["n_far_interactions"]}[dname]
         flops = float(per * pairs)
         roof = {"bound": "alu", "peak": PEAK_VALU_FP32, "unit": "TFLOP/s"}
     else:
@@ -674,11 +714,24 @@ def main():
         roof = {"bound": "alu", "peak": PEAK_VALU_FP32, "unit": "TFLOP/s"}
     avg_ms = dms / max(1, dcnt)
     achieved = flops / (avg_ms * 1e-3)
-    traffic = measured_traffic(dk, dname, args.precision)
+    traffic = measured_traffic(dk, dname, args.precision,
+                               grid=inf["n_items"] - inf["n_items_early"] if dname == "near" else None)
     roofline = {"bound": roof["bound"], "kernel": f"{dk}:{dname}", "achieved": round(achieved / 1e12, 3),
                 "peak": round(roof["peak"] / 1e12, 1), "unit": roof["unit"],
                 "frac": round(achieved / roof["peak"], 4), "traffic": traffic,
-                "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_launch": flops}
+                "avg_launch_ms": round(avg_ms, 4), "launches_timed": dcnt,
+                "ms_per_step_with_events": round(dt_ev / args.steps * 1e3, 4),
+                "algorithmic_flop_per_launch": flops}
+    ems, ecnt = prof[dk].get("near_early", (0.0, 0))
+    if dname == "near" and ecnt:
+        # the early launch (the shortest items on a small grid, beside the
+        # upward passes and the M2L): its own pairs over its own duration
+        ep = float(inf["n_p2p_early"])
+        roofline["early_launch"] = {
+            "pairs": int(ep), "avg_launch_ms": round(ems / ecnt, 4), "launches_timed": ecnt,
+            "achieved": round(ep * FLOP_PER_PAIR_SURVEY / (ems / ecnt * 1e-3) / 1e12, 3),
+            "note": "runs on near_early_grid waves beside the upward passes and the M2L, so its duration "
+                    "is set by the GPU it shares, not by its own rate"}
     if dname in ("near", "far"):
         fused = flops / FLOP_PER_PAIR_SURVEY * FLOP_PER_PAIR["pair"]
         roofline.update({
@@ -799,7 +852,7 @@ def main():
                                                                 "setup_lists_ms", "setup_items_ms", "setup_ops_ms")}
                      | {"tree_shared": infos[k]["tree_shared"]} for k in infos},
         "tree": {k: {kk: infos[k][kk] for kk in ("n_boxes", "n_leaves", "max_level", "n_v_pairs", "n_u_pairs",
-                                                   "n_w_pairs", "n_x_pairs", "n_p2p_interactions", "n_far_interactions",
+                                                   "n_w_pairs", "n_x_pairs", "n_p2p_interactions", "n_p2p_early", "n_far_interactions",
                                                    "rank_up", "rank_down")} for k in infos},
     }
     print(json.dumps(line), flush=True)

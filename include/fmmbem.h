@@ -271,6 +271,11 @@ typedef struct {
   int32_t chain_timeouts; /* nonzero: a wait of a chained launch (gemm_chain) led by this plan hit its
                              bound, and the evaluation it belonged to is not valid (never expected:
                              the chain drains by construction; fmm_info synchronises to read it) */
+  int64_t n_p2p_early;    /* of n_p2p_interactions, those in the near-field items that a pair
+                             evaluation led by this plan starts early (tunable near_early); the
+                             rest run in the main near-field launch */
+  int32_t n_items;        /* leaf work items: waves of the near- and far-field launches */
+  int32_t n_items_early;  /* of those, the items started early (the early launch loops over them) */
 } fmm_info_t;
 
 int fmm_info(const fmm_plan *plan, fmm_info_t *out);
@@ -313,8 +318,9 @@ enum {
   FMM_PHASE_LEAF = 9,    /* P2P + M2P + L2P at the leaves, unpermute, 1/(4 pi) */
   FMM_PHASE_NEAR = 10,   /* fmm_eval_pair: P2P of both kernels (first plan's timer) */
   FMM_PHASE_FAR = 11,    /* fmm_eval_pair: M2P + L2P of both kernels, unpermute */
-  FMM_PHASE_COUNT = 12,
-  FMM_PHASE_ALL = 0xfff,
+  FMM_PHASE_NEAR_EARLY = 12, /* fmm_eval_pair: the near-field items started early (near_early) */
+  FMM_PHASE_COUNT = 13,
+  FMM_PHASE_ALL = 0x1fff,
   /* flag in the fmm_set_profiling mask: pair evaluations led by this plan
    * run every pass on the caller's stream, one after the other (no side
    * stream), so that each phase's time is its own and not stretched by the

@@ -18,7 +18,8 @@ FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOTCONV, FMM_EBREAKDOWN = 0, -1, 
 BEM_RHS_SCRATCH_DOUBLES = 1 << 23
 FMM_PROFILE_SERIAL = 0x10000
 
-PHASES = ["permute", "p2m", "uc2e", "m2m", "p2l", "m2l", "m2l_sum", "l2l", "dc2e", "leaf", "near", "far"]
+PHASES = ["permute", "p2m", "uc2e", "m2m", "p2l", "m2l", "m2l_sum", "l2l", "dc2e", "leaf", "near", "far",
+          "near_early"]
 
 STATUS_NAMES = {0: "FMM_OK", -1: "FMM_EINVAL", -2: "FMM_ENOMEM", -3: "FMM_EHIP", -4: "FMM_ENOTCONV",
                 -5: "FMM_EBREAKDOWN"}
@@ -39,7 +40,8 @@ class FmmInfo(ctypes.Structure):
         ("n_far_interactions", ctypes.c_int64), ("rank_up", ctypes.c_int32), ("rank_down", ctypes.c_int32),
         ("setup_sort_ms", ctypes.c_double), ("setup_tree_ms", ctypes.c_double), ("setup_lists_ms", ctypes.c_double),
         ("setup_items_ms", ctypes.c_double), ("setup_ops_ms", ctypes.c_double), ("tree_on_device", ctypes.c_int32),
-        ("tree_shared", ctypes.c_int32), ("chain_timeouts", ctypes.c_int32),
+        ("tree_shared", ctypes.c_int32), ("chain_timeouts", ctypes.c_int32), ("n_p2p_early", ctypes.c_int64),
+        ("n_items", ctypes.c_int32), ("n_items_early", ctypes.c_int32),
     ]
 
 

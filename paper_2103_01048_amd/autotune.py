@@ -29,9 +29,12 @@ Tunables (fmm_set_tuning; defaults in DEFAULTS):
                               slower on every workload measured)
 
 The search is coordinate descent: ncrit first (with the defaults), then the
-work cap, the tile splits, the surface weight and the GEMM row blocks, each
-stage keeping the fastest value when it beats the current one by more than
-1% (the spread of repeated timings).  Plans built during a stage share their tree
+work cap, the tile splits, the surface weight, the GEMM forms and the pass
+order, each stage keeping the fastest value when it beats the current one by
+more than 1% (the spread of repeated timings).  The tunables interact with
+ncrit (the early near-field split gains most at larger leaves), so the two
+fastest ncrit values each run the stages, and their final settings are timed
+again side by side.  Plans built during a stage share their tree
 (same ncrit and item parameters) or their operators (same ncrit) with the
 live plans of the search, so a trial costs little more than its timing."""
 from __future__ import annotations
@@ -55,6 +58,7 @@ DEFAULTS = {"tile_split2": 32, "tile_split4": 16, "work_cap_min": 512, "work_cap
             "gemm_chain": 0, "m2l_cols": 64,
             "gemm_narrow": 0, "near_early": 0, "near_early_grid": 1024}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2103_01048_amd", "tuning.json")
+SHIPPED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_table.json")
 
 STAGES = (
     ("work_cap_div", [{"work_cap_div": v} for v in (8192, 16384, 32768, 65536, 131072)]),
@@ -100,10 +104,28 @@ def tuning(**kw):
         set_tuning(**old)
 
 
+def device_tag(device=None) -> str:
+    """The device as the tuning entries name it: its ISA and compute-unit
+    count (the marketing name is not reliable on every driver install)."""
+    if not torch.cuda.is_available():
+        return "cpu"
+    pr = torch.cuda.get_device_properties(device)
+    arch = (getattr(pr, "gcnArchName", "") or pr.name).split(":")[0]
+    return f"{arch}x{pr.multi_processor_count}cu"
+
+
 def cache_key(n: int, p: int, precision: str, device=None, nmol: int = 1) -> str:
-    name = torch.cuda.get_device_name(device) if torch.cuda.is_available() else "cpu"
     batch = f"|mol~2^{round(math.log2(nmol))}" if nmol > 1 else ""
-    return f"{name}|{precision}|p{p}|n~2^{round(math.log2(max(n, 1)))}{batch}"
+    return f"{device_tag(device)}|{precision}|p{p}|n~2^{round(math.log2(max(n, 1)))}{batch}"
+
+
+def shipped_table() -> dict:
+    """Tuning entries that ship with the package (the autotuner's choice for
+    the workloads it was run on), consulted after the user's cache."""
+    try:
+        return json.load(open(SHIPPED_TABLE))
+    except (OSError, ValueError):
+        return {}
 
 
 def _time_pair(xt, q, p, ncrit, precision, kappa, steps, warmup, keep, offsets=None, repeats=3):
@@ -126,12 +148,18 @@ def _time_pair(xt, q, p, ncrit, precision, kappa, steps, warmup, keep, offsets=N
 def autotune(points: torch.Tensor, p: int = 8, precision: str = "bf16x3", kappa: float = 0.125,
              ncrit_candidates=(64, 96, 128, 160, 192, 256), q: torch.Tensor | None = None, steps: int = 10,
              warmup: int = 10, cache_path: str | None = DEFAULT_CACHE, use_cache: bool = True,
-             log=None, offsets=None, repeats: int = 3) -> dict:
+             log=None, offsets=None, repeats: int = 3, width: int = 2) -> dict:
     """Fastest (ncrit, tunables) for pair evaluations on `points` ((N, 3)
     float64 CUDA tensor; with `offsets`, a batch of molecules as FMMPlan
     takes it).  Each trial is the best of `repeats` timings of `steps` pair
-    evaluations.  Returns {"key", "ncrit", "tuning", "ms", "trials",
-    "cached"}; the tunables in force are left unchanged (see apply)."""
+    evaluations.  Every ncrit candidate is timed with the defaults;
+    the `width` fastest run the stages of coordinate descent each, and the
+    fastest of their final settings, timed again side by side, is chosen.
+    With use_cache, an entry for this workload in the user's cache
+    (cache_path) or else in the package's shipped table is returned without
+    a search.  Returns {"key", "ncrit", "tuning", "ms", "trials", "cached"}
+    ("source" for a cached entry); the tunables in force are left unchanged
+    (see apply)."""
     n = int(points.shape[0])
     nmol = 1 if offsets is None else len(offsets) - 1
     key = cache_key(n, p, precision, points.device, nmol)
@@ -142,7 +170,12 @@ def autotune(points: torch.Tensor, p: int = 8, precision: str = "bf16x3", kappa:
         except (OSError, ValueError):
             cache = {}
     if use_cache and key in cache:
-        return {**cache[key], "key": key, "cached": True}
+        return {**cache[key], "key": key, "cached": True, "source": cache_path}
+    shipped = shipped_table() if use_cache else {}
+    if key in shipped:
+        e = shipped[key]
+        return {"ncrit": e["ncrit"], "tuning": {**DEFAULTS, **e["tuning"]}, "ms": e.get("ms"), "key": key,
+                "cached": True, "source": "shipped table"}
     xt = points.detach().to(torch.float64).contiguous()
     if q is None:
         g = torch.Generator(device="cpu").manual_seed(0)
@@ -151,34 +184,46 @@ def autotune(points: torch.Tensor, p: int = 8, precision: str = "bf16x3", kappa:
     trials = []
     old = get_tuning()
     keep = []
-    try:
-        best_t = dict(DEFAULTS)
-        set_tuning(**best_t)
-        best_ms, best_nc = float("inf"), None
-        for nc in ncrit_candidates:
-            ms = _time_pair(xt, q, p, nc, precision, kappa, steps, warmup, keep, offsets, repeats)
-            trials.append({"stage": "ncrit", "ncrit": nc, "tuning": dict(best_t), "ms": round(ms, 4)})
-            if log:
-                log(f"ncrit {nc}: {ms:.4f} ms")
-            if best_nc is None or ms < 0.99 * best_ms:
-                best_ms, best_nc = ms, nc
-        for stage, cands in STAGES:
-            keep = [pl for pl in keep if pl.ncrit == best_nc]
+
+    def trial(stage, nc, t):
+        set_tuning(**t)
+        ms = _time_pair(xt, q, p, nc, precision, kappa, steps, warmup, keep, offsets, repeats)
+        trials.append({"stage": stage, "ncrit": nc, "tuning": dict(t), "ms": round(ms, 4)})
+        if log:
+            log(f"{stage} ncrit {nc} {({k: v for k, v in t.items() if t[k] != DEFAULTS[k]})}: {ms:.4f} ms")
+        return ms
+
+    def descend(nc, ms0):
+        """The stages one after the other at this ncrit, from the defaults."""
+        nonlocal keep
+        best_t, best_ms = dict(DEFAULTS), ms0
+        for stage, stage_cands in STAGES:
+            keep = [pl for pl in keep if pl.ncrit == nc]
             stage_best = (best_ms, None)
-            for c in cands:
+            for c in stage_cands:
                 t = {**best_t, **c}
                 if t == best_t:
                     continue
-                set_tuning(**t)
-                ms = _time_pair(xt, q, p, best_nc, precision, kappa, steps, warmup, keep, offsets, repeats)
-                trials.append({"stage": stage, "ncrit": best_nc, "tuning": t, "ms": round(ms, 4)})
-                if log:
-                    log(f"{stage} {c}: {ms:.4f} ms")
+                ms = trial(stage, nc, t)
                 if ms < 0.99 * stage_best[0]:
                     stage_best = (ms, t)
             if stage_best[1] is not None:
                 best_ms, best_t = stage_best
-            set_tuning(**best_t)
+        return best_t
+
+    try:
+        nc_ms = {nc: trial("ncrit", nc, DEFAULTS) for nc in ncrit_candidates}
+        ranked = sorted(nc_ms, key=nc_ms.get)
+        # the `width` fastest ncrit values (within 5% of the fastest) each
+        # run the stages; their final settings are timed again side by side
+        finalists = [nc for nc in ranked[:max(1, width)] if nc_ms[nc] <= 1.05 * nc_ms[ranked[0]]]
+        finals = [(nc, descend(nc, nc_ms[nc])) for nc in finalists]
+        if len(finals) == 1:
+            best_nc, best_t = finals[0]
+            best_ms = min(t["ms"] for t in trials if t["ncrit"] == best_nc and t["tuning"] == best_t)
+        else:
+            timed = [(trial("final", nc, t), nc, t) for nc, t in finals]
+            best_ms, best_nc, best_t = min(timed, key=lambda r: r[0])
     finally:
         del keep
         set_tuning(**old)

@@ -758,12 +758,16 @@ static int upload_lists(fmm_plan *P) {
   // the surface radius
   std::vector<int32_t> it4, no = {0}, nrng, fo = {0}, far;
   std::vector<double> near_o, far_o;
+  P->item_pairs.clear();
   for (const int32_t io : order) {
     const Item &it = items[io];
     const int64_t tb = leaves[it.slot];
     const std::vector<Rng> &inear = it.whole ? src[it.slot].near : it.near;
     const std::vector<int32_t> &ifar = it.whole ? src[it.slot].far : it.far;
     it4.push_back(it.slot); it4.push_back(it.code); it4.push_back(it.part); it4.push_back(0);
+    int64_t nsrc = 0;
+    for (auto &r : inear) nsrc += r.j1 - r.j0;
+    P->item_pairs.push_back(std::min<int64_t>(64, src[it.slot].m - (it.code & 0xffffff)) * nsrc);
     for (auto &r : inear) {
       nrng.push_back(r.j0); nrng.push_back(r.j1);
       for (int d = 0; d < 3; ++d) near_o.push_back(cen(r.src, d) - cen(tb, d));
@@ -1273,6 +1277,24 @@ hipEvent_t prof_begin(fmm_plan *P, int phase, hipStream_t s) {
   return e;
 }
 
+void prof_launch(fmm_plan *P, int phase, hipEvent_t *begin, hipEvent_t *end) {
+  *begin = *end = nullptr;
+  if (!((P->profiling >> phase) & 1)) return;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (hipEvent_t &e : ev) {
+    if (!P->event_pool.empty()) {
+      e = P->event_pool.back();
+      P->event_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      if (ev[0]) P->event_pool.push_back(ev[0]);
+      return;
+    }
+  }
+  P->prof_events.push_back({phase, {ev[0], ev[1]}});
+  *begin = ev[0];
+  *end = ev[1];
+}
+
 void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
   if (!P->profiling || !begin) return;
   hipEvent_t e = nullptr;
@@ -1363,7 +1385,7 @@ static int share_tree(fmm_plan *P, const fmm_plan *A, hipStream_t s) {
   P->parent = A->parent; P->child_begin = A->child_begin; P->level_begin = A->level_begin; P->mol = A->mol;
   for (int k = 0; k < 4; ++k) { P->loff[k] = A->loff[k]; P->lidx[k] = A->lidx[k]; }
   P->leaf_ids = A->leaf_ids; P->vpair_src = A->vpair_src; P->vpair_tgt = A->vpair_tgt; P->p2l_boxes = A->p2l_boxes;
-  P->p2p_inter = A->p2p_inter; P->far_inter = A->far_inter;
+  P->p2p_inter = A->p2p_inter; P->far_inter = A->far_inter; P->item_pairs = A->item_pairs;
   P->tree_mem = A->tree_mem;
   P->dt = A->dt;
   P->dt.pts = nullptr;
@@ -1661,6 +1683,10 @@ int fmm_info(const fmm_plan *P, fmm_info_t *o) {
   o->setup_ops_ms = P->setup_split[4];
   o->tree_on_device = P->tree_on_device;
   o->tree_shared = P->tree_shared;
+  const int nit = (int)P->item_pairs.size();
+  o->n_items = nit;
+  o->n_items_early = near_early_items(P->tune, nit, P->dt.maxlevel >= 2);
+  for (int i = nit - o->n_items_early; i < nit; ++i) o->n_p2p_early += P->item_pairs[i];
   if (P->chain_ctr && P->chain_ctr_n > 0) {
     int32_t e = 0;
     FMM_HIP_TRY(hipDeviceSynchronize());

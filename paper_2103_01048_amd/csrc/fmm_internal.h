@@ -24,6 +24,18 @@ void set_error(const std::string &msg);
 int plan_upload(fmm_plan *P, void **ptr, const void *h, size_t bytes);
 hipEvent_t prof_begin(fmm_plan *P, int phase, hipStream_t s);
 void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s);
+// Timing events for a phase that is a single kernel launch: the launch
+// carries them (hipExtLaunchKernelGGL), so no marker goes on the stream
+// beside it.  Both null when the phase is not being timed.
+void prof_launch(fmm_plan *P, int phase, hipEvent_t *begin, hipEvent_t *end);
+// Near-field items of a pair evaluation that start at once on the second
+// side stream: near_early per mille of the items (the shortest, at the tail
+// of the item list), with pass order 3 and a far field only.
+inline int near_early_items(const fmm_tuning_t &t, int nitems, bool far) {
+  return (far && t.pair_order == 3 && t.near_early > 0)
+             ? (int)std::min<int64_t>(nitems, (int64_t)nitems * t.near_early / 1000)
+             : 0;
+}
 void pinv_tsvd(int n, const double *A, double tau, double *out);
 int tsvd_factors(int n, const double *A, double tau, double *UT, double *VS, int nthreads);
 int tsvd_split(int rows, int cols, const double *A, double tau, double *L, int ldl, double *R, int ldr);
@@ -185,6 +197,7 @@ struct fmm_plan {
   std::vector<int32_t> vpair_src, vpair_tgt;  // V pairs in GEMM order
   std::vector<int32_t> p2l_boxes;             // boxes whose X list goes through P2L
   int64_t p2p_inter = 0, far_inter = 0;
+  std::vector<int64_t> item_pairs;  // pair interactions (targets x near sources) per leaf item, in launch order
   // device
   fmm::DevTree dt;
   void *surf = nullptr;            // T4 grid offsets in [-1,1]^3, nsurf entries

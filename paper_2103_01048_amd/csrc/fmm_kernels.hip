@@ -11,6 +11,7 @@
 // Kernel arithmetic: every kernel evaluation omits the 1/(4 pi) of the
 // Green's functions (the matching equations are invariant to it); the final
 // write multiplies by 1/(4 pi).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -2397,9 +2398,7 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   // on a second side stream from the start, on a small grid of waves that
   // loop over them, beside the upward passes and the M2L
   const int nit = A->dt.nitems;
-  const int nearly = (far && order == 3 && A->tune.near_early > 0)
-                         ? std::min(nit, (int)((int64_t)nit * A->tune.near_early / 1000))
-                         : 0;
+  const int nearly = near_early_items(A->tune, nit, far);
   const int nmain = nit - nearly;
   const hipStream_t side2 = (A->profiling & FMM_PROFILE_SERIAL) ? s : A->aux2;
   if (far) {
@@ -2407,7 +2406,8 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
     FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_fork, 0));
     if (nearly > 0) {
       FMM_HIP_TRY(hipStreamWaitEvent(side2, A->ev_fork, 0));
-      if ((rc = near(side2, nmain, nearly, std::min(nearly, A->tune.near_early_grid)))) return rc;
+      if ((rc = near(side2, nmain, nearly, std::min(nearly, A->tune.near_early_grid), FMM_PHASE_NEAR_EARLY)))
+        return rc;
       FMM_HIP_TRY(hipEventRecord(A->ev_near, side2));
     }
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips))) return rc;
@@ -2429,7 +2429,7 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
       if (order == 1) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_up, 0));
     }
   }
-  if ((rc = near(s, 0, nmain, nmain))) return rc;
+  if ((rc = near(s, 0, nmain, nmain, FMM_PHASE_NEAR))) return rc;
   if (far) {
     if (order != 3 && (rc = pair_off_chain<T, NR>(A, B, s, dips, order == 0))) return rc;
     FMM_HIP_TRY(hipStreamWaitEvent(side, B->ev_join, 0));
@@ -2451,14 +2451,14 @@ static int eval_pair_chunk(fmm_plan *A, fmm_plan *B, const T *q, T *pot_a, T *gr
   const T kappa = (T)B->kappa;
   const T scale = (T)(1.0 / (4.0 * M_PI));
   T *acc = (T *)A->pair_acc;
-  auto near = [&](hipStream_t st, int i0, int cnt, int grid) -> int {
-    hipEvent_t e = prof_begin(A, FMM_PHASE_NEAR, st);
-    if (cnt > 0)
-      hipLaunchKernelGGL((k_near_pair<T, NR>), dim3(grid), dim3(64), A->tune.near_lds, st, D.items,
-                         D.leaves, (const T *)D.pts, (const T *)A->qs, N, D.box_begin, D.box_end, D.near_off,
-                         D.near_rng, (const T *)D.near_o, acc, kappa, cnt, i0);
+  auto near = [&](hipStream_t st, int i0, int cnt, int grid, int phase) -> int {
+    if (cnt <= 0) return FMM_OK;
+    hipEvent_t eb, ee;
+    prof_launch(A, phase, &eb, &ee);
+    hipExtLaunchKernelGGL((k_near_pair<T, NR>), dim3(grid), dim3(64), A->tune.near_lds, st, eb, ee, 0, D.items,
+                          D.leaves, (const T *)D.pts, (const T *)A->qs, N, D.box_begin, D.box_end, D.near_off,
+                          D.near_rng, (const T *)D.near_o, acc, kappa, cnt, i0);
     FMM_HIP_TRY(hipGetLastError());
-    prof_end(A, FMM_PHASE_NEAR, e, st);
     return FMM_OK;
   };
 
@@ -2538,20 +2538,19 @@ static int eval_pair_md_typed(fmm_plan *A, fmm_plan *B, const T *q, const T *dip
   const T kappa = (T)B->kappa;
   const T scale = (T)(1.0 / (4.0 * M_PI));
   T *acc = (T *)A->pair_acc;
-  auto near = [&](hipStream_t st, int i0, int cnt, int grid) -> int {
-    hipEvent_t e = prof_begin(A, FMM_PHASE_NEAR, st);
-    if (cnt > 0) {
-      if (grad)
-        hipLaunchKernelGGL((k_near_pair_md<T, true>), dim3(grid), dim3(64), A->tune.near_lds, st, D.items, D.leaves,
-                           (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
-                           (const T *)D.near_o, acc, kappa, cnt, i0);
-      else
-        hipLaunchKernelGGL((k_near_pair_md<T, false>), dim3(grid), dim3(64), A->tune.near_lds, st, D.items, D.leaves,
-                           (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off, D.near_rng,
-                           (const T *)D.near_o, acc, kappa, cnt, i0);
-    }
+  auto near = [&](hipStream_t st, int i0, int cnt, int grid, int phase) -> int {
+    if (cnt <= 0) return FMM_OK;
+    hipEvent_t eb, ee;
+    prof_launch(A, phase, &eb, &ee);
+    if (grad)
+      hipExtLaunchKernelGGL((k_near_pair_md<T, true>), dim3(grid), dim3(64), A->tune.near_lds, st, eb, ee, 0, D.items,
+                            D.leaves, (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off,
+                            D.near_rng, (const T *)D.near_o, acc, kappa, cnt, i0);
+    else
+      hipExtLaunchKernelGGL((k_near_pair_md<T, false>), dim3(grid), dim3(64), A->tune.near_lds, st, eb, ee, 0,
+                            D.items, D.leaves, (const T *)D.pts, (const T *)dips, D.box_begin, D.box_end, D.near_off,
+                            D.near_rng, (const T *)D.near_o, acc, kappa, cnt, i0);
     FMM_HIP_TRY(hipGetLastError());
-    prof_end(A, FMM_PHASE_NEAR, e, st);
     return FMM_OK;
   };
   if (A->tune.gemm_chain && D.maxlevel >= 2 && (rc = ensure_chains<T, 1>(A, B))) return rc;

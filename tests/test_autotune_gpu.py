@@ -162,3 +162,42 @@ def test_chained_level_launches_equal_per_level_launches(precision, p):
         ph = pls[0].phase_times()
         pls[0].set_profiling(False)
         assert (ph["m2m"][1] == 1 and ph["l2l"][1] == 1) == one, ph
+
+
+@pytest.mark.parametrize("near_early", [0, 500])
+def test_timed_near_launch_leaves_results_unchanged(near_early):
+    """Timing the near field (its launches carry the timing events) counts
+    one timed main launch per pair evaluation and, when the shortest items
+    start early, one early launch under a phase of its own; the durations
+    are positive and the results equal an untimed evaluation bit for bit.
+    fmm_info splits the items and their pair interactions between the two
+    launches."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, autotune as at, eval_pair
+    x = _cloud()
+    q = np.random.default_rng(137).standard_normal(len(x))
+    xt = torch.tensor(x, device="cuda")
+    qt = torch.tensor(q, device="cuda", dtype=torch.float32)
+    with at.tuning(near_early=near_early):
+        a = FMMPlan(xt, kernel="laplace", p=6, ncrit=48, precision="bf16x3")
+        b = FMMPlan(xt, kernel="yukawa", kappa=KAPPA, p=6, ncrit=48, precision="bf16x3")
+    inf = a.info()
+    assert inf["max_level"] >= 2 and inf["n_items"] > 0
+    assert inf["n_items_early"] == inf["n_items"] * near_early // 1000
+    if near_early:
+        assert 0 < inf["n_p2p_early"] < inf["n_p2p_interactions"]
+    else:
+        assert inf["n_p2p_early"] == 0
+    ref = [t.cpu().numpy() for o in eval_pair(a, b, qt) for t in o]
+    a.set_profiling(["near", "near_early"])
+    a.phase_times()
+    for _ in range(3):
+        got = [t.cpu().numpy() for o in eval_pair(a, b, qt) for t in o]
+        for r, g in zip(ref, got):
+            assert np.array_equal(r, g)
+    ph = a.phase_times()
+    a.set_profiling(False)
+    assert ph["near"][1] == 3 and ph["near"][0] > 0.0, ph
+    assert ph["near_early"][1] == (3 if near_early else 0), ph
+    assert (ph["near_early"][0] > 0.0) == bool(near_early), ph
+    assert all(c == 0 for k, (_, c) in ph.items() if k not in ("near", "near_early")), ph
