@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstring>
 #include <atomic>
+#include <array>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -1079,9 +1080,11 @@ int ensure_lists(fmm_plan *P, int nr) {
                       (int)(P->anchor[3 * a + 2] - P->anchor[3 * t + 2]));
     };
     int64_t i = 0;
+    L.m2l_t0.assign((size_t)maxl + 2, -1);
     while (i < np) {
       const int l = P->level[P->vpair_tgt[i]];
       const int code = code_of(i);
+      if (L.m2l_t0[l] < 0) L.m2l_t0[l] = (int)L.m2l.h_tasks.size();
       int64_t j = i;
       src.clear(); dst.clear();
       while (j < np && P->level[P->vpair_tgt[j]] == l && code_of(j) == code) {
@@ -1123,6 +1126,10 @@ int ensure_lists(fmm_plan *P, int nr) {
       i = j;
     }
   }
+  if (L.m2l_t0.size() != (size_t)maxl + 2) L.m2l_t0.assign((size_t)maxl + 2, -1);
+  L.m2l_t0[maxl + 1] = (int)L.m2l.h_tasks.size();
+  for (int l = maxl; l >= 0; --l)
+    if (L.m2l_t0[l] < 0) L.m2l_t0[l] = L.m2l_t0[l + 1];
   if ((rc = finish_batch(P, L.m2l))) return rc;
   if (fact && (rc = finish_batch(P, L.m2l_r))) return rc;
   if (!P->d_m2l_rows) {
@@ -1163,37 +1170,40 @@ static uint64_t tree_fingerprint(const fmm_plan *P) {
   return h;
 }
 
-// Side streams of pair evaluations: two per device for the whole process
+// Side streams of pair evaluations: three per device for the whole process
 // (default priority, created on first use, kept until the process ends).
-// Every plan pair on a device queues its far-field passes and its early
-// near-field items on the same two streams, so the hardware queues the
+// Every plan pair on a device queues its far-field passes, its early
+// near-field items and its early M2L levels on the same three streams, so the hardware queues the
 // library takes do not grow with the number of live plans.  HIP spreads
 // streams over a small pool of hardware queues (four by default); with
 // streams of their own, the plans set up after enough others had theirs land
 // on the caller's queue, and their side passes then wait behind the near
 // field instead of running beside it.
 static std::mutex g_side_mu;
-static std::map<int, std::pair<hipStream_t, hipStream_t>> g_side;
+static std::map<int, std::array<hipStream_t, 3>> g_side;
 
-static int side_streams(int device, hipStream_t *aux, hipStream_t *aux2) {
+static int side_streams(int device, hipStream_t *aux, hipStream_t *aux2, hipStream_t *aux3) {
   std::lock_guard<std::mutex> lock(g_side_mu);
   auto it = g_side.find(device);
   if (it == g_side.end()) {
     int cur = 0;
     FMM_HIP_TRY(hipGetDevice(&cur));
     if (cur != device) FMM_HIP_TRY(hipSetDevice(device));
-    hipStream_t a = nullptr, b = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b, hipStreamNonBlocking);
+    std::array<hipStream_t, 3> st{nullptr, nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (hipStream_t &x : st)
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
     if (cur != device) (void)hipSetDevice(cur);
     if (e != hipSuccess) {
-      if (a) (void)hipStreamDestroy(a);
+      for (hipStream_t x : st)
+        if (x) (void)hipStreamDestroy(x);
       FMM_HIP_TRY(e);
     }
-    it = g_side.emplace(device, std::make_pair(a, b)).first;
+    it = g_side.emplace(device, st).first;
   }
-  *aux = it->second.first;
-  *aux2 = it->second.second;
+  *aux = it->second[0];
+  *aux2 = it->second[1];
+  *aux3 = it->second[2];
   return FMM_OK;
 }
 
@@ -1203,15 +1213,17 @@ static int side_streams(int device, hipStream_t *aux, hipStream_t *aux2) {
 // the end of the surface passes and of the P2L projections, and A's buffer of
 // near-field running sums for nr columns.
 int ensure_pair(fmm_plan *A, fmm_plan *B, int nr) {
-  if (!A->aux || !A->aux2) {
+  if (!A->aux || !A->aux2 || !A->aux3) {
     int rc;
-    if ((rc = side_streams(A->device, &A->aux, &A->aux2))) return rc;
+    if ((rc = side_streams(A->device, &A->aux, &A->aux2, &A->aux3))) return rc;
   }
   if (!A->ev_near) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_near, hipEventDisableTiming));
   if (!A->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_fork, hipEventDisableTiming));
   if (!A->ev_join) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_join, hipEventDisableTiming));
   if (!A->ev_up) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_up, hipEventDisableTiming));
   if (!A->ev_m2l) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_m2l, hipEventDisableTiming));
+  if (!A->ev_m2m) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_m2m, hipEventDisableTiming));
+  if (!A->ev_m2lf) FMM_HIP_TRY(hipEventCreateWithFlags(&A->ev_m2lf, hipEventDisableTiming));
   if (!B->ev_fork) FMM_HIP_TRY(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
   if (!B->ev_join) FMM_HIP_TRY(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
   const size_t es = A->precision == FMM_FP64 ? 8 : 4;
@@ -1310,7 +1322,7 @@ void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
 
 // Tunables for plans set up from now on (fmm_set_tuning).
 static std::mutex g_tune_mu;
-static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0, 0, 1024};
+static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0, 0, 1024, 0};
 
 // Live plans whose tree later plans on the same points may share.
 static std::mutex g_tree_mu;
@@ -1737,7 +1749,8 @@ int fmm_set_tuning(const fmm_tuning_t *t) {
       t->pair_order > 3 || t->near_lds < 0 || t->near_lds > 65536 ||
       t->gemm_lat < 0 || t->gemm_lat > (1 << 20) || t->gemm_chain < 0 || t->gemm_chain > 1 ||
       (t->m2l_cols != 64 && t->m2l_cols != 128) || t->gemm_narrow < 0 || t->gemm_narrow > 1 ||
-      t->near_early < 0 || t->near_early > 900 || t->near_early_grid < 64 || t->near_early_grid > 65536) {
+      t->near_early < 0 || t->near_early > 900 || t->near_early_grid < 64 || t->near_early_grid > 65536 ||
+      t->m2l_early < 0 || t->m2l_early > 1) {
     set_error("fmm_set_tuning: value out of range");
     return FMM_EINVAL;
   }
@@ -1785,9 +1798,9 @@ void fmm_free(fmm_plan *P) {
   unregister_tree(P);
   for (auto &pe : P->prof_events) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
   for (hipEvent_t e : P->event_pool) (void)hipEventDestroy(e);
-  for (hipStream_t st : {P->aux, P->aux2})  // the device's shared side streams: wait, keep
+  for (hipStream_t st : {P->aux, P->aux2, P->aux3})  // the device's shared side streams: wait, keep
     if (st) (void)hipStreamSynchronize(st);
-  for (hipEvent_t e : {P->ev_fork, P->ev_join, P->ev_up, P->ev_m2l, P->ev_near})
+  for (hipEvent_t e : {P->ev_fork, P->ev_join, P->ev_up, P->ev_m2l, P->ev_near, P->ev_m2m, P->ev_m2lf})
     if (e) (void)hipEventDestroy(e);
   for (void *p : P->allocs) (void)hipFree(p);
   delete P;

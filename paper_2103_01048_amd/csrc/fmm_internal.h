@@ -127,6 +127,8 @@ struct PassLists {
   GemmBatch vs_d;               // c_d -> downward equivalent (leaves), all levels
   GemmBatch m2l;                // all levels, c_u -> pair slots of c_d (factored: intermediate -> slots)
   GemmBatch m2l_r;              // factored M2L: c_u -> per-pair intermediate (R factors)
+  std::vector<int> m2l_t0;      // per level (0 .. maxlevel + 1): the first M2L task of that level (tasks
+                                // ascend by level; entry maxlevel + 1 = the task count)
 };
 
 struct DevTree {
@@ -234,8 +236,10 @@ struct fmm_plan {
   std::vector<hipEvent_t> event_pool;
   // pair evaluation (this plan as the Laplace half): side stream, fork and
   // join events, and the near-field running sums of both kernels
-  hipStream_t aux = nullptr, aux2 = nullptr;  // the device's shared side streams: far passes; early near items
+  // the device's shared side streams: far passes; early near items; early M2L levels
+  hipStream_t aux = nullptr, aux2 = nullptr, aux3 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_up = nullptr, ev_m2l = nullptr, ev_near = nullptr;
+  hipEvent_t ev_m2m = nullptr, ev_m2lf = nullptr;  // the first M2M level done; the early M2L levels done
   void *pair_acc = nullptr;
   size_t pair_acc_bytes = 0;
   void *dips = nullptr;             // monopole + dipole sources: dipole records in Morton order
@@ -253,7 +257,7 @@ struct fmm_plan {
   double setup_ms = 0;
   double setup_split[5] = {0, 0, 0, 0, 0};  // sort, tree, lists, items, operators (ms)
   int tree_on_device = 0, tree_shared = 0;
-  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0, 0, 1024};  // tunables in force at setup
+  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0, 0, 1024, 0};  // tunables in force at setup
   std::vector<void *> allocs;      // everything to free
   std::shared_ptr<fmm::SharedAllocs> tree_mem;  // the tree's device buffers (shared with plans on the same points)
   std::shared_ptr<fmm::SharedAllocs> ops_mem;   // translation operators (shared with plans of the same kernel on the same tree)

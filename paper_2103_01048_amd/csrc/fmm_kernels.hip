@@ -2169,7 +2169,7 @@ static int launch_chain(const Chain &C, int32_t *ctr, int32_t *err, hipStream_t 
 
 template <typename T, int NR>
 static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, hipEvent_t surf_done,
-                            hipEvent_t up_done, const T *dips = nullptr) {
+                            hipEvent_t up_done, const T *dips = nullptr, hipStream_t s3 = nullptr) {
   const DevTree &D = A->dt;
   const int64_t N = A->n;
   const int ld = A->ld;
@@ -2187,6 +2187,22 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, h
           *chain_err = A->chain_ctr + A->chain_ctr_n - 1;
   if (part == 2) goto down;
   {
+  // m2l_early: the M2L of the levels >= ls runs on s3 once the M2M into
+  // level ls is done (the upward coordinates of every box at those levels
+  // are then final), beside the coarser M2M levels; the coarser levels' M2L
+  // follows on s, which then waits for s3.  M2L tasks ascend by level.
+  const bool fact = LA.m2l_r.ntask > 0 || LB.m2l_r.ntask > 0;
+  const int ls = D.maxlevel - 1;
+  const bool m2l_early = s3 && A->tune.m2l_early && !chain && !fact && ls >= 2 &&
+                         LA.m2l_t0.size() == (size_t)D.maxlevel + 2 && LB.m2l_t0.size() == (size_t)D.maxlevel + 2;
+  auto m2l_levels = [&](int l0, int l1, hipStream_t st) -> int {  // the M2L of levels [l0, l1)
+    GemmBatch a = LA.m2l, b = LB.m2l;
+    a.d_tasks += LA.m2l_t0[l0];
+    a.ntask = LA.m2l_t0[l1] - LA.m2l_t0[l0];
+    b.d_tasks += LB.m2l_t0[l0];
+    b.ntask = LB.m2l_t0[l1] - LB.m2l_t0[l0];
+    return launch_gemm2<T>(A, a, W(A->cu), W(A->pairbuf), B, &b, W(B->cu), W(B->pairbuf), st);
+  };
   if (chain) {
     hipLaunchKernelGGL(k_fill_zero<int32_t>, dim3(1), dim3(256), 0, s, A->chain_ctr, (int64_t)A->chain_ctr_n - 1);
     FMM_HIP_TRY(hipGetLastError());
@@ -2216,20 +2232,33 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, h
     prof_end(A, FMM_PHASE_M2M, ev, s);
   }
   for (int l = D.maxlevel - 1; l >= 2 && !(chain && A->chain_up.ntask); --l) {
-    if (!LA.m2m[l].ntask) continue;
-    ev = prof_begin(A, FMM_PHASE_M2M, s);
-    if ((rc = launch_gemm2<T>(A, LA.m2m[l], W(A->cu), W(A->mslot), B, &LB.m2m[l], W(B->cu), W(B->mslot), s)))
-      return rc;
-    hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.m2m_n[l], 2), dim3(64), 0, s, D.m2m_tgt[l], D.m2m_off[l],
-                       D.m2m_kid[l], (const T *)A->mslot, W(A->cu), NR, ld, ld, LA.m2m[l].nrb * 16,
-                       (const T *)B->mslot, W(B->cu), ld, LB.m2m[l].nrb * 16, (const int32_t *)nullptr,
-                       (const int32_t *)nullptr, (const T *)nullptr, (const T *)nullptr);
-    FMM_HIP_TRY(hipGetLastError());
-    prof_end(A, FMM_PHASE_M2M, ev, s);
+    if (LA.m2m[l].ntask) {
+      ev = prof_begin(A, FMM_PHASE_M2M, s);
+      if ((rc = launch_gemm2<T>(A, LA.m2m[l], W(A->cu), W(A->mslot), B, &LB.m2m[l], W(B->cu), W(B->mslot), s)))
+        return rc;
+      hipLaunchKernelGGL(k_pair_reduce<T>, dim3(D.m2m_n[l], 2), dim3(64), 0, s, D.m2m_tgt[l], D.m2m_off[l],
+                         D.m2m_kid[l], (const T *)A->mslot, W(A->cu), NR, ld, ld, LA.m2m[l].nrb * 16,
+                         (const T *)B->mslot, W(B->cu), ld, LB.m2m[l].nrb * 16, (const int32_t *)nullptr,
+                         (const int32_t *)nullptr, (const T *)nullptr, (const T *)nullptr);
+      FMM_HIP_TRY(hipGetLastError());
+      prof_end(A, FMM_PHASE_M2M, ev, s);
+    }
+    if (m2l_early && l == ls) {
+      FMM_HIP_TRY(hipEventRecord(A->ev_m2m, s));
+      FMM_HIP_TRY(hipStreamWaitEvent(s3, A->ev_m2m, 0));
+      ev = prof_begin(A, FMM_PHASE_M2L, s3);
+      if ((rc = m2l_levels(ls, D.maxlevel + 1, s3))) return rc;
+      prof_end(A, FMM_PHASE_M2L, ev, s3);
+      FMM_HIP_TRY(hipEventRecord(A->ev_m2lf, s3));
+    }
   }
   if (up_done) FMM_HIP_TRY(hipEventRecord(up_done, s));
   ev = prof_begin(A, FMM_PHASE_M2L, s);
-  {
+  if (m2l_early) {
+    if ((rc = m2l_levels(0, ls, s))) return rc;
+    prof_end(A, FMM_PHASE_M2L, ev, s);
+    FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_m2lf, 0));
+  } else {
     // a factored plan first maps its upward coordinates through R (one
     // launch for the factored plans), then every plan's L (or dense operator)
     // writes the pair slots
@@ -2241,8 +2270,8 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, h
     if ((rc = launch_gemm2<T>(A, LA.m2l, fa ? W(A->m2l_t) : W(A->cu), W(A->pairbuf), B, &LB.m2l,
                               fb ? W(B->m2l_t) : W(B->cu), W(B->pairbuf), s)))
       return rc;
+    prof_end(A, FMM_PHASE_M2L, ev, s);
   }
-  prof_end(A, FMM_PHASE_M2L, ev, s);
   }
   if (part == 1) return FMM_OK;
 down:
@@ -2401,6 +2430,7 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   const int nearly = near_early_items(A->tune, nit, far);
   const int nmain = nit - nearly;
   const hipStream_t side2 = (A->profiling & FMM_PROFILE_SERIAL) ? s : A->aux2;
+  const hipStream_t side3 = (A->profiling & FMM_PROFILE_SERIAL) ? s : A->aux3;
   if (far) {
     FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
     FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_fork, 0));
@@ -2410,7 +2440,7 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
         return rc;
       FMM_HIP_TRY(hipEventRecord(A->ev_near, side2));
     }
-    if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips))) return rc;
+    if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips, side3))) return rc;
     if (order == 3) FMM_HIP_TRY(hipEventRecord(A->ev_m2l, side));
     // the near field starts once P2M (VALU, like the near field) is done and
     // shares the GPU with the GEMM passes; P2L and its projection (which the

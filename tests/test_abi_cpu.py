@@ -128,7 +128,8 @@ def test_tuning_roundtrip_and_range_checks():
                 {"far_weight": 0.0}, {"far_weight": float("nan")}, {"gemm_rbw": 9}, {"gemm_rbw": -1},
                 {"m2l_factored": 2}, {"pair_order": 4}, {"pair_order": -1}, {"near_lds": 65537},
                 {"near_lds": -1}, {"gemm_lat": -1}, {"gemm_lat": (1 << 20) + 1},
-                {"gemm_chain": 2}, {"m2l_cols": 96}, {"m2l_cols": 0}, {"gemm_narrow": 2}, {"near_early": 901}, {"near_early_grid": 63}):
+                {"gemm_chain": 2}, {"m2l_cols": 96}, {"m2l_cols": 0}, {"gemm_narrow": 2}, {"near_early": 901}, {"near_early_grid": 63},
+                {"m2l_early": 2}, {"m2l_early": -1}):
         with pytest.raises(_lib.FmmError):
             at.set_tuning(**bad)
         assert at.get_tuning() == before

@@ -50,6 +50,8 @@ def _pair(xt, q, ncrit=48):
     {"gemm_narrow": 1, "pair_order": 3},
     {"near_early": 300},
     {"near_early": 900, "near_early_grid": 64},
+    {"m2l_early": 1},
+    {"m2l_early": 1, "near_early": 500, "gemm_narrow": 1},
 ])
 def test_every_setting_gives_the_same_fmm(setting):
     torch = require_gpu()
