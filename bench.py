@@ -192,7 +192,15 @@ def parse():
                     help="write a profile summary from rocprofv3 output (kernel-trace --stats, then --pmc "
                          "FETCH_SIZE and --pmc WRITE_SIZE runs of the same command) and the per-kernel HBM "
                          "bytes the bench line reads; no GPU work")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_DIR",
+                    help="write a counter summary (median per kernel over its dispatches) from rocprofv3 --pmc "
+                         "runs of one command, one directory per counter set; no GPU work")
+    ap.add_argument("--summary-note", action="append", default=[],
+                    help="a paragraph appended to a counter summary (repeat)")
     ap.add_argument("--summary-out", default="profiles/fmm_eval_pair_sphere_union_393k_p8.md")
+    ap.add_argument("--traffic-out", default="",
+                    help="per-kernel HBM bytes of --summarize-profile (default: profiles/traffic.json, which the "
+                         "bench line reads)")
     ap.add_argument("--summary-title", default="")
     ap.add_argument("--summary-cmd", action="append", default=[],
                     help="the command of each rocprofv3 run, recorded in the summary (repeat)")
@@ -531,14 +539,85 @@ def summarize_profile(args):
     rec = {"kernels_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
            "profile": os.path.basename(out_md), "fetch_scale": f_scale, "write_scale": w_scale,
            "traffic": {k: {"read_bytes": t["read_bytes"], "write_bytes": t["write_bytes"]} for k, t in traffic.items()}}
-    json.dump(rec, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
-    print(f"wrote {out_md} and profiles/traffic.json ({len(traffic)} kernels)")
+    traffic_out = args.traffic_out or os.path.join(ROOT, "profiles", "traffic.json")
+    json.dump(rec, open(traffic_out, "w"), indent=1)
+    print(f"wrote {out_md} and {traffic_out} ({len(traffic)} kernels)")
+
+
+def summarize_counters(args):
+    """Counter summary (markdown) from rocprofv3 --pmc runs of one command:
+    per kernel (the near-field kernel also per grid), the median over its
+    dispatches of every counter collected, the fraction of SIMD cycles with
+    the MFMA unit busy (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE / 8 XCDs
+    x 1,024 SIMDs) and the L2 hit rate, when those counters are there."""
+    per = {}
+    names = []
+    for d in args.summarize_counters:
+        for r in _csv_rows(d, "counter_collection.csv"):
+            k = _kname(r["Kernel_Name"])
+            keys = [k]
+            if any(g in k for g in GRID_SPLIT):
+                keys.append(f"{k} @{int(r['Grid_Size']) // max(1, int(r['Workgroup_Size']))}")
+            c = r["Counter_Name"]
+            if c not in names:
+                names.append(c)
+            for kk in keys:
+                per.setdefault(kk, {}).setdefault(c, {})[(d, r["Dispatch_Id"])] = float(r["Counter_Value"])
+    med = lambda v: float(np.median(list(v.values()))) if v else float("nan")
+    # a kernel launched with one grid only needs no per-grid row
+    grids = {}
+    for k in per:
+        if " @" in k:
+            grids.setdefault(k.split(" @")[0], []).append(k)
+    for base, ks in grids.items():
+        # one grid: its row equals the kernel's; several: the kernel's own
+        # row would be a median over launches of different kinds
+        del per[ks[0] if len(ks) == 1 else base]
+    rows = []
+    for k, cs in per.items():
+        if "fmm::" not in k:
+            continue
+        gui = med(cs.get("GRBM_GUI_ACTIVE", {}))
+        n = max(len(v) for v in cs.values())
+        rows.append((k, n, gui, cs))
+    rows.sort(key=lambda r: -(r[2] if r[2] == r[2] else 0) * r[1])
+    lines = [f"# rocprofv3 counters: {args.summary_title or os.path.basename(args.summary_out)}", "",
+             "Commands (from the repository root, TMPDIR=/tmp; one run per counter set):", ""]
+    lines += [f"    {c}" for c in args.summary_cmd] + [""]
+    lines += ["Medians over the dispatches of each kernel in the runs (the counter runs serialise kernels). "
+              "GRBM_GUI_ACTIVE is summed over the eight XCDs; SIMD cycles = GRBM_GUI_ACTIVE / 8 x 1,024 SIMDs.", ""]
+    derived = []
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in names and "GRBM_GUI_ACTIVE" in names:
+        derived.append("MFMA busy / SIMD cycles")
+    if "TCC_HIT_sum" in names and "TCC_MISS_sum" in names:
+        derived.append("L2 hit")
+    cols = [c for c in names if c != "GRBM_GUI_ACTIVE"]
+    lines.append("| kernel | dispatches | GRBM_GUI_ACTIVE | " + " | ".join(cols + derived) + " |")
+    lines.append("|---|" + "---:|" * (2 + len(cols) + len(derived)))
+    for k, n, gui, cs in rows:
+        if not gui or gui != gui or gui < 1e4:
+            continue
+        vals = [f"{med(cs.get(c, {})):,.0f}" for c in cols]
+        if "MFMA busy / SIMD cycles" in derived:
+            vals.append(f"{med(cs.get('SQ_VALU_MFMA_BUSY_CYCLES', {})) / (gui / 8 * 1024):.3f}")
+        if "L2 hit" in derived:
+            h, m = med(cs.get("TCC_HIT_sum", {})), med(cs.get("TCC_MISS_sum", {}))
+            vals.append(f"{h / (h + m):.3f}" if h + m > 0 else "")
+        lines.append(f"| `{k[:100]}` | {n} | {gui:,.0f} | " + " | ".join(vals) + " |")
+    for note in args.summary_note:
+        lines += ["", note]
+    os.makedirs(os.path.dirname(os.path.abspath(args.summary_out)), exist_ok=True)
+    open(args.summary_out, "w").write("\n".join(lines) + "\n")
+    print(f"wrote {args.summary_out} ({len(rows)} kernels)")
 
 
 def main():
     args = parse()
     if args.summarize_profile:
         summarize_profile(args)
+        return
+    if args.summarize_counters:
+        summarize_counters(args)
         return
     if args.gpus != 1:
         print("bench.py: runs on one GPU; --gpus must be 1 "
