@@ -379,7 +379,23 @@ def run_bem(args):
     precond = args.precond or ("mass" if p1 else "block")
     qxyz, q = synth.charges_in_spheres(su, 20000, seed=91)
     print(f"# mesh {len(t)} triangles in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    ncrit = args.ncrit or 128
+    tuned = None
+    if args.ncrit:
+        ncrit = args.ncrit
+    else:
+        # ncrit and the library's tunables from the autotuner for pair
+        # evaluations on a cloud of 3 points per triangle (the size and
+        # distribution of the operator's quadrature points; its shipped entry
+        # for this size when there is one)
+        from paper_2103_01048_amd import autotune as at
+        xq = torch.tensor(synth.three_point_cloud(v, t), device="cuda")
+        res = at.autotune(xq, p=P_ORDER, precision=args.precision, kappa=KAPPA, cache_path=None,
+                          use_cache=not args.retune,
+                          log=lambda m: print("# autotune " + m, file=sys.stderr, flush=True))
+        del xq
+        ncrit = at.apply(res)
+        tuned = {"ncrit": ncrit, "tuning": res["tuning"], "ms": res["ms"], "key": res["key"],
+                 "source": res.get("source", "search"), "trials": len(res.get("trials", []))}
     kw = dict(quad_pts=3, eps_in=4.0, eps_out=80.0, kappa=KAPPA, p=P_ORDER, ncrit=ncrit,
               formulation=args.formulation, preconditioner=precond)
     t0 = time.perf_counter()
@@ -433,7 +449,8 @@ def run_bem(args):
             "fp64_matvec_ms": round(t64 * 1e3, 3),
             "gmres": {"status": rc, "iterations": its, "seconds": round(t_solve, 3),
                       "fp64_residual": res, "tol": 1e-6, "inner_tol": 1e-3},
-            "energy_kcal_per_mol": energy, "energy_s": round(t_energy, 3), "rhs_s": round(t_rhs, 3), "setup_s": {args.precision: round(t_setup32, 2), "fp64": round(t_setup64, 2)}}
+            "energy_kcal_per_mol": energy, "energy_s": round(t_energy, 3), "rhs_s": round(t_rhs, 3),
+            "setup_s": {args.precision: round(t_setup32, 2), "fp64": round(t_setup64, 2)}, "autotune": tuned}
     print(json.dumps(line), flush=True)
 
 

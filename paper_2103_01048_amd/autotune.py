@@ -134,7 +134,10 @@ def shipped_table() -> dict:
 def _time_pair(xt, q, p, ncrit, precision, kappa, steps, warmup, keep, offsets=None, repeats=3):
     pls = [FMMPlan(xt, kernel=k, kappa=kappa, p=p, ncrit=ncrit, precision=precision, offsets=offsets)
            for k in ("laplace", "yukawa")]
-    keep.extend(pls)  # live plans let later trials share their tree and operators
+    # the latest trial's plans stay alive so that the next trial can share
+    # their tree and operators; older ones are released (at millions of
+    # points a pair holds gigabytes of pair slots)
+    keep[:] = pls
     for _ in range(warmup):
         eval_pair(pls[0], pls[1], q)
     torch.cuda.synchronize()

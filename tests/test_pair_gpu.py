@@ -260,3 +260,35 @@ def test_second_plan_shares_the_tree_and_outlives_the_first():
     e = FMMPlan(xt, kernel="laplace", p=6, ncrit=64, precision="bf16x3")
     assert c.info()["tree_shared"] == 0 and d.info()["tree_shared"] == 0
     assert e.info()["tree_shared"] == 1  # from b, which holds the tree alone now
+
+
+@pytest.mark.parametrize("setting", [
+    {"near_early": 450, "gemm_lat": 0, "gemm_narrow": 1},
+    {"near_early": 500, "m2l_early": 1},
+    {"pair_order": 2},
+])
+@pytest.mark.parametrize("grad", [True, False])
+def test_pair_monopole_dipole_under_other_tunables_equals_the_defaults(setting, grad):
+    """The monopole + dipole pair evaluation (the direct formulation's step)
+    under the pass-order and split tunables gives the default setting's
+    results within single-precision rounding."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, autotune as at, eval_pair_md
+    x = _cloud(6000, seed=141)
+    rng = np.random.default_rng(141)
+    q = torch.tensor(rng.standard_normal(len(x)), device="cuda", dtype=torch.float32)
+    dip = torch.tensor(rng.standard_normal((len(x), 3)), device="cuda", dtype=torch.float32)
+    xt = torch.tensor(x, device="cuda")
+
+    def run():
+        a = FMMPlan(xt, kernel="laplace", p=6, ncrit=48, precision="bf16x3")
+        b = FMMPlan(xt, kernel="yukawa", kappa=KAPPA, p=6, ncrit=48, precision="bf16x3")
+        assert a.info()["max_level"] >= 3
+        out = eval_pair_md(a, b, q, dip, -1.0, -0.05, gradient=grad)
+        return [t for o in out for t in (o if isinstance(o, tuple) else (o,))]
+
+    ref = run()
+    with at.tuning(**setting):
+        got = run()
+    for r, g in zip(ref, got):
+        assert _rel(g, r) < 1e-6
