@@ -226,7 +226,7 @@ def run_batch(args):
     else:
         from paper_2103_01048_amd import autotune as at
         res = at.autotune(xt, p=P_ORDER, precision=prec, kappa=KAPPA, q=qt, cache_path=None, offsets=off,
-                          ncrit_candidates=(64, 96, 128, 160, 192),
+                          ncrit_candidates=(64, 96, 128, 160, 192), use_cache=not args.retune,
                           log=lambda m: print("# autotune " + m, file=sys.stderr, flush=True))
         ncrit = at.apply(res)
         tuned = {"ncrit": ncrit, "tuning": res["tuning"], "ms": res["ms"], "trials": len(res.get("trials", [])),
@@ -341,13 +341,26 @@ def run_shell(args):
     t0 = time.perf_counter()
     x, q = synth.surface_cloud(30000, 10_000_000, seed=13, shell_radius=200.0)
     print(f"# shell of {len(x)} points in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    ncrit = args.ncrit or 128
     xt = torch.tensor(x, device=dev)
+    qt = torch.tensor(q, device=dev, dtype=torch.float32)
+    tuned = None
+    if args.ncrit:
+        ncrit = args.ncrit
+    else:
+        # the autotuner's choice (its shipped entry when there is one; a
+        # search here times 5 steps per trial, best of 2, to stay within
+        # minutes at 190 ms per step)
+        from paper_2103_01048_amd import autotune as at
+        res = at.autotune(xt, p=10, precision=args.precision, kappa=KAPPA, q=qt, cache_path=None,
+                          use_cache=not args.retune, ncrit_candidates=(96, 128, 160, 192), steps=5, warmup=2,
+                          repeats=2, log=lambda m: print("# autotune " + m, file=sys.stderr, flush=True))
+        ncrit = at.apply(res)
+        tuned = {"ncrit": ncrit, "tuning": res["tuning"], "ms": res["ms"], "key": res["key"],
+                 "source": res.get("source", "search"), "trials": len(res.get("trials", []))}
     t0 = time.perf_counter()
     plans = [FMMPlan(xt, kernel=k, kappa=KAPPA, p=10, ncrit=ncrit, precision=args.precision)
              for k in ("laplace", "yukawa")]
     t_setup = time.perf_counter() - t0
-    qt = torch.tensor(q, device=dev, dtype=torch.float32)
     t = _timed(torch, lambda: eval_pair(plans[0], plans[1], qt), args.steps, args.warmup)
     n = len(x)
     line = {"metric": "FMM matvec Mpoints/s (Laplace+Yukawa), 30M-point shell",
@@ -357,7 +370,7 @@ def run_shell(args):
             "config": {"workload": f"30,000-sphere shell, radius 200 A, {n} points; Laplace + Yukawa (kappa 0.125) "
                                    "fmm_eval_pair, potential + gradient",
                        "p": 10, "ncrit": ncrit, "precision": args.precision},
-            "setup_s_both_plans": round(t_setup, 2), "tree": plans[0].info()}
+            "setup_s_both_plans": round(t_setup, 2), "tree": plans[0].info(), "autotune": tuned}
     print(json.dumps(line), flush=True)
 
 

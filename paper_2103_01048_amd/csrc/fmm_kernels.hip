@@ -1870,8 +1870,11 @@ static int launch_gemm2(fmm_plan *P, const GemmBatch &bt, const T *X, T *Y, fmm_
     return FMM_OK;
   }
   // Small launches (few column tiles) split the row blocks over a second grid
-  // dimension so that more workgroups share the work.
-  int rbw = g0.ntask + g1.ntask >= 1024 ? (nrb + 3) / 4 : 1;
+  // dimension so that more workgroups share the work.  Large ones take one
+  // group of up to 4 blocks per wave: 5 (19 row blocks at p = 10) holds so
+  // many accumulators that the 30M-point pair step at p = 10 took 176 ms
+  // against 119 with 4 and 120 with 2.
+  int rbw = g0.ntask + g1.ntask >= 1024 ? std::min(4, (nrb + 3) / 4) : 1;
   if (P->tune.gemm_rbw > 0) rbw = std::min(P->tune.gemm_rbw, std::max(1, (nrb + 3) / 4));
   // FP64: at most two row blocks per wave (more y-groups, fewer registers,
   // more resident waves); measured on the FP64 pair evaluation: 2 -> 59.5,
