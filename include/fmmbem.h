@@ -124,9 +124,9 @@ int fmm_eval(fmm_plan *plan, const void *q_dev, int nrhs, void *pot_dev, void *g
  * passes of both kernels run as shared launches on an internal stream
  * while the near field of both kernels runs on `stream` in one launch that
  * computes each pair distance once; otherwise the two evaluations run one
- * after the other on `stream`.  The internal streams (two, default priority)
+ * after the other on `stream`.  The internal streams (three, default priority)
  * belong to the device, not to the plans: every pair evaluation on a device
- * uses the same two, so the hardware queues taken do not grow with the number
+ * uses the same three, so the hardware queues taken do not grow with the number
  * of plans, pair evaluations issued from different caller streams at once
  * queue their side passes one after the other, and a pair evaluation must not
  * be captured into a graph while another thread evaluates a pair on the same
