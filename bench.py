@@ -791,11 +791,29 @@ def main():
     other_plans = {}
     if args.precision != "fp32":
         other_plans["fp32"] = make("fp32", ncrit)
-    other_plans["fp64"] = make("fp64", ncrit)
+    # the FP64 path with the autotuner's choice for FP64 pair evaluations on
+    # this workload (its shipped entry when there is one), else the
+    # headline's ncrit and tunables
+    fp64_ncrit, fp64_tuned = ncrit, None
+    if not args.ncrit:
+        from paper_2103_01048_amd import autotune as at
+        r64 = at.autotune(xt, p=P_ORDER, precision="fp64", kappa=KAPPA, q=qd[torch.float64], cache_path=None,
+                          use_cache=not args.retune,
+                          log=lambda m: print("# autotune fp64 " + m, file=sys.stderr, flush=True))
+        fp64_ncrit = int(r64["ncrit"])
+        fp64_tuned = {"ncrit": fp64_ncrit, "tuning": r64["tuning"], "ms": r64["ms"], "key": r64["key"],
+                      "source": r64.get("source", "search")}
+        with at.tuning(**r64["tuning"]):
+            other_plans["fp64"] = make("fp64", fp64_ncrit)
+    else:
+        other_plans["fp64"] = make("fp64", ncrit)
     for tag, pls in other_plans.items():
         st = args.fp64_steps if tag == "fp64" else args.steps
         dto, _ = time_steps(step_pair, pls, qd, st, 1)
         others[tag] = {"value": round(n / (dto / st) / 1e6, 3), "ms_per_step": round(dto / st * 1e3, 4)}
+    others["fp64"]["ncrit"] = fp64_ncrit
+    if fp64_tuned:
+        others["fp64"]["autotune"] = fp64_tuned
 
     # outputs for the accuracy gate
     outs = {}
