@@ -779,41 +779,38 @@ def main():
     # the same plans as two separate fmm_eval calls, then the other paths on
     # the same points and ncrit: plain FP32 (when the headline is bf16x3)
     # and the plain FP64 form
-    dts, _ = time_steps(step_separate, plans, qd, args.steps, 1)
+    dts, _ = time_steps(step_separate, plans, qd, args.steps, args.warmup)
     others = {"separate_evals": {"value": round(n / (dts / args.steps) / 1e6, 3),
                                  "ms_per_step": round(dts / args.steps * 1e3, 4)}}
     # each kernel alone (one fmm_eval per step)
     per_kernel = {}
     for k, pl in plans.items():
-        dtk, _ = time_steps(lambda p_, q_, pl=pl: pl.eval(q_[pl.dtype]), plans, qd, args.steps, 1)
+        dtk, _ = time_steps(lambda p_, q_, pl=pl: pl.eval(q_[pl.dtype]), plans, qd, args.steps, args.warmup)
         per_kernel[k] = {"value": round(n / (dtk / args.steps) / 1e6, 3), "ms_per_eval": round(dtk / args.steps * 1e3, 4)}
     others["per_kernel"] = per_kernel
-    other_plans = {}
-    if args.precision != "fp32":
-        other_plans["fp32"] = make("fp32", ncrit)
-    # the FP64 path with the autotuner's choice for FP64 pair evaluations on
-    # this workload (its shipped entry when there is one), else the
-    # headline's ncrit and tunables
-    fp64_ncrit, fp64_tuned = ncrit, None
-    if not args.ncrit:
+    # plain FP32 (when the headline is bf16x3) and FP64, each with the
+    # autotuner's choice for its own pair evaluations on this workload (its
+    # shipped entry when there is one), else the headline's ncrit and tunables
+    other_plans, other_tuned = {}, {}
+    for tag in (["fp32"] if args.precision != "fp32" else []) + ["fp64"]:
+        if args.ncrit:
+            other_plans[tag] = make(tag, ncrit)
+            continue
         from paper_2103_01048_amd import autotune as at
-        r64 = at.autotune(xt, p=P_ORDER, precision="fp64", kappa=KAPPA, q=qd[torch.float64], cache_path=None,
-                          use_cache=not args.retune,
-                          log=lambda m: print("# autotune fp64 " + m, file=sys.stderr, flush=True))
-        fp64_ncrit = int(r64["ncrit"])
-        fp64_tuned = {"ncrit": fp64_ncrit, "tuning": r64["tuning"], "ms": r64["ms"], "key": r64["key"],
-                      "source": r64.get("source", "search")}
-        with at.tuning(**r64["tuning"]):
-            other_plans["fp64"] = make("fp64", fp64_ncrit)
-    else:
-        other_plans["fp64"] = make("fp64", ncrit)
+        qo = qd[torch.float64 if tag == "fp64" else torch.float32]
+        ro = at.autotune(xt, p=P_ORDER, precision=tag, kappa=KAPPA, q=qo, cache_path=None, use_cache=not args.retune,
+                         log=lambda m, tag=tag: print(f"# autotune {tag} " + m, file=sys.stderr, flush=True))
+        other_tuned[tag] = {"ncrit": int(ro["ncrit"]), "tuning": ro["tuning"], "ms": ro["ms"], "key": ro["key"],
+                            "source": ro.get("source", "search")}
+        with at.tuning(**ro["tuning"]):
+            other_plans[tag] = make(tag, int(ro["ncrit"]))
     for tag, pls in other_plans.items():
         st = args.fp64_steps if tag == "fp64" else args.steps
-        dto, _ = time_steps(step_pair, pls, qd, st, 1)
-        others[tag] = {"value": round(n / (dto / st) / 1e6, 3), "ms_per_step": round(dto / st * 1e3, 4)}
-    others["fp64"]["ncrit"] = fp64_ncrit
-    if fp64_tuned:
-        others["fp64"]["autotune"] = fp64_tuned
+        dto, _ = time_steps(step_pair, pls, qd, st, args.warmup)
+        others[tag] = {"value": round(n / (dto / st) / 1e6, 3), "ms_per_step": round(dto / st * 1e3, 4),
+                       "ncrit": pls["laplace"].ncrit}
+        if tag in other_tuned:
+            others[tag]["autotune"] = other_tuned[tag]
 
     # outputs for the accuracy gate
     outs = {}
@@ -925,7 +922,7 @@ def main():
         for pp in [int(v) for v in args.p_sweep.split(",") if v.strip()]:
             pls = {k: FMMPlan(xt, kernel=k, kappa=KAPPA, p=pp, ncrit=ncrit, precision=args.precision)
                    for k in ("laplace", "yukawa")}
-            dtp, _ = time_steps(step_pair, pls, qd, args.steps, 2)
+            dtp, _ = time_steps(step_pair, pls, qd, args.steps, args.warmup)
             (pa, ga), (pb, gb) = eval_pair(pls["laplace"], pls["yukawa"], qd[torch.float32])
             errp = {}
             for k, (pot, grad) in (("laplace", (pa, ga)), ("yukawa", (pb, gb))):
@@ -949,7 +946,7 @@ def main():
             for pp in sorted(int(v) for v in args.p_sweep.split(",") if v.strip()):
                 pls = {k: FMMPlan(xt, kernel=k, kappa=KAPPA, p=pp, ncrit=ncrit, precision=tag)
                        for k in ("laplace", "yukawa")}
-                dtp, _ = time_steps(step_pair, pls, qd, st, 1)
+                dtp, _ = time_steps(step_pair, pls, qd, st, args.warmup)
                 (pa, ga), (pb, gb) = eval_pair(pls["laplace"], pls["yukawa"], qd[pls["laplace"].dtype])
                 errp = {}
                 for k, (pot, grad) in (("laplace", (pa, ga)), ("yukawa", (pb, gb))):
