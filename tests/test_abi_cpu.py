@@ -135,3 +135,30 @@ def test_tuning_roundtrip_and_range_checks():
         assert at.get_tuning() == before
     with pytest.raises(ValueError):
         at.set_tuning(no_such_parameter=1)
+
+
+def test_shipped_tuning_entries_are_valid():
+    """Every entry of the package's tuning table names a device, precision,
+    order and point-count range in the autotuner's key format, holds only
+    known tunables (missing ones take the defaults), and is accepted by
+    fmm_set_tuning; ncrit is positive."""
+    import json
+    from paper_2103_01048_amd import autotune as at
+    table = json.load(open(at.SHIPPED_TABLE))
+    assert table == at.shipped_table() and len(table) >= 1
+    key_re = re.compile(r"^gfx[0-9a-f]+x\d+cu\|(fp64|fp32|bf16x3)\|p\d+\|n~2\^\d+(\|mol~2\^\d+)?$")
+    before = at.get_tuning()
+    for key, e in table.items():
+        assert key_re.match(key), key
+        assert int(e["ncrit"]) >= 1 and float(e["ms"]) > 0
+        assert set(e["tuning"]) <= set(at.DEFAULTS), key
+        with at.tuning(**{**at.DEFAULTS, **e["tuning"]}):
+            assert at.get_tuning() == {**at.DEFAULTS, **e["tuning"]}
+    assert at.get_tuning() == before
+
+
+def test_cache_key_format_on_a_host_without_a_gpu():
+    from paper_2103_01048_amd import autotune as at
+    assert at.device_tag() == "cpu"
+    assert at.cache_key(393216, 8, "bf16x3") == "cpu|bf16x3|p8|n~2^19"
+    assert at.cache_key(1364619, 8, "bf16x3", nmol=64) == "cpu|bf16x3|p8|n~2^20|mol~2^6"
