@@ -222,6 +222,10 @@ int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const v
  *                 start at once on a second side stream, on a grid of
  *                 near_early_grid waves (64..65536) that loop over them,
  *                 beside the upward passes and the M2L; 0: none
+ *   near_early_start
+ *                 with near_early: 0 starts the early items with the
+ *                 far-field passes, 1 once P2M (VALU work on the path of
+ *                 the upward pass) is done
  *   m2l_early     pair evaluations: 1 runs the M2L of the two finest levels
  *                 on a third side stream as soon as their upward densities
  *                 are final (after the first M2M level), beside the coarser
@@ -245,6 +249,7 @@ typedef struct {
   int32_t near_early;
   int32_t near_early_grid;
   int32_t m2l_early;
+  int32_t near_early_start;
 } fmm_tuning_t;
 int fmm_set_tuning(const fmm_tuning_t *tuning);
 int fmm_get_tuning(fmm_tuning_t *tuning);

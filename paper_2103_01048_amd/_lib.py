@@ -53,7 +53,7 @@ class FmmTuning(ctypes.Structure):
         ("near_lds", ctypes.c_int32), ("gemm_lat", ctypes.c_int32),
         ("gemm_chain", ctypes.c_int32), ("m2l_cols", ctypes.c_int32),
         ("gemm_narrow", ctypes.c_int32), ("near_early", ctypes.c_int32), ("near_early_grid", ctypes.c_int32),
-        ("m2l_early", ctypes.c_int32),
+        ("m2l_early", ctypes.c_int32), ("near_early_start", ctypes.c_int32),
     ]
 
 

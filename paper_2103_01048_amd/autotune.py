@@ -22,6 +22,8 @@ Tunables (fmm_set_tuning; defaults in DEFAULTS):
   near_early, near_early_grid per mille of the near-field items (the
                               shortest) started at once on a small grid
                               beside the upward passes and the M2L (order 3)
+  near_early_start            the early near-field items with the far-field
+                              passes (0) or once P2M is done (1)
   m2l_early                   the two finest levels' M2L on a third side
                               stream beside the coarser M2M levels
   m2l_cols                    bf16x3 M2L columns per workgroup (64 or 128;
@@ -58,7 +60,8 @@ DEFAULTS = {"tile_split2": 32, "tile_split4": 16, "work_cap_min": 512, "work_cap
             "gemm_rbw": 0, "m2l_factored": 0, "pair_order": 3,
             "near_lds": 0, "gemm_lat": 512,
             "gemm_chain": 0, "m2l_cols": 64,
-            "gemm_narrow": 0, "near_early": 0, "near_early_grid": 1024, "m2l_early": 0}
+            "gemm_narrow": 0, "near_early": 0, "near_early_grid": 1024, "m2l_early": 0,
+            "near_early_start": 0}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2103_01048_amd", "tuning.json")
 SHIPPED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_table.json")
 
@@ -71,6 +74,7 @@ STAGES = (
     ("gemm_narrow", [{"gemm_narrow": v} for v in (0, 1)]),
     ("m2l_early", [{"m2l_early": v} for v in (0, 1)]),
     ("near_early", [{"near_early": v} for v in (0, 350, 450, 500, 550)]),
+    ("near_early_start", [{"near_early_start": v} for v in (0, 1)]),
     ("pair_order", [{"pair_order": v} for v in (0, 1, 2, 3)]),
     ("near_lds", [{"near_lds": v} for v in (0, 8192, 13312)]),
     ("gemm_lat", [{"gemm_lat": v} for v in (0, 256, 512, 1024)]),

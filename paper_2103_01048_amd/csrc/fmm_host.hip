@@ -1322,7 +1322,7 @@ void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
 
 // Tunables for plans set up from now on (fmm_set_tuning).
 static std::mutex g_tune_mu;
-static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0, 0, 1024, 0};
+static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0, 0, 1024, 0, 0};
 
 // Live plans whose tree later plans on the same points may share.
 static std::mutex g_tree_mu;
@@ -1750,7 +1750,7 @@ int fmm_set_tuning(const fmm_tuning_t *t) {
       t->gemm_lat < 0 || t->gemm_lat > (1 << 20) || t->gemm_chain < 0 || t->gemm_chain > 1 ||
       (t->m2l_cols != 64 && t->m2l_cols != 128) || t->gemm_narrow < 0 || t->gemm_narrow > 1 ||
       t->near_early < 0 || t->near_early > 900 || t->near_early_grid < 64 || t->near_early_grid > 65536 ||
-      t->m2l_early < 0 || t->m2l_early > 1) {
+      t->m2l_early < 0 || t->m2l_early > 1 || t->near_early_start < 0 || t->near_early_start > 1) {
     set_error("fmm_set_tuning: value out of range");
     return FMM_EINVAL;
   }

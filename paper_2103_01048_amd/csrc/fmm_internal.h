@@ -257,7 +257,7 @@ struct fmm_plan {
   double setup_ms = 0;
   double setup_split[5] = {0, 0, 0, 0, 0};  // sort, tree, lists, items, operators (ms)
   int tree_on_device = 0, tree_shared = 0;
-  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0, 0, 1024, 0};  // tunables in force at setup
+  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0, 0, 1024, 0, 0};  // tunables in force at setup
   std::vector<void *> allocs;      // everything to free
   std::shared_ptr<fmm::SharedAllocs> tree_mem;  // the tree's device buffers (shared with plans on the same points)
   std::shared_ptr<fmm::SharedAllocs> ops_mem;   // translation operators (shared with plans of the same kernel on the same tree)

@@ -2437,13 +2437,19 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   if (far) {
     FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
     FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_fork, 0));
-    if (nearly > 0) {
-      FMM_HIP_TRY(hipStreamWaitEvent(side2, A->ev_fork, 0));
-      if ((rc = near(side2, nmain, nearly, std::min(nearly, A->tune.near_early_grid), FMM_PHASE_NEAR_EARLY)))
-        return rc;
+    // the early items start with the passes (near_early_start 0) or once
+    // P2M is done (1: P2M, VALU work at the head of the upward pass, then
+    // has the GPU to itself)
+    auto early = [&](hipEvent_t after) -> int {
+      FMM_HIP_TRY(hipStreamWaitEvent(side2, after, 0));
+      int r = near(side2, nmain, nearly, std::min(nearly, A->tune.near_early_grid), FMM_PHASE_NEAR_EARLY);
+      if (r) return r;
       FMM_HIP_TRY(hipEventRecord(A->ev_near, side2));
-    }
+      return FMM_OK;
+    };
+    if (nearly > 0 && !A->tune.near_early_start && (rc = early(A->ev_fork))) return rc;
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips, side3))) return rc;
+    if (nearly > 0 && A->tune.near_early_start && (rc = early(B->ev_fork))) return rc;
     if (order == 3) FMM_HIP_TRY(hipEventRecord(A->ev_m2l, side));
     // the near field starts once P2M (VALU, like the near field) is done and
     // shares the GPU with the GEMM passes; P2L and its projection (which the

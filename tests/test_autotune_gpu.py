@@ -52,6 +52,7 @@ def _pair(xt, q, ncrit=48):
     {"near_early": 900, "near_early_grid": 64},
     {"m2l_early": 1},
     {"m2l_early": 1, "near_early": 500, "gemm_narrow": 1},
+    {"near_early": 450, "near_early_start": 1},
 ])
 def test_every_setting_gives_the_same_fmm(setting):
     torch = require_gpu()
