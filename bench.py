@@ -56,11 +56,11 @@ PEAK_HBM = 8.0e12
 #            -kappa r (1), exp (1), g (1), (1 + kappa r) g / r^2 (4),
 #            per kernel pot (2) + f q (1) + grad (6)                    = 37
 FLOP_PER_PAIR = {"laplace": 20, "yukawa": 27, "pair": 37}
-# The survey's count for one pair of both kernels (potential and gradient):
-# Laplace 18 flop + 1 rsqrt, Yukawa about 24 flop + rsqrt + exp2 = 45; the
-# roofline fractions use it, the fused count (37, shared distance) is
-# reported beside it.
-FLOP_PER_PAIR_SURVEY = 45
+# The standard count for one pair of both kernels (potential and gradient,
+# each kernel on its own): Laplace 18 flop + 1 rsqrt, Yukawa about 24 flop +
+# rsqrt + exp2 = 45; the roofline fractions use it, the fused count (37,
+# shared distance) is reported beside it.
+FLOP_PER_PAIR_STD = 45
 # Surface evaluation (P2M, P2L): potential of both kernels from one
 # distance: d (3), r2 (5), rsqrt (1), Laplace q/r (2), r (1), -kappa r (1),
 # exp2 (1), g (1), Yukawa q g (2)
@@ -100,10 +100,10 @@ def phase_work(plan_l, plan_y, infos):
         "p2l": (p2l_pairs * FLOP_PER_SURF_PAIR, PEAK_VALU_FP32, "flop"),
         "dc2e": (gemm(lambda ru, rd: 2.0 * rd * ns * (p2l_boxes + nleaf2)), PEAK_MFMA["fp32"], "flop"),
         "l2l": (gemm(lambda ru, rd: 2.0 * rd * rd * child2), PEAK_MFMA["fp32"], "flop"),
-        "near": (float(inf_l["n_p2p_interactions"] - inf_l["n_p2p_early"]) * FLOP_PER_PAIR_SURVEY, PEAK_VALU_FP32,
+        "near": (float(inf_l["n_p2p_interactions"] - inf_l["n_p2p_early"]) * FLOP_PER_PAIR_STD, PEAK_VALU_FP32,
                  "flop"),
-        "near_early": (float(inf_l["n_p2p_early"]) * FLOP_PER_PAIR_SURVEY, PEAK_VALU_FP32, "flop"),
-        "far": (float(inf_l["n_far_interactions"]) * FLOP_PER_PAIR_SURVEY, PEAK_VALU_FP32, "flop"),
+        "near_early": (float(inf_l["n_p2p_early"]) * FLOP_PER_PAIR_STD, PEAK_VALU_FP32, "flop"),
+        "far": (float(inf_l["n_far_interactions"]) * FLOP_PER_PAIR_STD, PEAK_VALU_FP32, "flop"),
     }
     return work
 
@@ -827,7 +827,7 @@ def main():
         flops = 2.0 * inf["n_v_pairs"] * inf["rank_up"] * inf["rank_down"]
         roof = {"bound": "mfma", "peak": PEAK_MFMA[args.precision], "unit": "TFLOP/s"}
     elif dname in ("leaf", "near", "far"):
-        per = FLOP_PER_PAIR[dk] if dname == "leaf" else FLOP_PER_PAIR_SURVEY
+        per = FLOP_PER_PAIR[dk] if dname == "leaf" else FLOP_PER_PAIR_STD
         # the main near-field launch: the items not started early
         pairs = {"leaf": inf["n_p2p_interactions"] + inf["n_far_interactions"],
                  "near": inf["n_p2p_interactions"] - inf["n_p2p_early"], "far": inf["n_far_interactions"]}[dname]
@@ -853,13 +853,13 @@ def main():
         ep = float(inf["n_p2p_early"])
         roofline["early_launch"] = {
             "pairs": int(ep), "avg_launch_ms": round(ems / ecnt, 4), "launches_timed": ecnt,
-            "achieved": round(ep * FLOP_PER_PAIR_SURVEY / (ems / ecnt * 1e-3) / 1e12, 3),
+            "achieved": round(ep * FLOP_PER_PAIR_STD / (ems / ecnt * 1e-3) / 1e12, 3),
             "note": "runs on near_early_grid waves beside the upward passes and the M2L, so its duration "
                     "is set by the GPU it shares, not by its own rate"}
     if dname in ("near", "far"):
-        fused = flops / FLOP_PER_PAIR_SURVEY * FLOP_PER_PAIR["pair"]
+        fused = flops / FLOP_PER_PAIR_STD * FLOP_PER_PAIR["pair"]
         roofline.update({
-            "flop_per_pair": FLOP_PER_PAIR_SURVEY, "flop_per_pair_fused": FLOP_PER_PAIR["pair"],
+            "flop_per_pair": FLOP_PER_PAIR_STD, "flop_per_pair_fused": FLOP_PER_PAIR["pair"],
             "achieved_fused": round(fused / (avg_ms * 1e-3) / 1e12, 3),
             "peak_unpacked": round(PEAK_VALU_FP32_UNPACKED / 1e12, 1),
             "frac_unpacked": round(achieved / PEAK_VALU_FP32_UNPACKED, 4)})
