@@ -120,6 +120,44 @@ def test_surface393k_pair_tuned_and_factored(surface393k, precision, tol, tuning
         assert ep < tol and eg < tol
 
 
+def _shipped(at, n, p, precision, device):
+    key = at.cache_key(n, p, precision, device)
+    entry = at.shipped_table().get(key)
+    if entry is None:
+        pytest.skip(f"no shipped tuning entry for {key}")
+    return entry
+
+
+def _pair_rows(plans, torch, x, q, rows, tol, tag):
+    from paper_2103_01048_amd import eval_pair
+    dt = torch.float64 if plans[0].precision == "fp64" else torch.float32
+    outs = eval_pair(plans[0], plans[1], torch.tensor(q, device="cuda", dtype=dt))
+    torch.cuda.synchronize()
+    for kernel, (pot, grad) in zip(("laplace", "yukawa"), outs):
+        phi, g = D.direct(x[rows], x, q, kernel, KAPPA if kernel == "yukawa" else 0.0)
+        ep = _rel(pot.cpu().numpy()[rows], phi)
+        eg = _rel(grad.cpu().numpy()[rows], g)
+        _say(f"[{tag} {kernel}] pot {ep:.2e} grad {eg:.2e}")
+        assert ep < tol and eg < tol
+
+
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-4), ("fp32", 1e-4), ("fp64", 1e-6)])
+def test_surface393k_pair_with_the_shipped_entry(surface393k, precision, tol):
+    """The benchmark's step as it runs: the package's shipped tuning entry
+    for this workload, device and precision (ncrit and tunables), against the
+    direct sums on 2,048 sampled rows."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, autotune as at
+    x, q = surface393k
+    xt = torch.tensor(x, device="cuda")
+    e = _shipped(at, len(x), 8, precision, xt.device)
+    with at.tuning(**{**at.DEFAULTS, **e["tuning"]}):
+        plans = [FMMPlan(xt, kernel=k, kappa=KAPPA, p=8, ncrit=e["ncrit"], precision=precision)
+                 for k in ("laplace", "yukawa")]
+    rows = np.random.default_rng(77).choice(len(x), 2048, replace=False)
+    _pair_rows(plans, torch, x, q, rows, tol, f"393k pair {precision} shipped entry ncrit {e['ncrit']}")
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("fp64", 1e-6)])
 @pytest.mark.parametrize("kernel", ["laplace", "yukawa"])
 def test_surface393k_fp32_fp64(surface393k, kernel, precision, tol):
@@ -284,6 +322,22 @@ def test_shell_30m_points_p10(kernel):
     _say(f"[shell 30M {kernel}] setup {plan.info()['setup_ms']:.0f} ms")
     rows = np.random.default_rng(101).choice(len(x), 512, replace=False)
     _check_rows(plan, torch, x, q, rows, kernel, 1e-4, f"shell 30M {kernel} p10")
+
+
+def test_shell_30m_pair_with_the_shipped_entry():
+    """The 30M-point shell's pair evaluation (p = 10) with the shipped tuning
+    entry for it, against the direct sums on 256 sampled rows."""
+    torch = require_gpu()
+    from paper_2103_01048_amd import FMMPlan, autotune as at
+    x, q = _shell30m()
+    xt = torch.tensor(x, device="cuda")
+    e = _shipped(at, len(x), 10, "bf16x3", xt.device)
+    with at.tuning(**{**at.DEFAULTS, **e["tuning"]}):
+        plans = [FMMPlan(xt, kernel=k, kappa=KAPPA, p=10, ncrit=e["ncrit"], precision="bf16x3")
+                 for k in ("laplace", "yukawa")]
+    rows = np.random.default_rng(103).choice(len(x), 256, replace=False)
+    _pair_rows(plans, torch, x, q, rows, 1e-4, f"shell 30M pair shipped entry ncrit {e['ncrit']}")
+    del plans
 
 
 _SHELL = {}
