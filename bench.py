@@ -123,12 +123,22 @@ def cpu_model():
 GRID_SPLIT = ("k_near_pair<",)
 
 
+def kernel_source_digest(path: str) -> str:
+    """SHA-256 of a HIP source with its comments and whitespace removed: the
+    stored counter bytes stay valid across edits of comments only."""
+    import hashlib
+    import re
+    src = open(path).read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return hashlib.sha256("".join(src.split()).encode()).hexdigest()
+
+
 def measured_traffic(kernel: str, phase: str, precision: str, grid: int | None = None):
     """HBM bytes per launch (read + write) of the dominant kernel, from the
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in profiles/, or None
-    when the kernel source changed since those counters were taken.  grid:
+    when the kernel code changed since those counters were taken.  grid:
     only its launches of that many workgroups (for a kernel in GRID_SPLIT)."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_2103_01048_amd", "csrc", "fmm_kernels.hip")
     names = {"leaf": f"void fmm::k_leaf_eval<float, 1, {1 if kernel == 'yukawa' else 0}>",
@@ -136,7 +146,7 @@ def measured_traffic(kernel: str, phase: str, precision: str, grid: int | None =
     if phase not in names or precision == "fp64" or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernels_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if rec.get("kernels_code_sha256") != kernel_source_digest(src):
         return None
     name = names[phase]
     if grid is not None and any(g in name for g in GRID_SPLIT):
@@ -497,7 +507,6 @@ def summarize_profile(args):
     from three rocprofv3 runs of one command: --kernel-trace --stats, --pmc
     FETCH_SIZE, --pmc WRITE_SIZE.  Counter bytes are scaled by what the same
     counters read for the 256 MiB device copy of --copy-probe."""
-    import hashlib
     trace_dir, fetch_dir, write_dir = args.summarize_profile
     stats = _csv_rows(trace_dir, "kernel_stats.csv")
     per = {}
@@ -566,7 +575,7 @@ def summarize_profile(args):
                      f"{t['write_bytes'] / 1e6:.1f} |")
     os.makedirs(os.path.dirname(os.path.abspath(out_md)), exist_ok=True)
     open(out_md, "w").write("\n".join(lines) + "\n")
-    rec = {"kernels_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+    rec = {"kernels_code_sha256": kernel_source_digest(src),
            "profile": os.path.basename(out_md), "fetch_scale": f_scale, "write_scale": w_scale,
            "traffic": {k: {"read_bytes": t["read_bytes"], "write_bytes": t["write_bytes"]} for k, t in traffic.items()}}
     traffic_out = args.traffic_out or os.path.join(ROOT, "profiles", "traffic.json")

@@ -2413,12 +2413,16 @@ static int pair_off_chain(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   return FMM_OK;
 }
 
-// Fork and join of a pair evaluation around the near-field launch `near`:
-//   side stream: P2M   | upward GEMMs, M2L                        | wait P2L | M2L sums, downward GEMMs
-//   stream s:    wait  | near field, P2L, P2L proj., M2P eq.      | wait side stream | far field
-// P2L (VALU) after the near field shares the GPU with the M2L launch (bound
-// by memory latency) instead of delaying the near field: 1.431 against 1.488
-// ms per pair step on the 393k workload (A/B on one device).
+// Fork and join of a pair evaluation around the near-field launch `near`,
+// with pass order 3 (the default; orders 0-2 move P2L and the main near
+// field earlier, see below):
+//   side:    P2M | UT, M2M levels, M2L | wait P2L proj. | M2L sums, L2L, DC2E
+//   side2:   wait P2M (or the fork) | the early near items (near_early)
+//   side3:   wait the first M2M level | the finest levels' M2L (m2l_early)
+//   s:       wait P2M | P2L, its projection, M2P sources | wait M2L | main
+//            near items | wait side, side2 | far field (by the caller)
+// The VALU passes (P2M, P2L, near field) share the GPU with the GEMM passes,
+// which are bound by memory latency rather than by issue.
 template <typename T, int NR, typename Near>
 static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips, Near near) {
   int rc;

@@ -60,7 +60,7 @@ def test_profile_summary_splits_the_near_launches_by_grid_and_scales_counter_byt
     assert t["void fmm::k_near_pair<float, 1> @10"]["read_bytes"] == 4.0 * 1024 * 2
     assert t["void fmm::k_near_pair<float, 1> @10"]["write_bytes"] == 2.0 * 1024
     assert t["void fmm::k_near_pair<float, 1>"]["read_bytes"] == 7.0 * 1024 * 2
-    assert len(rec["kernels_source_sha256"]) == 64
+    assert len(rec["kernels_code_sha256"]) == 64
 
 
 def test_counter_summary_gives_medians_and_the_mfma_busy_fraction(tmp_path):
@@ -78,3 +78,12 @@ def test_counter_summary_gives_medians_and_the_mfma_busy_fraction(tmp_path):
     # medians: GRBM 80,000, busy 2,048,000 -> 2,048,000 / (80,000 / 8 x 1,024) = 0.2
     assert "| `void fmm::k_gemm_bf3<3, 64>` | 3 | 80,000 | 2,048,000 | 0.200 |" in md
     assert md.rstrip().endswith("a note")
+
+
+def test_kernel_digest_ignores_comments_and_whitespace_only(tmp_path):
+    a, b, c = (str(tmp_path / f) for f in ("a.hip", "b.hip", "c.hip"))
+    open(a, "w").write("// head\n__global__ void k(float *x) {\n  x[0] = 1.f;  /* set */\n}\n")
+    open(b, "w").write("/* another\n   head */\n__global__ void k(float *x)\n{ x[0] = 1.f; // set\n}\n")
+    open(c, "w").write("__global__ void k(float *x) {\n  x[0] = 2.f;\n}\n")
+    assert bench.kernel_source_digest(a) == bench.kernel_source_digest(b)
+    assert bench.kernel_source_digest(a) != bench.kernel_source_digest(c)
