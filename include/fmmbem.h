@@ -341,6 +341,10 @@ enum {
 int fmm_set_profiling(fmm_plan *plan, int enable);
 int fmm_get_phase_times(fmm_plan *plan, double *ms, int64_t *launches, int nphase);
 
+/* Release a plan and its device buffers (NULL is a no-op).  Waits for the
+ * device's side streams if the plan led a pair evaluation (they may also hold
+ * other plans' queued work) and for any evaluation of the plan still queued;
+ * the side streams themselves stay for the process. */
 void fmm_free(fmm_plan *plan);
 
 /* ------------------------------------------------------------------------
