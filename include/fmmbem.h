@@ -196,10 +196,15 @@ int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const v
  *                 passes run on a side stream meanwhile): 0 near field once
  *                 P2M is done, then P2L; 1 P2L once P2M is done, near field
  *                 once the upward pass is done; 2 P2L, then the near field,
- *                 both once P2M is done; 3 (the default) P2L, its projection
+ *                 both once P2M is done; 3 P2L, its projection
  *                 and the M2P sources' equivalent densities once P2M is done
  *                 (beside the upward GEMMs and the M2L), the near field once
- *                 the M2L is done (beside the M2L sums and the downward pass)
+ *                 the M2L is done (beside the M2L sums and the downward pass);
+ *                 4 (the default) the same overlap with the roles of the
+ *                 streams swapped:
+ *                 P2M, the upward GEMMs, the M2L and then the near field on
+ *                 the caller's stream (no wait across streams on that path),
+ *                 P2L and the downward pass on the side stream
  *   near_lds      pair evaluations: LDS bytes (0..65536, unused by the
  *                 kernel) reserved per near-field wave, which caps the
  *                 near-field waves per compute unit so that the far-field
@@ -217,7 +222,7 @@ int fmm_adjoint(fmm_plan *plan, const void *q_dev, const void *gbar_dev, const v
  *                 the leaves' downward projections as one-wave workgroups
  *                 (room beside the near field's waves); 0: 256-thread ones
  *   near_early, near_early_grid
- *                 pair evaluations with pair_order 3: the last near_early
+ *                 pair evaluations with pair_order 3 or 4: the last near_early
  *                 per mille (0..900) of the near-field items (the shortest)
  *                 start at once on a second side stream, on a grid of
  *                 near_early_grid waves (64..65536) that loop over them,

@@ -14,7 +14,7 @@ Tunables (fmm_set_tuning; defaults in DEFAULTS):
   m2l_factored                M2L operators split per offset by a truncated
                               SVD and applied in two passes
   pair_order                  order of the pair evaluation's near field and
-                              P2L against the far-field passes (0..3)
+                              P2L against the far-field passes (0..4)
   near_lds                    LDS bytes held per near-field wave of a pair
                               evaluation (caps its waves per compute unit)
   gemm_lat                    translation GEMM launches of at most this many
@@ -57,7 +57,7 @@ from ._lib import check, lib
 from .fmm import FMMPlan, eval_pair
 
 DEFAULTS = {"tile_split2": 32, "tile_split4": 16, "work_cap_min": 512, "work_cap_div": 16384, "far_weight": 1.15,
-            "gemm_rbw": 0, "m2l_factored": 0, "pair_order": 3,
+            "gemm_rbw": 0, "m2l_factored": 0, "pair_order": 4,
             "near_lds": 0, "gemm_lat": 512,
             "gemm_chain": 0, "m2l_cols": 64,
             "gemm_narrow": 0, "near_early": 0, "near_early_grid": 1024, "m2l_early": 0,
@@ -75,7 +75,7 @@ STAGES = (
     ("m2l_early", [{"m2l_early": v} for v in (0, 1)]),
     ("near_early", [{"near_early": v} for v in (0, 350, 450, 500, 550)]),
     ("near_early_start", [{"near_early_start": v} for v in (0, 1)]),
-    ("pair_order", [{"pair_order": v} for v in (0, 1, 2, 3)]),
+    ("pair_order", [{"pair_order": v} for v in (0, 1, 2, 3, 4)]),
     ("near_lds", [{"near_lds": v} for v in (0, 8192, 13312)]),
     ("gemm_lat", [{"gemm_lat": v} for v in (0, 256, 512, 1024)]),
 )

@@ -1322,7 +1322,7 @@ void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s) {
 
 // Tunables for plans set up from now on (fmm_set_tuning).
 static std::mutex g_tune_mu;
-static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0, 0, 1024, 0, 0};
+static fmm_tuning_t g_tune{32, 16, 512, 16384, 1.15, 0, 0, 4, 0, 512, 0, 64, 0, 0, 1024, 0, 0};
 
 // Live plans whose tree later plans on the same points may share.
 static std::mutex g_tree_mu;
@@ -1746,7 +1746,7 @@ int fmm_set_tuning(const fmm_tuning_t *t) {
   if (t->tile_split2 < 0 || t->tile_split2 > 32 || t->tile_split4 < 0 || t->tile_split4 > 16 ||
       t->work_cap_min < 1 || t->work_cap_div < 1 || !(t->far_weight > 0.0) || !std::isfinite(t->far_weight) ||
       t->gemm_rbw < 0 || t->gemm_rbw > 8 || t->m2l_factored < 0 || t->m2l_factored > 1 || t->pair_order < 0 ||
-      t->pair_order > 3 || t->near_lds < 0 || t->near_lds > 65536 ||
+      t->pair_order > 4 || t->near_lds < 0 || t->near_lds > 65536 ||
       t->gemm_lat < 0 || t->gemm_lat > (1 << 20) || t->gemm_chain < 0 || t->gemm_chain > 1 ||
       (t->m2l_cols != 64 && t->m2l_cols != 128) || t->gemm_narrow < 0 || t->gemm_narrow > 1 ||
       t->near_early < 0 || t->near_early > 900 || t->near_early_grid < 64 || t->near_early_grid > 65536 ||

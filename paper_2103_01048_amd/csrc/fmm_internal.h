@@ -30,9 +30,9 @@ void prof_end(fmm_plan *P, int phase, hipEvent_t begin, hipStream_t s);
 void prof_launch(fmm_plan *P, int phase, hipEvent_t *begin, hipEvent_t *end);
 // Near-field items of a pair evaluation that start at once on the second
 // side stream: near_early per mille of the items (the shortest, at the tail
-// of the item list), with pass order 3 and a far field only.
+// of the item list), with pass order 3 or 4 and a far field only.
 inline int near_early_items(const fmm_tuning_t &t, int nitems, bool far) {
-  return (far && t.pair_order == 3 && t.near_early > 0)
+  return (far && t.pair_order >= 3 && t.near_early > 0)
              ? (int)std::min<int64_t>(nitems, (int64_t)nitems * t.near_early / 1000)
              : 0;
 }
@@ -257,7 +257,7 @@ struct fmm_plan {
   double setup_ms = 0;
   double setup_split[5] = {0, 0, 0, 0, 0};  // sort, tree, lists, items, operators (ms)
   int tree_on_device = 0, tree_shared = 0;
-  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0, 0, 3, 0, 512, 0, 64, 0, 0, 1024, 0, 0};  // tunables in force at setup
+  fmm_tuning_t tune{32, 16, 512, 16384, 1.15, 0, 0, 4, 0, 512, 0, 64, 0, 0, 1024, 0, 0};  // tunables in force at setup
   std::vector<void *> allocs;      // everything to free
   std::shared_ptr<fmm::SharedAllocs> tree_mem;  // the tree's device buffers (shared with plans on the same points)
   std::shared_ptr<fmm::SharedAllocs> ops_mem;   // translation operators (shared with plans of the same kernel on the same tree)

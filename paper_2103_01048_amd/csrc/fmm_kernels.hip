@@ -2294,7 +2294,7 @@ down:
     prof_end(A, FMM_PHASE_L2L, ev, s);
   }
   // with gemm_narrow the downward passes use one-wave workgroups, which
-  // find room beside the near field's waves (pass order 3 runs them there)
+  // find room beside the near field's waves (pass orders 3 and 4 run them there)
   for (int l = 3; l <= D.maxlevel && !(chain && A->chain_down.ntask); ++l) {
     if (!LA.l2l[l].ntask) continue;
     ev = prof_begin(A, FMM_PHASE_L2L, s);
@@ -2414,8 +2414,8 @@ static int pair_off_chain(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
 }
 
 // Fork and join of a pair evaluation around the near-field launch `near`,
-// with pass order 3 (the default; orders 0-2 move P2L and the main near
-// field earlier, see below):
+// with pass order 3 (order 4, the default, swaps the streams of the two
+// chains, see below; orders 0-2 move P2L and the main near field earlier):
 //   side:    P2M | UT, M2M levels, M2L | wait P2L proj. | M2L sums, L2L, DC2E
 //   side2:   wait P2M (or the fork) | the early near items (near_early)
 //   side3:   wait the first M2M level | the finest levels' M2L (m2l_early)
@@ -2430,7 +2430,7 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   // FMM_PROFILE_SERIAL: the side stream's passes run on s, in the same order
   const hipStream_t side = (A->profiling & FMM_PROFILE_SERIAL) ? s : A->aux;
   const int order = A->tune.pair_order;
-  // order 3 with near_early: the shortest items (the tail of the item list)
+  // orders 3 and 4 with near_early: the shortest items (the tail of the item list)
   // on a second side stream from the start, on a small grid of waves that
   // loop over them, beside the upward passes and the M2L
   const int nit = A->dt.nitems;
@@ -2438,19 +2438,39 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
   const int nmain = nit - nearly;
   const hipStream_t side2 = (A->profiling & FMM_PROFILE_SERIAL) ? s : A->aux2;
   const hipStream_t side3 = (A->profiling & FMM_PROFILE_SERIAL) ? s : A->aux3;
+  auto early = [&](hipEvent_t after) -> int {
+    FMM_HIP_TRY(hipStreamWaitEvent(side2, after, 0));
+    int r = near(side2, nmain, nearly, std::min(nearly, A->tune.near_early_grid), FMM_PHASE_NEAR_EARLY);
+    if (r) return r;
+    FMM_HIP_TRY(hipEventRecord(A->ev_near, side2));
+    return FMM_OK;
+  };
+  if (far && order == 4) {
+    // order 4: the path that bounds the step stays on s with no wait across
+    // streams (P2M, UT, M2M, M2L, then the main near items); P2L, its
+    // projection and the M2P sources run on the side stream once P2M is
+    // done, and the downward pass there once the M2L is done
+    FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
+    if (nearly > 0 && !A->tune.near_early_start && (rc = early(A->ev_fork))) return rc;
+    if ((rc = eval_passes_pair<T, NR>(A, B, s, 1, B->ev_fork, A->ev_up, dips, side3))) return rc;
+    if (nearly > 0 && A->tune.near_early_start && (rc = early(B->ev_fork))) return rc;
+    FMM_HIP_TRY(hipEventRecord(A->ev_m2l, s));
+    FMM_HIP_TRY(hipStreamWaitEvent(side, B->ev_fork, 0));
+    if ((rc = pair_off_chain<T, NR>(A, B, side, dips, true, true))) return rc;
+    FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_m2l, 0));
+    if ((rc = eval_passes_pair<T, NR>(A, B, side, 2, nullptr, nullptr, dips))) return rc;
+    if (nearly > 0) FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_near, 0));
+    FMM_HIP_TRY(hipEventRecord(A->ev_join, side));
+    if ((rc = near(s, 0, nmain, nmain, FMM_PHASE_NEAR))) return rc;
+    FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
+    return FMM_OK;
+  }
   if (far) {
     FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
     FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_fork, 0));
     // the early items start with the passes (near_early_start 0) or once
     // P2M is done (1: P2M, VALU work at the head of the upward pass, then
     // has the GPU to itself)
-    auto early = [&](hipEvent_t after) -> int {
-      FMM_HIP_TRY(hipStreamWaitEvent(side2, after, 0));
-      int r = near(side2, nmain, nearly, std::min(nearly, A->tune.near_early_grid), FMM_PHASE_NEAR_EARLY);
-      if (r) return r;
-      FMM_HIP_TRY(hipEventRecord(A->ev_near, side2));
-      return FMM_OK;
-    };
     if (nearly > 0 && !A->tune.near_early_start && (rc = early(A->ev_fork))) return rc;
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips, side3))) return rc;
     if (nearly > 0 && A->tune.near_early_start && (rc = early(B->ev_fork))) return rc;
@@ -2477,9 +2497,11 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
     if (order != 3 && (rc = pair_off_chain<T, NR>(A, B, s, dips, order == 0))) return rc;
     FMM_HIP_TRY(hipStreamWaitEvent(side, B->ev_join, 0));
     if ((rc = eval_passes_pair<T, NR>(A, B, side, 2, nullptr, nullptr, dips))) return rc;
+    // the side stream takes in the early launch (done long before the
+    // downward pass ends), so that s waits on one event before the far field
+    if (nearly > 0) FMM_HIP_TRY(hipStreamWaitEvent(side, A->ev_near, 0));
     FMM_HIP_TRY(hipEventRecord(A->ev_join, side));
     FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_join, 0));
-    if (nearly > 0) FMM_HIP_TRY(hipStreamWaitEvent(s, A->ev_near, 0));
   }
   return FMM_OK;
 }

@@ -126,7 +126,7 @@ def test_tuning_roundtrip_and_range_checks():
     assert at.get_tuning() == before
     for bad in ({"tile_split2": 33}, {"tile_split4": 17}, {"work_cap_div": 0}, {"work_cap_min": 0},
                 {"far_weight": 0.0}, {"far_weight": float("nan")}, {"gemm_rbw": 9}, {"gemm_rbw": -1},
-                {"m2l_factored": 2}, {"pair_order": 4}, {"pair_order": -1}, {"near_lds": 65537},
+                {"m2l_factored": 2}, {"pair_order": 5}, {"pair_order": -1}, {"near_lds": 65537},
                 {"near_lds": -1}, {"gemm_lat": -1}, {"gemm_lat": (1 << 20) + 1},
                 {"gemm_chain": 2}, {"m2l_cols": 96}, {"m2l_cols": 0}, {"gemm_narrow": 2}, {"near_early": 901}, {"near_early_grid": 63},
                 {"m2l_early": 2}, {"m2l_early": -1}, {"near_early_start": 2}):

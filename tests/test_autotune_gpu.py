@@ -53,6 +53,9 @@ def _pair(xt, q, ncrit=48):
     {"m2l_early": 1},
     {"m2l_early": 1, "near_early": 500, "gemm_narrow": 1},
     {"near_early": 450, "near_early_start": 1},
+    {"pair_order": 4},
+    {"pair_order": 4, "near_early": 400, "near_early_start": 1, "gemm_narrow": 1, "m2l_early": 1},
+    {"pair_order": 4, "near_early": 300},
 ])
 def test_every_setting_gives_the_same_fmm(setting):
     torch = require_gpu()

@@ -266,6 +266,7 @@ def test_second_plan_shares_the_tree_and_outlives_the_first():
     {"near_early": 450, "gemm_lat": 0, "gemm_narrow": 1},
     {"near_early": 500, "m2l_early": 1},
     {"pair_order": 2},
+    {"pair_order": 4, "near_early": 400, "near_early_start": 1},
 ])
 @pytest.mark.parametrize("grad", [True, False])
 def test_pair_monopole_dipole_under_other_tunables_equals_the_defaults(setting, grad):
