@@ -2172,7 +2172,8 @@ static int launch_chain(const Chain &C, int32_t *ctr, int32_t *err, hipStream_t 
 
 template <typename T, int NR>
 static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, hipEvent_t surf_done,
-                            hipEvent_t up_done, const T *dips = nullptr, hipStream_t s3 = nullptr) {
+                            hipEvent_t up_done, const T *dips = nullptr, bool split_m2l = false,
+                            hipStream_t s3 = nullptr) {
   const DevTree &D = A->dt;
   const int64_t N = A->n;
   const int ld = A->ld;
@@ -2196,7 +2197,8 @@ static int eval_passes_pair(fmm_plan *A, fmm_plan *B, hipStream_t s, int part, h
   // follows on s, which then waits for s3.  M2L tasks ascend by level.
   const bool fact = LA.m2l_r.ntask > 0 || LB.m2l_r.ntask > 0;
   const int ls = D.maxlevel - 1;
-  const bool m2l_early = s3 && A->tune.m2l_early && !chain && !fact && ls >= 2 &&
+  // (s3 may be the null stream: split_m2l, not s3, says whether to split)
+  const bool m2l_early = split_m2l && A->tune.m2l_early && !chain && !fact && ls >= 2 &&
                          LA.m2l_t0.size() == (size_t)D.maxlevel + 2 && LB.m2l_t0.size() == (size_t)D.maxlevel + 2;
   auto m2l_levels = [&](int l0, int l1, hipStream_t st) -> int {  // the M2L of levels [l0, l1)
     GemmBatch a = LA.m2l, b = LB.m2l;
@@ -2452,7 +2454,7 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
     // done, and the downward pass there once the M2L is done
     FMM_HIP_TRY(hipEventRecord(A->ev_fork, s));
     if (nearly > 0 && !A->tune.near_early_start && (rc = early(A->ev_fork))) return rc;
-    if ((rc = eval_passes_pair<T, NR>(A, B, s, 1, B->ev_fork, A->ev_up, dips, side3))) return rc;
+    if ((rc = eval_passes_pair<T, NR>(A, B, s, 1, B->ev_fork, A->ev_up, dips, true, side3))) return rc;
     if (nearly > 0 && A->tune.near_early_start && (rc = early(B->ev_fork))) return rc;
     FMM_HIP_TRY(hipEventRecord(A->ev_m2l, s));
     FMM_HIP_TRY(hipStreamWaitEvent(side, B->ev_fork, 0));
@@ -2472,7 +2474,7 @@ static int pair_fork_join(fmm_plan *A, fmm_plan *B, hipStream_t s, const T *dips
     // P2M is done (1: P2M, VALU work at the head of the upward pass, then
     // has the GPU to itself)
     if (nearly > 0 && !A->tune.near_early_start && (rc = early(A->ev_fork))) return rc;
-    if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips, side3))) return rc;
+    if ((rc = eval_passes_pair<T, NR>(A, B, side, 1, B->ev_fork, A->ev_up, dips, true, side3))) return rc;
     if (nearly > 0 && A->tune.near_early_start && (rc = early(B->ev_fork))) return rc;
     if (order == 3) FMM_HIP_TRY(hipEventRecord(A->ev_m2l, side));
     // the near field starts once P2M (VALU, like the near field) is done and
