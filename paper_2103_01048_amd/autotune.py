@@ -23,7 +23,8 @@ Tunables (fmm_set_tuning; defaults in DEFAULTS):
                               shortest) started at once on a small grid
                               beside the upward passes and the M2L (order 3)
   near_early_start            the early near-field items with the far-field
-                              passes (0) or once P2M is done (1)
+                              passes (0) or once P2M is done (1); searched
+                              together with near_early
   m2l_early                   the two finest levels' M2L on a third side
                               stream beside the coarser M2M levels
   m2l_cols                    bf16x3 M2L columns per workgroup (64 or 128;
@@ -72,9 +73,13 @@ STAGES = (
     ("gemm_rbw", [{"gemm_rbw": v} for v in (0, 1, 2, 4)]),
     ("m2l_factored", [{"m2l_factored": v} for v in (0, 1)]),
     ("gemm_narrow", [{"gemm_narrow": v} for v in (0, 1)]),
+    # the share of early items and their start together: with pass order 4
+    # a split started with the passes is much slower than none, one started
+    # after P2M much faster, so one at a time would never take either
+    ("near_early", [{"near_early": v, "near_early_start": st} for v in (0, 300, 350, 400, 450, 500, 550)
+                    for st in (0, 1) if v or not st]),
+    # after the split: the early M2L levels pay off beside the early items
     ("m2l_early", [{"m2l_early": v} for v in (0, 1)]),
-    ("near_early", [{"near_early": v} for v in (0, 350, 450, 500, 550)]),
-    ("near_early_start", [{"near_early_start": v} for v in (0, 1)]),
     ("pair_order", [{"pair_order": v} for v in (0, 1, 2, 3, 4)]),
     ("near_lds", [{"near_lds": v} for v in (0, 8192, 13312)]),
     ("gemm_lat", [{"gemm_lat": v} for v in (0, 256, 512, 1024)]),
