@@ -20,5 +20,6 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_help_lists_the_workloads_and_formulations():
     r = _run("--help")
     assert r.returncode == 0
-    for w in ("bem2m", "batch64", "adjoint1m", "shell30m", "exterior_p1"):
+    for w in ("bem2m", "batch64", "adjoint1m", "shell30m", "exterior_p1", "--retune", "--summarize-profile",
+              "--summarize-counters"):
         assert w in r.stdout
